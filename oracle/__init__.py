@@ -1,0 +1,221 @@
+"""FP64 CPU oracle for the marginal-cost solver (Witsenhausen instance).
+
+TEST INFRASTRUCTURE ONLY.  Only ``tests/``, ``__graft_entry__.smoke()`` and
+the CPU-baseline leg of ``bench.py`` may import this package.  The product
+path (``paper_1908_04489_amd``) never does, and this package imports nothing
+from it.
+
+The arithmetic lives in ``ucp_oracle.c`` (plain C, FP64, dense sums in index
+order).  This module compiles it with gcc and exposes it through ctypes on
+numpy arrays.  ``mp_oracle.py`` holds an independent arbitrary-precision
+brute force for tiny grids.
+
+Problem objects are duck-typed: any object with ``k``, ``comps`` (a sequence
+of ``(weight, mean, sd)`` for the Gaussian-mixture prior of x0), ``x_lo``,
+``x_hi``, ``n_x``, ``y_lo``, ``y_hi``, ``n_y``.  Search objects need
+``u_lo``, ``u_hi``, ``levels``, ``cands``.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "ucp_oracle.c")
+_LIB = os.path.join(_HERE, "_ucp_oracle.so")
+MAX_COMP = 8
+TAU64 = 1e-12
+
+
+class _Problem(C.Structure):
+    _fields_ = [
+        ("k", C.c_double),
+        ("n_comp", C.c_int32),
+        ("pad_", C.c_int32),
+        ("w", C.c_double * MAX_COMP),
+        ("mu", C.c_double * MAX_COMP),
+        ("sd", C.c_double * MAX_COMP),
+        ("x_lo", C.c_double),
+        ("x_hi", C.c_double),
+        ("n_x", C.c_int64),
+        ("y_lo", C.c_double),
+        ("y_hi", C.c_double),
+        ("n_y", C.c_int64),
+    ]
+
+
+class _Search(C.Structure):
+    _fields_ = [
+        ("u_lo", C.c_double),
+        ("u_hi", C.c_double),
+        ("levels", C.c_int32),
+        ("cands", C.c_int32),
+    ]
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle into ``oracle/_ucp_oracle.so`` (gcc, OpenMP)."""
+    if force or not os.path.exists(_LIB):
+        cmd = [
+            "gcc", "-O2", "-fopenmp", "-ffp-contract=off", "-fno-fast-math",
+            "-fPIC", "-shared", "-o", _LIB + ".tmp", _SRC, "-lm",
+        ]
+        subprocess.run(cmd, check=True)
+        os.replace(_LIB + ".tmp", _LIB)
+    return _LIB
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+            build()
+        L = C.CDLL(_LIB)
+        P = C.POINTER
+        dp = P(C.c_double)
+        ip = P(C.c_int64)
+        L.orc_num_threads.restype = C.c_int
+        L.orc_grid.argtypes = [C.c_double, C.c_double, C.c_int64, dp]
+        L.orc_prior.argtypes = [P(_Problem), dp, dp]
+        L.orc_B.argtypes = [P(_Problem), dp, C.c_double, C.c_double]
+        L.orc_B.restype = C.c_double
+        L.orc_marginal_cost.argtypes = [P(_Problem), dp, dp, C.c_int64, dp]
+        L.orc_spacings.argtypes = [P(_Search), dp]
+        L.orc_argmin.argtypes = [P(_Problem), P(_Search), dp, dp, ip, C.c_int64, dp, dp]
+        L.orc_update_u1.argtypes = [P(_Problem), dp, ip, C.c_int64, dp]
+        L.orc_objective.argtypes = [P(_Problem), dp, dp]
+        L.orc_objective.restype = C.c_double
+        L.orc_solve.argtypes = [P(_Problem), P(_Search), C.c_int32, dp, dp, dp, dp]
+        _lib = L
+    return _lib
+
+
+def _prob(p) -> _Problem:
+    comps = list(p.comps)
+    if not 1 <= len(comps) <= MAX_COMP:
+        raise ValueError("prior must have 1..8 components")
+    s = _Problem()
+    s.k = float(p.k)
+    s.n_comp = len(comps)
+    for c, (w, mu, sd) in enumerate(comps):
+        s.w[c], s.mu[c], s.sd[c] = float(w), float(mu), float(sd)
+    s.x_lo, s.x_hi, s.n_x = float(p.x_lo), float(p.x_hi), int(p.n_x)
+    s.y_lo, s.y_hi, s.n_y = float(p.y_lo), float(p.y_hi), int(p.n_y)
+    return s
+
+
+def _search(s) -> _Search:
+    r = _Search()
+    r.u_lo, r.u_hi = float(s.u_lo), float(s.u_hi)
+    r.levels, r.cands = int(s.levels), int(s.cands)
+    return r
+
+
+def _dp(a):
+    return a.ctypes.data_as(C.POINTER(C.c_double))
+
+
+def _f64(a, n=None):
+    a = np.ascontiguousarray(a, dtype=np.float64)
+    if n is not None and a.shape != (n,):
+        raise ValueError(f"expected shape ({n},), got {a.shape}")
+    return a
+
+
+def num_threads() -> int:
+    return int(lib().orc_num_threads())
+
+
+def grid(lo: float, hi: float, n: int) -> np.ndarray:
+    out = np.empty(int(n), np.float64)
+    lib().orc_grid(float(lo), float(hi), int(n), _dp(out))
+    return out
+
+
+def prior(p):
+    """(f, log f) at the x-grid nodes."""
+    f = np.empty(int(p.n_x), np.float64)
+    lf = np.empty(int(p.n_x), np.float64)
+    lib().orc_prior(C.byref(_prob(p)), _dp(f), _dp(lf))
+    return f, lf
+
+
+def B(p, u1, x: float, u: float) -> float:
+    """B(u; x) = L_0(u, x) / f(x) for one point and one candidate."""
+    u1 = _f64(u1, int(p.n_y))
+    return float(lib().orc_B(C.byref(_prob(p)), _dp(u1), float(x), float(u)))
+
+
+def marginal_cost(p, u1, u) -> np.ndarray:
+    """L_0 = f_i B(u; x_i) for candidates u of shape [n_x, n_cand]."""
+    u1 = _f64(u1, int(p.n_y))
+    u = np.ascontiguousarray(u, dtype=np.float64)
+    if u.ndim != 2 or u.shape[0] != int(p.n_x):
+        raise ValueError("u must be [n_x, n_cand]")
+    out = np.empty_like(u)
+    lib().orc_marginal_cost(C.byref(_prob(p)), _dp(u1), _dp(u), u.shape[1], _dp(out))
+    return out
+
+
+def spacings(s) -> np.ndarray:
+    h = np.empty(int(s.levels), np.float64)
+    lib().orc_spacings(C.byref(_search(s)), _dp(h))
+    return h
+
+
+def argmin(p, s, u1, u0_in, rows=None):
+    """One coarse-to-fine u0 update.  Returns (u0_out, B_out) for the listed
+    rows (all rows when ``rows`` is None)."""
+    u1 = _f64(u1, int(p.n_y))
+    u0_in = _f64(u0_in, int(p.n_x))
+    if rows is None:
+        n = int(p.n_x)
+        rp = None
+    else:
+        rows = np.ascontiguousarray(rows, dtype=np.int64)
+        if rows.size and (rows.min() < 0 or rows.max() >= int(p.n_x)):
+            raise ValueError("row index out of range")
+        n = rows.size
+        rp = rows.ctypes.data_as(C.POINTER(C.c_int64))
+    u0o = np.empty(n, np.float64)
+    Bo = np.empty(n, np.float64)
+    lib().orc_argmin(C.byref(_prob(p)), C.byref(_search(s)), _dp(u1), _dp(u0_in),
+                     rp, n, _dp(u0o), _dp(Bo))
+    return u0o, Bo
+
+
+def update_u1(p, u0, rows=None) -> np.ndarray:
+    u0 = _f64(u0, int(p.n_x))
+    if rows is None:
+        n, rp = int(p.n_y), None
+    else:
+        rows = np.ascontiguousarray(rows, dtype=np.int64)
+        if rows.size and (rows.min() < 0 or rows.max() >= int(p.n_y)):
+            raise ValueError("row index out of range")
+        n, rp = rows.size, rows.ctypes.data_as(C.POINTER(C.c_int64))
+    out = np.empty(n, np.float64)
+    lib().orc_update_u1(C.byref(_prob(p)), _dp(u0), rp, n, _dp(out))
+    return out
+
+
+def objective(p, u0, u1) -> float:
+    u0 = _f64(u0, int(p.n_x))
+    u1 = _f64(u1, int(p.n_y))
+    return float(lib().orc_objective(C.byref(_prob(p)), _dp(u0), _dp(u1)))
+
+
+def solve(p, s, iters: int, u0_init):
+    """Returns (u0, u1, J_hist[iters + 1])."""
+    u0_init = _f64(u0_init, int(p.n_x))
+    u0 = np.empty(int(p.n_x), np.float64)
+    u1 = np.empty(int(p.n_y), np.float64)
+    J = np.empty(int(iters) + 1, np.float64)
+    lib().orc_solve(C.byref(_prob(p)), C.byref(_search(s)), int(iters), _dp(u0_init),
+                    _dp(u0), _dp(u1), _dp(J))
+    return u0, u1, J

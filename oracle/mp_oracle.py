@@ -1,0 +1,122 @@
+"""Arbitrary-precision brute force of the discrete problem, for tiny grids.
+
+TEST INFRASTRUCTURE ONLY (see ``oracle/__init__.py``).  It restates the
+discrete problem at 40 significant digits with mpmath so the FP64 C oracle
+can be checked for rounding and indexing mistakes on grids of a few dozen
+nodes.  It is written from the definitions (Section V-A objective,
+Section III-A marginal cost, Section III-D step-function discretisation),
+not from the C code.
+"""
+from __future__ import annotations
+
+import mpmath as mp
+
+DPS = 40
+TAU = mp.mpf("1e-12")
+
+
+def _nodes(lo, hi, n):
+    lo, hi = mp.mpf(lo), mp.mpf(hi)
+    return [lo + (hi - lo) * i / (n - 1) for i in range(n)]
+
+
+def _prior(p, xs):
+    out = []
+    for x in xs:
+        f = mp.mpf(0)
+        for (w, mu, sd) in p.comps:
+            w, mu, sd = mp.mpf(w), mp.mpf(mu), mp.mpf(sd)
+            f += w * mp.npdf(x, mu, sd)
+        out.append(f)
+    return out
+
+
+def _Bfun(p, ys, u1, x, u):
+    dy = ys[1] - ys[0]
+    z = x + u
+    acc = mp.mpf(0)
+    for y, v in zip(ys, u1):
+        acc += mp.npdf(y - z) * (z - v) ** 2
+    return mp.mpf(p.k) ** 2 * u ** 2 + dy * acc
+
+
+def _select(cands, vals, inc):
+    m = min(vals)
+    best = None
+    for c, v in zip(cands, vals):
+        if v <= m * (1 + TAU):
+            key = (abs(c - inc), c)
+            if best is None or key < best[0]:
+                best = (key, c, v)
+    return best[1], best[2]
+
+
+def u1_update(p, u0):
+    with mp.workdps(DPS):
+        xs = _nodes(p.x_lo, p.x_hi, p.n_x)
+        ys = _nodes(p.y_lo, p.y_hi, p.n_y)
+        f = _prior(p, xs)
+        x1 = [x + mp.mpf(float(u)) for x, u in zip(xs, u0)]
+        out = []
+        for y in ys:
+            num = mp.fsum(fi * mp.npdf(y - a) * a for fi, a in zip(f, x1))
+            den = mp.fsum(fi * mp.npdf(y - a) for fi, a in zip(f, x1))
+            out.append(num / den)
+        return out
+
+
+def objective(p, u0, u1):
+    with mp.workdps(DPS):
+        xs = _nodes(p.x_lo, p.x_hi, p.n_x)
+        ys = _nodes(p.y_lo, p.y_hi, p.n_y)
+        f = _prior(p, xs)
+        dx = xs[1] - xs[0]
+        dy = ys[1] - ys[0]
+        k2 = mp.mpf(p.k) ** 2
+        tot = mp.mpf(0)
+        for x, fi, u in zip(xs, f, u0):
+            u = mp.mpf(float(u))
+            a = x + u
+            inner = mp.fsum(mp.npdf(y - a) * (a - mp.mpf(float(v))) ** 2 for y, v in zip(ys, u1))
+            tot += fi * (k2 * u ** 2 + dy * inner)
+        return dx * tot
+
+
+def argmin(p, s, u1, u0_in):
+    """Coarse-to-fine search per point with FP64 candidate positions (the
+    positions are inputs of the decision, so they are formed in binary64
+    exactly as the discrete method defines them); costs at 40 digits."""
+    import numpy as np
+
+    with mp.workdps(DPS):
+        xs = _nodes(p.x_lo, p.x_hi, p.n_x)
+        ys = _nodes(p.y_lo, p.y_hi, p.n_y)
+        u1m = [mp.mpf(float(v)) for v in u1]
+        K, L = int(s.cands), int(s.levels)
+        h = [(float(s.u_hi) - float(s.u_lo)) / float(K - 1)]
+        for _ in range(1, L):
+            h.append(2.0 * h[-1] / float(K - 1))
+        out = []
+        for i in range(int(p.n_x)):
+            # the FP64 grid node, so the decision sees the same x as FP64 code
+            x64 = float(np.float64(p.x_lo) + np.float64(i) * ((np.float64(p.x_hi) - np.float64(p.x_lo)) / np.float64(p.n_x - 1)))
+            x = mp.mpf(x64)
+            inc = float(u0_in[i])
+            cs = [float(np.float64(s.u_lo) + np.float64(q) * np.float64(h[0])) for q in range(K)]
+            vs = [_Bfun(p, ys, u1m, x, mp.mpf(c)) for c in cs]
+            c_best, v_best = _select([mp.mpf(c) for c in cs], vs, mp.mpf(inc))
+            c_best = float(c_best)
+            for lvl in range(1, L):
+                cs = []
+                for q in range(K):
+                    v = float((np.float64(c_best) - np.float64(h[lvl - 1])) + np.float64(q) * np.float64(h[lvl]))
+                    cs.append(min(max(v, float(s.u_lo)), float(s.u_hi)))
+                vs = [_Bfun(p, ys, u1m, x, mp.mpf(c)) for c in cs]
+                cs.append(c_best)
+                vs.append(v_best)
+                cb, v_best = _select([mp.mpf(c) for c in cs], vs, mp.mpf(inc))
+                c_best = float(cb)
+            v_inc = _Bfun(p, ys, u1m, x, mp.mpf(inc))
+            cb, _ = _select([mp.mpf(c_best), mp.mpf(inc)], [v_best, v_inc], mp.mpf(inc))
+            out.append(float(cb))
+        return out

@@ -1,0 +1,320 @@
+/*
+ * Plain FP64 CPU oracle for the marginal-cost solver on Witsenhausen's
+ * counterexample.
+ *
+ * TEST INFRASTRUCTURE ONLY.  This is the slow, obviously correct statement
+ * of what the GPU path computes.  Only the tests, the smoke check and the
+ * CPU-baseline leg of the benchmark load it; the product path never does.
+ * It shares no code, header or constant with the HIP library.
+ *
+ * Problem (Section V-A): x0 ~ prior f, y0 = x0, x1 = x0 + u0(y0),
+ * y1 = x1 + w with w ~ N(0,1), x2 = x1 - u1(y1),
+ * J = E[k^2 u0(y0)^2 + x2^2].
+ *
+ * Discretisation (Section III-D, "Initialization"): each controller is a
+ * step function on a linearly spaced grid over [a,b]; every integral is
+ * taken by the rectangle rule with weight (b-a)/(d-1) at each node.
+ *
+ * Arithmetic: IEEE FP64, exp() from libm, every sum in ascending index
+ * order, dense over all grid nodes (no window), no fast-math and no FMA
+ * contraction.  OpenMP splits only the independent outer index (Section
+ * IV-A: the points of one controller are independent), so results do not
+ * depend on the thread count.
+ *
+ * Parity status of each function is stated in its comment; every function
+ * here is pinned by the CPU tests against closed forms, exact discrete
+ * identities or a high-precision brute force.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+#define ORC_MAX_COMP 8
+#define ORC_TAU64 1e-12 /* relative tie band of the selection rule */
+
+/* Problem description: stage-1 weight k, a Gaussian-mixture prior for x0
+ * (one component = the paper's N(0, sigma^2)), and the two grids. */
+typedef struct {
+  double k;
+  int32_t n_comp;
+  int32_t pad_;
+  double w[ORC_MAX_COMP];
+  double mu[ORC_MAX_COMP];
+  double sd[ORC_MAX_COMP];
+  double x_lo, x_hi;
+  int64_t n_x;
+  double y_lo, y_hi;
+  int64_t n_y;
+} orc_problem;
+
+/* Coarse-to-fine search settings for the u0 update. */
+typedef struct {
+  double u_lo, u_hi;
+  int32_t levels;
+  int32_t cands;
+} orc_search;
+
+static const double ORC_PI = 3.14159265358979323846264338327950288;
+
+int orc_num_threads(void) {
+#ifdef _OPENMP
+  return omp_get_max_threads();
+#else
+  return 1;
+#endif
+}
+
+/* Grid node i of a linspace over [lo,hi] with n nodes (Section III-D). */
+static double orc_node(double lo, double hi, int64_t n, int64_t i) {
+  double step = (hi - lo) / (double)(n - 1);
+  return lo + (double)i * step;
+}
+
+void orc_grid(double lo, double hi, int64_t n, double* out) {
+  for (int64_t i = 0; i < n; ++i) out[i] = orc_node(lo, hi, n, i);
+}
+
+/* Prior density of x0 and its logarithm at every x-grid node.
+ * Section V-A fixes x0 ~ N(0, sigma^2); a mixture generalises it.
+ * log f is a log-sum-exp over components so it never takes log(0). */
+void orc_prior(const orc_problem* p, double* f, double* logf) {
+  for (int64_t i = 0; i < p->n_x; ++i) {
+    double x = orc_node(p->x_lo, p->x_hi, p->n_x, i);
+    double lc[ORC_MAX_COMP];
+    double sum = 0.0;
+    double lmax = -INFINITY;
+    for (int c = 0; c < p->n_comp; ++c) {
+      double d = (x - p->mu[c]) / p->sd[c];
+      double dens = p->w[c] * exp(-0.5 * d * d) / (p->sd[c] * sqrt(2.0 * ORC_PI));
+      sum += dens;
+      lc[c] = log(p->w[c]) - log(p->sd[c]) - 0.5 * log(2.0 * ORC_PI) - 0.5 * d * d;
+      if (lc[c] > lmax) lmax = lc[c];
+    }
+    double acc = 0.0;
+    for (int c = 0; c < p->n_comp; ++c) acc += exp(lc[c] - lmax);
+    if (f) f[i] = sum;
+    if (logf) logf[i] = lmax + log(acc);
+  }
+}
+
+/* Noise density phi(t) of w ~ N(0,1) (Section V-A). */
+static double orc_phi(double t) { return exp(-0.5 * t * t) / sqrt(2.0 * ORC_PI); }
+
+/* B(u; x) = L_0(u, x) / f(x): the marginal cost of the first controller
+ * at the point x0 = x with u0(x) = u, divided by the prior density.
+ * Marginal cost C_0 (Section III-A, definition of C_m) applied to the
+ * Witsenhausen objective: k^2 u^2 + integral over y of
+ * phi(y - x - u) (x + u - u1(y))^2, by the rectangle rule on the y grid. */
+double orc_B(const orc_problem* p, const double* u1, double x, double u) {
+  double dy = (p->y_hi - p->y_lo) / (double)(p->n_y - 1);
+  double z = x + u;
+  double s = 0.0;
+  for (int64_t j = 0; j < p->n_y; ++j) {
+    double y = orc_node(p->y_lo, p->y_hi, p->n_y, j);
+    double e = z - u1[j];
+    s += orc_phi(y - z) * e * e;
+  }
+  return p->k * p->k * u * u + dy * s;
+}
+
+/* L_0(u; x_i) = f_i * B(u; x_i) for a set of candidates per point.
+ * u and out are row-major [n_x][n_cand]. */
+void orc_marginal_cost(const orc_problem* p, const double* u1, const double* u,
+                       int64_t n_cand, double* out) {
+  double* f = (double*)malloc(sizeof(double) * (size_t)p->n_x);
+  orc_prior(p, f, NULL);
+#pragma omp parallel for schedule(static)
+  for (int64_t i = 0; i < p->n_x; ++i) {
+    double x = orc_node(p->x_lo, p->x_hi, p->n_x, i);
+    for (int64_t c = 0; c < n_cand; ++c)
+      out[i * n_cand + c] = f[i] * orc_B(p, u1, x, u[i * n_cand + c]);
+  }
+  free(f);
+}
+
+/* Selection among a finite candidate set (the improvement rule of
+ * Section III-B on a finite set): the members whose B lies within a
+ * relative band TAU64 of the minimum are ties; among them the one nearest
+ * the incumbent u_inc wins, and an equal distance goes to the smaller u.
+ * Returns the index of the chosen member. */
+static int orc_select(int n, const double* c, const double* B, double u_inc) {
+  double m = B[0];
+  for (int s = 1; s < n; ++s)
+    if (B[s] < m) m = B[s];
+  double thr = m * (1.0 + ORC_TAU64);
+  int best = -1;
+  double bd = 0.0;
+  for (int s = 0; s < n; ++s) {
+    if (!(B[s] <= thr)) continue;
+    double d = fabs(c[s] - u_inc);
+    if (best < 0 || d < bd || (d == bd && c[s] < c[best])) {
+      best = s;
+      bd = d;
+    }
+  }
+  return best;
+}
+
+/* Spacing of the candidate grid at every level of the coarse-to-fine
+ * search: level 0 spans [u_lo,u_hi] with K nodes; each later level spans
+ * the neighbour bracket [c* - h_prev, c* + h_prev] with K nodes. */
+void orc_spacings(const orc_search* s, double* h) {
+  h[0] = (s->u_hi - s->u_lo) / (double)(s->cands - 1);
+  for (int l = 1; l < s->levels; ++l) h[l] = 2.0 * h[l - 1] / (double)(s->cands - 1);
+}
+
+static double orc_clamp(double v, double lo, double hi) {
+  if (v < lo) return lo;
+  if (v > hi) return hi;
+  return v;
+}
+
+/* Pointwise improvement of u0 at one point (Corollary 1 and the update
+ * rule of Section III-B): a coarse-to-fine search of argmin_u B(u; x_i),
+ * the best-so-far carried from level to level, and the incumbent u0_i
+ * kept in the final comparison so the update never raises the cost. */
+static double orc_argmin_point(const orc_problem* p, const orc_search* s,
+                               const double* u1, const double* h, int64_t i,
+                               double u_inc, double* B_out) {
+  int K = s->cands;
+  double x = orc_node(p->x_lo, p->x_hi, p->n_x, i);
+  double* c = (double*)malloc(sizeof(double) * (size_t)(K + 1));
+  double* B = (double*)malloc(sizeof(double) * (size_t)(K + 1));
+  /* level 0: the global grid over [u_lo, u_hi] */
+  for (int q = 0; q < K; ++q) {
+    c[q] = s->u_lo + (double)q * h[0];
+    B[q] = orc_B(p, u1, x, c[q]);
+  }
+  int b = orc_select(K, c, B, u_inc);
+  double cs = c[b], Bs = B[b];
+  /* finer levels around the best so far, which stays in the set */
+  for (int l = 1; l < s->levels; ++l) {
+    for (int q = 0; q < K; ++q) {
+      c[q] = orc_clamp(cs - h[l - 1] + (double)q * h[l], s->u_lo, s->u_hi);
+      B[q] = orc_B(p, u1, x, c[q]);
+    }
+    c[K] = cs;
+    B[K] = Bs;
+    b = orc_select(K + 1, c, B, u_inc);
+    cs = c[b];
+    Bs = B[b];
+  }
+  /* acceptance against the incumbent */
+  c[0] = cs;
+  B[0] = Bs;
+  c[1] = u_inc;
+  B[1] = orc_B(p, u1, x, u_inc);
+  b = orc_select(2, c, B, u_inc);
+  double r = c[b];
+  if (B_out) *B_out = B[b];
+  free(c);
+  free(B);
+  return r;
+}
+
+/* One u0 update over the listed points (rows == NULL: every point).
+ * u0_out[r] and B_out[r] are indexed like rows. */
+void orc_argmin(const orc_problem* p, const orc_search* s, const double* u1,
+                const double* u0_in, const int64_t* rows, int64_t n_rows,
+                double* u0_out, double* B_out) {
+  double h[64];
+  orc_spacings(s, h);
+  int64_t n = rows ? n_rows : p->n_x;
+#pragma omp parallel for schedule(static)
+  for (int64_t r = 0; r < n; ++r) {
+    int64_t i = rows ? rows[r] : r;
+    double Bv;
+    u0_out[r] = orc_argmin_point(p, s, u1, h, i, u0_in[i], &Bv);
+    if (B_out) B_out[r] = Bv;
+  }
+}
+
+/* Second controller by its closed form: u1(y) = E[x1 | y1 = y], the exact
+ * minimiser of the discrete marginal cost C_1(v, y) (the closed form the
+ * paper credits to the earlier algorithm, Section IV-B).  With
+ * l_ij = log f_i - (y_j - x1_i)^2 / 2 and M_j = max_i l_ij,
+ * u1_j = sum_i x1_i e^(l_ij - M_j) / sum_i e^(l_ij - M_j).
+ * rows == NULL: every y node; else only the listed nodes (out indexed
+ * like rows). */
+void orc_update_u1(const orc_problem* p, const double* u0, const int64_t* rows,
+                   int64_t n_rows, double* u1_out) {
+  double* logf = (double*)malloc(sizeof(double) * (size_t)p->n_x);
+  double* x1 = (double*)malloc(sizeof(double) * (size_t)p->n_x);
+  orc_prior(p, NULL, logf);
+  for (int64_t i = 0; i < p->n_x; ++i) x1[i] = orc_node(p->x_lo, p->x_hi, p->n_x, i) + u0[i];
+  int64_t n = rows ? n_rows : p->n_y;
+#pragma omp parallel for schedule(static)
+  for (int64_t r = 0; r < n; ++r) {
+    int64_t j = rows ? rows[r] : r;
+    double y = orc_node(p->y_lo, p->y_hi, p->n_y, j);
+    double M = -INFINITY;
+    for (int64_t i = 0; i < p->n_x; ++i) {
+      double d = y - x1[i];
+      double l = logf[i] - 0.5 * d * d;
+      if (l > M) M = l;
+    }
+    double num = 0.0, den = 0.0;
+    for (int64_t i = 0; i < p->n_x; ++i) {
+      double d = y - x1[i];
+      double e = exp(logf[i] - 0.5 * d * d - M);
+      num += x1[i] * e;
+      den += e;
+    }
+    u1_out[r] = num / den;
+  }
+  free(logf);
+  free(x1);
+}
+
+/* Objective J[U] of Section V-A by the rectangle rule in x0 and y:
+ * J = dx * sum_i f_i [k^2 u0_i^2 + dy * sum_j phi(y_j - x1_i)(x1_i - u1_j)^2]. */
+double orc_objective(const orc_problem* p, const double* u0, const double* u1) {
+  double dx = (p->x_hi - p->x_lo) / (double)(p->n_x - 1);
+  double dy = (p->y_hi - p->y_lo) / (double)(p->n_y - 1);
+  double* f = (double*)malloc(sizeof(double) * (size_t)p->n_x);
+  double* row = (double*)malloc(sizeof(double) * (size_t)p->n_x);
+  orc_prior(p, f, NULL);
+#pragma omp parallel for schedule(static)
+  for (int64_t i = 0; i < p->n_x; ++i) {
+    double x1 = orc_node(p->x_lo, p->x_hi, p->n_x, i) + u0[i];
+    double s = 0.0;
+    for (int64_t j = 0; j < p->n_y; ++j) {
+      double y = orc_node(p->y_lo, p->y_hi, p->n_y, j);
+      double e = x1 - u1[j];
+      s += orc_phi(y - x1) * e * e;
+    }
+    row[i] = f[i] * (p->k * p->k * u0[i] * u0[i] + dy * s);
+  }
+  double J = 0.0;
+  for (int64_t i = 0; i < p->n_x; ++i) J += row[i];
+  free(f);
+  free(row);
+  return dx * J;
+}
+
+/* The solve loop: u1 from the initial u0, then `iters` rounds of
+ * (u0 update, u1 update), J recorded after each round.  This is the
+ * controller loop of Algorithm 1 with M = 2 controllers visited in order,
+ * the u0 update done by the coarse-to-fine search and the u1 update by its
+ * closed form.  J_hist has iters + 1 entries. */
+void orc_solve(const orc_problem* p, const orc_search* s, int32_t iters,
+               const double* u0_init, double* u0_out, double* u1_out, double* J_hist) {
+  double* u0 = (double*)malloc(sizeof(double) * (size_t)p->n_x);
+  double* nxt = (double*)malloc(sizeof(double) * (size_t)p->n_x);
+  memcpy(u0, u0_init, sizeof(double) * (size_t)p->n_x);
+  orc_update_u1(p, u0, NULL, 0, u1_out);
+  J_hist[0] = orc_objective(p, u0, u1_out);
+  for (int32_t t = 1; t <= iters; ++t) {
+    orc_argmin(p, s, u1_out, u0, NULL, 0, nxt, NULL);
+    memcpy(u0, nxt, sizeof(double) * (size_t)p->n_x);
+    orc_update_u1(p, u0, NULL, 0, u1_out);
+    J_hist[t] = orc_objective(p, u0, u1_out);
+  }
+  memcpy(u0_out, u0, sizeof(double) * (size_t)p->n_x);
+  free(u0);
+  free(nxt);
+}
