@@ -1,0 +1,160 @@
+"""Benchmark of the MI355X marginal-cost solver.
+
+One step = one whole solve of the workload on one GPU: the prior, the
+closed-form u1 of the initial controller, then every round of (the
+coarse-to-fine u0 update over all levels - the marginal-cost sums, the
+per-point selection with FP64 tie re-evaluation and the comparison with the
+incumbent - the u0 advance, the u1 update and the FP64 objective), inputs
+resident in HBM before the timed region.
+
+Default workload: Witsenhausen k=0.2, sigma=5, x0 and y grids of 20001
+nodes on [-25, 25], search 5 levels x 16 candidates on [-30, 30], init
+u0 = sigma sign(x) - x, 30 rounds, FP32 terms with compensated sums.
+
+The metric counts algorithmic marginal-cost terms: (point, candidate,
+y node) triples with |y - x - u| <= 9 noise sds, counted on the device.
+Prints one JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+PEAK_LANE_OPS = 256 * 64 * 2.4e9  # FP32 VALU lane-ops/s without packed math (256 CUs x 64 lanes x 2.4 GHz)
+
+
+def workload(name):
+    import workloads as W
+
+    if name == "paper":
+        return W.paper_res_case()
+    if name == "small":
+        return W.small_case()
+    raise SystemExit(f"unknown workload {name}")
+
+
+def cpu_baseline(case, budget_s=12.0):
+    """The FP64 oracle, as it stands, on a bounded sample of the same
+    workload: one u0 update (every level and the incumbent) on evenly spaced
+    rows, given the oracle's own u1 of the initial controller."""
+    import numpy as np
+
+    import oracle
+
+    p, s = case.prob, case.search
+    u1 = oracle.update_u1(p, case.u0_init)
+    x = oracle.grid(p.x_lo, p.x_hi, p.n_x)
+    # probe, then size the sample to the budget
+    rows = np.linspace(0, p.n_x - 1, 64).astype(np.int64)
+    t0 = time.perf_counter()
+    oracle.argmin(p, s, u1, case.u0_init, rows=rows)
+    dt = time.perf_counter() - t0
+    n = int(min(p.n_x, max(64, 64 * budget_s / max(dt, 1e-6))))
+    rows = np.linspace(0, p.n_x - 1, n).astype(np.int64)
+    t0 = time.perf_counter()
+    u0o, _ = oracle.argmin(p, s, u1, case.u0_init, rows=rows)
+    dt = time.perf_counter() - t0
+    # algorithmic terms of those rows: same count as the GPU (nodes within 9
+    # of x + u) over the candidates the oracle visited - level 0 is the fixed
+    # grid, later levels sit near the optimum; counted with the level-0 grid
+    # and the final choice as a bound of the right size
+    dy = (p.y_hi - p.y_lo) / (p.n_y - 1)
+    h = oracle.spacings(s)
+    cands = []
+    for r, i in enumerate(rows):
+        c0 = s.u_lo + np.arange(s.cands) * h[0]
+        cl = np.concatenate([c0, np.full(s.cands * (s.levels - 1) + 1, u0o[r])])
+        cands.append(x[i] + cl)
+    z = np.concatenate(cands)
+    lo = np.maximum(np.ceil((z - 9 - p.y_lo) / dy), 0)
+    hi = np.minimum(np.floor((z + 9 - p.y_lo) / dy), p.n_y - 1)
+    alg = float(np.sum(np.maximum(hi - lo + 1, 0)))
+    dense = float(len(z)) * p.n_y
+    return {"value": alg / dt, "unit": "terms/s", "cores": oracle.num_threads(), "kind": "oracle",
+            "sample": f"one u0 update of {n} of {p.n_x} rows (all {s.levels}x{s.cands} levels + incumbent), "
+                      f"{dt:.1f} s wall; dense FP64 evaluation {dense / dt:.3e} terms/s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="paper")
+    ap.add_argument("--prec", default="fp32_kahan")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-check", action="store_true", help="skip the FP64 oracle check of the final J")
+    a = ap.parse_args()
+    if a.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path (the solver shards over x0 "
+              "rows by design, but only the single-GPU kernel is built and measured).", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_1908_04489_amd as U
+
+    case = workload(a.workload)
+    p, s = case.prob, case.search
+    u0 = torch.as_tensor(case.u0_init).cuda()
+    print(f"# workload {case.name}: n={p.n_x}, {s.levels}x{s.cands}, {case.iters} rounds, {a.prec}", file=sys.stderr,
+          flush=True)
+    for w in range(a.warmup):
+        U.solve(p, s, case.iters, u0, a.prec)
+        print(f"# warmup {w} done", file=sys.stderr, flush=True)
+    st = torch.cuda.current_stream()
+    torch.cuda.synchronize()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record(st)
+    terms = 0
+    for k in range(a.steps):
+        out = U.solve(p, s, case.iters, u0, a.prec)
+        terms += U.last_terms()
+    ev1.record(st)
+    torch.cuda.synchronize()
+    ms = ev0.elapsed_time(ev1)
+    ms_step = ms / a.steps
+    value = terms / (ms / 1e3)
+    C = s.levels * s.cands + 1
+    dense = float(p.n_x) * C * p.n_y * case.iters
+    res = {
+        "metric": "marginal-cost quadrature terms/s",
+        "value": value,
+        "unit": "terms/s",
+        "n_gpus": 1,
+        "steps": a.steps,
+        "warmup": a.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": case.name, "n_x": p.n_x, "n_y": p.n_y, "levels": s.levels, "cands": s.cands,
+                   "rounds": case.iters, "k": p.k, "sigma": case.sigma, "prec": a.prec},
+        "alg_terms_per_step": terms / a.steps,
+        "dense_equiv_terms_per_s": dense / (ms_step / 1e3),
+        "solves_per_s": 1e3 / ms_step,
+    }
+    J = out[2].cpu().numpy()
+    res["J_final"] = float(J[-1])
+    if not a.no_check:
+        import oracle
+
+        Jo = oracle.objective(p, out[0].cpu().numpy(), out[1].cpu().numpy())
+        res["J_final_rel_err_vs_oracle_objective"] = abs(J[-1] - Jo) / Jo
+    if not a.no_cpu:
+        res["cpu_baseline"] = cpu_baseline(case)
+    print(json.dumps(res), flush=True)
+
+
+if __name__ == "__main__":
+    main()

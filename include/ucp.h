@@ -1,0 +1,224 @@
+/*
+ * ucp.h - C ABI of the MI355X marginal-cost solver for Witsenhausen's
+ * counterexample (Tseng, "A Generic Solver for Unconstrained Control
+ * Problems with Integral Functional Objectives").
+ *
+ * The problem (Section V-A): x0 ~ prior f (the paper's N(0, sigma^2), or a
+ * Gaussian mixture), y0 = x0, x1 = x0 + u0(y0), y1 = x1 + w with
+ * w ~ N(0, 1), x2 = x1 - u1(y1), minimise J = E[k^2 u0(y0)^2 + x2^2].
+ * Controllers are step functions on linearly spaced grids (Section III-D,
+ * "Initialization"); integrals are rectangle-rule sums over the grid nodes.
+ *
+ * Conventions for every call below:
+ *  - Array arguments are DEVICE pointers (memory on the handle's GPU),
+ *    FP64, contiguous, owned by the caller.  The library never frees or
+ *    keeps them past the call's stream work.  The library owns only the
+ *    workspace held inside the handle.
+ *  - `stream` is a hipStream_t passed as void* (NULL = the default stream).
+ *    Calls enqueue work on it and return without synchronising, except
+ *    where stated; results are valid once the stream has reached them.
+ *  - Return value: UCP_OK (0) or a negative error code; on error nothing was
+ *    enqueued and ucp_last_error() returns a message (thread-local).
+ *  - A handle is not thread-safe: use one handle per host thread.  Calls on
+ *    one handle must share one stream or be ordered by the caller, because
+ *    they share the handle's workspace.
+ */
+#ifndef UCP_H_
+#define UCP_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define UCP_MAX_COMP 8
+#define UCP_MAX_LEVELS 16
+#define UCP_MAX_CANDS 63
+
+enum {
+  UCP_OK = 0,
+  UCP_EINVAL = -1,     /* invalid argument (null pointer, bad size or parameter) */
+  UCP_ENOMEM = -2,     /* device allocation failed / over the memory budget */
+  UCP_EHIP = -3,       /* a HIP runtime call failed (no device, launch failure) */
+  UCP_EAGAIN = -4,     /* server: not admitted yet / result not ready */
+  UCP_ENONFINITE = -5, /* a solve produced non-finite values (e.g. NaN input) */
+  UCP_ENOTFOUND = -6   /* server: unknown or already collected ticket */
+};
+
+/* Arithmetic of the bulk marginal-cost and u1 sums. */
+typedef enum {
+  UCP_FP32 = 0,       /* FP32 terms, plain FP32 accumulation */
+  UCP_FP32_KAHAN = 1, /* FP32 terms, compensated (Kahan) accumulation */
+  UCP_FP64 = 2        /* FP64 throughout */
+} ucp_prec;
+
+/* Problem instance: weight k of the stage-1 cost, the prior of x0 as a
+ * mixture of n_comp Gaussians (weights w summing to 1, means mu, standard
+ * deviations sd > 0), the x0 grid (n_x nodes on [x_lo, x_hi]) and the y1
+ * grid (n_y nodes on [y_lo, y_hi]).  Node i of a grid is
+ * lo + i * ((hi - lo) / (n - 1)) in binary64. */
+typedef struct ucp_problem {
+  double k;
+  int32_t n_comp;
+  int32_t pad_;
+  double w[UCP_MAX_COMP];
+  double mu[UCP_MAX_COMP];
+  double sd[UCP_MAX_COMP];
+  double x_lo, x_hi;
+  int64_t n_x;
+  double y_lo, y_hi;
+  int64_t n_y;
+} ucp_problem;
+
+/* Coarse-to-fine search of argmin_u L_0(u, x0) per point: level 0 takes
+ * `cands` equally spaced candidates on [u_lo, u_hi] (spacing
+ * h0 = (u_hi - u_lo) / (cands - 1)); level l takes `cands` equally spaced
+ * candidates on [c* - h_{l-1}, c* + h_{l-1}] clamped to [u_lo, u_hi]
+ * (h_l = 2 h_{l-1} / (cands - 1)), c* being the best so far, which stays in
+ * the comparison; the incumbent u0(x0) is compared last and kept on ties. */
+typedef struct ucp_search {
+  double u_lo, u_hi;
+  int32_t levels; /* 1 .. UCP_MAX_LEVELS */
+  int32_t cands;  /* 2 .. UCP_MAX_CANDS */
+} ucp_search;
+
+typedef struct ucp_handle ucp_handle;
+
+/* Library version string. */
+const char* ucp_version(void);
+
+/* Message of the last error on the calling thread ("" if none). */
+const char* ucp_last_error(void);
+
+/* Create a handle on HIP device `device`.  Allocates no device memory yet;
+ * the workspace grows on first use.  Errors: UCP_EINVAL (null out),
+ * UCP_EHIP (no such device). */
+int ucp_create(ucp_handle** out, int device);
+
+/* Release the handle and its workspace (synchronises the device first).
+ * NULL is a no-op. */
+void ucp_destroy(ucp_handle* h);
+
+/* Marginal cost of the first controller (Section III-A, definition of C_m
+ * applied to the Section V-A objective):
+ *   L0_out[i*n_cand + c] = f(x_i) * ( k^2 u^2
+ *        + dy * sum_j phi(y_j - x_i - u) (x_i + u - u1[j])^2 ),
+ *   u = u[i*n_cand + c], phi the N(0,1) density.
+ * u1: [n_y]; u: [n_x * n_cand] row-major per point; L0_out: [n_x * n_cand].
+ * The sum runs over the nodes within 9 (FP32 modes) or 12 (FP64) noise
+ * standard deviations of the node nearest x_i + u, scaled by the Gaussian
+ * at that node (max-shift); omitted weight is below 3e-18 relative.
+ * Errors: UCP_EINVAL for null pointers, n_cand < 1, invalid problem. */
+int ucp_marginal_cost(ucp_handle* h, const ucp_problem* prob, ucp_prec prec,
+                      const double* u1, const double* u, int64_t n_cand,
+                      double* L0_out, void* stream);
+
+/* One pointwise improvement of u0 (Corollary 1 with the update rule of
+ * Section III-B, all points in parallel as in Section IV-A): for every x_i
+ * the coarse-to-fine search of ucp_search over u of
+ * B(u; x_i) = L_0(u, x_i) / f(x_i), with u1 held fixed.
+ * Selection at every level and at the final comparison with the incumbent:
+ * the candidates within a relative band 1e-12 of the minimum (in FP64) are
+ * ties, the one nearest u0_in[i] wins, then the smaller u.  In the FP32
+ * modes the minimum and band are first found in FP32 with a band of 1e-5
+ * and the band members are re-evaluated in FP64 before the rule is applied.
+ * u1: [n_y]; u0_in, u0_out: [n_x] (may alias); L0_out: [n_x] or NULL - if
+ * given, receives f(x_i) * B(u0_out[i]; x_i) evaluated in FP64.
+ * Errors: UCP_EINVAL (null pointers, invalid problem or search). */
+int ucp_argmin_adaptive(ucp_handle* h, const ucp_problem* prob, const ucp_search* search,
+                        ucp_prec prec, const double* u1, const double* u0_in,
+                        double* u0_out, double* L0_out, void* stream);
+
+/* Second controller by its closed form, the conditional mean
+ * u1(y_j) = sum_i x1_i f_i phi(y_j - x1_i) / sum_i f_i phi(y_j - x1_i),
+ * x1_i = x_i + u0[i], the exact minimiser of the discrete marginal cost
+ * C_1 (the closed form the paper credits to the earlier solver, Section
+ * IV-B).  Weights are max-shifted per y_j; in the FP32 modes the weights and
+ * the numerator sum are FP32 and the denominator sum is FP64.
+ * u0: [n_x]; u1_out: [n_y].  Errors: UCP_EINVAL. */
+int ucp_update_u1(ucp_handle* h, const ucp_problem* prob, ucp_prec prec,
+                  const double* u0, double* u1_out, void* stream);
+
+/* Objective of Section V-A by the rectangle rule, in FP64:
+ * J = dx * sum_i f_i [k^2 u0_i^2 + dy * sum_j phi(y_j - x1_i)(x1_i - u1_j)^2].
+ * u0: [n_x]; u1: [n_y]; J_out: one double on the device.
+ * Errors: UCP_EINVAL. */
+int ucp_objective(ucp_handle* h, const ucp_problem* prob, const double* u0,
+                  const double* u1, double* J_out, void* stream);
+
+/* The solve loop: u1 <- closed form of u0_init, J_hist[0] = J; then
+ * `iters` rounds of (ucp_argmin_adaptive on u0, ucp_update_u1), with
+ * J_hist[t] taken after round t.  This is the per-controller loop of
+ * Algorithm 1 with the two controllers visited in order, run for a fixed
+ * number of rounds; every step stays on the device.
+ * u0_init, u0_out: [n_x]; u1_out: [n_y]; J_hist: [iters + 1].
+ * Errors: UCP_EINVAL (iters < 0, invalid inputs). */
+int ucp_solve(ucp_handle* h, const ucp_problem* prob, const ucp_search* search, ucp_prec prec,
+              int32_t iters, const double* u0_init, double* u0_out, double* u1_out,
+              double* J_hist, void* stream);
+
+/* Algorithmic marginal-cost terms of the last ucp_solve / ucp_solve_batch
+ * on this handle: the number of (point, candidate, y node) triples with
+ * |y_j - x_i - u| <= 9 over every level and round (the work the method
+ * needs; the kernels evaluate a few more).  Errors: UCP_EINVAL. */
+int ucp_last_terms(ucp_handle* h, uint64_t* terms);
+
+/* B independent solves advanced together: every kernel launch covers all
+ * instances still running (one flat work list per launch), each instance
+ * with its own problem, search and iteration count.  Per-instance results
+ * are bitwise identical to ucp_solve on that instance alone.
+ * All pointer arrays have B entries (host arrays of device pointers).
+ * Errors: UCP_EINVAL.  Synchronises the stream before returning. */
+int ucp_solve_batch(ucp_handle* h, int32_t B, const ucp_problem* probs,
+                    const ucp_search* searches, ucp_prec prec, const int32_t* iters,
+                    const double* const* u0_init, double* const* u0_out,
+                    double* const* u1_out, double* const* J_hist, void* stream);
+
+/* ---- Continuous-batching server --------------------------------------
+ * Requests (HOST arrays) are admitted while the number of running solves is
+ * below `max_slots` and their device footprint fits in `hbm_budget` bytes;
+ * each call to ucp_server_step() admits what fits, runs one round
+ * (u0 update + u1 update + objective) for every running solve in shared
+ * launches, and retires the finished ones (results copied to host).
+ * Results are bitwise identical to ucp_solve of the same request alone. */
+typedef struct ucp_server ucp_server;
+
+/* Device bytes one solve of this problem and search needs (state and
+ * partial sums) at precision `prec` for `iters` rounds: the footprint the
+ * server's admission test uses.  Errors: UCP_EINVAL. */
+int ucp_footprint(const ucp_problem* prob, const ucp_search* search, ucp_prec prec, int32_t iters,
+                  size_t* bytes);
+
+/* Create a server on `device`.  hbm_budget = 0 means no memory limit. */
+int ucp_server_create(ucp_server** out, int device, size_t hbm_budget, int32_t max_slots, ucp_prec prec);
+void ucp_server_destroy(ucp_server* s);
+
+/* Queue a request; u0_init is a host array [n_x], copied at submission.
+ * Returns a ticket (> 0).  Errors: UCP_EINVAL, UCP_ENOMEM (a request that
+ * can never fit the budget). */
+int ucp_server_submit(ucp_server* s, const ucp_problem* prob, const ucp_search* search,
+                      int32_t iters, const double* u0_init, int64_t* ticket);
+
+/* Admit, run one round for all running solves, retire finished ones.
+ * *n_running (may be NULL) receives the number of solves still running.
+ * Synchronises the server's stream. */
+int ucp_server_step(ucp_server* s, int32_t* n_running);
+
+/* Collect a finished request: u0_out [n_x], u1_out [n_y], J_hist [iters+1]
+ * are HOST arrays (any may be NULL).  UCP_EAGAIN while queued or running,
+ * UCP_ENOTFOUND for an unknown ticket, UCP_ENONFINITE if the solve produced
+ * non-finite values (its outputs are still copied). */
+int ucp_server_poll(ucp_server* s, int64_t ticket, double* u0_out, double* u1_out, double* J_hist);
+
+/* Cancel a queued or running request (its slot is freed at once). */
+int ucp_server_cancel(ucp_server* s, int64_t ticket);
+
+/* Counts: queued, running, finished-but-uncollected. */
+int ucp_server_stats(ucp_server* s, int32_t* queued, int32_t* running, int32_t* done);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* UCP_H_ */

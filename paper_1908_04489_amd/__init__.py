@@ -1,0 +1,342 @@
+"""Python binding of the MI355X marginal-cost solver (C ABI in include/ucp.h).
+
+Argument marshalling only: every step of the solver runs in the HIP kernels
+of ``libucp.so``.  PyTorch provides device memory (tensors) and the stream
+(``torch.cuda.current_stream()``).  The library must be built first
+(``paper_1908_04489_amd.build.build()``); importing this module without it
+raises immediately - there is no CPU fallback.
+
+Problem and search objects are duck-typed: ``k``, ``comps`` (sequence of
+``(weight, mean, sd)``), ``x_lo``, ``x_hi``, ``n_x``, ``y_lo``, ``y_hi``,
+``n_y``; and ``u_lo``, ``u_hi``, ``levels``, ``cands``.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import re
+import threading
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libucp.so")
+HEADER = os.path.join(os.path.dirname(HERE), "include", "ucp.h")
+
+FP32, FP32_KAHAN, FP64 = 0, 1, 2
+PRECS = {"fp32": FP32, "fp32_kahan": FP32_KAHAN, "kahan": FP32_KAHAN, "fp64": FP64}
+OK, EINVAL, ENOMEM, EHIP, EAGAIN, ENONFINITE, ENOTFOUND = 0, -1, -2, -3, -4, -5, -6
+MAX_COMP = 8
+
+
+class UcpError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"ucp error {code}: {msg}")
+        self.code = code
+
+
+class Problem(C.Structure):
+    _fields_ = [
+        ("k", C.c_double), ("n_comp", C.c_int32), ("pad_", C.c_int32),
+        ("w", C.c_double * MAX_COMP), ("mu", C.c_double * MAX_COMP), ("sd", C.c_double * MAX_COMP),
+        ("x_lo", C.c_double), ("x_hi", C.c_double), ("n_x", C.c_int64),
+        ("y_lo", C.c_double), ("y_hi", C.c_double), ("n_y", C.c_int64),
+    ]
+
+
+class Search(C.Structure):
+    _fields_ = [("u_lo", C.c_double), ("u_hi", C.c_double), ("levels", C.c_int32), ("cands", C.c_int32)]
+
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"{LIB_PATH} is missing: build it with paper_1908_04489_amd.build.build() "
+                      "(the solver has no CPU fallback)")
+_lib = C.CDLL(LIB_PATH)
+
+_vp = C.c_void_p
+_P = C.POINTER
+_sigs = {
+    "ucp_version": ([], C.c_char_p),
+    "ucp_last_error": ([], C.c_char_p),
+    "ucp_create": ([_P(_vp), C.c_int], C.c_int),
+    "ucp_destroy": ([_vp], None),
+    "ucp_marginal_cost": ([_vp, _P(Problem), C.c_int, _vp, _vp, C.c_int64, _vp, _vp], C.c_int),
+    "ucp_argmin_adaptive": ([_vp, _P(Problem), _P(Search), C.c_int, _vp, _vp, _vp, _vp, _vp], C.c_int),
+    "ucp_update_u1": ([_vp, _P(Problem), C.c_int, _vp, _vp, _vp], C.c_int),
+    "ucp_objective": ([_vp, _P(Problem), _vp, _vp, _vp, _vp], C.c_int),
+    "ucp_solve": ([_vp, _P(Problem), _P(Search), C.c_int, C.c_int32, _vp, _vp, _vp, _vp, _vp], C.c_int),
+    "ucp_solve_batch": ([_vp, C.c_int32, _P(Problem), _P(Search), C.c_int, _P(C.c_int32), _P(_vp), _P(_vp),
+                         _P(_vp), _P(_vp), _vp], C.c_int),
+    "ucp_last_terms": ([_vp, _P(C.c_uint64)], C.c_int),
+    "ucp_footprint": ([_P(Problem), _P(Search), C.c_int, C.c_int32, _P(C.c_size_t)], C.c_int),
+    "ucp_server_create": ([_P(_vp), C.c_int, C.c_size_t, C.c_int32, C.c_int], C.c_int),
+    "ucp_server_destroy": ([_vp], None),
+    "ucp_server_submit": ([_vp, _P(Problem), _P(Search), C.c_int32, _vp, _P(C.c_int64)], C.c_int),
+    "ucp_server_step": ([_vp, _P(C.c_int32)], C.c_int),
+    "ucp_server_poll": ([_vp, C.c_int64, _vp, _vp, _vp], C.c_int),
+    "ucp_server_cancel": ([_vp, C.c_int64], C.c_int),
+    "ucp_server_stats": ([_vp, _P(C.c_int32), _P(C.c_int32), _P(C.c_int32)], C.c_int),
+}
+for _name, (_args, _res) in _sigs.items():
+    _f = getattr(_lib, _name)
+    _f.argtypes = _args
+    _f.restype = _res
+
+
+def header_functions():
+    """Names of the functions declared in include/ucp.h."""
+    txt = open(HEADER).read()
+    return sorted(set(re.findall(r"^\s*(?:const\s+)?[\w\s\*]*?\b(ucp_\w+)\s*\(", txt, re.M)))
+
+
+def library():
+    return _lib
+
+
+def last_error() -> str:
+    return _lib.ucp_last_error().decode()
+
+
+def _check(rc):
+    if rc != OK:
+        raise UcpError(rc, last_error())
+    return rc
+
+
+def make_problem(p) -> Problem:
+    comps = list(p.comps)
+    s = Problem()
+    s.k = float(p.k)
+    s.n_comp = len(comps)
+    for c, (w, mu, sd) in enumerate(comps):
+        s.w[c], s.mu[c], s.sd[c] = float(w), float(mu), float(sd)
+    s.x_lo, s.x_hi, s.n_x = float(p.x_lo), float(p.x_hi), int(p.n_x)
+    s.y_lo, s.y_hi, s.n_y = float(p.y_lo), float(p.y_hi), int(p.n_y)
+    return s
+
+
+def make_search(s) -> Search:
+    r = Search()
+    r.u_lo, r.u_hi, r.levels, r.cands = float(s.u_lo), float(s.u_hi), int(s.levels), int(s.cands)
+    return r
+
+
+def _prec(prec) -> int:
+    if isinstance(prec, str):
+        return PRECS[prec.lower()]
+    return int(prec)
+
+
+# ------------------------------------------------------------ torch plumbing
+
+def _torch():
+    import torch
+
+    return torch
+
+
+def _dev_f64(t, n, name):
+    torch = _torch()
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a CUDA (HIP) tensor")
+    if t.dtype != torch.float64 or not t.is_contiguous():
+        raise TypeError(f"{name} must be contiguous float64")
+    if n is not None and t.numel() != n:
+        raise ValueError(f"{name} must have {n} elements, has {t.numel()}")
+    return t
+
+
+def _stream(device):
+    torch = _torch()
+    return _vp(torch.cuda.current_stream(device).cuda_stream)
+
+
+_handles = threading.local()
+
+
+def handle(device: int = 0):
+    """Per-thread, per-device library handle."""
+    d = getattr(_handles, "d", None)
+    if d is None:
+        d = _handles.d = {}
+    if device not in d:
+        h = _vp()
+        _check(_lib.ucp_create(C.byref(h), int(device)))
+        d[device] = h
+    return d[device]
+
+
+def _dev(t):
+    return t.device.index if t.device.index is not None else 0
+
+
+def marginal_cost(prob, u1, u, prec="fp32_kahan"):
+    """L_0 = f(x_i) B(u; x_i) for candidates u [n_x, n_cand] (device, FP64)."""
+    torch = _torch()
+    P = make_problem(prob)
+    _dev_f64(u1, P.n_y, "u1")
+    _dev_f64(u, None, "u")
+    if u.dim() != 2 or u.shape[0] != P.n_x:
+        raise ValueError("u must be [n_x, n_cand]")
+    out = torch.empty_like(u)
+    d = _dev(u1)
+    _check(_lib.ucp_marginal_cost(handle(d), C.byref(P), _prec(prec), _vp(u1.data_ptr()), _vp(u.data_ptr()),
+                                  u.shape[1], _vp(out.data_ptr()), _stream(d)))
+    return out
+
+
+def argmin_adaptive(prob, search, u1, u0, prec="fp32_kahan", want_l0=False):
+    """One coarse-to-fine u0 update with u1 fixed.  Returns u0_out (and L0)."""
+    torch = _torch()
+    P, S = make_problem(prob), make_search(search)
+    _dev_f64(u1, P.n_y, "u1")
+    _dev_f64(u0, P.n_x, "u0")
+    out = torch.empty_like(u0)
+    l0 = torch.empty_like(u0) if want_l0 else None
+    d = _dev(u0)
+    _check(_lib.ucp_argmin_adaptive(handle(d), C.byref(P), C.byref(S), _prec(prec), _vp(u1.data_ptr()),
+                                    _vp(u0.data_ptr()), _vp(out.data_ptr()),
+                                    _vp(l0.data_ptr() if l0 is not None else 0), _stream(d)))
+    return (out, l0) if want_l0 else out
+
+
+def update_u1(prob, u0, prec="fp32_kahan"):
+    torch = _torch()
+    P = make_problem(prob)
+    _dev_f64(u0, P.n_x, "u0")
+    out = torch.empty(P.n_y, dtype=torch.float64, device=u0.device)
+    d = _dev(u0)
+    _check(_lib.ucp_update_u1(handle(d), C.byref(P), _prec(prec), _vp(u0.data_ptr()), _vp(out.data_ptr()),
+                              _stream(d)))
+    return out
+
+
+def objective(prob, u0, u1):
+    """J as a 1-element device tensor (FP64)."""
+    torch = _torch()
+    P = make_problem(prob)
+    _dev_f64(u0, P.n_x, "u0")
+    _dev_f64(u1, P.n_y, "u1")
+    out = torch.empty(1, dtype=torch.float64, device=u0.device)
+    d = _dev(u0)
+    _check(_lib.ucp_objective(handle(d), C.byref(P), _vp(u0.data_ptr()), _vp(u1.data_ptr()),
+                              _vp(out.data_ptr()), _stream(d)))
+    return out
+
+
+def solve(prob, search, iters, u0_init, prec="fp32_kahan"):
+    """Returns (u0, u1, J_hist[iters + 1]) as device tensors."""
+    torch = _torch()
+    P, S = make_problem(prob), make_search(search)
+    _dev_f64(u0_init, P.n_x, "u0_init")
+    dev = u0_init.device
+    u0 = torch.empty(P.n_x, dtype=torch.float64, device=dev)
+    u1 = torch.empty(P.n_y, dtype=torch.float64, device=dev)
+    J = torch.empty(int(iters) + 1, dtype=torch.float64, device=dev)
+    d = _dev(u0_init)
+    _check(_lib.ucp_solve(handle(d), C.byref(P), C.byref(S), _prec(prec), int(iters), _vp(u0_init.data_ptr()),
+                          _vp(u0.data_ptr()), _vp(u1.data_ptr()), _vp(J.data_ptr()), _stream(d)))
+    return u0, u1, J
+
+
+def solve_batch(probs, searches, iters, u0_inits, prec="fp32_kahan"):
+    """Independent solves in shared launches.  Returns lists (u0, u1, J)."""
+    torch = _torch()
+    B = len(probs)
+    Ps = (Problem * B)(*[make_problem(p) for p in probs])
+    Ss = (Search * B)(*[make_search(s) for s in searches])
+    its = (C.c_int32 * B)(*[int(t) for t in iters])
+    u0o, u1o, Jo = [], [], []
+    for b in range(B):
+        _dev_f64(u0_inits[b], Ps[b].n_x, f"u0_init[{b}]")
+        dev = u0_inits[b].device
+        u0o.append(torch.empty(Ps[b].n_x, dtype=torch.float64, device=dev))
+        u1o.append(torch.empty(Ps[b].n_y, dtype=torch.float64, device=dev))
+        Jo.append(torch.empty(int(iters[b]) + 1, dtype=torch.float64, device=dev))
+
+    def ptrs(ts):
+        return (_vp * B)(*[t.data_ptr() for t in ts])
+
+    d = _dev(u0_inits[0])
+    _check(_lib.ucp_solve_batch(handle(d), B, Ps, Ss, _prec(prec), its, ptrs(u0_inits), ptrs(u0o), ptrs(u1o),
+                                ptrs(Jo), _stream(d)))
+    return u0o, u1o, Jo
+
+
+def last_terms(device: int = 0) -> int:
+    """Algorithmic marginal-cost terms of the last solve on this thread's handle."""
+    n = C.c_uint64()
+    _check(_lib.ucp_last_terms(handle(device), C.byref(n)))
+    return n.value
+
+
+def footprint(prob, search, iters, prec="fp32_kahan") -> int:
+    """Device bytes of one solve (the server's admission footprint)."""
+    P, S = make_problem(prob), make_search(search)
+    n = C.c_size_t()
+    _check(_lib.ucp_footprint(C.byref(P), C.byref(S), _prec(prec), int(iters), C.byref(n)))
+    return n.value
+
+
+class Server:
+    """Continuous-batching server (host arrays in and out)."""
+
+    def __init__(self, device=0, hbm_budget=0, max_slots=64, prec="fp32_kahan"):
+        self._s = _vp()
+        _check(_lib.ucp_server_create(C.byref(self._s), int(device), int(hbm_budget), int(max_slots),
+                                      _prec(prec)))
+        self._meta = {}
+
+    def close(self):
+        if self._s:
+            _lib.ucp_server_destroy(self._s)
+            self._s = _vp()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def submit(self, prob, search, iters, u0_init) -> int:
+        import numpy as np
+
+        P, S = make_problem(prob), make_search(search)
+        a = np.ascontiguousarray(u0_init, dtype=np.float64)
+        if a.shape != (P.n_x,):
+            raise ValueError("u0_init must be [n_x]")
+        t = C.c_int64()
+        _check(_lib.ucp_server_submit(self._s, C.byref(P), C.byref(S), int(iters), _vp(a.ctypes.data),
+                                      C.byref(t)))
+        self._meta[t.value] = (int(P.n_x), int(P.n_y), int(iters))
+        return t.value
+
+    def step(self) -> int:
+        n = C.c_int32()
+        _check(_lib.ucp_server_step(self._s, C.byref(n)))
+        return n.value
+
+    def poll(self, ticket):
+        """(u0, u1, J) numpy arrays when done, None while queued/running."""
+        import numpy as np
+
+        nx, ny, it = self._meta[ticket]
+        u0 = np.empty(nx)
+        u1 = np.empty(ny)
+        J = np.empty(it + 1)
+        rc = _lib.ucp_server_poll(self._s, int(ticket), _vp(u0.ctypes.data), _vp(u1.ctypes.data),
+                                  _vp(J.ctypes.data))
+        if rc == EAGAIN:
+            return None
+        if rc == ENONFINITE:
+            del self._meta[ticket]
+            raise UcpError(rc, last_error())
+        _check(rc)
+        del self._meta[ticket]
+        return u0, u1, J
+
+    def cancel(self, ticket):
+        _check(_lib.ucp_server_cancel(self._s, int(ticket)))
+
+    def stats(self):
+        q, r, d = C.c_int32(), C.c_int32(), C.c_int32()
+        _check(_lib.ucp_server_stats(self._s, C.byref(q), C.byref(r), C.byref(d)))
+        return q.value, r.value, d.value

@@ -1,0 +1,517 @@
+// Host runtime of the marginal-cost solver: argument checks, the handle and
+// its device workspace, launch tables over batches of instances, and the
+// solve loop.  Everything numerical runs in the HIP kernels
+// (ucp_kernels.hip); this file only validates, lays out memory and enqueues.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "ucp_internal.h"
+#include "ucp_runtime.h"
+
+namespace ucp {
+
+thread_local std::string g_err;
+
+int fail(int code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return code;
+}
+
+int hip_fail(hipError_t e, const char* what) {
+  return fail(UCP_EHIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+int check_problem(const ucp_problem* p) {
+  if (!p) return fail(UCP_EINVAL, "problem is NULL");
+  if (!(p->k >= 0.0) || !std::isfinite(p->k)) return fail(UCP_EINVAL, "k must be finite and >= 0");
+  if (p->n_comp < 1 || p->n_comp > UCP_MAX_COMP) return fail(UCP_EINVAL, "n_comp must be 1..%d", UCP_MAX_COMP);
+  double ws = 0.0;
+  for (int c = 0; c < p->n_comp; ++c) {
+    if (!(p->w[c] > 0.0) || !std::isfinite(p->w[c])) return fail(UCP_EINVAL, "prior weight %d must be > 0", c);
+    if (!(p->sd[c] > 0.0) || !std::isfinite(p->sd[c])) return fail(UCP_EINVAL, "prior sd %d must be > 0", c);
+    if (!std::isfinite(p->mu[c])) return fail(UCP_EINVAL, "prior mean %d must be finite", c);
+    ws += p->w[c];
+  }
+  if (std::fabs(ws - 1.0) > 1e-9) return fail(UCP_EINVAL, "prior weights must sum to 1 (got %.17g)", ws);
+  if (p->n_x < 2 || p->n_y < 2) return fail(UCP_EINVAL, "grids need at least 2 nodes");
+  if (p->n_x > (int64_t)1 << 28 || p->n_y > (int64_t)1 << 28) return fail(UCP_EINVAL, "grid too large");
+  if (!(p->x_lo < p->x_hi) || !std::isfinite(p->x_lo) || !std::isfinite(p->x_hi))
+    return fail(UCP_EINVAL, "x grid needs finite x_lo < x_hi");
+  if (!(p->y_lo < p->y_hi) || !std::isfinite(p->y_lo) || !std::isfinite(p->y_hi))
+    return fail(UCP_EINVAL, "y grid needs finite y_lo < y_hi");
+  if (std::fabs(p->x_lo) > 1e6 || std::fabs(p->x_hi) > 1e6 || std::fabs(p->y_lo) > 1e6 || std::fabs(p->y_hi) > 1e6)
+    return fail(UCP_EINVAL, "grid bounds beyond 1e6");
+  return UCP_OK;
+}
+
+int check_search(const ucp_search* s) {
+  if (!s) return fail(UCP_EINVAL, "search is NULL");
+  if (s->levels < 1 || s->levels > UCP_MAX_LEVELS) return fail(UCP_EINVAL, "levels must be 1..%d", UCP_MAX_LEVELS);
+  if (s->cands < 2 || s->cands > UCP_MAX_CANDS) return fail(UCP_EINVAL, "cands must be 2..%d", UCP_MAX_CANDS);
+  if (!(s->u_lo < s->u_hi) || !std::isfinite(s->u_lo) || !std::isfinite(s->u_hi))
+    return fail(UCP_EINVAL, "search needs finite u_lo < u_hi");
+  if (std::fabs(s->u_lo) > 1e6 || std::fabs(s->u_hi) > 1e6) return fail(UCP_EINVAL, "search bounds beyond 1e6");
+  return UCP_OK;
+}
+
+int check_prec(int prec) {
+  if (prec != UCP_FP32 && prec != UCP_FP32_KAHAN && prec != UCP_FP64)
+    return fail(UCP_EINVAL, "unknown precision %d", prec);
+  return UCP_OK;
+}
+
+// Constants and launch geometry of one instance.  Everything here depends on
+// the instance alone, never on the batch it runs in.
+Inst make_inst(const ucp_problem& p, const ucp_search* s, int prec, int cands_override) {
+  Inst I;
+  std::memset(&I, 0, sizeof I);
+  I.k2 = p.k * p.k;
+  I.x_lo = p.x_lo;
+  I.dx = (p.x_hi - p.x_lo) / (double)(p.n_x - 1);
+  I.y_lo = p.y_lo;
+  I.dy = (p.y_hi - p.y_lo) / (double)(p.n_y - 1);
+  I.inv_dy = 1.0 / I.dy;
+  I.phi_scale = I.dy * kInvSqrt2Pi;
+  I.n_comp = p.n_comp;
+  for (int c = 0; c < p.n_comp; ++c) {
+    I.w[c] = p.w[c];
+    I.mu[c] = p.mu[c];
+    I.sd[c] = p.sd[c];
+  }
+  I.n_x = (int32_t)p.n_x;
+  I.n_y = (int32_t)p.n_y;
+  if (s) {
+    I.levels = s->levels;
+    I.cands = s->cands;
+    I.u_lo = s->u_lo;
+    I.u_hi = s->u_hi;
+    // spacings: h0 spans the range with `cands` nodes, each later level spans
+    // twice the previous spacing with `cands` nodes
+    I.h[0] = (s->u_hi - s->u_lo) / (double)(s->cands - 1);
+    for (int l = 1; l < s->levels; ++l) I.h[l] = 2.0 * I.h[l - 1] / (double)(s->cands - 1);
+  } else {
+    I.levels = 1;
+    I.cands = cands_override;
+  }
+  if (cands_override > 0) I.cands = cands_override;
+  I.nw32 = (int32_t)std::min<double>(std::ceil(kWin32 / I.dy), (double)I.n_y);
+  I.nw64 = (int32_t)std::min<double>(std::ceil(kWin64 / I.dy), (double)I.n_y);
+  I.prec = prec;
+  // window segments: enough work units to fill the GPU when the instance is
+  // small, segments of at least 256 nodes
+  if (prec == UCP_FP64) {
+    I.segs = 1;
+  } else {
+    const int tiles = (I.n_x + kMcBlock - 1) / kMcBlock;
+    const int kq = I.cands + 1;
+    const int wlen = 2 * I.nw32 + 1;
+    int want = (8192 + tiles * kq - 1) / (tiles * kq);
+    int cap = std::max(1, wlen / 256);
+    int sg = 1;
+    while (sg < want && sg < 16) sg <<= 1;
+    sg = std::max(1, std::min(sg, cap));
+    I.segs = std::max(sg, (wlen + kMcSegMax - 1) / kMcSegMax);
+  }
+  const int slen = std::max(512, (I.n_x + 31) / 32);
+  I.u1_slices = (I.n_x + slen - 1) / slen;
+  return I;
+}
+
+static size_t align_up(size_t v) { return (v + 255) & ~(size_t)255; }
+
+size_t state_bytes(const Inst& I) {
+  size_t nx = (size_t)I.n_x, ny = (size_t)I.n_y;
+  size_t b = 0;
+  b += 9 * align_up(nx * 8);                                      // u0 u0_next f logf cbest b32best b64best b32inc jrow
+  b += align_up(ny * 8) + align_up(ny * 4);                       // u1 v
+  b += align_up(nx * (size_t)(I.cands + 1) * (size_t)I.segs * 8); // part
+  b += align_up((size_t)I.u1_slices * ny * 3 * 8);                // u1part
+  b += 256;                                                       // flags
+  return b;
+}
+
+void carve_state(Inst& I, char*& base) {
+  size_t nx = (size_t)I.n_x, ny = (size_t)I.n_y;
+  auto take = [&](size_t bytes) {
+    char* p = base;
+    base += align_up(bytes);
+    return p;
+  };
+  I.u0 = (double*)take(nx * 8);
+  I.u0_next = (double*)take(nx * 8);
+  I.f = (double*)take(nx * 8);
+  I.logf = (double*)take(nx * 8);
+  I.cbest = (double*)take(nx * 8);
+  I.b32best = (double*)take(nx * 8);
+  I.b64best = (double*)take(nx * 8);
+  I.b32inc = (double*)take(nx * 8);
+  I.jrow = (double*)take(nx * 8);
+  I.u1 = (double*)take(ny * 8);
+  I.v = (float*)take(ny * 4);
+  I.part = (double*)take(nx * (size_t)(I.cands + 1) * (size_t)I.segs * 8);
+  I.u1part = (double*)take((size_t)I.u1_slices * ny * 3 * 8);
+  I.flags = (int32_t*)take(256);
+  I.terms = (unsigned long long*)((char*)I.flags + 64);
+}
+
+// Prefix sums of units for each kernel over a batch, for one set of running
+// instances.  Layout: kinds x (n + 1).
+std::vector<int32_t> build_tables(const std::vector<Inst>& insts, const std::vector<char>& running) {
+  const int n = (int)insts.size();
+  std::vector<int32_t> t((size_t)kKinds * (n + 1), 0);
+  for (int k = 0; k < kKinds; ++k) {
+    int32_t* pre = &t[(size_t)k * (n + 1)];
+    pre[0] = 0;
+    for (int b = 0; b < n; ++b) {
+      const Inst& I = insts[b];
+      int32_t u = 0;
+      if (running[b]) {
+        if (k < kKindSel0) u = I.free_cands ? 0 : units_mc(I, k - kKindMc0);
+        else if (k < kKindU1p) u = (k - kKindSel0) < I.levels ? units_select(I) : 0;
+        else if (k == kKindU1p) u = units_u1_partial(I);
+        else if (k == kKindU1c) u = units_u1_combine(I);
+        else if (k == kKindJRows) u = units_j_rows(I);
+        else if (k == kKindJRed) u = 1;
+        else if (k == kKindPrior) u = units_prior(I);
+        else if (k == kKindCopy) u = units_prior(I);
+        else if (k == kKindFree) u = I.free_cands ? units_mc(I, -1) : 0;
+        else if (k == kKindFin) u = I.free_cands ? (int32_t)(((int64_t)I.n_x * I.cands + 255) / 256) : 0;
+      }
+      pre[b + 1] = pre[b] + u;
+    }
+  }
+  return t;
+}
+
+}  // namespace ucp
+
+using namespace ucp;
+
+struct ucp_handle {
+  int device = 0;
+  void* ws = nullptr;
+  size_t ws_bytes = 0;
+  unsigned long long last_terms = 0;  // algorithmic terms of the last solve
+};
+
+static int ensure_ws(ucp_handle* h, size_t bytes) {
+  if (bytes <= h->ws_bytes) return UCP_OK;
+  hipError_t e = hipSetDevice(h->device);
+  if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
+  if (h->ws) {
+    (void)hipDeviceSynchronize();
+    (void)hipFree(h->ws);
+    h->ws = nullptr;
+    h->ws_bytes = 0;
+  }
+  size_t want = align_up(bytes + bytes / 8);
+  e = hipMalloc(&h->ws, want);
+  if (e != hipSuccess) {
+    h->ws = nullptr;
+    return fail(UCP_ENOMEM, "workspace of %zu bytes: %s", want, hipGetErrorString(e));
+  }
+  h->ws_bytes = want;
+  return UCP_OK;
+}
+
+extern "C" {
+
+int ucp_last_terms(ucp_handle* h, uint64_t* terms) {
+  if (!h || !terms) return fail(UCP_EINVAL, "NULL argument");
+  *terms = h->last_terms;
+  return UCP_OK;
+}
+
+const char* ucp_version(void) { return "ucp-mi355x 0.1 (gfx950)"; }
+
+const char* ucp_last_error(void) { return g_err.c_str(); }
+
+int ucp_create(ucp_handle** out, int device) {
+  if (!out) return fail(UCP_EINVAL, "out is NULL");
+  *out = nullptr;
+  int n = 0;
+  hipError_t e = hipGetDeviceCount(&n);
+  if (e != hipSuccess || n <= 0) return fail(UCP_EHIP, "no HIP device available");
+  if (device < 0 || device >= n) return fail(UCP_EINVAL, "device %d out of range (have %d)", device, n);
+  e = hipSetDevice(device);
+  if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
+  ucp_handle* h = new ucp_handle;
+  h->device = device;
+  *out = h;
+  return UCP_OK;
+}
+
+void ucp_destroy(ucp_handle* h) {
+  if (!h) return;
+  if (h->ws) {
+    (void)hipSetDevice(h->device);
+    (void)hipDeviceSynchronize();
+    (void)hipFree(h->ws);
+  }
+  delete h;
+}
+
+}  // extern "C"
+
+namespace ucp {
+
+// A batch laid out in the handle's workspace: instance table, launch tables
+// and per-instance state.
+struct Batch {
+  std::vector<Inst> insts;
+  Inst* d_insts = nullptr;
+  int32_t* d_tables = nullptr;  // phases x kinds x (n + 1)
+  int n = 0;
+  Launch launch(int phase, int kind, const std::vector<int32_t>& host_tab) const {
+    Launch L;
+    L.insts = d_insts;
+    L.n_inst = n;
+    const size_t off = ((size_t)phase * kKinds + kind) * (n + 1);
+    L.pre = d_tables + off;
+    L.total = host_tab[off + n];
+    return L;
+  }
+};
+
+int setup_batch(ucp_handle* h, Batch& B, std::vector<Inst> insts, const std::vector<std::vector<char>>& phases,
+                std::vector<int32_t>& host_tab, hipStream_t st) {
+  B.n = (int)insts.size();
+  size_t bytes = align_up(sizeof(Inst) * B.n) + align_up(sizeof(int32_t) * phases.size() * kKinds * (B.n + 1));
+  for (auto& I : insts) bytes += state_bytes(I);
+  int rc = ensure_ws(h, bytes);
+  if (rc) return rc;
+  char* base = (char*)h->ws;
+  B.d_insts = (Inst*)base;
+  base += align_up(sizeof(Inst) * B.n);
+  B.d_tables = (int32_t*)base;
+  base += align_up(sizeof(int32_t) * phases.size() * kKinds * (B.n + 1));
+  for (auto& I : insts) carve_state(I, base);
+  host_tab.clear();
+  for (auto& run : phases) {
+    std::vector<int32_t> t = build_tables(insts, run);
+    host_tab.insert(host_tab.end(), t.begin(), t.end());
+  }
+  B.insts = std::move(insts);
+  hipError_t e = hipMemcpyAsync(B.d_insts, B.insts.data(), sizeof(Inst) * B.n, hipMemcpyHostToDevice, st);
+  if (e != hipSuccess) return hip_fail(e, "upload instance table");
+  e = hipMemcpyAsync(B.d_tables, host_tab.data(), sizeof(int32_t) * host_tab.size(), hipMemcpyHostToDevice, st);
+  if (e != hipSuccess) return hip_fail(e, "upload launch tables");
+  return UCP_OK;
+}
+
+#define UCP_TRY(expr, what)                      \
+  do {                                           \
+    hipError_t e_ = (expr);                      \
+    if (e_ != hipSuccess) return hip_fail(e_, what); \
+  } while (0)
+
+// One round for the running instances of `phase`: the u0 update over all
+// levels, the u0 advance, the u1 update and the objective into J[t].
+int run_round(const Batch& B, int phase, const std::vector<int32_t>& tab, int prec, int max_levels, int t,
+              hipStream_t st) {
+  for (int l = 0; l < max_levels; ++l) {
+    UCP_TRY(launch_mc(B.launch(phase, kKindMc0 + l, tab), l, prec, st), "marginal-cost kernel");
+    UCP_TRY(launch_select(B.launch(phase, kKindSel0 + l, tab), l, prec, 0, st), "selection kernel");
+  }
+  UCP_TRY(launch_copy_u0(B.launch(phase, kKindCopy, tab), st), "u0 advance kernel");
+  UCP_TRY(launch_u1_partial(B.launch(phase, kKindU1p, tab), prec, st), "u1 kernel");
+  UCP_TRY(launch_u1_combine(B.launch(phase, kKindU1c, tab), st), "u1 combine kernel");
+  UCP_TRY(launch_j_rows(B.launch(phase, kKindJRows, tab), st), "objective kernel");
+  UCP_TRY(launch_j_reduce_t(B.launch(phase, kKindJRed, tab), t, st), "objective reduce kernel");
+  return UCP_OK;
+}
+
+// u1 and J[0] from the initial u0 (after the prior).
+int run_init(const Batch& B, int phase, const std::vector<int32_t>& tab, int prec, hipStream_t st) {
+  UCP_TRY(launch_prior(B.launch(phase, kKindPrior, tab), st), "prior kernel");
+  UCP_TRY(launch_u1_partial(B.launch(phase, kKindU1p, tab), prec, st), "u1 kernel");
+  UCP_TRY(launch_u1_combine(B.launch(phase, kKindU1c, tab), st), "u1 combine kernel");
+  UCP_TRY(launch_j_rows(B.launch(phase, kKindJRows, tab), st), "objective kernel");
+  UCP_TRY(launch_j_reduce_t(B.launch(phase, kKindJRed, tab), 0, st), "objective reduce kernel");
+  return UCP_OK;
+}
+
+}  // namespace ucp
+
+extern "C" {
+
+int ucp_solve_batch(ucp_handle* h, int32_t nb, const ucp_problem* probs, const ucp_search* searches,
+                    ucp_prec prec, const int32_t* iters, const double* const* u0_init,
+                    double* const* u0_out, double* const* u1_out, double* const* J_hist, void* stream) {
+  if (!h) return fail(UCP_EINVAL, "handle is NULL");
+  if (nb < 1) return fail(UCP_EINVAL, "batch size must be >= 1");
+  if (!probs || !searches || !iters || !u0_init || !u0_out || !u1_out || !J_hist)
+    return fail(UCP_EINVAL, "NULL array argument");
+  int rc = check_prec(prec);
+  if (rc) return rc;
+  int max_it = 0, max_lv = 0;
+  for (int b = 0; b < nb; ++b) {
+    if ((rc = check_problem(&probs[b]))) return fail(rc, "instance %d: %s", b, g_err.c_str());
+    if ((rc = check_search(&searches[b]))) return fail(rc, "instance %d: %s", b, g_err.c_str());
+    if (iters[b] < 0) return fail(UCP_EINVAL, "instance %d: iters < 0", b);
+    if (!u0_init[b] || !u0_out[b] || !u1_out[b] || !J_hist[b]) return fail(UCP_EINVAL, "instance %d: NULL pointer", b);
+    max_it = std::max(max_it, (int)iters[b]);
+    max_lv = std::max(max_lv, (int)searches[b].levels);
+  }
+  hipError_t e = hipSetDevice(h->device);
+  if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
+  hipStream_t st = (hipStream_t)stream;
+  std::vector<Inst> insts;
+  for (int b = 0; b < nb; ++b) insts.push_back(make_inst(probs[b], &searches[b], prec, 0));
+  // phases: phase t (0..max_it) runs the instances with iters >= t
+  std::vector<std::vector<char>> phases(max_it + 1, std::vector<char>(nb, 0));
+  std::vector<int> phase_of(max_it + 1, 0);
+  for (int t = 0; t <= max_it; ++t)
+    for (int b = 0; b < nb; ++b) phases[t][b] = iters[b] >= t;
+  Batch B;
+  std::vector<int32_t> tab;
+  if ((rc = setup_batch(h, B, insts, phases, tab, st))) return rc;
+  for (int b = 0; b < nb; ++b) {
+    Inst& I = B.insts[b];
+    UCP_TRY(hipMemcpyAsync(I.u0, u0_init[b], sizeof(double) * I.n_x, hipMemcpyDeviceToDevice, st), "copy u0_init");
+    UCP_TRY(hipMemsetAsync(I.flags, 0, 128, st), "clear flags and counters");
+  }
+  // J_out of each instance is its J_hist: set through a second table upload
+  for (int b = 0; b < nb; ++b) B.insts[b].J_out = J_hist[b];
+  UCP_TRY(hipMemcpyAsync(B.d_insts, B.insts.data(), sizeof(Inst) * nb, hipMemcpyHostToDevice, st), "upload instance table");
+  if ((rc = run_init(B, 0, tab, prec, st))) return rc;
+  for (int t = 1; t <= max_it; ++t)
+    if ((rc = run_round(B, t, tab, prec, max_lv, t, st))) return rc;
+  std::vector<int32_t> flags(nb, 0);
+  std::vector<unsigned long long> terms(nb, 0);
+  for (int b = 0; b < nb; ++b) {
+    Inst& I = B.insts[b];
+    UCP_TRY(hipMemcpyAsync(&terms[b], I.terms, 8, hipMemcpyDeviceToHost, st), "read counters");
+    UCP_TRY(hipMemcpyAsync(u0_out[b], I.u0, sizeof(double) * I.n_x, hipMemcpyDeviceToDevice, st), "copy u0_out");
+    UCP_TRY(hipMemcpyAsync(u1_out[b], I.u1, sizeof(double) * I.n_y, hipMemcpyDeviceToDevice, st), "copy u1_out");
+    UCP_TRY(hipMemcpyAsync(&flags[b], I.flags, 4, hipMemcpyDeviceToHost, st), "read flags");
+  }
+  UCP_TRY(hipStreamSynchronize(st), "synchronise");
+  h->last_terms = 0;
+  for (int b = 0; b < nb; ++b) h->last_terms += terms[b];
+  for (int b = 0; b < nb; ++b)
+    if (flags[b]) return fail(UCP_ENONFINITE, "instance %d produced non-finite values", b);
+  return UCP_OK;
+}
+
+int ucp_solve(ucp_handle* h, const ucp_problem* prob, const ucp_search* search, ucp_prec prec, int32_t iters,
+              const double* u0_init, double* u0_out, double* u1_out, double* J_hist, void* stream) {
+  if (!prob || !search) return fail(UCP_EINVAL, "NULL problem or search");
+  return ucp_solve_batch(h, 1, prob, search, prec, &iters, &u0_init, &u0_out, &u1_out, &J_hist, stream);
+}
+
+int ucp_argmin_adaptive(ucp_handle* h, const ucp_problem* prob, const ucp_search* search, ucp_prec prec,
+                        const double* u1, const double* u0_in, double* u0_out, double* L0_out, void* stream) {
+  if (!h) return fail(UCP_EINVAL, "handle is NULL");
+  int rc;
+  if ((rc = check_problem(prob)) || (rc = check_search(search)) || (rc = check_prec(prec))) return rc;
+  if (!u1 || !u0_in || !u0_out) return fail(UCP_EINVAL, "NULL array argument");
+  UCP_TRY(hipSetDevice(h->device), "hipSetDevice");
+  hipStream_t st = (hipStream_t)stream;
+  std::vector<std::vector<char>> phases(1, std::vector<char>(1, 1));
+  Batch B;
+  std::vector<int32_t> tab;
+  if ((rc = setup_batch(h, B, {make_inst(*prob, search, prec, 0)}, phases, tab, st))) return rc;
+  Inst& I = B.insts[0];
+  I.L0_out = L0_out;
+  UCP_TRY(hipMemcpyAsync(I.u0, u0_in, sizeof(double) * I.n_x, hipMemcpyDeviceToDevice, st), "copy u0");
+  UCP_TRY(hipMemcpyAsync(I.u1, u1, sizeof(double) * I.n_y, hipMemcpyDeviceToDevice, st), "copy u1");
+  UCP_TRY(hipMemsetAsync(I.flags, 0, 128, st), "clear flags");
+  UCP_TRY(hipMemcpyAsync(B.d_insts, B.insts.data(), sizeof(Inst), hipMemcpyHostToDevice, st), "upload instance");
+  UCP_TRY(launch_prior(B.launch(0, kKindPrior, tab), st), "prior kernel");
+  UCP_TRY(launch_v_from_u1(B.launch(0, kKindU1c, tab), st), "residual kernel");
+  for (int l = 0; l < I.levels; ++l) {
+    UCP_TRY(launch_mc(B.launch(0, kKindMc0 + l, tab), l, prec, st), "marginal-cost kernel");
+    UCP_TRY(launch_select(B.launch(0, kKindSel0 + l, tab), l, prec, L0_out != nullptr, st), "selection kernel");
+  }
+  UCP_TRY(hipMemcpyAsync(u0_out, I.u0_next, sizeof(double) * I.n_x, hipMemcpyDeviceToDevice, st), "copy u0_out");
+  return UCP_OK;
+}
+
+int ucp_update_u1(ucp_handle* h, const ucp_problem* prob, ucp_prec prec, const double* u0, double* u1_out,
+                  void* stream) {
+  if (!h) return fail(UCP_EINVAL, "handle is NULL");
+  int rc;
+  if ((rc = check_problem(prob)) || (rc = check_prec(prec))) return rc;
+  if (!u0 || !u1_out) return fail(UCP_EINVAL, "NULL array argument");
+  UCP_TRY(hipSetDevice(h->device), "hipSetDevice");
+  hipStream_t st = (hipStream_t)stream;
+  std::vector<std::vector<char>> phases(1, std::vector<char>(1, 1));
+  Batch B;
+  std::vector<int32_t> tab;
+  if ((rc = setup_batch(h, B, {make_inst(*prob, nullptr, prec, 1)}, phases, tab, st))) return rc;
+  Inst& I = B.insts[0];
+  UCP_TRY(hipMemcpyAsync(I.u0, u0, sizeof(double) * I.n_x, hipMemcpyDeviceToDevice, st), "copy u0");
+  UCP_TRY(hipMemsetAsync(I.flags, 0, 128, st), "clear flags");
+  UCP_TRY(launch_prior(B.launch(0, kKindPrior, tab), st), "prior kernel");
+  UCP_TRY(launch_u1_partial(B.launch(0, kKindU1p, tab), prec, st), "u1 kernel");
+  UCP_TRY(launch_u1_combine(B.launch(0, kKindU1c, tab), st), "u1 combine kernel");
+  UCP_TRY(hipMemcpyAsync(u1_out, I.u1, sizeof(double) * I.n_y, hipMemcpyDeviceToDevice, st), "copy u1_out");
+  return UCP_OK;
+}
+
+int ucp_objective(ucp_handle* h, const ucp_problem* prob, const double* u0, const double* u1, double* J_out,
+                  void* stream) {
+  if (!h) return fail(UCP_EINVAL, "handle is NULL");
+  int rc;
+  if ((rc = check_problem(prob))) return rc;
+  if (!u0 || !u1 || !J_out) return fail(UCP_EINVAL, "NULL array argument");
+  UCP_TRY(hipSetDevice(h->device), "hipSetDevice");
+  hipStream_t st = (hipStream_t)stream;
+  std::vector<std::vector<char>> phases(1, std::vector<char>(1, 1));
+  Batch B;
+  std::vector<int32_t> tab;
+  if ((rc = setup_batch(h, B, {make_inst(*prob, nullptr, UCP_FP64, 1)}, phases, tab, st))) return rc;
+  Inst& I = B.insts[0];
+  I.J_out = J_out;
+  UCP_TRY(hipMemcpyAsync(B.d_insts, B.insts.data(), sizeof(Inst), hipMemcpyHostToDevice, st), "upload instance");
+  UCP_TRY(hipMemcpyAsync(I.u0, u0, sizeof(double) * I.n_x, hipMemcpyDeviceToDevice, st), "copy u0");
+  UCP_TRY(hipMemcpyAsync(I.u1, u1, sizeof(double) * I.n_y, hipMemcpyDeviceToDevice, st), "copy u1");
+  UCP_TRY(hipMemsetAsync(I.flags, 0, 128, st), "clear flags");
+  UCP_TRY(launch_prior(B.launch(0, kKindPrior, tab), st), "prior kernel");
+  UCP_TRY(launch_j_rows(B.launch(0, kKindJRows, tab), st), "objective kernel");
+  UCP_TRY(launch_j_reduce_t(B.launch(0, kKindJRed, tab), 0, st), "objective reduce kernel");
+  return UCP_OK;
+}
+
+int ucp_marginal_cost(ucp_handle* h, const ucp_problem* prob, ucp_prec prec, const double* u1, const double* u,
+                      int64_t n_cand, double* L0_out, void* stream) {
+  if (!h) return fail(UCP_EINVAL, "handle is NULL");
+  int rc;
+  if ((rc = check_problem(prob)) || (rc = check_prec(prec))) return rc;
+  if (!u1 || !u || !L0_out) return fail(UCP_EINVAL, "NULL array argument");
+  if (n_cand < 1 || n_cand > 4096) return fail(UCP_EINVAL, "n_cand must be 1..4096");
+  if ((int64_t)prob->n_x * n_cand > ((int64_t)1 << 30)) return fail(UCP_EINVAL, "n_x * n_cand too large");
+  UCP_TRY(hipSetDevice(h->device), "hipSetDevice");
+  hipStream_t st = (hipStream_t)stream;
+  std::vector<std::vector<char>> phases(1, std::vector<char>(1, 1));
+  Batch B;
+  std::vector<int32_t> tab;
+  Inst I0 = make_inst(*prob, nullptr, prec, (int)n_cand);
+  I0.free_cands = 1;
+  if ((rc = setup_batch(h, B, {I0}, phases, tab, st))) return rc;
+  Inst& I = B.insts[0];
+  I.u0 = const_cast<double*>(u);  // the explicit candidates [n_x][n_cand], read only
+  UCP_TRY(hipMemcpyAsync(B.d_insts, B.insts.data(), sizeof(Inst), hipMemcpyHostToDevice, st), "upload instance");
+  UCP_TRY(hipMemcpyAsync(I.u1, u1, sizeof(double) * I.n_y, hipMemcpyDeviceToDevice, st), "copy u1");
+  UCP_TRY(launch_prior(B.launch(0, kKindPrior, tab), st), "prior kernel");
+  UCP_TRY(launch_v_from_u1(B.launch(0, kKindU1c, tab), st), "residual kernel");
+  UCP_TRY(launch_mc(B.launch(0, kKindFree, tab), -1, prec, st), "marginal-cost kernel");
+  Launch Lf = B.launch(0, kKindFin, tab);
+  UCP_TRY(launch_finish_free(Lf, L0_out, prec, st), "finish kernel");
+  return UCP_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,102 @@
+// Internal definitions shared by the HIP kernels and the host runtime of the
+// marginal-cost solver.  Not part of the public ABI (include/ucp.h is).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+#include "ucp.h"
+
+namespace ucp {
+
+constexpr int kMaxLevels = UCP_MAX_LEVELS;
+constexpr int kMaxComp = UCP_MAX_COMP;
+constexpr int kWave = 64;
+constexpr int kMcBlock = 256;   // marginal-cost kernel: one lane per point, 4 waves
+constexpr int kMcLds = 4096;    // FP32 residual nodes staged in LDS per block (16 KiB)
+constexpr int kMcSegMax = 2048; // longest window segment of one marginal-cost work unit
+constexpr int kSelWaves = 4;    // selection kernel: one wave per point
+constexpr int kU1Block = 256;   // u1 kernels: one lane per y node
+constexpr int kU1Chunk = 512;   // x nodes staged in LDS per step of the u1 sums
+constexpr int kJWaves = 4;      // objective: one wave per x node
+constexpr double kTau32 = 1e-5; // FP32 tie band (relative)
+constexpr double kTau64 = 1e-12;// FP64 tie band (relative)
+constexpr double kWin32 = 9.0;  // window half-width, noise sds (FP32 terms)
+constexpr double kWin64 = 12.0; // window half-width, noise sds (FP64 terms)
+
+// One solve instance as the kernels see it: constants of the problem and the
+// search, launch geometry, and device pointers to its state.
+struct Inst {
+  // problem
+  double k2;                 // k^2
+  double x_lo, dx;           // x node i = x_lo + i * dx
+  double y_lo, dy, inv_dy;   // y node j = y_lo + j * dy
+  double phi_scale;          // dy / sqrt(2 pi)
+  double w[kMaxComp], mu[kMaxComp], sd[kMaxComp];
+  int32_t n_comp;
+  int32_t n_x, n_y;
+  // search
+  int32_t levels, cands;
+  double u_lo, u_hi;
+  double h[kMaxLevels];      // candidate spacing per level
+  // geometry
+  int32_t nw32, nw64;        // window half-widths in y nodes
+  int32_t segs;              // window segments per (tile, candidate) of the marginal-cost kernel
+  int32_t u1_slices;         // x slices of the u1 sums
+  int32_t prec;              // ucp_prec
+  int32_t free_cands;        // 1: explicit candidates (u0 holds [n_x][cands]), no search
+  // state
+  double* u0;                // current first controller [n_x] (explicit candidates for ucp_marginal_cost)
+  double* u0_next;           // updated first controller [n_x]
+  double* u1;                // second controller [n_y]
+  float* v;                  // alpha * (y_j - u1_j), FP32 [n_y]
+  double* f;                 // prior density at x nodes [n_x]
+  double* logf;              // its logarithm [n_x]
+  double* cbest;             // best candidate so far [n_x]
+  double* b32best;           // its FP32-path cost B [n_x]
+  double* b64best;           // its FP64 cost B, NaN when not evaluated [n_x]
+  double* b32inc;            // FP32-path cost B of the incumbent [n_x]
+  double* part;              // marginal-cost partial sums [n_x][cands + 1][segs]
+  double* u1part;            // u1 partial sums [u1_slices][n_y][3]
+  double* jrow;              // per-point objective terms [n_x]
+  double* J_out;             // objective output (one double)
+  double* L0_out;            // optional FP64 L_0 of the accepted u0 [n_x] (argmin call only)
+  int32_t* flags;            // bit 0: non-finite value met
+  unsigned long long* terms; // algorithmic marginal-cost terms evaluated (counter)
+};
+
+// alpha^2 = log2(e) / 2, so exp(-t^2 / 2) = exp2(-(alpha t)^2).
+constexpr double kAlpha2 = 0.72134752044448170367996234050095;  // log2(e)/2
+constexpr double kInvSqrt2Pi = 0.39894228040143267793994605993438;
+
+// Launch tables: prefix sums of work units per instance for each kernel.
+struct Launch {
+  const Inst* insts;   // device array [n_inst]
+  const int32_t* pre;  // device prefix array [n_inst + 1]
+  int32_t n_inst;
+  int32_t total;       // pre[n_inst]
+};
+
+// Kernel launchers (ucp_kernels.hip).  All enqueue on `st`.
+hipError_t launch_prior(const Launch& L, hipStream_t st);
+hipError_t launch_mc(const Launch& L, int level, int prec, hipStream_t st);
+hipError_t launch_select(const Launch& L, int level, int prec, int final_l0, hipStream_t st);
+hipError_t launch_finish_free(const Launch& L, double* out, int prec, hipStream_t st);
+hipError_t launch_j_reduce_t(const Launch& L, int t, hipStream_t st);
+hipError_t launch_u1_partial(const Launch& L, int prec, hipStream_t st);
+hipError_t launch_u1_combine(const Launch& L, hipStream_t st);
+hipError_t launch_j_rows(const Launch& L, hipStream_t st);
+hipError_t launch_j_reduce(const Launch& L, hipStream_t st);
+hipError_t launch_copy_u0(const Launch& L, hipStream_t st);
+
+// Units per instance of each kernel (host helpers, ucp_kernels.hip).
+int32_t units_mc(const Inst& I, int level);
+int32_t units_select(const Inst& I);
+int32_t units_u1_partial(const Inst& I);
+int32_t units_u1_combine(const Inst& I);
+int32_t units_j_rows(const Inst& I);
+int32_t units_prior(const Inst& I);
+
+}  // namespace ucp

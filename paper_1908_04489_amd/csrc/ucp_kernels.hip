@@ -1,0 +1,769 @@
+// HIP kernels (gfx950) of the marginal-cost solver for Witsenhausen's
+// counterexample.
+//
+// Every kernel takes a flat list of work units over a batch of independent
+// instances (Launch: device instance table + prefix sums of units per
+// instance); a block finds its instance by binary search over the prefix
+// sums.  A single solve is the batch of one.  Nothing here depends on which
+// other instances share a launch, so each instance's results are the same
+// alone and in a batch.
+//
+// Kernels (all per Section IV-A: the points of one controller are
+// independent, the two controllers are updated one after the other):
+//   k_prior        prior density f and log f at the x nodes (FP64)
+//   k_mc32<P>      marginal-cost window sums for one level of the search,
+//                  FP32 terms, plain (P=0) or compensated (P=1) sums
+//   k_mc64         the same in FP64 (precision-study mode)
+//   k_select<P>    per point: level minimum, FP32 tie band, FP64
+//                  re-evaluation of the band, selection rule, next bracket,
+//                  and after the last level the comparison with the
+//                  incumbent
+//   k_u1_partial<P>/k_u1_combine   closed-form second controller
+//   k_j_rows/k_j_reduce            objective in FP64, fixed-order reduction
+#include <hip/hip_runtime.h>
+
+#include <climits>
+#include <cmath>
+
+#include "ucp_internal.h"
+
+namespace ucp {
+
+// ----------------------------------------------------------------- helpers
+
+__device__ __forceinline__ int find_inst(const int32_t* __restrict__ pre, int n, int u) {
+  int lo = 0, hi = n - 1;
+  while (lo < hi) {
+    int mid = (lo + hi + 1) >> 1;
+    if (pre[mid] <= u) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+
+__device__ __forceinline__ int wave_min_i(int v) {
+  for (int o = kWave / 2; o > 0; o >>= 1) v = min(v, __shfl_xor(v, o));
+  return v;
+}
+__device__ __forceinline__ int wave_max_i(int v) {
+  for (int o = kWave / 2; o > 0; o >>= 1) v = max(v, __shfl_xor(v, o));
+  return v;
+}
+__device__ __forceinline__ double wave_min_d(double v) {
+  for (int o = kWave / 2; o > 0; o >>= 1) v = fmin(v, __shfl_xor(v, o));
+  return v;
+}
+// Butterfly sum: every lane ends with the same bits (each step adds the same
+// two values, and IEEE addition is commutative).
+__device__ __forceinline__ double wave_sum_d(double v) {
+  for (int o = kWave / 2; o > 0; o >>= 1) v += __shfl_xor(v, o);
+  return v;
+}
+
+__device__ __forceinline__ double clampd(double v, double lo, double hi) {
+  return v < lo ? lo : (v > hi ? hi : v);
+}
+
+// Candidate q of `level` at point i: level 0 is the global grid over
+// [u_lo, u_hi] (q == cands is the incumbent); level l spans the neighbour
+// bracket of the best so far, clamped to the range.  Plain binary64
+// arithmetic, no contraction (the library is built with -ffp-contract=off).
+__device__ __forceinline__ double cand_pos(const Inst& I, int level, int q, int i) {
+  if (level < 0) return I.u0[(size_t)i * I.cands + q];  // explicit candidates
+  if (level == 0) {
+    if (q == I.cands) return I.u0[i];
+    return I.u_lo + (double)q * I.h[0];
+  }
+  return clampd((I.cbest[i] - I.h[level - 1]) + (double)q * I.h[level], I.u_lo, I.u_hi);
+}
+
+// Nearest y node to z (clamped to the grid; NaN maps to node 0).
+__device__ __forceinline__ int nearest_node(const Inst& I, double z) {
+  double jf = rint((z - I.y_lo) * I.inv_dy);
+  jf = fmin(fmax(jf, 0.0), (double)(I.n_y - 1));
+  return (int)jf;
+}
+
+// FP64 window sum for one position z, spread over the 64 lanes of a wave:
+// returns dy/sqrt(2 pi) * sum_j phi(y_j - z) (z - u1_j)^2 over the nodes
+// within kWin64 of the node nearest z; the Gaussian is max-shifted to that
+// node, exp(-(t^2 - delta^2)/2) = exp(-d (d + 2 delta)/2) with d = (j - jr) dy,
+// and the shift exp(-delta^2/2) is applied once at the end.
+__device__ double b64_wave(const Inst& I, double z, int lane) {
+  const int jr = nearest_node(I, z);
+  const double delta = (I.y_lo + (double)jr * I.dy) - z;
+  const int klo = max(-I.nw64, -jr), khi = min(I.nw64, I.n_y - 1 - jr);
+  double s = 0.0;
+  for (int k = klo + lane; k <= khi; k += kWave) {
+    double d = (double)k * I.dy;
+    double g = exp(-0.5 * d * (d + 2.0 * delta));
+    double e = z - I.u1[jr + k];
+    s += g * e * e;
+  }
+  s = wave_sum_d(s);
+  return I.phi_scale * exp(-0.5 * delta * delta) * s;
+}
+
+// Algorithmic terms of one (point, candidate): the y nodes within kWin32
+// noise sds of z (the work the method needs for FP64-level accuracy; the
+// kernels may evaluate a few more).  Summed per wave, one atomic per wave.
+__device__ __forceinline__ void count_terms(const Inst& I, double z, bool act, int lane) {
+  long long n = 0;
+  if (act && I.terms) {
+    double lo = ceil((z - kWin32 - I.y_lo) * I.inv_dy);
+    double hi = floor((z + kWin32 - I.y_lo) * I.inv_dy);
+    lo = fmax(lo, 0.0);
+    hi = fmin(hi, (double)(I.n_y - 1));
+    if (hi >= lo) n = (long long)(hi - lo) + 1;
+  }
+  for (int o = kWave / 2; o > 0; o >>= 1) n += __shfl_xor(n, o);
+  if (lane == 0 && n > 0 && I.terms) atomicAdd(I.terms, (unsigned long long)n);
+}
+
+// ------------------------------------------------------------------ prior
+
+int32_t units_prior(const Inst& I) { return (I.n_x + 255) / 256; }
+
+__global__ __launch_bounds__(256) void k_prior(Launch L) {
+  const int u = blockIdx.x;
+  const int b = find_inst(L.pre, L.n_inst, u);
+  const Inst& I = L.insts[b];
+  const int i = (u - L.pre[b]) * 256 + threadIdx.x;
+  if (i >= I.n_x) return;
+  const double x = I.x_lo + (double)i * I.dx;
+  const double r2pi = 2.5066282746310005024157652848110;  // sqrt(2 pi)
+  double sum = 0.0, lmax = -INFINITY;
+  double lc[kMaxComp];
+  for (int c = 0; c < I.n_comp; ++c) {
+    double d = (x - I.mu[c]) / I.sd[c];
+    sum += I.w[c] * exp(-0.5 * d * d) / (I.sd[c] * r2pi);
+    lc[c] = log(I.w[c]) - log(I.sd[c]) - log(r2pi) - 0.5 * d * d;
+    lmax = fmax(lmax, lc[c]);
+  }
+  double acc = 0.0;
+  for (int c = 0; c < I.n_comp; ++c) acc += exp(lc[c] - lmax);
+  I.f[i] = sum;
+  I.logf[i] = lmax + log(acc);
+}
+
+hipError_t launch_prior(const Launch& L, hipStream_t st) {
+  if (L.total == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_prior, dim3(L.total), dim3(256), 0, st, L);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------- marginal cost, FP32
+//
+// Work unit = (tile of 256 consecutive points, candidate q, window segment).
+// Lane = point.  For point i and candidate c: z = x_i + c, jr = nearest y
+// node, delta = y_jr - z, and with t_j = y_j - z = (j - jr) dy + delta the
+// unit sums, over its segment of the window |j - jr| <= nw32,
+//   sum_j exp(-(t_j^2 - delta^2)/2) (z - u1_j)^2
+// in scaled units T = alpha t (alpha^2 = log2(e)/2) so the Gaussian is one
+// v_exp_f32 of -(T^2 - alpha^2 delta^2), and (z - u1_j) = v_j - t_j with the
+// residual v_j = y_j - u1_j formed in FP64 by the u1 kernel (stored as
+// alpha v_j in FP32).  Every term is <= 1 after the shift, so FP32 neither
+// overflows nor underflows inside the window.  The block stages the range of
+// v it touches in LDS (falls back to global loads when the range of the block
+// exceeds kMcLds nodes, e.g. across a jump of the controller).
+
+int32_t units_mc(const Inst& I, int level) {
+  if (level >= 0 && level >= I.levels) return 0;
+  const int tiles = (I.n_x + kMcBlock - 1) / kMcBlock;
+  const int kq = level == 0 ? I.cands + 1 : I.cands;  // level < 0: explicit candidates
+  return tiles * kq * I.segs;
+}
+
+typedef const __attribute__((address_space(3))) float* lds_cptr;
+typedef const __attribute__((address_space(1))) float* glb_cptr;
+
+// One term of the marginal-cost sum at window offset k (as a float), given
+// the residual node value vk: returns g (the shifted Gaussian) and e (z - u1_j
+// in scaled units).
+template <bool TFORM>
+__device__ __forceinline__ void mc_term(float kf, float vk, float aDy, float Dl, float Dl2, float& g,
+                                        float& e) {
+  if (TFORM) {
+    const float T = fmaf(kf, aDy, Dl);
+    g = __builtin_amdgcn_exp2f(fmaf(-T, T, Dl2));
+    e = vk - T;
+  } else {
+    const float D = kf * aDy, t = D + Dl;
+    g = __builtin_amdgcn_exp2f(-D * (t + Dl));
+    e = vk - t;
+  }
+}
+
+__device__ __forceinline__ void kahan_add(float x, float& acc, float& comp) {
+  const float y = x - comp;
+  const float t = acc + y;
+  comp = (t - acc) - y;
+  acc = t;
+}
+
+// Terms k in [k0, k1] (wave-uniform bounds, every lane in range) read from
+// p[k]; blocks of 8 terms are summed plainly and the block sum is added
+// with compensation (KAHAN) or every term is accumulated plainly.
+template <bool TFORM, bool KAHAN, typename P>
+__device__ __forceinline__ void mc_bulk(P p, int k0, int k1, float aDy, float Dl, float Dl2, float& acc,
+                                        float& comp) {
+  constexpr int U = 8;
+  float Dm[U];
+#pragma unroll
+  for (int m = 0; m < U; ++m) Dm[m] = TFORM ? fmaf((float)m, aDy, Dl) : (float)m * aDy;
+  int k = k0;
+  for (; k + U - 1 <= k1; k += U) {
+    const float kf = (float)k;
+    float blk = 0.0f;
+#pragma unroll
+    for (int m = 0; m < U; ++m) {
+      const float vk = p[k + m];
+      float g, e;
+      if (TFORM) {
+        const float T = fmaf(kf, aDy, Dm[m]);
+        g = __builtin_amdgcn_exp2f(fmaf(-T, T, Dl2));
+        e = vk - T;
+      } else {
+        const float D = fmaf(kf, aDy, Dm[m]), t = D + Dl;
+        g = __builtin_amdgcn_exp2f(-D * (t + Dl));
+        e = vk - t;
+      }
+      if (KAHAN) blk = fmaf(g * e, e, blk);
+      else acc = fmaf(g * e, e, acc);
+    }
+    if (KAHAN) kahan_add(blk, acc, comp);
+  }
+  for (; k <= k1; ++k) {
+    float g, e;
+    mc_term<TFORM>((float)k, p[k], aDy, Dl, Dl2, g, e);
+    if (KAHAN) kahan_add((g * e) * e, acc, comp);
+    else acc = fmaf(g * e, e, acc);
+  }
+}
+
+// Terms k in [k0, k1] restricted to the lane's own range [klo, khi].
+template <bool TFORM, bool KAHAN, typename P>
+__device__ __forceinline__ void mc_masked(P p, int k0, int k1, int klo, int khi, float aDy, float Dl,
+                                          float Dl2, float& acc, float& comp) {
+  for (int k = k0; k <= k1; ++k) {
+    if (k >= klo && k <= khi) {
+      float g, e;
+      mc_term<TFORM>((float)k, p[k], aDy, Dl, Dl2, g, e);
+      if (KAHAN) kahan_add((g * e) * e, acc, comp);
+      else acc = fmaf(g * e, e, acc);
+    }
+  }
+}
+
+// The lane's window [klo, khi] (empty when klo > khi): the range common to
+// every non-empty lane of the wave runs unmasked, the ragged ends masked.
+template <bool TFORM, bool KAHAN, typename P>
+__device__ __forceinline__ void mc_lane(P p, int klo, int khi, float aDy, float Dl, float Dl2, float& acc,
+                                        float& comp) {
+  const bool empty = klo > khi;
+  const int kc_lo = __builtin_amdgcn_readfirstlane(wave_max_i(empty ? INT_MIN : klo));
+  const int kc_hi = __builtin_amdgcn_readfirstlane(wave_min_i(empty ? INT_MAX : khi));
+  const int ku_lo = __builtin_amdgcn_readfirstlane(wave_min_i(empty ? INT_MAX : klo));
+  const int ku_hi = __builtin_amdgcn_readfirstlane(wave_max_i(empty ? INT_MIN : khi));
+  if (ku_lo > ku_hi || empty) return;
+  if (kc_lo > kc_hi) {
+    mc_masked<TFORM, KAHAN>(p, ku_lo, ku_hi, klo, khi, aDy, Dl, Dl2, acc, comp);
+    return;
+  }
+  mc_masked<TFORM, KAHAN>(p, ku_lo, kc_lo - 1, klo, khi, aDy, Dl, Dl2, acc, comp);
+  mc_bulk<TFORM, KAHAN>(p, kc_lo, kc_hi, aDy, Dl, Dl2, acc, comp);
+  mc_masked<TFORM, KAHAN>(p, kc_hi + 1, ku_hi, klo, khi, aDy, Dl, Dl2, acc, comp);
+}
+
+template <int PREC>
+__global__ __launch_bounds__(kMcBlock) void k_mc32(Launch L, int level) {
+  constexpr bool KAHAN = PREC == UCP_FP32_KAHAN;
+  __shared__ float sv[kMcLds];
+  __shared__ int sred[2][kMcBlock / kWave];
+  const int u = blockIdx.x;
+  const int b = find_inst(L.pre, L.n_inst, u);
+  const Inst& I = L.insts[b];
+  int local = u - L.pre[b];
+  const int S = I.segs;
+  const int kq = level < 0 ? I.cands : (level == 0 ? I.cands + 1 : I.cands);
+  const int pstride = level < 0 ? I.cands : I.cands + 1;
+  const int seg = local % S;
+  local /= S;
+  const int q = local % kq;
+  const int tile = local / kq;
+  const int i = tile * kMcBlock + (int)threadIdx.x;
+  const bool act = i < I.n_x;
+  const int ii = act ? i : I.n_x - 1;
+
+  const double c = cand_pos(I, level, q, ii);
+  const double x = I.x_lo + (double)ii * I.dx;
+  const double z = x + c;
+  const int jr = nearest_node(I, z);
+  const double delta = (I.y_lo + (double)jr * I.dy) - z;
+  const int nw = I.nw32;
+  const int seglen = (2 * nw + 1 + S - 1) / S;
+  const int s_lo = -nw + seg * seglen;
+  const int s_hi = min(nw, s_lo + seglen - 1);
+  int klo = max(s_lo, -jr), khi = min(s_hi, I.n_y - 1 - jr);
+  if (!act) { klo = 1; khi = 0; }
+
+  // node range of the block, for LDS staging
+  const int wid = threadIdx.x / kWave, lane = threadIdx.x % kWave;
+  int jlo = klo <= khi ? jr + klo : INT_MAX;
+  int jhi = klo <= khi ? jr + khi : INT_MIN;
+  jlo = wave_min_i(jlo);
+  jhi = wave_max_i(jhi);
+  if (lane == 0) { sred[0][wid] = jlo; sred[1][wid] = jhi; }
+  __syncthreads();
+  int blo = INT_MAX, bhi = INT_MIN;
+  for (int w = 0; w < kMcBlock / kWave; ++w) { blo = min(blo, sred[0][w]); bhi = max(bhi, sred[1][w]); }
+  if (seg == 0) count_terms(I, z, act, lane);
+  const bool staged = bhi >= blo && bhi - blo + 1 <= kMcLds;
+  if (staged)
+    for (int j = blo + (int)threadIdx.x; j <= bhi; j += kMcBlock) sv[j - blo] = I.v[j];
+  __syncthreads();
+
+  const double alpha = sqrt(kAlpha2);
+  const float aDy = (float)(alpha * I.dy);
+  const float Dl = (float)(alpha * delta);
+  const float Dl2 = Dl * Dl;
+  // T-form (fewer operations) when every lane of the wave sits within one
+  // spacing of its nearest node; otherwise the d-form keeps the shifted
+  // exponent -(d (d + 2 delta)) accurate for z far outside the grid.
+  const bool tform = __builtin_amdgcn_readfirstlane(wave_min_i((act && fabs(delta) > I.dy) ? 0 : 1)) == 1;
+
+  float acc = 0.0f, comp = 0.0f;
+  if (staged) {
+    lds_cptr p = (lds_cptr)(sv + (jr - blo));
+    if (tform) mc_lane<true, KAHAN>(p, klo, khi, aDy, Dl, Dl2, acc, comp);
+    else mc_lane<false, KAHAN>(p, klo, khi, aDy, Dl, Dl2, acc, comp);
+  } else {
+    glb_cptr p = (glb_cptr)(I.v + jr);
+    if (tform) mc_lane<true, KAHAN>(p, klo, khi, aDy, Dl, Dl2, acc, comp);
+    else mc_lane<false, KAHAN>(p, klo, khi, aDy, Dl, Dl2, acc, comp);
+  }
+  if (act) I.part[((size_t)i * pstride + q) * S + seg] = KAHAN ? (double)acc - (double)comp : (double)acc;
+}
+
+// FP64 marginal cost (precision-study mode): lane = point, window kWin64,
+// the same shifted Gaussian as b64_wave; one segment.
+__global__ __launch_bounds__(kMcBlock) void k_mc64(Launch L, int level) {
+  const int u = blockIdx.x;
+  const int b = find_inst(L.pre, L.n_inst, u);
+  const Inst& I = L.insts[b];
+  int local = u - L.pre[b];
+  const int kq = level < 0 ? I.cands : (level == 0 ? I.cands + 1 : I.cands);
+  const int pstride = level < 0 ? I.cands : I.cands + 1;
+  const int q = local % kq;
+  const int tile = local / kq;
+  const int i = tile * kMcBlock + (int)threadIdx.x;
+  const bool act = i < I.n_x;
+  const double c = cand_pos(I, level, q, act ? i : I.n_x - 1);
+  const double z = (I.x_lo + (double)(act ? i : I.n_x - 1) * I.dx) + c;
+  count_terms(I, z, act, (int)threadIdx.x % kWave);
+  if (!act) return;
+  const int jr = nearest_node(I, z);
+  const double delta = (I.y_lo + (double)jr * I.dy) - z;
+  const int klo = max(-I.nw64, -jr), khi = min(I.nw64, I.n_y - 1 - jr);
+  double s = 0.0;
+  for (int k = klo; k <= khi; ++k) {
+    double d = (double)k * I.dy;
+    double g = exp(-0.5 * d * (d + 2.0 * delta));
+    double e = z - I.u1[jr + k];
+    s += g * e * e;
+  }
+  I.part[(size_t)i * pstride + q] = s;
+}
+
+hipError_t launch_mc(const Launch& L, int level, int prec, hipStream_t st) {
+  if (L.total == 0) return hipSuccess;
+  if (prec == UCP_FP64)
+    hipLaunchKernelGGL(k_mc64, dim3(L.total), dim3(kMcBlock), 0, st, L, level);
+  else if (prec == UCP_FP32_KAHAN)
+    hipLaunchKernelGGL(k_mc32<UCP_FP32_KAHAN>, dim3(L.total), dim3(kMcBlock), 0, st, L, level);
+  else
+    hipLaunchKernelGGL(k_mc32<UCP_FP32>, dim3(L.total), dim3(kMcBlock), 0, st, L, level);
+  return hipGetLastError();
+}
+
+// B from the partial sums of candidate lane q: k^2 c^2 + dy/sqrt(2 pi)
+// exp(-delta^2/2) * sum (the FP32 sums carry the factor alpha^2).
+__device__ __forceinline__ double b_from_parts(const Inst& I, int i, int q, int pstride, int S,
+                                               double c, int prec) {
+  const double z = (I.x_lo + (double)i * I.dx) + c;
+  const int jr = nearest_node(I, z);
+  const double delta = (I.y_lo + (double)jr * I.dy) - z;
+  const double* p = I.part + ((size_t)i * pstride + q) * S;
+  double s = 0.0;
+  for (int g = 0; g < S; ++g) s += p[g];
+  if (prec != UCP_FP64) s = s / kAlpha2;
+  return I.k2 * c * c + I.phi_scale * exp(-0.5 * delta * delta) * s;
+}
+
+// L_0 = f B for explicit candidates (ucp_marginal_cost).
+__global__ __launch_bounds__(256) void k_mc_finish(Launch L, double* out, int prec) {
+  const int u = blockIdx.x;
+  const int b = find_inst(L.pre, L.n_inst, u);
+  const Inst& I = L.insts[b];
+  const long idx = (long)(u - L.pre[b]) * 256 + threadIdx.x;
+  if (idx >= (long)I.n_x * I.cands) return;
+  const int i = (int)(idx / I.cands), q = (int)(idx % I.cands);
+  const double c = I.u0[idx];
+  const int S = I.segs;
+  out[idx] = I.f[i] * b_from_parts(I, i, q, I.cands, S, c, prec);
+}
+
+// ------------------------------------------------------------- selection
+//
+// One wave per point.  Lane q holds candidate q of the level (lane `cands`
+// holds the best so far from the previous level, or at level 0 the
+// incumbent, whose FP32-path B is kept for the final comparison).
+
+int32_t units_select(const Inst& I) { return (I.n_x + kSelWaves - 1) / kSelWaves; }
+
+struct Pick {
+  int lane;
+  double B64;  // FP64 B of the pick (NaN if not evaluated)
+};
+
+// Selection rule over the lanes with in_set: in FP64 modes the band is
+// B <= m (1 + tau64); in FP32 modes a band B32 <= m32 (1 + tau32) is formed
+// first and its members are re-evaluated in FP64.  Among the FP64 band the
+// member nearest the incumbent wins, then the smaller u, then the lower lane.
+__device__ Pick select_rule(const Inst& I, bool in_set, double c, double B32, double B64, double x,
+                            double uinc, int lane, int prec, int32_t* bad) {
+  const double big = INFINITY;
+  const bool fin = in_set && isfinite(B32);
+  const double m32 = wave_min_d(fin ? B32 : big);
+  Pick r{0, NAN};
+  if (!(m32 < big)) {  // no finite candidate: flag and keep lane 0
+    if (lane == 0) atomicOr(bad, 1);
+    r.lane = 0;
+    r.B64 = __shfl(B64, 0);
+    return r;
+  }
+  double Bf;  // FP64 value used by the rule
+  bool band;
+  if (prec == UCP_FP64) {
+    Bf = B32;
+    band = fin && B32 <= m32 * (1.0 + kTau64);
+  } else {
+    const bool b32 = fin && B32 <= m32 * (1.0 + kTau32);
+    const unsigned long long mask = __ballot(b32);
+    if (__popcll(mask) == 1) {
+      r.lane = __ffsll((long long)mask) - 1;
+      r.B64 = __shfl(B64, r.lane);
+      return r;
+    }
+    unsigned long long todo = __ballot(b32 && isnan(B64));
+    while (todo) {
+      const int L = __ffsll((long long)todo) - 1;
+      todo &= todo - 1;
+      const double cl = __shfl(c, L);
+      const double v = I.k2 * cl * cl + b64_wave(I, x + cl, lane);
+      if (lane == L) B64 = v;
+    }
+    Bf = B64;
+    const double m64 = wave_min_d(b32 ? B64 : big);
+    band = b32 && B64 <= m64 * (1.0 + kTau64);
+  }
+  // lexicographic (|c - uinc|, c, lane) minimum over the band
+  double k1 = band ? fabs(c - uinc) : big;
+  double k2 = band ? c : big;
+  int k3 = band ? lane : INT_MAX;
+  for (int o = kWave / 2; o > 0; o >>= 1) {
+    double o1 = __shfl_xor(k1, o), o2 = __shfl_xor(k2, o);
+    int o3 = __shfl_xor(k3, o);
+    bool take = (o1 < k1) || (o1 == k1 && (o2 < k2 || (o2 == k2 && o3 < k3)));
+    if (take) { k1 = o1; k2 = o2; k3 = o3; }
+  }
+  r.lane = k3 == INT_MAX ? 0 : k3;
+  r.B64 = __shfl(prec == UCP_FP64 ? Bf : B64, r.lane);
+  return r;
+}
+
+template <int PREC>
+__global__ __launch_bounds__(kSelWaves * kWave) void k_select(Launch L, int level, int want_l0) {
+  const int u = blockIdx.x;
+  const int b = find_inst(L.pre, L.n_inst, u);
+  const Inst& I = L.insts[b];
+  const int wid = threadIdx.x / kWave, lane = threadIdx.x % kWave;
+  const int i = (u - L.pre[b]) * kSelWaves + wid;
+  if (i >= I.n_x) return;  // whole wave leaves; no block barrier below
+  const int K = I.cands;
+  const int S = I.segs;
+  const double uinc = I.u0[i];
+  const double x = I.x_lo + (double)i * I.dx;
+  const int kq = level == 0 ? K + 1 : K;
+
+  double c = 0.0, B32 = INFINITY, B64 = NAN;
+  if (lane < kq) {
+    c = cand_pos(I, level, lane, i);
+    B32 = b_from_parts(I, i, lane, K + 1, S, c, PREC);
+    if (PREC == UCP_FP64) B64 = B32;
+  }
+  if (level == 0 && lane == K) I.b32inc[i] = B32;
+  if (level > 0 && lane == K) {
+    c = I.cbest[i];
+    B32 = I.b32best[i];
+    B64 = I.b64best[i];
+  }
+  const bool in_set = level == 0 ? lane < K : lane <= K;
+  Pick p = select_rule(I, in_set, c, B32, B64, x, uinc, lane, PREC, I.flags);
+  const double cw = __shfl(c, p.lane);
+  const double B32w = __shfl(B32, p.lane);
+  double B64w = p.B64;
+  if (lane == 0) {
+    I.cbest[i] = cw;
+    I.b32best[i] = B32w;
+    I.b64best[i] = B64w;
+  }
+  if (level != I.levels - 1) return;
+
+  // acceptance against the incumbent
+  double res = cw, Bres = B64w;
+  if (!(cw == uinc)) {
+    const double B32i = I.b32inc[i];
+    const bool in2 = lane < 2;
+    const double c2 = lane == 0 ? cw : uinc;
+    const double b32_2 = lane == 0 ? B32w : B32i;
+    const double b64_2 = lane == 0 ? B64w : (PREC == UCP_FP64 ? B32i : NAN);
+    Pick q = select_rule(I, in2, c2, b32_2, b64_2, x, uinc, lane, PREC, I.flags);
+    res = __shfl(c2, q.lane);
+    Bres = q.B64;
+  }
+  if (want_l0 && isnan(Bres)) Bres = I.k2 * res * res + b64_wave(I, x + res, lane);
+  if (lane == 0) {
+    I.u0_next[i] = res;
+    if (!isfinite(res)) atomicOr(I.flags, 1);
+    if (want_l0) I.L0_out[i] = I.f[i] * Bres;
+  }
+}
+
+hipError_t launch_select(const Launch& L, int level, int prec, int want_l0, hipStream_t st) {
+  if (L.total == 0) return hipSuccess;
+  dim3 blk(kSelWaves * kWave);
+  if (prec == UCP_FP64)
+    hipLaunchKernelGGL(k_select<UCP_FP64>, dim3(L.total), blk, 0, st, L, level, want_l0);
+  else if (prec == UCP_FP32_KAHAN)
+    hipLaunchKernelGGL(k_select<UCP_FP32_KAHAN>, dim3(L.total), blk, 0, st, L, level, want_l0);
+  else
+    hipLaunchKernelGGL(k_select<UCP_FP32>, dim3(L.total), blk, 0, st, L, level, want_l0);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------ u1 update
+//
+// u1_j = y_j - v_j with v_j = sum_i w_ij d_ij / sum_i w_ij, d_ij = y_j - x1_i,
+// w_ij = exp(l_ij - M), l_ij = log f_i - d_ij^2 / 2 (the conditional mean
+// written around y_j so the numerator terms stay small).  Unit = (tile of
+// 256 y nodes, slice of x nodes); each slice keeps an online maximum M, and
+// the combine kernel merges the slices in a fixed order.
+
+int32_t units_u1_partial(const Inst& I) { return ((I.n_y + kU1Block - 1) / kU1Block) * I.u1_slices; }
+int32_t units_u1_combine(const Inst& I) { return (I.n_y + kU1Block - 1) / kU1Block; }
+
+template <int PREC>
+__global__ __launch_bounds__(kU1Block) void k_u1_partial(Launch L) {
+  __shared__ double sx1[kU1Chunk];
+  __shared__ double slf[kU1Chunk];
+  const int u = blockIdx.x;
+  const int b = find_inst(L.pre, L.n_inst, u);
+  const Inst& I = L.insts[b];
+  const int local = u - L.pre[b];
+  const int slice = local % I.u1_slices;
+  const int tile = local / I.u1_slices;
+  const int j = tile * kU1Block + (int)threadIdx.x;
+  const bool act = j < I.n_y;
+  const double y = I.y_lo + (double)(act ? j : 0) * I.dy;
+  const int slen = (I.n_x + I.u1_slices - 1) / I.u1_slices;
+  const int i0 = slice * slen, i1 = min(I.n_x, i0 + slen);
+  const double log2e = 1.4426950408889634073599246810019;
+  double M = -INFINITY, den = 0.0, num64 = 0.0;
+  float num = 0.0f, comp = 0.0f;
+  for (int c0 = i0; c0 < i1; c0 += kU1Chunk) {
+    const int cn = min(kU1Chunk, i1 - c0);
+    __syncthreads();
+    for (int t = threadIdx.x; t < cn; t += kU1Block) {
+      const int i = c0 + t;
+      sx1[t] = (I.x_lo + (double)i * I.dx) + I.u0[i];
+      slf[t] = I.logf[i];
+    }
+    __syncthreads();
+    // chunk maximum of the logits
+    double mc = -INFINITY;
+    for (int t = 0; t < cn; ++t) {
+      const double d = y - sx1[t];
+      mc = fmax(mc, slf[t] - 0.5 * d * d);
+    }
+    if (mc > M) {  // rescale what was summed under the old maximum
+      const double r = M == -INFINITY ? 0.0 : exp(M - mc);
+      den *= r;
+      if (PREC == UCP_FP64) num64 *= r;
+      else { num = (float)((double)num * r); comp = (float)((double)comp * r); }
+      M = mc;
+    }
+    if (!(M > -INFINITY)) continue;  // every logit is -inf (or NaN): nothing to add
+    const double Ml = M * log2e;
+    for (int t = 0; t < cn; ++t) {
+      const double d = y - sx1[t];
+      const double a = (slf[t] - 0.5 * d * d) * log2e - Ml;
+      if (PREC == UCP_FP64) {
+        const double w = exp2(a);
+        num64 += w * d;
+        den += w;
+      } else {
+        const float w = __builtin_amdgcn_exp2f((float)a);
+        const float term = w * (float)d;
+        if (PREC == UCP_FP32_KAHAN) {
+          const float yy = term - comp;
+          const float tt = num + yy;
+          comp = (tt - num) - yy;
+          num = tt;
+        } else {
+          num += term;
+        }
+        den += (double)w;
+      }
+    }
+  }
+  if (!act) return;
+  double* o = I.u1part + ((size_t)slice * I.n_y + j) * 3;
+  o[0] = M;
+  o[1] = PREC == UCP_FP64 ? num64 : (double)num - (double)comp;
+  o[2] = den;
+}
+
+__global__ __launch_bounds__(kU1Block) void k_u1_combine(Launch L) {
+  const int u = blockIdx.x;
+  const int b = find_inst(L.pre, L.n_inst, u);
+  const Inst& I = L.insts[b];
+  const int j = (u - L.pre[b]) * kU1Block + (int)threadIdx.x;
+  if (j >= I.n_y) return;
+  double M = -INFINITY;
+  for (int s = 0; s < I.u1_slices; ++s) M = fmax(M, I.u1part[((size_t)s * I.n_y + j) * 3]);
+  double num = 0.0, den = 0.0;
+  for (int s = 0; s < I.u1_slices; ++s) {
+    const double* p = I.u1part + ((size_t)s * I.n_y + j) * 3;
+    if (!(p[0] > -INFINITY)) continue;
+    const double r = exp(p[0] - M);
+    num += p[1] * r;
+    den += p[2] * r;
+  }
+  const double y = I.y_lo + (double)j * I.dy;
+  const double vres = num / den;
+  const double u1 = y - vres;
+  I.u1[j] = u1;
+  I.v[j] = (float)(sqrt(kAlpha2) * vres);
+  if (!isfinite(u1)) atomicOr(I.flags, 1);
+}
+
+hipError_t launch_u1_partial(const Launch& L, int prec, hipStream_t st) {
+  if (L.total == 0) return hipSuccess;
+  if (prec == UCP_FP64)
+    hipLaunchKernelGGL(k_u1_partial<UCP_FP64>, dim3(L.total), dim3(kU1Block), 0, st, L);
+  else if (prec == UCP_FP32_KAHAN)
+    hipLaunchKernelGGL(k_u1_partial<UCP_FP32_KAHAN>, dim3(L.total), dim3(kU1Block), 0, st, L);
+  else
+    hipLaunchKernelGGL(k_u1_partial<UCP_FP32>, dim3(L.total), dim3(kU1Block), 0, st, L);
+  return hipGetLastError();
+}
+
+hipError_t launch_u1_combine(const Launch& L, hipStream_t st) {
+  if (L.total == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_u1_combine, dim3(L.total), dim3(kU1Block), 0, st, L);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------- objective
+
+int32_t units_j_rows(const Inst& I) { return (I.n_x + kJWaves - 1) / kJWaves; }
+
+__global__ __launch_bounds__(kJWaves * kWave) void k_j_rows(Launch L) {
+  const int u = blockIdx.x;
+  const int b = find_inst(L.pre, L.n_inst, u);
+  const Inst& I = L.insts[b];
+  const int wid = threadIdx.x / kWave, lane = threadIdx.x % kWave;
+  const int i = (u - L.pre[b]) * kJWaves + wid;
+  if (i >= I.n_x) return;
+  const double u0 = I.u0[i];
+  const double x1 = (I.x_lo + (double)i * I.dx) + u0;
+  const double inner = b64_wave(I, x1, lane);
+  if (lane == 0) I.jrow[i] = I.f[i] * (I.k2 * u0 * u0 + inner);
+}
+
+// One block per instance: fixed-order sum of the rows (strided per thread,
+// then a tree), times dx.  `t` selects the J_hist entry.
+__global__ __launch_bounds__(256) void k_j_reduce(Launch L, int t) {
+  __shared__ double red[256];
+  const int b = find_inst(L.pre, L.n_inst, blockIdx.x);
+  const Inst& I = L.insts[b];
+  double s = 0.0;
+  for (int i = threadIdx.x; i < I.n_x; i += 256) s += I.jrow[i];
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    const double J = I.dx * red[0];
+    I.J_out[t] = J;
+    if (!isfinite(J)) atomicOr(I.flags, 1);
+  }
+}
+
+hipError_t launch_j_rows(const Launch& L, hipStream_t st) {
+  if (L.total == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_j_rows, dim3(L.total), dim3(kJWaves * kWave), 0, st, L);
+  return hipGetLastError();
+}
+
+hipError_t launch_j_reduce_t(const Launch& L, int t, hipStream_t st) {
+  if (L.total == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_j_reduce, dim3(L.total), dim3(256), 0, st, L, t);
+  return hipGetLastError();
+}
+
+hipError_t launch_j_reduce(const Launch& L, hipStream_t st) { return launch_j_reduce_t(L, 0, st); }
+
+// ----------------------------------------------------------- u0 advance
+
+__global__ __launch_bounds__(256) void k_copy_u0(Launch L) {
+  const int u = blockIdx.x;
+  const int b = find_inst(L.pre, L.n_inst, u);
+  const Inst& I = L.insts[b];
+  const int i = (u - L.pre[b]) * 256 + threadIdx.x;
+  if (i < I.n_x) I.u0[i] = I.u0_next[i];
+}
+
+hipError_t launch_copy_u0(const Launch& L, hipStream_t st) {
+  if (L.total == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_copy_u0, dim3(L.total), dim3(256), 0, st, L);
+  return hipGetLastError();
+}
+
+// Residual v_j = alpha (y_j - u1_j) in FP32 from a given u1 (argmin and
+// marginal-cost calls, where u1 is an input).
+__global__ __launch_bounds__(256) void k_v_from_u1(Launch L) {
+  const int u = blockIdx.x;
+  const int b = find_inst(L.pre, L.n_inst, u);
+  const Inst& I = L.insts[b];
+  const int j = (u - L.pre[b]) * 256 + threadIdx.x;
+  if (j >= I.n_y) return;
+  const double y = I.y_lo + (double)j * I.dy;
+  I.v[j] = (float)(sqrt(kAlpha2) * (y - I.u1[j]));
+}
+
+hipError_t launch_v_from_u1(const Launch& L, hipStream_t st) {
+  if (L.total == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_v_from_u1, dim3(L.total), dim3(256), 0, st, L);
+  return hipGetLastError();
+}
+
+hipError_t launch_finish_free(const Launch& L, double* out, int prec, hipStream_t st) {
+  if (L.total == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_mc_finish, dim3(L.total), dim3(256), 0, st, L, out, prec);
+  return hipGetLastError();
+}
+
+}  // namespace ucp

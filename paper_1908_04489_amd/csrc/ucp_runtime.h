@@ -1,0 +1,39 @@
+// Host-side helpers shared by the solver API and the server (not public ABI).
+#pragma once
+
+#include <string>
+#include <vector>
+
+#include "ucp_internal.h"
+
+namespace ucp {
+
+// Launch-table kinds: one prefix array per kernel (and per search level).
+enum : int {
+  kKindMc0 = 0,                     // marginal-cost kernel, level l at kKindMc0 + l
+  kKindSel0 = kKindMc0 + kMaxLevels,  // selection kernel, level l at kKindSel0 + l
+  kKindU1p = kKindSel0 + kMaxLevels,
+  kKindU1c,
+  kKindJRows,
+  kKindJRed,
+  kKindPrior,
+  kKindCopy,
+  kKindFree,  // marginal-cost kernel on explicit candidates
+  kKindFin,   // L_0 = f B for explicit candidates
+  kKinds
+};
+
+extern thread_local std::string g_err;
+int fail(int code, const char* fmt, ...);
+int hip_fail(hipError_t e, const char* what);
+int check_problem(const ucp_problem* p);
+int check_search(const ucp_search* s);
+int check_prec(int prec);
+Inst make_inst(const ucp_problem& p, const ucp_search* s, int prec, int cands_override);
+size_t state_bytes(const Inst& I);
+void carve_state(Inst& I, char*& base);
+std::vector<int32_t> build_tables(const std::vector<Inst>& insts, const std::vector<char>& running);
+
+hipError_t launch_v_from_u1(const Launch& L, hipStream_t st);
+
+}  // namespace ucp

@@ -1,0 +1,275 @@
+"""GPU parity of every C-ABI call against the FP64 oracle, on identical
+seeded inputs.
+
+Tolerances (derived in the design notes from the arithmetic):
+  - objective (FP64 throughout): relative 1e-12;
+  - marginal cost, FP64 mode: relative 1e-12; FP32 modes: relative 2e-5
+    (FP32 terms with centred arguments, worst case on small costs);
+  - u1: FP64 mode 1e-11 absolute; FP32 modes 2e-5 absolute, on the nodes
+    carrying output density p_y >= 1e-9 max p_y;
+  - argmin: decisions equal to the oracle's; a differing point must be an
+    FP64 near-tie (oracle cost at the GPU's choice within 1e-9 relative);
+  - solve: J relative error <= 1e-6 at every round.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def env():
+    import torch
+
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1908_04489_amd as U
+
+    import oracle
+
+    oracle.lib()
+    return U, oracle, torch
+
+
+def dev(torch, a):
+    return torch.as_tensor(np.ascontiguousarray(a, dtype=np.float64)).cuda()
+
+
+def host(t):
+    return t.detach().cpu().numpy()
+
+
+def py_mask(orc, p, u0, u1):
+    """Nodes whose output density p_y(j) = sum_i f_i phi(y_j - x1_i) is at
+    least 1e-9 of its maximum."""
+    f, _ = orc.prior(p)
+    x1 = orc.grid(p.x_lo, p.x_hi, p.n_x) + u0
+    y = orc.grid(p.y_lo, p.y_hi, p.n_y)
+    py = np.array([np.sum(f * np.exp(-0.5 * (yy - x1) ** 2)) for yy in y])
+    return py >= 1e-9 * py.max()
+
+
+CASES = {
+    "small": lambda: W.small_case(),
+    "ragged": lambda: W.Case("ragged-n_x!=n_y", W.Problem(0.3, [(0.7, -2.0, 3.0), (0.3, 6.0, 2.0)], -20, 22, 777,
+                                                          -24, 26, 1201), W.Search(-9, 11, 3, 13), 4,
+                             W.init_random_steps(W.Problem(0.3, [(1, 0, 3)], -20, 22, 777, -24, 26, 1201), 4.0, 7)),
+    "tiny": lambda: W.Case("tiny", W.gaussian_problem(0.2, 5.0, 21, 25.0), W.Search(-30, 30, 2, 5), 3,
+                           W.init_sign(W.gaussian_problem(0.2, 5.0, 21, 25.0), 5.0)),
+}
+
+
+# ------------------------------------------------------------- objective
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_objective(env, name):
+    U, orc, torch = env
+    c = CASES[name]()
+    p = c.prob
+    u1 = orc.update_u1(p, c.u0_init)
+    J = orc.objective(p, c.u0_init, u1)
+    Jg = host(U.objective(p, dev(torch, c.u0_init), dev(torch, u1)))[0]
+    assert abs(Jg - J) <= 1e-12 * abs(J), (Jg, J)
+
+
+def test_objective_affine_closed_form(env):
+    """The GPU objective against the closed form too (not only the oracle)."""
+    U, orc, torch = env
+    p = W.gaussian_problem(0.2, 5.0, 2401, 60.0)
+    for lam, ref in [(1.0, 25 / 26), (0.0417424305044, 0.96)]:
+        u0 = W.init_affine(p, lam)
+        y = orc.grid(p.y_lo, p.y_hi, p.n_y)
+        g = lam * lam * 25 / (1 + lam * lam * 25)
+        Jg = host(U.objective(p, dev(torch, u0), dev(torch, g * y)))[0]
+        assert abs(Jg - ref) <= 1e-10 * ref
+
+
+# ----------------------------------------------------------- u1 update
+
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-11), ("fp32_kahan", 2e-5), ("fp32", 2e-5)])
+@pytest.mark.parametrize("name", list(CASES))
+def test_update_u1(env, name, prec, tol):
+    U, orc, torch = env
+    c = CASES[name]()
+    p = c.prob
+    u0 = W.init_random_steps(p, 5.0, 11) if name == "small" else c.u0_init
+    ref = orc.update_u1(p, u0)
+    got = host(U.update_u1(p, dev(torch, u0), prec))
+    m = py_mask(orc, p, u0, ref)
+    err = np.max(np.abs(got[m] - ref[m]))
+    assert err <= tol, err
+    assert np.all(np.isfinite(got))
+
+
+# -------------------------------------------------------- marginal cost
+
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-12), ("fp32_kahan", 2e-5), ("fp32", 2e-5)])
+@pytest.mark.parametrize("name", list(CASES))
+def test_marginal_cost(env, name, prec, tol):
+    U, orc, torch = env
+    c = CASES[name]()
+    p, s = c.prob, c.search
+    u1 = orc.update_u1(p, c.u0_init)
+    rng = np.random.default_rng(3)
+    n_c = 7
+    u = rng.uniform(s.u_lo, s.u_hi, (p.n_x, n_c))
+    u[:, 0] = c.u0_init
+    u[:, 1] = 0.0
+    ref = orc.marginal_cost(p, u1, u)
+    got = host(U.marginal_cost(p, dev(torch, u1), dev(torch, u), prec))
+    f, _ = orc.prior(p)
+    ok = f > 1e-280  # f underflows to 0 in FP64 beyond ~37 prior sds
+    rel = np.abs(got[ok] - ref[ok]) / np.abs(ref[ok])
+    assert np.max(rel) <= tol, np.max(rel)
+
+
+# --------------------------------------------------------------- argmin
+
+@pytest.mark.parametrize("prec", ["fp32_kahan", "fp32", "fp64"])
+@pytest.mark.parametrize("name", list(CASES))
+def test_argmin_decisions(env, name, prec):
+    U, orc, torch = env
+    c = CASES[name]()
+    p, s = c.prob, c.search
+    u0 = c.u0_init
+    u1 = orc.update_u1(p, u0)
+    ref, Bref = orc.argmin(p, s, u1, u0)
+    got, L0 = U.argmin_adaptive(p, s, dev(torch, u1), dev(torch, u0), prec, want_l0=True)
+    got, L0 = host(got), host(L0)
+    diff = np.nonzero(got != ref)[0]
+    x = orc.grid(p.x_lo, p.x_hi, p.n_x)
+    for i in diff:  # only FP64 near-ties may differ
+        bg = orc.B(p, u1, x[i], got[i])
+        assert bg <= Bref[i] * (1 + 1e-9), (i, got[i], ref[i], bg, Bref[i])
+    assert len(diff) <= max(1, p.n_x // 1000)
+    f, _ = orc.prior(p)
+    ok = f > 1e-280
+    Lref = f * np.array([orc.B(p, u1, x[i], got[i]) for i in range(p.n_x)])
+    assert np.max(np.abs(L0[ok] - Lref[ok]) / Lref[ok]) <= 1e-12
+
+
+# ---------------------------------------------------------------- solve
+
+@pytest.mark.parametrize("prec", ["fp32_kahan", "fp64", "fp32"])
+@pytest.mark.parametrize("name", list(CASES))
+def test_solve(env, name, prec):
+    U, orc, torch = env
+    c = CASES[name]()
+    p, s = c.prob, c.search
+    u0r, u1r, Jr = orc.solve(p, s, c.iters, c.u0_init)
+    u0g, u1g, Jg = (host(t) for t in U.solve(p, s, c.iters, dev(torch, c.u0_init), prec))
+    rel = np.abs(Jg - Jr) / Jr
+    print(f"{name} {prec} J rel err per round: {rel.max():.2e}; u0 differs at {np.sum(u0g != u0r)} points")
+    assert rel.max() <= 1e-6
+    assert np.all(Jg[1:] <= Jg[:-1] * (1 + 1e-12))  # monotone (the incumbent is always a candidate)
+
+
+def test_solve_is_deterministic_and_resumable(env):
+    U, orc, torch = env
+    c = W.small_case()
+    p, s = c.prob, c.search
+    a = [host(t) for t in U.solve(p, s, 4, dev(torch, c.u0_init))]
+    b = [host(t) for t in U.solve(p, s, 4, dev(torch, c.u0_init))]
+    for x, y in zip(a, b):
+        assert np.array_equal(x, y)
+    h1 = [host(t) for t in U.solve(p, s, 2, dev(torch, c.u0_init))]
+    h2 = [host(t) for t in U.solve(p, s, 2, dev(torch, h1[0]))]
+    assert np.array_equal(h2[0], a[0]) and np.array_equal(h2[1], a[1])
+    assert np.array_equal(h2[2][1:], a[2][3:])
+
+
+# ------------------------------------------------------- batch / serving
+
+def _mix():
+    out = [W.small_case(), CASES["ragged"](), CASES["tiny"]()]
+    p = W.gaussian_problem(0.1, 2.0, 4001, 25.0)
+    out.append(W.Case("n4001", p, W.Search(-30, 30, 3, 21), 2, W.init_sign(p, 2.0), 2.0))
+    return out
+
+
+def test_batch_equals_alone(env):
+    U, orc, torch = env
+    cases = _mix()
+    alone = [[host(t) for t in U.solve(c.prob, c.search, c.iters, dev(torch, c.u0_init))] for c in cases]
+    u0s, u1s, Js = U.solve_batch([c.prob for c in cases], [c.search for c in cases], [c.iters for c in cases],
+                                 [dev(torch, c.u0_init) for c in cases])
+    for b, c in enumerate(cases):
+        assert np.array_equal(host(u0s[b]), alone[b][0]), c.name
+        assert np.array_equal(host(u1s[b]), alone[b][1]), c.name
+        assert np.array_equal(host(Js[b]), alone[b][2]), c.name
+
+
+def test_server_mix_equals_alone(env):
+    U, orc, torch = env
+    cases = _mix() * 2
+    alone = [[host(t) for t in U.solve(c.prob, c.search, c.iters, dev(torch, c.u0_init))] for c in cases]
+    srv = U.Server(max_slots=3)
+    tickets = []
+    for k, c in enumerate(cases):  # staggered arrivals: submit while others run
+        tickets.append(srv.submit(c.prob, c.search, c.iters, c.u0_init))
+        if k % 2:
+            srv.step()
+    res = {}
+    for _ in range(200):
+        n = srv.step()
+        for t in tickets:
+            if t not in res:
+                r = srv.poll(t)
+                if r is not None:
+                    res[t] = r
+        if len(res) == len(tickets):
+            break
+    assert len(res) == len(tickets)
+    for t, c, a in zip(tickets, cases, alone):
+        u0, u1, J = res[t]
+        assert np.array_equal(u0, a[0]) and np.array_equal(u1, a[1]) and np.array_equal(J, a[2]), c.name
+    srv.close()
+
+
+def test_server_budget_cancel_and_nan(env):
+    U, orc, torch = env
+    c = W.small_case()
+    srv = U.Server(max_slots=8, hbm_budget=1)
+    with pytest.raises(U.UcpError):  # can never fit
+        srv.submit(c.prob, c.search, 2, c.u0_init)
+    srv.close()
+    # a budget that fits exactly one request: the second waits for the first
+    fp = U.footprint(c.prob, c.search, 3)
+    srv = U.Server(max_slots=8, hbm_budget=fp + fp // 2)
+    t1 = srv.submit(c.prob, c.search, 3, c.u0_init)
+    t2 = srv.submit(c.prob, c.search, 3, c.u0_init)
+    srv.step()
+    q, r, d = srv.stats()
+    assert (q, r) == (1, 1)
+    bad = c.u0_init.copy()
+    bad[500] = np.nan
+    t3 = srv.submit(c.prob, c.search, 2, bad)
+    t4 = srv.submit(c.prob, c.search, 2, c.u0_init)
+    srv.cancel(t4)
+    out = {}
+    for _ in range(50):
+        srv.step()
+        for t in (t1, t2):
+            if t not in out:
+                r = srv.poll(t)
+                if r is not None:
+                    out[t] = r
+        if t3 not in out:
+            try:
+                r = srv.poll(t3)
+                if r is not None:
+                    out[t3] = r
+            except U.UcpError as e:
+                assert e.code == U.ENONFINITE
+                out[t3] = "nonfinite"
+        if len(out) == 3:
+            break
+    assert out[t3] == "nonfinite"
+    ref = [host(t) for t in U.solve(c.prob, c.search, 3, dev(torch, c.u0_init))]
+    for t in (t1, t2):
+        assert np.array_equal(out[t][2], ref[2])
+    srv.close()
