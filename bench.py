@@ -114,10 +114,12 @@ def main():
     torch.cuda.synchronize()
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     ev0.record(st)
-    terms = 0
+    terms = evals = 0
     for k in range(a.steps):
         out = U.solve(p, s, case.iters, u0, a.prec)
-        terms += U.last_terms()
+        t_, e_ = U.last_counts()
+        terms += t_
+        evals += e_
     ev1.record(st)
     torch.cuda.synchronize()
     ms = ev0.elapsed_time(ev1)
@@ -141,6 +143,7 @@ def main():
         "config": {"workload": case.name, "n_x": p.n_x, "n_y": p.n_y, "levels": s.levels, "cands": s.cands,
                    "rounds": case.iters, "k": p.k, "sigma": case.sigma, "prec": a.prec},
         "alg_terms_per_step": terms / a.steps,
+        "fp64_tie_evals_per_step": evals / a.steps,
         "dense_equiv_terms_per_s": dense / (ms_step / 1e3),
         "solves_per_s": 1e3 / ms_step,
     }

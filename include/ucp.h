@@ -122,8 +122,10 @@ int ucp_marginal_cost(ucp_handle* h, const ucp_problem* prob, ucp_prec prec,
  * Selection at every level and at the final comparison with the incumbent:
  * the candidates within a relative band 1e-12 of the minimum (in FP64) are
  * ties, the one nearest u0_in[i] wins, then the smaller u.  In the FP32
- * modes the minimum and band are first found in FP32 with a band of 1e-5
- * and the band members are re-evaluated in FP64 before the rule is applied.
+ * modes the minimum and band are first found in FP32 - the band is
+ * B <= m (1 + tau) + 6e-7 sqrt(m), tau = 5e-7 with compensated sums and
+ * 5e-6 with plain sums - and the band members are re-evaluated in FP64
+ * before the rule is applied.
  * u1: [n_y]; u0_in, u0_out: [n_x] (may alias); L0_out: [n_x] or NULL - if
  * given, receives f(x_i) * B(u0_out[i]; x_i) evaluated in FP64.
  * Errors: UCP_EINVAL (null pointers, invalid problem or search). */
@@ -159,11 +161,13 @@ int ucp_solve(ucp_handle* h, const ucp_problem* prob, const ucp_search* search, 
               int32_t iters, const double* u0_init, double* u0_out, double* u1_out,
               double* J_hist, void* stream);
 
-/* Algorithmic marginal-cost terms of the last ucp_solve / ucp_solve_batch
- * on this handle: the number of (point, candidate, y node) triples with
- * |y_j - x_i - u| <= 9 over every level and round (the work the method
- * needs; the kernels evaluate a few more).  Errors: UCP_EINVAL. */
-int ucp_last_terms(ucp_handle* h, uint64_t* terms);
+/* Work counters of the last ucp_solve / ucp_solve_batch on this handle
+ * (either pointer may be NULL): `terms` = algorithmic marginal-cost terms,
+ * the (point, candidate, y node) triples with |y_j - x_i - u| <= 9 over
+ * every level and round (the work the method needs; the kernels evaluate a
+ * few more); `fp64_evals` = FP64 re-evaluations of FP32 tie-band members.
+ * Errors: UCP_EINVAL. */
+int ucp_last_counts(ucp_handle* h, uint64_t* terms, uint64_t* fp64_evals);
 
 /* B independent solves advanced together: every kernel launch covers all
  * instances still running (one flat work list per launch), each instance

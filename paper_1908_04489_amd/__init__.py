@@ -65,7 +65,7 @@ _sigs = {
     "ucp_solve": ([_vp, _P(Problem), _P(Search), C.c_int, C.c_int32, _vp, _vp, _vp, _vp, _vp], C.c_int),
     "ucp_solve_batch": ([_vp, C.c_int32, _P(Problem), _P(Search), C.c_int, _P(C.c_int32), _P(_vp), _P(_vp),
                          _P(_vp), _P(_vp), _vp], C.c_int),
-    "ucp_last_terms": ([_vp, _P(C.c_uint64)], C.c_int),
+    "ucp_last_counts": ([_vp, _P(C.c_uint64), _P(C.c_uint64)], C.c_int),
     "ucp_footprint": ([_P(Problem), _P(Search), C.c_int, C.c_int32, _P(C.c_size_t)], C.c_int),
     "ucp_server_create": ([_P(_vp), C.c_int, C.c_size_t, C.c_int32, C.c_int], C.c_int),
     "ucp_server_destroy": ([_vp], None),
@@ -261,11 +261,12 @@ def solve_batch(probs, searches, iters, u0_inits, prec="fp32_kahan"):
     return u0o, u1o, Jo
 
 
-def last_terms(device: int = 0) -> int:
-    """Algorithmic marginal-cost terms of the last solve on this thread's handle."""
-    n = C.c_uint64()
-    _check(_lib.ucp_last_terms(handle(device), C.byref(n)))
-    return n.value
+def last_counts(device: int = 0):
+    """(algorithmic marginal-cost terms, FP64 tie re-evaluations) of the last
+    solve on this thread's handle."""
+    n, e = C.c_uint64(), C.c_uint64()
+    _check(_lib.ucp_last_counts(handle(device), C.byref(n), C.byref(e)))
+    return n.value, e.value
 
 
 def footprint(prob, search, iters, prec="fp32_kahan") -> int:

@@ -138,7 +138,7 @@ size_t state_bytes(const Inst& I) {
   b += align_up(ny * 8) + align_up(ny * 4);                       // u1 v
   b += align_up(nx * (size_t)(I.cands + 1) * (size_t)I.segs * 8); // part
   b += align_up((size_t)I.u1_slices * ny * 3 * 8);                // u1part
-  b += 256;                                                       // flags
+  b += 256 + kCountBytes;                                         // flags, counters
   return b;
 }
 
@@ -163,7 +163,7 @@ void carve_state(Inst& I, char*& base) {
   I.part = (double*)take(nx * (size_t)(I.cands + 1) * (size_t)I.segs * 8);
   I.u1part = (double*)take((size_t)I.u1_slices * ny * 3 * 8);
   I.flags = (int32_t*)take(256);
-  I.terms = (unsigned long long*)((char*)I.flags + 64);
+  I.terms = (unsigned long long*)take(kCountBytes);
 }
 
 // Prefix sums of units for each kernel over a batch, for one set of running
@@ -204,6 +204,7 @@ struct ucp_handle {
   void* ws = nullptr;
   size_t ws_bytes = 0;
   unsigned long long last_terms = 0;  // algorithmic terms of the last solve
+  unsigned long long last_evals = 0;  // FP64 tie re-evaluations of the last solve
 };
 
 static int ensure_ws(ucp_handle* h, size_t bytes) {
@@ -228,9 +229,10 @@ static int ensure_ws(ucp_handle* h, size_t bytes) {
 
 extern "C" {
 
-int ucp_last_terms(ucp_handle* h, uint64_t* terms) {
-  if (!h || !terms) return fail(UCP_EINVAL, "NULL argument");
-  *terms = h->last_terms;
+int ucp_last_counts(ucp_handle* h, uint64_t* terms, uint64_t* fp64_evals) {
+  if (!h) return fail(UCP_EINVAL, "NULL handle");
+  if (terms) *terms = h->last_terms;
+  if (fp64_evals) *fp64_evals = h->last_evals;
   return UCP_OK;
 }
 
@@ -381,7 +383,7 @@ int ucp_solve_batch(ucp_handle* h, int32_t nb, const ucp_problem* probs, const u
   for (int b = 0; b < nb; ++b) {
     Inst& I = B.insts[b];
     UCP_TRY(hipMemcpyAsync(I.u0, u0_init[b], sizeof(double) * I.n_x, hipMemcpyDeviceToDevice, st), "copy u0_init");
-    UCP_TRY(hipMemsetAsync(I.flags, 0, 128, st), "clear flags and counters");
+    UCP_TRY(hipMemsetAsync(I.flags, 0, 256 + kCountBytes, st), "clear flags and counters");
   }
   // J_out of each instance is its J_hist: set through a second table upload
   for (int b = 0; b < nb; ++b) B.insts[b].J_out = J_hist[b];
@@ -390,17 +392,22 @@ int ucp_solve_batch(ucp_handle* h, int32_t nb, const ucp_problem* probs, const u
   for (int t = 1; t <= max_it; ++t)
     if ((rc = run_round(B, t, tab, prec, max_lv, t, st))) return rc;
   std::vector<int32_t> flags(nb, 0);
-  std::vector<unsigned long long> terms(nb, 0);
+  std::vector<unsigned long long> counts((size_t)nb * kCountSlots * kCountStride, 0);
   for (int b = 0; b < nb; ++b) {
     Inst& I = B.insts[b];
-    UCP_TRY(hipMemcpyAsync(&terms[b], I.terms, 8, hipMemcpyDeviceToHost, st), "read counters");
+    UCP_TRY(hipMemcpyAsync(&counts[(size_t)b * kCountSlots * kCountStride], I.terms, kCountBytes, hipMemcpyDeviceToHost, st),
+            "read counters");
     UCP_TRY(hipMemcpyAsync(u0_out[b], I.u0, sizeof(double) * I.n_x, hipMemcpyDeviceToDevice, st), "copy u0_out");
     UCP_TRY(hipMemcpyAsync(u1_out[b], I.u1, sizeof(double) * I.n_y, hipMemcpyDeviceToDevice, st), "copy u1_out");
     UCP_TRY(hipMemcpyAsync(&flags[b], I.flags, 4, hipMemcpyDeviceToHost, st), "read flags");
   }
   UCP_TRY(hipStreamSynchronize(st), "synchronise");
-  h->last_terms = 0;
-  for (int b = 0; b < nb; ++b) h->last_terms += terms[b];
+  h->last_terms = h->last_evals = 0;
+  for (int b = 0; b < nb; ++b)
+    for (int sl = 0; sl < kCountSlots; ++sl) {
+      h->last_terms += counts[((size_t)b * kCountSlots + sl) * kCountStride + kCountTerms];
+      h->last_evals += counts[((size_t)b * kCountSlots + sl) * kCountStride + kCountEvals];
+    }
   for (int b = 0; b < nb; ++b)
     if (flags[b]) return fail(UCP_ENONFINITE, "instance %d produced non-finite values", b);
   return UCP_OK;
@@ -426,6 +433,7 @@ int ucp_argmin_adaptive(ucp_handle* h, const ucp_problem* prob, const ucp_search
   if ((rc = setup_batch(h, B, {make_inst(*prob, search, prec, 0)}, phases, tab, st))) return rc;
   Inst& I = B.insts[0];
   I.L0_out = L0_out;
+  I.terms = nullptr;
   UCP_TRY(hipMemcpyAsync(I.u0, u0_in, sizeof(double) * I.n_x, hipMemcpyDeviceToDevice, st), "copy u0");
   UCP_TRY(hipMemcpyAsync(I.u1, u1, sizeof(double) * I.n_y, hipMemcpyDeviceToDevice, st), "copy u1");
   UCP_TRY(hipMemsetAsync(I.flags, 0, 128, st), "clear flags");
@@ -476,6 +484,7 @@ int ucp_objective(ucp_handle* h, const ucp_problem* prob, const double* u0, cons
   if ((rc = setup_batch(h, B, {make_inst(*prob, nullptr, UCP_FP64, 1)}, phases, tab, st))) return rc;
   Inst& I = B.insts[0];
   I.J_out = J_out;
+  I.terms = nullptr;
   UCP_TRY(hipMemcpyAsync(B.d_insts, B.insts.data(), sizeof(Inst), hipMemcpyHostToDevice, st), "upload instance");
   UCP_TRY(hipMemcpyAsync(I.u0, u0, sizeof(double) * I.n_x, hipMemcpyDeviceToDevice, st), "copy u0");
   UCP_TRY(hipMemcpyAsync(I.u1, u1, sizeof(double) * I.n_y, hipMemcpyDeviceToDevice, st), "copy u1");
@@ -504,6 +513,7 @@ int ucp_marginal_cost(ucp_handle* h, const ucp_problem* prob, ucp_prec prec, con
   if ((rc = setup_batch(h, B, {I0}, phases, tab, st))) return rc;
   Inst& I = B.insts[0];
   I.u0 = const_cast<double*>(u);  // the explicit candidates [n_x][n_cand], read only
+  I.terms = nullptr;
   UCP_TRY(hipMemcpyAsync(B.d_insts, B.insts.data(), sizeof(Inst), hipMemcpyHostToDevice, st), "upload instance");
   UCP_TRY(hipMemcpyAsync(I.u1, u1, sizeof(double) * I.n_y, hipMemcpyDeviceToDevice, st), "copy u1");
   UCP_TRY(launch_prior(B.launch(0, kKindPrior, tab), st), "prior kernel");

@@ -21,10 +21,20 @@ constexpr int kSelWaves = 4;    // selection kernel: one wave per point
 constexpr int kU1Block = 256;   // u1 kernels: one lane per y node
 constexpr int kU1Chunk = 512;   // x nodes staged in LDS per step of the u1 sums
 constexpr int kJWaves = 4;      // objective: one wave per x node
-constexpr double kTau32 = 1e-5; // FP32 tie band (relative)
+// FP32 tie band B32 <= m (1 + tau) + kappa sqrt(m): tau covers the relative
+// error of the Gaussian weights and of the sums, kappa sqrt(m) the rounding
+// of z - u1 in FP32, which dominates where the cost is small (measured
+// worst case |dB| ~ 2e-7 sqrt(B); kappa is three times that).
+constexpr double kTau32Kahan = 5e-7;
+constexpr double kTau32Plain = 5e-6;
+constexpr double kKappa32 = 6e-7;
 constexpr double kTau64 = 1e-12;// FP64 tie band (relative)
 constexpr double kWin32 = 9.0;  // window half-width, noise sds (FP32 terms)
-constexpr double kWin64 = 12.0; // window half-width, noise sds (FP64 terms)
+constexpr double kWin64 = 10.0; // window half-width, noise sds (FP64 terms)
+// Device counters (spread over slots on separate cache lines): algorithmic
+// marginal-cost terms and FP64 tie re-evaluations.
+constexpr int kCountSlots = 32, kCountStride = 16, kCountTerms = 0, kCountEvals = 8;
+constexpr size_t kCountBytes = (size_t)kCountSlots * kCountStride * 8;
 
 // One solve instance as the kernels see it: constants of the problem and the
 // search, launch geometry, and device pointers to its state.
@@ -64,7 +74,7 @@ struct Inst {
   double* J_out;             // objective output (one double)
   double* L0_out;            // optional FP64 L_0 of the accepted u0 [n_x] (argmin call only)
   int32_t* flags;            // bit 0: non-finite value met
-  unsigned long long* terms; // algorithmic marginal-cost terms evaluated (counter)
+  unsigned long long* terms; // counters [kCountSlots][kCountStride] (NULL: not counted)
 };
 
 // alpha^2 = log2(e) / 2, so exp(-t^2 / 2) = exp2(-(alpha t)^2).

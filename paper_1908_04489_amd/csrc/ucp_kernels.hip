@@ -85,19 +85,44 @@ __device__ __forceinline__ int nearest_node(const Inst& I, double z) {
 
 // FP64 window sum for one position z, spread over the 64 lanes of a wave:
 // returns dy/sqrt(2 pi) * sum_j phi(y_j - z) (z - u1_j)^2 over the nodes
-// within kWin64 of the node nearest z; the Gaussian is max-shifted to that
-// node, exp(-(t^2 - delta^2)/2) = exp(-d (d + 2 delta)/2) with d = (j - jr) dy,
-// and the shift exp(-delta^2/2) is applied once at the end.
+// within kWin64 of the node nearest z.  The Gaussian is max-shifted to that
+// node, g_k = exp(-(t_k^2 - delta^2)/2) = exp(-d (d + 2 delta)/2) with
+// d = k dy, and the shift exp(-delta^2/2) is applied once at the end.
+// Lane l takes k = klo + l + 64 m; along m the Gaussian obeys the exact
+// recurrence g_{k+64} = g_k r_k, r_{k+64} = r_k q with
+// r_k = exp(-64 dy t_k - (64 dy)^2 / 2) and q = exp(-(64 dy)^2), so two
+// multiplies replace an exp; both are recomputed by exp every kReseed steps,
+// which bounds the relative error of any weight by ~kReseed^2/2 ulp (1.4e-14).
+constexpr int kReseed = 16;
+
 __device__ double b64_wave(const Inst& I, double z, int lane) {
   const int jr = nearest_node(I, z);
   const double delta = (I.y_lo + (double)jr * I.dy) - z;
   const int klo = max(-I.nw64, -jr), khi = min(I.nw64, I.n_y - 1 - jr);
+  const double dy = I.dy, D = (double)kWave * dy;
+  const double q = exp(-D * D);
+  const double* __restrict__ u1 = I.u1 + jr;
   double s = 0.0;
-  for (int k = klo + lane; k <= khi; k += kWave) {
-    double d = (double)k * I.dy;
+  // this lane's nodes: k = klo + lane + 64 m for m = 0 .. steps - 1
+  const int steps = (khi - klo + kWave) / kWave;
+  for (int m0 = 0; m0 < steps; m0 += kReseed) {
+    const int kb = klo + lane + kWave * m0;
+    double uv[kReseed];
+#pragma unroll
+    for (int mm = 0; mm < kReseed; ++mm) {  // loads first, so they overlap
+      const int k = kb + kWave * mm;
+      uv[mm] = k <= khi ? u1[k] : z;  // past the window: e = 0, no term
+    }
+    const double d = (double)kb * dy;
     double g = exp(-0.5 * d * (d + 2.0 * delta));
-    double e = z - I.u1[jr + k];
-    s += g * e * e;
+    double r = exp(-D * (d + delta) - 0.5 * D * D);
+#pragma unroll
+    for (int mm = 0; mm < kReseed; ++mm) {
+      const double e = z - uv[mm];
+      s += (g * e) * e;
+      g *= r;
+      r *= q;
+    }
   }
   s = wave_sum_d(s);
   return I.phi_scale * exp(-0.5 * delta * delta) * s;
@@ -116,7 +141,8 @@ __device__ __forceinline__ void count_terms(const Inst& I, double z, bool act, i
     if (hi >= lo) n = (long long)(hi - lo) + 1;
   }
   for (int o = kWave / 2; o > 0; o >>= 1) n += __shfl_xor(n, o);
-  if (lane == 0 && n > 0 && I.terms) atomicAdd(I.terms, (unsigned long long)n);
+  if (lane == 0 && n > 0 && I.terms)
+    atomicAdd(I.terms + kCountTerms + (blockIdx.x & (kCountSlots - 1)) * kCountStride, (unsigned long long)n);
 }
 
 // ------------------------------------------------------------------ prior
@@ -430,7 +456,7 @@ struct Pick {
 // first and its members are re-evaluated in FP64.  Among the FP64 band the
 // member nearest the incumbent wins, then the smaller u, then the lower lane.
 __device__ Pick select_rule(const Inst& I, bool in_set, double c, double B32, double B64, double x,
-                            double uinc, int lane, int prec, int32_t* bad) {
+                            double uinc, int lane, int prec, int32_t* bad, int& n_eval) {
   const double big = INFINITY;
   const bool fin = in_set && isfinite(B32);
   const double m32 = wave_min_d(fin ? B32 : big);
@@ -447,7 +473,10 @@ __device__ Pick select_rule(const Inst& I, bool in_set, double c, double B32, do
     Bf = B32;
     band = fin && B32 <= m32 * (1.0 + kTau64);
   } else {
-    const bool b32 = fin && B32 <= m32 * (1.0 + kTau32);
+    // FP32 band: relative part for the weights and the sum, absolute part
+    // kKappa32 sqrt(m) for the rounding of z - u1 (|dB| grows like sqrt(B))
+    const double tau = prec == UCP_FP32_KAHAN ? kTau32Kahan : kTau32Plain;
+    const bool b32 = fin && B32 <= m32 * (1.0 + tau) + kKappa32 * sqrt(m32);
     const unsigned long long mask = __ballot(b32);
     if (__popcll(mask) == 1) {
       r.lane = __ffsll((long long)mask) - 1;
@@ -461,6 +490,7 @@ __device__ Pick select_rule(const Inst& I, bool in_set, double c, double B32, do
       const double cl = __shfl(c, L);
       const double v = I.k2 * cl * cl + b64_wave(I, x + cl, lane);
       if (lane == L) B64 = v;
+      ++n_eval;
     }
     Bf = B64;
     const double m64 = wave_min_d(b32 ? B64 : big);
@@ -508,7 +538,8 @@ __global__ __launch_bounds__(kSelWaves * kWave) void k_select(Launch L, int leve
     B64 = I.b64best[i];
   }
   const bool in_set = level == 0 ? lane < K : lane <= K;
-  Pick p = select_rule(I, in_set, c, B32, B64, x, uinc, lane, PREC, I.flags);
+  int n_eval = 0;
+  Pick p = select_rule(I, in_set, c, B32, B64, x, uinc, lane, PREC, I.flags, n_eval);
   const double cw = __shfl(c, p.lane);
   const double B32w = __shfl(B32, p.lane);
   double B64w = p.B64;
@@ -517,7 +548,10 @@ __global__ __launch_bounds__(kSelWaves * kWave) void k_select(Launch L, int leve
     I.b32best[i] = B32w;
     I.b64best[i] = B64w;
   }
-  if (level != I.levels - 1) return;
+  if (level != I.levels - 1) {
+    if (lane == 0 && n_eval && I.terms) atomicAdd(I.terms + kCountEvals + (blockIdx.x & (kCountSlots - 1)) * kCountStride, (unsigned long long)n_eval);
+    return;
+  }
 
   // acceptance against the incumbent
   double res = cw, Bres = B64w;
@@ -527,11 +561,12 @@ __global__ __launch_bounds__(kSelWaves * kWave) void k_select(Launch L, int leve
     const double c2 = lane == 0 ? cw : uinc;
     const double b32_2 = lane == 0 ? B32w : B32i;
     const double b64_2 = lane == 0 ? B64w : (PREC == UCP_FP64 ? B32i : NAN);
-    Pick q = select_rule(I, in2, c2, b32_2, b64_2, x, uinc, lane, PREC, I.flags);
+    Pick q = select_rule(I, in2, c2, b32_2, b64_2, x, uinc, lane, PREC, I.flags, n_eval);
     res = __shfl(c2, q.lane);
     Bres = q.B64;
   }
   if (want_l0 && isnan(Bres)) Bres = I.k2 * res * res + b64_wave(I, x + res, lane);
+  if (lane == 0 && n_eval && I.terms) atomicAdd(I.terms + kCountEvals + (blockIdx.x & (kCountSlots - 1)) * kCountStride, (unsigned long long)n_eval);
   if (lane == 0) {
     I.u0_next[i] = res;
     if (!isfinite(res)) atomicOr(I.flags, 1);
@@ -653,7 +688,10 @@ __global__ __launch_bounds__(kU1Block) void k_u1_combine(Launch L) {
   const double vres = num / den;
   const double u1 = y - vres;
   I.u1[j] = u1;
-  I.v[j] = (float)(sqrt(kAlpha2) * vres);
+  // the residual from the stored u1, exactly as k_v_from_u1 forms it, so a
+  // u0 update sees the same FP32 residual whether u1 came from here or
+  // from the caller
+  I.v[j] = (float)(sqrt(kAlpha2) * (y - u1));
   if (!isfinite(u1)) atomicOr(I.flags, 1);
 }
 
