@@ -27,7 +27,15 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
-PEAK_LANE_OPS = 256 * 64 * 2.4e9  # FP32 VALU lane-ops/s without packed math (256 CUs x 64 lanes x 2.4 GHz)
+# ALU roofline of the marginal-cost kernel.  MI355X issues 128 FP32 VALU
+# lane-operations per clock per CU without packed math (the published
+# 157.3 TFLOP/s FP32 vector peak counts an FMA as two flops):
+# 256 CUs x 128 x 2.4 GHz = 78.6e12 slots/s.  v_exp_f32 issues at a quarter
+# of that rate (4 slots).  One algorithmic term needs 5 FP32 operations
+# (argument, exponent, residual, product, accumulate), one exp2 and half an
+# operation of compensated accumulation (4 per block of 8 terms): 9.5 slots.
+PEAK_SLOTS = 256 * 128 * 2.4e9
+SLOTS_PER_TERM = 9.5
 
 
 def workload(name):
@@ -112,18 +120,25 @@ def main():
         print(f"# warmup {w} done", file=sys.stderr, flush=True)
     st = torch.cuda.current_stream()
     torch.cuda.synchronize()
+    U.profile(True)  # HIP events around every kernel launch of the timed solves, on this stream
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     ev0.record(st)
-    terms = evals = 0
+    terms = evaluated = evals = 0
     for k in range(a.steps):
         out = U.solve(p, s, case.iters, u0, a.prec)
-        t_, e_ = U.last_counts()
+        t_, v_, e_ = U.last_counts()
         terms += t_
+        evaluated += v_
         evals += e_
     ev1.record(st)
     torch.cuda.synchronize()
     ms = ev0.elapsed_time(ev1)
     ms_step = ms / a.steps
+    prof = U.profile_read()
+    U.profile(False)
+    mc_ms, mc_n = prof["marginal_cost"]
+    mc_avg_s = mc_ms / 1e3 / max(mc_n, 1)
+    achieved = terms / max(mc_n, 1) * SLOTS_PER_TERM / mc_avg_s
     value = terms / (ms / 1e3)
     C = s.levels * s.cands + 1
     dense = float(p.n_x) * C * p.n_y * case.iters
@@ -143,9 +158,17 @@ def main():
         "config": {"workload": case.name, "n_x": p.n_x, "n_y": p.n_y, "levels": s.levels, "cands": s.cands,
                    "rounds": case.iters, "k": p.k, "sigma": case.sigma, "prec": a.prec},
         "alg_terms_per_step": terms / a.steps,
+        "evaluated_terms_per_step": evaluated / a.steps,
         "fp64_tie_evals_per_step": evals / a.steps,
         "dense_equiv_terms_per_s": dense / (ms_step / 1e3),
         "solves_per_s": 1e3 / ms_step,
+        "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_SLOTS / 1e12,
+                     "unit": "Tslot/s", "frac": achieved / PEAK_SLOTS, "traffic": None,
+                     "kernel": "k_mc32<FP32_KAHAN> (marginal-cost window sums)",
+                     "per_unit": f"{SLOTS_PER_TERM} FP32 VALU slots per algorithmic term",
+                     "kernel_avg_us": mc_avg_s * 1e6, "kernel_launches": mc_n,
+                     "kernel_terms_per_s": terms / max(mc_n, 1) / mc_avg_s},
+        "kernel_ms_per_step": {k: v[0] / a.steps for k, v in prof.items()},
     }
     J = out[2].cpu().numpy()
     res["J_final"] = float(J[-1])

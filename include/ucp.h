@@ -162,12 +162,29 @@ int ucp_solve(ucp_handle* h, const ucp_problem* prob, const ucp_search* search, 
               double* J_hist, void* stream);
 
 /* Work counters of the last ucp_solve / ucp_solve_batch on this handle
- * (either pointer may be NULL): `terms` = algorithmic marginal-cost terms,
+ * (any pointer may be NULL): `terms` = algorithmic marginal-cost terms,
  * the (point, candidate, y node) triples with |y_j - x_i - u| <= 9 over
- * every level and round (the work the method needs; the kernels evaluate a
- * few more); `fp64_evals` = FP64 re-evaluations of FP32 tie-band members.
+ * every level and round (the work the method needs); `evaluated` = the
+ * terms the FP32 kernels actually summed (windows around the nearest node,
+ * which for x_i + u outside the y grid still cover the nodes near its
+ * edge); `fp64_evals` = FP64 re-evaluations of FP32 tie-band members.
  * Errors: UCP_EINVAL. */
-int ucp_last_counts(ucp_handle* h, uint64_t* terms, uint64_t* fp64_evals);
+int ucp_last_counts(ucp_handle* h, uint64_t* terms, uint64_t* evaluated, uint64_t* fp64_evals);
+
+/* Kernel timing: with profiling on, ucp_solve / ucp_solve_batch record a
+ * pair of HIP events on the caller's stream around each launch of the
+ * marginal-cost kernel (UCP_PROF_MC), the selection kernel
+ * (UCP_PROF_SELECT), the u1 kernels (UCP_PROF_U1) and the objective kernels
+ * (UCP_PROF_J); totals accumulate until profiling is switched again.
+ * ucp_profile(h, on) switches and resets; ucp_profile_read returns the
+ * total milliseconds and the launch count of one kind.  Errors: UCP_EINVAL. */
+#define UCP_PROF_MC 0
+#define UCP_PROF_SELECT 1
+#define UCP_PROF_U1 2
+#define UCP_PROF_J 3
+#define UCP_PROF_KINDS 4
+int ucp_profile(ucp_handle* h, int enable);
+int ucp_profile_read(ucp_handle* h, int kind, double* total_ms, int64_t* launches);
 
 /* B independent solves advanced together: every kernel launch covers all
  * instances still running (one flat work list per launch), each instance

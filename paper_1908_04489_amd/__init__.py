@@ -65,7 +65,9 @@ _sigs = {
     "ucp_solve": ([_vp, _P(Problem), _P(Search), C.c_int, C.c_int32, _vp, _vp, _vp, _vp, _vp], C.c_int),
     "ucp_solve_batch": ([_vp, C.c_int32, _P(Problem), _P(Search), C.c_int, _P(C.c_int32), _P(_vp), _P(_vp),
                          _P(_vp), _P(_vp), _vp], C.c_int),
-    "ucp_last_counts": ([_vp, _P(C.c_uint64), _P(C.c_uint64)], C.c_int),
+    "ucp_profile": ([_vp, C.c_int], C.c_int),
+    "ucp_profile_read": ([_vp, C.c_int, _P(C.c_double), _P(C.c_int64)], C.c_int),
+    "ucp_last_counts": ([_vp, _P(C.c_uint64), _P(C.c_uint64), _P(C.c_uint64)], C.c_int),
     "ucp_footprint": ([_P(Problem), _P(Search), C.c_int, C.c_int32, _P(C.c_size_t)], C.c_int),
     "ucp_server_create": ([_P(_vp), C.c_int, C.c_size_t, C.c_int32, C.c_int], C.c_int),
     "ucp_server_destroy": ([_vp], None),
@@ -261,12 +263,30 @@ def solve_batch(probs, searches, iters, u0_inits, prec="fp32_kahan"):
     return u0o, u1o, Jo
 
 
+PROF_KINDS = {"marginal_cost": 0, "select": 1, "u1": 2, "objective": 3}
+
+
+def profile(enable: bool, device: int = 0):
+    """Switch per-kernel HIP-event timing of solves on and off (resets totals)."""
+    _check(_lib.ucp_profile(handle(device), 1 if enable else 0))
+
+
+def profile_read(device: int = 0):
+    """{kind: (total_ms, launches)} accumulated since profiling was switched on."""
+    out = {}
+    for name, k in PROF_KINDS.items():
+        ms, n = C.c_double(), C.c_int64()
+        _check(_lib.ucp_profile_read(handle(device), k, C.byref(ms), C.byref(n)))
+        out[name] = (ms.value, n.value)
+    return out
+
+
 def last_counts(device: int = 0):
-    """(algorithmic marginal-cost terms, FP64 tie re-evaluations) of the last
-    solve on this thread's handle."""
-    n, e = C.c_uint64(), C.c_uint64()
-    _check(_lib.ucp_last_counts(handle(device), C.byref(n), C.byref(e)))
-    return n.value, e.value
+    """(algorithmic marginal-cost terms, terms evaluated, FP64 tie
+    re-evaluations) of the last solve on this thread's handle."""
+    n, v, e = C.c_uint64(), C.c_uint64(), C.c_uint64()
+    _check(_lib.ucp_last_counts(handle(device), C.byref(n), C.byref(v), C.byref(e)))
+    return n.value, v.value, e.value
 
 
 def footprint(prob, search, iters, prec="fp32_kahan") -> int:

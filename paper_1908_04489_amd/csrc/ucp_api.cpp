@@ -203,8 +203,16 @@ struct ucp_handle {
   int device = 0;
   void* ws = nullptr;
   size_t ws_bytes = 0;
+  // kernel timing with HIP events on the caller's stream (ucp_profile)
+  bool prof = false;
+  std::vector<hipEvent_t> ev;   // pool of event pairs
+  std::vector<int> ev_kind;     // kind of each recorded pair
+  size_t ev_used = 0;           // pairs recorded since the last harvest
+  double prof_ms[UCP_PROF_KINDS] = {0};
+  int64_t prof_n[UCP_PROF_KINDS] = {0};
   unsigned long long last_terms = 0;  // algorithmic terms of the last solve
   unsigned long long last_evals = 0;  // FP64 tie re-evaluations of the last solve
+  unsigned long long last_evaluated = 0;  // marginal-cost terms the kernels evaluated
 };
 
 static int ensure_ws(ucp_handle* h, size_t bytes) {
@@ -227,11 +235,64 @@ static int ensure_ws(ucp_handle* h, size_t bytes) {
   return UCP_OK;
 }
 
+// Event pair around one launch of `kind` (no-op unless profiling is on).
+static hipError_t prof_begin(ucp_handle* h, int kind, hipStream_t st) {
+  if (!h || !h->prof) return hipSuccess;
+  if (h->ev_used * 2 + 2 > h->ev.size()) {
+    for (int k = 0; k < 64; ++k) {
+      hipEvent_t e;
+      hipError_t r = hipEventCreate(&e);
+      if (r != hipSuccess) return r;
+      h->ev.push_back(e);
+    }
+  }
+  if (h->ev_kind.size() <= h->ev_used) h->ev_kind.resize(h->ev_used + 1);
+  h->ev_kind[h->ev_used] = kind;
+  return hipEventRecord(h->ev[h->ev_used * 2], st);
+}
+static hipError_t prof_end(ucp_handle* h, hipStream_t st) {
+  if (!h || !h->prof) return hipSuccess;
+  hipError_t r = hipEventRecord(h->ev[h->ev_used * 2 + 1], st);
+  h->ev_used++;
+  return r;
+}
+// Accumulate the recorded pairs (the stream has been synchronised).
+static void prof_harvest(ucp_handle* h) {
+  if (!h || !h->prof) return;
+  for (size_t p = 0; p < h->ev_used; ++p) {
+    float ms = 0.0f;
+    if (hipEventElapsedTime(&ms, h->ev[2 * p], h->ev[2 * p + 1]) == hipSuccess) {
+      h->prof_ms[h->ev_kind[p]] += ms;
+      h->prof_n[h->ev_kind[p]] += 1;
+    }
+  }
+  h->ev_used = 0;
+}
+
 extern "C" {
 
-int ucp_last_counts(ucp_handle* h, uint64_t* terms, uint64_t* fp64_evals) {
+int ucp_profile(ucp_handle* h, int enable) {
+  if (!h) return fail(UCP_EINVAL, "NULL handle");
+  h->prof = enable != 0;
+  h->ev_used = 0;
+  for (int k = 0; k < UCP_PROF_KINDS; ++k) {
+    h->prof_ms[k] = 0.0;
+    h->prof_n[k] = 0;
+  }
+  return UCP_OK;
+}
+
+int ucp_profile_read(ucp_handle* h, int kind, double* total_ms, int64_t* launches) {
+  if (!h || kind < 0 || kind >= UCP_PROF_KINDS) return fail(UCP_EINVAL, "bad handle or kind");
+  if (total_ms) *total_ms = h->prof_ms[kind];
+  if (launches) *launches = h->prof_n[kind];
+  return UCP_OK;
+}
+
+int ucp_last_counts(ucp_handle* h, uint64_t* terms, uint64_t* evaluated, uint64_t* fp64_evals) {
   if (!h) return fail(UCP_EINVAL, "NULL handle");
   if (terms) *terms = h->last_terms;
+  if (evaluated) *evaluated = h->last_evaluated;
   if (fp64_evals) *fp64_evals = h->last_evals;
   return UCP_OK;
 }
@@ -257,11 +318,10 @@ int ucp_create(ucp_handle** out, int device) {
 
 void ucp_destroy(ucp_handle* h) {
   if (!h) return;
-  if (h->ws) {
-    (void)hipSetDevice(h->device);
-    (void)hipDeviceSynchronize();
-    (void)hipFree(h->ws);
-  }
+  (void)hipSetDevice(h->device);
+  (void)hipDeviceSynchronize();
+  if (h->ws) (void)hipFree(h->ws);
+  for (hipEvent_t e : h->ev) (void)hipEventDestroy(e);
   delete h;
 }
 
@@ -321,17 +381,25 @@ int setup_batch(ucp_handle* h, Batch& B, std::vector<Inst> insts, const std::vec
 
 // One round for the running instances of `phase`: the u0 update over all
 // levels, the u0 advance, the u1 update and the objective into J[t].
-int run_round(const Batch& B, int phase, const std::vector<int32_t>& tab, int prec, int max_levels, int t,
-              hipStream_t st) {
+int run_round(ucp_handle* h, const Batch& B, int phase, const std::vector<int32_t>& tab, int prec, int max_levels,
+              int t, hipStream_t st) {
   for (int l = 0; l < max_levels; ++l) {
+    UCP_TRY(prof_begin(h, UCP_PROF_MC, st), "event");
     UCP_TRY(launch_mc(B.launch(phase, kKindMc0 + l, tab), l, prec, st), "marginal-cost kernel");
+    UCP_TRY(prof_end(h, st), "event");
+    UCP_TRY(prof_begin(h, UCP_PROF_SELECT, st), "event");
     UCP_TRY(launch_select(B.launch(phase, kKindSel0 + l, tab), l, prec, 0, st), "selection kernel");
+    UCP_TRY(prof_end(h, st), "event");
   }
   UCP_TRY(launch_copy_u0(B.launch(phase, kKindCopy, tab), st), "u0 advance kernel");
+  UCP_TRY(prof_begin(h, UCP_PROF_U1, st), "event");
   UCP_TRY(launch_u1_partial(B.launch(phase, kKindU1p, tab), prec, st), "u1 kernel");
   UCP_TRY(launch_u1_combine(B.launch(phase, kKindU1c, tab), st), "u1 combine kernel");
+  UCP_TRY(prof_end(h, st), "event");
+  UCP_TRY(prof_begin(h, UCP_PROF_J, st), "event");
   UCP_TRY(launch_j_rows(B.launch(phase, kKindJRows, tab), st), "objective kernel");
   UCP_TRY(launch_j_reduce_t(B.launch(phase, kKindJRed, tab), t, st), "objective reduce kernel");
+  UCP_TRY(prof_end(h, st), "event");
   return UCP_OK;
 }
 
@@ -390,7 +458,7 @@ int ucp_solve_batch(ucp_handle* h, int32_t nb, const ucp_problem* probs, const u
   UCP_TRY(hipMemcpyAsync(B.d_insts, B.insts.data(), sizeof(Inst) * nb, hipMemcpyHostToDevice, st), "upload instance table");
   if ((rc = run_init(B, 0, tab, prec, st))) return rc;
   for (int t = 1; t <= max_it; ++t)
-    if ((rc = run_round(B, t, tab, prec, max_lv, t, st))) return rc;
+    if ((rc = run_round(h, B, t, tab, prec, max_lv, t, st))) return rc;
   std::vector<int32_t> flags(nb, 0);
   std::vector<unsigned long long> counts((size_t)nb * kCountSlots * kCountStride, 0);
   for (int b = 0; b < nb; ++b) {
@@ -402,10 +470,12 @@ int ucp_solve_batch(ucp_handle* h, int32_t nb, const ucp_problem* probs, const u
     UCP_TRY(hipMemcpyAsync(&flags[b], I.flags, 4, hipMemcpyDeviceToHost, st), "read flags");
   }
   UCP_TRY(hipStreamSynchronize(st), "synchronise");
-  h->last_terms = h->last_evals = 0;
+  prof_harvest(h);
+  h->last_terms = h->last_evals = h->last_evaluated = 0;
   for (int b = 0; b < nb; ++b)
     for (int sl = 0; sl < kCountSlots; ++sl) {
       h->last_terms += counts[((size_t)b * kCountSlots + sl) * kCountStride + kCountTerms];
+      h->last_evaluated += counts[((size_t)b * kCountSlots + sl) * kCountStride + kCountEvalTerms];
       h->last_evals += counts[((size_t)b * kCountSlots + sl) * kCountStride + kCountEvals];
     }
   for (int b = 0; b < nb; ++b)

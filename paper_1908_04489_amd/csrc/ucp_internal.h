@@ -33,7 +33,7 @@ constexpr double kWin32 = 9.0;  // window half-width, noise sds (FP32 terms)
 constexpr double kWin64 = 10.0; // window half-width, noise sds (FP64 terms)
 // Device counters (spread over slots on separate cache lines): algorithmic
 // marginal-cost terms and FP64 tie re-evaluations.
-constexpr int kCountSlots = 32, kCountStride = 16, kCountTerms = 0, kCountEvals = 8;
+constexpr int kCountSlots = 32, kCountStride = 16, kCountTerms = 0, kCountEvalTerms = 4, kCountEvals = 8;
 constexpr size_t kCountBytes = (size_t)kCountSlots * kCountStride * 8;
 
 // One solve instance as the kernels see it: constants of the problem and the

@@ -342,7 +342,14 @@ __global__ __launch_bounds__(kMcBlock) void k_mc32(Launch L, int level) {
   __syncthreads();
   int blo = INT_MAX, bhi = INT_MIN;
   for (int w = 0; w < kMcBlock / kWave; ++w) { blo = min(blo, sred[0][w]); bhi = max(bhi, sred[1][w]); }
-  if (seg == 0) count_terms(I, z, act, lane);
+  if (seg == 0) {
+    count_terms(I, z, act, lane);
+    // terms this unit's (point, candidate) evaluates over all its segments
+    long long ev = act ? (long long)(min(nw, I.n_y - 1 - jr) - max(-nw, -jr) + 1) : 0;
+    for (int o = kWave / 2; o > 0; o >>= 1) ev += __shfl_xor(ev, o);
+    if (lane == 0 && ev > 0 && I.terms)
+      atomicAdd(I.terms + kCountEvalTerms + (blockIdx.x & (kCountSlots - 1)) * kCountStride, (unsigned long long)ev);
+  }
   const bool staged = bhi >= blo && bhi - blo + 1 <= kMcLds;
   if (staged)
     for (int j = blo + (int)threadIdx.x; j <= bhi; j += kMcBlock) sv[j - blo] = I.v[j];
@@ -599,8 +606,10 @@ int32_t units_u1_combine(const Inst& I) { return (I.n_y + kU1Block - 1) / kU1Blo
 
 template <int PREC>
 __global__ __launch_bounds__(kU1Block) void k_u1_partial(Launch L) {
-  __shared__ double sx1[kU1Chunk];
-  __shared__ double slf[kU1Chunk];
+  __shared__ double sx1[kU1Chunk];   // x1_i
+  __shared__ double sL[kU1Chunk];    // log2(e) log f_i
+  __shared__ float sx1f[kU1Chunk];   // x1_i in FP32 (maximum pass only)
+  __shared__ float slff[kU1Chunk];   // log f_i in FP32 (maximum pass only)
   const int u = blockIdx.x;
   const int b = find_inst(L.pre, L.n_inst, u);
   const Inst& I = L.insts[b];
@@ -610,9 +619,11 @@ __global__ __launch_bounds__(kU1Block) void k_u1_partial(Launch L) {
   const int j = tile * kU1Block + (int)threadIdx.x;
   const bool act = j < I.n_y;
   const double y = I.y_lo + (double)(act ? j : 0) * I.dy;
+  const float yf = (float)y;
   const int slen = (I.n_x + I.u1_slices - 1) / I.u1_slices;
   const int i0 = slice * slen, i1 = min(I.n_x, i0 + slen);
   const double log2e = 1.4426950408889634073599246810019;
+  const double c2 = 0.5 * log2e;
   double M = -INFINITY, den = 0.0, num64 = 0.0;
   float num = 0.0f, comp = 0.0f;
   for (int c0 = i0; c0 < i1; c0 += kU1Chunk) {
@@ -620,16 +631,22 @@ __global__ __launch_bounds__(kU1Block) void k_u1_partial(Launch L) {
     __syncthreads();
     for (int t = threadIdx.x; t < cn; t += kU1Block) {
       const int i = c0 + t;
-      sx1[t] = (I.x_lo + (double)i * I.dx) + I.u0[i];
-      slf[t] = I.logf[i];
+      const double x1 = (I.x_lo + (double)i * I.dx) + I.u0[i];
+      const double lf = I.logf[i];
+      sx1[t] = x1;
+      sL[t] = lf * log2e;
+      sx1f[t] = (float)x1;
+      slff[t] = (float)lf;
     }
     __syncthreads();
-    // chunk maximum of the logits
-    double mc = -INFINITY;
+    // chunk maximum of the logits, in FP32: only a shift, any value near
+    // the maximum works (the sums below use exact FP64 exponents)
+    float mcf = -INFINITY;
     for (int t = 0; t < cn; ++t) {
-      const double d = y - sx1[t];
-      mc = fmax(mc, slf[t] - 0.5 * d * d);
+      const float d = yf - sx1f[t];
+      mcf = fmaxf(mcf, fmaf(-0.5f * d, d, slff[t]));
     }
+    const double mc = (double)mcf;
     if (mc > M) {  // rescale what was summed under the old maximum
       const double r = M == -INFINITY ? 0.0 : exp(M - mc);
       den *= r;
@@ -641,10 +658,10 @@ __global__ __launch_bounds__(kU1Block) void k_u1_partial(Launch L) {
     const double Ml = M * log2e;
     for (int t = 0; t < cn; ++t) {
       const double d = y - sx1[t];
-      const double a = (slf[t] - 0.5 * d * d) * log2e - Ml;
+      const double a = fma(d, -c2 * d, sL[t] - Ml);  // log2 of the shifted weight
       if (PREC == UCP_FP64) {
         const double w = exp2(a);
-        num64 += w * d;
+        num64 = fma(w, d, num64);
         den += w;
       } else {
         const float w = __builtin_amdgcn_exp2f((float)a);
