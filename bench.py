@@ -90,6 +90,140 @@ def cpu_baseline(case, budget_s=12.0):
                       f"{dt:.1f} s wall; dense FP64 evaluation {dense / dt:.3e} terms/s"}
 
 
+def bench_batch(a):
+    """64 instances of the 65536-node mixture family in shared launches."""
+    import torch
+
+    import paper_1908_04489_amd as U
+    import workloads as W
+
+    cases = W.mixture_batch(a.instances, n=65536)
+    probs, srch = [c.prob for c in cases], [c.search for c in cases]
+    iters = [c.iters for c in cases]
+    u0s = [torch.as_tensor(c.u0_init).cuda() for c in cases]
+    print(f"# batch: {len(cases)} x 65536 nodes, 4x32, {iters[0]} rounds", file=sys.stderr, flush=True)
+    for w in range(a.warmup):
+        U.solve_batch(probs, srch, iters, u0s, a.prec)
+        print(f"# warmup {w} done", file=sys.stderr, flush=True)
+    st = torch.cuda.current_stream()
+    torch.cuda.synchronize()
+    U.profile(True)
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record(st)
+    terms = evaluated = evals = 0
+    for k in range(a.steps):
+        U.solve_batch(probs, srch, iters, u0s, a.prec)
+        t_, v_, e_ = U.last_counts()
+        terms, evaluated, evals = terms + t_, evaluated + v_, evals + e_
+        print(f"# step {k} done", file=sys.stderr, flush=True)
+    ev1.record(st)
+    torch.cuda.synchronize()
+    ms = ev0.elapsed_time(ev1)
+    prof = U.profile_read()
+    U.profile(False)
+    mc_ms, mc_n = prof["marginal_cost"]
+    mc_avg_s = mc_ms / 1e3 / max(mc_n, 1)
+    achieved = terms / max(mc_n, 1) * SLOTS_PER_TERM / mc_avg_s
+    res = {"metric": "marginal-cost quadrature terms/s", "value": terms / (ms / 1e3), "unit": "terms/s",
+           "n_gpus": 1, "steps": a.steps, "warmup": a.warmup, "ms_per_step": ms / a.steps,
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+           "config": {"workload": f"mixture-batch-{len(cases)}x65536-4x32", "instances": len(cases),
+                      "n_x": 65536, "levels": 4, "cands": 32, "rounds": iters[0], "prec": a.prec},
+           "alg_terms_per_step": terms / a.steps, "evaluated_terms_per_step": evaluated / a.steps,
+           "fp64_tie_evals_per_step": evals / a.steps,
+           "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_SLOTS / 1e12, "unit": "Tslot/s",
+                        "frac": achieved / PEAK_SLOTS, "traffic": None, "kernel_avg_us": mc_avg_s * 1e6,
+                        "kernel_launches": mc_n},
+           "kernel_ms_per_step": {k: v[0] / a.steps for k, v in prof.items()}}
+    print(json.dumps(res), flush=True)
+
+
+def bench_serving(a):
+    """Continuous batching on a Poisson trace against one solve at a time."""
+    import numpy as np
+    import torch
+
+    import paper_1908_04489_amd as U
+    import workloads as W
+
+    n = a.requests
+    trace = W.serving_trace(n_req=n, rate=1.0, seed=0)  # unit rate: arrival times rescaled below
+    unit_t = np.array([r.arrival for r in trace])
+
+    def run_server(arrivals, max_slots):
+        srv = U.Server(max_slots=max_slots, prec=a.prec)
+        t0 = time.perf_counter()
+        nxt = 0
+        done = {}
+        live = []
+        while len(done) < n:
+            now = time.perf_counter() - t0
+            while nxt < n and arrivals[nxt] <= now:
+                c = trace[nxt].case
+                live.append((srv.submit(c.prob, c.search, c.iters, c.u0_init), nxt))
+                nxt += 1
+            q, r, _ = srv.stats()
+            if q + r == 0:
+                if nxt < n:
+                    time.sleep(max(0.0, min(0.01, arrivals[nxt] - now)))
+                continue
+            srv.step()
+            t_now = time.perf_counter() - t0
+            keep = []
+            for tk, idx in live:
+                out = srv.poll(tk)
+                if out is None:
+                    keep.append((tk, idx))
+                else:
+                    done[idx] = t_now
+            live = keep
+        srv.close()
+        fin = np.array([done[i] for i in range(n)])
+        return fin
+
+    # saturated throughput: every request queued at t = 0
+    fin = run_server(np.zeros(n), a.slots)
+    sat = n / fin.max()
+    print(f"# server saturated: {sat:.1f} solves/s", file=sys.stderr, flush=True)
+    rate = 0.8 * sat
+    arrivals = unit_t / rate
+    fin = run_server(arrivals, a.slots)
+    lat = fin - arrivals
+    served = n / fin.max()
+    print(f"# server on the trace: {served:.1f} solves/s", file=sys.stderr, flush=True)
+    # one solve at a time (ucp_solve, B = 1), FIFO on the same trace: service
+    # times measured on the GPU, schedule start = max(arrival, previous end)
+    st = torch.cuda.current_stream()
+    svc = np.empty(n)
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    for i, r in enumerate(trace):
+        c = r.case
+        u0 = torch.as_tensor(c.u0_init).cuda()
+        ev0.record(st)
+        U.solve(c.prob, c.search, c.iters, u0, a.prec)
+        ev1.record(st)
+        ev1.synchronize()
+        svc[i] = ev0.elapsed_time(ev1) / 1e3
+    end = np.empty(n)
+    prev = 0.0
+    for i in range(n):
+        prev = max(arrivals[i], prev) + svc[i]
+        end[i] = prev
+    lat1 = end - arrivals
+    res = {"metric": "served solves/s", "value": served, "unit": "solves/s", "n_gpus": 1, "steps": 1,
+           "warmup": 0, "ms_per_step": fin.max() * 1e3, "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+           "config": {"workload": f"serving-poisson-{n}", "requests": n, "rate_per_s": rate,
+                      "sizes": [1001, 4001, 8001, 20001], "search": "3x21", "rounds": 20, "max_slots": a.slots,
+                      "prec": a.prec},
+           "p50_latency_s": float(np.percentile(lat, 50)), "p99_latency_s": float(np.percentile(lat, 99)),
+           "saturated_solves_per_s": sat,
+           "one_at_a_time": {"solves_per_s": n / end.max(), "p50_latency_s": float(np.percentile(lat1, 50)),
+                             "p99_latency_s": float(np.percentile(lat1, 99)),
+                             "mean_service_s": float(svc.mean()), "saturated_solves_per_s": n / svc.sum()}}
+    print(json.dumps(res), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -99,11 +233,19 @@ def main():
     ap.add_argument("--prec", default="fp32_kahan")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-check", action="store_true", help="skip the FP64 oracle check of the final J")
+    ap.add_argument("--requests", type=int, default=1024, help="serving: requests taken from the trace")
+    ap.add_argument("--slots", type=int, default=64, help="serving: concurrent solves")
+    ap.add_argument("--instances", type=int, default=64, help="batch: instances per launch")
     a = ap.parse_args()
     if a.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path (the solver shards over x0 "
               "rows by design, but only the single-GPU kernel is built and measured).", file=sys.stderr)
         sys.exit(2)
+
+    if a.workload == "batch":
+        return bench_batch(a)
+    if a.workload == "serving":
+        return bench_serving(a)
 
     import numpy as np
     import torch

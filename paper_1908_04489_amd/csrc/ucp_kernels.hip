@@ -92,8 +92,11 @@ __device__ __forceinline__ int nearest_node(const Inst& I, double z) {
 // recurrence g_{k+64} = g_k r_k, r_{k+64} = r_k q with
 // r_k = exp(-64 dy t_k - (64 dy)^2 / 2) and q = exp(-(64 dy)^2), so two
 // multiplies replace an exp; both are recomputed by exp every kReseed steps,
-// which bounds the relative error of any weight by ~kReseed^2/2 ulp (1.4e-14).
-constexpr int kReseed = 16;
+// which bounds the relative error of any weight by ~kReseed^2/2 ulp
+// (5.7e-14).  Loads are issued kPrefetch at a time; two accumulators split
+// the dependency chain of the sum.
+constexpr int kReseed = 32;
+constexpr int kPrefetch = 16;
 
 __device__ double b64_wave(const Inst& I, double z, int lane) {
   const int jr = nearest_node(I, z);
@@ -102,29 +105,35 @@ __device__ double b64_wave(const Inst& I, double z, int lane) {
   const double dy = I.dy, D = (double)kWave * dy;
   const double q = exp(-D * D);
   const double* __restrict__ u1 = I.u1 + jr;
-  double s = 0.0;
+  double s0 = 0.0, s1 = 0.0;
   // this lane's nodes: k = klo + lane + 64 m for m = 0 .. steps - 1
   const int steps = (khi - klo + kWave) / kWave;
   for (int m0 = 0; m0 < steps; m0 += kReseed) {
     const int kb = klo + lane + kWave * m0;
-    double uv[kReseed];
-#pragma unroll
-    for (int mm = 0; mm < kReseed; ++mm) {  // loads first, so they overlap
-      const int k = kb + kWave * mm;
-      uv[mm] = k <= khi ? u1[k] : z;  // past the window: e = 0, no term
-    }
     const double d = (double)kb * dy;
     double g = exp(-0.5 * d * (d + 2.0 * delta));
     double r = exp(-D * (d + delta) - 0.5 * D * D);
+    for (int p0 = 0; p0 < kReseed && m0 + p0 < steps; p0 += kPrefetch) {
+      double uv[kPrefetch];
 #pragma unroll
-    for (int mm = 0; mm < kReseed; ++mm) {
-      const double e = z - uv[mm];
-      s += (g * e) * e;
-      g *= r;
-      r *= q;
+      for (int mm = 0; mm < kPrefetch; ++mm) {  // loads first, so they overlap
+        const int k = kb + kWave * (p0 + mm);
+        uv[mm] = k <= khi ? u1[k] : z;  // past the window: e = 0, no term
+      }
+#pragma unroll
+      for (int mm = 0; mm < kPrefetch; mm += 2) {
+        const double e0 = z - uv[mm];
+        s0 = fma(g * e0, e0, s0);
+        g *= r;
+        r *= q;
+        const double e1 = z - uv[mm + 1];
+        s1 = fma(g * e1, e1, s1);
+        g *= r;
+        r *= q;
+      }
     }
   }
-  s = wave_sum_d(s);
+  const double s = wave_sum_d(s0 + s1);
   return I.phi_scale * exp(-0.5 * delta * delta) * s;
 }
 

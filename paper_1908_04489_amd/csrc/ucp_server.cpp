@@ -48,6 +48,10 @@ size_t round_up(size_t v) { return (v + 255) & ~(size_t)255; }
 }  // namespace
 
 struct ucp_server {
+  // device blocks of retired requests kept for reuse (size -> pointer);
+  // they count against the memory budget
+  std::multimap<size_t, void*> pool;
+  size_t pooled = 0;
   int device = 0;
   hipStream_t stream = nullptr;
   size_t budget = 0;  // 0 = unlimited
@@ -68,12 +72,39 @@ static size_t footprint(const Inst& I, int32_t iters) {
   return state_bytes(I) + round_up(sizeof(double) * (size_t)(iters + 1));
 }
 
+// Return a request's block to the pool (the stream has no work of it left).
 static void release(ucp_server* s, Request* r) {
   if (r->dmem) {
-    (void)hipFree(r->dmem);
+    s->pool.emplace(r->bytes, r->dmem);
+    s->pooled += r->bytes;
     r->dmem = nullptr;
     s->used -= r->bytes;
   }
+}
+
+static void drain_pool(ucp_server* s) {
+  for (auto& kv : s->pool) (void)hipFree(kv.second);
+  s->pool.clear();
+  s->pooled = 0;
+}
+
+// A block of exactly `bytes` from the pool, or a new allocation; pooled
+// blocks of other sizes are freed first when the budget needs the room.
+static void* acquire(ucp_server* s, size_t bytes) {
+  auto it = s->pool.find(bytes);
+  if (it != s->pool.end()) {
+    void* p = it->second;
+    s->pool.erase(it);
+    s->pooled -= bytes;
+    return p;
+  }
+  if (s->budget && s->used + s->pooled + bytes > s->budget) drain_pool(s);
+  void* p = nullptr;
+  if (hipMalloc(&p, bytes) != hipSuccess) {
+    drain_pool(s);
+    if (hipMalloc(&p, bytes) != hipSuccess) return nullptr;
+  }
+  return p;
 }
 
 extern "C" {
@@ -120,6 +151,7 @@ void ucp_server_destroy(ucp_server* s) {
     release(s, kv.second);
     delete kv.second;
   }
+  drain_pool(s);
   if (s->d_insts) (void)hipFree(s->d_insts);
   if (s->d_tab) (void)hipFree(s->d_tab);
   (void)hipStreamDestroy(s->stream);
@@ -206,9 +238,8 @@ static int admit(ucp_server* s) {
   while (!s->queue.empty() && (int32_t)s->running.size() < s->max_slots) {
     Request* r = s->reqs[s->queue.front()];
     if (s->budget && s->used + r->bytes > s->budget) break;  // arrival order: wait for memory
-    void* mem = nullptr;
-    hipError_t e = hipMalloc(&mem, r->bytes);
-    if (e != hipSuccess) {
+    void* mem = acquire(s, r->bytes);
+    if (!mem) {
       if (s->running.empty()) return fail(UCP_ENOMEM, "cannot allocate %zu bytes for a request", r->bytes);
       break;  // retry once running requests retire
     }
