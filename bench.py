@@ -224,6 +224,71 @@ def bench_serving(a):
     print(json.dumps(res), flush=True)
 
 
+def bench_sweep(a):
+    """Precision study on 20001-node grids: k in {0.05, 0.2, 0.5}, sigma in
+    {1, 5, 10}, seeds 0..8 (random 8-step initial u0), 3 rounds in each
+    arithmetic.  Errors against the FP64 oracle on the same state:
+    - J of the final state (oracle objective in full);
+    - u1 on sampled y rows (oracle u1 of the same u0);
+    - one more u0 update on sampled x rows (oracle argmin given the same u1
+      and u0): fraction of differing decisions and their FP64 cost gap;
+    - marginal cost at u0 on sampled rows (relative error).
+    Prints one JSON line with per-precision maxima and medians."""
+    import numpy as np
+    import torch
+
+    import oracle
+    import paper_1908_04489_amd as U
+    import workloads as W
+
+    cases = W.sweep_cases(n=a.sweep_n, seeds=range(a.sweep_seeds))
+    rng = np.random.default_rng(0)
+    stats = {p: {"J_rel": [], "u1_abs": [], "L0_rel": [], "u0_diff_frac": [], "u0_gap": [], "ms": []}
+             for p in ("fp32", "fp32_kahan", "fp64")}
+    for ci, c in enumerate(cases):
+        p, s = c.prob, c.search
+        x = oracle.grid(p.x_lo, p.x_hi, p.n_x)
+        rows = np.sort(rng.choice(p.n_x, a.sweep_rows, replace=False))
+        yrows = np.sort(rng.choice(p.n_y, a.sweep_rows, replace=False))
+        u0i = torch.as_tensor(c.u0_init).cuda()
+        for prec in ("fp32", "fp32_kahan", "fp64"):
+            t0 = time.perf_counter()
+            u0g, u1g, Jg = U.solve(p, s, 3, u0i, prec)
+            torch.cuda.synchronize()
+            stats[prec]["ms"].append((time.perf_counter() - t0) * 1e3)
+            u0 = u0g.cpu().numpy()
+            u1 = u1g.cpu().numpy()
+            Jo = oracle.objective(p, u0, u1)
+            stats[prec]["J_rel"].append(abs(Jg.cpu().numpy()[-1] - Jo) / Jo)
+            ref_u1 = oracle.update_u1(p, u0, rows=yrows)
+            got_u1 = U.update_u1(p, u0g, prec).cpu().numpy()[yrows]
+            f, _ = oracle.prior(p)
+            stats[prec]["u1_abs"].append(float(np.max(np.abs(got_u1 - ref_u1))))
+            L0g = U.marginal_cost(p, u1g, u0g[:, None].contiguous(), prec).cpu().numpy()[rows, 0]
+            L0o = np.array([f[i] * oracle.B(p, u1, x[i], u0[i]) for i in rows])
+            ok = L0o > 1e-300
+            stats[prec]["L0_rel"].append(float(np.max(np.abs(L0g[ok] - L0o[ok]) / L0o[ok])) if ok.any() else 0.0)
+            nxt = U.argmin_adaptive(p, s, u1g, u0g, prec).cpu().numpy()[rows]
+            ref, Bref = oracle.argmin(p, s, u1, u0, rows=rows)
+            d = np.nonzero(nxt != ref)[0]
+            stats[prec]["u0_diff_frac"].append(len(d) / len(rows))
+            gaps = [(oracle.B(p, u1, x[rows[r]], nxt[r]) - Bref[r]) / Bref[r] for r in d]
+            stats[prec]["u0_gap"].append(float(max(gaps)) if gaps else 0.0)
+        print(f"# {ci + 1}/{len(cases)} {c.name} J_rel " +
+              " ".join(f"{k}={stats[k]['J_rel'][-1]:.1e}" for k in stats), file=sys.stderr, flush=True)
+    summ = {}
+    for k, v in stats.items():
+        summ[k] = {m: {"max": float(np.max(x)), "median": float(np.median(x))} for m, x in v.items()}
+    res = {"metric": "precision sweep: error vs FP64 oracle", "value": summ["fp32_kahan"]["J_rel"]["max"],
+           "unit": "max relative J error (FP32 compensated)", "n_gpus": 1, "steps": len(cases), "warmup": 0,
+           "ms_per_step": float(np.mean(stats["fp32_kahan"]["ms"])), "higher_is_better": False,
+           "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+           "config": {"workload": f"precision-sweep-{a.sweep_n}", "instances": len(cases), "rounds": 3,
+                      "rows_sampled": a.sweep_rows},
+           "by_precision": summ}
+    print(json.dumps(res), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -236,6 +301,9 @@ def main():
     ap.add_argument("--requests", type=int, default=1024, help="serving: requests taken from the trace")
     ap.add_argument("--slots", type=int, default=64, help="serving: concurrent solves")
     ap.add_argument("--instances", type=int, default=64, help="batch: instances per launch")
+    ap.add_argument("--sweep-n", type=int, default=20001, help="sweep: grid nodes")
+    ap.add_argument("--sweep-seeds", type=int, default=9, help="sweep: seeds per (k, sigma)")
+    ap.add_argument("--sweep-rows", type=int, default=48, help="sweep: sampled rows per check")
     a = ap.parse_args()
     if a.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path (the solver shards over x0 "
@@ -246,6 +314,8 @@ def main():
         return bench_batch(a)
     if a.workload == "serving":
         return bench_serving(a)
+    if a.workload == "sweep":
+        return bench_sweep(a)
 
     import numpy as np
     import torch

@@ -14,6 +14,7 @@ namespace ucp {
 constexpr int kMaxLevels = UCP_MAX_LEVELS;
 constexpr int kMaxComp = UCP_MAX_COMP;
 constexpr int kWave = 64;
+constexpr int kXcds = 8;        // accelerator complex dies of an MI355X
 constexpr int kMcBlock = 256;   // marginal-cost kernel: one lane per point, 4 waves
 constexpr int kMcLds = 4096;    // FP32 residual nodes staged in LDS per block (16 KiB)
 constexpr int kMcSegMax = 2048; // longest window segment of one marginal-cost work unit

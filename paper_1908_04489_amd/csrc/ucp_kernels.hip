@@ -40,6 +40,16 @@ __device__ __forceinline__ int find_inst(const int32_t* __restrict__ pre, int n,
   return lo;
 }
 
+// Workgroups are dispatched to the XCDs round-robin (block b to XCD b % 8,
+// each XCD with its own L2).  Map so that each XCD takes a contiguous range
+// of work units: neighbouring points and whole instances then share one L2.
+// A bijection on [0, G).
+__device__ __forceinline__ int xcd_unit(int b, int G) {
+  const int q = G / kXcds, r = G % kXcds;
+  const int x = b % kXcds, idx = b / kXcds;
+  return x * q + min(x, r) + idx;
+}
+
 __device__ __forceinline__ int wave_min_i(int v) {
   for (int o = kWave / 2; o > 0; o >>= 1) v = min(v, __shfl_xor(v, o));
   return v;
@@ -159,7 +169,7 @@ __device__ __forceinline__ void count_terms(const Inst& I, double z, bool act, i
 int32_t units_prior(const Inst& I) { return (I.n_x + 255) / 256; }
 
 __global__ __launch_bounds__(256) void k_prior(Launch L) {
-  const int u = blockIdx.x;
+  const int u = xcd_unit(blockIdx.x, gridDim.x);
   const int b = find_inst(L.pre, L.n_inst, u);
   const Inst& I = L.insts[b];
   const int i = (u - L.pre[b]) * 256 + threadIdx.x;
@@ -314,7 +324,7 @@ __global__ __launch_bounds__(kMcBlock) void k_mc32(Launch L, int level) {
   constexpr bool KAHAN = PREC == UCP_FP32_KAHAN;
   __shared__ float sv[kMcLds];
   __shared__ int sred[2][kMcBlock / kWave];
-  const int u = blockIdx.x;
+  const int u = xcd_unit(blockIdx.x, gridDim.x);
   const int b = find_inst(L.pre, L.n_inst, u);
   const Inst& I = L.insts[b];
   int local = u - L.pre[b];
@@ -387,9 +397,11 @@ __global__ __launch_bounds__(kMcBlock) void k_mc32(Launch L, int level) {
 }
 
 // FP64 marginal cost (precision-study mode): lane = point, window kWin64,
-// the same shifted Gaussian as b64_wave; one segment.
+// the same shifted Gaussian as b64_wave, walked node by node with the exact
+// recurrence g_{k+1} = g_k r_k, r_{k+1} = r_k exp(-dy^2),
+// r_k = exp(-dy t_k - dy^2/2), reseeded by exp every kReseed nodes.
 __global__ __launch_bounds__(kMcBlock) void k_mc64(Launch L, int level) {
-  const int u = blockIdx.x;
+  const int u = xcd_unit(blockIdx.x, gridDim.x);
   const int b = find_inst(L.pre, L.n_inst, u);
   const Inst& I = L.insts[b];
   int local = u - L.pre[b];
@@ -406,14 +418,31 @@ __global__ __launch_bounds__(kMcBlock) void k_mc64(Launch L, int level) {
   const int jr = nearest_node(I, z);
   const double delta = (I.y_lo + (double)jr * I.dy) - z;
   const int klo = max(-I.nw64, -jr), khi = min(I.nw64, I.n_y - 1 - jr);
-  double s = 0.0;
-  for (int k = klo; k <= khi; ++k) {
-    double d = (double)k * I.dy;
+  const double dy = I.dy, qd = exp(-dy * dy);
+  const double* __restrict__ u1 = I.u1 + jr;
+  double s0 = 0.0, s1 = 0.0;
+  for (int k0 = klo; k0 <= khi; k0 += kReseed) {
+    const double d = (double)k0 * dy;
     double g = exp(-0.5 * d * (d + 2.0 * delta));
-    double e = z - I.u1[jr + k];
-    s += g * e * e;
+    double r = exp(-dy * (d + delta) - 0.5 * dy * dy);
+    const int k1 = min(khi, k0 + kReseed - 1);
+    int k = k0;
+    for (; k + 1 <= k1; k += 2) {
+      const double e0 = z - u1[k];
+      s0 = fma(g * e0, e0, s0);
+      g *= r;
+      r *= qd;
+      const double e1 = z - u1[k + 1];
+      s1 = fma(g * e1, e1, s1);
+      g *= r;
+      r *= qd;
+    }
+    if (k <= k1) {
+      const double e0 = z - u1[k];
+      s0 = fma(g * e0, e0, s0);
+    }
   }
-  I.part[(size_t)i * pstride + q] = s;
+  I.part[(size_t)i * pstride + q] = s0 + s1;
 }
 
 hipError_t launch_mc(const Launch& L, int level, int prec, hipStream_t st) {
@@ -443,7 +472,7 @@ __device__ __forceinline__ double b_from_parts(const Inst& I, int i, int q, int 
 
 // L_0 = f B for explicit candidates (ucp_marginal_cost).
 __global__ __launch_bounds__(256) void k_mc_finish(Launch L, double* out, int prec) {
-  const int u = blockIdx.x;
+  const int u = xcd_unit(blockIdx.x, gridDim.x);
   const int b = find_inst(L.pre, L.n_inst, u);
   const Inst& I = L.insts[b];
   const long idx = (long)(u - L.pre[b]) * 256 + threadIdx.x;
@@ -529,7 +558,7 @@ __device__ Pick select_rule(const Inst& I, bool in_set, double c, double B32, do
 
 template <int PREC>
 __global__ __launch_bounds__(kSelWaves * kWave) void k_select(Launch L, int level, int want_l0) {
-  const int u = blockIdx.x;
+  const int u = xcd_unit(blockIdx.x, gridDim.x);
   const int b = find_inst(L.pre, L.n_inst, u);
   const Inst& I = L.insts[b];
   const int wid = threadIdx.x / kWave, lane = threadIdx.x % kWave;
@@ -619,7 +648,7 @@ __global__ __launch_bounds__(kU1Block) void k_u1_partial(Launch L) {
   __shared__ double sL[kU1Chunk];    // log2(e) log f_i
   __shared__ float sx1f[kU1Chunk];   // x1_i in FP32 (maximum pass only)
   __shared__ float slff[kU1Chunk];   // log f_i in FP32 (maximum pass only)
-  const int u = blockIdx.x;
+  const int u = xcd_unit(blockIdx.x, gridDim.x);
   const int b = find_inst(L.pre, L.n_inst, u);
   const Inst& I = L.insts[b];
   const int local = u - L.pre[b];
@@ -695,7 +724,7 @@ __global__ __launch_bounds__(kU1Block) void k_u1_partial(Launch L) {
 }
 
 __global__ __launch_bounds__(kU1Block) void k_u1_combine(Launch L) {
-  const int u = blockIdx.x;
+  const int u = xcd_unit(blockIdx.x, gridDim.x);
   const int b = find_inst(L.pre, L.n_inst, u);
   const Inst& I = L.insts[b];
   const int j = (u - L.pre[b]) * kU1Block + (int)threadIdx.x;
@@ -743,7 +772,7 @@ hipError_t launch_u1_combine(const Launch& L, hipStream_t st) {
 int32_t units_j_rows(const Inst& I) { return (I.n_x + kJWaves - 1) / kJWaves; }
 
 __global__ __launch_bounds__(kJWaves * kWave) void k_j_rows(Launch L) {
-  const int u = blockIdx.x;
+  const int u = xcd_unit(blockIdx.x, gridDim.x);
   const int b = find_inst(L.pre, L.n_inst, u);
   const Inst& I = L.insts[b];
   const int wid = threadIdx.x / kWave, lane = threadIdx.x % kWave;
@@ -759,7 +788,7 @@ __global__ __launch_bounds__(kJWaves * kWave) void k_j_rows(Launch L) {
 // then a tree), times dx.  `t` selects the J_hist entry.
 __global__ __launch_bounds__(256) void k_j_reduce(Launch L, int t) {
   __shared__ double red[256];
-  const int b = find_inst(L.pre, L.n_inst, blockIdx.x);
+  const int b = find_inst(L.pre, L.n_inst, xcd_unit(blockIdx.x, gridDim.x));
   const Inst& I = L.insts[b];
   double s = 0.0;
   for (int i = threadIdx.x; i < I.n_x; i += 256) s += I.jrow[i];
@@ -793,7 +822,7 @@ hipError_t launch_j_reduce(const Launch& L, hipStream_t st) { return launch_j_re
 // ----------------------------------------------------------- u0 advance
 
 __global__ __launch_bounds__(256) void k_copy_u0(Launch L) {
-  const int u = blockIdx.x;
+  const int u = xcd_unit(blockIdx.x, gridDim.x);
   const int b = find_inst(L.pre, L.n_inst, u);
   const Inst& I = L.insts[b];
   const int i = (u - L.pre[b]) * 256 + threadIdx.x;
@@ -809,7 +838,7 @@ hipError_t launch_copy_u0(const Launch& L, hipStream_t st) {
 // Residual v_j = alpha (y_j - u1_j) in FP32 from a given u1 (argmin and
 // marginal-cost calls, where u1 is an input).
 __global__ __launch_bounds__(256) void k_v_from_u1(Launch L) {
-  const int u = blockIdx.x;
+  const int u = xcd_unit(blockIdx.x, gridDim.x);
   const int b = find_inst(L.pre, L.n_inst, u);
   const Inst& I = L.insts[b];
   const int j = (u - L.pre[b]) * 256 + threadIdx.x;
