@@ -30,12 +30,15 @@ if ROOT not in sys.path:
 # ALU roofline of the marginal-cost kernel.  MI355X issues 128 FP32 VALU
 # lane-operations per clock per CU without packed math (the published
 # 157.3 TFLOP/s FP32 vector peak counts an FMA as two flops):
-# 256 CUs x 128 x 2.4 GHz = 78.6e12 slots/s.  v_exp_f32 issues at a quarter
-# of that rate (4 slots).  One algorithmic term needs 5 FP32 operations
-# (argument, exponent, residual, product, accumulate), one exp2 and half an
-# operation of compensated accumulation (4 per block of 8 terms): 9.5 slots.
+# 256 CUs x 128 x 2.4 GHz = 78.6e12 slots/s; v_exp_f32 issues at a quarter
+# of that rate (4 slots).  The kernel factors the shifted Gaussian into a
+# per-offset table value and a per-lane exponential, so one algorithmic term
+# needs 5 FP32 operations (residual argument, residual, weight, product,
+# accumulate) and each block of 8 terms 11 more slots (one exp2 and its
+# argument, the block scale, the two-chain combine, 4 of compensation):
+# 5 + 11/8 = 6.375 slots per term.
 PEAK_SLOTS = 256 * 128 * 2.4e9
-SLOTS_PER_TERM = 9.5
+SLOTS_PER_TERM = 6.375
 
 
 def workload(name):

@@ -136,6 +136,7 @@ size_t state_bytes(const Inst& I) {
   size_t b = 0;
   b += 9 * align_up(nx * 8);                                      // u0 u0_next f logf cbest b32best b64best b32inc jrow
   b += align_up(ny * 8) + align_up(ny * 4);                       // u1 v
+  b += align_up((size_t)(2 * I.nw32 + 1) * 4);                     // gtab
   b += align_up(nx * (size_t)(I.cands + 1) * (size_t)I.segs * 8); // part
   b += align_up((size_t)I.u1_slices * ny * 3 * 8);                // u1part
   b += 256 + kCountBytes;                                         // flags, counters
@@ -160,6 +161,7 @@ void carve_state(Inst& I, char*& base) {
   I.jrow = (double*)take(nx * 8);
   I.u1 = (double*)take(ny * 8);
   I.v = (float*)take(ny * 4);
+  I.gtab = (float*)take((size_t)(2 * I.nw32 + 1) * 4);
   I.part = (double*)take(nx * (size_t)(I.cands + 1) * (size_t)I.segs * 8);
   I.u1part = (double*)take((size_t)I.u1_slices * ny * 3 * 8);
   I.flags = (int32_t*)take(256);
@@ -188,6 +190,7 @@ std::vector<int32_t> build_tables(const std::vector<Inst>& insts, const std::vec
         else if (k == kKindCopy) u = units_prior(I);
         else if (k == kKindFree) u = I.free_cands ? units_mc(I, -1) : 0;
         else if (k == kKindFin) u = I.free_cands ? (int32_t)(((int64_t)I.n_x * I.cands + 255) / 256) : 0;
+        else if (k == kKindGtab) u = units_gtab(I);
       }
       pre[b + 1] = pre[b] + u;
     }
@@ -406,6 +409,7 @@ int run_round(ucp_handle* h, const Batch& B, int phase, const std::vector<int32_
 // u1 and J[0] from the initial u0 (after the prior).
 int run_init(const Batch& B, int phase, const std::vector<int32_t>& tab, int prec, hipStream_t st) {
   UCP_TRY(launch_prior(B.launch(phase, kKindPrior, tab), st), "prior kernel");
+  UCP_TRY(launch_gtab(B.launch(phase, kKindGtab, tab), st), "offset table kernel");
   UCP_TRY(launch_u1_partial(B.launch(phase, kKindU1p, tab), prec, st), "u1 kernel");
   UCP_TRY(launch_u1_combine(B.launch(phase, kKindU1c, tab), st), "u1 combine kernel");
   UCP_TRY(launch_j_rows(B.launch(phase, kKindJRows, tab), st), "objective kernel");
@@ -509,6 +513,7 @@ int ucp_argmin_adaptive(ucp_handle* h, const ucp_problem* prob, const ucp_search
   UCP_TRY(hipMemsetAsync(I.flags, 0, 128, st), "clear flags");
   UCP_TRY(hipMemcpyAsync(B.d_insts, B.insts.data(), sizeof(Inst), hipMemcpyHostToDevice, st), "upload instance");
   UCP_TRY(launch_prior(B.launch(0, kKindPrior, tab), st), "prior kernel");
+  UCP_TRY(launch_gtab(B.launch(0, kKindGtab, tab), st), "offset table kernel");
   UCP_TRY(launch_v_from_u1(B.launch(0, kKindU1c, tab), st), "residual kernel");
   for (int l = 0; l < I.levels; ++l) {
     UCP_TRY(launch_mc(B.launch(0, kKindMc0 + l, tab), l, prec, st), "marginal-cost kernel");
@@ -534,6 +539,7 @@ int ucp_update_u1(ucp_handle* h, const ucp_problem* prob, ucp_prec prec, const d
   UCP_TRY(hipMemcpyAsync(I.u0, u0, sizeof(double) * I.n_x, hipMemcpyDeviceToDevice, st), "copy u0");
   UCP_TRY(hipMemsetAsync(I.flags, 0, 128, st), "clear flags");
   UCP_TRY(launch_prior(B.launch(0, kKindPrior, tab), st), "prior kernel");
+  UCP_TRY(launch_gtab(B.launch(0, kKindGtab, tab), st), "offset table kernel");
   UCP_TRY(launch_u1_partial(B.launch(0, kKindU1p, tab), prec, st), "u1 kernel");
   UCP_TRY(launch_u1_combine(B.launch(0, kKindU1c, tab), st), "u1 combine kernel");
   UCP_TRY(hipMemcpyAsync(u1_out, I.u1, sizeof(double) * I.n_y, hipMemcpyDeviceToDevice, st), "copy u1_out");
@@ -560,6 +566,7 @@ int ucp_objective(ucp_handle* h, const ucp_problem* prob, const double* u0, cons
   UCP_TRY(hipMemcpyAsync(I.u1, u1, sizeof(double) * I.n_y, hipMemcpyDeviceToDevice, st), "copy u1");
   UCP_TRY(hipMemsetAsync(I.flags, 0, 128, st), "clear flags");
   UCP_TRY(launch_prior(B.launch(0, kKindPrior, tab), st), "prior kernel");
+  UCP_TRY(launch_gtab(B.launch(0, kKindGtab, tab), st), "offset table kernel");
   UCP_TRY(launch_j_rows(B.launch(0, kKindJRows, tab), st), "objective kernel");
   UCP_TRY(launch_j_reduce_t(B.launch(0, kKindJRed, tab), 0, st), "objective reduce kernel");
   return UCP_OK;
@@ -587,6 +594,7 @@ int ucp_marginal_cost(ucp_handle* h, const ucp_problem* prob, ucp_prec prec, con
   UCP_TRY(hipMemcpyAsync(B.d_insts, B.insts.data(), sizeof(Inst), hipMemcpyHostToDevice, st), "upload instance");
   UCP_TRY(hipMemcpyAsync(I.u1, u1, sizeof(double) * I.n_y, hipMemcpyDeviceToDevice, st), "copy u1");
   UCP_TRY(launch_prior(B.launch(0, kKindPrior, tab), st), "prior kernel");
+  UCP_TRY(launch_gtab(B.launch(0, kKindGtab, tab), st), "offset table kernel");
   UCP_TRY(launch_v_from_u1(B.launch(0, kKindU1c, tab), st), "residual kernel");
   UCP_TRY(launch_mc(B.launch(0, kKindFree, tab), -1, prec, st), "marginal-cost kernel");
   Launch Lf = B.launch(0, kKindFin, tab);

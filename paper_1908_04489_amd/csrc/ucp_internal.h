@@ -14,7 +14,6 @@ namespace ucp {
 constexpr int kMaxLevels = UCP_MAX_LEVELS;
 constexpr int kMaxComp = UCP_MAX_COMP;
 constexpr int kWave = 64;
-constexpr int kXcds = 8;        // accelerator complex dies of an MI355X
 constexpr int kMcBlock = 256;   // marginal-cost kernel: one lane per point, 4 waves
 constexpr int kMcLds = 4096;    // FP32 residual nodes staged in LDS per block (16 KiB)
 constexpr int kMcSegMax = 2048; // longest window segment of one marginal-cost work unit
@@ -63,6 +62,7 @@ struct Inst {
   double* u0_next;           // updated first controller [n_x]
   double* u1;                // second controller [n_y]
   float* v;                  // alpha * (y_j - u1_j), FP32 [n_y]
+  float* gtab;               // exp(-(k dy)^2 / 2) for |k| <= nw32, FP32 [2 nw32 + 1]
   double* f;                 // prior density at x nodes [n_x]
   double* logf;              // its logarithm [n_x]
   double* cbest;             // best candidate so far [n_x]
@@ -92,6 +92,7 @@ struct Launch {
 
 // Kernel launchers (ucp_kernels.hip).  All enqueue on `st`.
 hipError_t launch_prior(const Launch& L, hipStream_t st);
+hipError_t launch_gtab(const Launch& L, hipStream_t st);
 hipError_t launch_mc(const Launch& L, int level, int prec, hipStream_t st);
 hipError_t launch_select(const Launch& L, int level, int prec, int final_l0, hipStream_t st);
 hipError_t launch_finish_free(const Launch& L, double* out, int prec, hipStream_t st);
@@ -109,5 +110,6 @@ int32_t units_u1_partial(const Inst& I);
 int32_t units_u1_combine(const Inst& I);
 int32_t units_j_rows(const Inst& I);
 int32_t units_prior(const Inst& I);
+int32_t units_gtab(const Inst& I);
 
 }  // namespace ucp

@@ -40,16 +40,6 @@ __device__ __forceinline__ int find_inst(const int32_t* __restrict__ pre, int n,
   return lo;
 }
 
-// Workgroups are dispatched to the XCDs round-robin (block b to XCD b % 8,
-// each XCD with its own L2).  Map so that each XCD takes a contiguous range
-// of work units: neighbouring points and whole instances then share one L2.
-// A bijection on [0, G).
-__device__ __forceinline__ int xcd_unit(int b, int G) {
-  const int q = G / kXcds, r = G % kXcds;
-  const int x = b % kXcds, idx = b / kXcds;
-  return x * q + min(x, r) + idx;
-}
-
 __device__ __forceinline__ int wave_min_i(int v) {
   for (int o = kWave / 2; o > 0; o >>= 1) v = min(v, __shfl_xor(v, o));
   return v;
@@ -169,7 +159,7 @@ __device__ __forceinline__ void count_terms(const Inst& I, double z, bool act, i
 int32_t units_prior(const Inst& I) { return (I.n_x + 255) / 256; }
 
 __global__ __launch_bounds__(256) void k_prior(Launch L) {
-  const int u = xcd_unit(blockIdx.x, gridDim.x);
+  const int u = blockIdx.x;
   const int b = find_inst(L.pre, L.n_inst, u);
   const Inst& I = L.insts[b];
   const int i = (u - L.pre[b]) * 256 + threadIdx.x;
@@ -190,9 +180,29 @@ __global__ __launch_bounds__(256) void k_prior(Launch L) {
   I.logf[i] = lmax + log(acc);
 }
 
+// Offset table of the marginal-cost kernel: G_k = exp(-(k dy)^2 / 2) =
+// exp2(-(k alpha dy)^2) for |k| <= nw32, rounded once from FP64.
+__global__ __launch_bounds__(256) void k_gtab(Launch L) {
+  const int u = blockIdx.x;
+  const int b = find_inst(L.pre, L.n_inst, u);
+  const Inst& I = L.insts[b];
+  const int k = (u - L.pre[b]) * 256 + (int)threadIdx.x - I.nw32;
+  if (k > I.nw32) return;
+  const double d = (double)k * I.dy;
+  I.gtab[k + I.nw32] = (float)exp(-0.5 * d * d);
+}
+
+int32_t units_gtab(const Inst& I) { return (2 * I.nw32 + 1 + 255) / 256; }
+
 hipError_t launch_prior(const Launch& L, hipStream_t st) {
   if (L.total == 0) return hipSuccess;
   hipLaunchKernelGGL(k_prior, dim3(L.total), dim3(256), 0, st, L);
+  return hipGetLastError();
+}
+
+hipError_t launch_gtab(const Launch& L, hipStream_t st) {
+  if (L.total == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_gtab, dim3(L.total), dim3(256), 0, st, L);
   return hipGetLastError();
 }
 
@@ -200,16 +210,22 @@ hipError_t launch_prior(const Launch& L, hipStream_t st) {
 //
 // Work unit = (tile of 256 consecutive points, candidate q, window segment).
 // Lane = point.  For point i and candidate c: z = x_i + c, jr = nearest y
-// node, delta = y_jr - z, and with t_j = y_j - z = (j - jr) dy + delta the
-// unit sums, over its segment of the window |j - jr| <= nw32,
-//   sum_j exp(-(t_j^2 - delta^2)/2) (z - u1_j)^2
-// in scaled units T = alpha t (alpha^2 = log2(e)/2) so the Gaussian is one
-// v_exp_f32 of -(T^2 - alpha^2 delta^2), and (z - u1_j) = v_j - t_j with the
-// residual v_j = y_j - u1_j formed in FP64 by the u1 kernel (stored as
-// alpha v_j in FP32).  Every term is <= 1 after the shift, so FP32 neither
-// overflows nor underflows inside the window.  The block stages the range of
-// v it touches in LDS (falls back to global loads when the range of the block
-// exceeds kMcLds nodes, e.g. across a jump of the controller).
+// node, delta = y_jr - z, and with t_k = y_{jr+k} - z = k dy + delta the unit
+// sums, over its segment of the window |k| <= nw32,
+//   sum_k exp(-(t_k^2 - delta^2)/2) (z - u1_{jr+k})^2.
+// In scaled units (alpha^2 = log2(e)/2) the shifted Gaussian factors as
+//   exp(-(t_k^2 - delta^2)/2) = G_k * E_k,
+//   G_k = exp2(-(k alpha dy)^2)          (the same for every lane: a table),
+//   E_k = exp2(beta k), beta = -2 alpha^2 dy delta (one constant per lane).
+// Every lane of a wave is at the same window offset k, so G_k is one LDS
+// broadcast; E_k costs one v_exp_f32 per block of 8 offsets times the
+// per-lane constants exp2(beta m), m < 8.  The residual z - u1 = v - T with
+// T = alpha t (v = alpha (y - u1), formed in FP64 by the u1 kernel).  After
+// the shift every weight is <= 1, so FP32 neither overflows nor underflows
+// where terms matter.  The block stages the residual nodes it touches and
+// the G values of its offsets in LDS (falls back to global loads for the
+// residual when its node range exceeds kMcLds, e.g. across a jump of the
+// controller).
 
 int32_t units_mc(const Inst& I, int level) {
   if (level >= 0 && level >= I.levels) return 0;
@@ -221,23 +237,6 @@ int32_t units_mc(const Inst& I, int level) {
 typedef const __attribute__((address_space(3))) float* lds_cptr;
 typedef const __attribute__((address_space(1))) float* glb_cptr;
 
-// One term of the marginal-cost sum at window offset k (as a float), given
-// the residual node value vk: returns g (the shifted Gaussian) and e (z - u1_j
-// in scaled units).
-template <bool TFORM>
-__device__ __forceinline__ void mc_term(float kf, float vk, float aDy, float Dl, float Dl2, float& g,
-                                        float& e) {
-  if (TFORM) {
-    const float T = fmaf(kf, aDy, Dl);
-    g = __builtin_amdgcn_exp2f(fmaf(-T, T, Dl2));
-    e = vk - T;
-  } else {
-    const float D = kf * aDy, t = D + Dl;
-    g = __builtin_amdgcn_exp2f(-D * (t + Dl));
-    e = vk - t;
-  }
-}
-
 __device__ __forceinline__ void kahan_add(float x, float& acc, float& comp) {
   const float y = x - comp;
   const float t = acc + y;
@@ -245,54 +244,61 @@ __device__ __forceinline__ void kahan_add(float x, float& acc, float& comp) {
   acc = t;
 }
 
-// Terms k in [k0, k1] (wave-uniform bounds, every lane in range) read from
-// p[k]; blocks of 8 terms are summed plainly and the block sum is added
-// with compensation (KAHAN) or every term is accumulated plainly.
-template <bool TFORM, bool KAHAN, typename P>
-__device__ __forceinline__ void mc_bulk(P p, int k0, int k1, float aDy, float Dl, float Dl2, float& acc,
+constexpr int kMcUnroll = 8;
+
+// Per-lane constants of one unit.
+struct McLane {
+  float aDy;             // alpha dy
+  float Dl;              // alpha delta
+  float beta;            // -2 alpha^2 dy delta
+  float R[kMcUnroll];    // exp2(beta m)
+  float Dm[kMcUnroll];   // Dl + m alpha dy
+};
+
+// Offsets k in [k0, k1] (wave-uniform bounds, every lane in range): blocks of
+// 8 terms summed plainly in two chains, each block sum added with
+// compensation (KAHAN) or plainly.
+template <bool KAHAN, typename P>
+__device__ __forceinline__ void mc_bulk(P v, lds_cptr G, int k0, int k1, const McLane& c, float& acc,
                                         float& comp) {
-  constexpr int U = 8;
-  float Dm[U];
-#pragma unroll
-  for (int m = 0; m < U; ++m) Dm[m] = TFORM ? fmaf((float)m, aDy, Dl) : (float)m * aDy;
   int k = k0;
-  for (; k + U - 1 <= k1; k += U) {
+  for (; k + kMcUnroll - 1 <= k1; k += kMcUnroll) {
     const float kf = (float)k;
-    float blk = 0.0f;
+    // E_{k+m} = E_k R_m: the common factor E_k multiplies the block sum
+    const float E0 = __builtin_amdgcn_exp2f(c.beta * kf);
+    float b0 = 0.0f, b1 = 0.0f;
 #pragma unroll
-    for (int m = 0; m < U; ++m) {
-      const float vk = p[k + m];
-      float g, e;
-      if (TFORM) {
-        const float T = fmaf(kf, aDy, Dm[m]);
-        g = __builtin_amdgcn_exp2f(fmaf(-T, T, Dl2));
-        e = vk - T;
-      } else {
-        const float D = fmaf(kf, aDy, Dm[m]), t = D + Dl;
-        g = __builtin_amdgcn_exp2f(-D * (t + Dl));
-        e = vk - t;
-      }
-      if (KAHAN) blk = fmaf(g * e, e, blk);
-      else acc = fmaf(g * e, e, acc);
+    for (int m = 0; m < kMcUnroll; m += 2) {
+      const float T0 = fmaf(kf, c.aDy, c.Dm[m]);
+      const float g0 = G[k + m] * c.R[m];
+      const float e0 = v[k + m] - T0;
+      const float T1 = fmaf(kf, c.aDy, c.Dm[m + 1]);
+      const float g1 = G[k + m + 1] * c.R[m + 1];
+      const float e1 = v[k + m + 1] - T1;
+      b0 = fmaf(g0 * e0, e0, b0);
+      b1 = fmaf(g1 * e1, e1, b1);
     }
-    if (KAHAN) kahan_add(blk, acc, comp);
+    if (KAHAN) kahan_add(E0 * (b0 + b1), acc, comp);
+    else acc = fmaf(E0, b0 + b1, acc);
   }
   for (; k <= k1; ++k) {
-    float g, e;
-    mc_term<TFORM>((float)k, p[k], aDy, Dl, Dl2, g, e);
+    const float kf = (float)k;
+    const float g = G[k] * __builtin_amdgcn_exp2f(c.beta * kf);
+    const float e = v[k] - fmaf(kf, c.aDy, c.Dl);
     if (KAHAN) kahan_add((g * e) * e, acc, comp);
     else acc = fmaf(g * e, e, acc);
   }
 }
 
-// Terms k in [k0, k1] restricted to the lane's own range [klo, khi].
-template <bool TFORM, bool KAHAN, typename P>
-__device__ __forceinline__ void mc_masked(P p, int k0, int k1, int klo, int khi, float aDy, float Dl,
-                                          float Dl2, float& acc, float& comp) {
+// Offsets k in [k0, k1] restricted to the lane's own range [klo, khi].
+template <bool KAHAN, typename P>
+__device__ __forceinline__ void mc_masked(P v, lds_cptr G, int k0, int k1, int klo, int khi, const McLane& c,
+                                          float& acc, float& comp) {
   for (int k = k0; k <= k1; ++k) {
     if (k >= klo && k <= khi) {
-      float g, e;
-      mc_term<TFORM>((float)k, p[k], aDy, Dl, Dl2, g, e);
+      const float kf = (float)k;
+      const float g = G[k] * __builtin_amdgcn_exp2f(c.beta * kf);
+      const float e = v[k] - fmaf(kf, c.aDy, c.Dl);
       if (KAHAN) kahan_add((g * e) * e, acc, comp);
       else acc = fmaf(g * e, e, acc);
     }
@@ -301,8 +307,8 @@ __device__ __forceinline__ void mc_masked(P p, int k0, int k1, int klo, int khi,
 
 // The lane's window [klo, khi] (empty when klo > khi): the range common to
 // every non-empty lane of the wave runs unmasked, the ragged ends masked.
-template <bool TFORM, bool KAHAN, typename P>
-__device__ __forceinline__ void mc_lane(P p, int klo, int khi, float aDy, float Dl, float Dl2, float& acc,
+template <bool KAHAN, typename P>
+__device__ __forceinline__ void mc_lane(P v, lds_cptr G, int klo, int khi, const McLane& c, float& acc,
                                         float& comp) {
   const bool empty = klo > khi;
   const int kc_lo = __builtin_amdgcn_readfirstlane(wave_max_i(empty ? INT_MIN : klo));
@@ -311,20 +317,21 @@ __device__ __forceinline__ void mc_lane(P p, int klo, int khi, float aDy, float 
   const int ku_hi = __builtin_amdgcn_readfirstlane(wave_max_i(empty ? INT_MIN : khi));
   if (ku_lo > ku_hi || empty) return;
   if (kc_lo > kc_hi) {
-    mc_masked<TFORM, KAHAN>(p, ku_lo, ku_hi, klo, khi, aDy, Dl, Dl2, acc, comp);
+    mc_masked<KAHAN>(v, G, ku_lo, ku_hi, klo, khi, c, acc, comp);
     return;
   }
-  mc_masked<TFORM, KAHAN>(p, ku_lo, kc_lo - 1, klo, khi, aDy, Dl, Dl2, acc, comp);
-  mc_bulk<TFORM, KAHAN>(p, kc_lo, kc_hi, aDy, Dl, Dl2, acc, comp);
-  mc_masked<TFORM, KAHAN>(p, kc_hi + 1, ku_hi, klo, khi, aDy, Dl, Dl2, acc, comp);
+  mc_masked<KAHAN>(v, G, ku_lo, kc_lo - 1, klo, khi, c, acc, comp);
+  mc_bulk<KAHAN>(v, G, kc_lo, kc_hi, c, acc, comp);
+  mc_masked<KAHAN>(v, G, kc_hi + 1, ku_hi, klo, khi, c, acc, comp);
 }
 
 template <int PREC>
 __global__ __launch_bounds__(kMcBlock) void k_mc32(Launch L, int level) {
   constexpr bool KAHAN = PREC == UCP_FP32_KAHAN;
   __shared__ float sv[kMcLds];
-  __shared__ int sred[2][kMcBlock / kWave];
-  const int u = xcd_unit(blockIdx.x, gridDim.x);
+  __shared__ float sg[kMcSegMax];
+  __shared__ int sred[4][kMcBlock / kWave];
+  const int u = blockIdx.x;
   const int b = find_inst(L.pre, L.n_inst, u);
   const Inst& I = L.insts[b];
   int local = u - L.pre[b];
@@ -351,16 +358,27 @@ __global__ __launch_bounds__(kMcBlock) void k_mc32(Launch L, int level) {
   int klo = max(s_lo, -jr), khi = min(s_hi, I.n_y - 1 - jr);
   if (!act) { klo = 1; khi = 0; }
 
-  // node range of the block, for LDS staging
+  // node range and offset range of the block, for LDS staging
   const int wid = threadIdx.x / kWave, lane = threadIdx.x % kWave;
-  int jlo = klo <= khi ? jr + klo : INT_MAX;
-  int jhi = klo <= khi ? jr + khi : INT_MIN;
-  jlo = wave_min_i(jlo);
-  jhi = wave_max_i(jhi);
-  if (lane == 0) { sred[0][wid] = jlo; sred[1][wid] = jhi; }
+  const bool ne = klo <= khi;
+  const int jlo = wave_min_i(ne ? jr + klo : INT_MAX);
+  const int jhi = wave_max_i(ne ? jr + khi : INT_MIN);
+  const int klw = wave_min_i(ne ? klo : INT_MAX);
+  const int khw = wave_max_i(ne ? khi : INT_MIN);
+  if (lane == 0) {
+    sred[0][wid] = jlo;
+    sred[1][wid] = jhi;
+    sred[2][wid] = klw;
+    sred[3][wid] = khw;
+  }
   __syncthreads();
-  int blo = INT_MAX, bhi = INT_MIN;
-  for (int w = 0; w < kMcBlock / kWave; ++w) { blo = min(blo, sred[0][w]); bhi = max(bhi, sred[1][w]); }
+  int blo = INT_MAX, bhi = INT_MIN, bklo = INT_MAX, bkhi = INT_MIN;
+  for (int w = 0; w < kMcBlock / kWave; ++w) {
+    blo = min(blo, sred[0][w]);
+    bhi = max(bhi, sred[1][w]);
+    bklo = min(bklo, sred[2][w]);
+    bkhi = max(bkhi, sred[3][w]);
+  }
   if (seg == 0) {
     count_terms(I, z, act, lane);
     // terms this unit's (point, candidate) evaluates over all its segments
@@ -372,26 +390,31 @@ __global__ __launch_bounds__(kMcBlock) void k_mc32(Launch L, int level) {
   const bool staged = bhi >= blo && bhi - blo + 1 <= kMcLds;
   if (staged)
     for (int j = blo + (int)threadIdx.x; j <= bhi; j += kMcBlock) sv[j - blo] = I.v[j];
+  // offsets lie inside the segment, so at most kMcSegMax of them
+  if (bkhi >= bklo)
+    for (int k = bklo + (int)threadIdx.x; k <= bkhi; k += kMcBlock) sg[k - bklo] = I.gtab[k + nw];
   __syncthreads();
 
+  McLane cl;
   const double alpha = sqrt(kAlpha2);
-  const float aDy = (float)(alpha * I.dy);
-  const float Dl = (float)(alpha * delta);
-  const float Dl2 = Dl * Dl;
-  // T-form (fewer operations) when every lane of the wave sits within one
-  // spacing of its nearest node; otherwise the d-form keeps the shifted
-  // exponent -(d (d + 2 delta)) accurate for z far outside the grid.
-  const bool tform = __builtin_amdgcn_readfirstlane(wave_min_i((act && fabs(delta) > I.dy) ? 0 : 1)) == 1;
+  cl.aDy = (float)(alpha * I.dy);
+  cl.Dl = (float)(alpha * delta);
+  const double beta = -2.0 * kAlpha2 * I.dy * delta;
+  cl.beta = (float)beta;
+#pragma unroll
+  for (int m = 0; m < kMcUnroll; ++m) {
+    cl.R[m] = __builtin_amdgcn_exp2f((float)(beta * m));
+    cl.Dm[m] = (float)(alpha * (delta + m * I.dy));
+  }
 
   float acc = 0.0f, comp = 0.0f;
+  lds_cptr G = (lds_cptr)(sg - (bkhi >= bklo ? bklo : 0));
   if (staged) {
-    lds_cptr p = (lds_cptr)(sv + (jr - blo));
-    if (tform) mc_lane<true, KAHAN>(p, klo, khi, aDy, Dl, Dl2, acc, comp);
-    else mc_lane<false, KAHAN>(p, klo, khi, aDy, Dl, Dl2, acc, comp);
+    lds_cptr v = (lds_cptr)(sv + (jr - blo));
+    mc_lane<KAHAN>(v, G, klo, khi, cl, acc, comp);
   } else {
-    glb_cptr p = (glb_cptr)(I.v + jr);
-    if (tform) mc_lane<true, KAHAN>(p, klo, khi, aDy, Dl, Dl2, acc, comp);
-    else mc_lane<false, KAHAN>(p, klo, khi, aDy, Dl, Dl2, acc, comp);
+    glb_cptr v = (glb_cptr)(I.v + jr);
+    mc_lane<KAHAN>(v, G, klo, khi, cl, acc, comp);
   }
   if (act) I.part[((size_t)i * pstride + q) * S + seg] = KAHAN ? (double)acc - (double)comp : (double)acc;
 }
@@ -401,7 +424,7 @@ __global__ __launch_bounds__(kMcBlock) void k_mc32(Launch L, int level) {
 // recurrence g_{k+1} = g_k r_k, r_{k+1} = r_k exp(-dy^2),
 // r_k = exp(-dy t_k - dy^2/2), reseeded by exp every kReseed nodes.
 __global__ __launch_bounds__(kMcBlock) void k_mc64(Launch L, int level) {
-  const int u = xcd_unit(blockIdx.x, gridDim.x);
+  const int u = blockIdx.x;
   const int b = find_inst(L.pre, L.n_inst, u);
   const Inst& I = L.insts[b];
   int local = u - L.pre[b];
@@ -472,7 +495,7 @@ __device__ __forceinline__ double b_from_parts(const Inst& I, int i, int q, int 
 
 // L_0 = f B for explicit candidates (ucp_marginal_cost).
 __global__ __launch_bounds__(256) void k_mc_finish(Launch L, double* out, int prec) {
-  const int u = xcd_unit(blockIdx.x, gridDim.x);
+  const int u = blockIdx.x;
   const int b = find_inst(L.pre, L.n_inst, u);
   const Inst& I = L.insts[b];
   const long idx = (long)(u - L.pre[b]) * 256 + threadIdx.x;
@@ -558,7 +581,7 @@ __device__ Pick select_rule(const Inst& I, bool in_set, double c, double B32, do
 
 template <int PREC>
 __global__ __launch_bounds__(kSelWaves * kWave) void k_select(Launch L, int level, int want_l0) {
-  const int u = xcd_unit(blockIdx.x, gridDim.x);
+  const int u = blockIdx.x;
   const int b = find_inst(L.pre, L.n_inst, u);
   const Inst& I = L.insts[b];
   const int wid = threadIdx.x / kWave, lane = threadIdx.x % kWave;
@@ -648,7 +671,7 @@ __global__ __launch_bounds__(kU1Block) void k_u1_partial(Launch L) {
   __shared__ double sL[kU1Chunk];    // log2(e) log f_i
   __shared__ float sx1f[kU1Chunk];   // x1_i in FP32 (maximum pass only)
   __shared__ float slff[kU1Chunk];   // log f_i in FP32 (maximum pass only)
-  const int u = xcd_unit(blockIdx.x, gridDim.x);
+  const int u = blockIdx.x;
   const int b = find_inst(L.pre, L.n_inst, u);
   const Inst& I = L.insts[b];
   const int local = u - L.pre[b];
@@ -724,7 +747,7 @@ __global__ __launch_bounds__(kU1Block) void k_u1_partial(Launch L) {
 }
 
 __global__ __launch_bounds__(kU1Block) void k_u1_combine(Launch L) {
-  const int u = xcd_unit(blockIdx.x, gridDim.x);
+  const int u = blockIdx.x;
   const int b = find_inst(L.pre, L.n_inst, u);
   const Inst& I = L.insts[b];
   const int j = (u - L.pre[b]) * kU1Block + (int)threadIdx.x;
@@ -772,7 +795,7 @@ hipError_t launch_u1_combine(const Launch& L, hipStream_t st) {
 int32_t units_j_rows(const Inst& I) { return (I.n_x + kJWaves - 1) / kJWaves; }
 
 __global__ __launch_bounds__(kJWaves * kWave) void k_j_rows(Launch L) {
-  const int u = xcd_unit(blockIdx.x, gridDim.x);
+  const int u = blockIdx.x;
   const int b = find_inst(L.pre, L.n_inst, u);
   const Inst& I = L.insts[b];
   const int wid = threadIdx.x / kWave, lane = threadIdx.x % kWave;
@@ -788,7 +811,7 @@ __global__ __launch_bounds__(kJWaves * kWave) void k_j_rows(Launch L) {
 // then a tree), times dx.  `t` selects the J_hist entry.
 __global__ __launch_bounds__(256) void k_j_reduce(Launch L, int t) {
   __shared__ double red[256];
-  const int b = find_inst(L.pre, L.n_inst, xcd_unit(blockIdx.x, gridDim.x));
+  const int b = find_inst(L.pre, L.n_inst, blockIdx.x);
   const Inst& I = L.insts[b];
   double s = 0.0;
   for (int i = threadIdx.x; i < I.n_x; i += 256) s += I.jrow[i];
@@ -822,7 +845,7 @@ hipError_t launch_j_reduce(const Launch& L, hipStream_t st) { return launch_j_re
 // ----------------------------------------------------------- u0 advance
 
 __global__ __launch_bounds__(256) void k_copy_u0(Launch L) {
-  const int u = xcd_unit(blockIdx.x, gridDim.x);
+  const int u = blockIdx.x;
   const int b = find_inst(L.pre, L.n_inst, u);
   const Inst& I = L.insts[b];
   const int i = (u - L.pre[b]) * 256 + threadIdx.x;
@@ -838,7 +861,7 @@ hipError_t launch_copy_u0(const Launch& L, hipStream_t st) {
 // Residual v_j = alpha (y_j - u1_j) in FP32 from a given u1 (argmin and
 // marginal-cost calls, where u1 is an input).
 __global__ __launch_bounds__(256) void k_v_from_u1(Launch L) {
-  const int u = xcd_unit(blockIdx.x, gridDim.x);
+  const int u = blockIdx.x;
   const int b = find_inst(L.pre, L.n_inst, u);
   const Inst& I = L.insts[b];
   const int j = (u - L.pre[b]) * 256 + threadIdx.x;

@@ -20,6 +20,7 @@ enum : int {
   kKindCopy,
   kKindFree,  // marginal-cost kernel on explicit candidates
   kKindFin,   // L_0 = f B for explicit candidates
+  kKindGtab,  // offset table of the marginal-cost kernel
   kKinds
 };
 

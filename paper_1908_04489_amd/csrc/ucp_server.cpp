@@ -333,6 +333,7 @@ extern "C" int ucp_server_step(ucp_server* s, int32_t* n_running) {
     hipStream_t st = s->stream;
     // set-up of the new requests
     SRV_TRY(launch_prior(L(0, kKindPrior, 0), st), "prior kernel");
+    SRV_TRY(launch_gtab(L(0, kKindGtab, 0), st), "offset table kernel");
     SRV_TRY(launch_u1_partial(L(0, kKindU1p, 0), prec, st), "u1 kernel");
     SRV_TRY(launch_u1_combine(L(0, kKindU1c, 0), st), "u1 combine kernel");
     SRV_TRY(launch_j_rows(L(0, kKindJRows, 0), st), "objective kernel");
