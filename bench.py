@@ -41,6 +41,34 @@ PEAK_SLOTS = 256 * 128 * 2.4e9
 SLOTS_PER_TERM = 6.375
 
 
+def kernel_source_hash():
+    import hashlib
+
+    path = os.path.join(ROOT, "paper_1908_04489_amd", "csrc", "ucp_kernels.hip")
+    return hashlib.sha256(open(path, "rb").read()).hexdigest()[:16]
+
+
+def measured_traffic(workload_name):
+    """HBM bytes per launch of the marginal-cost kernel from the committed
+    rocprofv3 PMC summary (FETCH_SIZE and WRITE_SIZE, scaled by the same
+    counters on a plain copy of known size), or None when the summary is
+    missing or was taken on a different kernel source."""
+    path = os.path.join(ROOT, "profiles", f"pmc-traffic_{workload_name}.md")
+    if not os.path.exists(path):
+        return None
+    vals = {}
+    for line in open(path):
+        if ":" in line and line.startswith("- "):
+            k, v = line[2:].split(":", 1)
+            vals[k.strip()] = v.strip().strip("`")
+    if vals.get("kernel source sha256[:16]") != kernel_source_hash():
+        return None
+    try:
+        return float(vals["marginal-cost kernel HBM bytes per launch"])
+    except (KeyError, ValueError):
+        return None
+
+
 def workload(name):
     import workloads as W
 
@@ -110,7 +138,7 @@ def bench_batch(a):
         print(f"# warmup {w} done", file=sys.stderr, flush=True)
     st = torch.cuda.current_stream()
     torch.cuda.synchronize()
-    U.profile(True)
+    U.profile(["marginal_cost"])  # HIP events around each marginal-cost launch of the timed steps
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     ev0.record(st)
     terms = evaluated = evals = 0
@@ -122,9 +150,8 @@ def bench_batch(a):
     ev1.record(st)
     torch.cuda.synchronize()
     ms = ev0.elapsed_time(ev1)
-    prof = U.profile_read()
-    U.profile(False)
-    mc_ms, mc_n = prof["marginal_cost"]
+    mc_ms, mc_n = U.profile_read()["marginal_cost"]
+    breakdown = kernel_breakdown(U, lambda: U.solve_batch(probs, srch, iters, u0s, a.prec))
     mc_avg_s = mc_ms / 1e3 / max(mc_n, 1)
     achieved = terms / max(mc_n, 1) * SLOTS_PER_TERM / mc_avg_s
     res = {"metric": "marginal-cost quadrature terms/s", "value": terms / (ms / 1e3), "unit": "terms/s",
@@ -137,7 +164,7 @@ def bench_batch(a):
            "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_SLOTS / 1e12, "unit": "Tslot/s",
                         "frac": achieved / PEAK_SLOTS, "traffic": None, "kernel_avg_us": mc_avg_s * 1e6,
                         "kernel_launches": mc_n},
-           "kernel_ms_per_step": {k: v[0] / a.steps for k, v in prof.items()}}
+           "kernel_ms_per_step": breakdown}
     print(json.dumps(res), flush=True)
 
 
@@ -292,6 +319,34 @@ def bench_sweep(a):
     print(json.dumps(res), flush=True)
 
 
+def kernel_breakdown(U, step):
+    """Milliseconds per kind of kernel in one extra, untimed step with every
+    launch bracketed by HIP events (the events themselves add a few
+    microseconds per launch, which is why the timed steps time only the
+    marginal-cost kernel)."""
+    import torch
+
+    torch.cuda.synchronize()
+    U.profile(True)
+    step()
+    torch.cuda.synchronize()
+    prof = U.profile_read()
+    U.profile(None)
+    return {k: v[0] for k, v in prof.items()}
+
+
+def copy_calibration():
+    """Plain device-to-device copies of a known size (3 x 256 MiB), run under
+    rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE to scale those counters to bytes."""
+    import torch
+
+    x = torch.empty(64 << 20, dtype=torch.float32, device="cuda").uniform_()
+    for _ in range(3):
+        x.clone()
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_calibration_bytes": 3 * (256 << 20)}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -319,6 +374,8 @@ def main():
         return bench_serving(a)
     if a.workload == "sweep":
         return bench_sweep(a)
+    if a.workload == "copy-calibration":
+        return copy_calibration()
 
     import numpy as np
     import torch
@@ -335,7 +392,7 @@ def main():
         print(f"# warmup {w} done", file=sys.stderr, flush=True)
     st = torch.cuda.current_stream()
     torch.cuda.synchronize()
-    U.profile(True)  # HIP events around every kernel launch of the timed solves, on this stream
+    U.profile(["marginal_cost"])  # HIP events around each marginal-cost launch of the timed solves
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     ev0.record(st)
     terms = evaluated = evals = 0
@@ -349,9 +406,8 @@ def main():
     torch.cuda.synchronize()
     ms = ev0.elapsed_time(ev1)
     ms_step = ms / a.steps
-    prof = U.profile_read()
-    U.profile(False)
-    mc_ms, mc_n = prof["marginal_cost"]
+    mc_ms, mc_n = U.profile_read()["marginal_cost"]
+    breakdown = kernel_breakdown(U, lambda: U.solve(p, s, case.iters, u0, a.prec))
     mc_avg_s = mc_ms / 1e3 / max(mc_n, 1)
     achieved = terms / max(mc_n, 1) * SLOTS_PER_TERM / mc_avg_s
     value = terms / (ms / 1e3)
@@ -378,12 +434,12 @@ def main():
         "dense_equiv_terms_per_s": dense / (ms_step / 1e3),
         "solves_per_s": 1e3 / ms_step,
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_SLOTS / 1e12,
-                     "unit": "Tslot/s", "frac": achieved / PEAK_SLOTS, "traffic": None,
+                     "unit": "Tslot/s", "frac": achieved / PEAK_SLOTS, "traffic": measured_traffic(case.name),
                      "kernel": "k_mc32<FP32_KAHAN> (marginal-cost window sums)",
                      "per_unit": f"{SLOTS_PER_TERM} FP32 VALU slots per algorithmic term",
                      "kernel_avg_us": mc_avg_s * 1e6, "kernel_launches": mc_n,
                      "kernel_terms_per_s": terms / max(mc_n, 1) / mc_avg_s},
-        "kernel_ms_per_step": {k: v[0] / a.steps for k, v in prof.items()},
+        "kernel_ms_per_step": breakdown,
     }
     J = out[2].cpu().numpy()
     res["J_final"] = float(J[-1])

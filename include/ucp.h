@@ -171,18 +171,22 @@ int ucp_solve(ucp_handle* h, const ucp_problem* prob, const ucp_search* search, 
  * Errors: UCP_EINVAL. */
 int ucp_last_counts(ucp_handle* h, uint64_t* terms, uint64_t* evaluated, uint64_t* fp64_evals);
 
-/* Kernel timing: with profiling on, ucp_solve / ucp_solve_batch record a
- * pair of HIP events on the caller's stream around each launch of the
- * marginal-cost kernel (UCP_PROF_MC), the selection kernel
- * (UCP_PROF_SELECT), the u1 kernels (UCP_PROF_U1) and the objective kernels
- * (UCP_PROF_J); totals accumulate until profiling is switched again.
- * ucp_profile(h, on) switches and resets; ucp_profile_read returns the
- * total milliseconds and the launch count of one kind.  Errors: UCP_EINVAL. */
+/* Kernel timing: ucp_solve / ucp_solve_batch record a pair of HIP events on
+ * the caller's stream around each launch of every kind selected in the
+ * profiling mask: the marginal-cost kernel (UCP_PROF_MC), the selection
+ * kernels (UCP_PROF_SELECT), the u1 kernels (UCP_PROF_U1) and the
+ * objective kernels (UCP_PROF_J); totals accumulate until the mask is set
+ * again.  ucp_profile(h, mask) sets the mask (bit 1 << kind per kind, 0 =
+ * off, UCP_PROF_ALL = every kind) and resets the totals; ucp_profile_read
+ * returns the total milliseconds and the launch count of one kind.  Each
+ * timed launch costs a few microseconds of stream time for its events, so
+ * time only the kinds needed.  Errors: UCP_EINVAL (unknown kind bits). */
 #define UCP_PROF_MC 0
 #define UCP_PROF_SELECT 1
 #define UCP_PROF_U1 2
 #define UCP_PROF_J 3
 #define UCP_PROF_KINDS 4
+#define UCP_PROF_ALL 15
 int ucp_profile(ucp_handle* h, int enable);
 int ucp_profile_read(ucp_handle* h, int kind, double* total_ms, int64_t* launches);
 

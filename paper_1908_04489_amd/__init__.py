@@ -18,7 +18,8 @@ import re
 import threading
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libucp.so")
+# UCP_LIBRARY selects another build of the library (e.g. one compiled with different flags)
+LIB_PATH = os.environ.get("UCP_LIBRARY") or os.path.join(HERE, "libucp.so")
 HEADER = os.path.join(os.path.dirname(HERE), "include", "ucp.h")
 
 FP32, FP32_KAHAN, FP64 = 0, 1, 2
@@ -266,9 +267,19 @@ def solve_batch(probs, searches, iters, u0_inits, prec="fp32_kahan"):
 PROF_KINDS = {"marginal_cost": 0, "select": 1, "u1": 2, "objective": 3}
 
 
-def profile(enable: bool, device: int = 0):
-    """Switch per-kernel HIP-event timing of solves on and off (resets totals)."""
-    _check(_lib.ucp_profile(handle(device), 1 if enable else 0))
+def profile(kinds=None, device: int = 0):
+    """Set per-kernel HIP-event timing of solves (resets totals): ``kinds`` is
+    an iterable of names from PROF_KINDS, True for all, and None/False/empty
+    for off."""
+    if kinds is True:
+        mask = (1 << len(PROF_KINDS)) - 1
+    elif not kinds:
+        mask = 0
+    else:
+        mask = 0
+        for k in kinds:
+            mask |= 1 << PROF_KINDS[k]
+    _check(_lib.ucp_profile(handle(device), mask))
 
 
 def profile_read(device: int = 0):

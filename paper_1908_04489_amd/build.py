@@ -35,24 +35,26 @@ def flags():
     ]
 
 
-def build(verbose: bool = False) -> str:
-    """Compile every source and link the shared library (always rebuilds)."""
+def build(verbose: bool = False, out: str = LIB, extra=()) -> str:
+    """Compile every source and link the shared library (always rebuilds);
+    ``out`` and ``extra`` (more hipcc flags) serve alternative builds."""
     objs = []
-    os.makedirs(os.path.join(HERE, "_build"), exist_ok=True)
+    bdir = os.path.join(os.path.dirname(os.path.abspath(out)), "_build")
+    os.makedirs(bdir, exist_ok=True)
     for src in SOURCES:
-        obj = os.path.join(HERE, "_build", src + ".o")
-        cmd = [hipcc()] + flags() + ["-c", os.path.join(CSRC, src), "-o", obj]
+        obj = os.path.join(bdir, src + ".o")
+        cmd = [hipcc()] + flags() + list(extra) + ["-c", os.path.join(CSRC, src), "-o", obj]
         if src.endswith(".hip"):
             cmd.insert(1, "-xhip")
         if verbose:
             print(" ".join(cmd), flush=True)
         subprocess.run(cmd, check=True)
         objs.append(obj)
-    tmp = LIB + ".tmp"
+    tmp = out + ".tmp"
     cmd = [hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp] + objs
     subprocess.run(cmd, check=True)
-    os.replace(tmp, LIB)
-    return LIB
+    os.replace(tmp, out)
+    return out
 
 
 if __name__ == "__main__":

@@ -137,6 +137,9 @@ size_t state_bytes(const Inst& I) {
   b += 9 * align_up(nx * 8);                                      // u0 u0_next f logf cbest b32best b64best b32inc jrow
   b += align_up(ny * 8) + align_up(ny * 4);                       // u1 v
   b += align_up((size_t)(2 * I.nw32 + 1) * 4);                     // gtab
+  b += align_up(nx * (size_t)(I.cands + 3) * 8);                   // ev
+  b += align_up(nx * (size_t)(I.cands + 3) * sizeof(EvalItem));    // items
+  b += align_up(nx * 4) + 256;                                     // pend, nitems
   b += align_up(nx * (size_t)(I.cands + 1) * (size_t)I.segs * 8); // part
   b += align_up((size_t)I.u1_slices * ny * 3 * 8);                // u1part
   b += 256 + kCountBytes;                                         // flags, counters
@@ -162,10 +165,24 @@ void carve_state(Inst& I, char*& base) {
   I.u1 = (double*)take(ny * 8);
   I.v = (float*)take(ny * 4);
   I.gtab = (float*)take((size_t)(2 * I.nw32 + 1) * 4);
+  I.ev = (double*)take(nx * (size_t)(I.cands + 3) * 8);
+  I.items = (EvalItem*)take(nx * (size_t)(I.cands + 3) * sizeof(EvalItem));
+  I.pend = (int32_t*)take(nx * 4);
+  I.nitems = (int32_t*)take(256);
   I.part = (double*)take(nx * (size_t)(I.cands + 1) * (size_t)I.segs * 8);
   I.u1part = (double*)take((size_t)I.u1_slices * ny * 3 * 8);
   I.flags = (int32_t*)take(256);
   I.terms = (unsigned long long*)take(kCountBytes);
+}
+
+// Zero what a solve expects zero: flags, work counters, the FP64 queue and
+// the per-point pending marks.
+hipError_t clear_state(const Inst& I, hipStream_t st) {
+  hipError_t e = hipMemsetAsync(I.flags, 0, 256, st);
+  if (e == hipSuccess && I.terms) e = hipMemsetAsync(I.terms, 0, kCountBytes, st);
+  if (e == hipSuccess) e = hipMemsetAsync(I.pend, 0, (size_t)I.n_x * 4, st);
+  if (e == hipSuccess) e = hipMemsetAsync(I.nitems, 0, 4, st);
+  return e;
 }
 
 // Prefix sums of units for each kernel over a batch, for one set of running
@@ -207,7 +224,7 @@ struct ucp_handle {
   void* ws = nullptr;
   size_t ws_bytes = 0;
   // kernel timing with HIP events on the caller's stream (ucp_profile)
-  bool prof = false;
+  int prof = 0;                 // bit k: time launches of kind k
   std::vector<hipEvent_t> ev;   // pool of event pairs
   std::vector<int> ev_kind;     // kind of each recorded pair
   size_t ev_used = 0;           // pairs recorded since the last harvest
@@ -238,9 +255,16 @@ static int ensure_ws(ucp_handle* h, size_t bytes) {
   return UCP_OK;
 }
 
-// Event pair around one launch of `kind` (no-op unless profiling is on).
-static hipError_t prof_begin(ucp_handle* h, int kind, hipStream_t st) {
-  if (!h || !h->prof) return hipSuccess;
+// Event pair for one timed launch (range) of `kind`: both null unless that
+// kind is being timed and the launch will run.  The launchers hand the
+// events to hipExtLaunchKernel, which records them at the start of the first
+// and the end of the last kernel without extra packets in the stream.
+struct EvPair {
+  hipEvent_t a = nullptr, b = nullptr;
+};
+static hipError_t prof_pair(ucp_handle* h, int kind, bool runs, EvPair& p) {
+  p = EvPair();
+  if (!h || !runs || !((h->prof >> kind) & 1)) return hipSuccess;
   if (h->ev_used * 2 + 2 > h->ev.size()) {
     for (int k = 0; k < 64; ++k) {
       hipEvent_t e;
@@ -251,13 +275,10 @@ static hipError_t prof_begin(ucp_handle* h, int kind, hipStream_t st) {
   }
   if (h->ev_kind.size() <= h->ev_used) h->ev_kind.resize(h->ev_used + 1);
   h->ev_kind[h->ev_used] = kind;
-  return hipEventRecord(h->ev[h->ev_used * 2], st);
-}
-static hipError_t prof_end(ucp_handle* h, hipStream_t st) {
-  if (!h || !h->prof) return hipSuccess;
-  hipError_t r = hipEventRecord(h->ev[h->ev_used * 2 + 1], st);
+  p.a = h->ev[h->ev_used * 2];
+  p.b = h->ev[h->ev_used * 2 + 1];
   h->ev_used++;
-  return r;
+  return hipSuccess;
 }
 // Accumulate the recorded pairs (the stream has been synchronised).
 static void prof_harvest(ucp_handle* h) {
@@ -276,7 +297,8 @@ extern "C" {
 
 int ucp_profile(ucp_handle* h, int enable) {
   if (!h) return fail(UCP_EINVAL, "NULL handle");
-  h->prof = enable != 0;
+  if (enable & ~((1 << UCP_PROF_KINDS) - 1)) return fail(UCP_EINVAL, "profile mask has unknown kinds");
+  h->prof = enable;
   h->ev_used = 0;
   for (int k = 0; k < UCP_PROF_KINDS; ++k) {
     h->prof_ms[k] = 0.0;
@@ -386,23 +408,23 @@ int setup_batch(ucp_handle* h, Batch& B, std::vector<Inst> insts, const std::vec
 // levels, the u0 advance, the u1 update and the objective into J[t].
 int run_round(ucp_handle* h, const Batch& B, int phase, const std::vector<int32_t>& tab, int prec, int max_levels,
               int t, hipStream_t st) {
+  EvPair p;
   for (int l = 0; l < max_levels; ++l) {
-    UCP_TRY(prof_begin(h, UCP_PROF_MC, st), "event");
-    UCP_TRY(launch_mc(B.launch(phase, kKindMc0 + l, tab), l, prec, st), "marginal-cost kernel");
-    UCP_TRY(prof_end(h, st), "event");
-    UCP_TRY(prof_begin(h, UCP_PROF_SELECT, st), "event");
-    UCP_TRY(launch_select(B.launch(phase, kKindSel0 + l, tab), l, prec, 0, st), "selection kernel");
-    UCP_TRY(prof_end(h, st), "event");
+    const Launch Lm = B.launch(phase, kKindMc0 + l, tab), Ls = B.launch(phase, kKindSel0 + l, tab);
+    UCP_TRY(prof_pair(h, UCP_PROF_MC, Lm.total > 0, p), "event");
+    UCP_TRY(launch_mc(Lm, l, prec, st, p.a, p.b), "marginal-cost kernel");
+    UCP_TRY(prof_pair(h, UCP_PROF_SELECT, Ls.total > 0, p), "event");
+    UCP_TRY(launch_select(Ls, l, prec, 0, st, p.a, p.b), "selection kernel");
   }
   UCP_TRY(launch_copy_u0(B.launch(phase, kKindCopy, tab), st), "u0 advance kernel");
-  UCP_TRY(prof_begin(h, UCP_PROF_U1, st), "event");
-  UCP_TRY(launch_u1_partial(B.launch(phase, kKindU1p, tab), prec, st), "u1 kernel");
-  UCP_TRY(launch_u1_combine(B.launch(phase, kKindU1c, tab), st), "u1 combine kernel");
-  UCP_TRY(prof_end(h, st), "event");
-  UCP_TRY(prof_begin(h, UCP_PROF_J, st), "event");
-  UCP_TRY(launch_j_rows(B.launch(phase, kKindJRows, tab), st), "objective kernel");
-  UCP_TRY(launch_j_reduce_t(B.launch(phase, kKindJRed, tab), t, st), "objective reduce kernel");
-  UCP_TRY(prof_end(h, st), "event");
+  const Launch Lp = B.launch(phase, kKindU1p, tab), Lc = B.launch(phase, kKindU1c, tab);
+  UCP_TRY(prof_pair(h, UCP_PROF_U1, Lp.total > 0 && Lc.total > 0, p), "event");
+  UCP_TRY(launch_u1_partial(Lp, prec, st, p.a), "u1 kernel");
+  UCP_TRY(launch_u1_combine(Lc, st, p.b), "u1 combine kernel");
+  const Launch Lr = B.launch(phase, kKindJRows, tab), Ld = B.launch(phase, kKindJRed, tab);
+  UCP_TRY(prof_pair(h, UCP_PROF_J, Lr.total > 0 && Ld.total > 0, p), "event");
+  UCP_TRY(launch_j_rows(Lr, st, p.a), "objective kernel");
+  UCP_TRY(launch_j_reduce_t(Ld, t, st, p.b), "objective reduce kernel");
   return UCP_OK;
 }
 
@@ -455,7 +477,7 @@ int ucp_solve_batch(ucp_handle* h, int32_t nb, const ucp_problem* probs, const u
   for (int b = 0; b < nb; ++b) {
     Inst& I = B.insts[b];
     UCP_TRY(hipMemcpyAsync(I.u0, u0_init[b], sizeof(double) * I.n_x, hipMemcpyDeviceToDevice, st), "copy u0_init");
-    UCP_TRY(hipMemsetAsync(I.flags, 0, 256 + kCountBytes, st), "clear flags and counters");
+    UCP_TRY(clear_state(I, st), "clear state");
   }
   // J_out of each instance is its J_hist: set through a second table upload
   for (int b = 0; b < nb; ++b) B.insts[b].J_out = J_hist[b];
@@ -510,7 +532,7 @@ int ucp_argmin_adaptive(ucp_handle* h, const ucp_problem* prob, const ucp_search
   I.terms = nullptr;
   UCP_TRY(hipMemcpyAsync(I.u0, u0_in, sizeof(double) * I.n_x, hipMemcpyDeviceToDevice, st), "copy u0");
   UCP_TRY(hipMemcpyAsync(I.u1, u1, sizeof(double) * I.n_y, hipMemcpyDeviceToDevice, st), "copy u1");
-  UCP_TRY(hipMemsetAsync(I.flags, 0, 128, st), "clear flags");
+  UCP_TRY(clear_state(I, st), "clear state");
   UCP_TRY(hipMemcpyAsync(B.d_insts, B.insts.data(), sizeof(Inst), hipMemcpyHostToDevice, st), "upload instance");
   UCP_TRY(launch_prior(B.launch(0, kKindPrior, tab), st), "prior kernel");
   UCP_TRY(launch_gtab(B.launch(0, kKindGtab, tab), st), "offset table kernel");

@@ -17,7 +17,9 @@ constexpr int kWave = 64;
 constexpr int kMcBlock = 256;   // marginal-cost kernel: one lane per point, 4 waves
 constexpr int kMcLds = 4096;    // FP32 residual nodes staged in LDS per block (16 KiB)
 constexpr int kMcSegMax = 2048; // longest window segment of one marginal-cost work unit
-constexpr int kSelWaves = 4;    // selection kernel: one wave per point
+constexpr int kSelWaves = 16;   // selection kernels: one wave per point ...
+constexpr int kSelPts = 1;      // ... for kSelPts consecutive points in turn
+constexpr int kEvalWaves = 4;   // queue-draining kernel: one wave per queued sum
 constexpr int kU1Block = 256;   // u1 kernels: one lane per y node
 constexpr int kU1Chunk = 512;   // x nodes staged in LDS per step of the u1 sums
 constexpr int kJWaves = 4;      // objective: one wave per x node
@@ -35,6 +37,15 @@ constexpr double kWin64 = 10.0; // window half-width, noise sds (FP64 terms)
 // marginal-cost terms and FP64 tie re-evaluations.
 constexpr int kCountSlots = 32, kCountStride = 16, kCountTerms = 0, kCountEvalTerms = 4, kCountEvals = 8;
 constexpr size_t kCountBytes = (size_t)kCountSlots * kCountStride * 8;
+
+// A queued FP64 window sum: point, result slot, candidate position.
+struct EvalItem {
+  int32_t i;
+  int32_t slot;
+  double c;
+};
+
+constexpr int kEvalBlocks = 2048;  // grid of the queue-draining kernel
 
 // One solve instance as the kernels see it: constants of the problem and the
 // search, launch geometry, and device pointers to its state.
@@ -72,6 +83,10 @@ struct Inst {
   double* part;              // marginal-cost partial sums [n_x][cands + 1][segs]
   double* u1part;            // u1 partial sums [u1_slices][n_y][3]
   double* jrow;              // per-point objective terms [n_x]
+  double* ev;                // FP64 results of queued sums [n_x][cands + 3]
+  EvalItem* items;           // queue of FP64 sums [n_x (cands + 3)]
+  int32_t* nitems;           // queue length
+  int32_t* pend;             // per point: 0 decided, 1 level band queued, 2 incumbent comparison queued
   double* J_out;             // objective output (one double)
   double* L0_out;            // optional FP64 L_0 of the accepted u0 [n_x] (argmin call only)
   int32_t* flags;            // bit 0: non-finite value met
@@ -93,13 +108,17 @@ struct Launch {
 // Kernel launchers (ucp_kernels.hip).  All enqueue on `st`.
 hipError_t launch_prior(const Launch& L, hipStream_t st);
 hipError_t launch_gtab(const Launch& L, hipStream_t st);
-hipError_t launch_mc(const Launch& L, int level, int prec, hipStream_t st);
-hipError_t launch_select(const Launch& L, int level, int prec, int final_l0, hipStream_t st);
+// Launchers that take (e0, e1) record e0 when the first kernel starts and e1
+// when the last one ends (hipExtLaunchKernel: no extra packets in the stream).
+hipError_t launch_mc(const Launch& L, int level, int prec, hipStream_t st, hipEvent_t e0 = nullptr,
+                     hipEvent_t e1 = nullptr);
+hipError_t launch_select(const Launch& L, int level, int prec, int final_l0, hipStream_t st, hipEvent_t e0 = nullptr,
+                         hipEvent_t e1 = nullptr);
 hipError_t launch_finish_free(const Launch& L, double* out, int prec, hipStream_t st);
-hipError_t launch_j_reduce_t(const Launch& L, int t, hipStream_t st);
-hipError_t launch_u1_partial(const Launch& L, int prec, hipStream_t st);
-hipError_t launch_u1_combine(const Launch& L, hipStream_t st);
-hipError_t launch_j_rows(const Launch& L, hipStream_t st);
+hipError_t launch_j_reduce_t(const Launch& L, int t, hipStream_t st, hipEvent_t e1 = nullptr);
+hipError_t launch_u1_partial(const Launch& L, int prec, hipStream_t st, hipEvent_t e0 = nullptr);
+hipError_t launch_u1_combine(const Launch& L, hipStream_t st, hipEvent_t e1 = nullptr);
+hipError_t launch_j_rows(const Launch& L, hipStream_t st, hipEvent_t e0 = nullptr);
 hipError_t launch_j_reduce(const Launch& L, hipStream_t st);
 hipError_t launch_copy_u0(const Launch& L, hipStream_t st);
 

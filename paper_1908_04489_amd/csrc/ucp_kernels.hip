@@ -14,13 +14,15 @@
 //   k_mc32<P>      marginal-cost window sums for one level of the search,
 //                  FP32 terms, plain (P=0) or compensated (P=1) sums
 //   k_mc64         the same in FP64 (precision-study mode)
-//   k_select<P>    per point: level minimum, FP32 tie band, FP64
-//                  re-evaluation of the band, selection rule, next bracket,
-//                  and after the last level the comparison with the
-//                  incumbent
+//   k_band<P>, k_eval, k_resolve<P>
+//                  per point: level minimum, FP32 tie band, FP64
+//                  re-evaluation of the band members (queued and drained at
+//                  full occupancy), selection rule, next bracket, and after
+//                  the last level the comparison with the incumbent
 //   k_u1_partial<P>/k_u1_combine   closed-form second controller
 //   k_j_rows/k_j_reduce            objective in FP64, fixed-order reduction
 #include <hip/hip_runtime.h>
+#include <hip/hip_ext.h>
 
 #include <climits>
 #include <cmath>
@@ -93,33 +95,36 @@ __device__ __forceinline__ int nearest_node(const Inst& I, double z) {
 // r_k = exp(-64 dy t_k - (64 dy)^2 / 2) and q = exp(-(64 dy)^2), so two
 // multiplies replace an exp; both are recomputed by exp every kReseed steps,
 // which bounds the relative error of any weight by ~kReseed^2/2 ulp
-// (5.7e-14).  Loads are issued kPrefetch at a time; two accumulators split
-// the dependency chain of the sum.
+// (5.7e-14).  Every lane has a node in the first floor(n/64) steps, which
+// run without masks, kPrefetch loads issued ahead of their use; only the
+// last step can be partial.  Two accumulators split the dependency chain.
 constexpr int kReseed = 32;
-constexpr int kPrefetch = 16;
+constexpr int kPrefetch = 8;
+typedef const __attribute__((address_space(1))) double* glb_dptr;
 
 __device__ double b64_wave(const Inst& I, double z, int lane) {
   const int jr = nearest_node(I, z);
   const double delta = (I.y_lo + (double)jr * I.dy) - z;
+  // 0 <= jr <= n_y - 1, so klo <= 0 <= khi and the window is never empty
   const int klo = max(-I.nw64, -jr), khi = min(I.nw64, I.n_y - 1 - jr);
+  const int n = khi - klo + 1;
   const double dy = I.dy, D = (double)kWave * dy;
   const double q = exp(-D * D);
-  const double* __restrict__ u1 = I.u1 + jr;
+  glb_dptr u1 = (glb_dptr)(I.u1 + jr + klo + lane);  // this lane's node of step m: u1[64 m]
   double s0 = 0.0, s1 = 0.0;
-  // this lane's nodes: k = klo + lane + 64 m for m = 0 .. steps - 1
-  const int steps = (khi - klo + kWave) / kWave;
+  const int steps = (n + kWave - 1) / kWave;
+  const int full = n / kWave;
   for (int m0 = 0; m0 < steps; m0 += kReseed) {
-    const int kb = klo + lane + kWave * m0;
-    const double d = (double)kb * dy;
+    const double d = (double)(klo + lane + kWave * m0) * dy;
     double g = exp(-0.5 * d * (d + 2.0 * delta));
     double r = exp(-D * (d + delta) - 0.5 * D * D);
-    for (int p0 = 0; p0 < kReseed && m0 + p0 < steps; p0 += kPrefetch) {
+    const int mend = min(m0 + kReseed, steps);
+    const int mu = min(mend, full);
+    int m = m0;
+    for (; m + kPrefetch <= mu; m += kPrefetch) {
       double uv[kPrefetch];
 #pragma unroll
-      for (int mm = 0; mm < kPrefetch; ++mm) {  // loads first, so they overlap
-        const int k = kb + kWave * (p0 + mm);
-        uv[mm] = k <= khi ? u1[k] : z;  // past the window: e = 0, no term
-      }
+      for (int mm = 0; mm < kPrefetch; ++mm) uv[mm] = u1[kWave * (m + mm)];
 #pragma unroll
       for (int mm = 0; mm < kPrefetch; mm += 2) {
         const double e0 = z - uv[mm];
@@ -131,6 +136,14 @@ __device__ double b64_wave(const Inst& I, double z, int lane) {
         g *= r;
         r *= q;
       }
+    }
+    for (; m < mend; ++m) {  // fewer than kPrefetch steps, the last one possibly partial
+      double e = 0.0;
+      if (lane + kWave * m < n) e = z - u1[kWave * m];
+      if (m & 1) s1 = fma(g * e, e, s1);  // the same accumulator as in the blocks above
+      else s0 = fma(g * e, e, s0);
+      g *= r;
+      r *= q;
     }
   }
   const double s = wave_sum_d(s0 + s1);
@@ -217,15 +230,14 @@ hipError_t launch_gtab(const Launch& L, hipStream_t st) {
 //   exp(-(t_k^2 - delta^2)/2) = G_k * E_k,
 //   G_k = exp2(-(k alpha dy)^2)          (the same for every lane: a table),
 //   E_k = exp2(beta k), beta = -2 alpha^2 dy delta (one constant per lane).
-// Every lane of a wave is at the same window offset k, so G_k is one LDS
-// broadcast; E_k costs one v_exp_f32 per block of 8 offsets times the
+// Every lane of a wave is at the same window offset k, so G_k is one scalar
+// load; E_k costs one v_exp_f32 per block of 8 offsets times the
 // per-lane constants exp2(beta m), m < 8.  The residual z - u1 = v - T with
 // T = alpha t (v = alpha (y - u1), formed in FP64 by the u1 kernel).  After
 // the shift every weight is <= 1, so FP32 neither overflows nor underflows
-// where terms matter.  The block stages the residual nodes it touches and
-// the G values of its offsets in LDS (falls back to global loads for the
-// residual when its node range exceeds kMcLds, e.g. across a jump of the
-// controller).
+// where terms matter.  The block stages the residual nodes it touches in LDS
+// (falls back to global loads when its node range exceeds kMcLds, e.g.
+// across a jump of the controller).
 
 int32_t units_mc(const Inst& I, int level) {
   if (level >= 0 && level >= I.levels) return 0;
@@ -236,6 +248,7 @@ int32_t units_mc(const Inst& I, int level) {
 
 typedef const __attribute__((address_space(3))) float* lds_cptr;
 typedef const __attribute__((address_space(1))) float* glb_cptr;
+typedef const __attribute__((address_space(4))) float* cst_cptr;  // read through the scalar cache
 
 __device__ __forceinline__ void kahan_add(float x, float& acc, float& comp) {
   const float y = x - comp;
@@ -257,42 +270,88 @@ struct McLane {
 
 // Offsets k in [k0, k1] (wave-uniform bounds, every lane in range): blocks of
 // 8 terms summed plainly in two chains, each block sum added with
-// compensation (KAHAN) or plainly.
-template <bool KAHAN, typename P>
-__device__ __forceinline__ void mc_bulk(P v, lds_cptr G, int k0, int k1, const McLane& c, float& acc,
-                                        float& comp) {
-  int k = k0;
-  for (; k + kMcUnroll - 1 <= k1; k += kMcUnroll) {
-    const float kf = (float)k;
-    // E_{k+m} = E_k R_m: the common factor E_k multiplies the block sum
-    const float E0 = __builtin_amdgcn_exp2f(c.beta * kf);
-    float b0 = 0.0f, b1 = 0.0f;
+// compensation (KAHAN) or plainly.  Two register buffers alternate: the
+// residuals (LDS) and table values (scalar loads) of block b + 1 are
+// requested once block b's have been consumed into its first partial
+// products, so their latency overlaps the rest of block b.  (LDS and scalar
+// loads share one wait counter: loads issued any earlier would be waited
+// for together with block b's.)
+struct McBlk {
+  float g[kMcUnroll];  // table values G_{k+m}
+  float v[kMcUnroll];  // residuals v_{jr+k+m}
+};
+
+template <typename P, typename Q>
+__device__ __forceinline__ void mc_load(McBlk& B, P v, Q G, int k) {
 #pragma unroll
-    for (int m = 0; m < kMcUnroll; m += 2) {
-      const float T0 = fmaf(kf, c.aDy, c.Dm[m]);
-      const float g0 = G[k + m] * c.R[m];
-      const float e0 = v[k + m] - T0;
-      const float T1 = fmaf(kf, c.aDy, c.Dm[m + 1]);
-      const float g1 = G[k + m + 1] * c.R[m + 1];
-      const float e1 = v[k + m + 1] - T1;
-      b0 = fmaf(g0 * e0, e0, b0);
-      b1 = fmaf(g1 * e1, e1, b1);
-    }
-    if (KAHAN) kahan_add(E0 * (b0 + b1), acc, comp);
-    else acc = fmaf(E0, b0 + b1, acc);
+  for (int m = 0; m < kMcUnroll; ++m) {
+    B.g[m] = G[k + m];
+    B.v[m] = v[k + m];
+  }
+}
+
+// First half of a block: e_m = v - T_m and g_m R_m (consumes the loads).
+__device__ __forceinline__ void mc_first(const McBlk& B, float kf, const McLane& c, float* e, float* gr) {
+#pragma unroll
+  for (int m = 0; m < kMcUnroll; ++m) {
+    e[m] = B.v[m] - fmaf(kf, c.aDy, c.Dm[m]);
+    gr[m] = B.g[m] * c.R[m];
+  }
+}
+
+// Second half: the block sum times E_k = exp2(beta k) (E_{k+m} = E_k R_m).
+template <bool KAHAN>
+__device__ __forceinline__ void mc_second(const float* e, const float* gr, float kf, const McLane& c, float& acc,
+                                          float& comp) {
+  const float E0 = __builtin_amdgcn_exp2f(c.beta * kf);
+  float b0 = 0.0f, b1 = 0.0f;
+#pragma unroll
+  for (int m = 0; m < kMcUnroll; m += 2) {
+    b0 = fmaf(gr[m] * e[m], e[m], b0);
+    b1 = fmaf(gr[m + 1] * e[m + 1], e[m + 1], b1);
+  }
+  if (KAHAN) kahan_add(E0 * (b0 + b1), acc, comp);
+  else acc = fmaf(E0, b0 + b1, acc);
+}
+
+template <bool KAHAN, typename P, typename Q>
+__device__ __forceinline__ void mc_bulk(P v, Q G, int k0, int k1, const McLane& c, float& acc,
+                                        float& comp) {
+  constexpr int U = kMcUnroll;
+  int k = k0;
+  McBlk A, B;
+  float e[U], gr[U];
+  if (k + U - 1 <= k1) mc_load(A, v, G, k);
+  for (; k + 2 * U - 1 <= k1; k += 2 * U) {
+    mc_first(A, (float)k, c, e, gr);
+    __builtin_amdgcn_sched_barrier(0);
+    mc_load(B, v, G, k + U);
+    __builtin_amdgcn_sched_barrier(0);
+    mc_second<KAHAN>(e, gr, (float)k, c, acc, comp);
+    mc_first(B, (float)(k + U), c, e, gr);
+    __builtin_amdgcn_sched_barrier(0);
+    // the next block, or (past the end, unused) the last full block: always in range
+    mc_load(A, v, G, min(k + 2 * U, k1 - U + 1));
+    __builtin_amdgcn_sched_barrier(0);
+    mc_second<KAHAN>(e, gr, (float)(k + U), c, acc, comp);
+  }
+  if (k + U - 1 <= k1) {  // one block left, already loaded into A
+    mc_first(A, (float)k, c, e, gr);
+    mc_second<KAHAN>(e, gr, (float)k, c, acc, comp);
+    k += U;
   }
   for (; k <= k1; ++k) {
     const float kf = (float)k;
     const float g = G[k] * __builtin_amdgcn_exp2f(c.beta * kf);
-    const float e = v[k] - fmaf(kf, c.aDy, c.Dl);
-    if (KAHAN) kahan_add((g * e) * e, acc, comp);
-    else acc = fmaf(g * e, e, acc);
+    const float e1 = v[k] - fmaf(kf, c.aDy, c.Dl);
+    if (KAHAN) kahan_add((g * e1) * e1, acc, comp);
+    else acc = fmaf(g * e1, e1, acc);
   }
 }
 
 // Offsets k in [k0, k1] restricted to the lane's own range [klo, khi].
-template <bool KAHAN, typename P>
-__device__ __forceinline__ void mc_masked(P v, lds_cptr G, int k0, int k1, int klo, int khi, const McLane& c,
+template <bool KAHAN, typename P, typename Q>
+__device__ __forceinline__ void mc_masked(P v, Q G, int k0, int k1, int klo, int khi, const McLane& c,
                                           float& acc, float& comp) {
   for (int k = k0; k <= k1; ++k) {
     if (k >= klo && k <= khi) {
@@ -307,8 +366,8 @@ __device__ __forceinline__ void mc_masked(P v, lds_cptr G, int k0, int k1, int k
 
 // The lane's window [klo, khi] (empty when klo > khi): the range common to
 // every non-empty lane of the wave runs unmasked, the ragged ends masked.
-template <bool KAHAN, typename P>
-__device__ __forceinline__ void mc_lane(P v, lds_cptr G, int klo, int khi, const McLane& c, float& acc,
+template <bool KAHAN, typename P, typename Q>
+__device__ __forceinline__ void mc_lane(P v, Q G, int klo, int khi, const McLane& c, float& acc,
                                         float& comp) {
   const bool empty = klo > khi;
   const int kc_lo = __builtin_amdgcn_readfirstlane(wave_max_i(empty ? INT_MIN : klo));
@@ -329,7 +388,6 @@ template <int PREC>
 __global__ __launch_bounds__(kMcBlock) void k_mc32(Launch L, int level) {
   constexpr bool KAHAN = PREC == UCP_FP32_KAHAN;
   __shared__ float sv[kMcLds];
-  __shared__ float sg[kMcSegMax];
   __shared__ int sred[4][kMcBlock / kWave];
   const int u = blockIdx.x;
   const int b = find_inst(L.pre, L.n_inst, u);
@@ -390,9 +448,6 @@ __global__ __launch_bounds__(kMcBlock) void k_mc32(Launch L, int level) {
   const bool staged = bhi >= blo && bhi - blo + 1 <= kMcLds;
   if (staged)
     for (int j = blo + (int)threadIdx.x; j <= bhi; j += kMcBlock) sv[j - blo] = I.v[j];
-  // offsets lie inside the segment, so at most kMcSegMax of them
-  if (bkhi >= bklo)
-    for (int k = bklo + (int)threadIdx.x; k <= bkhi; k += kMcBlock) sg[k - bklo] = I.gtab[k + nw];
   __syncthreads();
 
   McLane cl;
@@ -408,7 +463,8 @@ __global__ __launch_bounds__(kMcBlock) void k_mc32(Launch L, int level) {
   }
 
   float acc = 0.0f, comp = 0.0f;
-  lds_cptr G = (lds_cptr)(sg - (bkhi >= bklo ? bklo : 0));
+  // the offset table is read at wave-uniform offsets: scalar loads
+  cst_cptr G = (cst_cptr)(I.gtab + nw);
   if (staged) {
     lds_cptr v = (lds_cptr)(sv + (jr - blo));
     mc_lane<KAHAN>(v, G, klo, khi, cl, acc, comp);
@@ -468,14 +524,14 @@ __global__ __launch_bounds__(kMcBlock) void k_mc64(Launch L, int level) {
   I.part[(size_t)i * pstride + q] = s0 + s1;
 }
 
-hipError_t launch_mc(const Launch& L, int level, int prec, hipStream_t st) {
+hipError_t launch_mc(const Launch& L, int level, int prec, hipStream_t st, hipEvent_t e0, hipEvent_t e1) {
   if (L.total == 0) return hipSuccess;
   if (prec == UCP_FP64)
-    hipLaunchKernelGGL(k_mc64, dim3(L.total), dim3(kMcBlock), 0, st, L, level);
+    hipExtLaunchKernelGGL(k_mc64, dim3(L.total), dim3(kMcBlock), 0, st, e0, e1, 0, L, level);
   else if (prec == UCP_FP32_KAHAN)
-    hipLaunchKernelGGL(k_mc32<UCP_FP32_KAHAN>, dim3(L.total), dim3(kMcBlock), 0, st, L, level);
+    hipExtLaunchKernelGGL(k_mc32<UCP_FP32_KAHAN>, dim3(L.total), dim3(kMcBlock), 0, st, e0, e1, 0, L, level);
   else
-    hipLaunchKernelGGL(k_mc32<UCP_FP32>, dim3(L.total), dim3(kMcBlock), 0, st, L, level);
+    hipExtLaunchKernelGGL(k_mc32<UCP_FP32>, dim3(L.total), dim3(kMcBlock), 0, st, e0, e1, 0, L, level);
   return hipGetLastError();
 }
 
@@ -508,133 +564,101 @@ __global__ __launch_bounds__(256) void k_mc_finish(Launch L, double* out, int pr
 
 // ------------------------------------------------------------- selection
 //
-// One wave per point.  Lane q holds candidate q of the level (lane `cands`
-// holds the best so far from the previous level, or at level 0 the
-// incumbent, whose FP32-path B is kept for the final comparison).
+// Three kernels per level:
+//   k_band     one wave per point.  Lane q holds candidate q of the level
+//              (lane `cands` the best so far, or at level 0 the incumbent,
+//              whose FP32-path B is kept for the final comparison).  FP32
+//              minimum and tie band; a one-member band (and FP64 mode)
+//              decides at once, otherwise the members without an FP64 value
+//              are queued.  On the last level a decided point runs the
+//              comparison with the incumbent the same way.
+//   k_eval     drains the queues: one FP64 window sum per wave, a fixed grid
+//              at full occupancy whatever the number of items.
+//   k_resolve  the queued points: the selection rule on the FP64 values, and
+//              on the last level the comparison with the incumbent.
 
-int32_t units_select(const Inst& I) { return (I.n_x + kSelWaves - 1) / kSelWaves; }
+int32_t units_select(const Inst& I) { return (I.n_x + kSelWaves * kSelPts - 1) / (kSelWaves * kSelPts); }
 
-struct Pick {
-  int lane;
-  double B64;  // FP64 B of the pick (NaN if not evaluated)
-};
+// Slots of the per-point FP64 results: 0..cands-1 level candidates, `cands`
+// the best so far, then the two members of the incumbent comparison.
+__device__ __forceinline__ int slot_best(const Inst& I) { return I.cands + 1; }
+__device__ __forceinline__ int slot_inc(const Inst& I) { return I.cands + 2; }
+__device__ __forceinline__ double* ev_row(const Inst& I, int i) { return I.ev + (size_t)i * (I.cands + 3); }
 
-// Selection rule over the lanes with in_set: in FP64 modes the band is
-// B <= m (1 + tau64); in FP32 modes a band B32 <= m32 (1 + tau32) is formed
-// first and its members are re-evaluated in FP64.  Among the FP64 band the
-// member nearest the incumbent wins, then the smaller u, then the lower lane.
-__device__ Pick select_rule(const Inst& I, bool in_set, double c, double B32, double B64, double x,
-                            double uinc, int lane, int prec, int32_t* bad, int& n_eval) {
+// The selection rule on FP64 values among the lanes with `member`: ties
+// within kTau64 of the minimum, the one nearest the incumbent wins, then the
+// smaller u, then the lower lane.  Returns the lane (0 if there is none).
+__device__ int tie_rule(bool member, double c, double Bf, double uinc, int lane) {
   const double big = INFINITY;
-  const bool fin = in_set && isfinite(B32);
-  const double m32 = wave_min_d(fin ? B32 : big);
-  Pick r{0, NAN};
-  if (!(m32 < big)) {  // no finite candidate: flag and keep lane 0
-    if (lane == 0) atomicOr(bad, 1);
-    r.lane = 0;
-    r.B64 = __shfl(B64, 0);
-    return r;
-  }
-  double Bf;  // FP64 value used by the rule
-  bool band;
-  if (prec == UCP_FP64) {
-    Bf = B32;
-    band = fin && B32 <= m32 * (1.0 + kTau64);
-  } else {
-    // FP32 band: relative part for the weights and the sum, absolute part
-    // kKappa32 sqrt(m) for the rounding of z - u1 (|dB| grows like sqrt(B))
-    const double tau = prec == UCP_FP32_KAHAN ? kTau32Kahan : kTau32Plain;
-    const bool b32 = fin && B32 <= m32 * (1.0 + tau) + kKappa32 * sqrt(m32);
-    const unsigned long long mask = __ballot(b32);
-    if (__popcll(mask) == 1) {
-      r.lane = __ffsll((long long)mask) - 1;
-      r.B64 = __shfl(B64, r.lane);
-      return r;
-    }
-    unsigned long long todo = __ballot(b32 && isnan(B64));
-    while (todo) {
-      const int L = __ffsll((long long)todo) - 1;
-      todo &= todo - 1;
-      const double cl = __shfl(c, L);
-      const double v = I.k2 * cl * cl + b64_wave(I, x + cl, lane);
-      if (lane == L) B64 = v;
-      ++n_eval;
-    }
-    Bf = B64;
-    const double m64 = wave_min_d(b32 ? B64 : big);
-    band = b32 && B64 <= m64 * (1.0 + kTau64);
-  }
-  // lexicographic (|c - uinc|, c, lane) minimum over the band
+  const double m = wave_min_d(member ? Bf : big);
+  const bool band = member && Bf <= m * (1.0 + kTau64);
   double k1 = band ? fabs(c - uinc) : big;
   double k2 = band ? c : big;
   int k3 = band ? lane : INT_MAX;
   for (int o = kWave / 2; o > 0; o >>= 1) {
-    double o1 = __shfl_xor(k1, o), o2 = __shfl_xor(k2, o);
-    int o3 = __shfl_xor(k3, o);
-    bool take = (o1 < k1) || (o1 == k1 && (o2 < k2 || (o2 == k2 && o3 < k3)));
+    const double o1 = __shfl_xor(k1, o), o2 = __shfl_xor(k2, o);
+    const int o3 = __shfl_xor(k3, o);
+    const bool take = (o1 < k1) || (o1 == k1 && (o2 < k2 || (o2 == k2 && o3 < k3)));
     if (take) { k1 = o1; k2 = o2; k3 = o3; }
   }
-  r.lane = k3 == INT_MAX ? 0 : k3;
-  r.B64 = __shfl(prec == UCP_FP64 ? Bf : B64, r.lane);
-  return r;
+  return k3 == INT_MAX ? 0 : k3;
 }
 
-template <int PREC>
-__global__ __launch_bounds__(kSelWaves * kWave) void k_select(Launch L, int level, int want_l0) {
-  const int u = blockIdx.x;
-  const int b = find_inst(L.pre, L.n_inst, u);
-  const Inst& I = L.insts[b];
-  const int wid = threadIdx.x / kWave, lane = threadIdx.x % kWave;
-  const int i = (u - L.pre[b]) * kSelWaves + wid;
-  if (i >= I.n_x) return;  // whole wave leaves; no block barrier below
-  const int K = I.cands;
-  const int S = I.segs;
-  const double uinc = I.u0[i];
-  const double x = I.x_lo + (double)i * I.dx;
-  const int kq = level == 0 ? K + 1 : K;
+// FP32 tie band over the lanes with `in_set`: B32 <= m (1 + tau) + kappa
+// sqrt(m), tau covering the relative error of the weights and the sum and
+// kappa sqrt(m) the rounding of z - u1 (|dB| grows like sqrt(B)).  Returns
+// the member mask (0 when no candidate is finite).
+__device__ unsigned long long band32(bool in_set, double B32, int prec) {
+  const bool fin = in_set && isfinite(B32);
+  const double m32 = wave_min_d(fin ? B32 : INFINITY);
+  if (!(m32 < INFINITY)) return 0ull;
+  const double tau = prec == UCP_FP32_KAHAN ? kTau32Kahan : kTau32Plain;
+  return __ballot(fin && B32 <= m32 * (1.0 + tau) + kKappa32 * sqrt(m32));
+}
 
-  double c = 0.0, B32 = INFINITY, B64 = NAN;
+// This lane's candidate of the level: position, FP32-path B and (FP64 mode,
+// or the carried best) its FP64 B.
+template <int PREC>
+__device__ void level_view(const Inst& I, int level, int i, int lane, double& c, double& B32, double& B64,
+                           bool& in_set) {
+  const int K = I.cands;
+  const int kq = level == 0 ? K + 1 : K;
+  c = 0.0;
+  B32 = INFINITY;
+  B64 = NAN;
   if (lane < kq) {
     c = cand_pos(I, level, lane, i);
-    B32 = b_from_parts(I, i, lane, K + 1, S, c, PREC);
+    B32 = b_from_parts(I, i, lane, K + 1, I.segs, c, PREC);
     if (PREC == UCP_FP64) B64 = B32;
   }
-  if (level == 0 && lane == K) I.b32inc[i] = B32;
   if (level > 0 && lane == K) {
     c = I.cbest[i];
     B32 = I.b32best[i];
     B64 = I.b64best[i];
   }
-  const bool in_set = level == 0 ? lane < K : lane <= K;
-  int n_eval = 0;
-  Pick p = select_rule(I, in_set, c, B32, B64, x, uinc, lane, PREC, I.flags, n_eval);
-  const double cw = __shfl(c, p.lane);
-  const double B32w = __shfl(B32, p.lane);
-  double B64w = p.B64;
-  if (lane == 0) {
-    I.cbest[i] = cw;
-    I.b32best[i] = B32w;
-    I.b64best[i] = B64w;
-  }
-  if (level != I.levels - 1) {
-    if (lane == 0 && n_eval && I.terms) atomicAdd(I.terms + kCountEvals + (blockIdx.x & (kCountSlots - 1)) * kCountStride, (unsigned long long)n_eval);
-    return;
-  }
+  in_set = level == 0 ? lane < K : lane <= K;
+}
 
-  // acceptance against the incumbent
-  double res = cw, Bres = B64w;
-  if (!(cw == uinc)) {
-    const double B32i = I.b32inc[i];
-    const bool in2 = lane < 2;
-    const double c2 = lane == 0 ? cw : uinc;
-    const double b32_2 = lane == 0 ? B32w : B32i;
-    const double b64_2 = lane == 0 ? B64w : (PREC == UCP_FP64 ? B32i : NAN);
-    Pick q = select_rule(I, in2, c2, b32_2, b64_2, x, uinc, lane, PREC, I.flags, n_eval);
-    res = __shfl(c2, q.lane);
-    Bres = q.B64;
-  }
+__device__ __forceinline__ void count_evals(const Inst& I, int n) {
+  if (n && I.terms)
+    atomicAdd(I.terms + kCountEvals + (blockIdx.x & (kCountSlots - 1)) * kCountStride, (unsigned long long)n);
+}
+
+// Points whose decision needs FP64 window sums are queued: kind 1 = the
+// level's band members (slot = lane), kind 2 = the comparison of the
+// level's winner (slot cands + 1) with the incumbent (slot cands + 2).
+struct Queued {
+  unsigned long long todo;  // lanes whose sum is needed
+  int kind;                 // 0: nothing queued
+  double c;                 // this lane's position
+};
+
+__device__ __forceinline__ int queued_slot(const Inst& I, int kind, int lane) {
+  return kind == 1 ? lane : (lane == 0 ? slot_best(I) : slot_inc(I));
+}
+
+__device__ void finish_point(const Inst& I, int i, double res, double Bres, double x, int lane, int want_l0) {
   if (want_l0 && isnan(Bres)) Bres = I.k2 * res * res + b64_wave(I, x + res, lane);
-  if (lane == 0 && n_eval && I.terms) atomicAdd(I.terms + kCountEvals + (blockIdx.x & (kCountSlots - 1)) * kCountStride, (unsigned long long)n_eval);
   if (lane == 0) {
     I.u0_next[i] = res;
     if (!isfinite(res)) atomicOr(I.flags, 1);
@@ -642,15 +666,244 @@ __global__ __launch_bounds__(kSelWaves * kWave) void k_select(Launch L, int leve
   }
 }
 
-hipError_t launch_select(const Launch& L, int level, int prec, int want_l0, hipStream_t st) {
+// Comparison of the level's winner (cw, B32w, B64w) with the incumbent.  In
+// k_band (inline_eval = false) a two-member band is queued (returned in Q);
+// in k_resolve the missing FP64 sums are evaluated in place.
+template <int PREC>
+__device__ void accept(const Inst& I, int i, double x, double uinc, double cw, double B32w, double B64w, int lane,
+                       bool inline_eval, int want_l0, int& n_eval, Queued& Q) {
+  if (cw == uinc) {
+    finish_point(I, i, uinc, B64w, x, lane, want_l0);
+    return;
+  }
+  const double B32i = I.b32inc[i];
+  const bool in2 = lane < 2;
+  const double c2 = lane == 0 ? cw : uinc;
+  const double b32 = lane == 0 ? B32w : B32i;
+  double b64 = lane == 0 ? B64w : (PREC == UCP_FP64 ? B32i : NAN);
+  if (PREC == UCP_FP64) {
+    const bool fin = in2 && isfinite(b32);
+    const int w = tie_rule(fin, c2, b32, uinc, lane);
+    if (__ballot(fin) == 0ull && lane == 0) atomicOr(I.flags, 1);
+    finish_point(I, i, __shfl(c2, w), __shfl(b64, w), x, lane, want_l0);
+    return;
+  }
+  const unsigned long long mask = band32(in2, b32, PREC);
+  if (mask == 0ull) {
+    if (lane == 0) atomicOr(I.flags, 1);
+    finish_point(I, i, uinc, NAN, x, lane, want_l0);
+    return;
+  }
+  if (__popcll(mask) == 1) {
+    const int w = __ffsll((long long)mask) - 1;
+    finish_point(I, i, __shfl(c2, w), __shfl(b64, w), x, lane, want_l0);
+    return;
+  }
+  const unsigned long long todo = __ballot(in2 && isnan(b64));
+  if (!inline_eval && todo) {
+    Q.todo = todo;
+    Q.kind = 2;
+    Q.c = c2;
+    return;
+  }
+  for (unsigned long long t = todo; t; t &= t - 1) {
+    const int L = __ffsll((long long)t) - 1;
+    const double cl = __shfl(c2, L);
+    const double v = I.k2 * cl * cl + b64_wave(I, x + cl, lane);
+    if (lane == L) b64 = v;
+    ++n_eval;
+  }
+  const int w = tie_rule(in2, c2, b64, uinc, lane);
+  finish_point(I, i, __shfl(c2, w), __shfl(b64, w), x, lane, want_l0);
+}
+
+// One point of k_band: decide it, or return in Q the FP64 sums it needs.
+template <int PREC>
+__device__ void band_point(const Inst& I, int level, int i, int lane, int want_l0, int& n_eval, Queued& Q) {
+  Q.todo = 0ull;
+  Q.kind = 0;
+  Q.c = 0.0;
+  const int K = I.cands;
+  const double uinc = I.u0[i];
+  const double x = I.x_lo + (double)i * I.dx;
+  double c, B32, B64;
+  bool in_set;
+  level_view<PREC>(I, level, i, lane, c, B32, B64, in_set);
+  if (level == 0 && lane == K) I.b32inc[i] = B32;
+  int w;
+  if (PREC == UCP_FP64) {
+    const bool fin = in_set && isfinite(B32);
+    if (__ballot(fin) == 0ull && lane == 0) atomicOr(I.flags, 1);
+    w = tie_rule(fin, c, B32, uinc, lane);
+  } else {
+    const unsigned long long mask = band32(in_set, B32, PREC);
+    if (mask == 0ull) {
+      if (lane == 0) atomicOr(I.flags, 1);
+      w = 0;
+    } else if (__popcll(mask) == 1) {
+      w = __ffsll((long long)mask) - 1;
+    } else {
+      const unsigned long long todo = __ballot(((mask >> lane) & 1ull) && isnan(B64));
+      if (todo) {  // FP64 sums needed: k_resolve decides
+        Q.todo = todo;
+        Q.kind = 1;
+        Q.c = c;
+        return;
+      }
+      w = tie_rule((mask >> lane) & 1ull, c, B64, uinc, lane);
+    }
+  }
+  const double cw = __shfl(c, w), B32w = __shfl(B32, w), B64w = __shfl(B64, w);
+  if (lane == 0) {
+    I.cbest[i] = cw;
+    I.b32best[i] = B32w;
+    I.b64best[i] = B64w;
+  }
+  if (level == I.levels - 1) accept<PREC>(I, i, x, uinc, cw, B32w, B64w, lane, false, want_l0, n_eval, Q);
+}
+
+// Each wave takes kSelPts consecutive points; the block reserves queue
+// space for all of them with one atomic.
+template <int PREC>
+__global__ __launch_bounds__(kSelWaves * kWave) void k_band(Launch L, int level, int want_l0) {
+  __shared__ int s_cnt[kSelWaves];
+  __shared__ int s_base;
+  const int u = blockIdx.x;
+  const int b = find_inst(L.pre, L.n_inst, u);
+  const Inst& I = L.insts[b];
+  const int wid = threadIdx.x / kWave, lane = threadIdx.x % kWave;
+  const int i0 = ((u - L.pre[b]) * kSelWaves + wid) * kSelPts;
+  Queued Q[kSelPts];
+  int n_eval = 0, cnt = 0;
+#pragma unroll
+  for (int p = 0; p < kSelPts; ++p) {
+    Q[p].todo = 0ull;
+    Q[p].kind = 0;
+    Q[p].c = 0.0;
+    if (i0 + p < I.n_x) band_point<PREC>(I, level, i0 + p, lane, want_l0, n_eval, Q[p]);
+    cnt += __popcll(Q[p].todo);
+  }
+  if (lane == 0) s_cnt[wid] = cnt;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int tot = 0;
+    for (int w = 0; w < kSelWaves; ++w) tot += s_cnt[w];
+    s_base = tot ? atomicAdd(I.nitems, tot) : 0;
+  }
+  __syncthreads();
+  if (cnt) {
+    int base = s_base;
+    for (int w = 0; w < wid; ++w) base += s_cnt[w];
+#pragma unroll
+    for (int p = 0; p < kSelPts; ++p) {
+      const unsigned long long todo = Q[p].todo;
+      if (!todo) continue;
+      if ((todo >> lane) & 1ull) {
+        EvalItem it;
+        it.i = i0 + p;
+        it.slot = queued_slot(I, Q[p].kind, lane);
+        it.c = Q[p].c;
+        I.items[base + __popcll(todo & ((1ull << lane) - 1ull))] = it;
+      }
+      if (lane == 0) I.pend[i0 + p] = Q[p].kind;
+      base += __popcll(todo);
+    }
+  }
+  if (lane == 0) count_evals(I, n_eval);
+}
+
+// One FP64 window sum per wave over the queued items of every instance.
+__global__ __launch_bounds__(kEvalWaves * kWave) void k_eval(Launch L) {
+  const int wid = threadIdx.x / kWave, lane = threadIdx.x % kWave;
+  const int gw = blockIdx.x * kEvalWaves + wid, nw = gridDim.x * kEvalWaves;
+  for (int b = 0; b < L.n_inst; ++b) {
+    if (L.pre[b + 1] == L.pre[b]) continue;  // instance not running
+    const Inst& I = L.insts[b];
+    const int n = *I.nitems;
+    int done = 0;
+    for (int it = gw; it < n; it += nw) {
+      const EvalItem e = I.items[it];
+      const double x = I.x_lo + (double)e.i * I.dx;
+      const double v = I.k2 * e.c * e.c + b64_wave(I, x + e.c, lane);
+      if (lane == 0) ev_row(I, e.i)[e.slot] = v;
+      ++done;
+    }
+    if (lane == 0) count_evals(I, done);
+  }
+}
+
+template <int PREC>
+__device__ void resolve_point(const Inst& I, int level, int i, int lane, int want_l0, int& n_eval) {
+  const int pend = I.pend[i];
+  if (pend == 0) return;
+  const double uinc = I.u0[i];
+  const double x = I.x_lo + (double)i * I.dx;
+  const double* evr = ev_row(I, i);
+  if (pend == 1) {
+    double c, B32, B64;
+    bool in_set;
+    level_view<PREC>(I, level, i, lane, c, B32, B64, in_set);
+    const unsigned long long mask = band32(in_set, B32, PREC);
+    const bool member = (mask >> lane) & 1ull;
+    if (member && isnan(B64)) B64 = evr[lane];
+    const int w = tie_rule(member, c, B64, uinc, lane);
+    const double cw = __shfl(c, w), B32w = __shfl(B32, w), B64w = __shfl(B64, w);
+    if (lane == 0) {
+      I.cbest[i] = cw;
+      I.b32best[i] = B32w;
+      I.b64best[i] = B64w;
+      I.pend[i] = 0;
+    }
+    if (level == I.levels - 1) {
+      Queued Q;
+      accept<PREC>(I, i, x, uinc, cw, B32w, B64w, lane, true, want_l0, n_eval, Q);
+    }
+  } else {
+    // the queued incumbent comparison: lane 0 the winner, lane 1 the incumbent
+    const double cw = I.cbest[i], B64w = I.b64best[i];
+    const bool in2 = lane < 2;
+    const double c2 = lane == 0 ? cw : uinc;
+    const double b32 = lane == 0 ? I.b32best[i] : I.b32inc[i];
+    double b64 = lane == 0 ? (isnan(B64w) ? evr[slot_best(I)] : B64w) : evr[slot_inc(I)];
+    const unsigned long long mask = band32(in2, b32, PREC);
+    const bool member = (mask >> lane) & 1ull;
+    const int w = tie_rule(member, c2, b64, uinc, lane);
+    finish_point(I, i, __shfl(c2, w), __shfl(b64, w), x, lane, want_l0);
+    if (lane == 0) I.pend[i] = 0;
+  }
+}
+
+template <int PREC>
+__global__ __launch_bounds__(kSelWaves * kWave) void k_resolve(Launch L, int level, int want_l0) {
+  const int u = blockIdx.x;
+  const int b = find_inst(L.pre, L.n_inst, u);
+  const Inst& I = L.insts[b];
+  if (u == L.pre[b] && threadIdx.x == 0) *I.nitems = 0;  // the queue has been drained
+  const int wid = threadIdx.x / kWave, lane = threadIdx.x % kWave;
+  const int i0 = ((u - L.pre[b]) * kSelWaves + wid) * kSelPts;
+  int n_eval = 0;
+  for (int p = 0; p < kSelPts && i0 + p < I.n_x; ++p) resolve_point<PREC>(I, level, i0 + p, lane, want_l0, n_eval);
+  if (lane == 0) count_evals(I, n_eval);
+}
+
+hipError_t launch_select(const Launch& L, int level, int prec, int want_l0, hipStream_t st, hipEvent_t e0,
+                         hipEvent_t e1) {
   if (L.total == 0) return hipSuccess;
-  dim3 blk(kSelWaves * kWave);
-  if (prec == UCP_FP64)
-    hipLaunchKernelGGL(k_select<UCP_FP64>, dim3(L.total), blk, 0, st, L, level, want_l0);
-  else if (prec == UCP_FP32_KAHAN)
-    hipLaunchKernelGGL(k_select<UCP_FP32_KAHAN>, dim3(L.total), blk, 0, st, L, level, want_l0);
-  else
-    hipLaunchKernelGGL(k_select<UCP_FP32>, dim3(L.total), blk, 0, st, L, level, want_l0);
+  const dim3 blk(kSelWaves * kWave);
+  if (prec == UCP_FP64) {
+    hipExtLaunchKernelGGL(k_band<UCP_FP64>, dim3(L.total), blk, 0, st, e0, e1, 0, L, level, want_l0);
+    return hipGetLastError();
+  }
+  if (prec == UCP_FP32_KAHAN) {
+    hipExtLaunchKernelGGL(k_band<UCP_FP32_KAHAN>, dim3(L.total), blk, 0, st, e0, nullptr, 0, L, level, want_l0);
+    hipLaunchKernelGGL(k_eval, dim3(kEvalBlocks), dim3(kEvalWaves * kWave), 0, st, L);
+    hipExtLaunchKernelGGL(k_resolve<UCP_FP32_KAHAN>, dim3(L.total), blk, 0, st, nullptr, e1, 0, L, level,
+                          want_l0);
+  } else {
+    hipExtLaunchKernelGGL(k_band<UCP_FP32>, dim3(L.total), blk, 0, st, e0, nullptr, 0, L, level, want_l0);
+    hipLaunchKernelGGL(k_eval, dim3(kEvalBlocks), dim3(kEvalWaves * kWave), 0, st, L);
+    hipExtLaunchKernelGGL(k_resolve<UCP_FP32>, dim3(L.total), blk, 0, st, nullptr, e1, 0, L, level, want_l0);
+  }
   return hipGetLastError();
 }
 
@@ -773,20 +1026,20 @@ __global__ __launch_bounds__(kU1Block) void k_u1_combine(Launch L) {
   if (!isfinite(u1)) atomicOr(I.flags, 1);
 }
 
-hipError_t launch_u1_partial(const Launch& L, int prec, hipStream_t st) {
+hipError_t launch_u1_partial(const Launch& L, int prec, hipStream_t st, hipEvent_t e0) {
   if (L.total == 0) return hipSuccess;
   if (prec == UCP_FP64)
-    hipLaunchKernelGGL(k_u1_partial<UCP_FP64>, dim3(L.total), dim3(kU1Block), 0, st, L);
+    hipExtLaunchKernelGGL(k_u1_partial<UCP_FP64>, dim3(L.total), dim3(kU1Block), 0, st, e0, nullptr, 0, L);
   else if (prec == UCP_FP32_KAHAN)
-    hipLaunchKernelGGL(k_u1_partial<UCP_FP32_KAHAN>, dim3(L.total), dim3(kU1Block), 0, st, L);
+    hipExtLaunchKernelGGL(k_u1_partial<UCP_FP32_KAHAN>, dim3(L.total), dim3(kU1Block), 0, st, e0, nullptr, 0, L);
   else
-    hipLaunchKernelGGL(k_u1_partial<UCP_FP32>, dim3(L.total), dim3(kU1Block), 0, st, L);
+    hipExtLaunchKernelGGL(k_u1_partial<UCP_FP32>, dim3(L.total), dim3(kU1Block), 0, st, e0, nullptr, 0, L);
   return hipGetLastError();
 }
 
-hipError_t launch_u1_combine(const Launch& L, hipStream_t st) {
+hipError_t launch_u1_combine(const Launch& L, hipStream_t st, hipEvent_t e1) {
   if (L.total == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_u1_combine, dim3(L.total), dim3(kU1Block), 0, st, L);
+  hipExtLaunchKernelGGL(k_u1_combine, dim3(L.total), dim3(kU1Block), 0, st, nullptr, e1, 0, L);
   return hipGetLastError();
 }
 
@@ -828,15 +1081,15 @@ __global__ __launch_bounds__(256) void k_j_reduce(Launch L, int t) {
   }
 }
 
-hipError_t launch_j_rows(const Launch& L, hipStream_t st) {
+hipError_t launch_j_rows(const Launch& L, hipStream_t st, hipEvent_t e0) {
   if (L.total == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_j_rows, dim3(L.total), dim3(kJWaves * kWave), 0, st, L);
+  hipExtLaunchKernelGGL(k_j_rows, dim3(L.total), dim3(kJWaves * kWave), 0, st, e0, nullptr, 0, L);
   return hipGetLastError();
 }
 
-hipError_t launch_j_reduce_t(const Launch& L, int t, hipStream_t st) {
+hipError_t launch_j_reduce_t(const Launch& L, int t, hipStream_t st, hipEvent_t e1) {
   if (L.total == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_j_reduce, dim3(L.total), dim3(256), 0, st, L, t);
+  hipExtLaunchKernelGGL(k_j_reduce, dim3(L.total), dim3(256), 0, st, nullptr, e1, 0, L, t);
   return hipGetLastError();
 }
 

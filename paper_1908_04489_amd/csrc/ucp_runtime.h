@@ -33,6 +33,7 @@ int check_prec(int prec);
 Inst make_inst(const ucp_problem& p, const ucp_search* s, int prec, int cands_override);
 size_t state_bytes(const Inst& I);
 void carve_state(Inst& I, char*& base);
+hipError_t clear_state(const Inst& I, hipStream_t st);
 std::vector<int32_t> build_tables(const std::vector<Inst>& insts, const std::vector<char>& running);
 
 hipError_t launch_v_from_u1(const Launch& L, hipStream_t st);

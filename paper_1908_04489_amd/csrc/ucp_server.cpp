@@ -255,7 +255,7 @@ static int admit(ucp_server* s) {
     s->running.push_back(r);
     SRV_TRY(hipMemcpyAsync(r->inst.u0, r->u0_init.data(), sizeof(double) * r->inst.n_x, hipMemcpyHostToDevice,
                            s->stream), "upload u0_init");
-    SRV_TRY(hipMemsetAsync(r->inst.flags, 0, 128, s->stream), "clear flags");
+    SRV_TRY(clear_state(r->inst, s->stream), "clear state");
   }
   return UCP_OK;
 }
