@@ -32,13 +32,15 @@ if ROOT not in sys.path:
 # 157.3 TFLOP/s FP32 vector peak counts an FMA as two flops):
 # 256 CUs x 128 x 2.4 GHz = 78.6e12 slots/s; v_exp_f32 issues at a quarter
 # of that rate (4 slots).  The kernel factors the shifted Gaussian into a
-# per-offset table value and a per-lane exponential, so one algorithmic term
-# needs 5 FP32 operations (residual argument, residual, weight, product,
-# accumulate) and each block of 8 terms 11 more slots (one exp2 and its
-# argument, the block scale, the two-chain combine, 4 of compensation):
-# 5 + 11/8 = 6.375 slots per term.
+# per-offset table value and a per-lane exponential and stages the
+# differences around a per-block reference, so one algorithmic term needs 4
+# FP32 operations (difference, weight, product, accumulate) and each block
+# of 8 terms 11 more slots (one exp2 and its argument, the block scale, the
+# two-chain combine, 4 of compensation): 4 + 11/8 = 5.375 slots per term.
+# (Blocks whose positions spread wider than the reference form allows take
+# one more operation per term; the count above is the smaller one.)
 PEAK_SLOTS = 256 * 128 * 2.4e9
-SLOTS_PER_TERM = 6.375
+SLOTS_PER_TERM = 5.375
 
 
 def kernel_source_hash():

@@ -262,23 +262,37 @@ constexpr int kMcUnroll = 8;
 // Per-lane constants of one unit.
 struct McLane {
   float aDy;             // alpha dy
-  float Dl;              // alpha delta
+  float Dl;              // residual form: alpha delta; reference form: alpha (z - z_c)
   float beta;            // -2 alpha^2 dy delta
   float R[kMcUnroll];    // exp2(beta m)
   float Dm[kMcUnroll];   // Dl + m alpha dy
 };
 
+// The scaled difference e = alpha (z - u1_j) of node j = jr + k, from the
+// staged value s_j, in one of two forms:
+//  - residual form (REF = false): s_j = alpha (y_j - u1_j), e = s_j - T_k
+//    with T_k = alpha (y_j - z) = alpha (delta + k dy);
+//  - reference form (REF = true): s_j = alpha (z_c - u1_j) around one z_c per
+//    block, e = s_j + alpha (z - z_c), one add per term.  Used when every z
+//    of the block lies within kMcRefHalf of z_c, where its rounding error
+//    (<= ulp of alpha |z - z_c| and of |e|) is no larger than the residual
+//    form's (<= ulp of alpha |y_j - z|, a few units over the weighted nodes).
+template <bool REF>
+__device__ __forceinline__ float mc_e(float sj, float kf, float Dm, const McLane& c) {
+  return REF ? sj + c.Dl : sj - fmaf(kf, c.aDy, Dm);
+}
+
 // Offsets k in [k0, k1] (wave-uniform bounds, every lane in range): blocks of
 // 8 terms summed plainly in two chains, each block sum added with
 // compensation (KAHAN) or plainly.  Two register buffers alternate: the
-// residuals (LDS) and table values (scalar loads) of block b + 1 are
+// staged values (LDS) and table values (scalar loads) of block b + 1 are
 // requested once block b's have been consumed into its first partial
 // products, so their latency overlaps the rest of block b.  (LDS and scalar
 // loads share one wait counter: loads issued any earlier would be waited
 // for together with block b's.)
 struct McBlk {
   float g[kMcUnroll];  // table values G_{k+m}
-  float v[kMcUnroll];  // residuals v_{jr+k+m}
+  float v[kMcUnroll];  // staged values s_{jr+k+m}
 };
 
 template <typename P, typename Q>
@@ -290,11 +304,12 @@ __device__ __forceinline__ void mc_load(McBlk& B, P v, Q G, int k) {
   }
 }
 
-// First half of a block: e_m = v - T_m and g_m R_m (consumes the loads).
+// First half of a block: the differences e_m and g_m R_m (consumes the loads).
+template <bool REF>
 __device__ __forceinline__ void mc_first(const McBlk& B, float kf, const McLane& c, float* e, float* gr) {
 #pragma unroll
   for (int m = 0; m < kMcUnroll; ++m) {
-    e[m] = B.v[m] - fmaf(kf, c.aDy, c.Dm[m]);
+    e[m] = mc_e<REF>(B.v[m], kf, c.Dm[m], c);
     gr[m] = B.g[m] * c.R[m];
   }
 }
@@ -314,7 +329,17 @@ __device__ __forceinline__ void mc_second(const float* e, const float* gr, float
   else acc = fmaf(E0, b0 + b1, acc);
 }
 
-template <bool KAHAN, typename P, typename Q>
+// One term outside the unrolled blocks.
+template <bool KAHAN, bool REF, typename P, typename Q>
+__device__ __forceinline__ void mc_one(P v, Q G, int k, const McLane& c, float& acc, float& comp) {
+  const float kf = (float)k;
+  const float g = G[k] * __builtin_amdgcn_exp2f(c.beta * kf);
+  const float e = mc_e<REF>(v[k], kf, c.Dl, c);
+  if (KAHAN) kahan_add((g * e) * e, acc, comp);
+  else acc = fmaf(g * e, e, acc);
+}
+
+template <bool KAHAN, bool REF, typename P, typename Q>
 __device__ __forceinline__ void mc_bulk(P v, Q G, int k0, int k1, const McLane& c, float& acc,
                                         float& comp) {
   constexpr int U = kMcUnroll;
@@ -323,12 +348,12 @@ __device__ __forceinline__ void mc_bulk(P v, Q G, int k0, int k1, const McLane& 
   float e[U], gr[U];
   if (k + U - 1 <= k1) mc_load(A, v, G, k);
   for (; k + 2 * U - 1 <= k1; k += 2 * U) {
-    mc_first(A, (float)k, c, e, gr);
+    mc_first<REF>(A, (float)k, c, e, gr);
     __builtin_amdgcn_sched_barrier(0);
     mc_load(B, v, G, k + U);
     __builtin_amdgcn_sched_barrier(0);
     mc_second<KAHAN>(e, gr, (float)k, c, acc, comp);
-    mc_first(B, (float)(k + U), c, e, gr);
+    mc_first<REF>(B, (float)(k + U), c, e, gr);
     __builtin_amdgcn_sched_barrier(0);
     // the next block, or (past the end, unused) the last full block: always in range
     mc_load(A, v, G, min(k + 2 * U, k1 - U + 1));
@@ -336,37 +361,24 @@ __device__ __forceinline__ void mc_bulk(P v, Q G, int k0, int k1, const McLane& 
     mc_second<KAHAN>(e, gr, (float)(k + U), c, acc, comp);
   }
   if (k + U - 1 <= k1) {  // one block left, already loaded into A
-    mc_first(A, (float)k, c, e, gr);
+    mc_first<REF>(A, (float)k, c, e, gr);
     mc_second<KAHAN>(e, gr, (float)k, c, acc, comp);
     k += U;
   }
-  for (; k <= k1; ++k) {
-    const float kf = (float)k;
-    const float g = G[k] * __builtin_amdgcn_exp2f(c.beta * kf);
-    const float e1 = v[k] - fmaf(kf, c.aDy, c.Dl);
-    if (KAHAN) kahan_add((g * e1) * e1, acc, comp);
-    else acc = fmaf(g * e1, e1, acc);
-  }
+  for (; k <= k1; ++k) mc_one<KAHAN, REF>(v, G, k, c, acc, comp);
 }
 
 // Offsets k in [k0, k1] restricted to the lane's own range [klo, khi].
-template <bool KAHAN, typename P, typename Q>
+template <bool KAHAN, bool REF, typename P, typename Q>
 __device__ __forceinline__ void mc_masked(P v, Q G, int k0, int k1, int klo, int khi, const McLane& c,
                                           float& acc, float& comp) {
-  for (int k = k0; k <= k1; ++k) {
-    if (k >= klo && k <= khi) {
-      const float kf = (float)k;
-      const float g = G[k] * __builtin_amdgcn_exp2f(c.beta * kf);
-      const float e = v[k] - fmaf(kf, c.aDy, c.Dl);
-      if (KAHAN) kahan_add((g * e) * e, acc, comp);
-      else acc = fmaf(g * e, e, acc);
-    }
-  }
+  for (int k = k0; k <= k1; ++k)
+    if (k >= klo && k <= khi) mc_one<KAHAN, REF>(v, G, k, c, acc, comp);
 }
 
 // The lane's window [klo, khi] (empty when klo > khi): the range common to
 // every non-empty lane of the wave runs unmasked, the ragged ends masked.
-template <bool KAHAN, typename P, typename Q>
+template <bool KAHAN, bool REF, typename P, typename Q>
 __device__ __forceinline__ void mc_lane(P v, Q G, int klo, int khi, const McLane& c, float& acc,
                                         float& comp) {
   const bool empty = klo > khi;
@@ -376,19 +388,21 @@ __device__ __forceinline__ void mc_lane(P v, Q G, int klo, int khi, const McLane
   const int ku_hi = __builtin_amdgcn_readfirstlane(wave_max_i(empty ? INT_MIN : khi));
   if (ku_lo > ku_hi || empty) return;
   if (kc_lo > kc_hi) {
-    mc_masked<KAHAN>(v, G, ku_lo, ku_hi, klo, khi, c, acc, comp);
+    mc_masked<KAHAN, REF>(v, G, ku_lo, ku_hi, klo, khi, c, acc, comp);
     return;
   }
-  mc_masked<KAHAN>(v, G, ku_lo, kc_lo - 1, klo, khi, c, acc, comp);
-  mc_bulk<KAHAN>(v, G, kc_lo, kc_hi, c, acc, comp);
-  mc_masked<KAHAN>(v, G, kc_hi + 1, ku_hi, klo, khi, c, acc, comp);
+  mc_masked<KAHAN, REF>(v, G, ku_lo, kc_lo - 1, klo, khi, c, acc, comp);
+  mc_bulk<KAHAN, REF>(v, G, kc_lo, kc_hi, c, acc, comp);
+  mc_masked<KAHAN, REF>(v, G, kc_hi + 1, ku_hi, klo, khi, c, acc, comp);
 }
 
 template <int PREC>
 __global__ __launch_bounds__(kMcBlock) void k_mc32(Launch L, int level) {
   constexpr bool KAHAN = PREC == UCP_FP32_KAHAN;
+  constexpr int NW = kMcBlock / kWave;
   __shared__ float sv[kMcLds];
-  __shared__ int sred[4][kMcBlock / kWave];
+  __shared__ int sred[4][NW];
+  __shared__ double szr[2][NW];
   const int u = blockIdx.x;
   const int b = find_inst(L.pre, L.n_inst, u);
   const Inst& I = L.insts[b];
@@ -416,26 +430,33 @@ __global__ __launch_bounds__(kMcBlock) void k_mc32(Launch L, int level) {
   int klo = max(s_lo, -jr), khi = min(s_hi, I.n_y - 1 - jr);
   if (!act) { klo = 1; khi = 0; }
 
-  // node range and offset range of the block, for LDS staging
+  // node range, offset range and z range of the block, for LDS staging
   const int wid = threadIdx.x / kWave, lane = threadIdx.x % kWave;
   const bool ne = klo <= khi;
   const int jlo = wave_min_i(ne ? jr + klo : INT_MAX);
   const int jhi = wave_max_i(ne ? jr + khi : INT_MIN);
   const int klw = wave_min_i(ne ? klo : INT_MAX);
   const int khw = wave_max_i(ne ? khi : INT_MIN);
+  const double zlo = wave_min_d(ne ? z : INFINITY);
+  const double zhi = -wave_min_d(ne ? -z : INFINITY);
   if (lane == 0) {
     sred[0][wid] = jlo;
     sred[1][wid] = jhi;
     sred[2][wid] = klw;
     sred[3][wid] = khw;
+    szr[0][wid] = zlo;
+    szr[1][wid] = zhi;
   }
   __syncthreads();
   int blo = INT_MAX, bhi = INT_MIN, bklo = INT_MAX, bkhi = INT_MIN;
-  for (int w = 0; w < kMcBlock / kWave; ++w) {
+  double bzlo = INFINITY, bzhi = -INFINITY;
+  for (int w = 0; w < NW; ++w) {
     blo = min(blo, sred[0][w]);
     bhi = max(bhi, sred[1][w]);
     bklo = min(bklo, sred[2][w]);
     bkhi = max(bkhi, sred[3][w]);
+    bzlo = fmin(bzlo, szr[0][w]);
+    bzhi = fmax(bzhi, szr[1][w]);
   }
   if (seg == 0) {
     count_terms(I, z, act, lane);
@@ -445,15 +466,19 @@ __global__ __launch_bounds__(kMcBlock) void k_mc32(Launch L, int level) {
     if (lane == 0 && ev > 0 && I.terms)
       atomicAdd(I.terms + kCountEvalTerms + (blockIdx.x & (kCountSlots - 1)) * kCountStride, (unsigned long long)ev);
   }
+  const double alpha = sqrt(kAlpha2);
   const bool staged = bhi >= blo && bhi - blo + 1 <= kMcLds;
-  if (staged)
+  const bool ref = staged && bzhi - bzlo <= 2.0 * kMcRefHalf;
+  const double zc = 0.5 * (bzlo + bzhi);  // block-uniform
+  if (ref)
+    for (int j = blo + (int)threadIdx.x; j <= bhi; j += kMcBlock) sv[j - blo] = (float)(alpha * (zc - I.u1[j]));
+  else if (staged)
     for (int j = blo + (int)threadIdx.x; j <= bhi; j += kMcBlock) sv[j - blo] = I.v[j];
   __syncthreads();
 
   McLane cl;
-  const double alpha = sqrt(kAlpha2);
   cl.aDy = (float)(alpha * I.dy);
-  cl.Dl = (float)(alpha * delta);
+  cl.Dl = ref ? (float)(alpha * (z - zc)) : (float)(alpha * delta);
   const double beta = -2.0 * kAlpha2 * I.dy * delta;
   cl.beta = (float)beta;
 #pragma unroll
@@ -465,12 +490,15 @@ __global__ __launch_bounds__(kMcBlock) void k_mc32(Launch L, int level) {
   float acc = 0.0f, comp = 0.0f;
   // the offset table is read at wave-uniform offsets: scalar loads
   cst_cptr G = (cst_cptr)(I.gtab + nw);
-  if (staged) {
+  if (ref) {
     lds_cptr v = (lds_cptr)(sv + (jr - blo));
-    mc_lane<KAHAN>(v, G, klo, khi, cl, acc, comp);
+    mc_lane<KAHAN, true>(v, G, klo, khi, cl, acc, comp);
+  } else if (staged) {
+    lds_cptr v = (lds_cptr)(sv + (jr - blo));
+    mc_lane<KAHAN, false>(v, G, klo, khi, cl, acc, comp);
   } else {
     glb_cptr v = (glb_cptr)(I.v + jr);
-    mc_lane<KAHAN>(v, G, klo, khi, cl, acc, comp);
+    mc_lane<KAHAN, false>(v, G, klo, khi, cl, acc, comp);
   }
   if (act) I.part[((size_t)i * pstride + q) * S + seg] = KAHAN ? (double)acc - (double)comp : (double)acc;
 }
