@@ -208,6 +208,8 @@ def bench_serving(a):
                     keep.append((tk, idx))
                 else:
                     done[idx] = t_now
+                    if len(done) % 512 == 0:
+                        print(f"# {len(done)}/{n} served", file=sys.stderr, flush=True)
             live = keep
         srv.close()
         fin = np.array([done[i] for i in range(n)])
@@ -236,6 +238,8 @@ def bench_serving(a):
         ev1.record(st)
         ev1.synchronize()
         svc[i] = ev0.elapsed_time(ev1) / 1e3
+        if (i + 1) % 512 == 0:
+            print(f"# one at a time: {i + 1}/{n}", file=sys.stderr, flush=True)
     end = np.empty(n)
     prev = 0.0
     for i in range(n):
@@ -358,7 +362,7 @@ def main():
     ap.add_argument("--prec", default="fp32_kahan")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-check", action="store_true", help="skip the FP64 oracle check of the final J")
-    ap.add_argument("--requests", type=int, default=1024, help="serving: requests taken from the trace")
+    ap.add_argument("--requests", type=int, default=4096, help="serving: requests taken from the trace")
     ap.add_argument("--slots", type=int, default=64, help="serving: concurrent solves")
     ap.add_argument("--instances", type=int, default=64, help="batch: instances per launch")
     ap.add_argument("--sweep-n", type=int, default=20001, help="sweep: grid nodes")

@@ -409,7 +409,6 @@ __global__ __launch_bounds__(kMcBlock) void k_mc32(Launch L, int level) {
   int local = u - L.pre[b];
   const int S = I.segs;
   const int kq = level < 0 ? I.cands : (level == 0 ? I.cands + 1 : I.cands);
-  const int pstride = level < 0 ? I.cands : I.cands + 1;
   const int seg = local % S;
   local /= S;
   const int q = local % kq;
@@ -500,7 +499,8 @@ __global__ __launch_bounds__(kMcBlock) void k_mc32(Launch L, int level) {
     glb_cptr v = (glb_cptr)(I.v + jr);
     mc_lane<KAHAN, false>(v, G, klo, khi, cl, acc, comp);
   }
-  if (act) I.part[((size_t)i * pstride + q) * S + seg] = KAHAN ? (double)acc - (double)comp : (double)acc;
+  // point-fastest layout: a wave writes 64 consecutive doubles (whole cache lines)
+  if (act) I.part[(size_t)(q * S + seg) * I.n_x + i] = KAHAN ? (double)acc - (double)comp : (double)acc;
 }
 
 // FP64 marginal cost (precision-study mode): lane = point, window kWin64,
@@ -513,7 +513,6 @@ __global__ __launch_bounds__(kMcBlock) void k_mc64(Launch L, int level) {
   const Inst& I = L.insts[b];
   int local = u - L.pre[b];
   const int kq = level < 0 ? I.cands : (level == 0 ? I.cands + 1 : I.cands);
-  const int pstride = level < 0 ? I.cands : I.cands + 1;
   const int q = local % kq;
   const int tile = local / kq;
   const int i = tile * kMcBlock + (int)threadIdx.x;
@@ -549,7 +548,7 @@ __global__ __launch_bounds__(kMcBlock) void k_mc64(Launch L, int level) {
       s0 = fma(g * e0, e0, s0);
     }
   }
-  I.part[(size_t)i * pstride + q] = s0 + s1;
+  I.part[(size_t)q * I.n_x + i] = s0 + s1;
 }
 
 hipError_t launch_mc(const Launch& L, int level, int prec, hipStream_t st, hipEvent_t e0, hipEvent_t e1) {
@@ -565,14 +564,14 @@ hipError_t launch_mc(const Launch& L, int level, int prec, hipStream_t st, hipEv
 
 // B from the partial sums of candidate lane q: k^2 c^2 + dy/sqrt(2 pi)
 // exp(-delta^2/2) * sum (the FP32 sums carry the factor alpha^2).
-__device__ __forceinline__ double b_from_parts(const Inst& I, int i, int q, int pstride, int S,
+__device__ __forceinline__ double b_from_parts(const Inst& I, int i, int q, int S,
                                                double c, int prec) {
   const double z = (I.x_lo + (double)i * I.dx) + c;
   const int jr = nearest_node(I, z);
   const double delta = (I.y_lo + (double)jr * I.dy) - z;
-  const double* p = I.part + ((size_t)i * pstride + q) * S;
+  const double* p = I.part + (size_t)q * S * I.n_x + i;  // [slot][segment][point]
   double s = 0.0;
-  for (int g = 0; g < S; ++g) s += p[g];
+  for (int g = 0; g < S; ++g) s += p[(size_t)g * I.n_x];
   if (prec != UCP_FP64) s = s / kAlpha2;
   return I.k2 * c * c + I.phi_scale * exp(-0.5 * delta * delta) * s;
 }
@@ -587,7 +586,7 @@ __global__ __launch_bounds__(256) void k_mc_finish(Launch L, double* out, int pr
   const int i = (int)(idx / I.cands), q = (int)(idx % I.cands);
   const double c = I.u0[idx];
   const int S = I.segs;
-  out[idx] = I.f[i] * b_from_parts(I, i, q, I.cands, S, c, prec);
+  out[idx] = I.f[i] * b_from_parts(I, i, q, S, c, prec);
 }
 
 // ------------------------------------------------------------- selection
@@ -656,7 +655,7 @@ __device__ void level_view(const Inst& I, int level, int i, int lane, double& c,
   B64 = NAN;
   if (lane < kq) {
     c = cand_pos(I, level, lane, i);
-    B32 = b_from_parts(I, i, lane, K + 1, I.segs, c, PREC);
+    B32 = b_from_parts(I, i, lane, I.segs, c, PREC);
     if (PREC == UCP_FP64) B64 = B32;
   }
   if (level > 0 && lane == K) {
