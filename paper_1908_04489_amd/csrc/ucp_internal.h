@@ -84,7 +84,7 @@ struct Inst {
   double* b32best;           // its FP32-path cost B [n_x]
   double* b64best;           // its FP64 cost B, NaN when not evaluated [n_x]
   double* b32inc;            // FP32-path cost B of the incumbent [n_x]
-  double* part;              // marginal-cost partial sums [cands + 1][segs][n_x]
+  double* part;              // marginal-cost partial sums [n_x][cands + 1][segs]
   double* u1part;            // u1 partial sums [u1_slices][n_y][3]
   double* jrow;              // per-point objective terms [n_x]
   double* ev;                // FP64 results of queued sums [n_x][cands + 3]

@@ -499,8 +499,12 @@ __global__ __launch_bounds__(kMcBlock) void k_mc32(Launch L, int level) {
     glb_cptr v = (glb_cptr)(I.v + jr);
     mc_lane<KAHAN, false>(v, G, klo, khi, cl, acc, comp);
   }
-  // point-fastest layout: a wave writes 64 consecutive doubles (whole cache lines)
-  if (act) I.part[(size_t)(q * S + seg) * I.n_x + i] = KAHAN ? (double)acc - (double)comp : (double)acc;
+  // point-major layout [n_x][cands + 1][segs]: the selection's wave for point
+  // i reads its whole row (a few cache lines).  The row is written by blocks
+  // spread over all XCDs, so each L2 writes back partial lines (about 4x the
+  // array's bytes); the kernel is ALU-bound and this costs no time, while the
+  // point-fastest layout costs the selection kernels more.
+  if (act) I.part[((size_t)i * (I.cands + 1) + q) * S + seg] = KAHAN ? (double)acc - (double)comp : (double)acc;
 }
 
 // FP64 marginal cost (precision-study mode): lane = point, window kWin64,
@@ -548,7 +552,7 @@ __global__ __launch_bounds__(kMcBlock) void k_mc64(Launch L, int level) {
       s0 = fma(g * e0, e0, s0);
     }
   }
-  I.part[(size_t)q * I.n_x + i] = s0 + s1;
+  I.part[(size_t)i * (I.cands + 1) + q] = s0 + s1;
 }
 
 hipError_t launch_mc(const Launch& L, int level, int prec, hipStream_t st, hipEvent_t e0, hipEvent_t e1) {
@@ -569,9 +573,9 @@ __device__ __forceinline__ double b_from_parts(const Inst& I, int i, int q, int 
   const double z = (I.x_lo + (double)i * I.dx) + c;
   const int jr = nearest_node(I, z);
   const double delta = (I.y_lo + (double)jr * I.dy) - z;
-  const double* p = I.part + (size_t)q * S * I.n_x + i;  // [slot][segment][point]
+  const double* p = I.part + ((size_t)i * (I.cands + 1) + q) * S;  // [point][slot][segment]
   double s = 0.0;
-  for (int g = 0; g < S; ++g) s += p[(size_t)g * I.n_x];
+  for (int g = 0; g < S; ++g) s += p[g];
   if (prec != UCP_FP64) s = s / kAlpha2;
   return I.k2 * c * c + I.phi_scale * exp(-0.5 * delta * delta) * s;
 }
