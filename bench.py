@@ -35,12 +35,12 @@ if ROOT not in sys.path:
 # per-offset table value and a per-lane exponential and stages the
 # differences around a per-block reference, so one algorithmic term needs 4
 # FP32 operations (difference, weight, product, accumulate) and each block
-# of 8 terms 11 more slots (one exp2 and its argument, the block scale, the
-# two-chain combine, 4 of compensation): 4 + 11/8 = 5.375 slots per term.
+# of 16 terms 11 more slots (one exp2 and its argument, the block scale, the
+# two-chain combine, 4 of compensation): 4 + 11/16 = 4.6875 slots per term.
 # (Blocks whose positions spread wider than the reference form allows take
 # one more operation per term; the count above is the smaller one.)
 PEAK_SLOTS = 256 * 128 * 2.4e9
-SLOTS_PER_TERM = 5.375
+SLOTS_PER_TERM = 4.6875
 
 
 def kernel_source_hash():
@@ -201,8 +201,11 @@ def bench_serving(a):
                 continue
             srv.step()
             t_now = time.perf_counter() - t0
+            # admission is first-come first-served and at most max_slots
+            # requests run at once, so only the first max_slots unfinished
+            # requests (in submission order) can have finished in this step
             keep = []
-            for tk, idx in live:
+            for tk, idx in live[:max_slots]:
                 out = srv.poll(tk)
                 if out is None:
                     keep.append((tk, idx))
@@ -210,7 +213,7 @@ def bench_serving(a):
                     done[idx] = t_now
                     if len(done) % 512 == 0:
                         print(f"# {len(done)}/{n} served", file=sys.stderr, flush=True)
-            live = keep
+            live = keep + live[max_slots:]
         srv.close()
         fin = np.array([done[i] for i in range(n)])
         return fin

@@ -231,13 +231,13 @@ hipError_t launch_gtab(const Launch& L, hipStream_t st) {
 //   G_k = exp2(-(k alpha dy)^2)          (the same for every lane: a table),
 //   E_k = exp2(beta k), beta = -2 alpha^2 dy delta (one constant per lane).
 // Every lane of a wave is at the same window offset k, so G_k is one scalar
-// load; E_k costs one v_exp_f32 per block of 8 offsets times the
-// per-lane constants exp2(beta m), m < 8.  The residual z - u1 = v - T with
-// T = alpha t (v = alpha (y - u1), formed in FP64 by the u1 kernel).  After
-// the shift every weight is <= 1, so FP32 neither overflows nor underflows
-// where terms matter.  The block stages the residual nodes it touches in LDS
-// (falls back to global loads when its node range exceeds kMcLds, e.g.
-// across a jump of the controller).
+// load; E_k costs one v_exp_f32 per block of kMcUnroll offsets times the
+// per-lane constants exp2(beta m), m < kMcUnroll.  The difference
+// alpha (z - u1) comes from a staged array in one of two forms (see mc_e).
+// After the shift every weight is <= 1, so FP32 neither overflows nor
+// underflows where terms matter.  The block stages the nodes it touches in
+// LDS (falls back to global loads of the residual form when its node range
+// exceeds kMcLds, e.g. across a jump of the controller).
 
 int32_t units_mc(const Inst& I, int level) {
   if (level >= 0 && level >= I.levels) return 0;
@@ -257,7 +257,7 @@ __device__ __forceinline__ void kahan_add(float x, float& acc, float& comp) {
   acc = t;
 }
 
-constexpr int kMcUnroll = 8;
+constexpr int kMcUnroll = 16;
 
 // Per-lane constants of one unit.
 struct McLane {
@@ -283,7 +283,7 @@ __device__ __forceinline__ float mc_e(float sj, float kf, float Dm, const McLane
 }
 
 // Offsets k in [k0, k1] (wave-uniform bounds, every lane in range): blocks of
-// 8 terms summed plainly in two chains, each block sum added with
+// kMcUnroll terms summed plainly in two chains, each block sum added with
 // compensation (KAHAN) or plainly.  Two register buffers alternate: the
 // staged values (LDS) and table values (scalar loads) of block b + 1 are
 // requested once block b's have been consumed into its first partial
@@ -1091,17 +1091,27 @@ __global__ __launch_bounds__(kJWaves * kWave) void k_j_rows(Launch L) {
   if (lane == 0) I.jrow[i] = I.f[i] * (I.k2 * u0 * u0 + inner);
 }
 
-// One block per instance: fixed-order sum of the rows (strided per thread,
-// then a tree), times dx.  `t` selects the J_hist entry.
-__global__ __launch_bounds__(256) void k_j_reduce(Launch L, int t) {
-  __shared__ double red[256];
+// One block per instance: fixed-order sum of the rows (each thread four
+// independent strided partial sums, so the loads overlap, then a tree),
+// times dx.  `t` selects the J_hist entry.
+constexpr int kJRed = 1024;
+__global__ __launch_bounds__(kJRed) void k_j_reduce(Launch L, int t) {
+  __shared__ double red[kJRed];
   const int b = find_inst(L.pre, L.n_inst, blockIdx.x);
   const Inst& I = L.insts[b];
-  double s = 0.0;
-  for (int i = threadIdx.x; i < I.n_x; i += 256) s += I.jrow[i];
-  red[threadIdx.x] = s;
+  const int n = I.n_x;
+  double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+  int i = threadIdx.x;
+  for (; i + 3 * kJRed < n; i += 4 * kJRed) {
+    s0 += I.jrow[i];
+    s1 += I.jrow[i + kJRed];
+    s2 += I.jrow[i + 2 * kJRed];
+    s3 += I.jrow[i + 3 * kJRed];
+  }
+  for (; i < n; i += kJRed) s0 += I.jrow[i];
+  red[threadIdx.x] = (s0 + s1) + (s2 + s3);
   __syncthreads();
-  for (int o = 128; o > 0; o >>= 1) {
+  for (int o = kJRed / 2; o > 0; o >>= 1) {
     if ((int)threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
     __syncthreads();
   }
@@ -1120,7 +1130,7 @@ hipError_t launch_j_rows(const Launch& L, hipStream_t st, hipEvent_t e0) {
 
 hipError_t launch_j_reduce_t(const Launch& L, int t, hipStream_t st, hipEvent_t e1) {
   if (L.total == 0) return hipSuccess;
-  hipExtLaunchKernelGGL(k_j_reduce, dim3(L.total), dim3(256), 0, st, nullptr, e1, 0, L, t);
+  hipExtLaunchKernelGGL(k_j_reduce, dim3(L.total), dim3(kJRed), 0, st, nullptr, e1, 0, L, t);
   return hipGetLastError();
 }
 
