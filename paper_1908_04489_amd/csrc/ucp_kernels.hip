@@ -95,12 +95,39 @@ __device__ __forceinline__ int nearest_node(const Inst& I, double z) {
 // r_k = exp(-64 dy t_k - (64 dy)^2 / 2) and q = exp(-(64 dy)^2), so two
 // multiplies replace an exp; both are recomputed by exp every kReseed steps,
 // which bounds the relative error of any weight by ~kReseed^2/2 ulp
-// (5.7e-14).  Every lane has a node in the first floor(n/64) steps, which
-// run without masks, kPrefetch loads issued ahead of their use; only the
-// last step can be partial.  Two accumulators split the dependency chain.
+// (5.7e-14).  Every lane has a node in the first floor(n/64) steps: they run
+// without masks in groups of kPrefetch, the loads of group g + 1 issued
+// before group g is summed (two register buffers); only the last step can be
+// partial.  Even steps go to one accumulator and odd steps to another.
 constexpr int kReseed = 32;
-constexpr int kPrefetch = 8;
+constexpr int kPrefetch = 4;
+static_assert(kReseed % kPrefetch == 0, "reseeds fall on group boundaries");
 typedef const __attribute__((address_space(1))) double* glb_dptr;
+
+struct B64Walk {
+  double g, r;  // weight of the lane's next node and its ratio
+};
+
+__device__ __forceinline__ void b64_reseed(B64Walk& w, int klo, int lane, int m, double dy, double delta, double D) {
+  const double d = (double)(klo + lane + kWave * m) * dy;
+  w.g = exp(-0.5 * d * (d + 2.0 * delta));
+  w.r = exp(-D * (d + delta) - 0.5 * D * D);
+}
+
+// Sum one group of kPrefetch steps starting at step m (m even).
+__device__ __forceinline__ void b64_group(const double* uv, double z, double q, B64Walk& w, double& s0, double& s1) {
+#pragma unroll
+  for (int mm = 0; mm < kPrefetch; mm += 2) {
+    const double e0 = z - uv[mm];
+    s0 = fma(w.g * e0, e0, s0);
+    w.g *= w.r;
+    w.r *= q;
+    const double e1 = z - uv[mm + 1];
+    s1 = fma(w.g * e1, e1, s1);
+    w.g *= w.r;
+    w.r *= q;
+  }
+}
 
 __device__ double b64_wave(const Inst& I, double z, int lane) {
   const int jr = nearest_node(I, z);
@@ -113,38 +140,40 @@ __device__ double b64_wave(const Inst& I, double z, int lane) {
   glb_dptr u1 = (glb_dptr)(I.u1 + jr + klo + lane);  // this lane's node of step m: u1[64 m]
   double s0 = 0.0, s1 = 0.0;
   const int steps = (n + kWave - 1) / kWave;
-  const int full = n / kWave;
-  for (int m0 = 0; m0 < steps; m0 += kReseed) {
-    const double d = (double)(klo + lane + kWave * m0) * dy;
-    double g = exp(-0.5 * d * (d + 2.0 * delta));
-    double r = exp(-D * (d + delta) - 0.5 * D * D);
-    const int mend = min(m0 + kReseed, steps);
-    const int mu = min(mend, full);
-    int m = m0;
-    for (; m + kPrefetch <= mu; m += kPrefetch) {
-      double uv[kPrefetch];
+  const int groups = (n / kWave) / kPrefetch;  // unmasked groups
+  B64Walk w;
+  double ua[kPrefetch], ub[kPrefetch];
+  if (groups > 0) {
 #pragma unroll
-      for (int mm = 0; mm < kPrefetch; ++mm) uv[mm] = u1[kWave * (m + mm)];
+    for (int mm = 0; mm < kPrefetch; ++mm) ua[mm] = u1[kWave * mm];
+  }
+  int gi = 0;
+  for (; gi + 2 <= groups; gi += 2) {
+    const int m = gi * kPrefetch;
 #pragma unroll
-      for (int mm = 0; mm < kPrefetch; mm += 2) {
-        const double e0 = z - uv[mm];
-        s0 = fma(g * e0, e0, s0);
-        g *= r;
-        r *= q;
-        const double e1 = z - uv[mm + 1];
-        s1 = fma(g * e1, e1, s1);
-        g *= r;
-        r *= q;
-      }
-    }
-    for (; m < mend; ++m) {  // fewer than kPrefetch steps, the last one possibly partial
-      double e = 0.0;
-      if (lane + kWave * m < n) e = z - u1[kWave * m];
-      if (m & 1) s1 = fma(g * e, e, s1);  // the same accumulator as in the blocks above
-      else s0 = fma(g * e, e, s0);
-      g *= r;
-      r *= q;
-    }
+    for (int mm = 0; mm < kPrefetch; ++mm) ub[mm] = u1[kWave * (m + kPrefetch + mm)];
+    if (m % kReseed == 0) b64_reseed(w, klo, lane, m, dy, delta, D);
+    b64_group(ua, z, q, w, s0, s1);
+    // the group after next, or (past the end, unused) the last one: in range
+    const int mn = min(m + 2 * kPrefetch, (groups - 1) * kPrefetch);
+#pragma unroll
+    for (int mm = 0; mm < kPrefetch; ++mm) ua[mm] = u1[kWave * (mn + mm)];
+    if ((m + kPrefetch) % kReseed == 0) b64_reseed(w, klo, lane, m + kPrefetch, dy, delta, D);
+    b64_group(ub, z, q, w, s0, s1);
+  }
+  if (gi < groups) {  // one group left, already loaded
+    const int m = gi * kPrefetch;
+    if (m % kReseed == 0) b64_reseed(w, klo, lane, m, dy, delta, D);
+    b64_group(ua, z, q, w, s0, s1);
+  }
+  for (int m = groups * kPrefetch; m < steps; ++m) {  // the rest, the last step possibly partial
+    if (m % kReseed == 0) b64_reseed(w, klo, lane, m, dy, delta, D);
+    double e = 0.0;
+    if (lane + kWave * m < n) e = z - u1[kWave * m];
+    if (m & 1) s1 = fma(w.g * e, e, s1);
+    else s0 = fma(w.g * e, e, s0);
+    w.g *= w.r;
+    w.r *= q;
   }
   const double s = wave_sum_d(s0 + s1);
   return I.phi_scale * exp(-0.5 * delta * delta) * s;
@@ -304,26 +333,25 @@ __device__ __forceinline__ void mc_load(McBlk& B, P v, Q G, int k) {
   }
 }
 
-// First half of a block: the differences e_m and g_m R_m (consumes the loads).
+// First half of a block: the differences e_m (consumes the staged values;
+// the table values stay in scalar registers until the second half).
 template <bool REF>
-__device__ __forceinline__ void mc_first(const McBlk& B, float kf, const McLane& c, float* e, float* gr) {
+__device__ __forceinline__ void mc_first(const McBlk& B, float kf, const McLane& c, float* e) {
 #pragma unroll
-  for (int m = 0; m < kMcUnroll; ++m) {
-    e[m] = mc_e<REF>(B.v[m], kf, c.Dm[m], c);
-    gr[m] = B.g[m] * c.R[m];
-  }
+  for (int m = 0; m < kMcUnroll; ++m) e[m] = mc_e<REF>(B.v[m], kf, c.Dm[m], c);
 }
 
-// Second half: the block sum times E_k = exp2(beta k) (E_{k+m} = E_k R_m).
+// Second half: the weights g_m R_m and the block sum times E_k = exp2(beta k)
+// (E_{k+m} = E_k R_m).
 template <bool KAHAN>
-__device__ __forceinline__ void mc_second(const float* e, const float* gr, float kf, const McLane& c, float& acc,
+__device__ __forceinline__ void mc_second(const McBlk& B, const float* e, float kf, const McLane& c, float& acc,
                                           float& comp) {
   const float E0 = __builtin_amdgcn_exp2f(c.beta * kf);
   float b0 = 0.0f, b1 = 0.0f;
 #pragma unroll
   for (int m = 0; m < kMcUnroll; m += 2) {
-    b0 = fmaf(gr[m] * e[m], e[m], b0);
-    b1 = fmaf(gr[m + 1] * e[m + 1], e[m + 1], b1);
+    b0 = fmaf((B.g[m] * c.R[m]) * e[m], e[m], b0);
+    b1 = fmaf((B.g[m + 1] * c.R[m + 1]) * e[m + 1], e[m + 1], b1);
   }
   if (KAHAN) kahan_add(E0 * (b0 + b1), acc, comp);
   else acc = fmaf(E0, b0 + b1, acc);
@@ -345,24 +373,24 @@ __device__ __forceinline__ void mc_bulk(P v, Q G, int k0, int k1, const McLane& 
   constexpr int U = kMcUnroll;
   int k = k0;
   McBlk A, B;
-  float e[U], gr[U];
+  float e[U];
   if (k + U - 1 <= k1) mc_load(A, v, G, k);
   for (; k + 2 * U - 1 <= k1; k += 2 * U) {
-    mc_first<REF>(A, (float)k, c, e, gr);
+    mc_first<REF>(A, (float)k, c, e);
     __builtin_amdgcn_sched_barrier(0);
     mc_load(B, v, G, k + U);
     __builtin_amdgcn_sched_barrier(0);
-    mc_second<KAHAN>(e, gr, (float)k, c, acc, comp);
-    mc_first<REF>(B, (float)(k + U), c, e, gr);
+    mc_second<KAHAN>(A, e, (float)k, c, acc, comp);
+    mc_first<REF>(B, (float)(k + U), c, e);
     __builtin_amdgcn_sched_barrier(0);
     // the next block, or (past the end, unused) the last full block: always in range
     mc_load(A, v, G, min(k + 2 * U, k1 - U + 1));
     __builtin_amdgcn_sched_barrier(0);
-    mc_second<KAHAN>(e, gr, (float)(k + U), c, acc, comp);
+    mc_second<KAHAN>(B, e, (float)(k + U), c, acc, comp);
   }
   if (k + U - 1 <= k1) {  // one block left, already loaded into A
-    mc_first<REF>(A, (float)k, c, e, gr);
-    mc_second<KAHAN>(e, gr, (float)k, c, acc, comp);
+    mc_first<REF>(A, (float)k, c, e);
+    mc_second<KAHAN>(A, e, (float)k, c, acc, comp);
     k += U;
   }
   for (; k <= k1; ++k) mc_one<KAHAN, REF>(v, G, k, c, acc, comp);
@@ -409,8 +437,11 @@ __global__ __launch_bounds__(kMcBlock) void k_mc32(Launch L, int level) {
   int local = u - L.pre[b];
   const int S = I.segs;
   const int kq = level < 0 ? I.cands : (level == 0 ? I.cands + 1 : I.cands);
-  const int seg = local % S;
-  local /= S;
+  // window segment slowest: blocks dispatched together read the same part
+  // of the offset table, which then stays in the scalar cache
+  const int per_seg = ((I.n_x + kMcBlock - 1) / kMcBlock) * kq;
+  const int seg = local / per_seg;
+  local %= per_seg;
   const int q = local % kq;
   const int tile = local / kq;
   const int i = tile * kMcBlock + (int)threadIdx.x;
