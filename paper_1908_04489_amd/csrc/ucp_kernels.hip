@@ -179,6 +179,92 @@ __device__ double b64_wave(const Inst& I, double z, int lane) {
   return I.phi_scale * exp(-0.5 * delta * delta) * s;
 }
 
+// FP64 window sums for R positions z_q sharing one pass over the union of
+// their windows (the positions of one point's queued candidates lie within
+// a small bracket): each lane's u1 load serves all R sums.  Per position the
+// same shifted Gaussian and reseeded recurrence as b64_wave, relative to its
+// own nearest node; nodes of the union beyond a position's own window add
+// weights below exp(-50).  One accumulator per position.
+template <int R>
+__device__ void b64_multi(const Inst& I, const double* z, int lane, double* out) {
+  int jr[R];
+  double delta[R];
+  int jlo = INT_MAX, jhi = INT_MIN;
+#pragma unroll
+  for (int q = 0; q < R; ++q) {
+    jr[q] = nearest_node(I, z[q]);
+    delta[q] = (I.y_lo + (double)jr[q] * I.dy) - z[q];
+    jlo = min(jlo, max(0, jr[q] - I.nw64));
+    jhi = max(jhi, min(I.n_y - 1, jr[q] + I.nw64));
+  }
+  const int n = jhi - jlo + 1;
+  const double dy = I.dy, D = (double)kWave * dy;
+  const double qf = exp(-D * D);
+  glb_dptr u1 = (glb_dptr)(I.u1 + jlo + lane);  // this lane's node of step m: u1[64 m]
+  double g[R], r[R], s[R];
+#pragma unroll
+  for (int q = 0; q < R; ++q) s[q] = 0.0;
+  auto reseed = [&](int m) {
+#pragma unroll
+    for (int q = 0; q < R; ++q) {
+      const double d = (double)(jlo + lane + kWave * m - jr[q]) * dy;
+      g[q] = exp(-0.5 * d * (d + 2.0 * delta[q]));
+      r[q] = exp(-D * (d + delta[q]) - 0.5 * D * D);
+    }
+  };
+  auto group = [&](const double* uv) {
+#pragma unroll
+    for (int mm = 0; mm < kPrefetch; ++mm) {
+#pragma unroll
+      for (int q = 0; q < R; ++q) {
+        const double e = z[q] - uv[mm];
+        s[q] = fma(g[q] * e, e, s[q]);
+        g[q] *= r[q];
+        r[q] *= qf;
+      }
+    }
+  };
+  const int steps = (n + kWave - 1) / kWave;
+  const int groups = (n / kWave) / kPrefetch;  // unmasked groups
+  double ua[kPrefetch], ub[kPrefetch];
+  if (groups > 0) {
+#pragma unroll
+    for (int mm = 0; mm < kPrefetch; ++mm) ua[mm] = u1[kWave * mm];
+  }
+  int gi = 0;
+  for (; gi + 2 <= groups; gi += 2) {
+    const int m = gi * kPrefetch;
+#pragma unroll
+    for (int mm = 0; mm < kPrefetch; ++mm) ub[mm] = u1[kWave * (m + kPrefetch + mm)];
+    if (m % kReseed == 0) reseed(m);
+    group(ua);
+    const int mn = min(m + 2 * kPrefetch, (groups - 1) * kPrefetch);
+#pragma unroll
+    for (int mm = 0; mm < kPrefetch; ++mm) ua[mm] = u1[kWave * (mn + mm)];
+    if ((m + kPrefetch) % kReseed == 0) reseed(m + kPrefetch);
+    group(ub);
+  }
+  if (gi < groups) {
+    const int m = gi * kPrefetch;
+    if (m % kReseed == 0) reseed(m);
+    group(ua);
+  }
+  for (int m = groups * kPrefetch; m < steps; ++m) {
+    if (m % kReseed == 0) reseed(m);
+    const bool in = lane + kWave * m < n;
+    const double u = in ? u1[kWave * m] : 0.0;
+#pragma unroll
+    for (int q = 0; q < R; ++q) {
+      const double e = in ? z[q] - u : 0.0;
+      s[q] = fma(g[q] * e, e, s[q]);
+      g[q] *= r[q];
+      r[q] *= qf;
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < R; ++q) out[q] = I.phi_scale * exp(-0.5 * delta[q] * delta[q]) * wave_sum_d(s[q]);
+}
+
 // Algorithmic terms of one (point, candidate): the y nodes within kWin32
 // noise sds of z (the work the method needs for FP64-level accuracy; the
 // kernels may evaluate a few more).  Summed per wave, one atomic per wave.
@@ -874,7 +960,11 @@ __global__ __launch_bounds__(kSelWaves * kWave) void k_band(Launch L, int level,
   if (lane == 0) count_evals(I, n_eval);
 }
 
-// One FP64 window sum per wave over the queued items of every instance.
+// Drains the queue of every instance: each wave takes kEvalChunk
+// consecutive items; the queued candidates of one point are contiguous, so
+// the chunk's items of one point share one pass over their windows.
+constexpr int kEvalChunk = 4;
+
 __global__ __launch_bounds__(kEvalWaves * kWave) void k_eval(Launch L) {
   const int wid = threadIdx.x / kWave, lane = threadIdx.x % kWave;
   const int gw = blockIdx.x * kEvalWaves + wid, nw = gridDim.x * kEvalWaves;
@@ -882,13 +972,37 @@ __global__ __launch_bounds__(kEvalWaves * kWave) void k_eval(Launch L) {
     if (L.pre[b + 1] == L.pre[b]) continue;  // instance not running
     const Inst& I = L.insts[b];
     const int n = *I.nitems;
+    const int nch = (n + kEvalChunk - 1) / kEvalChunk;
     int done = 0;
-    for (int it = gw; it < n; it += nw) {
-      const EvalItem e = I.items[it];
-      const double x = I.x_lo + (double)e.i * I.dx;
-      const double v = I.k2 * e.c * e.c + b64_wave(I, x + e.c, lane);
-      if (lane == 0) ev_row(I, e.i)[e.slot] = v;
-      ++done;
+    for (int ch = gw; ch < nch; ch += nw) {
+      const int e_end = min(n, (ch + 1) * kEvalChunk);
+      for (int p = ch * kEvalChunk; p < e_end;) {
+        const EvalItem it0 = I.items[p];
+        int cnt = 1;
+        while (p + cnt < e_end && I.items[p + cnt].i == it0.i) ++cnt;
+        const double x = I.x_lo + (double)it0.i * I.dx;
+        double c[kEvalChunk], z[kEvalChunk], v[kEvalChunk];
+        int slot[kEvalChunk];
+#pragma unroll
+        for (int q = 0; q < kEvalChunk; ++q) {
+          const EvalItem it = I.items[p + min(q, cnt - 1)];
+          c[q] = it.c;
+          slot[q] = it.slot;
+          z[q] = x + it.c;
+        }
+        if (cnt == 1) v[0] = b64_wave(I, z[0], lane);
+        else if (cnt == 2) b64_multi<2>(I, z, lane, v);
+        else if (cnt == 3) b64_multi<3>(I, z, lane, v);
+        else b64_multi<4>(I, z, lane, v);
+        if (lane == 0) {
+          double* row = ev_row(I, it0.i);
+#pragma unroll
+          for (int q = 0; q < kEvalChunk; ++q)
+            if (q < cnt) row[slot[q]] = I.k2 * c[q] * c[q] + v[q];
+        }
+        done += cnt;
+        p += cnt;
+      }
     }
     if (lane == 0) count_evals(I, done);
   }
