@@ -23,7 +23,8 @@ constexpr int kSelPts = 1;      // ... for kSelPts consecutive points in turn
 constexpr int kEvalWaves = 4;   // queue-draining kernel: one wave per queued sum
 constexpr int kU1Block = 256;   // u1 kernels: one lane per y node
 constexpr int kU1Chunk = 512;   // x nodes staged in LDS per step of the u1 sums
-constexpr int kJWaves = 4;      // objective: one wave per x node
+constexpr int kJWaves = 4;      // objective: one wave ...
+constexpr int kJPts = 4;        // ... per kJPts consecutive x nodes
 // FP32 tie band B32 <= m (1 + tau) + kappa sqrt(m): tau covers the relative
 // error of the Gaussian weights and of the sums, kappa sqrt(m) the rounding
 // of z - u1 in FP32, which dominates where the cost is small.  The band keeps

@@ -854,8 +854,16 @@ __device__ void accept(const Inst& I, int i, double x, double uinc, double cw, d
     Q.c = c2;
     return;
   }
-  for (unsigned long long t = todo; t; t &= t - 1) {
-    const int L = __ffsll((long long)t) - 1;
+  if (todo == 3ull) {  // both: one pass over their windows
+    const double c0 = __shfl(c2, 0), c1 = __shfl(c2, 1);
+    const double z[2] = {x + c0, x + c1};
+    double v[2];
+    b64_multi<2>(I, z, lane, v);
+    if (lane == 0) b64 = I.k2 * c0 * c0 + v[0];
+    if (lane == 1) b64 = I.k2 * c1 * c1 + v[1];
+    n_eval += 2;
+  } else if (todo) {
+    const int L = __ffsll((long long)todo) - 1;
     const double cl = __shfl(c2, L);
     const double v = I.k2 * cl * cl + b64_wave(I, x + cl, lane);
     if (lane == L) b64 = v;
@@ -1221,19 +1229,34 @@ hipError_t launch_u1_combine(const Launch& L, hipStream_t st, hipEvent_t e1) {
 
 // ------------------------------------------------------------- objective
 
-int32_t units_j_rows(const Inst& I) { return (I.n_x + kJWaves - 1) / kJWaves; }
+int32_t units_j_rows(const Inst& I) { return (I.n_x + kJWaves * kJPts - 1) / (kJWaves * kJPts); }
 
 __global__ __launch_bounds__(kJWaves * kWave) void k_j_rows(Launch L) {
   const int u = blockIdx.x;
   const int b = find_inst(L.pre, L.n_inst, u);
   const Inst& I = L.insts[b];
   const int wid = threadIdx.x / kWave, lane = threadIdx.x % kWave;
-  const int i = (u - L.pre[b]) * kJWaves + wid;
-  if (i >= I.n_x) return;
-  const double u0 = I.u0[i];
-  const double x1 = (I.x_lo + (double)i * I.dx) + u0;
-  const double inner = b64_wave(I, x1, lane);
-  if (lane == 0) I.jrow[i] = I.f[i] * (I.k2 * u0 * u0 + inner);
+  // kJPts consecutive points per wave: their x1 mostly coincide (the
+  // controller is a staircase), so one pass over the union of their windows
+  const int i0 = ((u - L.pre[b]) * kJWaves + wid) * kJPts;
+  if (i0 >= I.n_x) return;
+  const int cnt = min(kJPts, I.n_x - i0);
+  double u0[kJPts], z[kJPts], v[kJPts];
+#pragma unroll
+  for (int p = 0; p < kJPts; ++p) {
+    const int i = i0 + min(p, cnt - 1);
+    u0[p] = I.u0[i];
+    z[p] = (I.x_lo + (double)i * I.dx) + u0[p];
+  }
+  if (cnt == 1) v[0] = b64_wave(I, z[0], lane);
+  else if (cnt == 2) b64_multi<2>(I, z, lane, v);
+  else if (cnt == 3) b64_multi<3>(I, z, lane, v);
+  else b64_multi<4>(I, z, lane, v);
+  if (lane == 0) {
+#pragma unroll
+    for (int p = 0; p < kJPts; ++p)
+      if (p < cnt) I.jrow[i0 + p] = I.f[i0 + p] * (I.k2 * u0[p] * u0[p] + v[p]);
+  }
 }
 
 // One block per instance: fixed-order sum of the rows (each thread four
