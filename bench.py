@@ -32,15 +32,16 @@ if ROOT not in sys.path:
 # 157.3 TFLOP/s FP32 vector peak counts an FMA as two flops):
 # 256 CUs x 128 x 2.4 GHz = 78.6e12 slots/s; v_exp_f32 issues at a quarter
 # of that rate (4 slots).  The kernel factors the shifted Gaussian into a
-# per-offset table value and a per-lane exponential and stages the
-# differences around a per-block reference, so one algorithmic term needs 4
-# FP32 operations (difference, weight, product, accumulate) and each block
-# of 16 terms 11 more slots (one exp2 and its argument, the block scale, the
-# two-chain combine, 4 of compensation): 4 + 11/16 = 4.6875 slots per term.
+# per-offset table value and a per-lane exponential, stages the differences
+# around a per-block reference and folds the per-lane factor of the
+# exponential into the difference, so one algorithmic term needs 3 FP32
+# operations (scaled difference, weight, accumulate) and each block of 16
+# terms 11 more slots (one exp2 and its argument, the block scale, the
+# two-chain combine, 4 of compensation): 3 + 11/16 = 3.6875 slots per term.
 # (Blocks whose positions spread wider than the reference form allows take
-# one more operation per term; the count above is the smaller one.)
+# two more operations per term; the count above is the smaller one.)
 PEAK_SLOTS = 256 * 128 * 2.4e9
-SLOTS_PER_TERM = 4.6875
+SLOTS_PER_TERM = 3.6875
 
 
 def kernel_source_hash():

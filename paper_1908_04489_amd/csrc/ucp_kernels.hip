@@ -377,10 +377,10 @@ constexpr int kMcUnroll = 16;
 // Per-lane constants of one unit.
 struct McLane {
   float aDy;             // alpha dy
-  float Dl;              // residual form: alpha delta; reference form: alpha (z - z_c)
+  float Dl;              // residual form: alpha delta; reference form: a = alpha (z - z_c)
   float beta;            // -2 alpha^2 dy delta
-  float R[kMcUnroll];    // exp2(beta m)
-  float Dm[kMcUnroll];   // Dl + m alpha dy
+  float R[kMcUnroll];    // residual form: exp2(beta m); reference form: exp2(beta m / 2)
+  float Dm[kMcUnroll];   // residual form: Dl + m alpha dy; reference form: exp2(beta m / 2) a
 };
 
 // The scaled difference e = alpha (z - u1_j) of node j = jr + k, from the
@@ -388,10 +388,13 @@ struct McLane {
 //  - residual form (REF = false): s_j = alpha (y_j - u1_j), e = s_j - T_k
 //    with T_k = alpha (y_j - z) = alpha (delta + k dy);
 //  - reference form (REF = true): s_j = alpha (z_c - u1_j) around one z_c per
-//    block, e = s_j + alpha (z - z_c), one add per term.  Used when every z
-//    of the block lies within kMcRefHalf of z_c, where its rounding error
-//    (<= ulp of alpha |z - z_c| and of |e|) is no larger than the residual
-//    form's (<= ulp of alpha |y_j - z|, a few units over the weighted nodes).
+//    block, e = s_j + a with a = alpha (z - z_c).  Used when every z of the
+//    block lies within kMcRefHalf of z_c, where its rounding error (<= ulp
+//    of |a| and of |e|) is no larger than the residual form's (<= ulp of
+//    alpha |y_j - z|, a few units over the weighted nodes).  In the unrolled
+//    blocks the term's factor R_m = exp2(beta m) is folded into the
+//    difference: R_m e^2 = e'^2 with e' = fma(sqrt R_m, s_j, sqrt R_m a), so
+//    a term costs one fma, one multiply and one fma.
 template <bool REF>
 __device__ __forceinline__ float mc_e(float sj, float kf, float Dm, const McLane& c) {
   return REF ? sj + c.Dl : sj - fmaf(kf, c.aDy, Dm);
@@ -419,25 +422,32 @@ __device__ __forceinline__ void mc_load(McBlk& B, P v, Q G, int k) {
   }
 }
 
-// First half of a block: the differences e_m (consumes the staged values;
-// the table values stay in scalar registers until the second half).
+// First half of a block: the differences (consumes the staged values; the
+// table values stay in scalar registers until the second half).  Reference
+// form: e'_m = sqrt(R_m) e_m.
 template <bool REF>
 __device__ __forceinline__ void mc_first(const McBlk& B, float kf, const McLane& c, float* e) {
 #pragma unroll
-  for (int m = 0; m < kMcUnroll; ++m) e[m] = mc_e<REF>(B.v[m], kf, c.Dm[m], c);
+  for (int m = 0; m < kMcUnroll; ++m)
+    e[m] = REF ? fmaf(c.R[m], B.v[m], c.Dm[m]) : mc_e<false>(B.v[m], kf, c.Dm[m], c);
 }
 
 // Second half: the weights g_m R_m and the block sum times E_k = exp2(beta k)
 // (E_{k+m} = E_k R_m).
-template <bool KAHAN>
+template <bool KAHAN, bool REF>
 __device__ __forceinline__ void mc_second(const McBlk& B, const float* e, float kf, const McLane& c, float& acc,
                                           float& comp) {
   const float E0 = __builtin_amdgcn_exp2f(c.beta * kf);
   float b0 = 0.0f, b1 = 0.0f;
 #pragma unroll
   for (int m = 0; m < kMcUnroll; m += 2) {
-    b0 = fmaf((B.g[m] * c.R[m]) * e[m], e[m], b0);
-    b1 = fmaf((B.g[m + 1] * c.R[m + 1]) * e[m + 1], e[m + 1], b1);
+    if (REF) {  // R_m is inside e'
+      b0 = fmaf(B.g[m] * e[m], e[m], b0);
+      b1 = fmaf(B.g[m + 1] * e[m + 1], e[m + 1], b1);
+    } else {
+      b0 = fmaf((B.g[m] * c.R[m]) * e[m], e[m], b0);
+      b1 = fmaf((B.g[m + 1] * c.R[m + 1]) * e[m + 1], e[m + 1], b1);
+    }
   }
   if (KAHAN) kahan_add(E0 * (b0 + b1), acc, comp);
   else acc = fmaf(E0, b0 + b1, acc);
@@ -466,17 +476,17 @@ __device__ __forceinline__ void mc_bulk(P v, Q G, int k0, int k1, const McLane& 
     __builtin_amdgcn_sched_barrier(0);
     mc_load(B, v, G, k + U);
     __builtin_amdgcn_sched_barrier(0);
-    mc_second<KAHAN>(A, e, (float)k, c, acc, comp);
+    mc_second<KAHAN, REF>(A, e, (float)k, c, acc, comp);
     mc_first<REF>(B, (float)(k + U), c, e);
     __builtin_amdgcn_sched_barrier(0);
     // the next block, or (past the end, unused) the last full block: always in range
     mc_load(A, v, G, min(k + 2 * U, k1 - U + 1));
     __builtin_amdgcn_sched_barrier(0);
-    mc_second<KAHAN>(B, e, (float)(k + U), c, acc, comp);
+    mc_second<KAHAN, REF>(B, e, (float)(k + U), c, acc, comp);
   }
   if (k + U - 1 <= k1) {  // one block left, already loaded into A
     mc_first<REF>(A, (float)k, c, e);
-    mc_second<KAHAN>(A, e, (float)k, c, acc, comp);
+    mc_second<KAHAN, REF>(A, e, (float)k, c, acc, comp);
     k += U;
   }
   for (; k <= k1; ++k) mc_one<KAHAN, REF>(v, G, k, c, acc, comp);
@@ -599,8 +609,13 @@ __global__ __launch_bounds__(kMcBlock) void k_mc32(Launch L, int level) {
   cl.beta = (float)beta;
 #pragma unroll
   for (int m = 0; m < kMcUnroll; ++m) {
-    cl.R[m] = __builtin_amdgcn_exp2f((float)(beta * m));
-    cl.Dm[m] = (float)(alpha * (delta + m * I.dy));
+    if (ref) {
+      cl.R[m] = __builtin_amdgcn_exp2f((float)(0.5 * beta * m));
+      cl.Dm[m] = cl.R[m] * cl.Dl;
+    } else {
+      cl.R[m] = __builtin_amdgcn_exp2f((float)(beta * m));
+      cl.Dm[m] = (float)(alpha * (delta + m * I.dy));
+    }
   }
 
   float acc = 0.0f, comp = 0.0f;
