@@ -17,7 +17,8 @@ constexpr int kWave = 64;
 constexpr int kMcBlock = 256;   // marginal-cost kernel: one lane per point, 4 waves
 constexpr int kMcLds = 4096;    // FP32 residual nodes staged in LDS per block (16 KiB)
 constexpr int kMcSegMax = 2048; // longest window segment of one marginal-cost work unit
-constexpr double kMcRefHalf = 1.0;  // reference form when every z of a block is within this of z_c
+constexpr double kMcRefHalf = 1.0;
+constexpr double kMcBetaMax = 4.0; // blocked sums only where weights change by <= 2^4 per node  // reference form when every z of a block is within this of z_c
 constexpr int kSelWaves = 16;   // selection kernels: one wave per point ...
 constexpr int kSelPts = 1;      // ... for kSelPts consecutive points in turn
 constexpr int kEvalWaves = 4;   // queue-draining kernel: one wave per queued sum

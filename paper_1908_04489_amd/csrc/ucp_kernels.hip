@@ -437,6 +437,8 @@ __device__ __forceinline__ void mc_first(const McBlk& B, float kf, const McLane&
 template <bool KAHAN, bool REF>
 __device__ __forceinline__ void mc_second(const McBlk& B, const float* e, float kf, const McLane& c, float& acc,
                                           float& comp) {
+  // |beta| <= kMcBetaMax for every lane that reaches the blocked loops, so
+  // every factor here stays within FP32 range
   const float E0 = __builtin_amdgcn_exp2f(c.beta * kf);
   float b0 = 0.0f, b1 = 0.0f;
 #pragma unroll
@@ -555,14 +557,21 @@ __global__ __launch_bounds__(kMcBlock) void k_mc32(Launch L, int level) {
   const int s_hi = min(nw, s_lo + seglen - 1);
   int klo = max(s_lo, -jr), khi = min(s_hi, I.n_y - 1 - jr);
   if (!act) { klo = 1; khi = 0; }
+  const double beta = -2.0 * kAlpha2 * I.dy * delta;
+  // Lanes whose weights change by more than 2^kMcBetaMax from node to node
+  // (very coarse y grids, or positions far outside the y grid) sum their
+  // window term by term below with exact weights; the blocked loops see
+  // them as empty, so the per-lane factors exp2(beta m) stay within range.
+  const bool bigb = fabs(beta) > kMcBetaMax && klo <= khi;
+  const int wlo = bigb ? 1 : klo, whi = bigb ? 0 : khi;
 
   // node range, offset range and z range of the block, for LDS staging
   const int wid = threadIdx.x / kWave, lane = threadIdx.x % kWave;
-  const bool ne = klo <= khi;
-  const int jlo = wave_min_i(ne ? jr + klo : INT_MAX);
-  const int jhi = wave_max_i(ne ? jr + khi : INT_MIN);
-  const int klw = wave_min_i(ne ? klo : INT_MAX);
-  const int khw = wave_max_i(ne ? khi : INT_MIN);
+  const bool ne = wlo <= whi;
+  const int jlo = wave_min_i(ne ? jr + wlo : INT_MAX);
+  const int jhi = wave_max_i(ne ? jr + whi : INT_MIN);
+  const int klw = wave_min_i(ne ? wlo : INT_MAX);
+  const int khw = wave_max_i(ne ? whi : INT_MIN);
   const double zlo = wave_min_d(ne ? z : INFINITY);
   const double zhi = -wave_min_d(ne ? -z : INFINITY);
   if (lane == 0) {
@@ -605,7 +614,6 @@ __global__ __launch_bounds__(kMcBlock) void k_mc32(Launch L, int level) {
   McLane cl;
   cl.aDy = (float)(alpha * I.dy);
   cl.Dl = ref ? (float)(alpha * (z - zc)) : (float)(alpha * delta);
-  const double beta = -2.0 * kAlpha2 * I.dy * delta;
   cl.beta = (float)beta;
 #pragma unroll
   for (int m = 0; m < kMcUnroll; ++m) {
@@ -623,13 +631,25 @@ __global__ __launch_bounds__(kMcBlock) void k_mc32(Launch L, int level) {
   cst_cptr G = (cst_cptr)(I.gtab + nw);
   if (ref) {
     lds_cptr v = (lds_cptr)(sv + (jr - blo));
-    mc_lane<KAHAN, true>(v, G, klo, khi, cl, acc, comp);
+    mc_lane<KAHAN, true>(v, G, wlo, whi, cl, acc, comp);
   } else if (staged) {
     lds_cptr v = (lds_cptr)(sv + (jr - blo));
-    mc_lane<KAHAN, false>(v, G, klo, khi, cl, acc, comp);
+    mc_lane<KAHAN, false>(v, G, wlo, whi, cl, acc, comp);
   } else {
     glb_cptr v = (glb_cptr)(I.v + jr);
-    mc_lane<KAHAN, false>(v, G, klo, khi, cl, acc, comp);
+    mc_lane<KAHAN, false>(v, G, wlo, whi, cl, acc, comp);
+  }
+  if (bigb) {  // term by term, residual form from global memory, exact weights
+    glb_cptr vg = (glb_cptr)(I.v + jr);
+    glb_cptr Gg = (glb_cptr)(I.gtab + nw);
+    const float Dr = (float)(alpha * delta);
+    for (int k = klo; k <= khi; ++k) {
+      const float kf = (float)k;
+      const float g = Gg[k] * __builtin_amdgcn_exp2f(cl.beta * kf);
+      const float e = vg[k] - fmaf(kf, cl.aDy, Dr);
+      if (KAHAN) kahan_add((g * e) * e, acc, comp);
+      else acc = fmaf(g * e, e, acc);
+    }
   }
   // point-major layout [n_x][cands + 1][segs]: the selection's wave for point
   // i reads its whole row (a few cache lines).  The row is written by blocks
