@@ -57,8 +57,8 @@ typedef enum {
 /* Problem instance: weight k of the stage-1 cost, the prior of x0 as a
  * mixture of n_comp Gaussians (weights w summing to 1, means mu, standard
  * deviations sd > 0), the x0 grid (n_x nodes on [x_lo, x_hi]) and the y1
- * grid (n_y nodes on [y_lo, y_hi]).  Node i of a grid is
- * lo + i * ((hi - lo) / (n - 1)) in binary64. */
+ * grid (n_y nodes on [y_lo, y_hi]), 2 <= n_x, n_y <= 2^24.  Node i of a
+ * grid is lo + i * ((hi - lo) / (n - 1)) in binary64. */
 typedef struct ucp_problem {
   double k;
   int32_t n_comp;

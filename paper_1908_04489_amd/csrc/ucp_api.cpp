@@ -46,7 +46,8 @@ int check_problem(const ucp_problem* p) {
   }
   if (std::fabs(ws - 1.0) > 1e-9) return fail(UCP_EINVAL, "prior weights must sum to 1 (got %.17g)", ws);
   if (p->n_x < 2 || p->n_y < 2) return fail(UCP_EINVAL, "grids need at least 2 nodes");
-  if (p->n_x > (int64_t)1 << 28 || p->n_y > (int64_t)1 << 28) return fail(UCP_EINVAL, "grid too large");
+  // per-wave work counters are 32-bit sums of up to 64 windows of at most n_y nodes
+  if (p->n_x > (int64_t)1 << 24 || p->n_y > (int64_t)1 << 24) return fail(UCP_EINVAL, "grid too large (more than 2^24 nodes)");
   if (!(p->x_lo < p->x_hi) || !std::isfinite(p->x_lo) || !std::isfinite(p->x_hi))
     return fail(UCP_EINVAL, "x grid needs finite x_lo < x_hi");
   if (!(p->y_lo < p->y_hi) || !std::isfinite(p->y_lo) || !std::isfinite(p->y_hi))

@@ -54,6 +54,45 @@ __device__ __forceinline__ double wave_min_d(double v) {
   for (int o = kWave / 2; o > 0; o >>= 1) v = fmin(v, __shfl_xor(v, o));
   return v;
 }
+// Reductions over a wave whose 64 lanes are all active, through DPP lane
+// moves (no LDS traffic): quad swaps and row mirrors reduce each row of 16,
+// two row broadcasts fold the rows into lane 63, whose value is returned to
+// every lane (the sum's order is fixed, so its bits are reproducible).
+template <int CTRL, int ROWS>
+__device__ __forceinline__ int dpp_mov(int v) {
+  return __builtin_amdgcn_update_dpp(v, v, CTRL, ROWS, 0xF, false);
+}
+template <int CTRL, int ROWS>
+__device__ __forceinline__ double dpp_mov_d(double v) {
+  const int lo = dpp_mov<CTRL, ROWS>(__double2loint(v));
+  const int hi = dpp_mov<CTRL, ROWS>(__double2hiint(v));
+  return __hiloint2double(hi, lo);
+}
+template <typename T, typename Op>
+__device__ __forceinline__ T dpp_reduce(T v, Op op) {
+  if constexpr (sizeof(T) == 8) {
+    v = op(v, dpp_mov_d<0xB1, 0xF>(v));   // quad_perm [1,0,3,2]
+    v = op(v, dpp_mov_d<0x4E, 0xF>(v));   // quad_perm [2,3,0,1]
+    v = op(v, dpp_mov_d<0x141, 0xF>(v));  // row_half_mirror
+    v = op(v, dpp_mov_d<0x140, 0xF>(v));  // row_mirror
+    v = op(v, dpp_mov_d<0x142, 0xA>(v));  // row_bcast:15 into rows 1, 3
+    v = op(v, dpp_mov_d<0x143, 0xC>(v));  // row_bcast:31 into rows 2, 3
+    return __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(v), 63),
+                            __builtin_amdgcn_readlane(__double2loint(v), 63));
+  } else {
+    v = op(v, dpp_mov<0xB1, 0xF>(v));
+    v = op(v, dpp_mov<0x4E, 0xF>(v));
+    v = op(v, dpp_mov<0x141, 0xF>(v));
+    v = op(v, dpp_mov<0x140, 0xF>(v));
+    v = op(v, dpp_mov<0x142, 0xA>(v));
+    v = op(v, dpp_mov<0x143, 0xC>(v));
+    return __builtin_amdgcn_readlane(v, 63);
+  }
+}
+__device__ __forceinline__ double wred_sum_d(double v) {
+  return dpp_reduce(v, [](double a, double b) { return a + b; });
+}
+
 // Butterfly sum: every lane ends with the same bits (each step adds the same
 // two values, and IEEE addition is commutative).
 __device__ __forceinline__ double wave_sum_d(double v) {
@@ -175,7 +214,7 @@ __device__ double b64_wave(const Inst& I, double z, int lane) {
     w.g *= w.r;
     w.r *= q;
   }
-  const double s = wave_sum_d(s0 + s1);
+  const double s = wred_sum_d(s0 + s1);
   return I.phi_scale * exp(-0.5 * delta * delta) * s;
 }
 
@@ -262,7 +301,7 @@ __device__ void b64_multi(const Inst& I, const double* z, int lane, double* out)
     }
   }
 #pragma unroll
-  for (int q = 0; q < R; ++q) out[q] = I.phi_scale * exp(-0.5 * delta[q] * delta[q]) * wave_sum_d(s[q]);
+  for (int q = 0; q < R; ++q) out[q] = I.phi_scale * exp(-0.5 * delta[q] * delta[q]) * wred_sum_d(s[q]);
 }
 
 // Algorithmic terms of one (point, candidate): the y nodes within kWin32
@@ -527,7 +566,7 @@ __global__ __launch_bounds__(kMcBlock) void k_mc32(Launch L, int level) {
   constexpr bool KAHAN = PREC == UCP_FP32_KAHAN;
   constexpr int NW = kMcBlock / kWave;
   __shared__ float sv[kMcLds];
-  __shared__ int sred[4][NW];
+  __shared__ int sred[2][NW];
   __shared__ double szr[2][NW];
   const int u = blockIdx.x;
   const int b = find_inst(L.pre, L.n_inst, u);
@@ -570,26 +609,20 @@ __global__ __launch_bounds__(kMcBlock) void k_mc32(Launch L, int level) {
   const bool ne = wlo <= whi;
   const int jlo = wave_min_i(ne ? jr + wlo : INT_MAX);
   const int jhi = wave_max_i(ne ? jr + whi : INT_MIN);
-  const int klw = wave_min_i(ne ? wlo : INT_MAX);
-  const int khw = wave_max_i(ne ? whi : INT_MIN);
   const double zlo = wave_min_d(ne ? z : INFINITY);
   const double zhi = -wave_min_d(ne ? -z : INFINITY);
   if (lane == 0) {
     sred[0][wid] = jlo;
     sred[1][wid] = jhi;
-    sred[2][wid] = klw;
-    sred[3][wid] = khw;
     szr[0][wid] = zlo;
     szr[1][wid] = zhi;
   }
   __syncthreads();
-  int blo = INT_MAX, bhi = INT_MIN, bklo = INT_MAX, bkhi = INT_MIN;
+  int blo = INT_MAX, bhi = INT_MIN;
   double bzlo = INFINITY, bzhi = -INFINITY;
   for (int w = 0; w < NW; ++w) {
     blo = min(blo, sred[0][w]);
     bhi = max(bhi, sred[1][w]);
-    bklo = min(bklo, sred[2][w]);
-    bkhi = max(bkhi, sred[3][w]);
     bzlo = fmin(bzlo, szr[0][w]);
     bzhi = fmax(bzhi, szr[1][w]);
   }
