@@ -118,7 +118,8 @@ Inst make_inst(const ucp_problem& p, const ucp_search* s, int prec, int cands_ov
     const int tiles = (I.n_x + kMcBlock - 1) / kMcBlock;
     const int kq = I.cands + 1;
     const int wlen = 2 * I.nw32 + 1;
-    int want = (8192 + tiles * kq - 1) / (tiles * kq);
+    const int wpb = kMcBlock / 64;  // waves per work unit
+    int want = (32768 + tiles * kq * wpb - 1) / (tiles * kq * wpb);  // about 32768 waves per launch
     int cap = std::max(1, wlen / 256);
     int sg = 1;
     while (sg < want && sg < 16) sg <<= 1;
@@ -137,7 +138,7 @@ size_t state_bytes(const Inst& I) {
   size_t b = 0;
   b += 9 * align_up(nx * 8);                                      // u0 u0_next f logf cbest b32best b64best b32inc jrow
   b += align_up(ny * 8) + align_up(ny * 4);                       // u1 v
-  b += align_up((size_t)(2 * I.nw32 + 1) * 4);                     // gtab
+  b += align_up((size_t)(2 * I.nw32 + 1 + kGtabPad) * 4);          // gtab (padded past the window)
   b += align_up(nx * (size_t)(I.cands + 3) * 8);                   // ev
   b += align_up(nx * (size_t)(I.cands + 3) * sizeof(EvalItem));    // items
   b += align_up(nx * 4) + 256;                                     // pend, nitems
@@ -165,7 +166,7 @@ void carve_state(Inst& I, char*& base) {
   I.jrow = (double*)take(nx * 8);
   I.u1 = (double*)take(ny * 8);
   I.v = (float*)take(ny * 4);
-  I.gtab = (float*)take((size_t)(2 * I.nw32 + 1) * 4);
+  I.gtab = (float*)take((size_t)(2 * I.nw32 + 1 + kGtabPad) * 4);
   I.ev = (double*)take(nx * (size_t)(I.cands + 3) * 8);
   I.items = (EvalItem*)take(nx * (size_t)(I.cands + 3) * sizeof(EvalItem));
   I.pend = (int32_t*)take(nx * 4);

@@ -15,8 +15,9 @@ constexpr int kMaxLevels = UCP_MAX_LEVELS;
 constexpr int kMaxComp = UCP_MAX_COMP;
 constexpr int kWave = 64;
 constexpr int kMcBlock = 256;   // marginal-cost kernel: one lane per point, 4 waves
-constexpr int kMcLds = 4096;    // FP32 residual nodes staged in LDS per block (16 KiB)
+constexpr int kMcLds = 8192;    // FP32 nodes staged in LDS per block (32 KiB)
 constexpr int kMcSegMax = 2048; // longest window segment of one marginal-cost work unit
+constexpr int kGtabPad = 16;    // offset-table entries past the window (>= the marginal-cost unroll)
 constexpr double kMcRefHalf = 1.0;
 constexpr double kMcBetaMax = 4.0; // blocked sums only where weights change by <= 2^4 per node  // reference form when every z of a block is within this of z_c
 constexpr int kSelWaves = 16;   // selection kernels: one wave per point ...
@@ -79,7 +80,7 @@ struct Inst {
   double* u0_next;           // updated first controller [n_x]
   double* u1;                // second controller [n_y]
   float* v;                  // alpha * (y_j - u1_j), FP32 [n_y]
-  float* gtab;               // exp(-(k dy)^2 / 2) for |k| <= nw32, FP32 [2 nw32 + 1]
+  float* gtab;               // exp(-(k dy)^2 / 2) for -nw32 <= k <= nw32 + kGtabPad, FP32
   double* f;                 // prior density at x nodes [n_x]
   double* logf;              // its logarithm [n_x]
   double* cbest;             // best candidate so far [n_x]

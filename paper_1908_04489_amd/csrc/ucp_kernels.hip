@@ -354,12 +354,12 @@ __global__ __launch_bounds__(256) void k_gtab(Launch L) {
   const int b = find_inst(L.pre, L.n_inst, u);
   const Inst& I = L.insts[b];
   const int k = (u - L.pre[b]) * 256 + (int)threadIdx.x - I.nw32;
-  if (k > I.nw32) return;
+  if (k > I.nw32 + kGtabPad) return;  // padded past the window for the last block's reads
   const double d = (double)k * I.dy;
   I.gtab[k + I.nw32] = (float)exp(-0.5 * d * d);
 }
 
-int32_t units_gtab(const Inst& I) { return (2 * I.nw32 + 1 + 255) / 256; }
+int32_t units_gtab(const Inst& I) { return (2 * I.nw32 + 1 + kGtabPad + 255) / 256; }
 
 hipError_t launch_prior(const Launch& L, hipStream_t st) {
   if (L.total == 0) return hipSuccess;
@@ -412,6 +412,7 @@ __device__ __forceinline__ void kahan_add(float x, float& acc, float& comp) {
 }
 
 constexpr int kMcUnroll = 16;
+static_assert(kGtabPad >= kMcUnroll, "the offset table covers the last block's reads");
 
 // Per-lane constants of one unit.
 struct McLane {
@@ -477,8 +478,10 @@ template <bool KAHAN, bool REF>
 __device__ __forceinline__ void mc_second(const McBlk& B, const float* e, float kf, const McLane& c, float& acc,
                                           float& comp) {
   // |beta| <= kMcBetaMax for every lane that reaches the blocked loops, so
-  // every factor here stays within FP32 range
-  const float E0 = __builtin_amdgcn_exp2f(c.beta * kf);
+  // in a block holding a term of the lane's window beta k <= 79 at most; a
+  // masked block before the window can have beta k beyond FP32 range, and
+  // the cap keeps its zero sum from meeting an infinite factor
+  const float E0 = __builtin_amdgcn_exp2f(fminf(c.beta * kf, 126.0f));
   float b0 = 0.0f, b1 = 0.0f;
 #pragma unroll
   for (int m = 0; m < kMcUnroll; m += 2) {
@@ -561,6 +564,52 @@ __device__ __forceinline__ void mc_lane(P v, Q G, int klo, int khi, const McLane
   mc_masked<KAHAN, REF>(v, G, kc_hi + 1, ku_hi, klo, khi, c, acc, comp);
 }
 
+// One block of kMcUnroll offsets from k, each term kept only where the
+// offset lies in the lane's [lo, hi] (the others are zeroed through their
+// difference).  Reads k .. k + kMcUnroll - 1, which may run past the
+// window: the staged array and the offset table are padded for that.
+template <bool KAHAN, bool REF, typename P, typename Q>
+__device__ __forceinline__ void mc_block_masked(P v, Q G, int k, int lo, int hi, const McLane& c, float& acc,
+                                                float& comp) {
+  McBlk B;
+  mc_load(B, v, G, k);
+  float e[kMcUnroll];
+  mc_first<REF>(B, (float)k, c, e);
+#pragma unroll
+  for (int m = 0; m < kMcUnroll; ++m)
+    if (!(k + m >= lo && k + m <= hi)) e[m] = 0.0f;
+  mc_second<KAHAN, REF>(B, e, (float)k, c, acc, comp);
+}
+
+// Offsets [a, b] in masked blocks; the lane keeps [max(a, klo), min(b, khi)].
+template <bool KAHAN, bool REF, typename P, typename Q>
+__device__ __forceinline__ void mc_region_masked(P v, Q G, int a, int b, int klo, int khi, const McLane& c,
+                                                 float& acc, float& comp) {
+  const int lo = max(a, klo), hi = min(b, khi);
+  for (int k = a; k <= b; k += kMcUnroll) mc_block_masked<KAHAN, REF>(v, G, k, lo, hi, c, acc, comp);
+}
+
+// The lane's window [klo, khi] from a staged, padded array: the offsets
+// common to every non-empty lane of the wave ([kc_lo, kc_hi]) run in the
+// unrolled loop, its last partial block and the ragged ends of the wave's
+// union [ku_lo, ku_hi] in masked blocks (the ragged ends are long where a
+// wave straddles a jump of the controller next to the grid's edge).
+template <bool KAHAN, bool REF, typename P, typename Q>
+__device__ __forceinline__ void mc_lane_padded(P v, Q G, int klo, int khi, int kc_lo, int kc_hi, int ku_lo,
+                                               int ku_hi, const McLane& c, float& acc, float& comp) {
+  // a lane with an empty window takes no part (its node range is not staged)
+  if (ku_lo > ku_hi || klo > khi) return;
+  if (kc_lo > kc_hi) {
+    mc_region_masked<KAHAN, REF>(v, G, ku_lo, ku_hi, klo, khi, c, acc, comp);
+    return;
+  }
+  mc_region_masked<KAHAN, REF>(v, G, ku_lo, kc_lo - 1, klo, khi, c, acc, comp);
+  const int nfull = (kc_hi - kc_lo + 1) / kMcUnroll * kMcUnroll;
+  if (nfull) mc_bulk<KAHAN, REF>(v, G, kc_lo, kc_lo + nfull - 1, c, acc, comp);
+  mc_region_masked<KAHAN, REF>(v, G, kc_lo + nfull, kc_hi, klo, khi, c, acc, comp);
+  mc_region_masked<KAHAN, REF>(v, G, kc_hi + 1, ku_hi, klo, khi, c, acc, comp);
+}
+
 template <int PREC>
 __global__ __launch_bounds__(kMcBlock) void k_mc32(Launch L, int level) {
   constexpr bool KAHAN = PREC == UCP_FP32_KAHAN;
@@ -604,16 +653,23 @@ __global__ __launch_bounds__(kMcBlock) void k_mc32(Launch L, int level) {
   const bool bigb = fabs(beta) > kMcBetaMax && klo <= khi;
   const int wlo = bigb ? 1 : klo, whi = bigb ? 0 : khi;
 
-  // node range, offset range and z range of the block, for LDS staging
+  // the wave's common and union offset ranges, and the node range it reads
+  // (staged in LDS with kMcUnroll - 1 nodes of padding past the union, zero
+  // beyond the grid), plus the z range of the block
   const int wid = threadIdx.x / kWave, lane = threadIdx.x % kWave;
   const bool ne = wlo <= whi;
-  const int jlo = wave_min_i(ne ? jr + wlo : INT_MAX);
-  const int jhi = wave_max_i(ne ? jr + whi : INT_MIN);
+  const int kc_lo = __builtin_amdgcn_readfirstlane(wave_max_i(ne ? wlo : INT_MIN));
+  const int kc_hi = __builtin_amdgcn_readfirstlane(wave_min_i(ne ? whi : INT_MAX));
+  const int ku_lo = __builtin_amdgcn_readfirstlane(wave_min_i(ne ? wlo : INT_MAX));
+  const int ku_hi = __builtin_amdgcn_readfirstlane(wave_max_i(ne ? whi : INT_MIN));
+  const int jmin = wave_min_i(ne ? jr : INT_MAX);
+  const int jmax = wave_max_i(ne ? jr : INT_MIN);
+  const bool wne = ku_lo <= ku_hi;  // some lane of the wave has offsets
   const double zlo = wave_min_d(ne ? z : INFINITY);
   const double zhi = -wave_min_d(ne ? -z : INFINITY);
   if (lane == 0) {
-    sred[0][wid] = jlo;
-    sred[1][wid] = jhi;
+    sred[0][wid] = wne ? jmin + ku_lo : INT_MAX;
+    sred[1][wid] = wne ? jmax + ku_hi + (kMcUnroll - 1) : INT_MIN;
     szr[0][wid] = zlo;
     szr[1][wid] = zhi;
   }
@@ -639,9 +695,10 @@ __global__ __launch_bounds__(kMcBlock) void k_mc32(Launch L, int level) {
   const bool ref = staged && bzhi - bzlo <= 2.0 * kMcRefHalf;
   const double zc = 0.5 * (bzlo + bzhi);  // block-uniform
   if (ref)
-    for (int j = blo + (int)threadIdx.x; j <= bhi; j += kMcBlock) sv[j - blo] = (float)(alpha * (zc - I.u1[j]));
+    for (int j = blo + (int)threadIdx.x; j <= bhi; j += kMcBlock)
+      sv[j - blo] = j >= 0 && j < I.n_y ? (float)(alpha * (zc - I.u1[j])) : 0.0f;
   else if (staged)
-    for (int j = blo + (int)threadIdx.x; j <= bhi; j += kMcBlock) sv[j - blo] = I.v[j];
+    for (int j = blo + (int)threadIdx.x; j <= bhi; j += kMcBlock) sv[j - blo] = j >= 0 && j < I.n_y ? I.v[j] : 0.0f;
   __syncthreads();
 
   McLane cl;
@@ -664,10 +721,10 @@ __global__ __launch_bounds__(kMcBlock) void k_mc32(Launch L, int level) {
   cst_cptr G = (cst_cptr)(I.gtab + nw);
   if (ref) {
     lds_cptr v = (lds_cptr)(sv + (jr - blo));
-    mc_lane<KAHAN, true>(v, G, wlo, whi, cl, acc, comp);
+    mc_lane_padded<KAHAN, true>(v, G, wlo, whi, kc_lo, kc_hi, ku_lo, ku_hi, cl, acc, comp);
   } else if (staged) {
     lds_cptr v = (lds_cptr)(sv + (jr - blo));
-    mc_lane<KAHAN, false>(v, G, wlo, whi, cl, acc, comp);
+    mc_lane_padded<KAHAN, false>(v, G, wlo, whi, kc_lo, kc_hi, ku_lo, ku_hi, cl, acc, comp);
   } else {
     glb_cptr v = (glb_cptr)(I.v + jr);
     mc_lane<KAHAN, false>(v, G, wlo, whi, cl, acc, comp);
