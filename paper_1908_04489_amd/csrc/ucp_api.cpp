@@ -126,6 +126,7 @@ Inst make_inst(const ucp_problem& p, const ucp_search* s, int prec, int cands_ov
     sg = std::max(1, std::min(sg, cap));
     I.segs = std::max(sg, (wlen + kMcSegMax - 1) / kMcSegMax);
   }
+  // at most 32 slices (the combine kernel's lane groups take 32)
   const int slen = std::max(512, (I.n_x + 31) / 32);
   I.u1_slices = (I.n_x + slen - 1) / slen;
   return I;
@@ -140,7 +141,7 @@ size_t state_bytes(const Inst& I) {
   b += align_up(ny * 8) + align_up(ny * 4);                       // u1 v
   b += align_up((size_t)(2 * I.nw32 + 1 + kGtabPad) * 4);          // gtab (padded past the window)
   b += align_up(nx * (size_t)(I.cands + 3) * 8);                   // ev
-  b += align_up(nx * (size_t)(I.cands + 3) * sizeof(EvalItem));    // items
+  b += align_up(nx * (size_t)eval_row_cap(I.cands) * sizeof(EvalItem));  // items
   b += align_up(nx * 4) + 256;                                     // pend, nitems
   b += align_up(nx * (size_t)(I.cands + 1) * (size_t)I.segs * 8); // part
   b += align_up((size_t)I.u1_slices * ny * 3 * 8);                // u1part
@@ -168,7 +169,7 @@ void carve_state(Inst& I, char*& base) {
   I.v = (float*)take(ny * 4);
   I.gtab = (float*)take((size_t)(2 * I.nw32 + 1 + kGtabPad) * 4);
   I.ev = (double*)take(nx * (size_t)(I.cands + 3) * 8);
-  I.items = (EvalItem*)take(nx * (size_t)(I.cands + 3) * sizeof(EvalItem));
+  I.items = (EvalItem*)take(nx * (size_t)eval_row_cap(I.cands) * sizeof(EvalItem));
   I.pend = (int32_t*)take(nx * 4);
   I.nitems = (int32_t*)take(256);
   I.part = (double*)take(nx * (size_t)(I.cands + 1) * (size_t)I.segs * 8);

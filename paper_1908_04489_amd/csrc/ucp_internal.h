@@ -18,10 +18,13 @@ constexpr int kMcBlock = 256;   // marginal-cost kernel: one lane per point, 4 w
 constexpr int kMcLds = 8192;    // FP32 nodes staged in LDS per block (32 KiB)
 constexpr int kMcSegMax = 2048; // longest window segment of one marginal-cost work unit
 constexpr int kGtabPad = 16;    // offset-table entries past the window (>= the marginal-cost unroll)
-constexpr double kMcRefHalf = 1.0;
+// reference form when every z of a block lies within this of the block's
+// centre: wide enough for the jumps of a point's best candidate on the
+// coarse level-0 grid within a block, narrow enough that the staged
+// differences round no worse than the residual form's
+constexpr double kMcRefHalf = 2.5;
 constexpr double kMcBetaMax = 4.0; // blocked sums only where weights change by <= 2^4 per node  // reference form when every z of a block is within this of z_c
-constexpr int kSelWaves = 16;   // selection kernels: one wave per point ...
-constexpr int kSelPts = 1;      // ... for kSelPts consecutive points in turn
+constexpr int kSelWaves = 16;   // selection kernels: waves per block
 constexpr int kEvalWaves = 4;   // queue-draining kernel: one wave per queued sum
 constexpr int kU1Block = 256;   // u1 kernels: one lane per y node
 constexpr int kU1Chunk = 512;   // x nodes staged in LDS per step of the u1 sums
@@ -39,7 +42,9 @@ constexpr double kTau32Plain = 5e-6;
 constexpr double kKappa32 = 6e-7;
 constexpr double kTau64 = 1e-12;// FP64 tie band (relative)
 constexpr double kWin32 = 9.0;  // window half-width, noise sds (FP32 terms)
-constexpr double kWin64 = 10.0; // window half-width, noise sds (FP64 terms)
+// FP64 window half-width, noise sds: the dropped tail sums to below 1e-16
+// of B (B >= the unit noise variance, and the tail is ~2 phi(9) (9 + v^2/9))
+constexpr double kWin64 = 9.0;
 // Device counters (spread over slots on separate cache lines): algorithmic
 // marginal-cost terms and FP64 tie re-evaluations.
 constexpr int kCountSlots = 32, kCountStride = 16, kCountTerms = 0, kCountEvalTerms = 4, kCountEvals = 8;
@@ -53,6 +58,11 @@ struct EvalItem {
 };
 
 constexpr int kEvalBlocks = 2048;  // grid of the queue-draining kernel
+// A point's queued sums take a whole number of chunks of kEvalChunk entries
+// (padding entries have i = -1), so the chunks, and the positions that share
+// one pass over their windows, depend on the point alone.
+constexpr int kEvalChunk = 4;
+inline int eval_row_cap(int cands) { return (cands + 3 + kEvalChunk - 1) / kEvalChunk * kEvalChunk; }
 
 // One solve instance as the kernels see it: constants of the problem and the
 // search, launch geometry, and device pointers to its state.
@@ -91,14 +101,18 @@ struct Inst {
   double* u1part;            // u1 partial sums [u1_slices][n_y][3]
   double* jrow;              // per-point objective terms [n_x]
   double* ev;                // FP64 results of queued sums [n_x][cands + 3]
-  EvalItem* items;           // queue of FP64 sums [n_x (cands + 3)]
+  EvalItem* items;           // queue of FP64 sums [n_x eval_row_cap(cands)]
   int32_t* nitems;           // queue length
-  int32_t* pend;             // per point: 0 decided, 1 level band queued, 2 incumbent comparison queued
+  int32_t* pend;             // per point: 0 decided, else the kind of its queued sums (1, 2 or 3)
   double* J_out;             // objective output (one double)
   double* L0_out;            // optional FP64 L_0 of the accepted u0 [n_x] (argmin call only)
   int32_t* flags;            // bit 0: non-finite value met
   unsigned long long* terms; // counters [kCountSlots][kCountStride] (NULL: not counted)
 };
+
+// Lanes per point in the selection kernels: two points per wave when the
+// level's set and the incumbent (cands + 2 lanes) fit in half a wave.
+__host__ __device__ inline int sel_width(const Inst& I) { return I.cands + 2 <= 32 ? 32 : 64; }
 
 // alpha^2 = log2(e) / 2, so exp(-t^2 / 2) = exp2(-(alpha t)^2).
 constexpr double kAlpha2 = 0.72134752044448170367996234050095;  // log2(e)/2

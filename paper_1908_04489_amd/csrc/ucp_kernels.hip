@@ -100,6 +100,18 @@ __device__ __forceinline__ double wave_sum_d(double v) {
   return v;
 }
 
+// Sum over a group of W lanes (the whole wave, or an aligned half): DPP for
+// a whole wave, a butterfly within the half otherwise.
+template <int W>
+__device__ __forceinline__ double grp_sum_d(double v) {
+  if constexpr (W == kWave) {
+    return wred_sum_d(v);
+  } else {
+    for (int o = W / 2; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    return v;
+  }
+}
+
 __device__ __forceinline__ double clampd(double v, double lo, double hi) {
   return v < lo ? lo : (v > hi ? hi : v);
 }
@@ -124,17 +136,18 @@ __device__ __forceinline__ int nearest_node(const Inst& I, double z) {
   return (int)jf;
 }
 
-// FP64 window sum for one position z, spread over the 64 lanes of a wave:
+// FP64 window sum for one position z, spread over a group of W lanes (a
+// wave, or in the selection kernels possibly an aligned half of one):
 // returns dy/sqrt(2 pi) * sum_j phi(y_j - z) (z - u1_j)^2 over the nodes
 // within kWin64 of the node nearest z.  The Gaussian is max-shifted to that
 // node, g_k = exp(-(t_k^2 - delta^2)/2) = exp(-d (d + 2 delta)/2) with
 // d = k dy, and the shift exp(-delta^2/2) is applied once at the end.
-// Lane l takes k = klo + l + 64 m; along m the Gaussian obeys the exact
-// recurrence g_{k+64} = g_k r_k, r_{k+64} = r_k q with
-// r_k = exp(-64 dy t_k - (64 dy)^2 / 2) and q = exp(-(64 dy)^2), so two
+// Lane l takes k = klo + l + W m; along m the Gaussian obeys the exact
+// recurrence g_{k+W} = g_k r_k, r_{k+W} = r_k q with
+// r_k = exp(-W dy t_k - (W dy)^2 / 2) and q = exp(-(W dy)^2), so two
 // multiplies replace an exp; both are recomputed by exp every kReseed steps,
 // which bounds the relative error of any weight by ~kReseed^2/2 ulp
-// (5.7e-14).  Every lane has a node in the first floor(n/64) steps: they run
+// (5.7e-14).  Every lane has a node in the first floor(n/W) steps: they run
 // without masks in groups of kPrefetch, the loads of group g + 1 issued
 // before group g is summed (two register buffers); only the last step can be
 // partial.  Even steps go to one accumulator and odd steps to another.
@@ -147,8 +160,9 @@ struct B64Walk {
   double g, r;  // weight of the lane's next node and its ratio
 };
 
+template <int W>
 __device__ __forceinline__ void b64_reseed(B64Walk& w, int klo, int lane, int m, double dy, double delta, double D) {
-  const double d = (double)(klo + lane + kWave * m) * dy;
+  const double d = (double)(klo + lane + W * m) * dy;
   w.g = exp(-0.5 * d * (d + 2.0 * delta));
   w.r = exp(-D * (d + delta) - 0.5 * D * D);
 }
@@ -168,53 +182,54 @@ __device__ __forceinline__ void b64_group(const double* uv, double z, double q, 
   }
 }
 
+template <int W = kWave>
 __device__ double b64_wave(const Inst& I, double z, int lane) {
   const int jr = nearest_node(I, z);
   const double delta = (I.y_lo + (double)jr * I.dy) - z;
   // 0 <= jr <= n_y - 1, so klo <= 0 <= khi and the window is never empty
   const int klo = max(-I.nw64, -jr), khi = min(I.nw64, I.n_y - 1 - jr);
   const int n = khi - klo + 1;
-  const double dy = I.dy, D = (double)kWave * dy;
+  const double dy = I.dy, D = (double)W * dy;
   const double q = exp(-D * D);
-  glb_dptr u1 = (glb_dptr)(I.u1 + jr + klo + lane);  // this lane's node of step m: u1[64 m]
+  glb_dptr u1 = (glb_dptr)(I.u1 + jr + klo + lane);  // this lane's node of step m: u1[W m]
   double s0 = 0.0, s1 = 0.0;
-  const int steps = (n + kWave - 1) / kWave;
-  const int groups = (n / kWave) / kPrefetch;  // unmasked groups
+  const int steps = (n + W - 1) / W;
+  const int groups = (n / W) / kPrefetch;  // unmasked groups
   B64Walk w;
   double ua[kPrefetch], ub[kPrefetch];
   if (groups > 0) {
 #pragma unroll
-    for (int mm = 0; mm < kPrefetch; ++mm) ua[mm] = u1[kWave * mm];
+    for (int mm = 0; mm < kPrefetch; ++mm) ua[mm] = u1[W * mm];
   }
   int gi = 0;
   for (; gi + 2 <= groups; gi += 2) {
     const int m = gi * kPrefetch;
 #pragma unroll
-    for (int mm = 0; mm < kPrefetch; ++mm) ub[mm] = u1[kWave * (m + kPrefetch + mm)];
-    if (m % kReseed == 0) b64_reseed(w, klo, lane, m, dy, delta, D);
+    for (int mm = 0; mm < kPrefetch; ++mm) ub[mm] = u1[W * (m + kPrefetch + mm)];
+    if (m % kReseed == 0) b64_reseed<W>(w, klo, lane, m, dy, delta, D);
     b64_group(ua, z, q, w, s0, s1);
     // the group after next, or (past the end, unused) the last one: in range
     const int mn = min(m + 2 * kPrefetch, (groups - 1) * kPrefetch);
 #pragma unroll
-    for (int mm = 0; mm < kPrefetch; ++mm) ua[mm] = u1[kWave * (mn + mm)];
-    if ((m + kPrefetch) % kReseed == 0) b64_reseed(w, klo, lane, m + kPrefetch, dy, delta, D);
+    for (int mm = 0; mm < kPrefetch; ++mm) ua[mm] = u1[W * (mn + mm)];
+    if ((m + kPrefetch) % kReseed == 0) b64_reseed<W>(w, klo, lane, m + kPrefetch, dy, delta, D);
     b64_group(ub, z, q, w, s0, s1);
   }
   if (gi < groups) {  // one group left, already loaded
     const int m = gi * kPrefetch;
-    if (m % kReseed == 0) b64_reseed(w, klo, lane, m, dy, delta, D);
+    if (m % kReseed == 0) b64_reseed<W>(w, klo, lane, m, dy, delta, D);
     b64_group(ua, z, q, w, s0, s1);
   }
   for (int m = groups * kPrefetch; m < steps; ++m) {  // the rest, the last step possibly partial
-    if (m % kReseed == 0) b64_reseed(w, klo, lane, m, dy, delta, D);
+    if (m % kReseed == 0) b64_reseed<W>(w, klo, lane, m, dy, delta, D);
     double e = 0.0;
-    if (lane + kWave * m < n) e = z - u1[kWave * m];
+    if (lane + W * m < n) e = z - u1[W * m];
     if (m & 1) s1 = fma(w.g * e, e, s1);
     else s0 = fma(w.g * e, e, s0);
     w.g *= w.r;
     w.r *= q;
   }
-  const double s = wred_sum_d(s0 + s1);
+  const double s = grp_sum_d<W>(s0 + s1);
   return I.phi_scale * exp(-0.5 * delta * delta) * s;
 }
 
@@ -223,8 +238,9 @@ __device__ double b64_wave(const Inst& I, double z, int lane) {
 // a small bracket): each lane's u1 load serves all R sums.  Per position the
 // same shifted Gaussian and reseeded recurrence as b64_wave, relative to its
 // own nearest node; nodes of the union beyond a position's own window add
-// weights below exp(-50).  One accumulator per position.
-template <int R>
+// weights below exp(-40) (terms of the dense sum all the same).  One
+// accumulator per position.
+template <int R, int W = kWave>
 __device__ void b64_multi(const Inst& I, const double* z, int lane, double* out) {
   int jr[R];
   double delta[R];
@@ -237,16 +253,16 @@ __device__ void b64_multi(const Inst& I, const double* z, int lane, double* out)
     jhi = max(jhi, min(I.n_y - 1, jr[q] + I.nw64));
   }
   const int n = jhi - jlo + 1;
-  const double dy = I.dy, D = (double)kWave * dy;
+  const double dy = I.dy, D = (double)W * dy;
   const double qf = exp(-D * D);
-  glb_dptr u1 = (glb_dptr)(I.u1 + jlo + lane);  // this lane's node of step m: u1[64 m]
+  glb_dptr u1 = (glb_dptr)(I.u1 + jlo + lane);  // this lane's node of step m: u1[W m]
   double g[R], r[R], s[R];
 #pragma unroll
   for (int q = 0; q < R; ++q) s[q] = 0.0;
   auto reseed = [&](int m) {
 #pragma unroll
     for (int q = 0; q < R; ++q) {
-      const double d = (double)(jlo + lane + kWave * m - jr[q]) * dy;
+      const double d = (double)(jlo + lane + W * m - jr[q]) * dy;
       g[q] = exp(-0.5 * d * (d + 2.0 * delta[q]));
       r[q] = exp(-D * (d + delta[q]) - 0.5 * D * D);
     }
@@ -263,23 +279,23 @@ __device__ void b64_multi(const Inst& I, const double* z, int lane, double* out)
       }
     }
   };
-  const int steps = (n + kWave - 1) / kWave;
-  const int groups = (n / kWave) / kPrefetch;  // unmasked groups
+  const int steps = (n + W - 1) / W;
+  const int groups = (n / W) / kPrefetch;  // unmasked groups
   double ua[kPrefetch], ub[kPrefetch];
   if (groups > 0) {
 #pragma unroll
-    for (int mm = 0; mm < kPrefetch; ++mm) ua[mm] = u1[kWave * mm];
+    for (int mm = 0; mm < kPrefetch; ++mm) ua[mm] = u1[W * mm];
   }
   int gi = 0;
   for (; gi + 2 <= groups; gi += 2) {
     const int m = gi * kPrefetch;
 #pragma unroll
-    for (int mm = 0; mm < kPrefetch; ++mm) ub[mm] = u1[kWave * (m + kPrefetch + mm)];
+    for (int mm = 0; mm < kPrefetch; ++mm) ub[mm] = u1[W * (m + kPrefetch + mm)];
     if (m % kReseed == 0) reseed(m);
     group(ua);
     const int mn = min(m + 2 * kPrefetch, (groups - 1) * kPrefetch);
 #pragma unroll
-    for (int mm = 0; mm < kPrefetch; ++mm) ua[mm] = u1[kWave * (mn + mm)];
+    for (int mm = 0; mm < kPrefetch; ++mm) ua[mm] = u1[W * (mn + mm)];
     if ((m + kPrefetch) % kReseed == 0) reseed(m + kPrefetch);
     group(ub);
   }
@@ -290,8 +306,8 @@ __device__ void b64_multi(const Inst& I, const double* z, int lane, double* out)
   }
   for (int m = groups * kPrefetch; m < steps; ++m) {
     if (m % kReseed == 0) reseed(m);
-    const bool in = lane + kWave * m < n;
-    const double u = in ? u1[kWave * m] : 0.0;
+    const bool in = lane + W * m < n;
+    const double u = in ? u1[W * m] : 0.0;
 #pragma unroll
     for (int q = 0; q < R; ++q) {
       const double e = in ? z[q] - u : 0.0;
@@ -301,7 +317,7 @@ __device__ void b64_multi(const Inst& I, const double* z, int lane, double* out)
     }
   }
 #pragma unroll
-  for (int q = 0; q < R; ++q) out[q] = I.phi_scale * exp(-0.5 * delta[q] * delta[q]) * wred_sum_d(s[q]);
+  for (int q = 0; q < R; ++q) out[q] = I.phi_scale * exp(-0.5 * delta[q] * delta[q]) * grp_sum_d<W>(s[q]);
 }
 
 // Algorithmic terms of one (point, candidate): the y nodes within kWin32
@@ -430,8 +446,8 @@ struct McLane {
 //  - reference form (REF = true): s_j = alpha (z_c - u1_j) around one z_c per
 //    block, e = s_j + a with a = alpha (z - z_c).  Used when every z of the
 //    block lies within kMcRefHalf of z_c, where its rounding error (<= ulp
-//    of |a| and of |e|) is no larger than the residual form's (<= ulp of
-//    alpha |y_j - z|, a few units over the weighted nodes).  In the unrolled
+//    of |a| <= 2.1 and of |e|) is no larger than the residual form's (<= ulp
+//    of alpha |y_j - z|, a few units over the weighted nodes).  In the unrolled
 //    blocks the term's factor R_m = exp2(beta m) is folded into the
 //    difference: R_m e^2 = e'^2 with e' = fma(sqrt R_m, s_j, sqrt R_m a), so
 //    a term costs one fma, one multiply and one fma.
@@ -838,19 +854,51 @@ __global__ __launch_bounds__(256) void k_mc_finish(Launch L, double* out, int pr
 // ------------------------------------------------------------- selection
 //
 // Three kernels per level:
-//   k_band     one wave per point.  Lane q holds candidate q of the level
+//   k_band     one group of W lanes per point: a wave (W = 64), or, where
+//              the level's set and the incumbent fit in 32 lanes
+//              (cands + 2 <= 32), an aligned half-wave (W = 32, two points
+//              per wave).  Lane q of the group holds candidate q of the level
 //              (lane `cands` the best so far, or at level 0 the incumbent,
 //              whose FP32-path B is kept for the final comparison).  FP32
 //              minimum and tie band; a one-member band (and FP64 mode)
 //              decides at once, otherwise the members without an FP64 value
 //              are queued.  On the last level a decided point runs the
 //              comparison with the incumbent the same way.
-//   k_eval     drains the queues: one FP64 window sum per wave, a fixed grid
-//              at full occupancy whatever the number of items.
+//   k_eval     drains the queues (whole waves): a fixed grid at full
+//              occupancy whatever the number of items.
 //   k_resolve  the queued points: the selection rule on the FP64 values, and
 //              on the last level the comparison with the incumbent.
+// Every cross-lane step of the group kernels (minimum, ballot, shuffle)
+// reads lanes of its own group only, and every branch depends on values
+// uniform over the group, so the two groups of a wave may take different
+// paths.  W is a function of the instance alone.
 
-int32_t units_select(const Inst& I) { return (I.n_x + kSelWaves * kSelPts - 1) / (kSelWaves * kSelPts); }
+__device__ __forceinline__ int pad_chunk(int n) { return (n + kEvalChunk - 1) / kEvalChunk * kEvalChunk; }
+
+int32_t units_select(const Inst& I) {
+  const int pts = kSelWaves * (kWave / sel_width(I));  // points per block
+  return (I.n_x + pts - 1) / pts;
+}
+
+template <int W>
+__device__ __forceinline__ int grp_base() {
+  return W == kWave ? 0 : ((int)threadIdx.x % kWave) / W * W;
+}
+template <int W>
+__device__ __forceinline__ unsigned long long grp_ballot(bool p) {
+  const unsigned long long b = __ballot(p);
+  if constexpr (W == kWave) return b;
+  else return (b >> grp_base<W>()) & ((1ull << W) - 1ull);
+}
+template <int W, typename T>
+__device__ __forceinline__ T grp_shfl(T v, int l) {
+  return __shfl(v, grp_base<W>() + l);
+}
+template <int W>
+__device__ __forceinline__ double grp_min_d(double v) {
+  for (int o = W / 2; o > 0; o >>= 1) v = fmin(v, __shfl_xor(v, o));
+  return v;
+}
 
 // Slots of the per-point FP64 results: 0..cands-1 level candidates, `cands`
 // the best so far, then the two members of the incumbent comparison.
@@ -860,15 +908,17 @@ __device__ __forceinline__ double* ev_row(const Inst& I, int i) { return I.ev + 
 
 // The selection rule on FP64 values among the lanes with `member`: ties
 // within kTau64 of the minimum, the one nearest the incumbent wins, then the
-// smaller u, then the lower lane.  Returns the lane (0 if there is none).
+// smaller u, then the lower lane.  Returns the group lane (0 if there is
+// none).
+template <int W>
 __device__ int tie_rule(bool member, double c, double Bf, double uinc, int lane) {
   const double big = INFINITY;
-  const double m = wave_min_d(member ? Bf : big);
+  const double m = grp_min_d<W>(member ? Bf : big);
   const bool band = member && Bf <= m * (1.0 + kTau64);
   double k1 = band ? fabs(c - uinc) : big;
   double k2 = band ? c : big;
   int k3 = band ? lane : INT_MAX;
-  for (int o = kWave / 2; o > 0; o >>= 1) {
+  for (int o = W / 2; o > 0; o >>= 1) {
     const double o1 = __shfl_xor(k1, o), o2 = __shfl_xor(k2, o);
     const int o3 = __shfl_xor(k3, o);
     const bool take = (o1 < k1) || (o1 == k1 && (o2 < k2 || (o2 == k2 && o3 < k3)));
@@ -880,13 +930,14 @@ __device__ int tie_rule(bool member, double c, double Bf, double uinc, int lane)
 // FP32 tie band over the lanes with `in_set`: B32 <= m (1 + tau) + kappa
 // sqrt(m), tau covering the relative error of the weights and the sum and
 // kappa sqrt(m) the rounding of z - u1 (|dB| grows like sqrt(B)).  Returns
-// the member mask (0 when no candidate is finite).
+// the member mask over the group (0 when no candidate is finite).
+template <int W>
 __device__ unsigned long long band32(bool in_set, double B32, int prec) {
   const bool fin = in_set && isfinite(B32);
-  const double m32 = wave_min_d(fin ? B32 : INFINITY);
+  const double m32 = grp_min_d<W>(fin ? B32 : INFINITY);
   if (!(m32 < INFINITY)) return 0ull;
   const double tau = prec == UCP_FP32_KAHAN ? kTau32Kahan : kTau32Plain;
-  return __ballot(fin && B32 <= m32 * (1.0 + tau) + kKappa32 * sqrt(m32));
+  return grp_ballot<W>(fin && B32 <= m32 * (1.0 + tau) + kKappa32 * sqrt(m32));
 }
 
 // This lane's candidate of the level: position, FP32-path B and (FP64 mode,
@@ -919,19 +970,40 @@ __device__ __forceinline__ void count_evals(const Inst& I, int n) {
 
 // Points whose decision needs FP64 window sums are queued: kind 1 = the
 // level's band members (slot = lane), kind 2 = the comparison of the
-// level's winner (slot cands + 1) with the incumbent (slot cands + 2).
+// level's winner (slot cands + 1) with the incumbent (slot cands + 2),
+// kind 3 = on the last level, the band members and (lane cands + 1) the
+// incumbent, whose sum the comparison that follows may need.
 struct Queued {
-  unsigned long long todo;  // lanes whose sum is needed
+  unsigned long long todo;  // group lanes whose sum is needed
   int kind;                 // 0: nothing queued
   double c;                 // this lane's position
 };
 
 __device__ __forceinline__ int queued_slot(const Inst& I, int kind, int lane) {
-  return kind == 1 ? lane : (lane == 0 ? slot_best(I) : slot_inc(I));
+  if (kind == 2) return lane == 0 ? slot_best(I) : slot_inc(I);
+  return kind == 3 && lane == I.cands + 1 ? slot_inc(I) : lane;
 }
 
+// The FP64 value of the incumbent where a lane of the set sits at its
+// position with a known FP64 value (the carried best often does), else NaN.
+template <int W>
+__device__ __forceinline__ double inc_from_set(bool in_set, double c, double B64, double uinc) {
+  const unsigned long long m = grp_ballot<W>(in_set && c == uinc && !isnan(B64));
+  return m ? grp_shfl<W>(B64, __ffsll((long long)m) - 1) : NAN;
+}
+
+// Whether the FP32 band of the pair {b0, b1} (as band32 forms it) holds both.
+__device__ __forceinline__ bool pair_band_both(double b0, double b1, int prec) {
+  if (!isfinite(b0) || !isfinite(b1)) return false;
+  const double m = fmin(b0, b1);
+  const double tau = prec == UCP_FP32_KAHAN ? kTau32Kahan : kTau32Plain;
+  const double lim = m * (1.0 + tau) + kKappa32 * sqrt(m);
+  return b0 <= lim && b1 <= lim;
+}
+
+template <int W>
 __device__ void finish_point(const Inst& I, int i, double res, double Bres, double x, int lane, int want_l0) {
-  if (want_l0 && isnan(Bres)) Bres = I.k2 * res * res + b64_wave(I, x + res, lane);
+  if (want_l0 && isnan(Bres)) Bres = I.k2 * res * res + b64_wave<W>(I, x + res, lane);
   if (lane == 0) {
     I.u0_next[i] = res;
     if (!isfinite(res)) atomicOr(I.flags, 1);
@@ -939,40 +1011,41 @@ __device__ void finish_point(const Inst& I, int i, double res, double Bres, doub
   }
 }
 
-// Comparison of the level's winner (cw, B32w, B64w) with the incumbent.  In
-// k_band (inline_eval = false) a two-member band is queued (returned in Q);
-// in k_resolve the missing FP64 sums are evaluated in place.
-template <int PREC>
-__device__ void accept(const Inst& I, int i, double x, double uinc, double cw, double B32w, double B64w, int lane,
-                       bool inline_eval, int want_l0, int& n_eval, Queued& Q) {
+// Comparison of the level's winner (cw, B32w, B64w) with the incumbent
+// (B64i its FP64 value where known).  In k_band (inline_eval = false) a
+// two-member band is queued (returned in Q); in k_resolve missing FP64 sums
+// are evaluated in place.
+template <int PREC, int W>
+__device__ void accept(const Inst& I, int i, double x, double uinc, double cw, double B32w, double B64w, double B64i,
+                       int lane, bool inline_eval, int want_l0, int& n_eval, Queued& Q) {
   if (cw == uinc) {
-    finish_point(I, i, uinc, B64w, x, lane, want_l0);
+    finish_point<W>(I, i, uinc, B64w, x, lane, want_l0);
     return;
   }
   const double B32i = I.b32inc[i];
   const bool in2 = lane < 2;
   const double c2 = lane == 0 ? cw : uinc;
   const double b32 = lane == 0 ? B32w : B32i;
-  double b64 = lane == 0 ? B64w : (PREC == UCP_FP64 ? B32i : NAN);
+  double b64 = lane == 0 ? B64w : (PREC == UCP_FP64 ? B32i : B64i);
   if (PREC == UCP_FP64) {
     const bool fin = in2 && isfinite(b32);
-    const int w = tie_rule(fin, c2, b32, uinc, lane);
-    if (__ballot(fin) == 0ull && lane == 0) atomicOr(I.flags, 1);
-    finish_point(I, i, __shfl(c2, w), __shfl(b64, w), x, lane, want_l0);
+    const int w = tie_rule<W>(fin, c2, b32, uinc, lane);
+    if (grp_ballot<W>(fin) == 0ull && lane == 0) atomicOr(I.flags, 1);
+    finish_point<W>(I, i, grp_shfl<W>(c2, w), grp_shfl<W>(b64, w), x, lane, want_l0);
     return;
   }
-  const unsigned long long mask = band32(in2, b32, PREC);
+  const unsigned long long mask = band32<W>(in2, b32, PREC);
   if (mask == 0ull) {
     if (lane == 0) atomicOr(I.flags, 1);
-    finish_point(I, i, uinc, NAN, x, lane, want_l0);
+    finish_point<W>(I, i, uinc, NAN, x, lane, want_l0);
     return;
   }
   if (__popcll(mask) == 1) {
     const int w = __ffsll((long long)mask) - 1;
-    finish_point(I, i, __shfl(c2, w), __shfl(b64, w), x, lane, want_l0);
+    finish_point<W>(I, i, grp_shfl<W>(c2, w), grp_shfl<W>(b64, w), x, lane, want_l0);
     return;
   }
-  const unsigned long long todo = __ballot(in2 && isnan(b64));
+  const unsigned long long todo = grp_ballot<W>(in2 && isnan(b64));
   if (!inline_eval && todo) {
     Q.todo = todo;
     Q.kind = 2;
@@ -980,30 +1053,27 @@ __device__ void accept(const Inst& I, int i, double x, double uinc, double cw, d
     return;
   }
   if (todo == 3ull) {  // both: one pass over their windows
-    const double c0 = __shfl(c2, 0), c1 = __shfl(c2, 1);
+    const double c0 = grp_shfl<W>(c2, 0), c1 = grp_shfl<W>(c2, 1);
     const double z[2] = {x + c0, x + c1};
     double v[2];
-    b64_multi<2>(I, z, lane, v);
+    b64_multi<2, W>(I, z, lane, v);
     if (lane == 0) b64 = I.k2 * c0 * c0 + v[0];
     if (lane == 1) b64 = I.k2 * c1 * c1 + v[1];
     n_eval += 2;
   } else if (todo) {
     const int L = __ffsll((long long)todo) - 1;
-    const double cl = __shfl(c2, L);
-    const double v = I.k2 * cl * cl + b64_wave(I, x + cl, lane);
+    const double cl = grp_shfl<W>(c2, L);
+    const double v = I.k2 * cl * cl + b64_wave<W>(I, x + cl, lane);
     if (lane == L) b64 = v;
     ++n_eval;
   }
-  const int w = tie_rule(in2, c2, b64, uinc, lane);
-  finish_point(I, i, __shfl(c2, w), __shfl(b64, w), x, lane, want_l0);
+  const int w = tie_rule<W>(in2, c2, b64, uinc, lane);
+  finish_point<W>(I, i, grp_shfl<W>(c2, w), grp_shfl<W>(b64, w), x, lane, want_l0);
 }
 
 // One point of k_band: decide it, or return in Q the FP64 sums it needs.
-template <int PREC>
+template <int PREC, int W>
 __device__ void band_point(const Inst& I, int level, int i, int lane, int want_l0, int& n_eval, Queued& Q) {
-  Q.todo = 0ull;
-  Q.kind = 0;
-  Q.c = 0.0;
   const int K = I.cands;
   const double uinc = I.u0[i];
   const double x = I.x_lo + (double)i * I.dx;
@@ -1014,57 +1084,78 @@ __device__ void band_point(const Inst& I, int level, int i, int lane, int want_l
   int w;
   if (PREC == UCP_FP64) {
     const bool fin = in_set && isfinite(B32);
-    if (__ballot(fin) == 0ull && lane == 0) atomicOr(I.flags, 1);
-    w = tie_rule(fin, c, B32, uinc, lane);
+    if (grp_ballot<W>(fin) == 0ull && lane == 0) atomicOr(I.flags, 1);
+    w = tie_rule<W>(fin, c, B32, uinc, lane);
   } else {
-    const unsigned long long mask = band32(in_set, B32, PREC);
+    const unsigned long long mask = band32<W>(in_set, B32, PREC);
     if (mask == 0ull) {
       if (lane == 0) atomicOr(I.flags, 1);
       w = 0;
     } else if (__popcll(mask) == 1) {
       w = __ffsll((long long)mask) - 1;
     } else {
-      const unsigned long long todo = __ballot(((mask >> lane) & 1ull) && isnan(B64));
+      const bool member = (mask >> lane) & 1ull;
+      const unsigned long long todo = grp_ballot<W>(member && isnan(B64));
       if (todo) {  // FP64 sums needed: k_resolve decides
         Q.todo = todo;
         Q.kind = 1;
         Q.c = c;
+        // last level: if the incumbent could share the FP32 band of the
+        // winner, whichever member wins, its sum is queued too, so the
+        // comparison in k_resolve evaluates nothing itself.  (An incumbent
+        // that is itself a member, as the carried best, gets its FP64 value
+        // as a member.)
+        if (level == I.levels - 1 && K + 1 < W && !grp_ballot<W>(member && c == uinc)) {
+          const double b32i = I.b32inc[i];
+          if (grp_ballot<W>(member && pair_band_both(B32, b32i, PREC))) {
+            Q.todo |= 1ull << (K + 1);
+            Q.kind = 3;
+            if (lane == K + 1) Q.c = uinc;
+          }
+        }
         return;
       }
-      w = tie_rule((mask >> lane) & 1ull, c, B64, uinc, lane);
+      w = tie_rule<W>(member, c, B64, uinc, lane);
     }
   }
-  const double cw = __shfl(c, w), B32w = __shfl(B32, w), B64w = __shfl(B64, w);
+  const double cw = grp_shfl<W>(c, w), B32w = grp_shfl<W>(B32, w), B64w = grp_shfl<W>(B64, w);
   if (lane == 0) {
     I.cbest[i] = cw;
     I.b32best[i] = B32w;
     I.b64best[i] = B64w;
   }
-  if (level == I.levels - 1) accept<PREC>(I, i, x, uinc, cw, B32w, B64w, lane, false, want_l0, n_eval, Q);
+  if (level == I.levels - 1) {
+    const double B64i = inc_from_set<W>(in_set, c, B64, uinc);
+    accept<PREC, W>(I, i, x, uinc, cw, B32w, B64w, B64i, lane, false, want_l0, n_eval, Q);
+  }
 }
 
-// Each wave takes kSelPts consecutive points; the block reserves queue
-// space for all of them with one atomic.
-template <int PREC>
-__global__ __launch_bounds__(kSelWaves * kWave) void k_band(Launch L, int level, int want_l0) {
+// Block body of k_band: each group takes one point; the block reserves
+// queue space for all of them with one atomic.  A point's entries are
+// padded to a whole number of chunks.
+template <int PREC, int W>
+__device__ void band_block(const Inst& I, int local, int level, int want_l0) {
+  constexpr int G = kWave / W;  // points per wave
   __shared__ int s_cnt[kSelWaves];
   __shared__ int s_base;
-  const int u = blockIdx.x;
-  const int b = find_inst(L.pre, L.n_inst, u);
-  const Inst& I = L.insts[b];
-  const int wid = threadIdx.x / kWave, lane = threadIdx.x % kWave;
-  const int i0 = ((u - L.pre[b]) * kSelWaves + wid) * kSelPts;
-  Queued Q[kSelPts];
-  int n_eval = 0, cnt = 0;
-#pragma unroll
-  for (int p = 0; p < kSelPts; ++p) {
-    Q[p].todo = 0ull;
-    Q[p].kind = 0;
-    Q[p].c = 0.0;
-    if (i0 + p < I.n_x) band_point<PREC>(I, level, i0 + p, lane, want_l0, n_eval, Q[p]);
-    cnt += __popcll(Q[p].todo);
+  const int wid = threadIdx.x / kWave, lane = (int)threadIdx.x % W, g = ((int)threadIdx.x % kWave) / W;
+  const int i = (local * kSelWaves + wid) * G + g;
+  Queued Q;
+  Q.todo = 0ull;
+  Q.kind = 0;
+  Q.c = 0.0;
+  int n_eval = 0;
+  if (i < I.n_x) band_point<PREC, W>(I, level, i, lane, want_l0, n_eval, Q);
+  // this group's entries, and (two groups) the wave's total and the group's
+  // offset within the wave
+  const int mine = pad_chunk(__popcll(Q.todo));
+  int cnt = mine, before = 0;
+  if constexpr (G == 2) {
+    const int other = __shfl_xor(mine, W);
+    cnt = mine + other;
+    before = g == 1 ? other : 0;
   }
-  if (lane == 0) s_cnt[wid] = cnt;
+  if (threadIdx.x % kWave == 0) s_cnt[wid] = cnt;
   __syncthreads();
   if (threadIdx.x == 0) {
     int tot = 0;
@@ -1072,32 +1163,42 @@ __global__ __launch_bounds__(kSelWaves * kWave) void k_band(Launch L, int level,
     s_base = tot ? atomicAdd(I.nitems, tot) : 0;
   }
   __syncthreads();
-  if (cnt) {
-    int base = s_base;
+  const unsigned long long todo = Q.todo;
+  if (todo) {
+    int base = s_base + before;
     for (int w = 0; w < wid; ++w) base += s_cnt[w];
-#pragma unroll
-    for (int p = 0; p < kSelPts; ++p) {
-      const unsigned long long todo = Q[p].todo;
-      if (!todo) continue;
-      if ((todo >> lane) & 1ull) {
-        EvalItem it;
-        it.i = i0 + p;
-        it.slot = queued_slot(I, Q[p].kind, lane);
-        it.c = Q[p].c;
-        I.items[base + __popcll(todo & ((1ull << lane) - 1ull))] = it;
-      }
-      if (lane == 0) I.pend[i0 + p] = Q[p].kind;
-      base += __popcll(todo);
+    const int nq = __popcll(todo), np = pad_chunk(nq);
+    if ((todo >> lane) & 1ull) {
+      EvalItem it;
+      it.i = i;
+      it.slot = queued_slot(I, Q.kind, lane);
+      it.c = Q.c;
+      I.items[base + __popcll(todo & ((1ull << lane) - 1ull))] = it;
     }
+    if (lane >= nq && lane < np) {
+      EvalItem it;
+      it.i = -1;
+      it.slot = 0;
+      it.c = 0.0;
+      I.items[base + lane] = it;
+    }
+    if (lane == 0) I.pend[i] = Q.kind;
   }
   if (lane == 0) count_evals(I, n_eval);
 }
 
-// Drains the queue of every instance: each wave takes kEvalChunk
-// consecutive items; the queued candidates of one point are contiguous, so
-// the chunk's items of one point share one pass over their windows.
-constexpr int kEvalChunk = 4;
+template <int PREC>
+__global__ __launch_bounds__(kSelWaves * kWave) void k_band(Launch L, int level, int want_l0) {
+  const int u = blockIdx.x;
+  const int b = find_inst(L.pre, L.n_inst, u);
+  const Inst& I = L.insts[b];
+  if (sel_width(I) == 32) band_block<PREC, 32>(I, u - L.pre[b], level, want_l0);
+  else band_block<PREC, kWave>(I, u - L.pre[b], level, want_l0);
+}
 
+// Drains the queue of every instance: each wave takes a chunk of
+// kEvalChunk entries, all of one point, whose positions share one pass over
+// their windows.
 __global__ __launch_bounds__(kEvalWaves * kWave) void k_eval(Launch L) {
   const int wid = threadIdx.x / kWave, lane = threadIdx.x % kWave;
   const int gw = blockIdx.x * kEvalWaves + wid, nw = gridDim.x * kEvalWaves;
@@ -1108,55 +1209,49 @@ __global__ __launch_bounds__(kEvalWaves * kWave) void k_eval(Launch L) {
     const int nch = (n + kEvalChunk - 1) / kEvalChunk;
     int done = 0;
     for (int ch = gw; ch < nch; ch += nw) {
-      const int e_end = min(n, (ch + 1) * kEvalChunk);
-      for (int p = ch * kEvalChunk; p < e_end;) {
-        const EvalItem it0 = I.items[p];
-        int cnt = 1;
-        while (p + cnt < e_end && I.items[p + cnt].i == it0.i) ++cnt;
-        const double x = I.x_lo + (double)it0.i * I.dx;
-        double c[kEvalChunk], z[kEvalChunk], v[kEvalChunk];
-        int slot[kEvalChunk];
+      EvalItem it[kEvalChunk];
 #pragma unroll
-        for (int q = 0; q < kEvalChunk; ++q) {
-          const EvalItem it = I.items[p + min(q, cnt - 1)];
-          c[q] = it.c;
-          slot[q] = it.slot;
-          z[q] = x + it.c;
-        }
-        if (cnt == 1) v[0] = b64_wave(I, z[0], lane);
-        else if (cnt == 2) b64_multi<2>(I, z, lane, v);
-        else if (cnt == 3) b64_multi<3>(I, z, lane, v);
-        else b64_multi<4>(I, z, lane, v);
-        if (lane == 0) {
-          double* row = ev_row(I, it0.i);
+      for (int q = 0; q < kEvalChunk; ++q) it[q] = I.items[ch * kEvalChunk + q];
+      int cnt = 0;  // valid entries lead the chunk
 #pragma unroll
-          for (int q = 0; q < kEvalChunk; ++q)
-            if (q < cnt) row[slot[q]] = I.k2 * c[q] * c[q] + v[q];
-        }
-        done += cnt;
-        p += cnt;
+      for (int q = 0; q < kEvalChunk; ++q) cnt += it[q].i >= 0;
+      if (cnt == 0) continue;
+      const double x = I.x_lo + (double)it[0].i * I.dx;
+      double z[kEvalChunk], v[kEvalChunk];
+#pragma unroll
+      for (int q = 0; q < kEvalChunk; ++q) z[q] = x + (q < cnt ? it[q].c : it[0].c);  // static indices only
+      if (cnt == 1) v[0] = b64_wave(I, z[0], lane);
+      else if (cnt == 2) b64_multi<2>(I, z, lane, v);
+      else if (cnt == 3) b64_multi<3>(I, z, lane, v);
+      else b64_multi<4>(I, z, lane, v);
+      if (lane == 0) {
+        double* row = ev_row(I, it[0].i);
+#pragma unroll
+        for (int q = 0; q < kEvalChunk; ++q)
+          if (q < cnt) row[it[q].slot] = I.k2 * it[q].c * it[q].c + v[q];
       }
+      done += cnt;
     }
     if (lane == 0) count_evals(I, done);
   }
 }
 
-template <int PREC>
+template <int PREC, int W>
 __device__ void resolve_point(const Inst& I, int level, int i, int lane, int want_l0, int& n_eval) {
   const int pend = I.pend[i];
   if (pend == 0) return;
   const double uinc = I.u0[i];
   const double x = I.x_lo + (double)i * I.dx;
   const double* evr = ev_row(I, i);
-  if (pend == 1) {
+  if (pend != 2) {
     double c, B32, B64;
     bool in_set;
     level_view<PREC>(I, level, i, lane, c, B32, B64, in_set);
-    const unsigned long long mask = band32(in_set, B32, PREC);
+    const unsigned long long mask = band32<W>(in_set, B32, PREC);
     const bool member = (mask >> lane) & 1ull;
     if (member && isnan(B64)) B64 = evr[lane];
-    const int w = tie_rule(member, c, B64, uinc, lane);
-    const double cw = __shfl(c, w), B32w = __shfl(B32, w), B64w = __shfl(B64, w);
+    const int w = tie_rule<W>(member, c, B64, uinc, lane);
+    const double cw = grp_shfl<W>(c, w), B32w = grp_shfl<W>(B32, w), B64w = grp_shfl<W>(B64, w);
     if (lane == 0) {
       I.cbest[i] = cw;
       I.b32best[i] = B32w;
@@ -1165,7 +1260,9 @@ __device__ void resolve_point(const Inst& I, int level, int i, int lane, int wan
     }
     if (level == I.levels - 1) {
       Queued Q;
-      accept<PREC>(I, i, x, uinc, cw, B32w, B64w, lane, true, want_l0, n_eval, Q);
+      double B64i = inc_from_set<W>(in_set, c, B64, uinc);
+      if (pend == 3 && isnan(B64i)) B64i = evr[slot_inc(I)];
+      accept<PREC, W>(I, i, x, uinc, cw, B32w, B64w, B64i, lane, true, want_l0, n_eval, Q);
     }
   } else {
     // the queued incumbent comparison: lane 0 the winner, lane 1 the incumbent
@@ -1174,12 +1271,22 @@ __device__ void resolve_point(const Inst& I, int level, int i, int lane, int wan
     const double c2 = lane == 0 ? cw : uinc;
     const double b32 = lane == 0 ? I.b32best[i] : I.b32inc[i];
     double b64 = lane == 0 ? (isnan(B64w) ? evr[slot_best(I)] : B64w) : evr[slot_inc(I)];
-    const unsigned long long mask = band32(in2, b32, PREC);
+    const unsigned long long mask = band32<W>(in2, b32, PREC);
     const bool member = (mask >> lane) & 1ull;
-    const int w = tie_rule(member, c2, b64, uinc, lane);
-    finish_point(I, i, __shfl(c2, w), __shfl(b64, w), x, lane, want_l0);
+    const int w = tie_rule<W>(member, c2, b64, uinc, lane);
+    finish_point<W>(I, i, grp_shfl<W>(c2, w), grp_shfl<W>(b64, w), x, lane, want_l0);
     if (lane == 0) I.pend[i] = 0;
   }
+}
+
+template <int PREC, int W>
+__device__ void resolve_block(const Inst& I, int local, int level, int want_l0) {
+  constexpr int G = kWave / W;
+  const int wid = threadIdx.x / kWave, lane = (int)threadIdx.x % W, g = ((int)threadIdx.x % kWave) / W;
+  const int i = (local * kSelWaves + wid) * G + g;
+  int n_eval = 0;
+  if (i < I.n_x) resolve_point<PREC, W>(I, level, i, lane, want_l0, n_eval);
+  if (lane == 0) count_evals(I, n_eval);
 }
 
 template <int PREC>
@@ -1188,11 +1295,8 @@ __global__ __launch_bounds__(kSelWaves * kWave) void k_resolve(Launch L, int lev
   const int b = find_inst(L.pre, L.n_inst, u);
   const Inst& I = L.insts[b];
   if (u == L.pre[b] && threadIdx.x == 0) *I.nitems = 0;  // the queue has been drained
-  const int wid = threadIdx.x / kWave, lane = threadIdx.x % kWave;
-  const int i0 = ((u - L.pre[b]) * kSelWaves + wid) * kSelPts;
-  int n_eval = 0;
-  for (int p = 0; p < kSelPts && i0 + p < I.n_x; ++p) resolve_point<PREC>(I, level, i0 + p, lane, want_l0, n_eval);
-  if (lane == 0) count_evals(I, n_eval);
+  if (sel_width(I) == 32) resolve_block<PREC, 32>(I, u - L.pre[b], level, want_l0);
+  else resolve_block<PREC, kWave>(I, u - L.pre[b], level, want_l0);
 }
 
 hipError_t launch_select(const Launch& L, int level, int prec, int want_l0, hipStream_t st, hipEvent_t e0,
@@ -1225,7 +1329,11 @@ hipError_t launch_select(const Launch& L, int level, int prec, int want_l0, hipS
 // the combine kernel merges the slices in a fixed order.
 
 int32_t units_u1_partial(const Inst& I) { return ((I.n_y + kU1Block - 1) / kU1Block) * I.u1_slices; }
-int32_t units_u1_combine(const Inst& I) { return (I.n_y + kU1Block - 1) / kU1Block; }
+// The combine gives each y node a group of kU1Grp lanes, lane g taking the
+// slices g, g + kU1Grp, ... (at most 32 slices), so a block covers
+// kU1Block / kU1Grp nodes.
+constexpr int kU1Grp = 8;
+int32_t units_u1_combine(const Inst& I) { return (I.n_y + kU1Block / kU1Grp - 1) / (kU1Block / kU1Grp); }
 
 template <int PREC>
 __global__ __launch_bounds__(kU1Block) void k_u1_partial(Launch L) {
@@ -1312,18 +1420,42 @@ __global__ __launch_bounds__(kU1Block) void k_u1_combine(Launch L) {
   const int u = blockIdx.x;
   const int b = find_inst(L.pre, L.n_inst, u);
   const Inst& I = L.insts[b];
-  const int j = (u - L.pre[b]) * kU1Block + (int)threadIdx.x;
-  if (j >= I.n_y) return;
-  double M = -INFINITY;
-  for (int s = 0; s < I.u1_slices; ++s) M = fmax(M, I.u1part[((size_t)s * I.n_y + j) * 3]);
-  double num = 0.0, den = 0.0;
-  for (int s = 0; s < I.u1_slices; ++s) {
-    const double* p = I.u1part + ((size_t)s * I.n_y + j) * 3;
-    if (!(p[0] > -INFINITY)) continue;
-    const double r = exp(p[0] - M);
-    num += p[1] * r;
-    den += p[2] * r;
+  const int g = (int)threadIdx.x % kU1Grp;
+  const int j = (u - L.pre[b]) * (kU1Block / kU1Grp) + (int)threadIdx.x / kU1Grp;
+  const bool act = j < I.n_y;
+  const int jj = act ? j : I.n_y - 1;
+  constexpr int kPer = 32 / kU1Grp;  // slices per lane
+  double pm[kPer], pn[kPer], pd[kPer];
+#pragma unroll
+  for (int t = 0; t < kPer; ++t) {
+    const int s = g + t * kU1Grp;
+    pm[t] = -INFINITY;
+    pn[t] = pd[t] = 0.0;
+    if (s < I.u1_slices) {
+      const double* p = I.u1part + ((size_t)s * I.n_y + jj) * 3;
+      pm[t] = p[0];
+      pn[t] = p[1];
+      pd[t] = p[2];
+    }
   }
+  double M = pm[0];
+#pragma unroll
+  for (int t = 1; t < kPer; ++t) M = fmax(M, pm[t]);
+  for (int o = 1; o < kU1Grp; o <<= 1) M = fmax(M, __shfl_xor(M, o));
+  double num = 0.0, den = 0.0;
+#pragma unroll
+  for (int t = 0; t < kPer; ++t) {
+    if (!(pm[t] > -INFINITY)) continue;
+    const double r = exp(pm[t] - M);
+    num += pn[t] * r;
+    den += pd[t] * r;
+  }
+  // fixed pairing over the group: the same order for every node and launch
+  for (int o = 1; o < kU1Grp; o <<= 1) {
+    num += __shfl_xor(num, o);
+    den += __shfl_xor(den, o);
+  }
+  if (!act || g != 0) return;
   const double y = I.y_lo + (double)j * I.dy;
   const double vres = num / den;
   const double u1 = y - vres;

@@ -60,6 +60,9 @@ CASES = {
                              W.init_random_steps(W.Problem(0.3, [(1, 0, 3)], -20, 22, 777, -24, 26, 1201), 4.0, 7)),
     "tiny": lambda: W.Case("tiny", W.gaussian_problem(0.2, 5.0, 21, 25.0), W.Search(-30, 30, 2, 5), 3,
                            W.init_sign(W.gaussian_problem(0.2, 5.0, 21, 25.0), 5.0)),
+    # more candidates than half a wave holds: the selection runs one point per wave
+    "wide": lambda: W.Case("wide-k40", W.gaussian_problem(0.2, 3.0, 401, 25.0), W.Search(-30, 30, 2, 40), 3,
+                           W.init_random_steps(W.gaussian_problem(0.2, 3.0, 401, 25.0), 3.0, 5)),
 }
 
 
@@ -185,7 +188,7 @@ def test_solve_is_deterministic_and_resumable(env):
 # ------------------------------------------------------- batch / serving
 
 def _mix():
-    out = [W.small_case(), CASES["ragged"](), CASES["tiny"]()]
+    out = [W.small_case(), CASES["ragged"](), CASES["tiny"](), CASES["wide"]()]
     p = W.gaussian_problem(0.1, 2.0, 4001, 25.0)
     out.append(W.Case("n4001", p, W.Search(-30, 30, 3, 21), 2, W.init_sign(p, 2.0), 2.0))
     return out
