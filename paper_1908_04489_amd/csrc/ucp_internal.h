@@ -28,6 +28,8 @@ constexpr int kSelWaves = 16;   // selection kernels: waves per block
 constexpr int kEvalWaves = 4;   // queue-draining kernel: one wave per queued sum
 constexpr int kU1Block = 256;   // u1 kernels: one lane per y node
 constexpr int kU1Chunk = 512;   // x nodes staged in LDS per step of the u1 sums
+constexpr int kU1Sample = 32;   // x-node stride of the sample bounding a tile's logit maximum
+constexpr double kU1Cull = 64.0; // chunks whose logits all lie this far below that bound are skipped
 constexpr int kJWaves = 4;      // objective: one wave ...
 constexpr int kJPts = 4;        // ... per kJPts consecutive x nodes
 // FP32 tie band B32 <= m (1 + tau) + kappa sqrt(m): tau covers the relative

@@ -1324,9 +1324,11 @@ hipError_t launch_select(const Launch& L, int level, int prec, int want_l0, hipS
 //
 // u1_j = y_j - v_j with v_j = sum_i w_ij d_ij / sum_i w_ij, d_ij = y_j - x1_i,
 // w_ij = exp(l_ij - M), l_ij = log f_i - d_ij^2 / 2 (the conditional mean
-// written around y_j so the numerator terms stay small).  Unit = (tile of
-// 256 y nodes, slice of x nodes); each slice keeps an online maximum M, and
-// the combine kernel merges the slices in a fixed order.
+// written around the y nodes so the numerator terms stay small).  Unit =
+// (tile of 256 y nodes, slice of x nodes); each slice keeps an online
+// maximum M, and the combine kernel merges the slices in a fixed order.
+// Chunks of x nodes whose weights are negligible for the whole tile are
+// skipped.
 
 int32_t units_u1_partial(const Inst& I) { return ((I.n_y + kU1Block - 1) / kU1Block) * I.u1_slices; }
 // The combine gives each y node a group of kU1Grp lanes, lane g taking the
@@ -1335,12 +1337,24 @@ int32_t units_u1_partial(const Inst& I) { return ((I.n_y + kU1Block - 1) / kU1Bl
 constexpr int kU1Grp = 8;
 int32_t units_u1_combine(const Inst& I) { return (I.n_y + kU1Block / kU1Grp - 1) / (kU1Block / kU1Grp); }
 
+// Block maximum of v (every thread gets it); `sw` holds one value per wave.
+__device__ __forceinline__ double block_max_d(double v, double* sw) {
+  for (int o = kWave / 2; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o));
+  if (threadIdx.x % kWave == 0) sw[threadIdx.x / kWave] = v;
+  __syncthreads();
+  v = sw[0];
+  for (int w = 1; w < (int)blockDim.x / kWave; ++w) v = fmax(v, sw[w]);
+  return v;
+}
+
 template <int PREC>
 __global__ __launch_bounds__(kU1Block) void k_u1_partial(Launch L) {
-  __shared__ double sx1[kU1Chunk];   // x1_i
-  __shared__ double sL[kU1Chunk];    // log2(e) log f_i
-  __shared__ float sx1f[kU1Chunk];   // x1_i in FP32 (maximum pass only)
-  __shared__ float slff[kU1Chunk];   // log f_i in FP32 (maximum pass only)
+  constexpr int NW = kU1Block / kWave;
+  __shared__ double sD[kU1Chunk];    // D_i = y_c - x1_i
+  __shared__ double sP[kU1Chunk];    // P_i = log2(e) (log f_i - D_i^2 / 2)
+  __shared__ float sDf[kU1Chunk];    // D_i in FP32 (maximum pass only)
+  __shared__ float sPf[kU1Chunk];    // log f_i - D_i^2 / 2 in FP32 (maximum pass only)
+  __shared__ double sb[4][NW];       // per-wave bounds
   const int u = blockIdx.x;
   const int b = find_inst(L.pre, L.n_inst, u);
   const Inst& I = L.insts[b];
@@ -1350,69 +1364,104 @@ __global__ __launch_bounds__(kU1Block) void k_u1_partial(Launch L) {
   const int j = tile * kU1Block + (int)threadIdx.x;
   const bool act = j < I.n_y;
   const double y = I.y_lo + (double)(act ? j : 0) * I.dy;
-  const float yf = (float)y;
   const int slen = (I.n_x + I.u1_slices - 1) / I.u1_slices;
   const int i0 = slice * slen, i1 = min(I.n_x, i0 + slen);
   const double log2e = 1.4426950408889634073599246810019;
   const double c2 = 0.5 * log2e;
-  double M = -INFINITY, den = 0.0, num64 = 0.0;
-  float num = 0.0f, comp = 0.0f;
+  // A lower bound on the logit maximum M_j of every node of the tile: any x
+  // node gives one, M_j >= l_ij >= log f_i - max over the tile's y of
+  // (y - x1_i)^2 / 2; every kU1Sample-th node is taken.
+  const int j0 = tile * kU1Block, j1 = min(I.n_y, j0 + kU1Block) - 1;
+  const double ya = I.y_lo + (double)j0 * I.dy, yb = I.y_lo + (double)j1 * I.dy;
+  double lb = -INFINITY;
+  for (int i = (int)threadIdx.x * kU1Sample; i < I.n_x; i += kU1Block * kU1Sample) {
+    const double x1 = (I.x_lo + (double)i * I.dx) + I.u0[i];
+    const double da = ya - x1, db = yb - x1;
+    lb = fmax(lb, I.logf[i] - 0.5 * fmax(da * da, db * db));  // NaN terms drop out
+  }
+  lb = block_max_d(lb, sb[0]);
+  // Around the middle node y_c of the tile, y_j - x1_i = eta_j + D_i with
+  // eta_j = y_j - y_c and D_i = y_c - x1_i, so the log2 weight
+  //   log2(e) (log f_i - (y_j - x1_i)^2 / 2 - M_j) = P_i + Q_j + E_j D_i,
+  // P_i = log2(e) (log f_i - D_i^2 / 2) staged per node, Q_j = -log2(e)
+  // (M_j + eta_j^2 / 2) and E_j = -log2(e) eta_j per lane: one add and one
+  // fma in FP64.  The FP64 numerator sums w D_i (one fma); eta_j times the
+  // denominator is added once at the end (sum_i w (y_j - x1_i) =
+  // sum_i w D_i + eta_j sum_i w).
+  const double yc = I.y_lo + (double)((j0 + j1) / 2) * I.dy;
+  const double eta = y - yc;
+  const double E = -log2e * eta;
+  const float etaf = (float)eta;
+  double M = -INFINITY, den = 0.0, num = 0.0;
   for (int c0 = i0; c0 < i1; c0 += kU1Chunk) {
     const int cn = min(kU1Chunk, i1 - c0);
     __syncthreads();
+    double xmn = INFINITY, xmx = -INFINITY, fmx = -INFINITY;
+    bool bad = false;
     for (int t = threadIdx.x; t < cn; t += kU1Block) {
       const int i = c0 + t;
       const double x1 = (I.x_lo + (double)i * I.dx) + I.u0[i];
       const double lf = I.logf[i];
-      sx1[t] = x1;
-      sL[t] = lf * log2e;
-      sx1f[t] = (float)x1;
-      slff[t] = (float)lf;
+      const double D = yc - x1;
+      const double Pn = lf - 0.5 * D * D;
+      sD[t] = D;
+      sP[t] = Pn * log2e;
+      sDf[t] = (float)D;
+      sPf[t] = (float)Pn;
+      xmn = fmin(xmn, x1);
+      xmx = fmax(xmx, x1);
+      fmx = fmax(fmx, lf);
+      bad |= !isfinite(x1) || isnan(lf);
+    }
+    // the chunk's largest possible logit over the tile's nodes:
+    // max log f - (distance from [ya, yb] to [min x1, max x1])^2 / 2
+    for (int o = kWave / 2; o > 0; o >>= 1) {
+      xmn = fmin(xmn, __shfl_xor(xmn, o));
+      xmx = fmax(xmx, __shfl_xor(xmx, o));
+      fmx = fmax(fmx, __shfl_xor(fmx, o));
+    }
+    const bool wbad = __ballot(bad) != 0ull;
+    if (threadIdx.x % kWave == 0) {
+      sb[1][threadIdx.x / kWave] = xmn;
+      sb[2][threadIdx.x / kWave] = xmx;
+      sb[3][threadIdx.x / kWave] = wbad ? NAN : fmx;
     }
     __syncthreads();
+    for (int w = 0; w < NW; ++w) {
+      xmn = fmin(xmn, sb[1][w]);
+      xmx = fmax(xmx, sb[2][w]);
+      fmx = fmax(fmx, sb[3][w]);
+      bad |= isnan(sb[3][w]);
+    }
+    const double dist = fmax(0.0, fmax(xmn - yb, ya - xmx));
+    // skipped weights are below exp(-kU1Cull) of the largest: none of the
+    // sums moves (n_x exp(-kU1Cull) < 2^-60)
+    if (!bad && fmx - 0.5 * dist * dist < lb - kU1Cull) continue;
     // chunk maximum of the logits, in FP32: only a shift, any value near
     // the maximum works (the sums below use exact FP64 exponents)
     float mcf = -INFINITY;
-    for (int t = 0; t < cn; ++t) {
-      const float d = yf - sx1f[t];
-      mcf = fmaxf(mcf, fmaf(-0.5f * d, d, slff[t]));
-    }
-    const double mc = (double)mcf;
+    for (int t = 0; t < cn; ++t) mcf = fmaxf(mcf, fmaf(-etaf, sDf[t], sPf[t]));
+    const double mc = (double)mcf - 0.5 * eta * eta;
     if (mc > M) {  // rescale what was summed under the old maximum
       const double r = M == -INFINITY ? 0.0 : exp(M - mc);
       den *= r;
-      if (PREC == UCP_FP64) num64 *= r;
-      else { num = (float)((double)num * r); comp = (float)((double)comp * r); }
+      num *= r;
       M = mc;
     }
     if (!(M > -INFINITY)) continue;  // every logit is -inf (or NaN): nothing to add
-    const double Ml = M * log2e;
+    const double Q = -log2e * M - c2 * eta * eta;
     for (int t = 0; t < cn; ++t) {
-      const double d = y - sx1[t];
-      const double a = fma(d, -c2 * d, sL[t] - Ml);  // log2 of the shifted weight
-      if (PREC == UCP_FP64) {
-        const double w = exp2(a);
-        num64 = fma(w, d, num64);
-        den += w;
-      } else {
-        const float w = __builtin_amdgcn_exp2f((float)a);
-        const float term = w * (float)d;
-        if (PREC == UCP_FP32_KAHAN) {
-          const float yy = term - comp;
-          const float tt = num + yy;
-          comp = (tt - num) - yy;
-          num = tt;
-        } else {
-          num += term;
-        }
-        den += (double)w;
-      }
+      const double a = fma(E, sD[t], sP[t] + Q);  // log2 of the shifted weight
+      // FP64 weight in FP64 mode, else the FP32 exp2 of the rounded exponent
+      const double w = PREC == UCP_FP64 ? exp2(a) : (double)__builtin_amdgcn_exp2f((float)a);
+      num = fma(w, sD[t], num);
+      den += w;
     }
   }
   if (!act) return;
   double* o = I.u1part + ((size_t)slice * I.n_y + j) * 3;
   o[0] = M;
-  o[1] = PREC == UCP_FP64 ? num64 : (double)num - (double)comp;
+  o[1] = num + eta * den;
   o[2] = den;
 }
 
