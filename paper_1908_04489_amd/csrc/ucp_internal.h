@@ -15,7 +15,9 @@ constexpr int kMaxLevels = UCP_MAX_LEVELS;
 constexpr int kMaxComp = UCP_MAX_COMP;
 constexpr int kWave = 64;
 constexpr int kMcBlock = 256;   // marginal-cost kernel: one lane per point, 4 waves
-constexpr int kMcLds = 8192;    // FP32 nodes staged in LDS per block (32 KiB)
+// FP32 nodes staged in LDS per block (40 KiB: with the block's other LDS,
+// four blocks fill a CU's 160 KiB, the occupancy the registers allow anyway)
+constexpr int kMcLds = 10208;
 constexpr int kMcSegMax = 2048; // longest window segment of one marginal-cost work unit
 constexpr int kGtabPad = 16;    // offset-table entries past the window (>= the marginal-cost unroll)
 // reference form when every z of a block lies within this of the block's
