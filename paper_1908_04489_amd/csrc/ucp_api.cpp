@@ -119,7 +119,7 @@ Inst make_inst(const ucp_problem& p, const ucp_search* s, int prec, int cands_ov
     const int kq = I.cands + 1;
     const int wlen = 2 * I.nw32 + 1;
     const int wpb = kMcBlock / 64;  // waves per work unit
-    int want = (32768 + tiles * kq * wpb - 1) / (tiles * kq * wpb);  // about 32768 waves per launch
+    int want = (16384 + tiles * kq * wpb - 1) / (tiles * kq * wpb);  // about 16384 waves per launch
     int cap = std::max(1, wlen / 256);
     int sg = 1;
     while (sg < want && sg < 16) sg <<= 1;

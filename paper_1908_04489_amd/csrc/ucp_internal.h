@@ -18,7 +18,9 @@ constexpr int kMcBlock = 256;   // marginal-cost kernel: one lane per point, 4 w
 // FP32 nodes staged in LDS per block (40 KiB: with the block's other LDS,
 // four blocks fill a CU's 160 KiB, the occupancy the registers allow anyway)
 constexpr int kMcLds = 10208;
-constexpr int kMcSegMax = 2048; // longest window segment of one marginal-cost work unit
+// longest window segment of one marginal-cost work unit (a block's stage,
+// 256 points plus a segment, still fits the LDS stage)
+constexpr int kMcSegMax = 8192;
 constexpr int kGtabPad = 16;    // offset-table entries past the window (>= the marginal-cost unroll)
 // reference form when every z of a block lies within this of the block's
 // centre: wide enough for the jumps of a point's best candidate on the
