@@ -710,11 +710,41 @@ __global__ __launch_bounds__(kMcBlock) void k_mc32(Launch L, int level) {
   const bool staged = bhi >= blo && bhi - blo + 1 <= kMcLds;
   const bool ref = staged && bzhi - bzlo <= 2.0 * kMcRefHalf;
   const double zc = 0.5 * (bzlo + bzhi);  // block-uniform
-  if (ref)
-    for (int j = blo + (int)threadIdx.x; j <= bhi; j += kMcBlock)
-      sv[j - blo] = j >= 0 && j < I.n_y ? (float)(alpha * (zc - I.u1[j])) : 0.0f;
-  else if (staged)
-    for (int j = blo + (int)threadIdx.x; j <= bhi; j += kMcBlock) sv[j - blo] = j >= 0 && j < I.n_y ? I.v[j] : 0.0f;
+  {
+    // fields in registers and global-space pointers: the instance is read
+    // through a generic pointer, which the LDS stores below could alias, so
+    // it would be reloaded (three dependent loads) on every iteration
+    const int ny = I.n_y;
+    const glb_dptr u1g = (glb_dptr)I.u1;
+    const glb_cptr vg = (glb_cptr)I.v;
+    // four nodes per thread per step, their loads issued together (indices
+    // clamped into the grid, so every load is in bounds; nodes beyond the
+    // grid are stored as zero)
+    constexpr int SU = 4;
+    if (ref) {
+      for (int j0 = blo + (int)threadIdx.x; j0 <= bhi; j0 += SU * kMcBlock) {
+        double uv[SU];
+#pragma unroll
+        for (int t = 0; t < SU; ++t) uv[t] = u1g[min(max(j0 + t * kMcBlock, 0), ny - 1)];
+#pragma unroll
+        for (int t = 0; t < SU; ++t) {
+          const int j = j0 + t * kMcBlock;
+          if (j <= bhi) sv[j - blo] = j >= 0 && j < ny ? (float)(alpha * (zc - uv[t])) : 0.0f;
+        }
+      }
+    } else if (staged) {
+      for (int j0 = blo + (int)threadIdx.x; j0 <= bhi; j0 += SU * kMcBlock) {
+        float vv[SU];
+#pragma unroll
+        for (int t = 0; t < SU; ++t) vv[t] = vg[min(max(j0 + t * kMcBlock, 0), ny - 1)];
+#pragma unroll
+        for (int t = 0; t < SU; ++t) {
+          const int j = j0 + t * kMcBlock;
+          if (j <= bhi) sv[j - blo] = j >= 0 && j < ny ? vv[t] : 0.0f;
+        }
+      }
+    }
+  }
   __syncthreads();
 
   McLane cl;
@@ -1373,11 +1403,17 @@ __global__ __launch_bounds__(kU1Block) void k_u1_partial(Launch L) {
   // (y - x1_i)^2 / 2; every kU1Sample-th node is taken.
   const int j0 = tile * kU1Block, j1 = min(I.n_y, j0 + kU1Block) - 1;
   const double ya = I.y_lo + (double)j0 * I.dy, yb = I.y_lo + (double)j1 * I.dy;
+  // the instance is read through a generic pointer, which the LDS stores
+  // below could alias: its fields and arrays are taken into registers and
+  // global-space pointers once
+  const int nx = I.n_x;
+  const double x_lo = I.x_lo, dx = I.dx;
+  const glb_dptr u0g = (glb_dptr)I.u0, lfg = (glb_dptr)I.logf;
   double lb = -INFINITY;
-  for (int i = (int)threadIdx.x * kU1Sample; i < I.n_x; i += kU1Block * kU1Sample) {
-    const double x1 = (I.x_lo + (double)i * I.dx) + I.u0[i];
+  for (int i = (int)threadIdx.x * kU1Sample; i < nx; i += kU1Block * kU1Sample) {
+    const double x1 = (x_lo + (double)i * dx) + u0g[i];
     const double da = ya - x1, db = yb - x1;
-    lb = fmax(lb, I.logf[i] - 0.5 * fmax(da * da, db * db));  // NaN terms drop out
+    lb = fmax(lb, lfg[i] - 0.5 * fmax(da * da, db * db));  // NaN terms drop out
   }
   lb = block_max_d(lb, sb[0]);
   // Around the middle node y_c of the tile, y_j - x1_i = eta_j + D_i with
@@ -1400,8 +1436,8 @@ __global__ __launch_bounds__(kU1Block) void k_u1_partial(Launch L) {
     bool bad = false;
     for (int t = threadIdx.x; t < cn; t += kU1Block) {
       const int i = c0 + t;
-      const double x1 = (I.x_lo + (double)i * I.dx) + I.u0[i];
-      const double lf = I.logf[i];
+      const double x1 = (x_lo + (double)i * dx) + u0g[i];
+      const double lf = lfg[i];
       const double D = yc - x1;
       const double Pn = lf - 0.5 * D * D;
       sD[t] = D;
