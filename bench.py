@@ -57,14 +57,20 @@ def measured_traffic(workload_name):
     counters on a plain copy of known size), or None when the summary is
     missing or was taken on a different kernel source."""
     path = os.path.join(ROOT, "profiles", f"pmc-traffic_{workload_name}.md")
+    return parse_traffic(path, kernel_source_hash())
+
+
+def parse_traffic(path, src_hash):
+    """The marginal-cost bytes per launch of a PMC traffic summary, if the
+    summary was taken on the kernel source with hash `src_hash`."""
     if not os.path.exists(path):
         return None
     vals = {}
     for line in open(path):
-        if ":" in line and line.startswith("- "):
-            k, v = line[2:].split(":", 1)
+        if ": " in line and line.startswith("- "):
+            k, v = line[2:].split(": ", 1)  # keys may hold a colon ("sha256[:16]")
             vals[k.strip()] = v.strip().strip("`")
-    if vals.get("kernel source sha256[:16]") != kernel_source_hash():
+    if vals.get("kernel source sha256[:16]") != src_hash:
         return None
     try:
         return float(vals["marginal-cost kernel HBM bytes per launch"])

@@ -148,3 +148,16 @@ def test_no_oracle_in_product_path():
             if f.endswith((".py", ".cpp", ".hip", ".h")):
                 txt = open(os.path.join(dp, f)).read()
                 assert "oracle" not in txt.replace("Oracle", "oracle").lower().replace("no cpu fallback", ""), f
+
+
+def test_bench_reads_committed_traffic_only_for_its_kernel_source(tmp_path):
+    """bench.py reports the HBM traffic of the PMC summary only while the
+    summary's kernel-source hash matches (the hash key itself holds a colon)."""
+    import bench
+
+    p = tmp_path / "pmc-traffic_x.md"
+    p.write_text("# HBM traffic\n\n- kernel source sha256[:16]: `0123456789abcdef`\n"
+                 "- marginal-cost kernel HBM bytes per launch: 49956841\n")
+    assert bench.parse_traffic(str(p), "0123456789abcdef") == 49956841.0
+    assert bench.parse_traffic(str(p), "fedcba9876543210") is None
+    assert bench.parse_traffic(str(tmp_path / "missing.md"), "0123456789abcdef") is None
