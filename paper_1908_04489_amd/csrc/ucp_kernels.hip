@@ -642,7 +642,11 @@ __global__ __launch_bounds__(kMcBlock) void k_mc32(Launch L, int level) {
   // window segment slowest: blocks dispatched together read the same part
   // of the offset table, which then stays in the scalar cache
   const int per_seg = ((I.n_x + kMcBlock - 1) / kMcBlock) * kq;
-  const int seg = local / per_seg;
+  // middle segments first and the window's two end segments last: the end
+  // segments lose the most to the grid's edges, so the last units of the
+  // launch are the shorter ones and the launch drains sooner
+  const int sidx = local / per_seg;
+  const int seg = (S - 1) / 2 + ((sidx & 1) ? (sidx + 1) / 2 : -(sidx / 2));
   local %= per_seg;
   const int q = local % kq;
   const int tile = local / kq;
