@@ -63,6 +63,10 @@ CASES = {
     # more candidates than half a wave holds: the selection runs one point per wave
     "wide": lambda: W.Case("wide-k40", W.gaussian_problem(0.2, 3.0, 401, 25.0), W.Search(-30, 30, 2, 40), 3,
                            W.init_random_steps(W.gaussian_problem(0.2, 3.0, 401, 25.0), 3.0, 5)),
+    # the largest set that still runs two points per wave (30 candidates, the
+    # carried best and the incumbent's queue lane fill 32 lanes); odd n_x
+    "k30": lambda: W.Case("k30-two-per-wave", W.gaussian_problem(0.3, 4.0, 333, 25.0), W.Search(-30, 30, 3, 30), 3,
+                          W.init_random_steps(W.gaussian_problem(0.3, 4.0, 333, 25.0), 4.0, 9)),
 }
 
 
