@@ -140,9 +140,6 @@ size_t state_bytes(const Inst& I) {
   b += 9 * align_up(nx * 8);                                      // u0 u0_next f logf cbest b32best b64best b32inc jrow
   b += align_up(ny * 8) + align_up(ny * 4);                       // u1 v
   b += align_up((size_t)(2 * I.nw32 + 1 + kGtabPad) * 4);          // gtab (padded past the window)
-  b += align_up(nx * (size_t)(I.cands + 3) * 8);                   // ev
-  b += align_up(nx * (size_t)eval_row_cap(I.cands) * sizeof(EvalItem));  // items
-  b += align_up(nx * 4) + 256;                                     // pend, nitems
   b += align_up(nx * (size_t)(I.cands + 1) * (size_t)I.segs * 8); // part
   b += align_up((size_t)I.u1_slices * ny * 3 * 8);                // u1part
   b += 256 + kCountBytes;                                         // flags, counters
@@ -168,23 +165,16 @@ void carve_state(Inst& I, char*& base) {
   I.u1 = (double*)take(ny * 8);
   I.v = (float*)take(ny * 4);
   I.gtab = (float*)take((size_t)(2 * I.nw32 + 1 + kGtabPad) * 4);
-  I.ev = (double*)take(nx * (size_t)(I.cands + 3) * 8);
-  I.items = (EvalItem*)take(nx * (size_t)eval_row_cap(I.cands) * sizeof(EvalItem));
-  I.pend = (int32_t*)take(nx * 4);
-  I.nitems = (int32_t*)take(256);
   I.part = (double*)take(nx * (size_t)(I.cands + 1) * (size_t)I.segs * 8);
   I.u1part = (double*)take((size_t)I.u1_slices * ny * 3 * 8);
   I.flags = (int32_t*)take(256);
   I.terms = (unsigned long long*)take(kCountBytes);
 }
 
-// Zero what a solve expects zero: flags, work counters, the FP64 queue and
-// the per-point pending marks.
+// Zero what a solve expects zero: flags and work counters.
 hipError_t clear_state(const Inst& I, hipStream_t st) {
   hipError_t e = hipMemsetAsync(I.flags, 0, 256, st);
   if (e == hipSuccess && I.terms) e = hipMemsetAsync(I.terms, 0, kCountBytes, st);
-  if (e == hipSuccess) e = hipMemsetAsync(I.pend, 0, (size_t)I.n_x * 4, st);
-  if (e == hipSuccess) e = hipMemsetAsync(I.nitems, 0, 4, st);
   return e;
 }
 

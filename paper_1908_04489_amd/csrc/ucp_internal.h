@@ -27,9 +27,8 @@ constexpr int kGtabPad = 16;    // offset-table entries past the window (>= the 
 // coarse level-0 grid within a block, narrow enough that the staged
 // differences round no worse than the residual form's
 constexpr double kMcRefHalf = 2.5;
-constexpr double kMcBetaMax = 4.0; // blocked sums only where weights change by <= 2^4 per node  // reference form when every z of a block is within this of z_c
-constexpr int kSelWaves = 16;   // selection kernels: waves per block
-constexpr int kEvalWaves = 4;   // queue-draining kernel: one wave per queued sum
+constexpr double kMcBetaMax = 4.0; // blocked sums only where weights change by <= 2^4 per node
+constexpr int kSelWaves = 4;    // selection kernel: waves per block
 constexpr int kU1Block = 256;   // u1 kernels: one lane per y node
 constexpr int kU1Chunk = 512;   // x nodes staged in LDS per step of the u1 sums
 constexpr int kU1Sample = 32;   // x-node stride of the sample bounding a tile's logit maximum
@@ -56,19 +55,10 @@ constexpr double kWin64 = 9.0;
 constexpr int kCountSlots = 32, kCountStride = 16, kCountTerms = 0, kCountEvalTerms = 4, kCountEvals = 8;
 constexpr size_t kCountBytes = (size_t)kCountSlots * kCountStride * 8;
 
-// A queued FP64 window sum: point, result slot, candidate position.
-struct EvalItem {
-  int32_t i;
-  int32_t slot;
-  double c;
-};
-
-constexpr int kEvalBlocks = 2048;  // grid of the queue-draining kernel
-// A point's queued sums take a whole number of chunks of kEvalChunk entries
-// (padding entries have i = -1), so the chunks, and the positions that share
-// one pass over their windows, depend on the point alone.
+// A point's queued FP64 sums take a whole number of chunks of kEvalChunk
+// entries (padding entries have i = -1), so the chunks, and the positions
+// that share one pass over their windows, depend on the point alone.
 constexpr int kEvalChunk = 4;
-inline int eval_row_cap(int cands) { return (cands + 3 + kEvalChunk - 1) / kEvalChunk * kEvalChunk; }
 
 // One solve instance as the kernels see it: constants of the problem and the
 // search, launch geometry, and device pointers to its state.
@@ -106,10 +96,6 @@ struct Inst {
   double* part;              // marginal-cost partial sums [n_x][cands + 1][segs]
   double* u1part;            // u1 partial sums [u1_slices][n_y][3]
   double* jrow;              // per-point objective terms [n_x]
-  double* ev;                // FP64 results of queued sums [n_x][cands + 3]
-  EvalItem* items;           // queue of FP64 sums [n_x eval_row_cap(cands)]
-  int32_t* nitems;           // queue length
-  int32_t* pend;             // per point: 0 decided, else the kind of its queued sums (1, 2 or 3)
   double* J_out;             // objective output (one double)
   double* L0_out;            // optional FP64 L_0 of the accepted u0 [n_x] (argmin call only)
   int32_t* flags;            // bit 0: non-finite value met

@@ -14,11 +14,10 @@
 //   k_mc32<P>      marginal-cost window sums for one level of the search,
 //                  FP32 terms, plain (P=0) or compensated (P=1) sums
 //   k_mc64         the same in FP64 (precision-study mode)
-//   k_band<P>, k_eval, k_resolve<P>
-//                  per point: level minimum, FP32 tie band, FP64
-//                  re-evaluation of the band members (queued and drained at
-//                  full occupancy), selection rule, next bracket, and after
-//                  the last level the comparison with the incumbent
+//   k_select<P>    per point: level minimum, FP32 tie band, FP64
+//                  re-evaluation of the band members (queued and evaluated
+//                  within the block), selection rule, next bracket, and
+//                  after the last level the comparison with the incumbent
 //   k_u1_partial<P>/k_u1_combine   closed-form second controller
 //   k_j_rows/k_j_reduce            objective in FP64, fixed-order reduction
 #include <hip/hip_runtime.h>
@@ -887,22 +886,17 @@ __global__ __launch_bounds__(256) void k_mc_finish(Launch L, double* out, int pr
 
 // ------------------------------------------------------------- selection
 //
-// Three kernels per level:
-//   k_band     one group of W lanes per point: a wave (W = 64), or, where
-//              the level's set and the incumbent fit in 32 lanes
-//              (cands + 2 <= 32), an aligned half-wave (W = 32, two points
-//              per wave).  Lane q of the group holds candidate q of the level
-//              (lane `cands` the best so far, or at level 0 the incumbent,
-//              whose FP32-path B is kept for the final comparison).  FP32
-//              minimum and tie band; a one-member band (and FP64 mode)
-//              decides at once, otherwise the members without an FP64 value
-//              are queued.  On the last level a decided point runs the
-//              comparison with the incumbent the same way.
-//   k_eval     drains the queues (whole waves): a fixed grid at full
-//              occupancy whatever the number of items.
-//   k_resolve  the queued points: the selection rule on the FP64 values, and
-//              on the last level the comparison with the incumbent.
-// Every cross-lane step of the group kernels (minimum, ballot, shuffle)
+// One kernel per level (k_select), one block per kSelWaves * 64 / W
+// points.  A point is handled by a group of W lanes: a wave (W = 64), or,
+// where the level's set and the incumbent fit in 32 lanes (cands + 2 <= 32),
+// an aligned half-wave (W = 32, two points per wave).  Lane q of the group
+// holds candidate q of the level (lane `cands` the best so far, or at level
+// 0 the incumbent, whose FP32-path B is kept for the final comparison).
+// FP32 minimum and tie band; a one-member band (and FP64 mode) decides at
+// once, otherwise the members without an FP64 value queue their FP64
+// window sums in the block, which evaluates them and then decides.  On the
+// last level a decided point runs the comparison with the incumbent the
+// same way.  Every cross-lane step of a group (minimum, ballot, shuffle)
 // reads lanes of its own group only, and every branch depends on values
 // uniform over the group, so the two groups of a wave may take different
 // paths.  W is a function of the instance alone.
@@ -933,12 +927,6 @@ __device__ __forceinline__ double grp_min_d(double v) {
   for (int o = W / 2; o > 0; o >>= 1) v = fmin(v, __shfl_xor(v, o));
   return v;
 }
-
-// Slots of the per-point FP64 results: 0..cands-1 level candidates, `cands`
-// the best so far, then the two members of the incumbent comparison.
-__device__ __forceinline__ int slot_best(const Inst& I) { return I.cands + 1; }
-__device__ __forceinline__ int slot_inc(const Inst& I) { return I.cands + 2; }
-__device__ __forceinline__ double* ev_row(const Inst& I, int i) { return I.ev + (size_t)i * (I.cands + 3); }
 
 // The selection rule on FP64 values among the lanes with `member`: ties
 // within kTau64 of the minimum, the one nearest the incumbent wins, then the
@@ -1002,21 +990,16 @@ __device__ __forceinline__ void count_evals(const Inst& I, int n) {
     atomicAdd(I.terms + kCountEvals + (blockIdx.x & (kCountSlots - 1)) * kCountStride, (unsigned long long)n);
 }
 
-// Points whose decision needs FP64 window sums are queued: kind 1 = the
-// level's band members (slot = lane), kind 2 = the comparison of the
-// level's winner (slot cands + 1) with the incumbent (slot cands + 2),
-// kind 3 = on the last level, the band members and (lane cands + 1) the
-// incumbent, whose sum the comparison that follows may need.
+// Points whose decision needs FP64 window sums queue them in their block:
+// kind 1 = the level's band members (lane q), kind 2 = the comparison of
+// the level's winner (lane 0) with the incumbent (lane 1), kind 3 = on the
+// last level, the band members and (lane cands + 1) the incumbent, whose
+// sum the comparison that follows may need.
 struct Queued {
   unsigned long long todo;  // group lanes whose sum is needed
   int kind;                 // 0: nothing queued
   double c;                 // this lane's position
 };
-
-__device__ __forceinline__ int queued_slot(const Inst& I, int kind, int lane) {
-  if (kind == 2) return lane == 0 ? slot_best(I) : slot_inc(I);
-  return kind == 3 && lane == I.cands + 1 ? slot_inc(I) : lane;
-}
 
 // The FP64 value of the incumbent where a lane of the set sits at its
 // position with a known FP64 value (the carried best often does), else NaN.
@@ -1046,9 +1029,9 @@ __device__ void finish_point(const Inst& I, int i, double res, double Bres, doub
 }
 
 // Comparison of the level's winner (cw, B32w, B64w) with the incumbent
-// (B64i its FP64 value where known).  In k_band (inline_eval = false) a
-// two-member band is queued (returned in Q); in k_resolve missing FP64 sums
-// are evaluated in place.
+// (B64i its FP64 value where known).  In the band phase (inline_eval =
+// false) a two-member band is queued (returned in Q); in the resolve phase
+// missing FP64 sums are evaluated in place.
 template <int PREC, int W>
 __device__ void accept(const Inst& I, int i, double x, double uinc, double cw, double B32w, double B64w, double B64i,
                        int lane, bool inline_eval, int want_l0, int& n_eval, Queued& Q) {
@@ -1105,14 +1088,15 @@ __device__ void accept(const Inst& I, int i, double x, double uinc, double cw, d
   finish_point<W>(I, i, grp_shfl<W>(c2, w), grp_shfl<W>(b64, w), x, lane, want_l0);
 }
 
-// One point of k_band: decide it, or return in Q the FP64 sums it needs.
+// Band phase for one point: decide it, or return in Q the FP64 sums it
+// needs; the lane's view of the level (c, B32, B64, in_set) is returned for
+// the resolve phase.
 template <int PREC, int W>
-__device__ void band_point(const Inst& I, int level, int i, int lane, int want_l0, int& n_eval, Queued& Q) {
+__device__ void band_point(const Inst& I, int level, int i, int lane, int want_l0, int& n_eval, Queued& Q,
+                           double& c, double& B32, double& B64, bool& in_set) {
   const int K = I.cands;
   const double uinc = I.u0[i];
   const double x = I.x_lo + (double)i * I.dx;
-  double c, B32, B64;
-  bool in_set;
   level_view<PREC>(I, level, i, lane, c, B32, B64, in_set);
   if (level == 0 && lane == K) I.b32inc[i] = B32;
   int w;
@@ -1130,15 +1114,15 @@ __device__ void band_point(const Inst& I, int level, int i, int lane, int want_l
     } else {
       const bool member = (mask >> lane) & 1ull;
       const unsigned long long todo = grp_ballot<W>(member && isnan(B64));
-      if (todo) {  // FP64 sums needed: k_resolve decides
+      if (todo) {  // FP64 sums needed: the resolve phase decides
         Q.todo = todo;
         Q.kind = 1;
         Q.c = c;
         // last level: if the incumbent could share the FP32 band of the
         // winner, whichever member wins, its sum is queued too, so the
-        // comparison in k_resolve evaluates nothing itself.  (An incumbent
-        // that is itself a member, as the carried best, gets its FP64 value
-        // as a member.)
+        // comparison in the resolve phase evaluates nothing itself.  (An
+        // incumbent that is itself a member, as the carried best, gets its
+        // FP64 value as a member.)
         if (level == I.levels - 1 && K + 1 < W && !grp_ballot<W>(member && c == uinc)) {
           const double b32i = I.b32inc[i];
           if (grp_ballot<W>(member && pair_band_both(B32, b32i, PREC))) {
@@ -1164,138 +1148,28 @@ __device__ void band_point(const Inst& I, int level, int i, int lane, int want_l
   }
 }
 
-// Block body of k_band: each group takes one point; the block reserves
-// queue space for all of them with one atomic.  A point's entries are
-// padded to a whole number of chunks.
+// Resolve phase for a point that queued FP64 sums; `qv` is this lane's
+// queued sum (NaN where the lane queued none).
 template <int PREC, int W>
-__device__ void band_block(const Inst& I, int local, int level, int want_l0) {
-  constexpr int G = kWave / W;  // points per wave
-  __shared__ int s_cnt[kSelWaves];
-  __shared__ int s_base;
-  const int wid = threadIdx.x / kWave, lane = (int)threadIdx.x % W, g = ((int)threadIdx.x % kWave) / W;
-  const int i = (local * kSelWaves + wid) * G + g;
-  Queued Q;
-  Q.todo = 0ull;
-  Q.kind = 0;
-  Q.c = 0.0;
-  int n_eval = 0;
-  if (i < I.n_x) band_point<PREC, W>(I, level, i, lane, want_l0, n_eval, Q);
-  // this group's entries, and (two groups) the wave's total and the group's
-  // offset within the wave
-  const int mine = pad_chunk(__popcll(Q.todo));
-  int cnt = mine, before = 0;
-  if constexpr (G == 2) {
-    const int other = __shfl_xor(mine, W);
-    cnt = mine + other;
-    before = g == 1 ? other : 0;
-  }
-  if (threadIdx.x % kWave == 0) s_cnt[wid] = cnt;
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    int tot = 0;
-    for (int w = 0; w < kSelWaves; ++w) tot += s_cnt[w];
-    s_base = tot ? atomicAdd(I.nitems, tot) : 0;
-  }
-  __syncthreads();
-  const unsigned long long todo = Q.todo;
-  if (todo) {
-    int base = s_base + before;
-    for (int w = 0; w < wid; ++w) base += s_cnt[w];
-    const int nq = __popcll(todo), np = pad_chunk(nq);
-    if ((todo >> lane) & 1ull) {
-      EvalItem it;
-      it.i = i;
-      it.slot = queued_slot(I, Q.kind, lane);
-      it.c = Q.c;
-      I.items[base + __popcll(todo & ((1ull << lane) - 1ull))] = it;
-    }
-    if (lane >= nq && lane < np) {
-      EvalItem it;
-      it.i = -1;
-      it.slot = 0;
-      it.c = 0.0;
-      I.items[base + lane] = it;
-    }
-    if (lane == 0) I.pend[i] = Q.kind;
-  }
-  if (lane == 0) count_evals(I, n_eval);
-}
-
-template <int PREC>
-__global__ __launch_bounds__(kSelWaves * kWave) void k_band(Launch L, int level, int want_l0) {
-  const int u = blockIdx.x;
-  const int b = find_inst(L.pre, L.n_inst, u);
-  const Inst& I = L.insts[b];
-  if (sel_width(I) == 32) band_block<PREC, 32>(I, u - L.pre[b], level, want_l0);
-  else band_block<PREC, kWave>(I, u - L.pre[b], level, want_l0);
-}
-
-// Drains the queue of every instance: each wave takes a chunk of
-// kEvalChunk entries, all of one point, whose positions share one pass over
-// their windows.
-__global__ __launch_bounds__(kEvalWaves * kWave) void k_eval(Launch L) {
-  const int wid = threadIdx.x / kWave, lane = threadIdx.x % kWave;
-  const int gw = blockIdx.x * kEvalWaves + wid, nw = gridDim.x * kEvalWaves;
-  for (int b = 0; b < L.n_inst; ++b) {
-    if (L.pre[b + 1] == L.pre[b]) continue;  // instance not running
-    const Inst& I = L.insts[b];
-    const int n = *I.nitems;
-    const int nch = (n + kEvalChunk - 1) / kEvalChunk;
-    int done = 0;
-    for (int ch = gw; ch < nch; ch += nw) {
-      EvalItem it[kEvalChunk];
-#pragma unroll
-      for (int q = 0; q < kEvalChunk; ++q) it[q] = I.items[ch * kEvalChunk + q];
-      int cnt = 0;  // valid entries lead the chunk
-#pragma unroll
-      for (int q = 0; q < kEvalChunk; ++q) cnt += it[q].i >= 0;
-      if (cnt == 0) continue;
-      const double x = I.x_lo + (double)it[0].i * I.dx;
-      double z[kEvalChunk], v[kEvalChunk];
-#pragma unroll
-      for (int q = 0; q < kEvalChunk; ++q) z[q] = x + (q < cnt ? it[q].c : it[0].c);  // static indices only
-      if (cnt == 1) v[0] = b64_wave(I, z[0], lane);
-      else if (cnt == 2) b64_multi<2>(I, z, lane, v);
-      else if (cnt == 3) b64_multi<3>(I, z, lane, v);
-      else b64_multi<4>(I, z, lane, v);
-      if (lane == 0) {
-        double* row = ev_row(I, it[0].i);
-#pragma unroll
-        for (int q = 0; q < kEvalChunk; ++q)
-          if (q < cnt) row[it[q].slot] = I.k2 * it[q].c * it[q].c + v[q];
-      }
-      done += cnt;
-    }
-    if (lane == 0) count_evals(I, done);
-  }
-}
-
-template <int PREC, int W>
-__device__ void resolve_point(const Inst& I, int level, int i, int lane, int want_l0, int& n_eval) {
-  const int pend = I.pend[i];
-  if (pend == 0) return;
+__device__ void resolve_point(const Inst& I, int level, int i, int lane, int want_l0, int& n_eval, int kind,
+                              double qv, double c, double B32, double B64, bool in_set) {
   const double uinc = I.u0[i];
   const double x = I.x_lo + (double)i * I.dx;
-  const double* evr = ev_row(I, i);
-  if (pend != 2) {
-    double c, B32, B64;
-    bool in_set;
-    level_view<PREC>(I, level, i, lane, c, B32, B64, in_set);
+  if (kind != 2) {
     const unsigned long long mask = band32<W>(in_set, B32, PREC);
     const bool member = (mask >> lane) & 1ull;
-    if (member && isnan(B64)) B64 = evr[lane];
+    if (member && isnan(B64)) B64 = qv;
     const int w = tie_rule<W>(member, c, B64, uinc, lane);
     const double cw = grp_shfl<W>(c, w), B32w = grp_shfl<W>(B32, w), B64w = grp_shfl<W>(B64, w);
     if (lane == 0) {
       I.cbest[i] = cw;
       I.b32best[i] = B32w;
       I.b64best[i] = B64w;
-      I.pend[i] = 0;
     }
     if (level == I.levels - 1) {
       Queued Q;
       double B64i = inc_from_set<W>(in_set, c, B64, uinc);
-      if (pend == 3 && isnan(B64i)) B64i = evr[slot_inc(I)];
+      if (kind == 3 && isnan(B64i)) B64i = grp_shfl<W>(qv, I.cands + 1);
       accept<PREC, W>(I, i, x, uinc, cw, B32w, B64w, B64i, lane, true, want_l0, n_eval, Q);
     }
   } else {
@@ -1304,53 +1178,134 @@ __device__ void resolve_point(const Inst& I, int level, int i, int lane, int wan
     const bool in2 = lane < 2;
     const double c2 = lane == 0 ? cw : uinc;
     const double b32 = lane == 0 ? I.b32best[i] : I.b32inc[i];
-    double b64 = lane == 0 ? (isnan(B64w) ? evr[slot_best(I)] : B64w) : evr[slot_inc(I)];
+    const double b64 = lane == 0 ? (isnan(B64w) ? qv : B64w) : qv;
     const unsigned long long mask = band32<W>(in2, b32, PREC);
     const bool member = (mask >> lane) & 1ull;
     const int w = tie_rule<W>(member, c2, b64, uinc, lane);
     finish_point<W>(I, i, grp_shfl<W>(c2, w), grp_shfl<W>(b64, w), x, lane, want_l0);
-    if (lane == 0) I.pend[i] = 0;
   }
 }
 
+// A queued FP64 window sum of the block: point and position (i < 0 pads).
+struct SelItem {
+  int32_t i;
+  double c;
+};
+
+// Largest number of queue entries of one point: cands + 2 lanes, padded to
+// whole chunks.
+constexpr int kSelCapMax = (UCP_MAX_CANDS + 2 + kEvalChunk - 1) / kEvalChunk * kEvalChunk;
+
+// One selection block (kSelWaves waves, G points per wave):
+//  1. band: every group decides its point or queues the FP64 sums it needs
+//     in the block's queue (a point's entries padded to whole chunks of
+//     kEvalChunk, so the positions that share one pass depend on the point
+//     alone);
+//  2. eval: the block's whole waves take the chunks in turn, one pass of
+//     b64_multi over the union of a chunk's windows, results to LDS;
+//  3. resolve: the queued points decide on their FP64 values.
+// Every dependency stays in the block, so one launch serves a level.
 template <int PREC, int W>
-__device__ void resolve_block(const Inst& I, int local, int level, int want_l0) {
+__device__ void select_block(const Inst& I, int local, int level, int want_l0, SelItem* sq, double* sres,
+                             int* s_cnt) {
   constexpr int G = kWave / W;
-  const int wid = threadIdx.x / kWave, lane = (int)threadIdx.x % W, g = ((int)threadIdx.x % kWave) / W;
-  const int i = (local * kSelWaves + wid) * G + g;
+  constexpr int NP = kSelWaves * G;  // points per block
+  const int wid = threadIdx.x / kWave, g = ((int)threadIdx.x % kWave) / W, lane = (int)threadIdx.x % W;
+  const int grp = wid * G + g;
+  const int i = local * NP + grp;
+  const bool have = i < I.n_x;
+  Queued Q;
+  Q.todo = 0ull;
+  Q.kind = 0;
+  Q.c = 0.0;
+  double c = 0.0, B32 = INFINITY, B64 = NAN;
+  bool in_set = false;
   int n_eval = 0;
-  if (i < I.n_x) resolve_point<PREC, W>(I, level, i, lane, want_l0, n_eval);
-  if (lane == 0) count_evals(I, n_eval);
+  if (have) band_point<PREC, W>(I, level, i, lane, want_l0, n_eval, Q, c, B32, B64, in_set);
+  const int nq = __popcll(Q.todo);
+  if (lane == 0) s_cnt[grp] = pad_chunk(nq);
+  __syncthreads();
+  int base = 0, total = 0;
+  for (int k = 0; k < NP; ++k) {
+    const int n = s_cnt[k];
+    base += k < grp ? n : 0;
+    total += n;
+  }
+  if (Q.todo) {
+    if ((Q.todo >> lane) & 1ull) {
+      SelItem it;
+      it.i = i;
+      it.c = Q.c;
+      sq[base + __popcll(Q.todo & ((1ull << lane) - 1ull))] = it;
+    }
+    if (lane >= nq && lane < pad_chunk(nq)) {
+      SelItem it;
+      it.i = -1;
+      it.c = 0.0;
+      sq[base + lane] = it;
+    }
+  }
+  __syncthreads();
+  if (total) {
+    const int wl = (int)threadIdx.x % kWave;
+    for (int ch = wid; ch * kEvalChunk < total; ch += kSelWaves) {
+      SelItem it[kEvalChunk];
+#pragma unroll
+      for (int q = 0; q < kEvalChunk; ++q) it[q] = sq[ch * kEvalChunk + q];
+      int cnt = 0;  // valid entries lead the chunk
+#pragma unroll
+      for (int q = 0; q < kEvalChunk; ++q) cnt += it[q].i >= 0;
+      if (cnt == 0) continue;
+      const double x = I.x_lo + (double)it[0].i * I.dx;
+      double z[kEvalChunk], v[kEvalChunk];
+#pragma unroll
+      for (int q = 0; q < kEvalChunk; ++q) z[q] = x + (q < cnt ? it[q].c : it[0].c);  // static indices only
+      if (cnt == 1) v[0] = b64_wave(I, z[0], wl);
+      else if (cnt == 2) b64_multi<2>(I, z, wl, v);
+      else if (cnt == 3) b64_multi<3>(I, z, wl, v);
+      else b64_multi<4>(I, z, wl, v);
+      if (wl == 0) {
+#pragma unroll
+        for (int q = 0; q < kEvalChunk; ++q)
+          if (q < cnt) sres[ch * kEvalChunk + q] = I.k2 * it[q].c * it[q].c + v[q];
+      }
+      n_eval += wl == 0 ? cnt : 0;
+    }
+    __syncthreads();
+    if (Q.kind) {
+      const double qv = (Q.todo >> lane) & 1ull ? sres[base + __popcll(Q.todo & ((1ull << lane) - 1ull))] : NAN;
+      resolve_point<PREC, W>(I, level, i, lane, want_l0, n_eval, Q.kind, qv, c, B32, B64, in_set);
+    }
+  }
+  // one count per wave: the group leaders' counts (band and resolve) and
+  // the wave's chunk counts
+  int ne = lane == 0 ? n_eval : ((int)threadIdx.x % kWave == 0 ? n_eval : 0);
+  for (int o = kWave / 2; o > 0; o >>= 1) ne += __shfl_xor(ne, o);
+  if ((int)threadIdx.x % kWave == 0) count_evals(I, ne);
 }
 
 template <int PREC>
-__global__ __launch_bounds__(kSelWaves * kWave) void k_resolve(Launch L, int level, int want_l0) {
+__global__ __launch_bounds__(kSelWaves * kWave) void k_select(Launch L, int level, int want_l0) {
+  __shared__ SelItem sq[kSelWaves * 2 * kSelCapMax];
+  __shared__ double sres[kSelWaves * 2 * kSelCapMax];
+  __shared__ int s_cnt[kSelWaves * 2];
   const int u = blockIdx.x;
   const int b = find_inst(L.pre, L.n_inst, u);
   const Inst& I = L.insts[b];
-  if (u == L.pre[b] && threadIdx.x == 0) *I.nitems = 0;  // the queue has been drained
-  if (sel_width(I) == 32) resolve_block<PREC, 32>(I, u - L.pre[b], level, want_l0);
-  else resolve_block<PREC, kWave>(I, u - L.pre[b], level, want_l0);
+  if (sel_width(I) == 32) select_block<PREC, 32>(I, u - L.pre[b], level, want_l0, sq, sres, s_cnt);
+  else select_block<PREC, kWave>(I, u - L.pre[b], level, want_l0, sq, sres, s_cnt);
 }
 
 hipError_t launch_select(const Launch& L, int level, int prec, int want_l0, hipStream_t st, hipEvent_t e0,
                          hipEvent_t e1) {
   if (L.total == 0) return hipSuccess;
   const dim3 blk(kSelWaves * kWave);
-  if (prec == UCP_FP64) {
-    hipExtLaunchKernelGGL(k_band<UCP_FP64>, dim3(L.total), blk, 0, st, e0, e1, 0, L, level, want_l0);
-    return hipGetLastError();
-  }
-  if (prec == UCP_FP32_KAHAN) {
-    hipExtLaunchKernelGGL(k_band<UCP_FP32_KAHAN>, dim3(L.total), blk, 0, st, e0, nullptr, 0, L, level, want_l0);
-    hipLaunchKernelGGL(k_eval, dim3(kEvalBlocks), dim3(kEvalWaves * kWave), 0, st, L);
-    hipExtLaunchKernelGGL(k_resolve<UCP_FP32_KAHAN>, dim3(L.total), blk, 0, st, nullptr, e1, 0, L, level,
-                          want_l0);
-  } else {
-    hipExtLaunchKernelGGL(k_band<UCP_FP32>, dim3(L.total), blk, 0, st, e0, nullptr, 0, L, level, want_l0);
-    hipLaunchKernelGGL(k_eval, dim3(kEvalBlocks), dim3(kEvalWaves * kWave), 0, st, L);
-    hipExtLaunchKernelGGL(k_resolve<UCP_FP32>, dim3(L.total), blk, 0, st, nullptr, e1, 0, L, level, want_l0);
-  }
+  if (prec == UCP_FP64)
+    hipExtLaunchKernelGGL(k_select<UCP_FP64>, dim3(L.total), blk, 0, st, e0, e1, 0, L, level, want_l0);
+  else if (prec == UCP_FP32_KAHAN)
+    hipExtLaunchKernelGGL(k_select<UCP_FP32_KAHAN>, dim3(L.total), blk, 0, st, e0, e1, 0, L, level, want_l0);
+  else
+    hipExtLaunchKernelGGL(k_select<UCP_FP32>, dim3(L.total), blk, 0, st, e0, e1, 0, L, level, want_l0);
   return hipGetLastError();
 }
 
