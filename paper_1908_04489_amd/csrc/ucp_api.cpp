@@ -114,6 +114,7 @@ Inst make_inst(const ucp_problem& p, const ucp_search* s, int prec, int cands_ov
   // small, segments of at least 256 nodes
   if (prec == UCP_FP64) {
     I.segs = 1;
+    I.wsegs = 1;
   } else {
     const int tiles = (I.n_x + kMcBlock - 1) / kMcBlock;
     const int kq = I.cands + 1;
@@ -124,7 +125,11 @@ Inst make_inst(const ucp_problem& p, const ucp_search* s, int prec, int cands_ov
     int sg = 1;
     while (sg < want && sg < 16) sg <<= 1;
     sg = std::max(1, std::min(sg, cap));
-    I.segs = std::max(sg, (wlen + kMcSegMax - 1) / kMcSegMax);
+    I.wsegs = std::max(sg, (wlen + kMcSegMax - 1) / kMcSegMax);
+    // an instance that needs four or more segments to fill the chip is small
+    // enough for the end of each launch to matter: the last segment it
+    // dispatches is split in two, so the launch ends on half-length units
+    I.segs = I.wsegs >= 4 ? I.wsegs + 1 : I.wsegs;
   }
   // at most 32 slices (the combine kernel's lane groups take 32)
   const int slen = std::max(512, (I.n_x + 31) / 32);

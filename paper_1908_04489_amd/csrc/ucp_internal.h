@@ -77,7 +77,8 @@ struct Inst {
   double h[kMaxLevels];      // candidate spacing per level
   // geometry
   int32_t nw32, nw64;        // window half-widths in y nodes
-  int32_t segs;              // window segments per (tile, candidate) of the marginal-cost kernel
+  int32_t segs;              // marginal-cost units (partial sums) per (tile, candidate)
+  int32_t wsegs;             // equal window segments (the last one dispatched split in two when segs > wsegs)
   int32_t u1_slices;         // x slices of the u1 sums
   int32_t prec;              // ucp_prec
   int32_t free_cands;        // 1: explicit candidates (u0 holds [n_x][cands]), no search

@@ -645,7 +645,11 @@ __global__ __launch_bounds__(kMcBlock) void k_mc32(Launch L, int level) {
   // segments lose the most to the grid's edges, so the last units of the
   // launch are the shorter ones and the launch drains sooner
   const int sidx = local / per_seg;
-  const int seg = (S - 1) / 2 + ((sidx & 1) ? (sidx + 1) / 2 : -(sidx / 2));
+  const int WS = I.wsegs;
+  const int so = min(sidx, WS - 1);
+  const int seg = (WS - 1) / 2 + ((so & 1) ? (so + 1) / 2 : -(so / 2));
+  // units past the window segments are the two halves of the last one
+  const int half = S > WS && sidx >= WS - 1 ? sidx - (WS - 1) : -1;
   local %= per_seg;
   const int q = local % kq;
   const int tile = local / kq;
@@ -659,9 +663,14 @@ __global__ __launch_bounds__(kMcBlock) void k_mc32(Launch L, int level) {
   const int jr = nearest_node(I, z);
   const double delta = (I.y_lo + (double)jr * I.dy) - z;
   const int nw = I.nw32;
-  const int seglen = (2 * nw + 1 + S - 1) / S;
-  const int s_lo = -nw + seg * seglen;
-  const int s_hi = min(nw, s_lo + seglen - 1);
+  const int seglen = (2 * nw + 1 + WS - 1) / WS;
+  int s_lo = -nw + seg * seglen;
+  int s_hi = min(nw, s_lo + seglen - 1);
+  if (half >= 0) {
+    const int mid = s_lo + (s_hi - s_lo + 1) / 2;
+    if (half == 0) s_hi = mid - 1;
+    else s_lo = mid;
+  }
   int klo = max(s_lo, -jr), khi = min(s_hi, I.n_y - 1 - jr);
   if (!act) { klo = 1; khi = 0; }
   const double beta = -2.0 * kAlpha2 * I.dy * delta;
@@ -701,7 +710,7 @@ __global__ __launch_bounds__(kMcBlock) void k_mc32(Launch L, int level) {
     bzlo = fmin(bzlo, szr[0][w]);
     bzhi = fmax(bzhi, szr[1][w]);
   }
-  if (seg == 0) {
+  if (sidx == 0) {
     count_terms(I, z, act, lane);
     // terms this unit's (point, candidate) evaluates over all its segments
     long long ev = act ? (long long)(min(nw, I.n_y - 1 - jr) - max(-nw, -jr) + 1) : 0;
@@ -795,7 +804,7 @@ __global__ __launch_bounds__(kMcBlock) void k_mc32(Launch L, int level) {
   // spread over all XCDs, so each L2 writes back partial lines (about 4x the
   // array's bytes); the kernel is ALU-bound and this costs no time, while the
   // point-fastest layout costs the selection kernels more.
-  if (act) I.part[((size_t)i * (I.cands + 1) + q) * S + seg] = KAHAN ? (double)acc - (double)comp : (double)acc;
+  if (act) I.part[((size_t)i * (I.cands + 1) + q) * S + sidx] = KAHAN ? (double)acc - (double)comp : (double)acc;
 }
 
 // FP64 marginal cost (precision-study mode): lane = point, window kWin64,
