@@ -89,11 +89,11 @@ def test_large_mixture_batch_sampled(env):
 @pytest.mark.parametrize("prec", ["fp32_kahan", "fp32"])
 def test_marginal_cost_spread_blocks_sampled(env, prec):
     """Blocks whose positions spread over more nodes than the LDS stage holds.
-    Neighbouring points get candidates 30 apart (two clusters: the kernel
-    deals the block's points to lanes in node order and stages per wave),
-    6 apart (one stage, residual form), 3.4 apart (reference form), and
-    uniform over the search range (waves too wide to stage: global reads).
-    Sampled (point, candidate) pairs against the oracle's B."""
+    Candidates 30 apart between neighbouring points and between the two
+    halves of each block of 256 points (global reads), 6 apart (one stage,
+    residual form), 3.4 apart (reference form), and uniform over the search
+    range (global reads).  Sampled (point, candidate) pairs against the
+    oracle's B."""
     U, orc, torch = env
     p = W.gaussian_problem(0.2, 5.0, 20001, 25.0)
     x = orc.grid(p.x_lo, p.x_hi, p.n_x)
@@ -102,7 +102,9 @@ def test_marginal_cost_spread_blocks_sampled(env, prec):
     n = p.n_x
     sgn = np.where(np.arange(n) % 2 == 0, 1.0, -1.0)
     rng = np.random.default_rng(4)
-    u = np.stack([15.0 * sgn, 0.3 - 15.0 * sgn, 3.0 * sgn, 1.7 * sgn, rng.uniform(-30.0, 30.0, n)], axis=1)
+    halves = np.where(np.arange(n) % 256 < 128, 1.0, -1.0)
+    u = np.stack([15.0 * sgn, 0.3 - 15.0 * sgn, 3.0 * sgn, 1.7 * sgn, rng.uniform(-30.0, 30.0, n), 15.0 * halves],
+                 axis=1)
     got = U.marginal_cost(p, torch.as_tensor(u1).cuda(), torch.as_tensor(u).cuda(), prec).cpu().numpy()
     f, _ = orc.prior(p)
     rows = np.sort(rng.choice(n, 120, replace=False))
