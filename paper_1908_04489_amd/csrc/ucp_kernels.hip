@@ -67,36 +67,15 @@ __device__ __forceinline__ double dpp_mov_d(double v) {
   const int hi = dpp_mov<CTRL, ROWS>(__double2hiint(v));
   return __hiloint2double(hi, lo);
 }
-template <typename T, typename Op>
-__device__ __forceinline__ T dpp_reduce(T v, Op op) {
-  if constexpr (sizeof(T) == 8) {
-    v = op(v, dpp_mov_d<0xB1, 0xF>(v));   // quad_perm [1,0,3,2]
-    v = op(v, dpp_mov_d<0x4E, 0xF>(v));   // quad_perm [2,3,0,1]
-    v = op(v, dpp_mov_d<0x141, 0xF>(v));  // row_half_mirror
-    v = op(v, dpp_mov_d<0x140, 0xF>(v));  // row_mirror
-    v = op(v, dpp_mov_d<0x142, 0xA>(v));  // row_bcast:15 into rows 1, 3
-    v = op(v, dpp_mov_d<0x143, 0xC>(v));  // row_bcast:31 into rows 2, 3
-    return __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(v), 63),
-                            __builtin_amdgcn_readlane(__double2loint(v), 63));
-  } else {
-    v = op(v, dpp_mov<0xB1, 0xF>(v));
-    v = op(v, dpp_mov<0x4E, 0xF>(v));
-    v = op(v, dpp_mov<0x141, 0xF>(v));
-    v = op(v, dpp_mov<0x140, 0xF>(v));
-    v = op(v, dpp_mov<0x142, 0xA>(v));
-    v = op(v, dpp_mov<0x143, 0xC>(v));
-    return __builtin_amdgcn_readlane(v, 63);
-  }
-}
 __device__ __forceinline__ double wred_sum_d(double v) {
-  return dpp_reduce(v, [](double a, double b) { return a + b; });
-}
-
-// Butterfly sum: every lane ends with the same bits (each step adds the same
-// two values, and IEEE addition is commutative).
-__device__ __forceinline__ double wave_sum_d(double v) {
-  for (int o = kWave / 2; o > 0; o >>= 1) v += __shfl_xor(v, o);
-  return v;
+  v += dpp_mov_d<0xB1, 0xF>(v);   // quad_perm [1,0,3,2]
+  v += dpp_mov_d<0x4E, 0xF>(v);   // quad_perm [2,3,0,1]
+  v += dpp_mov_d<0x141, 0xF>(v);  // row_half_mirror
+  v += dpp_mov_d<0x140, 0xF>(v);  // row_mirror
+  v += dpp_mov_d<0x142, 0xA>(v);  // row_bcast:15 into rows 1, 3
+  v += dpp_mov_d<0x143, 0xC>(v);  // row_bcast:31 into rows 2, 3
+  return __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(v), 63),
+                          __builtin_amdgcn_readlane(__double2loint(v), 63));
 }
 
 // Sum over a group of W lanes (the whole wave, or an aligned half): DPP for
