@@ -468,6 +468,24 @@ __device__ __forceinline__ void mc_first(const McBlk& B, float kf, const McLane&
 
 // Second half: the weights g_m R_m and the block sum times E_k = exp2(beta k)
 // (E_{k+m} = E_k R_m).
+// The block's sum times E_k, not yet added.
+template <bool REF>
+__device__ __forceinline__ float mc_block_sum(const McBlk& B, const float* e, float kf, const McLane& c) {
+  const float E0 = __builtin_amdgcn_exp2f(fminf(c.beta * kf, 126.0f));
+  float b0 = 0.0f, b1 = 0.0f;
+#pragma unroll
+  for (int m = 0; m < kMcUnroll; m += 2) {
+    if (REF) {
+      b0 = fmaf(B.g[m] * e[m], e[m], b0);
+      b1 = fmaf(B.g[m + 1] * e[m + 1], e[m + 1], b1);
+    } else {
+      b0 = fmaf((B.g[m] * c.R[m]) * e[m], e[m], b0);
+      b1 = fmaf((B.g[m + 1] * c.R[m + 1]) * e[m + 1], e[m + 1], b1);
+    }
+  }
+  return E0 * (b0 + b1);
+}
+
 template <bool KAHAN, bool REF>
 __device__ __forceinline__ void mc_second(const McBlk& B, const float* e, float kf, const McLane& c, float& acc,
                                           float& comp) {
@@ -514,13 +532,15 @@ __device__ __forceinline__ void mc_bulk(P v, Q G, int k0, int k1, const McLane& 
     __builtin_amdgcn_sched_barrier(0);
     mc_load(B, v, G, k + U);
     __builtin_amdgcn_sched_barrier(0);
-    mc_second<KAHAN, REF>(A, e, (float)k, c, acc, comp);
+    const float sa = mc_block_sum<REF>(A, e, (float)k, c);
     mc_first<REF>(B, (float)(k + U), c, e);
     __builtin_amdgcn_sched_barrier(0);
     // the next block, or (past the end, unused) the last full block: always in range
     mc_load(A, v, G, min(k + 2 * U, k1 - U + 1));
     __builtin_amdgcn_sched_barrier(0);
-    mc_second<KAHAN, REF>(B, e, (float)(k + U), c, acc, comp);
+    const float sb = mc_block_sum<REF>(B, e, (float)(k + U), c);
+    if (KAHAN) kahan_add(sa + sb, acc, comp);  // one compensated add per pair of blocks
+    else acc += sa + sb;
   }
   if (k + U - 1 <= k1) {  // one block left, already loaded into A
     mc_first<REF>(A, (float)k, c, e);
