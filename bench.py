@@ -35,14 +35,16 @@ if ROOT not in sys.path:
 # per-offset table value and a per-lane exponential, stages the differences
 # around a per-block reference and folds the per-lane factor of the
 # exponential into the difference, so one algorithmic term needs 3 FP32
-# operations (scaled difference, weight, accumulate); each block of 16
-# terms 7 more slots (one exp2 = 4 and its argument, the block scale, the
-# two-chain combine) and each pair of blocks 5 (adding the pair, 4 of
-# compensation): 3 + (7 + 2.5)/16 = 3.59375 slots per term.  (Blocks whose
+# operations (scaled difference, weight, accumulate).  Blocks of 16 terms go
+# in pairs that share one exponential: the first block takes 7 more slots
+# (one exp2 = 4 and its argument, the block scale, the two-chain combine),
+# the second 3 (its factor exp2(16 beta) times the first's, the scale, the
+# combine) and the pair 5 (adding the two, 4 of compensation):
+# 3 + (7 + 3 + 5)/32 = 3.46875 slots per term.  (Blocks whose
 # positions spread wider than the reference form allows take two more
 # operations per term; the count above is the smaller one.)
 PEAK_SLOTS = 256 * 128 * 2.4e9
-SLOTS_PER_TERM = 3.59375
+SLOTS_PER_TERM = 3.46875
 
 
 def kernel_source_hash():

@@ -413,6 +413,7 @@ struct McLane {
   float aDy;             // alpha dy
   float Dl;              // residual form: alpha delta; reference form: a = alpha (z - z_c)
   float beta;            // -2 alpha^2 dy delta
+  float F16;             // exp2(beta kMcUnroll): the factor from one block's E_k to the next's
   float R[kMcUnroll];    // residual form: exp2(beta m); reference form: exp2(beta m / 2)
   float Dm[kMcUnroll];   // residual form: Dl + m alpha dy; reference form: exp2(beta m / 2) a
 };
@@ -467,11 +468,10 @@ __device__ __forceinline__ void mc_first(const McBlk& B, float kf, const McLane&
 }
 
 // Second half: the weights g_m R_m and the block sum times E_k = exp2(beta k)
-// (E_{k+m} = E_k R_m).
-// The block's sum times E_k, not yet added.
+// (E_{k+m} = E_k R_m).  mc_block_sum returns the block's sum times a given
+// E_k, not yet added; mc_second computes E_k and adds the sum.
 template <bool REF>
-__device__ __forceinline__ float mc_block_sum(const McBlk& B, const float* e, float kf, const McLane& c) {
-  const float E0 = __builtin_amdgcn_exp2f(fminf(c.beta * kf, 126.0f));
+__device__ __forceinline__ float mc_block_sum(const McBlk& B, const float* e, float E0, const McLane& c) {
   float b0 = 0.0f, b1 = 0.0f;
 #pragma unroll
   for (int m = 0; m < kMcUnroll; m += 2) {
@@ -532,13 +532,16 @@ __device__ __forceinline__ void mc_bulk(P v, Q G, int k0, int k1, const McLane& 
     __builtin_amdgcn_sched_barrier(0);
     mc_load(B, v, G, k + U);
     __builtin_amdgcn_sched_barrier(0);
-    const float sa = mc_block_sum<REF>(A, e, (float)k, c);
+    // E_k of the pair's first block; the second's is E_k exp2(16 beta)
+    // (beta k <= 79 in these blocks, so neither factor overflows)
+    const float Ea = __builtin_amdgcn_exp2f(fminf(c.beta * (float)k, 126.0f));
+    const float sa = mc_block_sum<REF>(A, e, Ea, c);
     mc_first<REF>(B, (float)(k + U), c, e);
     __builtin_amdgcn_sched_barrier(0);
     // the next block, or (past the end, unused) the last full block: always in range
     mc_load(A, v, G, min(k + 2 * U, k1 - U + 1));
     __builtin_amdgcn_sched_barrier(0);
-    const float sb = mc_block_sum<REF>(B, e, (float)(k + U), c);
+    const float sb = mc_block_sum<REF>(B, e, Ea * c.F16, c);
     if (KAHAN) kahan_add(sa + sb, acc, comp);  // one compensated add per pair of blocks
     else acc += sa + sb;
   }
@@ -762,6 +765,7 @@ __global__ __launch_bounds__(kMcBlock) void k_mc32(Launch L, int level) {
   cl.aDy = (float)(alpha * I.dy);
   cl.Dl = ref ? (float)(alpha * (z - zc)) : (float)(alpha * delta);
   cl.beta = (float)beta;
+  cl.F16 = __builtin_amdgcn_exp2f((float)(beta * kMcUnroll));
 #pragma unroll
   for (int m = 0; m < kMcUnroll; ++m) {
     if (ref) {
