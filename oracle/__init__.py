@@ -10,7 +10,8 @@ order).  This module compiles it with gcc and exposes it through ctypes on
 numpy arrays.  ``mp_oracle.py`` holds an independent arbitrary-precision
 brute force for tiny grids.
 
-Problem objects are duck-typed: any object with ``k``, ``comps`` (a sequence
+Problem objects are duck-typed: any object with ``k`` (``lam`` for the
+coding problem of Section V-B, the ``coding_*`` functions), ``comps`` (a sequence
 of ``(weight, mean, sd)`` for the Gaussian-mixture prior of x0), ``x_lo``,
 ``x_hi``, ``n_x``, ``y_lo``, ``y_hi``, ``n_y``.  Search objects need
 ``u_lo``, ``u_hi``, ``levels``, ``cands``.
@@ -92,6 +93,15 @@ def lib():
         L.orc_objective.argtypes = [P(_Problem), dp, dp]
         L.orc_objective.restype = C.c_double
         L.orc_solve.argtypes = [P(_Problem), P(_Search), C.c_int32, dp, dp, dp, dp]
+        D = C.c_double
+        L.orc_cd_B.argtypes = [P(_Problem), D, dp, D, D]
+        L.orc_cd_B.restype = D
+        L.orc_cd_marginal_cost.argtypes = [P(_Problem), D, dp, dp, C.c_int64, dp]
+        L.orc_cd_argmin.argtypes = [P(_Problem), D, P(_Search), dp, dp, ip, C.c_int64, dp, dp]
+        L.orc_cd_update_u1.argtypes = [P(_Problem), dp, ip, C.c_int64, dp]
+        L.orc_cd_objective.argtypes = [P(_Problem), D, dp, dp]
+        L.orc_cd_objective.restype = D
+        L.orc_cd_solve.argtypes = [P(_Problem), D, P(_Search), C.c_int32, dp, dp, dp, dp]
         _lib = L
     return _lib
 
@@ -101,7 +111,7 @@ def _prob(p) -> _Problem:
     if not 1 <= len(comps) <= MAX_COMP:
         raise ValueError("prior must have 1..8 components")
     s = _Problem()
-    s.k = float(p.k)
+    s.k = float(getattr(p, "k", 0.0))
     s.n_comp = len(comps)
     for c, (w, mu, sd) in enumerate(comps):
         s.w[c], s.mu[c], s.sd[c] = float(w), float(mu), float(sd)
@@ -218,4 +228,70 @@ def solve(p, s, iters: int, u0_init):
     J = np.empty(int(iters) + 1, np.float64)
     lib().orc_solve(C.byref(_prob(p)), C.byref(_search(s)), int(iters), _dp(u0_init),
                     _dp(u0), _dp(u1), _dp(J))
+    return u0, u1, J
+
+
+# ---------------------------------------------------------------------------
+# Zero-delay source-channel coding (Section V-B): w ~ U(-1, 1), stage-0
+# weight ``lam``; the problem object carries ``lam`` instead of ``k``.
+
+def _rows(rows, n):
+    if rows is None:
+        return n, None
+    rows = np.ascontiguousarray(rows, dtype=np.int64)
+    if rows.size and (rows.min() < 0 or rows.max() >= n):
+        raise ValueError("row index out of range")
+    return rows.size, rows
+
+
+def coding_B(p, u1, x: float, u: float) -> float:
+    u1 = _f64(u1, int(p.n_y))
+    return float(lib().orc_cd_B(C.byref(_prob(p)), float(p.lam), _dp(u1), float(x), float(u)))
+
+
+def coding_marginal_cost(p, u1, u) -> np.ndarray:
+    u1 = _f64(u1, int(p.n_y))
+    u = np.ascontiguousarray(u, dtype=np.float64)
+    if u.ndim != 2 or u.shape[0] != int(p.n_x):
+        raise ValueError("u must be [n_x, n_cand]")
+    out = np.empty_like(u)
+    lib().orc_cd_marginal_cost(C.byref(_prob(p)), float(p.lam), _dp(u1), _dp(u), u.shape[1], _dp(out))
+    return out
+
+
+def coding_argmin(p, s, u1, u0_in, rows=None):
+    u1 = _f64(u1, int(p.n_y))
+    u0_in = _f64(u0_in, int(p.n_x))
+    n, r = _rows(rows, int(p.n_x))
+    rp = r.ctypes.data_as(C.POINTER(C.c_int64)) if r is not None else None
+    u0o = np.empty(n, np.float64)
+    Bo = np.empty(n, np.float64)
+    lib().orc_cd_argmin(C.byref(_prob(p)), float(p.lam), C.byref(_search(s)), _dp(u1), _dp(u0_in),
+                        rp, n, _dp(u0o), _dp(Bo))
+    return u0o, Bo
+
+
+def coding_update_u1(p, u0, rows=None) -> np.ndarray:
+    u0 = _f64(u0, int(p.n_x))
+    n, r = _rows(rows, int(p.n_y))
+    rp = r.ctypes.data_as(C.POINTER(C.c_int64)) if r is not None else None
+    out = np.empty(n, np.float64)
+    lib().orc_cd_update_u1(C.byref(_prob(p)), _dp(u0), rp, n, _dp(out))
+    return out
+
+
+def coding_objective(p, u0, u1) -> float:
+    u0 = _f64(u0, int(p.n_x))
+    u1 = _f64(u1, int(p.n_y))
+    return float(lib().orc_cd_objective(C.byref(_prob(p)), float(p.lam), _dp(u0), _dp(u1)))
+
+
+def coding_solve(p, s, iters: int, u0_init):
+    """Returns (u0, u1, J_hist[iters + 1])."""
+    u0_init = _f64(u0_init, int(p.n_x))
+    u0 = np.empty(int(p.n_x), np.float64)
+    u1 = np.empty(int(p.n_y), np.float64)
+    J = np.empty(int(iters) + 1, np.float64)
+    lib().orc_cd_solve(C.byref(_prob(p)), float(p.lam), C.byref(_search(s)), int(iters), _dp(u0_init),
+                       _dp(u0), _dp(u1), _dp(J))
     return u0, u1, J

@@ -177,9 +177,19 @@ static double orc_clamp(double v, double lo, double hi) {
  * rule of Section III-B): a coarse-to-fine search of argmin_u B(u; x_i),
  * the best-so-far carried from level to level, and the incumbent u0_i
  * kept in the final comparison so the update never raises the cost. */
+double orc_cd_B(const orc_problem* p, double lam, const double* u1, double x, double u);
+
+/* B of the problem being searched: model 0 is the Witsenhausen objective
+ * above, model 1 the source-channel coding objective further below (with
+ * stage-0 weight lam). */
+static double orc_model_B(int model, double lam, const orc_problem* p, const double* u1, double x,
+                          double u) {
+  return model == 1 ? orc_cd_B(p, lam, u1, x, u) : orc_B(p, u1, x, u);
+}
+
 static double orc_argmin_point(const orc_problem* p, const orc_search* s,
                                const double* u1, const double* h, int64_t i,
-                               double u_inc, double* B_out) {
+                               double u_inc, double* B_out, int model, double lam) {
   int K = s->cands;
   double x = orc_node(p->x_lo, p->x_hi, p->n_x, i);
   double* c = (double*)malloc(sizeof(double) * (size_t)(K + 1));
@@ -187,7 +197,7 @@ static double orc_argmin_point(const orc_problem* p, const orc_search* s,
   /* level 0: the global grid over [u_lo, u_hi] */
   for (int q = 0; q < K; ++q) {
     c[q] = s->u_lo + (double)q * h[0];
-    B[q] = orc_B(p, u1, x, c[q]);
+    B[q] = orc_model_B(model, lam, p, u1, x, c[q]);
   }
   int b = orc_select(K, c, B, u_inc);
   double cs = c[b], Bs = B[b];
@@ -195,7 +205,7 @@ static double orc_argmin_point(const orc_problem* p, const orc_search* s,
   for (int l = 1; l < s->levels; ++l) {
     for (int q = 0; q < K; ++q) {
       c[q] = orc_clamp(cs - h[l - 1] + (double)q * h[l], s->u_lo, s->u_hi);
-      B[q] = orc_B(p, u1, x, c[q]);
+      B[q] = orc_model_B(model, lam, p, u1, x, c[q]);
     }
     c[K] = cs;
     B[K] = Bs;
@@ -207,7 +217,7 @@ static double orc_argmin_point(const orc_problem* p, const orc_search* s,
   c[0] = cs;
   B[0] = Bs;
   c[1] = u_inc;
-  B[1] = orc_B(p, u1, x, u_inc);
+  B[1] = orc_model_B(model, lam, p, u1, x, u_inc);
   b = orc_select(2, c, B, u_inc);
   double r = c[b];
   if (B_out) *B_out = B[b];
@@ -216,11 +226,12 @@ static double orc_argmin_point(const orc_problem* p, const orc_search* s,
   return r;
 }
 
-/* One u0 update over the listed points (rows == NULL: every point).
- * u0_out[r] and B_out[r] are indexed like rows. */
-void orc_argmin(const orc_problem* p, const orc_search* s, const double* u1,
-                const double* u0_in, const int64_t* rows, int64_t n_rows,
-                double* u0_out, double* B_out) {
+/* One u0 update over the listed points (rows == NULL: every point) of
+ * model 0 or 1 (see orc_model_B).  u0_out[r] and B_out[r] are indexed like
+ * rows. */
+static void orc_argmin_model(const orc_problem* p, const orc_search* s, const double* u1,
+                             const double* u0_in, const int64_t* rows, int64_t n_rows,
+                             double* u0_out, double* B_out, int model, double lam) {
   double h[64];
   orc_spacings(s, h);
   int64_t n = rows ? n_rows : p->n_x;
@@ -228,9 +239,15 @@ void orc_argmin(const orc_problem* p, const orc_search* s, const double* u1,
   for (int64_t r = 0; r < n; ++r) {
     int64_t i = rows ? rows[r] : r;
     double Bv;
-    u0_out[r] = orc_argmin_point(p, s, u1, h, i, u0_in[i], &Bv);
+    u0_out[r] = orc_argmin_point(p, s, u1, h, i, u0_in[i], &Bv, model, lam);
     if (B_out) B_out[r] = Bv;
   }
+}
+
+void orc_argmin(const orc_problem* p, const orc_search* s, const double* u1,
+                const double* u0_in, const int64_t* rows, int64_t n_rows,
+                double* u0_out, double* B_out) {
+  orc_argmin_model(p, s, u1, u0_in, rows, n_rows, u0_out, B_out, 0, 0.0);
 }
 
 /* Second controller by its closed form: u1(y) = E[x1 | y1 = y], the exact
@@ -313,6 +330,127 @@ void orc_solve(const orc_problem* p, const orc_search* s, int32_t iters,
     memcpy(u0, nxt, sizeof(double) * (size_t)p->n_x);
     orc_update_u1(p, u0, NULL, 0, u1_out);
     J_hist[t] = orc_objective(p, u0, u1_out);
+  }
+  memcpy(u0_out, u0, sizeof(double) * (size_t)p->n_x);
+  free(u0);
+  free(nxt);
+}
+
+/* ------------------------------------------------------------------------
+ * Zero-delay source-channel coding (Section V-B): x0 ~ prior f (the
+ * paper's N(0,1), or a mixture), y0 = x0, x1 = u0(y0) + w with
+ * w ~ U(-1, 1), y1 = x1, J = E[lam u0(y0)^2 + (u1(y1) - x0)^2].
+ * The same grids and rectangle rule as above; p->k is not used, the stage-0
+ * weight is lam.  Parity status: pinned by the CPU tests (zero and one-bit
+ * encoders against their closed forms, the linear decoder's minimiser,
+ * J = dx sum f B, and u1 as the minimiser of J over u1).
+ * ------------------------------------------------------------------------ */
+
+/* Density of w ~ U(-1, 1): 1/2 on the closed interval |t| <= 1, else 0.
+ * (The interval's end points carry no probability; taking them in is a
+ * reading, and it decides which grid nodes a window holds.) */
+static double orc_box(double t) { return fabs(t) <= 1.0 ? 0.5 : 0.0; }
+
+/* B(u; x) = L_0(u, x) / f(x) for the coding objective (Section III-A,
+ * marginal cost C_0): lam u^2 + integral over y of p_w(y - u)(u1(y) - x)^2,
+ * by the rectangle rule over every y node in index order. */
+double orc_cd_B(const orc_problem* p, double lam, const double* u1, double x, double u) {
+  double dy = (p->y_hi - p->y_lo) / (double)(p->n_y - 1);
+  double s = 0.0;
+  for (int64_t j = 0; j < p->n_y; ++j) {
+    double y = orc_node(p->y_lo, p->y_hi, p->n_y, j);
+    double e = u1[j] - x;
+    s += orc_box(y - u) * e * e;
+  }
+  return lam * u * u + dy * s;
+}
+
+/* L_0(u; x_i) = f_i B(u; x_i) for candidates u [n_x][n_cand]. */
+void orc_cd_marginal_cost(const orc_problem* p, double lam, const double* u1, const double* u,
+                          int64_t n_cand, double* out) {
+  double* f = (double*)malloc(sizeof(double) * (size_t)p->n_x);
+  orc_prior(p, f, NULL);
+#pragma omp parallel for schedule(static)
+  for (int64_t i = 0; i < p->n_x; ++i) {
+    double x = orc_node(p->x_lo, p->x_hi, p->n_x, i);
+    for (int64_t c = 0; c < n_cand; ++c)
+      out[i * n_cand + c] = f[i] * orc_cd_B(p, lam, u1, x, u[i * n_cand + c]);
+  }
+  free(f);
+}
+
+/* The coarse-to-fine u0 update of the Witsenhausen case with the coding
+ * B: the same levels, selection rule and incumbent comparison. */
+void orc_cd_argmin(const orc_problem* p, double lam, const orc_search* s, const double* u1,
+                   const double* u0_in, const int64_t* rows, int64_t n_rows,
+                   double* u0_out, double* B_out) {
+  orc_argmin_model(p, s, u1, u0_in, rows, n_rows, u0_out, B_out, 1, lam);
+}
+
+/* Second controller by its closed form, the conditional mean
+ * u1(y_j) = E[x0 | x1 = y_j] = sum_i f_i p_w(y_j - u0_i) x_i / sum_i f_i p_w(y_j - u0_i),
+ * the minimiser of the discrete marginal cost C_1(v, y_j).  Where no node
+ * has |y_j - u0_i| <= 1 the ratio is undefined (such y_j carry no
+ * probability): u1_j = 0 there, a reading.  rows as in orc_update_u1. */
+void orc_cd_update_u1(const orc_problem* p, const double* u0, const int64_t* rows,
+                      int64_t n_rows, double* u1_out) {
+  double* f = (double*)malloc(sizeof(double) * (size_t)p->n_x);
+  orc_prior(p, f, NULL);
+  int64_t n = rows ? n_rows : p->n_y;
+#pragma omp parallel for schedule(static)
+  for (int64_t r = 0; r < n; ++r) {
+    int64_t j = rows ? rows[r] : r;
+    double y = orc_node(p->y_lo, p->y_hi, p->n_y, j);
+    double num = 0.0, den = 0.0;
+    for (int64_t i = 0; i < p->n_x; ++i) {
+      double wgt = f[i] * orc_box(y - u0[i]);
+      num += wgt * orc_node(p->x_lo, p->x_hi, p->n_x, i);
+      den += wgt;
+    }
+    u1_out[r] = den > 0.0 ? num / den : 0.0;
+  }
+  free(f);
+}
+
+/* Objective of Section V-B by the rectangle rule:
+ * J = dx * sum_i f_i [lam u0_i^2 + dy * sum_j p_w(y_j - u0_i)(u1_j - x_i)^2]. */
+double orc_cd_objective(const orc_problem* p, double lam, const double* u0, const double* u1) {
+  double dx = (p->x_hi - p->x_lo) / (double)(p->n_x - 1);
+  double dy = (p->y_hi - p->y_lo) / (double)(p->n_y - 1);
+  double* f = (double*)malloc(sizeof(double) * (size_t)p->n_x);
+  double* row = (double*)malloc(sizeof(double) * (size_t)p->n_x);
+  orc_prior(p, f, NULL);
+#pragma omp parallel for schedule(static)
+  for (int64_t i = 0; i < p->n_x; ++i) {
+    double x = orc_node(p->x_lo, p->x_hi, p->n_x, i);
+    double s = 0.0;
+    for (int64_t j = 0; j < p->n_y; ++j) {
+      double y = orc_node(p->y_lo, p->y_hi, p->n_y, j);
+      double e = u1[j] - x;
+      s += orc_box(y - u0[i]) * e * e;
+    }
+    row[i] = f[i] * (lam * u0[i] * u0[i] + dy * s);
+  }
+  double J = 0.0;
+  for (int64_t i = 0; i < p->n_x; ++i) J += row[i];
+  free(f);
+  free(row);
+  return dx * J;
+}
+
+/* The solve loop of orc_solve for the coding problem. */
+void orc_cd_solve(const orc_problem* p, double lam, const orc_search* s, int32_t iters,
+                  const double* u0_init, double* u0_out, double* u1_out, double* J_hist) {
+  double* u0 = (double*)malloc(sizeof(double) * (size_t)p->n_x);
+  double* nxt = (double*)malloc(sizeof(double) * (size_t)p->n_x);
+  memcpy(u0, u0_init, sizeof(double) * (size_t)p->n_x);
+  orc_cd_update_u1(p, u0, NULL, 0, u1_out);
+  J_hist[0] = orc_cd_objective(p, lam, u0, u1_out);
+  for (int32_t t = 1; t <= iters; ++t) {
+    orc_cd_argmin(p, lam, s, u1_out, u0, NULL, 0, nxt, NULL);
+    memcpy(u0, nxt, sizeof(double) * (size_t)p->n_x);
+    orc_cd_update_u1(p, u0, NULL, 0, u1_out);
+    J_hist[t] = orc_cd_objective(p, lam, u0, u1_out);
   }
   memcpy(u0_out, u0, sizeof(double) * (size_t)p->n_x);
   free(u0);

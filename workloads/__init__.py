@@ -163,3 +163,59 @@ def mixture_case(s: int, n: int = 65536, levels: int = 4, cands: int = 32, iters
 
 def mixture_batch(n_inst: int = 64, n: int = 65536) -> List[Case]:
     return [mixture_case(s, n) for s in range(n_inst)]
+
+
+# --- zero-delay source-channel coding (Section V-B) ------------------------
+# x0 ~ N(0, 1), x1 = u0(x0) + w with w ~ U(-1, 1), stage-0 weight lam; the
+# paper's figure uses lam = 2.
+
+@dataclass
+class CodingProblem:
+    lam: float
+    comps: Sequence[Tuple[float, float, float]]
+    x_lo: float
+    x_hi: float
+    n_x: int
+    y_lo: float
+    y_hi: float
+    n_y: int
+
+
+@dataclass
+class CodingCase:
+    name: str
+    prob: CodingProblem
+    search: Search
+    iters: int
+    u0_init: np.ndarray = field(repr=False)
+
+
+def coding_problem(n_x: int, n_y: int, lam: float = 2.0, comps=((1.0, 0.0, 1.0),)) -> CodingProblem:
+    """x grid [-8, 8] (prior tail below 1e-14), y grid [-5, 5] (encoder
+    range [-4, 4] plus the noise's reach)."""
+    return CodingProblem(lam=lam, comps=list(comps), x_lo=-8.0, x_hi=8.0, n_x=n_x,
+                         y_lo=-5.0, y_hi=5.0, n_y=n_y)
+
+
+def coding_init(prob: CodingProblem, seed: int = 0, steps: int = 6) -> np.ndarray:
+    """Piecewise-constant encoder: breakpoints sorted uniform on [-3, 3],
+    levels sorted uniform on [-2.5, 2.5] (a monotone quantiser)."""
+    rng = np.random.default_rng(seed)
+    bp = np.sort(rng.uniform(-3.0, 3.0, steps - 1))
+    vals = np.sort(rng.uniform(-2.5, 2.5, steps))
+    x = nodes(prob.x_lo, prob.x_hi, prob.n_x)
+    return vals[np.searchsorted(bp, x, side="right")]
+
+
+def coding_small_case() -> CodingCase:
+    """801 x-nodes, 1201 y-nodes (ragged against 256-wide tiles);
+    3 levels x 9 candidates on [-4, 4]; 4 rounds."""
+    p = coding_problem(801, 1201)
+    return CodingCase("coding-801x1201-3x9", p, Search(-4.0, 4.0, 3, 9), 4, coding_init(p, 1))
+
+
+def coding_paper_case(n: int = 20001, iters: int = 30) -> CodingCase:
+    """lam = 2 (the paper's figure), 20001-node grids, the 5 x 16 search of
+    the Witsenhausen runs on [-4, 4], 30 rounds."""
+    p = coding_problem(n, n)
+    return CodingCase(f"coding-{n}-5x16", p, Search(-4.0, 4.0, 5, 16), iters, coding_init(p, 0))
