@@ -201,6 +201,74 @@ int ucp_solve_batch(ucp_handle* h, int32_t B, const ucp_problem* probs,
                     const double* const* u0_init, double* const* u0_out,
                     double* const* u1_out, double* const* J_hist, void* stream);
 
+/* ---- Zero-delay source-channel coding (Section V-B) --------------------
+ * x0 ~ prior f (the paper's N(0, 1), or a Gaussian mixture), y0 = x0,
+ * x1 = u0(y0) + w with w ~ U(-1, 1), y1 = x1; minimise
+ * J = E[lam u0(y0)^2 + (u1(y1) - x0)^2] (the paper's figure: lam = 2).
+ * The same grids, rectangle rule, conventions and error codes as above; the
+ * noise density is p_w(t) = 1/2 for |t| <= 1 (end points included) and 0
+ * otherwise, the test evaluated in binary64 as fabs(y_j - v) <= 1 with
+ * y_j = y_lo + j * dy.  Everything is FP64. */
+typedef struct ucp_coding_problem {
+  double lam; /* weight of the encoder's power, finite and >= 0 */
+  int32_t n_comp;
+  int32_t pad_;
+  double w[UCP_MAX_COMP];
+  double mu[UCP_MAX_COMP];
+  double sd[UCP_MAX_COMP];
+  double x_lo, x_hi;
+  int64_t n_x;
+  double y_lo, y_hi;
+  int64_t n_y;
+} ucp_coding_problem;
+
+/* Marginal cost of the encoder (Section III-A, C_0 of the coding
+ * objective):
+ *   L0_out[i*n_cand + c] = f(x_i) * ( lam u^2
+ *        + dy * sum_j p_w(y_j - u) (u1[j] - x_i)^2 ),  u = u[i*n_cand + c].
+ * The window sum is taken from double-double prefix sums of u1 and u1^2
+ * over the nodes with |y_j - u| <= 1 (exact window membership).
+ * u1: [n_y]; u: [n_x * n_cand]; L0_out: [n_x * n_cand].
+ * Errors: UCP_EINVAL (null pointers, n_cand outside 1..4096, invalid
+ * problem). */
+int ucp_coding_marginal_cost(ucp_handle* h, const ucp_coding_problem* prob, const double* u1,
+                             const double* u, int64_t n_cand, double* L0_out, void* stream);
+
+/* One pointwise improvement of u0 with u1 fixed: the coarse-to-fine search
+ * and the selection rule of ucp_argmin_adaptive (relative tie band 1e-12,
+ * nearest to u0_in[i], then the smaller u; the incumbent compared last),
+ * every B evaluated in FP64 as in ucp_coding_marginal_cost.
+ * u1: [n_y]; u0_in, u0_out: [n_x] (may alias); L0_out: [n_x] or NULL
+ * (receives f(x_i) B(u0_out[i]; x_i)).  Errors: UCP_EINVAL. */
+int ucp_coding_argmin(ucp_handle* h, const ucp_coding_problem* prob, const ucp_search* search,
+                      const double* u1, const double* u0_in, double* u0_out, double* L0_out,
+                      void* stream);
+
+/* Decoder by its closed form, the conditional mean
+ * u1(y_j) = sum_i f_i p_w(y_j - u0_i) x_i / sum_i f_i p_w(y_j - u0_i),
+ * and u1(y_j) = 0 where no x node has |y_j - u0_i| <= 1 (no probability
+ * reaches y_j).  u0: [n_x]; u1_out: [n_y].  Errors: UCP_EINVAL. */
+int ucp_coding_update_u1(ucp_handle* h, const ucp_coding_problem* prob, const double* u0,
+                         double* u1_out, void* stream);
+
+/* Objective of Section V-B by the rectangle rule, in FP64:
+ * J = dx * sum_i f_i [lam u0_i^2 + dy * sum_j p_w(y_j - u0_i)(u1_j - x_i)^2].
+ * u0: [n_x]; u1: [n_y]; J_out: one double on the device.  Errors: UCP_EINVAL. */
+int ucp_coding_objective(ucp_handle* h, const ucp_coding_problem* prob, const double* u0,
+                         const double* u1, double* J_out, void* stream);
+
+/* The solve loop of ucp_solve for the coding problem: u1 <- closed form of
+ * u0_init, J_hist[0] = J, then `iters` rounds of (ucp_coding_argmin,
+ * ucp_coding_update_u1) with J_hist[t] after round t.  Under ucp_profile
+ * the launches are timed with the kinds UCP_PROF_MC (the u0 search),
+ * UCP_PROF_SELECT (the prefix sums), UCP_PROF_U1 and UCP_PROF_J, and the
+ * call synchronises the stream before returning; otherwise it does not.
+ * u0_init, u0_out: [n_x] (may alias); u1_out: [n_y]; J_hist: [iters + 1].
+ * Errors: UCP_EINVAL. */
+int ucp_coding_solve(ucp_handle* h, const ucp_coding_problem* prob, const ucp_search* search,
+                     int32_t iters, const double* u0_init, double* u0_out, double* u1_out,
+                     double* J_hist, void* stream);
+
 /* ---- Continuous-batching server --------------------------------------
  * Requests (HOST arrays) are admitted while the number of running solves is
  * below `max_slots` and their device footprint fits in `hbm_budget` bytes;

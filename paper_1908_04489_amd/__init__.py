@@ -43,6 +43,15 @@ class Problem(C.Structure):
     ]
 
 
+class CodingProblem(C.Structure):
+    _fields_ = [
+        ("lam", C.c_double), ("n_comp", C.c_int32), ("pad_", C.c_int32),
+        ("w", C.c_double * MAX_COMP), ("mu", C.c_double * MAX_COMP), ("sd", C.c_double * MAX_COMP),
+        ("x_lo", C.c_double), ("x_hi", C.c_double), ("n_x", C.c_int64),
+        ("y_lo", C.c_double), ("y_hi", C.c_double), ("n_y", C.c_int64),
+    ]
+
+
 class Search(C.Structure):
     _fields_ = [("u_lo", C.c_double), ("u_hi", C.c_double), ("levels", C.c_int32), ("cands", C.c_int32)]
 
@@ -70,6 +79,11 @@ _sigs = {
     "ucp_profile_read": ([_vp, C.c_int, _P(C.c_double), _P(C.c_int64)], C.c_int),
     "ucp_last_counts": ([_vp, _P(C.c_uint64), _P(C.c_uint64), _P(C.c_uint64)], C.c_int),
     "ucp_footprint": ([_P(Problem), _P(Search), C.c_int, C.c_int32, _P(C.c_size_t)], C.c_int),
+    "ucp_coding_marginal_cost": ([_vp, _P(CodingProblem), _vp, _vp, C.c_int64, _vp, _vp], C.c_int),
+    "ucp_coding_argmin": ([_vp, _P(CodingProblem), _P(Search), _vp, _vp, _vp, _vp, _vp], C.c_int),
+    "ucp_coding_update_u1": ([_vp, _P(CodingProblem), _vp, _vp, _vp], C.c_int),
+    "ucp_coding_objective": ([_vp, _P(CodingProblem), _vp, _vp, _vp, _vp], C.c_int),
+    "ucp_coding_solve": ([_vp, _P(CodingProblem), _P(Search), C.c_int32, _vp, _vp, _vp, _vp, _vp], C.c_int),
     "ucp_server_create": ([_P(_vp), C.c_int, C.c_size_t, C.c_int32, C.c_int], C.c_int),
     "ucp_server_destroy": ([_vp], None),
     "ucp_server_submit": ([_vp, _P(Problem), _P(Search), C.c_int32, _vp, _P(C.c_int64)], C.c_int),
@@ -372,3 +386,88 @@ class Server:
         q, r, d = C.c_int32(), C.c_int32(), C.c_int32()
         _check(_lib.ucp_server_stats(self._s, C.byref(q), C.byref(r), C.byref(d)))
         return q.value, r.value, d.value
+
+
+# ------------------------------------------- source-channel coding (Section V-B)
+
+def make_coding_problem(p) -> CodingProblem:
+    """From a duck-typed problem with ``lam`` (weight of the encoder's power)
+    and the fields of ``make_problem`` other than ``k``."""
+    comps = list(p.comps)
+    s = CodingProblem()
+    s.lam = float(p.lam)
+    s.n_comp = len(comps)
+    for c, (w, mu, sd) in enumerate(comps):
+        s.w[c], s.mu[c], s.sd[c] = float(w), float(mu), float(sd)
+    s.x_lo, s.x_hi, s.n_x = float(p.x_lo), float(p.x_hi), int(p.n_x)
+    s.y_lo, s.y_hi, s.n_y = float(p.y_lo), float(p.y_hi), int(p.n_y)
+    return s
+
+
+def coding_marginal_cost(prob, u1, u):
+    """L_0 = f(x_i) B(u; x_i) for candidates u [n_x, n_cand] (device, FP64)."""
+    torch = _torch()
+    P = make_coding_problem(prob)
+    _dev_f64(u1, P.n_y, "u1")
+    _dev_f64(u, None, "u")
+    if u.dim() != 2 or u.shape[0] != P.n_x:
+        raise ValueError("u must be [n_x, n_cand]")
+    out = torch.empty_like(u)
+    d = _dev(u1)
+    _check(_lib.ucp_coding_marginal_cost(handle(d), C.byref(P), _vp(u1.data_ptr()), _vp(u.data_ptr()),
+                                         u.shape[1], _vp(out.data_ptr()), _stream(d)))
+    return out
+
+
+def coding_argmin(prob, search, u1, u0, want_l0=False):
+    """One coarse-to-fine encoder update with u1 fixed.  Returns u0_out (and L0)."""
+    torch = _torch()
+    P, S = make_coding_problem(prob), make_search(search)
+    _dev_f64(u1, P.n_y, "u1")
+    _dev_f64(u0, P.n_x, "u0")
+    out = torch.empty_like(u0)
+    l0 = torch.empty_like(u0) if want_l0 else None
+    d = _dev(u0)
+    _check(_lib.ucp_coding_argmin(handle(d), C.byref(P), C.byref(S), _vp(u1.data_ptr()), _vp(u0.data_ptr()),
+                                  _vp(out.data_ptr()), _vp(l0.data_ptr() if l0 is not None else 0),
+                                  _stream(d)))
+    return (out, l0) if want_l0 else out
+
+
+def coding_update_u1(prob, u0):
+    torch = _torch()
+    P = make_coding_problem(prob)
+    _dev_f64(u0, P.n_x, "u0")
+    out = torch.empty(P.n_y, dtype=torch.float64, device=u0.device)
+    d = _dev(u0)
+    _check(_lib.ucp_coding_update_u1(handle(d), C.byref(P), _vp(u0.data_ptr()), _vp(out.data_ptr()),
+                                     _stream(d)))
+    return out
+
+
+def coding_objective(prob, u0, u1):
+    """J as a 1-element device tensor (FP64)."""
+    torch = _torch()
+    P = make_coding_problem(prob)
+    _dev_f64(u0, P.n_x, "u0")
+    _dev_f64(u1, P.n_y, "u1")
+    out = torch.empty(1, dtype=torch.float64, device=u0.device)
+    d = _dev(u0)
+    _check(_lib.ucp_coding_objective(handle(d), C.byref(P), _vp(u0.data_ptr()), _vp(u1.data_ptr()),
+                                     _vp(out.data_ptr()), _stream(d)))
+    return out
+
+
+def coding_solve(prob, search, iters, u0_init):
+    """Returns (u0, u1, J_hist[iters + 1]) as device tensors."""
+    torch = _torch()
+    P, S = make_coding_problem(prob), make_search(search)
+    _dev_f64(u0_init, P.n_x, "u0_init")
+    dev = u0_init.device
+    u0 = torch.empty(P.n_x, dtype=torch.float64, device=dev)
+    u1 = torch.empty(P.n_y, dtype=torch.float64, device=dev)
+    J = torch.empty(int(iters) + 1, dtype=torch.float64, device=dev)
+    d = _dev(u0_init)
+    _check(_lib.ucp_coding_solve(handle(d), C.byref(P), C.byref(S), int(iters), _vp(u0_init.data_ptr()),
+                                 _vp(u0.data_ptr()), _vp(u1.data_ptr()), _vp(J.data_ptr()), _stream(d)))
+    return u0, u1, J

@@ -291,6 +291,25 @@ static void prof_harvest(ucp_handle* h) {
   h->ev_used = 0;
 }
 
+namespace ucp {
+// Access to the handle for the entry points defined in other files.
+int handle_device(ucp_handle* h) { return h->device; }
+int handle_workspace(ucp_handle* h, size_t bytes, void** out) {
+  int rc = ensure_ws(h, bytes);
+  if (rc == UCP_OK) *out = h->ws;
+  return rc;
+}
+hipError_t handle_events(ucp_handle* h, int kind, hipEvent_t* a, hipEvent_t* b) {
+  EvPair p;
+  hipError_t e = prof_pair(h, kind, true, p);
+  *a = p.a;
+  *b = p.b;
+  return e;
+}
+bool handle_profiling(ucp_handle* h) { return h->prof != 0; }
+void handle_harvest(ucp_handle* h) { prof_harvest(h); }
+}  // namespace ucp
+
 extern "C" {
 
 int ucp_profile(ucp_handle* h, int enable) {

@@ -1,0 +1,647 @@
+// Zero-delay source-channel coding (Section V-B) on the device, all FP64:
+// x0 ~ prior f, x1 = u0(x0) + w with w ~ U(-1, 1), y1 = x1,
+// J = E[lam u0(x0)^2 + (u1(y1) - x0)^2].
+//
+// The uniform noise turns every window sum into a box: the marginal cost of
+// a candidate u needs the sums of u1 and u1^2 over the y nodes within 1 of
+// u, which double-double prefix sums give in O(1).  So the encoder search is
+// one thread per point walking all levels of the coarse-to-fine search, and
+// the decoder's closed form (a box-filtered conditional mean over the x
+// nodes) is the only quadratic-cost step.
+//
+//   k_cd_prior    f and f x at the x nodes
+//   k_cd_prefix   double-double prefix sums of u1 and u1^2 (one block)
+//   k_cd_search   per point: the coarse-to-fine search of B(u; x_i)
+//   k_cd_mc       L_0 = f B for explicit candidates
+//   k_cd_extent   min and max of u0 over tiles of x nodes
+//   k_cd_u1_part  decoder sums for 64 y nodes over one segment of x nodes
+//   k_cd_u1_fin   segment partials added in order; the ratio
+//   k_cd_jrows / k_cd_jsum   objective rows, one wave per x node; their sum
+#include <hip/hip_runtime.h>
+#include <hip/hip_ext.h>
+
+#include <cmath>
+#include <cstring>
+
+#include "ucp.h"
+#include "ucp_runtime.h"
+
+namespace ucp {
+namespace {
+
+constexpr int kCdTile = 256;    // x nodes per extent tile and per LDS stage
+constexpr int kCdSegMin = 2048; // x nodes per decoder segment (at least)
+constexpr int kCdSegMax = 16;   // decoder segments (at most)
+constexpr int kCdYGrp = 64;     // y nodes per decoder wave
+constexpr int kCdScan = 1024;   // threads of the prefix-sum block
+constexpr double kCdCull = 1.0 + 1e-6;  // tile culling distance (exact test inside)
+
+struct CdParams {
+  double lam;
+  int n_comp;
+  int n_x, n_y;
+  double w[UCP_MAX_COMP], mu[UCP_MAX_COMP], sd[UCP_MAX_COMP];
+  double x_lo, dx;  // x node i = x_lo + i * dx
+  double y_lo, dy;  // y node j = y_lo + j * dy
+  double u_lo, u_hi;
+  int levels, cands;
+  double h[UCP_MAX_LEVELS];  // candidate spacing per level
+  int seg_tiles;             // decoder segment length in tiles
+  int n_seg;                 // decoder segments
+};
+
+// ------------------------------------------------------------ arithmetic
+
+struct dd {
+  double h, l;
+};
+__device__ __forceinline__ dd two_sum(double a, double b) {
+  const double s = a + b;
+  const double bb = s - a;
+  return {s, (a - (s - bb)) + (b - bb)};
+}
+__device__ __forceinline__ dd fast_two_sum(double a, double b) {
+  const double s = a + b;
+  return {s, b - (s - a)};
+}
+__device__ __forceinline__ dd two_prod(double a, double b) {
+  const double p = a * b;
+  return {p, fma(a, b, -p)};
+}
+__device__ __forceinline__ dd dd_add(dd a, dd b) {
+  dd s = two_sum(a.h, b.h);
+  return fast_two_sum(s.h, s.l + (a.l + b.l));
+}
+__device__ __forceinline__ dd dd_mul_d(dd a, double d) {
+  dd p = two_prod(a.h, d);
+  return fast_two_sum(p.h, p.l + a.l * d);
+}
+
+__device__ __forceinline__ double xnode(const CdParams& P, int i) { return P.x_lo + (double)i * P.dx; }
+__device__ __forceinline__ double ynode(const CdParams& P, int j) { return P.y_lo + (double)j * P.dy; }
+
+// Noise support test of the density p_w(y_j - v): |y_j - v| <= 1.
+__device__ __forceinline__ bool in_box(const CdParams& P, int j, double v) {
+  return fabs(ynode(P, j) - v) <= 1.0;
+}
+
+// The y nodes with |y_j - v| <= 1 form one index interval [a, b] (b < a
+// when empty): the rounded difference is monotone in j.  The estimate from
+// the grid spacing is corrected by walking with the exact test; the walks
+// move monotonically within [-1, n_y], so they end.
+__device__ void box_window(const CdParams& P, double v, int& a, int& b) {
+  const int n = P.n_y;
+  double ta = (v - 1.0 - P.y_lo) / P.dy;
+  double tb = (v + 1.0 - P.y_lo) / P.dy;
+  ta = fmin(fmax(ta, 0.0), (double)(n - 1));
+  tb = fmin(fmax(tb, 0.0), (double)(n - 1));
+  int ja = (int)ceil(ta), jb = (int)floor(tb);
+  // lower end: step down over window nodes and nodes above v, then up over
+  // nodes below the window
+  while (ja > 0 && (in_box(P, ja - 1, v) || ynode(P, ja - 1) > v)) --ja;
+  while (ja < n && !in_box(P, ja, v) && ynode(P, ja) < v) ++ja;
+  // upper end: the mirror image
+  while (jb < n - 1 && (in_box(P, jb + 1, v) || ynode(P, jb + 1) < v)) ++jb;
+  while (jb >= 0 && !in_box(P, jb, v) && ynode(P, jb) > v) --jb;
+  a = ja;
+  b = jb;
+}
+
+// B(u; x) = lam u^2 + dy * 1/2 * sum over the box window of (u1_j - x)^2,
+// the window sum expanded as S2 - 2 x S1 + n x^2 in double-double from the
+// prefix sums S (four arrays of n_y + 1: S1 high, S1 low, S2 high, S2 low;
+// entry j = sum over the nodes below j).
+__device__ double cd_B(const CdParams& P, const double* __restrict__ S, double x, double u) {
+  int a, b;
+  box_window(P, u, a, b);
+  double s = 0.0;
+  if (b >= a) {
+    const int n1 = P.n_y + 1;
+    const dd s1 = dd_add({S[b + 1], S[n1 + b + 1]}, {-S[a], -S[n1 + a]});
+    const dd s2 = dd_add({S[2 * n1 + b + 1], S[3 * n1 + b + 1]}, {-S[2 * n1 + a], -S[3 * n1 + a]});
+    dd t = dd_add(s2, dd_mul_d(s1, -2.0 * x));
+    t = dd_add(t, dd_mul_d(two_prod(x, x), (double)(b - a + 1)));
+    s = 0.5 * (t.h + t.l);
+  }
+  return P.lam * u * u + P.dy * s;
+}
+
+// ---------------------------------------------------------------- kernels
+
+__global__ __launch_bounds__(256) void k_cd_prior(CdParams P, double* __restrict__ f, double* __restrict__ fx) {
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i >= P.n_x) return;
+  const double x = xnode(P, i);
+  const double r2pi = sqrt(2.0 * 3.14159265358979323846);
+  double sum = 0.0;
+  for (int c = 0; c < P.n_comp; ++c) {
+    const double d = (x - P.mu[c]) / P.sd[c];
+    sum += P.w[c] * exp(-0.5 * d * d) / (P.sd[c] * r2pi);
+  }
+  f[i] = sum;
+  fx[i] = sum * x;
+}
+
+// One block: thread t sums a contiguous chunk of nodes, the chunk totals are
+// scanned in LDS (Hillis-Steele, double-double), then every thread writes
+// its chunk's running prefix.
+__global__ __launch_bounds__(kCdScan) void k_cd_prefix(int n, const double* __restrict__ u1,
+                                                         double* __restrict__ S) {
+  __shared__ double sh[4][kCdScan];
+  const int t = threadIdx.x;
+  const int chunk = (n + kCdScan - 1) / kCdScan;
+  const int lo = min(n, t * chunk), hi = min(n, lo + chunk);
+  dd a1 = {0.0, 0.0}, a2 = {0.0, 0.0};
+  for (int j = lo; j < hi; ++j) {
+    const double v = u1[j];
+    a1 = dd_add(a1, {v, 0.0});
+    a2 = dd_add(a2, two_prod(v, v));
+  }
+  sh[0][t] = a1.h;
+  sh[1][t] = a1.l;
+  sh[2][t] = a2.h;
+  sh[3][t] = a2.l;
+  __syncthreads();
+  for (int o = 1; o < kCdScan; o <<= 1) {
+    const bool take = t >= o;
+    dd b1 = {0.0, 0.0}, b2 = {0.0, 0.0};
+    if (take) {
+      b1 = {sh[0][t - o], sh[1][t - o]};
+      b2 = {sh[2][t - o], sh[3][t - o]};
+    }
+    __syncthreads();
+    if (take) {
+      a1 = dd_add(b1, a1);
+      a2 = dd_add(b2, a2);
+      sh[0][t] = a1.h;
+      sh[1][t] = a1.l;
+      sh[2][t] = a2.h;
+      sh[3][t] = a2.l;
+    }
+    __syncthreads();
+  }
+  dd r1 = {0.0, 0.0}, r2 = {0.0, 0.0};
+  if (t > 0) {
+    r1 = {sh[0][t - 1], sh[1][t - 1]};
+    r2 = {sh[2][t - 1], sh[3][t - 1]};
+  }
+  const int n1 = n + 1;
+  if (t == 0) S[0] = S[n1] = S[2 * n1] = S[3 * n1] = 0.0;
+  for (int j = lo; j < hi; ++j) {
+    const double v = u1[j];
+    r1 = dd_add(r1, {v, 0.0});
+    r2 = dd_add(r2, two_prod(v, v));
+    S[j + 1] = r1.h;
+    S[n1 + j + 1] = r1.l;
+    S[2 * n1 + j + 1] = r2.h;
+    S[3 * n1 + j + 1] = r2.l;
+  }
+}
+
+// The selection rule: candidates with B within the relative band 1e-12 of
+// the minimum are ties; the one nearest the incumbent wins, then the
+// smaller u, then the earlier one.  Walked in candidate order by `best`.
+struct Pick {
+  bool any = false;
+  double c = 0.0, B = 0.0, d = 0.0;
+  __device__ void offer(double cu, double Bu, double thr, double uinc) {
+    if (!(Bu <= thr)) return;
+    const double du = fabs(cu - uinc);
+    if (!any || du < d || (du == d && cu < c)) {
+      any = true;
+      c = cu;
+      B = Bu;
+      d = du;
+    }
+  }
+};
+
+__device__ __forceinline__ double level_cand(const CdParams& P, int l, int q, double cs) {
+  if (l == 0) return P.u_lo + (double)q * P.h[0];
+  double v = cs - P.h[l - 1] + (double)q * P.h[l];
+  if (v < P.u_lo) v = P.u_lo;
+  if (v > P.u_hi) v = P.u_hi;
+  return v;
+}
+
+// One thread per point.  B is O(1), so each level takes two passes over
+// its candidates (the minimum, then the rule) instead of keeping them.
+// u0_in and u0_out may alias: a thread reads its own entry before writing it.
+__global__ __launch_bounds__(256) void k_cd_search(CdParams P, const double* __restrict__ S,
+                                                   const double* __restrict__ f, const double* u0_in,
+                                                   double* u0_out, double* L0_out) {
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i >= P.n_x) return;
+  const double x = xnode(P, i);
+  const double uinc = u0_in[i];
+  const int K = P.cands;
+  double cs = 0.0, Bs = 0.0;
+  for (int l = 0; l < P.levels; ++l) {
+    double m = cd_B(P, S, x, level_cand(P, l, 0, cs));
+    for (int q = 1; q < K; ++q) m = fmin(m, cd_B(P, S, x, level_cand(P, l, q, cs)));
+    if (l > 0 && Bs < m) m = Bs;
+    const double thr = m * (1.0 + 1e-12);
+    Pick pk;
+    for (int q = 0; q < K; ++q) {
+      const double c = level_cand(P, l, q, cs);
+      pk.offer(c, cd_B(P, S, x, c), thr, uinc);
+    }
+    if (l > 0) pk.offer(cs, Bs, thr, uinc);
+    cs = pk.c;
+    Bs = pk.B;
+  }
+  // acceptance against the incumbent
+  const double Binc = cd_B(P, S, x, uinc);
+  double m = Bs;
+  if (Binc < m) m = Binc;
+  const double thr = m * (1.0 + 1e-12);
+  Pick pk;
+  pk.offer(cs, Bs, thr, uinc);
+  pk.offer(uinc, Binc, thr, uinc);
+  u0_out[i] = pk.c;
+  if (L0_out) L0_out[i] = f[i] * pk.B;
+}
+
+__global__ __launch_bounds__(256) void k_cd_mc(CdParams P, const double* __restrict__ S,
+                                               const double* __restrict__ f, const double* __restrict__ u,
+                                               int n_cand, double* __restrict__ out) {
+  const long g = (long)blockIdx.x * 256 + threadIdx.x;
+  if (g >= (long)P.n_x * n_cand) return;
+  const int i = (int)(g / n_cand);
+  out[g] = f[i] * cd_B(P, S, xnode(P, i), u[g]);
+}
+
+__device__ __forceinline__ double wave_sum_d(double v) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+  return v;
+}
+
+// ext[2 t], ext[2 t + 1] = min and max of u0 over tile t (kCdTile nodes).
+__global__ __launch_bounds__(kCdTile) void k_cd_extent(int n_x, const double* __restrict__ u0,
+                                                       double* __restrict__ ext) {
+  __shared__ double smin[kCdTile / 64], smax[kCdTile / 64];
+  const int i = blockIdx.x * kCdTile + threadIdx.x;
+  double lo = INFINITY, hi = -INFINITY;
+  if (i < n_x) lo = hi = u0[i];
+  for (int o = 32; o > 0; o >>= 1) {
+    lo = fmin(lo, __shfl_xor(lo, o));
+    hi = fmax(hi, __shfl_xor(hi, o));
+  }
+  if ((threadIdx.x & 63) == 0) {
+    smin[threadIdx.x >> 6] = lo;
+    smax[threadIdx.x >> 6] = hi;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int k = 1; k < kCdTile / 64; ++k) {
+      lo = fmin(lo, smin[k]);
+      hi = fmax(hi, smax[k]);
+    }
+    ext[2 * blockIdx.x] = lo;
+    ext[2 * blockIdx.x + 1] = hi;
+  }
+}
+
+// One wave: 64 consecutive y nodes (lane = node) against the x nodes of
+// segment blockIdx.y, in ascending order, tile by tile through LDS; tiles
+// whose u0 range lies farther than 1 from the wave's y range are skipped
+// (the exact test decides inside).  part[(seg * n_y + j) * 2 + {0, 1}] =
+// (sum f x, sum f) over the nodes with |y_j - u0_i| <= 1.
+__global__ __launch_bounds__(kCdYGrp) void k_cd_u1_part(CdParams P, const double* __restrict__ u0,
+                                                        const double* __restrict__ f,
+                                                        const double* __restrict__ fx,
+                                                        const double* __restrict__ ext,
+                                                        double* __restrict__ part) {
+  __shared__ double su[kCdTile], sf[kCdTile], sfx[kCdTile];
+  const int j0 = blockIdx.x * kCdYGrp;
+  const int j = j0 + threadIdx.x;
+  const bool live = j < P.n_y;
+  const double y = ynode(P, live ? j : P.n_y - 1);
+  const double ya = ynode(P, j0), yb = ynode(P, min(P.n_y - 1, j0 + kCdYGrp - 1));
+  const int n_tiles = (P.n_x + kCdTile - 1) / kCdTile;
+  const int t0 = blockIdx.y * P.seg_tiles, t1 = min(n_tiles, t0 + P.seg_tiles);
+  double num = 0.0, den = 0.0;
+  for (int t = t0; t < t1; ++t) {
+    const double tmin = ext[2 * t], tmax = ext[2 * t + 1];
+    if (!(tmin - yb <= kCdCull) || !(ya - tmax <= kCdCull)) continue;  // also skips an all-NaN tile
+    const int i0 = t * kCdTile;
+    const int cnt = min(kCdTile, P.n_x - i0);
+    for (int k = threadIdx.x; k < cnt; k += kCdYGrp) {
+      su[k] = u0[i0 + k];
+      sf[k] = f[i0 + k];
+      sfx[k] = fx[i0 + k];
+    }
+    __syncthreads();
+    for (int k = 0; k < cnt; ++k) {
+      if (fabs(y - su[k]) <= 1.0) {
+        num += sfx[k];
+        den += sf[k];
+      }
+    }
+    __syncthreads();
+  }
+  if (live) {
+    const long o = ((long)blockIdx.y * P.n_y + j) * 2;
+    part[o] = num;
+    part[o + 1] = den;
+  }
+}
+
+__global__ __launch_bounds__(256) void k_cd_u1_fin(CdParams P, const double* __restrict__ part,
+                                                   double* __restrict__ u1) {
+  const int j = blockIdx.x * 256 + threadIdx.x;
+  if (j >= P.n_y) return;
+  double num = 0.0, den = 0.0;
+  for (int s = 0; s < P.n_seg; ++s) {
+    const long o = ((long)s * P.n_y + j) * 2;
+    num += part[o];
+    den += part[o + 1];
+  }
+  u1[j] = den > 0.0 ? num / den : 0.0;
+}
+
+// One wave per x node: the box window of u0_i, lanes strided over it.
+__global__ __launch_bounds__(256) void k_cd_jrows(CdParams P, const double* __restrict__ u0,
+                                                  const double* __restrict__ u1,
+                                                  const double* __restrict__ f, double* __restrict__ rows) {
+  const int i = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (i >= P.n_x) return;
+  const double x = xnode(P, i);
+  const double v = u0[i];
+  int a, b;
+  box_window(P, v, a, b);
+  double s = 0.0;
+  for (int j = a + lane; j <= b; j += 64) {
+    const double e = u1[j] - x;
+    s += e * e;
+  }
+  s = wave_sum_d(s);
+  if (lane == 0) rows[i] = f[i] * (P.lam * v * v + P.dy * (0.5 * s));
+}
+
+// J = dx * sum of the rows, in a fixed order (strided partials, then a tree).
+__global__ __launch_bounds__(256) void k_cd_jsum(int n, double dx, const double* __restrict__ rows,
+                                                 double* __restrict__ J) {
+  __shared__ double sh[256];
+  double s = 0.0;
+  for (int i = threadIdx.x; i < n; i += 256) s += rows[i];
+  sh[threadIdx.x] = s;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) sh[threadIdx.x] += sh[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *J = dx * sh[0];
+}
+
+// ------------------------------------------------------------------- host
+
+inline size_t al(size_t v) { return (v + 255) & ~(size_t)255; }
+
+struct CdWork {
+  double *f, *fx, *S, *ext, *part, *rows;
+};
+
+int cd_params(const ucp_coding_problem* p, const ucp_search* s, CdParams& P) {
+  if (!p) return fail(UCP_EINVAL, "problem is NULL");
+  if (!(p->lam >= 0.0) || !std::isfinite(p->lam)) return fail(UCP_EINVAL, "lam must be finite and >= 0");
+  ucp_problem q;
+  std::memset(&q, 0, sizeof q);
+  q.k = 0.0;
+  q.n_comp = p->n_comp;
+  std::memcpy(q.w, p->w, sizeof q.w);
+  std::memcpy(q.mu, p->mu, sizeof q.mu);
+  std::memcpy(q.sd, p->sd, sizeof q.sd);
+  q.x_lo = p->x_lo;
+  q.x_hi = p->x_hi;
+  q.n_x = p->n_x;
+  q.y_lo = p->y_lo;
+  q.y_hi = p->y_hi;
+  q.n_y = p->n_y;
+  int rc = check_problem(&q);
+  if (rc) return rc;
+  if (s && (rc = check_search(s))) return rc;
+  std::memset(&P, 0, sizeof P);
+  P.lam = p->lam;
+  P.n_comp = p->n_comp;
+  P.n_x = (int)p->n_x;
+  P.n_y = (int)p->n_y;
+  for (int c = 0; c < p->n_comp; ++c) {
+    P.w[c] = p->w[c];
+    P.mu[c] = p->mu[c];
+    P.sd[c] = p->sd[c];
+  }
+  P.x_lo = p->x_lo;
+  P.dx = (p->x_hi - p->x_lo) / (double)(p->n_x - 1);
+  P.y_lo = p->y_lo;
+  P.dy = (p->y_hi - p->y_lo) / (double)(p->n_y - 1);
+  if (s) {
+    P.u_lo = s->u_lo;
+    P.u_hi = s->u_hi;
+    P.levels = s->levels;
+    P.cands = s->cands;
+    P.h[0] = (s->u_hi - s->u_lo) / (double)(s->cands - 1);
+    for (int l = 1; l < s->levels; ++l) P.h[l] = 2.0 * P.h[l - 1] / (double)(s->cands - 1);
+  }
+  const int n_tiles = (P.n_x + kCdTile - 1) / kCdTile;
+  int n_seg = (P.n_x + kCdSegMin - 1) / kCdSegMin;
+  if (n_seg > kCdSegMax) n_seg = kCdSegMax;
+  P.seg_tiles = (n_tiles + n_seg - 1) / n_seg;
+  P.n_seg = (n_tiles + P.seg_tiles - 1) / P.seg_tiles;
+  return UCP_OK;
+}
+
+int cd_work(ucp_handle* h, const CdParams& P, CdWork& W) {
+  const size_t nx = (size_t)P.n_x, ny = (size_t)P.n_y;
+  const size_t n_tiles = (nx + kCdTile - 1) / kCdTile;
+  const size_t sz[6] = {al(8 * nx), al(8 * nx), al(8 * 4 * (ny + 1)), al(8 * 2 * n_tiles),
+                        al(8 * 2 * (size_t)P.n_seg * ny), al(8 * nx)};
+  size_t total = 0;
+  for (size_t v : sz) total += v;
+  void* base = nullptr;
+  int rc = handle_workspace(h, total, &base);
+  if (rc) return rc;
+  char* p = (char*)base;
+  double** slot[6] = {&W.f, &W.fx, &W.S, &W.ext, &W.part, &W.rows};
+  for (int k = 0; k < 6; ++k) {
+    *slot[k] = (double*)p;
+    p += sz[k];
+  }
+  return UCP_OK;
+}
+
+#define CD_TRY(expr, what)                      \
+  do {                                          \
+    hipError_t e_ = (expr);                     \
+    if (e_ != hipSuccess) return hip_fail(e_, what); \
+  } while (0)
+
+inline unsigned blocks(long n, int per) { return (unsigned)((n + per - 1) / per); }
+
+hipError_t cd_prior(const CdParams& P, const CdWork& W, hipStream_t st) {
+  hipLaunchKernelGGL(k_cd_prior, dim3(blocks(P.n_x, 256)), dim3(256), 0, st, P, W.f, W.fx);
+  return hipGetLastError();
+}
+
+hipError_t cd_prefix(ucp_handle* h, const CdParams& P, const CdWork& W, const double* u1, hipStream_t st) {
+  hipEvent_t a, b;
+  hipError_t e = handle_events(h, UCP_PROF_SELECT, &a, &b);
+  if (e != hipSuccess) return e;
+  hipExtLaunchKernelGGL(k_cd_prefix, dim3(1), dim3(kCdScan), 0, st, a, b, 0, P.n_y, u1, W.S);
+  return hipGetLastError();
+}
+
+hipError_t cd_search(ucp_handle* h, const CdParams& P, const CdWork& W, const double* u0_in, double* u0_out,
+                     double* L0_out, hipStream_t st) {
+  hipEvent_t a, b;
+  hipError_t e = handle_events(h, UCP_PROF_MC, &a, &b);
+  if (e != hipSuccess) return e;
+  hipExtLaunchKernelGGL(k_cd_search, dim3(blocks(P.n_x, 256)), dim3(256), 0, st, a, b, 0, P,
+                        (const double*)W.S, (const double*)W.f, u0_in, u0_out, L0_out);
+  return hipGetLastError();
+}
+
+hipError_t cd_u1(ucp_handle* h, const CdParams& P, const CdWork& W, const double* u0, double* u1,
+                 hipStream_t st) {
+  hipEvent_t a, b;
+  hipError_t e = handle_events(h, UCP_PROF_U1, &a, &b);
+  if (e != hipSuccess) return e;
+  const unsigned n_tiles = blocks(P.n_x, kCdTile);
+  hipExtLaunchKernelGGL(k_cd_extent, dim3(n_tiles), dim3(kCdTile), 0, st, a, nullptr, 0, P.n_x, u0, W.ext);
+  hipLaunchKernelGGL(k_cd_u1_part, dim3(blocks(P.n_y, kCdYGrp), P.n_seg), dim3(kCdYGrp), 0, st, P, u0,
+                     (const double*)W.f, (const double*)W.fx, (const double*)W.ext, W.part);
+  hipExtLaunchKernelGGL(k_cd_u1_fin, dim3(blocks(P.n_y, 256)), dim3(256), 0, st, nullptr, b, 0, P,
+                        (const double*)W.part, u1);
+  return hipGetLastError();
+}
+
+hipError_t cd_objective(ucp_handle* h, const CdParams& P, const CdWork& W, const double* u0, const double* u1,
+                        double* J, hipStream_t st) {
+  hipEvent_t a, b;
+  hipError_t e = handle_events(h, UCP_PROF_J, &a, &b);
+  if (e != hipSuccess) return e;
+  hipExtLaunchKernelGGL(k_cd_jrows, dim3(blocks(P.n_x, 4)), dim3(256), 0, st, a, nullptr, 0, P, u0, u1,
+                        (const double*)W.f, W.rows);
+  hipExtLaunchKernelGGL(k_cd_jsum, dim3(1), dim3(256), 0, st, nullptr, b, 0, P.n_x, P.dx,
+                        (const double*)W.rows, J);
+  return hipGetLastError();
+}
+
+// After the argument checks: the handle's device made current.
+int cd_begin(ucp_handle* h) {
+  hipError_t e = hipSetDevice(handle_device(h));
+  if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
+  return UCP_OK;
+}
+
+}  // namespace
+}  // namespace ucp
+
+using namespace ucp;
+
+extern "C" {
+
+int ucp_coding_marginal_cost(ucp_handle* h, const ucp_coding_problem* prob, const double* u1, const double* u,
+                             int64_t n_cand, double* L0_out, void* stream) {
+  int rc;
+  CdParams P;
+  if (!h) return fail(UCP_EINVAL, "handle is NULL");
+  if ((rc = cd_params(prob, nullptr, P))) return rc;
+  if (!u1 || !u || !L0_out) return fail(UCP_EINVAL, "NULL array argument");
+  if (n_cand < 1 || n_cand > 4096) return fail(UCP_EINVAL, "n_cand must be 1..4096");
+  if ((int64_t)P.n_x * n_cand > ((int64_t)1 << 30)) return fail(UCP_EINVAL, "n_x * n_cand too large");
+  if ((rc = cd_begin(h))) return rc;
+  CdWork W;
+  if ((rc = cd_work(h, P, W))) return rc;
+  hipStream_t st = (hipStream_t)stream;
+  CD_TRY(cd_prior(P, W, st), "prior kernel");
+  CD_TRY(cd_prefix(nullptr, P, W, u1, st), "prefix-sum kernel");
+  hipLaunchKernelGGL(k_cd_mc, dim3(blocks((long)P.n_x * n_cand, 256)), dim3(256), 0, st, P, (const double*)W.S,
+                     (const double*)W.f, u, (int)n_cand, L0_out);
+  CD_TRY(hipGetLastError(), "marginal-cost kernel");
+  return UCP_OK;
+}
+
+int ucp_coding_argmin(ucp_handle* h, const ucp_coding_problem* prob, const ucp_search* search, const double* u1,
+                      const double* u0_in, double* u0_out, double* L0_out, void* stream) {
+  int rc;
+  CdParams P;
+  if (!h) return fail(UCP_EINVAL, "handle is NULL");
+  if (!search) return fail(UCP_EINVAL, "search is NULL");
+  if ((rc = cd_params(prob, search, P))) return rc;
+  if (!u1 || !u0_in || !u0_out) return fail(UCP_EINVAL, "NULL array argument");
+  if ((rc = cd_begin(h))) return rc;
+  CdWork W;
+  if ((rc = cd_work(h, P, W))) return rc;
+  hipStream_t st = (hipStream_t)stream;
+  CD_TRY(cd_prior(P, W, st), "prior kernel");
+  CD_TRY(cd_prefix(nullptr, P, W, u1, st), "prefix-sum kernel");
+  CD_TRY(cd_search(nullptr, P, W, u0_in, u0_out, L0_out, st), "search kernel");
+  return UCP_OK;
+}
+
+int ucp_coding_update_u1(ucp_handle* h, const ucp_coding_problem* prob, const double* u0, double* u1_out,
+                         void* stream) {
+  int rc;
+  CdParams P;
+  if (!h) return fail(UCP_EINVAL, "handle is NULL");
+  if ((rc = cd_params(prob, nullptr, P))) return rc;
+  if (!u0 || !u1_out) return fail(UCP_EINVAL, "NULL array argument");
+  if ((rc = cd_begin(h))) return rc;
+  CdWork W;
+  if ((rc = cd_work(h, P, W))) return rc;
+  hipStream_t st = (hipStream_t)stream;
+  CD_TRY(cd_prior(P, W, st), "prior kernel");
+  CD_TRY(cd_u1(nullptr, P, W, u0, u1_out, st), "decoder kernels");
+  return UCP_OK;
+}
+
+int ucp_coding_objective(ucp_handle* h, const ucp_coding_problem* prob, const double* u0, const double* u1,
+                         double* J_out, void* stream) {
+  int rc;
+  CdParams P;
+  if (!h) return fail(UCP_EINVAL, "handle is NULL");
+  if ((rc = cd_params(prob, nullptr, P))) return rc;
+  if (!u0 || !u1 || !J_out) return fail(UCP_EINVAL, "NULL array argument");
+  if ((rc = cd_begin(h))) return rc;
+  CdWork W;
+  if ((rc = cd_work(h, P, W))) return rc;
+  hipStream_t st = (hipStream_t)stream;
+  CD_TRY(cd_prior(P, W, st), "prior kernel");
+  CD_TRY(cd_objective(nullptr, P, W, u0, u1, J_out, st), "objective kernels");
+  return UCP_OK;
+}
+
+int ucp_coding_solve(ucp_handle* h, const ucp_coding_problem* prob, const ucp_search* search, int32_t iters,
+                     const double* u0_init, double* u0_out, double* u1_out, double* J_hist, void* stream) {
+  int rc;
+  CdParams P;
+  if (!h) return fail(UCP_EINVAL, "handle is NULL");
+  if (!search) return fail(UCP_EINVAL, "search is NULL");
+  if ((rc = cd_params(prob, search, P))) return rc;
+  if (!u0_init || !u0_out || !u1_out || !J_hist) return fail(UCP_EINVAL, "NULL array argument");
+  if (iters < 0) return fail(UCP_EINVAL, "iters must be >= 0");
+  if ((rc = cd_begin(h))) return rc;
+  CdWork W;
+  if ((rc = cd_work(h, P, W))) return rc;
+  hipStream_t st = (hipStream_t)stream;
+  CD_TRY(cd_prior(P, W, st), "prior kernel");
+  if (u0_out != u0_init)
+    CD_TRY(hipMemcpyAsync(u0_out, u0_init, sizeof(double) * P.n_x, hipMemcpyDeviceToDevice, st), "copy u0");
+  CD_TRY(cd_u1(h, P, W, u0_out, u1_out, st), "decoder kernels");
+  CD_TRY(cd_objective(h, P, W, u0_out, u1_out, J_hist, st), "objective kernels");
+  for (int t = 1; t <= iters; ++t) {
+    CD_TRY(cd_prefix(h, P, W, u1_out, st), "prefix-sum kernel");
+    CD_TRY(cd_search(h, P, W, u0_out, u0_out, nullptr, st), "search kernel");
+    CD_TRY(cd_u1(h, P, W, u0_out, u1_out, st), "decoder kernels");
+    CD_TRY(cd_objective(h, P, W, u0_out, u1_out, J_hist + t, st), "objective kernels");
+  }
+  if (handle_profiling(h)) {
+    CD_TRY(hipStreamSynchronize(st), "synchronise");
+    handle_harvest(h);
+  }
+  return UCP_OK;
+}
+
+}  // extern "C"

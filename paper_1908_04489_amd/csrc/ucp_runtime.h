@@ -38,4 +38,15 @@ std::vector<int32_t> build_tables(const std::vector<Inst>& insts, const std::vec
 
 hipError_t launch_v_from_u1(const Launch& L, hipStream_t st);
 
+// The handle, for entry points defined outside ucp_api.cpp: its device, its
+// workspace (grown to at least `bytes`; earlier contents are lost when it
+// grows), and event pairs for timed launches (both null unless launches of
+// `kind` are being timed; handle_harvest adds up the recorded pairs once the
+// stream has been synchronised).
+int handle_device(ucp_handle* h);
+int handle_workspace(ucp_handle* h, size_t bytes, void** out);
+hipError_t handle_events(ucp_handle* h, int kind, hipEvent_t* a, hipEvent_t* b);
+bool handle_profiling(ucp_handle* h);
+void handle_harvest(ucp_handle* h);
+
 }  // namespace ucp

@@ -117,6 +117,44 @@ def test_invalid_problem_rejected_before_device_use(U):
     assert lib.ucp_solve_batch(fake, 0, C.byref(P), C.byref(S), 1, its, arr, arr, arr, arr, None) == U.EINVAL
 
 
+def test_coding_struct_and_argument_checks(U):
+    # ucp_coding_problem has the layout of ucp_problem with lam in place of k
+    assert C.sizeof(U.CodingProblem) == C.sizeof(U.Problem)
+    lib = U.library()
+    fake = C.c_void_p(1)
+    S = U.make_search(W.Search(-4, 4, 3, 9))
+    good = W.coding_problem(101, 101)
+    bad = []
+    for field, val in [("lam", -1.0), ("lam", float("nan")), ("n_x", 1), ("n_y", 1), ("x_lo", 9.0),
+                       ("y_hi", -6.0)]:
+        p = W.coding_problem(101, 101)
+        setattr(p, field, val)
+        bad.append(p)
+    p = W.coding_problem(101, 101)
+    p.comps = [(0.5, 0.0, 1.0)]
+    bad.append(p)
+    v = C.c_void_p(8)
+    for p in bad:
+        P = U.make_coding_problem(p)
+        assert lib.ucp_coding_objective(fake, C.byref(P), v, v, v, None) == U.EINVAL
+        assert lib.ucp_coding_update_u1(fake, C.byref(P), v, v, None) == U.EINVAL
+        assert lib.ucp_coding_argmin(fake, C.byref(P), C.byref(S), v, v, v, None, None) == U.EINVAL
+        assert lib.ucp_coding_marginal_cost(fake, C.byref(P), v, v, 4, v, None) == U.EINVAL
+        assert lib.ucp_coding_solve(fake, C.byref(P), C.byref(S), 2, v, v, v, v, None) == U.EINVAL
+        assert U.last_error() != ""
+    P = U.make_coding_problem(good)
+    for s in [W.Search(4, -4, 3, 9), W.Search(-4, 4, 0, 9), W.Search(-4, 4, 3, 1), W.Search(-4, 4, 3, 64)]:
+        S2 = U.make_search(s)
+        assert lib.ucp_coding_argmin(fake, C.byref(P), C.byref(S2), v, v, v, None, None) == U.EINVAL
+        assert lib.ucp_coding_solve(fake, C.byref(P), C.byref(S2), 2, v, v, v, v, None) == U.EINVAL
+    assert lib.ucp_coding_argmin(fake, C.byref(P), None, v, v, v, None, None) == U.EINVAL
+    assert lib.ucp_coding_solve(fake, C.byref(P), C.byref(S), -1, v, v, v, v, None) == U.EINVAL
+    assert lib.ucp_coding_solve(fake, C.byref(P), C.byref(S), 2, v, None, v, v, None) == U.EINVAL
+    assert lib.ucp_coding_marginal_cost(fake, C.byref(P), v, v, 0, v, None) == U.EINVAL
+    assert lib.ucp_coding_update_u1(fake, C.byref(P), None, v, None) == U.EINVAL
+    assert lib.ucp_coding_objective(None, C.byref(P), v, v, v, None) == U.EINVAL
+
+
 def test_footprint_without_device(U):
     c = W.small_case()
     n = U.footprint(c.prob, c.search, 10)
