@@ -4,19 +4,22 @@
 //
 // The uniform noise turns every window sum into a box: the marginal cost of
 // a candidate u needs the sums of u1 and u1^2 over the y nodes within 1 of
-// u, which double-double prefix sums give in O(1).  So the encoder search is
-// one thread per point walking all levels of the coarse-to-fine search, and
-// the decoder's closed form (a box-filtered conditional mean over the x
-// nodes) is the only quadratic-cost step.
+// u, which double-double prefix sums give in O(1).  So the encoder search
+// takes one lane per candidate and one lane group per point, the objective
+// one lane per point, and the decoder's closed form (a box-filtered
+// conditional mean over the x nodes) is the only quadratic-cost step; its
+// tiles of x nodes that lie wholly inside or outside a wave's windows cost
+// O(1) each.
 //
-//   k_cd_prior    f and f x at the x nodes
-//   k_cd_prefix   double-double prefix sums of u1 and u1^2 (one block)
-//   k_cd_search   per point: the coarse-to-fine search of B(u; x_i)
-//   k_cd_mc       L_0 = f B for explicit candidates
-//   k_cd_extent   min and max of u0 over tiles of x nodes
-//   k_cd_u1_part  decoder sums for 64 y nodes over one segment of x nodes
-//   k_cd_u1_fin   segment partials added in order; the ratio
-//   k_cd_jrows / k_cd_jsum   objective rows, one wave per x node; their sum
+//   k_cd_prior      f and f x at the x nodes
+//   k_cd_extent     per tile of x nodes: min and max of u0, sums of f and f x
+//   k_cd_u1_part    decoder sums for 64 y nodes over one segment (tile) of x nodes
+//   k_cd_fin_scan   decoder ratio (segment partials added in order) and the
+//                   block-local double-double prefix sums of u1 and u1^2
+//   k_cd_scan_top   exclusive prefix of the block totals (one block)
+//   k_cd_search<G>  per point, G lanes: the coarse-to-fine search of B(u; x_i)
+//   k_cd_mc         L_0 = f B for explicit candidates
+//   k_cd_jrows / k_cd_jsum   objective rows f_i B(u0_i; x_i), block sums, total
 #include <hip/hip_runtime.h>
 #include <hip/hip_ext.h>
 
@@ -30,11 +33,17 @@ namespace ucp {
 namespace {
 
 constexpr int kCdTile = 256;    // x nodes per extent tile and per LDS stage
-constexpr int kCdSegMin = 2048; // x nodes per decoder segment (at least)
-constexpr int kCdSegMax = 16;   // decoder segments (at most)
+constexpr int kCdSegMax = 128;  // decoder segments (at most; one tile each where possible)
+constexpr size_t kCdPartBytes = size_t(1) << 28;  // bound of the decoder's partial sums
 constexpr int kCdYGrp = 64;     // y nodes per decoder wave
-constexpr int kCdScan = 1024;   // threads of the prefix-sum block
-constexpr double kCdCull = 1.0 + 1e-6;  // tile culling distance (exact test inside)
+constexpr int kCdBlk = 256;     // y nodes per block of the local prefix sums
+constexpr int kCdScan = 1024;   // threads of the top-level prefix block
+// A tile whose u0 range lies within these distances of a wave's y range is
+// wholly outside (skipped) or wholly inside (its sums added) every window of
+// the wave; the margins exceed any rounding of y - u0 for |y|, |u0| <= 1e6,
+// and the exact test decides every other tile node by node.
+constexpr double kCdOut = 1.0 + 1e-6;
+constexpr double kCdIn = 1.0 - 1e-6;
 
 struct CdParams {
   double lam;
@@ -43,11 +52,22 @@ struct CdParams {
   double w[UCP_MAX_COMP], mu[UCP_MAX_COMP], sd[UCP_MAX_COMP];
   double x_lo, dx;  // x node i = x_lo + i * dx
   double y_lo, dy;  // y node j = y_lo + j * dy
+  double inv_dy;
   double u_lo, u_hi;
   int levels, cands;
   double h[UCP_MAX_LEVELS];  // candidate spacing per level
   int seg_tiles;             // decoder segment length in tiles
   int n_seg;                 // decoder segments
+  int n_blk;                 // blocks of the local prefix sums
+};
+
+// Prefix sums of u1 and u1^2 in double-double, in two levels: L holds the
+// inclusive sums within each block of kCdBlk nodes (four arrays of n_y:
+// S1 high, S1 low, S2 high, S2 low), off the exclusive sums of the block
+// totals (four arrays of n_blk).
+struct Pre {
+  const double* L;
+  const double* off;
 };
 
 // ------------------------------------------------------------ arithmetic
@@ -72,6 +92,7 @@ __device__ __forceinline__ dd dd_add(dd a, dd b) {
   dd s = two_sum(a.h, b.h);
   return fast_two_sum(s.h, s.l + (a.l + b.l));
 }
+__device__ __forceinline__ dd dd_neg(dd a) { return {-a.h, -a.l}; }
 __device__ __forceinline__ dd dd_mul_d(dd a, double d) {
   dd p = two_prod(a.h, d);
   return fast_two_sum(p.h, p.l + a.l * d);
@@ -91,8 +112,8 @@ __device__ __forceinline__ bool in_box(const CdParams& P, int j, double v) {
 // move monotonically within [-1, n_y], so they end.
 __device__ void box_window(const CdParams& P, double v, int& a, int& b) {
   const int n = P.n_y;
-  double ta = (v - 1.0 - P.y_lo) / P.dy;
-  double tb = (v + 1.0 - P.y_lo) / P.dy;
+  double ta = (v - 1.0 - P.y_lo) * P.inv_dy;
+  double tb = (v + 1.0 - P.y_lo) * P.inv_dy;
   ta = fmin(fmax(ta, 0.0), (double)(n - 1));
   tb = fmin(fmax(tb, 0.0), (double)(n - 1));
   int ja = (int)ceil(ta), jb = (int)floor(tb);
@@ -107,18 +128,29 @@ __device__ void box_window(const CdParams& P, double v, int& a, int& b) {
   b = jb;
 }
 
+// Sums of u1 and u1^2 over the nodes below j (0 <= j <= n_y).
+__device__ __forceinline__ void pre_at(const CdParams& P, const Pre& S, int j, dd& s1, dd& s2) {
+  if (j == 0) {
+    s1 = s2 = {0.0, 0.0};
+    return;
+  }
+  const int n = P.n_y, nb = P.n_blk, k = j - 1, b = k / kCdBlk;
+  s1 = dd_add({S.L[k], S.L[n + k]}, {S.off[b], S.off[nb + b]});
+  s2 = dd_add({S.L[2 * n + k], S.L[3 * n + k]}, {S.off[2 * nb + b], S.off[3 * nb + b]});
+}
+
 // B(u; x) = lam u^2 + dy * 1/2 * sum over the box window of (u1_j - x)^2,
-// the window sum expanded as S2 - 2 x S1 + n x^2 in double-double from the
-// prefix sums S (four arrays of n_y + 1: S1 high, S1 low, S2 high, S2 low;
-// entry j = sum over the nodes below j).
-__device__ double cd_B(const CdParams& P, const double* __restrict__ S, double x, double u) {
+// the window sum expanded as S2 - 2 x S1 + n x^2 in double-double.
+__device__ double cd_B(const CdParams& P, const Pre& S, double x, double u) {
   int a, b;
   box_window(P, u, a, b);
   double s = 0.0;
   if (b >= a) {
-    const int n1 = P.n_y + 1;
-    const dd s1 = dd_add({S[b + 1], S[n1 + b + 1]}, {-S[a], -S[n1 + a]});
-    const dd s2 = dd_add({S[2 * n1 + b + 1], S[3 * n1 + b + 1]}, {-S[2 * n1 + a], -S[3 * n1 + a]});
+    dd hi1, hi2, lo1, lo2;
+    pre_at(P, S, b + 1, hi1, hi2);
+    pre_at(P, S, a, lo1, lo2);
+    const dd s1 = dd_add(hi1, dd_neg(lo1));
+    const dd s2 = dd_add(hi2, dd_neg(lo2));
     dd t = dd_add(s2, dd_mul_d(s1, -2.0 * x));
     t = dd_add(t, dd_mul_d(two_prod(x, x), (double)(b - a + 1)));
     s = 0.5 * (t.h + t.l);
@@ -142,20 +174,190 @@ __global__ __launch_bounds__(256) void k_cd_prior(CdParams P, double* __restrict
   fx[i] = sum * x;
 }
 
-// One block: thread t sums a contiguous chunk of nodes, the chunk totals are
-// scanned in LDS (Hillis-Steele, double-double), then every thread writes
-// its chunk's running prefix.
-__global__ __launch_bounds__(kCdScan) void k_cd_prefix(int n, const double* __restrict__ u1,
-                                                         double* __restrict__ S) {
+__device__ __forceinline__ double wave_sum_d(double v) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+  return v;
+}
+
+// ext[4 t .. 4 t + 3] = min and max of u0 over tile t (NaN makes the range
+// infinite, so the tile goes through the exact test), sum of f, sum of f x
+// (fixed order: wave trees, then the waves in order).
+__global__ __launch_bounds__(kCdTile) void k_cd_extent(int n_x, const double* __restrict__ u0,
+                                                       const double* __restrict__ f,
+                                                       const double* __restrict__ fx,
+                                                       double* __restrict__ ext) {
+  __shared__ double sh[4][kCdTile / 64];
+  const int i = blockIdx.x * kCdTile + threadIdx.x;
+  double lo = INFINITY, hi = -INFINITY, sf = 0.0, sfx = 0.0;
+  if (i < n_x) {
+    const double v = u0[i];
+    lo = hi = v;
+    if (v != v) {
+      lo = -INFINITY;
+      hi = INFINITY;
+    }
+    sf = f[i];
+    sfx = fx[i];
+  }
+  for (int o = 32; o > 0; o >>= 1) {
+    lo = fmin(lo, __shfl_xor(lo, o));
+    hi = fmax(hi, __shfl_xor(hi, o));
+  }
+  sf = wave_sum_d(sf);
+  sfx = wave_sum_d(sfx);
+  const int wv = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0) {
+    sh[0][wv] = lo;
+    sh[1][wv] = hi;
+    sh[2][wv] = sf;
+    sh[3][wv] = sfx;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int k = 1; k < kCdTile / 64; ++k) {
+      lo = fmin(lo, sh[0][k]);
+      hi = fmax(hi, sh[1][k]);
+      sf += sh[2][k];
+      sfx += sh[3][k];
+    }
+    ext[4 * blockIdx.x] = lo;
+    ext[4 * blockIdx.x + 1] = hi;
+    ext[4 * blockIdx.x + 2] = sf;
+    ext[4 * blockIdx.x + 3] = sfx;
+  }
+}
+
+// One wave: 64 consecutive y nodes (lane = node) against the x nodes of
+// segment blockIdx.y, tile by tile in ascending order.  A tile wholly
+// outside every window of the wave is skipped, one wholly inside adds its
+// sums, any other is staged in LDS and tested node by node.
+// part[(seg * n_y + j) * 2 + {0, 1}] = (sum f x, sum f) over the nodes with
+// |y_j - u0_i| <= 1.
+__global__ __launch_bounds__(kCdYGrp) void k_cd_u1_part(CdParams P, const double* __restrict__ u0,
+                                                        const double* __restrict__ f,
+                                                        const double* __restrict__ fx,
+                                                        const double* __restrict__ ext,
+                                                        double* __restrict__ part) {
+  __shared__ double su[kCdTile], sf[kCdTile], sfx[kCdTile];
+  const int j0 = blockIdx.x * kCdYGrp;
+  const int j = j0 + threadIdx.x;
+  const bool live = j < P.n_y;
+  const double y = ynode(P, live ? j : P.n_y - 1);
+  const double ya = ynode(P, j0), yb = ynode(P, min(P.n_y - 1, j0 + kCdYGrp - 1));
+  const int n_tiles = (P.n_x + kCdTile - 1) / kCdTile;
+  const int t0 = blockIdx.y * P.seg_tiles, t1 = min(n_tiles, t0 + P.seg_tiles);
+  double num = 0.0, den = 0.0;
+  for (int t = t0; t < t1; ++t) {
+    const double tmin = ext[4 * t], tmax = ext[4 * t + 1];
+    if (!(tmin - yb <= kCdOut) || !(ya - tmax <= kCdOut)) continue;  // also skips an empty range
+    if (tmax - ya <= kCdIn && yb - tmin <= kCdIn) {
+      num += ext[4 * t + 3];
+      den += ext[4 * t + 2];
+      continue;
+    }
+    const int i0 = t * kCdTile;
+    const int cnt = min(kCdTile, P.n_x - i0);
+    for (int k = threadIdx.x; k < cnt; k += kCdYGrp) {
+      su[k] = u0[i0 + k];
+      sf[k] = f[i0 + k];
+      sfx[k] = fx[i0 + k];
+    }
+    __syncthreads();
+    // branch-free: a node outside the window adds an exact zero
+#pragma unroll 8
+    for (int k = 0; k < cnt; ++k) {
+      const bool in = fabs(y - su[k]) <= 1.0;
+      num += in ? sfx[k] : 0.0;
+      den += in ? sf[k] : 0.0;
+    }
+    __syncthreads();
+  }
+  if (live) {
+    const long o = ((long)blockIdx.y * P.n_y + j) * 2;
+    part[o] = num;
+    part[o + 1] = den;
+  }
+}
+
+// One block per kCdBlk y nodes.  FROM_PARTS: u1_j = (sum of the segment
+// partials of f x) / (sum of those of f), 0 where nothing reaches y_j, and
+// u1 is written; otherwise u1 is read.  Then the block's inclusive
+// double-double prefix sums of u1 and u1^2 (Hillis-Steele in LDS) go to L
+// and the block totals to tot (four arrays of n_blk).
+template <bool FROM_PARTS>
+__global__ __launch_bounds__(kCdBlk) void k_cd_fin_scan(CdParams P, const double* __restrict__ part, double* u1,
+                                                        double* __restrict__ L, double* __restrict__ tot) {
+  __shared__ double sh[4][kCdBlk];
+  const int t = threadIdx.x;
+  const int j = blockIdx.x * kCdBlk + t;
+  const int n = P.n_y;
+  double v = 0.0;
+  if (j < n) {
+    if (FROM_PARTS) {
+      double num = 0.0, den = 0.0;
+      for (int s = 0; s < P.n_seg; ++s) {
+        const long o = ((long)s * n + j) * 2;
+        num += part[o];
+        den += part[o + 1];
+      }
+      v = den > 0.0 ? num / den : 0.0;
+      u1[j] = v;
+    } else {
+      v = u1[j];
+    }
+  }
+  dd a1 = {v, 0.0}, a2 = two_prod(v, v);
+  sh[0][t] = a1.h;
+  sh[1][t] = a1.l;
+  sh[2][t] = a2.h;
+  sh[3][t] = a2.l;
+  __syncthreads();
+  for (int o = 1; o < kCdBlk; o <<= 1) {
+    const bool take = t >= o;
+    dd b1 = {0.0, 0.0}, b2 = {0.0, 0.0};
+    if (take) {
+      b1 = {sh[0][t - o], sh[1][t - o]};
+      b2 = {sh[2][t - o], sh[3][t - o]};
+    }
+    __syncthreads();
+    if (take) {
+      a1 = dd_add(b1, a1);
+      a2 = dd_add(b2, a2);
+      sh[0][t] = a1.h;
+      sh[1][t] = a1.l;
+      sh[2][t] = a2.h;
+      sh[3][t] = a2.l;
+    }
+    __syncthreads();
+  }
+  if (j < n) {
+    L[j] = a1.h;
+    L[n + j] = a1.l;
+    L[2 * n + j] = a2.h;
+    L[3 * n + j] = a2.l;
+  }
+  if (t == kCdBlk - 1) {
+    const int nb = P.n_blk, b = blockIdx.x;
+    tot[b] = a1.h;
+    tot[nb + b] = a1.l;
+    tot[2 * nb + b] = a2.h;
+    tot[3 * nb + b] = a2.l;
+  }
+}
+
+// One block: exclusive prefix of the n_blk block totals.  Thread t adds a
+// contiguous chunk, the chunk sums are scanned in LDS, then each thread
+// writes its chunk's running sums.
+__global__ __launch_bounds__(kCdScan) void k_cd_scan_top(int nb, const double* __restrict__ tot,
+                                                         double* __restrict__ off) {
   __shared__ double sh[4][kCdScan];
   const int t = threadIdx.x;
-  const int chunk = (n + kCdScan - 1) / kCdScan;
-  const int lo = min(n, t * chunk), hi = min(n, lo + chunk);
+  const int chunk = (nb + kCdScan - 1) / kCdScan;
+  const int lo = min(nb, t * chunk), hi = min(nb, lo + chunk);
   dd a1 = {0.0, 0.0}, a2 = {0.0, 0.0};
-  for (int j = lo; j < hi; ++j) {
-    const double v = u1[j];
-    a1 = dd_add(a1, {v, 0.0});
-    a2 = dd_add(a2, two_prod(v, v));
+  for (int b = lo; b < hi; ++b) {
+    a1 = dd_add(a1, {tot[b], tot[nb + b]});
+    a2 = dd_add(a2, {tot[2 * nb + b], tot[3 * nb + b]});
   }
   sh[0][t] = a1.h;
   sh[1][t] = a1.l;
@@ -185,36 +387,15 @@ __global__ __launch_bounds__(kCdScan) void k_cd_prefix(int n, const double* __re
     r1 = {sh[0][t - 1], sh[1][t - 1]};
     r2 = {sh[2][t - 1], sh[3][t - 1]};
   }
-  const int n1 = n + 1;
-  if (t == 0) S[0] = S[n1] = S[2 * n1] = S[3 * n1] = 0.0;
-  for (int j = lo; j < hi; ++j) {
-    const double v = u1[j];
-    r1 = dd_add(r1, {v, 0.0});
-    r2 = dd_add(r2, two_prod(v, v));
-    S[j + 1] = r1.h;
-    S[n1 + j + 1] = r1.l;
-    S[2 * n1 + j + 1] = r2.h;
-    S[3 * n1 + j + 1] = r2.l;
+  for (int b = lo; b < hi; ++b) {
+    off[b] = r1.h;
+    off[nb + b] = r1.l;
+    off[2 * nb + b] = r2.h;
+    off[3 * nb + b] = r2.l;
+    r1 = dd_add(r1, {tot[b], tot[nb + b]});
+    r2 = dd_add(r2, {tot[2 * nb + b], tot[3 * nb + b]});
   }
 }
-
-// The selection rule: candidates with B within the relative band 1e-12 of
-// the minimum are ties; the one nearest the incumbent wins, then the
-// smaller u, then the earlier one.  Walked in candidate order by `best`.
-struct Pick {
-  bool any = false;
-  double c = 0.0, B = 0.0, d = 0.0;
-  __device__ void offer(double cu, double Bu, double thr, double uinc) {
-    if (!(Bu <= thr)) return;
-    const double du = fabs(cu - uinc);
-    if (!any || du < d || (du == d && cu < c)) {
-      any = true;
-      c = cu;
-      B = Bu;
-      d = du;
-    }
-  }
-};
 
 __device__ __forceinline__ double level_cand(const CdParams& P, int l, int q, double cs) {
   if (l == 0) return P.u_lo + (double)q * P.h[0];
@@ -224,168 +405,120 @@ __device__ __forceinline__ double level_cand(const CdParams& P, int l, int q, do
   return v;
 }
 
-// One thread per point.  B is O(1), so each level takes two passes over
-// its candidates (the minimum, then the rule) instead of keeping them.
-// u0_in and u0_out may alias: a thread reads its own entry before writing it.
-__global__ __launch_bounds__(256) void k_cd_search(CdParams P, const double* __restrict__ S,
-                                                   const double* __restrict__ f, const double* u0_in,
-                                                   double* u0_out, double* L0_out) {
-  const int i = blockIdx.x * 256 + threadIdx.x;
-  if (i >= P.n_x) return;
+// The selection rule as a reduction over a group of G lanes: among the
+// candidates with B within the relative band 1e-12 of the minimum, the
+// smallest (distance to the incumbent, u, index) wins - the nearest, then
+// the smaller u, then the earlier candidate.  Lanes out of the band carry
+// infinite keys.  Every lane of the group ends with the winner.
+template <int G>
+__device__ __forceinline__ void group_pick(double& d, double& c, int& q, double& B) {
+  for (int o = G / 2; o > 0; o >>= 1) {
+    const double od = __shfl_xor(d, o, G), oc = __shfl_xor(c, o, G), oB = __shfl_xor(B, o, G);
+    const int oq = __shfl_xor(q, o, G);
+    if (od < d || (od == d && (oc < c || (oc == c && oq < q)))) {
+      d = od;
+      c = oc;
+      q = oq;
+      B = oB;
+    }
+  }
+}
+template <int G>
+__device__ __forceinline__ double group_min(double v) {
+  for (int o = G / 2; o > 0; o >>= 1) v = fmin(v, __shfl_xor(v, o, G));
+  return v;
+}
+
+// G lanes per point, lane q = candidate q of the level; the best so far
+// (index K) and the incumbent's final comparison are handled by every lane
+// alike.  u0_in and u0_out may alias: a group reads its entry before lane 0
+// writes it.
+template <int G>
+__global__ __launch_bounds__(256) void k_cd_search(CdParams P, Pre S, const double* __restrict__ f,
+                                                   const double* u0_in, double* u0_out, double* L0_out) {
+  const int i = (blockIdx.x * 256 + threadIdx.x) / G;
+  const int q = threadIdx.x % G;
+  if (i >= P.n_x) return;  // whole groups
   const double x = xnode(P, i);
   const double uinc = u0_in[i];
   const int K = P.cands;
   double cs = 0.0, Bs = 0.0;
   for (int l = 0; l < P.levels; ++l) {
-    double m = cd_B(P, S, x, level_cand(P, l, 0, cs));
-    for (int q = 1; q < K; ++q) m = fmin(m, cd_B(P, S, x, level_cand(P, l, q, cs)));
+    const bool live = q < K;
+    const double c = live ? level_cand(P, l, q, cs) : 0.0;
+    const double B = live ? cd_B(P, S, x, c) : INFINITY;
+    double m = group_min<G>(B);
     if (l > 0 && Bs < m) m = Bs;
     const double thr = m * (1.0 + 1e-12);
-    Pick pk;
-    for (int q = 0; q < K; ++q) {
-      const double c = level_cand(P, l, q, cs);
-      pk.offer(c, cd_B(P, S, x, c), thr, uinc);
+    double kd = INFINITY, kc = INFINITY, kB = B;
+    int kq = 1 << 30;
+    if (live && B <= thr) {
+      kd = fabs(c - uinc);
+      kc = c;
+      kq = q;
     }
-    if (l > 0) pk.offer(cs, Bs, thr, uinc);
-    cs = pk.c;
-    Bs = pk.B;
+    group_pick<G>(kd, kc, kq, kB);
+    if (l > 0 && Bs <= thr) {  // the best so far, index K, after every lane
+      const double ds = fabs(cs - uinc);
+      if (kq == (1 << 30) || ds < kd || (ds == kd && cs < kc)) {
+        kc = cs;
+        kB = Bs;
+      }
+    }
+    cs = kc;
+    Bs = kB;
   }
-  // acceptance against the incumbent
+  // acceptance against the incumbent (index 1, after the search's winner)
   const double Binc = cd_B(P, S, x, uinc);
   double m = Bs;
   if (Binc < m) m = Binc;
   const double thr = m * (1.0 + 1e-12);
-  Pick pk;
-  pk.offer(cs, Bs, thr, uinc);
-  pk.offer(uinc, Binc, thr, uinc);
-  u0_out[i] = pk.c;
-  if (L0_out) L0_out[i] = f[i] * pk.B;
+  double rc = cs, rB = Bs;
+  const bool win_in = Bs <= thr;
+  if (Binc <= thr) {
+    const double ds = fabs(cs - uinc), di = fabs(uinc - uinc);
+    if (!win_in || di < ds || (di == ds && uinc < cs)) {
+      rc = uinc;
+      rB = Binc;
+    }
+  }
+  if (q == 0) {
+    u0_out[i] = rc;
+    if (L0_out) L0_out[i] = f[i] * rB;
+  }
 }
 
-__global__ __launch_bounds__(256) void k_cd_mc(CdParams P, const double* __restrict__ S,
-                                               const double* __restrict__ f, const double* __restrict__ u,
-                                               int n_cand, double* __restrict__ out) {
+__global__ __launch_bounds__(256) void k_cd_mc(CdParams P, Pre S, const double* __restrict__ f,
+                                               const double* __restrict__ u, int n_cand, double* __restrict__ out) {
   const long g = (long)blockIdx.x * 256 + threadIdx.x;
   if (g >= (long)P.n_x * n_cand) return;
   const int i = (int)(g / n_cand);
   out[g] = f[i] * cd_B(P, S, xnode(P, i), u[g]);
 }
 
-__device__ __forceinline__ double wave_sum_d(double v) {
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
-  return v;
-}
-
-// ext[2 t], ext[2 t + 1] = min and max of u0 over tile t (kCdTile nodes).
-__global__ __launch_bounds__(kCdTile) void k_cd_extent(int n_x, const double* __restrict__ u0,
-                                                       double* __restrict__ ext) {
-  __shared__ double smin[kCdTile / 64], smax[kCdTile / 64];
-  const int i = blockIdx.x * kCdTile + threadIdx.x;
-  double lo = INFINITY, hi = -INFINITY;
-  if (i < n_x) lo = hi = u0[i];
-  for (int o = 32; o > 0; o >>= 1) {
-    lo = fmin(lo, __shfl_xor(lo, o));
-    hi = fmax(hi, __shfl_xor(hi, o));
-  }
-  if ((threadIdx.x & 63) == 0) {
-    smin[threadIdx.x >> 6] = lo;
-    smax[threadIdx.x >> 6] = hi;
-  }
+// Objective rows f_i B(u0_i; x_i), one lane per x node, summed per block in a
+// fixed tree into jpart[block].
+__global__ __launch_bounds__(256) void k_cd_jrows(CdParams P, Pre S, const double* __restrict__ u0,
+                                                  const double* __restrict__ f, double* __restrict__ jpart) {
+  __shared__ double sh[256];
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  double r = 0.0;
+  if (i < P.n_x) r = f[i] * cd_B(P, S, xnode(P, i), u0[i]);
+  sh[threadIdx.x] = r;
   __syncthreads();
-  if (threadIdx.x == 0) {
-    for (int k = 1; k < kCdTile / 64; ++k) {
-      lo = fmin(lo, smin[k]);
-      hi = fmax(hi, smax[k]);
-    }
-    ext[2 * blockIdx.x] = lo;
-    ext[2 * blockIdx.x + 1] = hi;
-  }
-}
-
-// One wave: 64 consecutive y nodes (lane = node) against the x nodes of
-// segment blockIdx.y, in ascending order, tile by tile through LDS; tiles
-// whose u0 range lies farther than 1 from the wave's y range are skipped
-// (the exact test decides inside).  part[(seg * n_y + j) * 2 + {0, 1}] =
-// (sum f x, sum f) over the nodes with |y_j - u0_i| <= 1.
-__global__ __launch_bounds__(kCdYGrp) void k_cd_u1_part(CdParams P, const double* __restrict__ u0,
-                                                        const double* __restrict__ f,
-                                                        const double* __restrict__ fx,
-                                                        const double* __restrict__ ext,
-                                                        double* __restrict__ part) {
-  __shared__ double su[kCdTile], sf[kCdTile], sfx[kCdTile];
-  const int j0 = blockIdx.x * kCdYGrp;
-  const int j = j0 + threadIdx.x;
-  const bool live = j < P.n_y;
-  const double y = ynode(P, live ? j : P.n_y - 1);
-  const double ya = ynode(P, j0), yb = ynode(P, min(P.n_y - 1, j0 + kCdYGrp - 1));
-  const int n_tiles = (P.n_x + kCdTile - 1) / kCdTile;
-  const int t0 = blockIdx.y * P.seg_tiles, t1 = min(n_tiles, t0 + P.seg_tiles);
-  double num = 0.0, den = 0.0;
-  for (int t = t0; t < t1; ++t) {
-    const double tmin = ext[2 * t], tmax = ext[2 * t + 1];
-    if (!(tmin - yb <= kCdCull) || !(ya - tmax <= kCdCull)) continue;  // also skips an all-NaN tile
-    const int i0 = t * kCdTile;
-    const int cnt = min(kCdTile, P.n_x - i0);
-    for (int k = threadIdx.x; k < cnt; k += kCdYGrp) {
-      su[k] = u0[i0 + k];
-      sf[k] = f[i0 + k];
-      sfx[k] = fx[i0 + k];
-    }
-    __syncthreads();
-    for (int k = 0; k < cnt; ++k) {
-      if (fabs(y - su[k]) <= 1.0) {
-        num += sfx[k];
-        den += sf[k];
-      }
-    }
+  for (int o = 128; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) sh[threadIdx.x] += sh[threadIdx.x + o];
     __syncthreads();
   }
-  if (live) {
-    const long o = ((long)blockIdx.y * P.n_y + j) * 2;
-    part[o] = num;
-    part[o + 1] = den;
-  }
+  if (threadIdx.x == 0) jpart[blockIdx.x] = sh[0];
 }
 
-__global__ __launch_bounds__(256) void k_cd_u1_fin(CdParams P, const double* __restrict__ part,
-                                                   double* __restrict__ u1) {
-  const int j = blockIdx.x * 256 + threadIdx.x;
-  if (j >= P.n_y) return;
-  double num = 0.0, den = 0.0;
-  for (int s = 0; s < P.n_seg; ++s) {
-    const long o = ((long)s * P.n_y + j) * 2;
-    num += part[o];
-    den += part[o + 1];
-  }
-  u1[j] = den > 0.0 ? num / den : 0.0;
-}
-
-// One wave per x node: the box window of u0_i, lanes strided over it.
-__global__ __launch_bounds__(256) void k_cd_jrows(CdParams P, const double* __restrict__ u0,
-                                                  const double* __restrict__ u1,
-                                                  const double* __restrict__ f, double* __restrict__ rows) {
-  const int i = blockIdx.x * 4 + (threadIdx.x >> 6);
-  const int lane = threadIdx.x & 63;
-  if (i >= P.n_x) return;
-  const double x = xnode(P, i);
-  const double v = u0[i];
-  int a, b;
-  box_window(P, v, a, b);
-  double s = 0.0;
-  for (int j = a + lane; j <= b; j += 64) {
-    const double e = u1[j] - x;
-    s += e * e;
-  }
-  s = wave_sum_d(s);
-  if (lane == 0) rows[i] = f[i] * (P.lam * v * v + P.dy * (0.5 * s));
-}
-
-// J = dx * sum of the rows, in a fixed order (strided partials, then a tree).
-__global__ __launch_bounds__(256) void k_cd_jsum(int n, double dx, const double* __restrict__ rows,
+// J = dx * sum of the block sums, in a fixed order (strided partials, then a tree).
+__global__ __launch_bounds__(256) void k_cd_jsum(int n, double dx, const double* __restrict__ jpart,
                                                  double* __restrict__ J) {
   __shared__ double sh[256];
   double s = 0.0;
-  for (int i = threadIdx.x; i < n; i += 256) s += rows[i];
+  for (int i = threadIdx.x; i < n; i += 256) s += jpart[i];
   sh[threadIdx.x] = s;
   __syncthreads();
   for (int o = 128; o > 0; o >>= 1) {
@@ -400,7 +533,8 @@ __global__ __launch_bounds__(256) void k_cd_jsum(int n, double dx, const double*
 inline size_t al(size_t v) { return (v + 255) & ~(size_t)255; }
 
 struct CdWork {
-  double *f, *fx, *S, *ext, *part, *rows;
+  double *f, *fx, *L, *tot, *off, *ext, *part, *jpart;
+  Pre pre() const { return {L, off}; }
 };
 
 int cd_params(const ucp_coding_problem* p, const ucp_search* s, CdParams& P) {
@@ -436,6 +570,7 @@ int cd_params(const ucp_coding_problem* p, const ucp_search* s, CdParams& P) {
   P.dx = (p->x_hi - p->x_lo) / (double)(p->n_x - 1);
   P.y_lo = p->y_lo;
   P.dy = (p->y_hi - p->y_lo) / (double)(p->n_y - 1);
+  P.inv_dy = 1.0 / P.dy;
   if (s) {
     P.u_lo = s->u_lo;
     P.u_hi = s->u_hi;
@@ -444,36 +579,42 @@ int cd_params(const ucp_coding_problem* p, const ucp_search* s, CdParams& P) {
     P.h[0] = (s->u_hi - s->u_lo) / (double)(s->cands - 1);
     for (int l = 1; l < s->levels; ++l) P.h[l] = 2.0 * P.h[l - 1] / (double)(s->cands - 1);
   }
+  // decoder segments: as many as tiles (a wave's run of exact tests is then
+  // one tile long), at most kCdSegMax and within kCdPartBytes of partials
   const int n_tiles = (P.n_x + kCdTile - 1) / kCdTile;
-  int n_seg = (P.n_x + kCdSegMin - 1) / kCdSegMin;
+  size_t cap = kCdPartBytes / (16 * (size_t)P.n_y);
+  if (cap < 1) cap = 1;
+  int n_seg = n_tiles;
   if (n_seg > kCdSegMax) n_seg = kCdSegMax;
+  if ((size_t)n_seg > cap) n_seg = (int)cap;
   P.seg_tiles = (n_tiles + n_seg - 1) / n_seg;
   P.n_seg = (n_tiles + P.seg_tiles - 1) / P.seg_tiles;
+  P.n_blk = (P.n_y + kCdBlk - 1) / kCdBlk;
   return UCP_OK;
 }
 
 int cd_work(ucp_handle* h, const CdParams& P, CdWork& W) {
-  const size_t nx = (size_t)P.n_x, ny = (size_t)P.n_y;
+  const size_t nx = (size_t)P.n_x, ny = (size_t)P.n_y, nb = (size_t)P.n_blk;
   const size_t n_tiles = (nx + kCdTile - 1) / kCdTile;
-  const size_t sz[6] = {al(8 * nx), al(8 * nx), al(8 * 4 * (ny + 1)), al(8 * 2 * n_tiles),
-                        al(8 * 2 * (size_t)P.n_seg * ny), al(8 * nx)};
+  const size_t sz[8] = {al(8 * nx), al(8 * nx), al(8 * 4 * ny), al(8 * 4 * nb), al(8 * 4 * nb),
+                        al(8 * 4 * n_tiles), al(8 * 2 * (size_t)P.n_seg * ny), al(8 * ((nx + 255) / 256))};
   size_t total = 0;
   for (size_t v : sz) total += v;
   void* base = nullptr;
   int rc = handle_workspace(h, total, &base);
   if (rc) return rc;
   char* p = (char*)base;
-  double** slot[6] = {&W.f, &W.fx, &W.S, &W.ext, &W.part, &W.rows};
-  for (int k = 0; k < 6; ++k) {
+  double** slot[8] = {&W.f, &W.fx, &W.L, &W.tot, &W.off, &W.ext, &W.part, &W.jpart};
+  for (int k = 0; k < 8; ++k) {
     *slot[k] = (double*)p;
     p += sz[k];
   }
   return UCP_OK;
 }
 
-#define CD_TRY(expr, what)                      \
-  do {                                          \
-    hipError_t e_ = (expr);                     \
+#define CD_TRY(expr, what)                           \
+  do {                                               \
+    hipError_t e_ = (expr);                          \
     if (e_ != hipSuccess) return hip_fail(e_, what); \
   } while (0)
 
@@ -484,12 +625,46 @@ hipError_t cd_prior(const CdParams& P, const CdWork& W, hipStream_t st) {
   return hipGetLastError();
 }
 
-hipError_t cd_prefix(ucp_handle* h, const CdParams& P, const CdWork& W, const double* u1, hipStream_t st) {
+// Prefix sums of a given u1 (an input array).
+hipError_t cd_scan_input(ucp_handle* h, const CdParams& P, const CdWork& W, const double* u1, hipStream_t st) {
   hipEvent_t a, b;
   hipError_t e = handle_events(h, UCP_PROF_SELECT, &a, &b);
   if (e != hipSuccess) return e;
-  hipExtLaunchKernelGGL(k_cd_prefix, dim3(1), dim3(kCdScan), 0, st, a, b, 0, P.n_y, u1, W.S);
+  hipExtLaunchKernelGGL(k_cd_fin_scan<false>, dim3(P.n_blk), dim3(kCdBlk), 0, st, a, nullptr, 0, P,
+                        (const double*)nullptr, const_cast<double*>(u1), W.L, W.tot);
+  hipExtLaunchKernelGGL(k_cd_scan_top, dim3(1), dim3(kCdScan), 0, st, nullptr, b, 0, P.n_blk,
+                        (const double*)W.tot, W.off);
   return hipGetLastError();
+}
+
+// Decoder of u0 into u1, and the prefix sums of the new u1.
+hipError_t cd_u1(ucp_handle* h, const CdParams& P, const CdWork& W, const double* u0, double* u1,
+                 hipStream_t st) {
+  hipEvent_t a, b;
+  hipError_t e = handle_events(h, UCP_PROF_U1, &a, &b);
+  if (e != hipSuccess) return e;
+  const unsigned n_tiles = blocks(P.n_x, kCdTile);
+  hipExtLaunchKernelGGL(k_cd_extent, dim3(n_tiles), dim3(kCdTile), 0, st, a, nullptr, 0, P.n_x, u0,
+                        (const double*)W.f, (const double*)W.fx, W.ext);
+  hipLaunchKernelGGL(k_cd_u1_part, dim3(blocks(P.n_y, kCdYGrp), P.n_seg), dim3(kCdYGrp), 0, st, P, u0,
+                     (const double*)W.f, (const double*)W.fx, (const double*)W.ext, W.part);
+  hipExtLaunchKernelGGL(k_cd_fin_scan<true>, dim3(P.n_blk), dim3(kCdBlk), 0, st, nullptr, b, 0, P,
+                        (const double*)W.part, u1, W.L, W.tot);
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipEvent_t a2, b2;
+  e = handle_events(h, UCP_PROF_SELECT, &a2, &b2);
+  if (e != hipSuccess) return e;
+  hipExtLaunchKernelGGL(k_cd_scan_top, dim3(1), dim3(kCdScan), 0, st, a2, b2, 0, P.n_blk, (const double*)W.tot,
+                        W.off);
+  return hipGetLastError();
+}
+
+template <int G>
+void launch_search(const CdParams& P, const CdWork& W, const double* u0_in, double* u0_out, double* L0_out,
+                   hipEvent_t a, hipEvent_t b, hipStream_t st) {
+  hipExtLaunchKernelGGL(k_cd_search<G>, dim3(blocks((long)P.n_x * G, 256)), dim3(256), 0, st, a, b, 0, P,
+                        W.pre(), (const double*)W.f, u0_in, u0_out, L0_out);
 }
 
 hipError_t cd_search(ucp_handle* h, const CdParams& P, const CdWork& W, const double* u0_in, double* u0_out,
@@ -497,34 +672,25 @@ hipError_t cd_search(ucp_handle* h, const CdParams& P, const CdWork& W, const do
   hipEvent_t a, b;
   hipError_t e = handle_events(h, UCP_PROF_MC, &a, &b);
   if (e != hipSuccess) return e;
-  hipExtLaunchKernelGGL(k_cd_search, dim3(blocks(P.n_x, 256)), dim3(256), 0, st, a, b, 0, P,
-                        (const double*)W.S, (const double*)W.f, u0_in, u0_out, L0_out);
+  if (P.cands <= 2) launch_search<2>(P, W, u0_in, u0_out, L0_out, a, b, st);
+  else if (P.cands <= 4) launch_search<4>(P, W, u0_in, u0_out, L0_out, a, b, st);
+  else if (P.cands <= 8) launch_search<8>(P, W, u0_in, u0_out, L0_out, a, b, st);
+  else if (P.cands <= 16) launch_search<16>(P, W, u0_in, u0_out, L0_out, a, b, st);
+  else if (P.cands <= 32) launch_search<32>(P, W, u0_in, u0_out, L0_out, a, b, st);
+  else launch_search<64>(P, W, u0_in, u0_out, L0_out, a, b, st);
   return hipGetLastError();
 }
 
-hipError_t cd_u1(ucp_handle* h, const CdParams& P, const CdWork& W, const double* u0, double* u1,
-                 hipStream_t st) {
-  hipEvent_t a, b;
-  hipError_t e = handle_events(h, UCP_PROF_U1, &a, &b);
-  if (e != hipSuccess) return e;
-  const unsigned n_tiles = blocks(P.n_x, kCdTile);
-  hipExtLaunchKernelGGL(k_cd_extent, dim3(n_tiles), dim3(kCdTile), 0, st, a, nullptr, 0, P.n_x, u0, W.ext);
-  hipLaunchKernelGGL(k_cd_u1_part, dim3(blocks(P.n_y, kCdYGrp), P.n_seg), dim3(kCdYGrp), 0, st, P, u0,
-                     (const double*)W.f, (const double*)W.fx, (const double*)W.ext, W.part);
-  hipExtLaunchKernelGGL(k_cd_u1_fin, dim3(blocks(P.n_y, 256)), dim3(256), 0, st, nullptr, b, 0, P,
-                        (const double*)W.part, u1);
-  return hipGetLastError();
-}
-
-hipError_t cd_objective(ucp_handle* h, const CdParams& P, const CdWork& W, const double* u0, const double* u1,
-                        double* J, hipStream_t st) {
+hipError_t cd_objective(ucp_handle* h, const CdParams& P, const CdWork& W, const double* u0, double* J,
+                        hipStream_t st) {
   hipEvent_t a, b;
   hipError_t e = handle_events(h, UCP_PROF_J, &a, &b);
   if (e != hipSuccess) return e;
-  hipExtLaunchKernelGGL(k_cd_jrows, dim3(blocks(P.n_x, 4)), dim3(256), 0, st, a, nullptr, 0, P, u0, u1,
-                        (const double*)W.f, W.rows);
-  hipExtLaunchKernelGGL(k_cd_jsum, dim3(1), dim3(256), 0, st, nullptr, b, 0, P.n_x, P.dx,
-                        (const double*)W.rows, J);
+  const unsigned nb = blocks(P.n_x, 256);
+  hipExtLaunchKernelGGL(k_cd_jrows, dim3(nb), dim3(256), 0, st, a, nullptr, 0, P, W.pre(), u0, (const double*)W.f,
+                        W.jpart);
+  hipExtLaunchKernelGGL(k_cd_jsum, dim3(1), dim3(256), 0, st, nullptr, b, 0, (int)nb, P.dx,
+                        (const double*)W.jpart, J);
   return hipGetLastError();
 }
 
@@ -556,8 +722,8 @@ int ucp_coding_marginal_cost(ucp_handle* h, const ucp_coding_problem* prob, cons
   if ((rc = cd_work(h, P, W))) return rc;
   hipStream_t st = (hipStream_t)stream;
   CD_TRY(cd_prior(P, W, st), "prior kernel");
-  CD_TRY(cd_prefix(nullptr, P, W, u1, st), "prefix-sum kernel");
-  hipLaunchKernelGGL(k_cd_mc, dim3(blocks((long)P.n_x * n_cand, 256)), dim3(256), 0, st, P, (const double*)W.S,
+  CD_TRY(cd_scan_input(nullptr, P, W, u1, st), "prefix-sum kernels");
+  hipLaunchKernelGGL(k_cd_mc, dim3(blocks((long)P.n_x * n_cand, 256)), dim3(256), 0, st, P, W.pre(),
                      (const double*)W.f, u, (int)n_cand, L0_out);
   CD_TRY(hipGetLastError(), "marginal-cost kernel");
   return UCP_OK;
@@ -576,7 +742,7 @@ int ucp_coding_argmin(ucp_handle* h, const ucp_coding_problem* prob, const ucp_s
   if ((rc = cd_work(h, P, W))) return rc;
   hipStream_t st = (hipStream_t)stream;
   CD_TRY(cd_prior(P, W, st), "prior kernel");
-  CD_TRY(cd_prefix(nullptr, P, W, u1, st), "prefix-sum kernel");
+  CD_TRY(cd_scan_input(nullptr, P, W, u1, st), "prefix-sum kernels");
   CD_TRY(cd_search(nullptr, P, W, u0_in, u0_out, L0_out, st), "search kernel");
   return UCP_OK;
 }
@@ -609,7 +775,8 @@ int ucp_coding_objective(ucp_handle* h, const ucp_coding_problem* prob, const do
   if ((rc = cd_work(h, P, W))) return rc;
   hipStream_t st = (hipStream_t)stream;
   CD_TRY(cd_prior(P, W, st), "prior kernel");
-  CD_TRY(cd_objective(nullptr, P, W, u0, u1, J_out, st), "objective kernels");
+  CD_TRY(cd_scan_input(nullptr, P, W, u1, st), "prefix-sum kernels");
+  CD_TRY(cd_objective(nullptr, P, W, u0, J_out, st), "objective kernels");
   return UCP_OK;
 }
 
@@ -629,13 +796,14 @@ int ucp_coding_solve(ucp_handle* h, const ucp_coding_problem* prob, const ucp_se
   CD_TRY(cd_prior(P, W, st), "prior kernel");
   if (u0_out != u0_init)
     CD_TRY(hipMemcpyAsync(u0_out, u0_init, sizeof(double) * P.n_x, hipMemcpyDeviceToDevice, st), "copy u0");
+  // every round ends with the prefix sums of its u1, which the objective
+  // and the next round's search read
   CD_TRY(cd_u1(h, P, W, u0_out, u1_out, st), "decoder kernels");
-  CD_TRY(cd_objective(h, P, W, u0_out, u1_out, J_hist, st), "objective kernels");
+  CD_TRY(cd_objective(h, P, W, u0_out, J_hist, st), "objective kernels");
   for (int t = 1; t <= iters; ++t) {
-    CD_TRY(cd_prefix(h, P, W, u1_out, st), "prefix-sum kernel");
     CD_TRY(cd_search(h, P, W, u0_out, u0_out, nullptr, st), "search kernel");
     CD_TRY(cd_u1(h, P, W, u0_out, u1_out, st), "decoder kernels");
-    CD_TRY(cd_objective(h, P, W, u0_out, u1_out, J_hist + t, st), "objective kernels");
+    CD_TRY(cd_objective(h, P, W, u0_out, J_hist + t, st), "objective kernels");
   }
   if (handle_profiling(h)) {
     CD_TRY(hipStreamSynchronize(st), "synchronise");
