@@ -44,6 +44,13 @@ if ROOT not in sys.path:
 # positions spread wider than the reference form allows take two more
 # operations per term; the count above is the smaller one.)
 PEAK_SLOTS = 256 * 128 * 2.4e9
+# Source-channel coding: the encoder search is FP64 work; MI355X's FP64
+# vector peak is 78.6 TFLOP/s (an FMA counts two).  One B evaluation in the
+# double-double box-window form takes about 144 FP64 flops: the two prefix
+# lookups (44), the window sums (22), the expanded quadratic (42), the
+# scaling (6) and the window's ends (30).
+PEAK_FP64 = 78.6e12
+CODING_FLOPS_PER_B = 144
 SLOTS_PER_TERM = 3.46875
 
 
@@ -356,6 +363,7 @@ def bench_coding(a):
         U.coding_solve(p, s, case.iters, u0)
     st = torch.cuda.current_stream()
     torch.cuda.synchronize()
+    U.profile(["marginal_cost"])  # HIP events around each encoder-search launch of the timed solves
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     ev0.record(st)
     for k in range(a.steps):
@@ -363,13 +371,22 @@ def bench_coding(a):
     ev1.record(st)
     torch.cuda.synchronize()
     ms_step = ev0.elapsed_time(ev1) / a.steps
+    se_ms, se_n = U.profile_read()["marginal_cost"]
     breakdown = kernel_breakdown(U, lambda: U.coding_solve(p, s, case.iters, u0))
+    se_avg_s = se_ms / 1e3 / max(se_n, 1)
+    evals = p.n_x * (s.levels * s.cands + 1)  # B evaluations per search launch
+    achieved = evals * CODING_FLOPS_PER_B / se_avg_s
     J = out[2].cpu().numpy()
     res = {"metric": "coding solves/s", "value": 1e3 / ms_step, "unit": "solves/s", "n_gpus": 1,
            "steps": a.steps, "warmup": a.warmup, "ms_per_step": ms_step, "higher_is_better": True,
            "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
            "config": {"workload": case.name, "n_x": p.n_x, "n_y": p.n_y, "levels": s.levels, "cands": s.cands,
                       "rounds": case.iters, "lam": p.lam},
+           "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP64 / 1e12, "unit": "TFLOP/s",
+                        "frac": achieved / PEAK_FP64, "traffic": None,
+                        "kernel": "k_cd_search<16> (encoder search)",
+                        "per_unit": f"{CODING_FLOPS_PER_B} FP64 flops per B evaluation, {evals} per launch",
+                        "kernel_avg_us": se_avg_s * 1e6, "kernel_launches": se_n},
            "kernel_ms_per_step": {"search": breakdown["marginal_cost"], "prefix": breakdown["select"],
                                   "u1": breakdown["u1"], "objective": breakdown["objective"]},
            "J_final": float(J[-1])}
@@ -378,7 +395,40 @@ def bench_coding(a):
 
         Jo = oracle.coding_objective(p, out[0].cpu().numpy(), out[1].cpu().numpy())
         res["J_final_rel_err_vs_oracle_objective"] = abs(J[-1] - Jo) / Jo
+    if not a.no_cpu:
+        res["cpu_baseline"] = coding_cpu_baseline(case)
     print(json.dumps(res), flush=True)
+
+
+def coding_cpu_baseline(case):
+    """The oracle's coding functions, as they stand, on a bounded sample of
+    the same workload, scaled to one whole solve: an encoder update on evenly
+    spaced rows, one full decoder and one full objective."""
+    import numpy as np
+
+    import oracle
+
+    p, s = case.prob, case.search
+    u1 = oracle.coding_update_u1(p, case.u0_init)
+    # probe, then size the encoder sample to about 10 s
+    rows = np.linspace(0, p.n_x - 1, 256).astype(np.int64)
+    t0 = time.perf_counter()
+    oracle.coding_argmin(p, s, u1, case.u0_init, rows)
+    n = int(min(p.n_x, 256 * 10.0 / max(time.perf_counter() - t0, 1e-6)))
+    rows = np.linspace(0, p.n_x - 1, n).astype(np.int64)
+    t0 = time.perf_counter()
+    oracle.coding_argmin(p, s, u1, case.u0_init, rows)
+    t_arg = (time.perf_counter() - t0) * p.n_x / len(rows)
+    t0 = time.perf_counter()
+    oracle.coding_update_u1(p, case.u0_init)
+    t_u1 = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    oracle.coding_objective(p, case.u0_init, u1)
+    t_j = time.perf_counter() - t0
+    solve_s = t_u1 + t_j + case.iters * (t_arg + t_u1 + t_j)
+    return {"value": 1.0 / solve_s, "unit": "solves/s", "cores": oracle.num_threads(), "kind": "oracle",
+            "sample": f"encoder update on {len(rows)} of {p.n_x} rows ({t_arg * len(rows) / p.n_x:.1f} s), one "
+                      f"full decoder and objective, scaled to {case.iters} rounds: {solve_s:.1f} s per solve"}
 
 
 def kernel_breakdown(U, step):
