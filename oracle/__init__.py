@@ -102,6 +102,14 @@ def lib():
         L.orc_cd_objective.argtypes = [P(_Problem), D, dp, dp]
         L.orc_cd_objective.restype = D
         L.orc_cd_solve.argtypes = [P(_Problem), D, P(_Search), C.c_int32, dp, dp, dp, dp]
+        L.orc2_B.argtypes = [P(_Problem), dp, D, D, D, D]
+        L.orc2_B.restype = D
+        L.orc2_marginal_cost.argtypes = [P(_Problem), dp, dp, C.c_int64, dp]
+        L.orc2_argmin.argtypes = [P(_Problem), P(_Search), dp, dp, ip, C.c_int64, dp, dp]
+        L.orc2_update_u1.argtypes = [P(_Problem), dp, ip, C.c_int64, dp]
+        L.orc2_objective.argtypes = [P(_Problem), dp, dp]
+        L.orc2_objective.restype = D
+        L.orc2_solve.argtypes = [P(_Problem), P(_Search), C.c_int32, dp, dp, dp, dp]
         _lib = L
     return _lib
 
@@ -294,4 +302,70 @@ def coding_solve(p, s, iters: int, u0_init):
     J = np.empty(int(iters) + 1, np.float64)
     lib().orc_cd_solve(C.byref(_prob(p)), float(p.lam), C.byref(_search(s)), int(iters), _dp(u0_init),
                        _dp(u0), _dp(u1), _dp(J))
+    return u0, u1, J
+
+
+# ---------------------------------------------------------------------------
+# Two-dimensional Witsenhausen (Section V-E): tensor grids, vector fields as
+# arrays [2, n * n] (node (i1, i2) at i1 * n + i2).
+
+def _planes(a, n, name):
+    a = np.ascontiguousarray(a, dtype=np.float64)
+    if a.shape != (2, n):
+        raise ValueError(f"{name} must be [2, {n}]")
+    return a
+
+
+def w2_B(p, u1, x, u) -> float:
+    u1 = _planes(u1, int(p.n_y) ** 2, "u1")
+    return float(lib().orc2_B(C.byref(_prob(p)), _dp(u1), float(x[0]), float(x[1]), float(u[0]), float(u[1])))
+
+
+def w2_marginal_cost(p, u1, u) -> np.ndarray:
+    """u: [2, n_x^2, n_cand]; returns L_0 [n_x^2, n_cand]."""
+    nn = int(p.n_x) ** 2
+    u1 = _planes(u1, int(p.n_y) ** 2, "u1")
+    u = np.ascontiguousarray(u, dtype=np.float64)
+    if u.ndim != 3 or u.shape[:2] != (2, nn):
+        raise ValueError("u must be [2, n_x^2, n_cand]")
+    out = np.empty((nn, u.shape[2]), np.float64)
+    lib().orc2_marginal_cost(C.byref(_prob(p)), _dp(u1), _dp(u), u.shape[2], _dp(out))
+    return out
+
+
+def w2_argmin(p, s, u1, u0_in, rows=None):
+    nn = int(p.n_x) ** 2
+    u1 = _planes(u1, int(p.n_y) ** 2, "u1")
+    u0_in = _planes(u0_in, nn, "u0")
+    n, r = _rows(rows, nn)
+    rp = r.ctypes.data_as(C.POINTER(C.c_int64)) if r is not None else None
+    u0o = np.empty((2, n), np.float64)
+    Bo = np.empty(n, np.float64)
+    lib().orc2_argmin(C.byref(_prob(p)), C.byref(_search(s)), _dp(u1), _dp(u0_in), rp, n, _dp(u0o), _dp(Bo))
+    return u0o, Bo
+
+
+def w2_update_u1(p, u0, rows=None) -> np.ndarray:
+    nn = int(p.n_x) ** 2
+    u0 = _planes(u0, nn, "u0")
+    n, r = _rows(rows, int(p.n_y) ** 2)
+    rp = r.ctypes.data_as(C.POINTER(C.c_int64)) if r is not None else None
+    out = np.empty((2, n), np.float64)
+    lib().orc2_update_u1(C.byref(_prob(p)), _dp(u0), rp, n, _dp(out))
+    return out
+
+
+def w2_objective(p, u0, u1) -> float:
+    u0 = _planes(u0, int(p.n_x) ** 2, "u0")
+    u1 = _planes(u1, int(p.n_y) ** 2, "u1")
+    return float(lib().orc2_objective(C.byref(_prob(p)), _dp(u0), _dp(u1)))
+
+
+def w2_solve(p, s, iters: int, u0_init):
+    nn = int(p.n_x) ** 2
+    u0_init = _planes(u0_init, nn, "u0_init")
+    u0 = np.empty((2, nn), np.float64)
+    u1 = np.empty((2, int(p.n_y) ** 2), np.float64)
+    J = np.empty(int(iters) + 1, np.float64)
+    lib().orc2_solve(C.byref(_prob(p)), C.byref(_search(s)), int(iters), _dp(u0_init), _dp(u0), _dp(u1), _dp(J))
     return u0, u1, J

@@ -456,3 +456,240 @@ void orc_cd_solve(const orc_problem* p, double lam, const orc_search* s, int32_t
   free(u0);
   free(nxt);
 }
+
+/* ------------------------------------------------------------------------
+ * Two-dimensional Witsenhausen counterexample (Section V-E): x0 in R^2 with
+ * both coordinates independent draws of the prior above, x1 = x0 + u0(x0),
+ * y1 = x1 + w with w ~ N(0, I_2), x2 = x1 - u1(y1),
+ * J = 1/2 E[k^2 |u0(x0)|^2 + |x2|^2].
+ * Grids are tensor products of the 1-D grids above: x node (i1, i2) at
+ * index i1 * n_x + i2, y node (j1, j2) at j1 * n_y + j2; vector fields are
+ * stored as two planes (first coordinates, then second).  Rectangle rule
+ * with weights dx^2 and dy^2.  Parity status: pinned by the CPU tests
+ * (separable inputs reduce every function to the 1-D oracle, a closed form
+ * for the affine controllers, symmetry).
+ * ------------------------------------------------------------------------ */
+
+/* B(u; x) = L_0(u, x) / f(x) for the 2-D objective: 1/2 [k^2 |u|^2 +
+ * sum over every y node of dy^2 phi(y1 - z1) phi(y2 - z2) |z - u1(y)|^2],
+ * z = x + u; u1 is [2][n_y * n_y]. */
+double orc2_B(const orc_problem* p, const double* u1, double x1, double x2, double ua, double ub) {
+  double dy = (p->y_hi - p->y_lo) / (double)(p->n_y - 1);
+  int64_t ny = p->n_y, nn = ny * ny;
+  double z1 = x1 + ua, z2 = x2 + ub;
+  double s = 0.0;
+  for (int64_t j1 = 0; j1 < ny; ++j1) {
+    double g1 = orc_phi(orc_node(p->y_lo, p->y_hi, ny, j1) - z1);
+    for (int64_t j2 = 0; j2 < ny; ++j2) {
+      double g2 = orc_phi(orc_node(p->y_lo, p->y_hi, ny, j2) - z2);
+      double e1 = z1 - u1[j1 * ny + j2];
+      double e2 = z2 - u1[nn + j1 * ny + j2];
+      s += g1 * g2 * (e1 * e1 + e2 * e2);
+    }
+  }
+  return 0.5 * (p->k * p->k * (ua * ua + ub * ub) + dy * dy * s);
+}
+
+/* Prior density of x0 at every 2-D node: f(x1) f(x2). */
+static void orc2_prior(const orc_problem* p, double* f2) {
+  int64_t n = p->n_x;
+  double* f = (double*)malloc(sizeof(double) * (size_t)n);
+  orc_prior(p, f, NULL);
+  for (int64_t i1 = 0; i1 < n; ++i1)
+    for (int64_t i2 = 0; i2 < n; ++i2) f2[i1 * n + i2] = f[i1] * f[i2];
+  free(f);
+}
+
+/* L_0 = f B for candidates u [2][n_x^2][n_cand] (first coordinates, then
+ * second). */
+void orc2_marginal_cost(const orc_problem* p, const double* u1, const double* u, int64_t n_cand,
+                        double* out) {
+  int64_t n = p->n_x, nn = n * n;
+  double* f2 = (double*)malloc(sizeof(double) * (size_t)nn);
+  orc2_prior(p, f2);
+#pragma omp parallel for schedule(dynamic, 16)
+  for (int64_t i = 0; i < nn; ++i) {
+    double x1 = orc_node(p->x_lo, p->x_hi, n, i / n), x2 = orc_node(p->x_lo, p->x_hi, n, i % n);
+    for (int64_t c = 0; c < n_cand; ++c)
+      out[i * n_cand + c] =
+          f2[i] * orc2_B(p, u1, x1, x2, u[i * n_cand + c], u[nn * n_cand + i * n_cand + c]);
+  }
+  free(f2);
+}
+
+/* Selection among 2-D candidates: ties within the relative band TAU64 of the
+ * minimum; the one nearest the incumbent (squared Euclidean distance) wins,
+ * then the smaller first coordinate, then the smaller second, then the
+ * earlier index. */
+static int orc2_select(int n, const double* ca, const double* cb, const double* B, double ia, double ib) {
+  double m = B[0];
+  for (int s = 1; s < n; ++s)
+    if (B[s] < m) m = B[s];
+  double thr = m * (1.0 + ORC_TAU64);
+  int best = -1;
+  double bd = 0.0;
+  for (int s = 0; s < n; ++s) {
+    if (!(B[s] <= thr)) continue;
+    double da = ca[s] - ia, db = cb[s] - ib;
+    double d = da * da + db * db;
+    if (best < 0 || d < bd || (d == bd && (ca[s] < ca[best] || (ca[s] == ca[best] && cb[s] < cb[best])))) {
+      best = s;
+      bd = d;
+    }
+  }
+  return best;
+}
+
+/* Coarse-to-fine search in 2-D: level 0 is the K x K tensor grid on
+ * [u_lo, u_hi]^2 (candidate q1 * K + q2 at (u_lo + q1 h0, u_lo + q2 h0));
+ * level l the K x K grid on the bracket c* -/+ h_{l-1} in each coordinate,
+ * clamped, the best so far carried as index K^2; the incumbent compared
+ * last.  Same spacings as the 1-D search. */
+static void orc2_argmin_point(const orc_problem* p, const orc_search* s, const double* u1,
+                              const double* h, double x1, double x2, double ia, double ib,
+                              double* oa, double* ob, double* oB) {
+  int K = s->cands, KK = K * K;
+  double* ca = (double*)malloc(sizeof(double) * (size_t)(KK + 1));
+  double* cb = (double*)malloc(sizeof(double) * (size_t)(KK + 1));
+  double* B = (double*)malloc(sizeof(double) * (size_t)(KK + 1));
+  double sa = 0.0, sb = 0.0, sB = 0.0;
+  for (int l = 0; l < s->levels; ++l) {
+    for (int q1 = 0; q1 < K; ++q1)
+      for (int q2 = 0; q2 < K; ++q2) {
+        int q = q1 * K + q2;
+        if (l == 0) {
+          ca[q] = s->u_lo + (double)q1 * h[0];
+          cb[q] = s->u_lo + (double)q2 * h[0];
+        } else {
+          ca[q] = orc_clamp(sa - h[l - 1] + (double)q1 * h[l], s->u_lo, s->u_hi);
+          cb[q] = orc_clamp(sb - h[l - 1] + (double)q2 * h[l], s->u_lo, s->u_hi);
+        }
+        B[q] = orc2_B(p, u1, x1, x2, ca[q], cb[q]);
+      }
+    int n = KK;
+    if (l > 0) {
+      ca[KK] = sa;
+      cb[KK] = sb;
+      B[KK] = sB;
+      n = KK + 1;
+    }
+    int b = orc2_select(n, ca, cb, B, ia, ib);
+    sa = ca[b];
+    sb = cb[b];
+    sB = B[b];
+  }
+  ca[0] = sa;
+  cb[0] = sb;
+  B[0] = sB;
+  ca[1] = ia;
+  cb[1] = ib;
+  B[1] = orc2_B(p, u1, x1, x2, ia, ib);
+  int b = orc2_select(2, ca, cb, B, ia, ib);
+  *oa = ca[b];
+  *ob = cb[b];
+  if (oB) *oB = B[b];
+  free(ca);
+  free(cb);
+  free(B);
+}
+
+/* One u0 update of the listed 2-D points (rows == NULL: all n_x^2);
+ * u0_in is [2][n_x^2], u0_out [2][n_rows], B_out [n_rows]. */
+void orc2_argmin(const orc_problem* p, const orc_search* s, const double* u1, const double* u0_in,
+                 const int64_t* rows, int64_t n_rows, double* u0_out, double* B_out) {
+  double h[64];
+  orc_spacings(s, h);
+  int64_t n = p->n_x, nn = n * n;
+  int64_t m = rows ? n_rows : nn;
+#pragma omp parallel for schedule(dynamic, 4)
+  for (int64_t r = 0; r < m; ++r) {
+    int64_t i = rows ? rows[r] : r;
+    double x1 = orc_node(p->x_lo, p->x_hi, n, i / n), x2 = orc_node(p->x_lo, p->x_hi, n, i % n);
+    double Bv;
+    orc2_argmin_point(p, s, u1, h, x1, x2, u0_in[i], u0_in[nn + i], &u0_out[r], &u0_out[m + r], &Bv);
+    if (B_out) B_out[r] = Bv;
+  }
+}
+
+/* Second controller by its closed form, the conditional mean of x1 given
+ * y1 = y_j, with the weights max-shifted per y node as in orc_update_u1:
+ * l_ij = log f_i - |y_j - x1_i|^2 / 2.  u1_out is [2][n_rows]. */
+void orc2_update_u1(const orc_problem* p, const double* u0, const int64_t* rows, int64_t n_rows,
+                    double* u1_out) {
+  int64_t n = p->n_x, nn = n * n, ny = p->n_y;
+  double* lf = (double*)malloc(sizeof(double) * (size_t)n);
+  double* lf2 = (double*)malloc(sizeof(double) * (size_t)nn);
+  double* xa = (double*)malloc(sizeof(double) * (size_t)nn);
+  double* xb = (double*)malloc(sizeof(double) * (size_t)nn);
+  orc_prior(p, NULL, lf);
+  for (int64_t i = 0; i < nn; ++i) {
+    lf2[i] = lf[i / n] + lf[i % n];
+    xa[i] = orc_node(p->x_lo, p->x_hi, n, i / n) + u0[i];
+    xb[i] = orc_node(p->x_lo, p->x_hi, n, i % n) + u0[nn + i];
+  }
+  int64_t m = rows ? n_rows : ny * ny;
+#pragma omp parallel for schedule(dynamic, 16)
+  for (int64_t r = 0; r < m; ++r) {
+    int64_t j = rows ? rows[r] : r;
+    double ya = orc_node(p->y_lo, p->y_hi, ny, j / ny), yb = orc_node(p->y_lo, p->y_hi, ny, j % ny);
+    double M = -INFINITY;
+    for (int64_t i = 0; i < nn; ++i) {
+      double da = ya - xa[i], db = yb - xb[i];
+      double l = lf2[i] - 0.5 * (da * da + db * db);
+      if (l > M) M = l;
+    }
+    double na = 0.0, nb = 0.0, den = 0.0;
+    for (int64_t i = 0; i < nn; ++i) {
+      double da = ya - xa[i], db = yb - xb[i];
+      double e = exp(lf2[i] - 0.5 * (da * da + db * db) - M);
+      na += xa[i] * e;
+      nb += xb[i] * e;
+      den += e;
+    }
+    u1_out[r] = na / den;
+    u1_out[m + r] = nb / den;
+  }
+  free(lf);
+  free(lf2);
+  free(xa);
+  free(xb);
+}
+
+/* J = dx^2 sum_i f_i B(u0_i; x_i) for the 2-D problem. */
+double orc2_objective(const orc_problem* p, const double* u0, const double* u1) {
+  int64_t n = p->n_x, nn = n * n;
+  double dx = (p->x_hi - p->x_lo) / (double)(n - 1);
+  double* f2 = (double*)malloc(sizeof(double) * (size_t)nn);
+  double* row = (double*)malloc(sizeof(double) * (size_t)nn);
+  orc2_prior(p, f2);
+#pragma omp parallel for schedule(dynamic, 16)
+  for (int64_t i = 0; i < nn; ++i) {
+    double x1 = orc_node(p->x_lo, p->x_hi, n, i / n), x2 = orc_node(p->x_lo, p->x_hi, n, i % n);
+    row[i] = f2[i] * orc2_B(p, u1, x1, x2, u0[i], u0[nn + i]);
+  }
+  double J = 0.0;
+  for (int64_t i = 0; i < nn; ++i) J += row[i];
+  free(f2);
+  free(row);
+  return dx * dx * J;
+}
+
+/* The solve loop of orc_solve in 2-D; u0 and u1 are two planes each. */
+void orc2_solve(const orc_problem* p, const orc_search* s, int32_t iters, const double* u0_init,
+                double* u0_out, double* u1_out, double* J_hist) {
+  int64_t nn = p->n_x * p->n_x;
+  double* u0 = (double*)malloc(sizeof(double) * (size_t)(2 * nn));
+  double* nxt = (double*)malloc(sizeof(double) * (size_t)(2 * nn));
+  memcpy(u0, u0_init, sizeof(double) * (size_t)(2 * nn));
+  orc2_update_u1(p, u0, NULL, 0, u1_out);
+  J_hist[0] = orc2_objective(p, u0, u1_out);
+  for (int32_t t = 1; t <= iters; ++t) {
+    orc2_argmin(p, s, u1_out, u0, NULL, 0, nxt, NULL);
+    memcpy(u0, nxt, sizeof(double) * (size_t)(2 * nn));
+    orc2_update_u1(p, u0, NULL, 0, u1_out);
+    J_hist[t] = orc2_objective(p, u0, u1_out);
+  }
+  memcpy(u0_out, u0, sizeof(double) * (size_t)(2 * nn));
+  free(u0);
+  free(nxt);
+}

@@ -219,3 +219,58 @@ def coding_paper_case(n: int = 20001, iters: int = 30) -> CodingCase:
     the Witsenhausen runs on [-4, 4], 30 rounds."""
     p = coding_problem(n, n)
     return CodingCase(f"coding-{n}-5x16", p, Search(-4.0, 4.0, 5, 16), iters, coding_init(p, 0))
+
+
+# --- two-dimensional Witsenhausen (Section V-E) -----------------------------
+# x0 in R^2 with both coordinates drawn from the same prior, w ~ N(0, I_2),
+# J = 1/2 E[k^2 |u0|^2 + |x2|^2]; the paper runs k = 0.2, sigma = 5 on
+# 160 x 160 nodes.  Vector fields are arrays [2, n * n], node (i1, i2) at
+# index i1 * n + i2.
+
+def w2_problem(n: int, n_y: int = None, k: float = 0.2, sigma: float = 5.0, half: float = 25.0) -> Problem:
+    """The 1-D problem whose tensor product is the 2-D grid."""
+    return Problem(k=k, comps=[(1.0, 0.0, sigma)], x_lo=-half, x_hi=half, n_x=n, y_lo=-half, y_hi=half,
+                   n_y=n_y or n)
+
+
+def w2_separable(prob: Problem, g: np.ndarray) -> np.ndarray:
+    """u0(x) = (g(x1), g(x2)) from a 1-D field g on the grid."""
+    n = int(prob.n_x)
+    return np.stack([np.repeat(g, n), np.tile(g, n)])
+
+
+def w2_init(prob: Problem, seed: int = 0) -> np.ndarray:
+    """A non-separable start: sigma sign(x_c) - x_c in each coordinate c,
+    plus a seeded smooth coupling 0.5 sin(x_2 / 3) in the first coordinate."""
+    n = int(prob.n_x)
+    x = nodes(prob.x_lo, prob.x_hi, n)
+    sigma = float(prob.comps[0][2])
+    g = sigma * np.sign(x) - x
+    u = w2_separable(prob, g)
+    rng = np.random.default_rng(seed)
+    ph = rng.uniform(0, 2 * math.pi)
+    u[0] += 0.5 * np.sin(np.tile(x, n) / 3.0 + ph)
+    return u
+
+
+@dataclass
+class W2Case:
+    name: str
+    prob: Problem
+    search: Search
+    iters: int
+    u0_init: np.ndarray = field(repr=False)
+
+
+def w2_small_case() -> W2Case:
+    """21 x 21 x-nodes, 31 x 31 y-nodes on [-25, 25], 3 levels x 5 x 5
+    candidates on [-30, 30], 3 rounds."""
+    p = w2_problem(21, 31)
+    return W2Case("w2-21x31-3x5", p, Search(-30.0, 30.0, 3, 5), 3, w2_init(p, 1))
+
+
+def w2_paper_case(iters: int = 10) -> W2Case:
+    """k = 0.2, sigma = 5, 160 x 160 nodes on [-25, 25] (the paper's sample
+    count), 4 levels x 8 x 8 candidates on [-30, 30]."""
+    p = w2_problem(160)
+    return W2Case("w2-160-4x8x8", p, Search(-30.0, 30.0, 4, 8), iters, w2_init(p, 0))
