@@ -269,6 +269,60 @@ int ucp_coding_solve(ucp_handle* h, const ucp_coding_problem* prob, const ucp_se
                      int32_t iters, const double* u0_init, double* u0_out, double* u1_out,
                      double* J_hist, void* stream);
 
+/* ---- Two-dimensional Witsenhausen counterexample (Section V-E) ---------
+ * x0 in R^2 with both coordinates independent draws of the prior of
+ * `prob`, x1 = x0 + u0(x0), y1 = x1 + w with w ~ N(0, I_2),
+ * x2 = x1 - u1(y1); minimise J = 1/2 E[k^2 |u0|^2 + |x2|^2] (the paper:
+ * k = 0.2, sigma = 5 on 160 x 160 nodes).  The grids are tensor products:
+ * x node (i1, i2) at index i1 * n_x + i2, y node (j1, j2) at j1 * n_y + j2,
+ * at most 4096 nodes per coordinate; rectangle rule with weights dx^2 and
+ * dy^2.  Vector fields are two planes: [2][n_x^2] for u0, [2][n_y^2] for
+ * u1 (first coordinates, then second).  FP64 throughout.  The noise sums
+ * run over the nodes within 10 standard deviations of the node nearest
+ * x + u in each coordinate (omitted weight below 1e-21 relative). */
+
+/* L0_out[i*n_cand + c] = f(x_i1) f(x_i2) B(u; x_i) with
+ * B = 1/2 [k^2 |u|^2 + dy^2 sum_j phi(y_j1 - z1) phi(y_j2 - z2) |z - u1(y_j)|^2],
+ * z = x_i + u, u = (u[i*n_cand + c], u[n_x^2 * n_cand + i*n_cand + c]).
+ * u1: [2][n_y^2]; u: [2][n_x^2][n_cand]; L0_out: [n_x^2][n_cand].
+ * Errors: UCP_EINVAL (null pointers, n_cand outside 1..4096, invalid or too
+ * large problem). */
+int ucp_w2_marginal_cost(ucp_handle* h, const ucp_problem* prob, const double* u1, const double* u,
+                         int64_t n_cand, double* L0_out, void* stream);
+
+/* One pointwise improvement of u0 with u1 fixed: the coarse-to-fine search
+ * over the K x K tensor grid of candidates per level (K = cands <= 8;
+ * level 0 on [u_lo, u_hi]^2, level l on c* -/+ h_{l-1} in each coordinate,
+ * clamped; the best so far carried; spacings as in ucp_search), then the
+ * incumbent.  Selection: the candidates within a relative band 1e-12 of
+ * the minimum are ties; the nearest to u0_in (squared distance) wins, then
+ * the smaller first coordinate, then the smaller second, then the earlier
+ * candidate (index q1 * K + q2, the best so far last).
+ * u0_in, u0_out: [2][n_x^2] (may alias); L0_out: [n_x^2] or NULL.
+ * Errors: UCP_EINVAL (also cands > 8). */
+int ucp_w2_argmin(ucp_handle* h, const ucp_problem* prob, const ucp_search* search, const double* u1,
+                  const double* u0_in, double* u0_out, double* L0_out, void* stream);
+
+/* u1(y_j) = E[x1 | y1 = y_j] = sum_i f_i phi2(y_j - x1_i) x1_i / sum_i f_i phi2(y_j - x1_i),
+ * x1_i = x_i + u0_i, phi2 the N(0, I_2) density; the weights are
+ * max-shifted (log f(x_i1) + log f(x_i2) - |y_j - x1_i|^2 / 2).
+ * u0: [2][n_x^2]; u1_out: [2][n_y^2].  Errors: UCP_EINVAL. */
+int ucp_w2_update_u1(ucp_handle* h, const ucp_problem* prob, const double* u0, double* u1_out,
+                     void* stream);
+
+/* J = dx^2 sum_i f(x_i1) f(x_i2) B(u0_i; x_i), in FP64.
+ * u0: [2][n_x^2]; u1: [2][n_y^2]; J_out: one double.  Errors: UCP_EINVAL. */
+int ucp_w2_objective(ucp_handle* h, const ucp_problem* prob, const double* u0, const double* u1,
+                     double* J_out, void* stream);
+
+/* The solve loop of ucp_solve in 2-D (u1 from u0_init, J_hist[0], then
+ * `iters` rounds of ucp_w2_argmin and ucp_w2_update_u1 with J after each).
+ * Profiling kinds as for ucp_coding_solve (UCP_PROF_MC = the search).
+ * u0_init, u0_out: [2][n_x^2] (may alias); u1_out: [2][n_y^2];
+ * J_hist: [iters + 1].  Errors: UCP_EINVAL. */
+int ucp_w2_solve(ucp_handle* h, const ucp_problem* prob, const ucp_search* search, int32_t iters,
+                 const double* u0_init, double* u0_out, double* u1_out, double* J_hist, void* stream);
+
 /* ---- Continuous-batching server --------------------------------------
  * Requests (HOST arrays) are admitted while the number of running solves is
  * below `max_slots` and their device footprint fits in `hbm_budget` bytes;

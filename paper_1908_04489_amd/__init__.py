@@ -84,6 +84,11 @@ _sigs = {
     "ucp_coding_update_u1": ([_vp, _P(CodingProblem), _vp, _vp, _vp], C.c_int),
     "ucp_coding_objective": ([_vp, _P(CodingProblem), _vp, _vp, _vp, _vp], C.c_int),
     "ucp_coding_solve": ([_vp, _P(CodingProblem), _P(Search), C.c_int32, _vp, _vp, _vp, _vp, _vp], C.c_int),
+    "ucp_w2_marginal_cost": ([_vp, _P(Problem), _vp, _vp, C.c_int64, _vp, _vp], C.c_int),
+    "ucp_w2_argmin": ([_vp, _P(Problem), _P(Search), _vp, _vp, _vp, _vp, _vp], C.c_int),
+    "ucp_w2_update_u1": ([_vp, _P(Problem), _vp, _vp, _vp], C.c_int),
+    "ucp_w2_objective": ([_vp, _P(Problem), _vp, _vp, _vp, _vp], C.c_int),
+    "ucp_w2_solve": ([_vp, _P(Problem), _P(Search), C.c_int32, _vp, _vp, _vp, _vp, _vp], C.c_int),
     "ucp_server_create": ([_P(_vp), C.c_int, C.c_size_t, C.c_int32, C.c_int], C.c_int),
     "ucp_server_destroy": ([_vp], None),
     "ucp_server_submit": ([_vp, _P(Problem), _P(Search), C.c_int32, _vp, _P(C.c_int64)], C.c_int),
@@ -470,4 +475,79 @@ def coding_solve(prob, search, iters, u0_init):
     d = _dev(u0_init)
     _check(_lib.ucp_coding_solve(handle(d), C.byref(P), C.byref(S), int(iters), _vp(u0_init.data_ptr()),
                                  _vp(u0.data_ptr()), _vp(u1.data_ptr()), _vp(J.data_ptr()), _stream(d)))
+    return u0, u1, J
+
+
+# ------------------------------------ two-dimensional Witsenhausen (Section V-E)
+# Vector fields are device tensors [2, n * n] (node (i1, i2) at i1 * n + i2).
+
+def _dev_planes(t, n, name):
+    _dev_f64(t, 2 * n, name)
+    if t.dim() != 2 or t.shape[0] != 2:
+        raise ValueError(f"{name} must be [2, {n}]")
+    return t
+
+
+def w2_marginal_cost(prob, u1, u):
+    """L_0 [n_x^2, n_cand] for candidates u [2, n_x^2, n_cand]."""
+    torch = _torch()
+    P = make_problem(prob)
+    _dev_planes(u1, P.n_y ** 2, "u1")
+    _dev_f64(u, None, "u")
+    if u.dim() != 3 or u.shape[0] != 2 or u.shape[1] != P.n_x ** 2:
+        raise ValueError("u must be [2, n_x^2, n_cand]")
+    out = torch.empty(u.shape[1], u.shape[2], dtype=torch.float64, device=u.device)
+    d = _dev(u1)
+    _check(_lib.ucp_w2_marginal_cost(handle(d), C.byref(P), _vp(u1.data_ptr()), _vp(u.data_ptr()), u.shape[2],
+                                     _vp(out.data_ptr()), _stream(d)))
+    return out
+
+
+def w2_argmin(prob, search, u1, u0, want_l0=False):
+    torch = _torch()
+    P, S = make_problem(prob), make_search(search)
+    _dev_planes(u1, P.n_y ** 2, "u1")
+    _dev_planes(u0, P.n_x ** 2, "u0")
+    out = torch.empty_like(u0)
+    l0 = torch.empty(P.n_x ** 2, dtype=torch.float64, device=u0.device) if want_l0 else None
+    d = _dev(u0)
+    _check(_lib.ucp_w2_argmin(handle(d), C.byref(P), C.byref(S), _vp(u1.data_ptr()), _vp(u0.data_ptr()),
+                              _vp(out.data_ptr()), _vp(l0.data_ptr() if l0 is not None else 0), _stream(d)))
+    return (out, l0) if want_l0 else out
+
+
+def w2_update_u1(prob, u0):
+    torch = _torch()
+    P = make_problem(prob)
+    _dev_planes(u0, P.n_x ** 2, "u0")
+    out = torch.empty(2, P.n_y ** 2, dtype=torch.float64, device=u0.device)
+    d = _dev(u0)
+    _check(_lib.ucp_w2_update_u1(handle(d), C.byref(P), _vp(u0.data_ptr()), _vp(out.data_ptr()), _stream(d)))
+    return out
+
+
+def w2_objective(prob, u0, u1):
+    torch = _torch()
+    P = make_problem(prob)
+    _dev_planes(u0, P.n_x ** 2, "u0")
+    _dev_planes(u1, P.n_y ** 2, "u1")
+    out = torch.empty(1, dtype=torch.float64, device=u0.device)
+    d = _dev(u0)
+    _check(_lib.ucp_w2_objective(handle(d), C.byref(P), _vp(u0.data_ptr()), _vp(u1.data_ptr()),
+                                 _vp(out.data_ptr()), _stream(d)))
+    return out
+
+
+def w2_solve(prob, search, iters, u0_init):
+    """Returns (u0 [2, n_x^2], u1 [2, n_y^2], J_hist[iters + 1]) as device tensors."""
+    torch = _torch()
+    P, S = make_problem(prob), make_search(search)
+    _dev_planes(u0_init, P.n_x ** 2, "u0_init")
+    dev = u0_init.device
+    u0 = torch.empty(2, P.n_x ** 2, dtype=torch.float64, device=dev)
+    u1 = torch.empty(2, P.n_y ** 2, dtype=torch.float64, device=dev)
+    J = torch.empty(int(iters) + 1, dtype=torch.float64, device=dev)
+    d = _dev(u0_init)
+    _check(_lib.ucp_w2_solve(handle(d), C.byref(P), C.byref(S), int(iters), _vp(u0_init.data_ptr()),
+                             _vp(u0.data_ptr()), _vp(u1.data_ptr()), _vp(J.data_ptr()), _stream(d)))
     return u0, u1, J

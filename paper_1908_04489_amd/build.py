@@ -1,6 +1,10 @@
 """Build step of the HIP library: compiles csrc/ for gfx950 into
 ``paper_1908_04489_amd/libucp.so`` with hipcc.
 
+Load this file by path (importlib), not as
+``paper_1908_04489_amd.build``: importing the package binds the library,
+which does not exist yet (or is stale) when a build is needed.
+
 Flags: -O3, no FP contraction outside explicit fmaf (candidate positions and
 grid nodes are plain binary64 sums and products), packed-FP32 instructions
 disabled.
@@ -15,7 +19,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libucp.so")
-SOURCES = ["ucp_kernels.hip", "ucp_coding.hip", "ucp_api.cpp", "ucp_server.cpp"]
+SOURCES = ["ucp_kernels.hip", "ucp_coding.hip", "ucp_w2.hip", "ucp_api.cpp", "ucp_server.cpp"]
 ARCH = os.environ.get("UCP_OFFLOAD_ARCH", "gfx950")
 
 

@@ -16,8 +16,12 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 def U():
     lib = os.path.join(ROOT, "paper_1908_04489_amd", "libucp.so")
     if not os.path.exists(lib):
-        from paper_1908_04489_amd import build as B
+        import importlib.util
 
+        spec = importlib.util.spec_from_file_location("ucp_build",
+                                                      os.path.join(ROOT, "paper_1908_04489_amd", "build.py"))
+        B = importlib.util.module_from_spec(spec)
+        spec.loader.exec_module(B)
         B.build()
     import paper_1908_04489_amd as U
 
@@ -153,6 +157,27 @@ def test_coding_struct_and_argument_checks(U):
     assert lib.ucp_coding_marginal_cost(fake, C.byref(P), v, v, 0, v, None) == U.EINVAL
     assert lib.ucp_coding_update_u1(fake, C.byref(P), None, v, None) == U.EINVAL
     assert lib.ucp_coding_objective(None, C.byref(P), v, v, v, None) == U.EINVAL
+
+
+def test_w2_argument_checks(U):
+    lib = U.library()
+    fake = C.c_void_p(1)
+    v = C.c_void_p(8)
+    P = U.make_problem(W.w2_problem(21, 31))
+    S = U.make_search(W.Search(-30, 30, 3, 5))
+    big = U.make_problem(W.w2_problem(4097, 31))
+    for Pb in (big, U.make_problem(W.gaussian_problem(-1.0, 5.0, 21, 25.0))):
+        assert lib.ucp_w2_objective(fake, C.byref(Pb), v, v, v, None) == U.EINVAL
+        assert lib.ucp_w2_update_u1(fake, C.byref(Pb), v, v, None) == U.EINVAL
+        assert lib.ucp_w2_marginal_cost(fake, C.byref(Pb), v, v, 2, v, None) == U.EINVAL
+        assert lib.ucp_w2_argmin(fake, C.byref(Pb), C.byref(S), v, v, v, None, None) == U.EINVAL
+        assert lib.ucp_w2_solve(fake, C.byref(Pb), C.byref(S), 1, v, v, v, v, None) == U.EINVAL
+    S9 = U.make_search(W.Search(-30, 30, 3, 9))  # 9 x 9 candidates exceed one wave
+    assert lib.ucp_w2_argmin(fake, C.byref(P), C.byref(S9), v, v, v, None, None) == U.EINVAL
+    assert lib.ucp_w2_solve(fake, C.byref(P), C.byref(S), -1, v, v, v, v, None) == U.EINVAL
+    assert lib.ucp_w2_solve(fake, C.byref(P), None, 1, v, v, v, v, None) == U.EINVAL
+    assert lib.ucp_w2_marginal_cost(fake, C.byref(P), v, v, 0, v, None) == U.EINVAL
+    assert lib.ucp_w2_objective(None, C.byref(P), v, v, v, None) == U.EINVAL
 
 
 def test_footprint_without_device(U):
