@@ -51,6 +51,10 @@ PEAK_SLOTS = 256 * 128 * 2.4e9
 # scaling (6) and the window's ends (30).
 PEAK_FP64 = 78.6e12
 CODING_FLOPS_PER_B = 144
+# Two-dimensional Witsenhausen search: one windowed noise term is two
+# differences, |e|^2 (two products and a sum), the weighted accumulate (an
+# FMA) and the Gaussian recurrence (two products): 9 FP64 flops.
+W2_FLOPS_PER_TERM = 9
 SLOTS_PER_TERM = 3.46875
 
 
@@ -400,6 +404,115 @@ def bench_coding(a):
     print(json.dumps(res), flush=True)
 
 
+def bench_w2(a):
+    """Two-dimensional Witsenhausen (Section V-E): k = 0.2, sigma = 5,
+    160 x 160 nodes, 4 levels x 8 x 8 candidates, 10 rounds; one step is
+    one whole solve, FP64."""
+    import numpy as np
+    import torch
+
+    import paper_1908_04489_amd as U
+    import workloads as W
+
+    case = W.w2_paper_case()
+    p, s = case.prob, case.search
+    u0 = torch.as_tensor(case.u0_init).cuda()
+    print(f"# workload {case.name}: {p.n_x}^2 nodes, {s.levels}x{s.cands}^2, {case.iters} rounds, fp64",
+          file=sys.stderr, flush=True)
+    for w in range(a.warmup):
+        U.w2_solve(p, s, case.iters, u0)
+    st = torch.cuda.current_stream()
+    torch.cuda.synchronize()
+    U.profile(["marginal_cost"])  # HIP events around each search launch of the timed solves
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record(st)
+    for k in range(a.steps):
+        out = U.w2_solve(p, s, case.iters, u0)
+        print(f"# step {k} done", file=sys.stderr, flush=True)
+    ev1.record(st)
+    torch.cuda.synchronize()
+    ms_step = ev0.elapsed_time(ev1) / a.steps
+    se_ms, se_n = U.profile_read()["marginal_cost"]
+    breakdown = kernel_breakdown(U, lambda: U.w2_solve(p, s, case.iters, u0))
+    se_avg_s = se_ms / 1e3 / max(se_n, 1)
+    terms = w2_search_terms(p, s, out[0].cpu().numpy())
+    achieved = terms * W2_FLOPS_PER_TERM / se_avg_s
+    J = out[2].cpu().numpy()
+    res = {"metric": "2-D Witsenhausen solves/s", "value": 1e3 / ms_step, "unit": "solves/s", "n_gpus": 1,
+           "steps": a.steps, "warmup": a.warmup, "ms_per_step": ms_step, "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+           "config": {"workload": case.name, "n_x": p.n_x, "n_y": p.n_y, "levels": s.levels, "cands": s.cands,
+                      "rounds": case.iters, "k": p.k, "sigma": 5.0},
+           "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP64 / 1e12, "unit": "TFLOP/s",
+                        "frac": achieved / PEAK_FP64, "traffic": None, "kernel": "k_w2_search (2-D search)",
+                        "per_unit": f"{W2_FLOPS_PER_TERM} FP64 flops per windowed term, {terms:.3e} per launch",
+                        "kernel_avg_us": se_avg_s * 1e6, "kernel_launches": se_n},
+           "kernel_ms_per_step": {"search": breakdown["marginal_cost"], "u1": breakdown["u1"],
+                                  "objective": breakdown["objective"]},
+           "J_final": float(J[-1]), "J_paper_context": 0.166719}
+    if not a.no_cpu:
+        res["cpu_baseline"] = w2_cpu_baseline(case)
+    print(json.dumps(res), flush=True)
+
+
+def w2_cpu_baseline(case):
+    """The oracle's 2-D functions, as they stand, on a bounded sample of the
+    same workload scaled to one whole solve: the search on evenly spaced
+    points (sized to about 10 s), the decoder on evenly spaced y nodes, one
+    full objective."""
+    import numpy as np
+
+    import oracle
+
+    p, s = case.prob, case.search
+    nn, m = p.n_x ** 2, p.n_y ** 2
+    u1 = oracle.w2_update_u1(p, case.u0_init)
+    rows = np.linspace(0, nn - 1, 16).astype(np.int64)
+    t0 = time.perf_counter()
+    oracle.w2_argmin(p, s, u1, case.u0_init, rows)
+    n = int(min(nn, 16 * 10.0 / max(time.perf_counter() - t0, 1e-6)))
+    rows = np.linspace(0, nn - 1, n).astype(np.int64)
+    t0 = time.perf_counter()
+    oracle.w2_argmin(p, s, u1, case.u0_init, rows)
+    t_arg = (time.perf_counter() - t0) * nn / n
+    t0 = time.perf_counter()
+    oracle.w2_update_u1(p, case.u0_init)
+    t_u1 = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    oracle.w2_objective(p, case.u0_init, u1)
+    t_j = time.perf_counter() - t0
+    solve_s = t_u1 + t_j + case.iters * (t_arg + t_u1 + t_j)
+    return {"value": 1.0 / solve_s, "unit": "solves/s", "cores": oracle.num_threads(), "kind": "oracle",
+            "sample": f"search on {n} of {nn} points ({t_arg * n / nn:.1f} s), one full decoder and objective, "
+                      f"scaled to {case.iters} rounds: {solve_s:.0f} s per solve"}
+
+
+def w2_search_terms(p, s, u0):
+    """Windowed noise terms one 2-D search launch sums: level 0 exactly (its
+    candidates are the fixed grid), the later levels' and the incumbent's
+    K^2 (levels - 1) + 1 candidates counted at the final controller (they
+    sit within a few spacings of it)."""
+    import numpy as np
+
+    n, ny = p.n_x, p.n_y
+    dy = (p.y_hi - p.y_lo) / (ny - 1)
+    wn = max(1, min(int(np.floor(10.0 / dy)), ny))
+    x = p.x_lo + np.arange(n) * ((p.x_hi - p.x_lo) / (n - 1))
+
+    def width(z):
+        c = np.clip(np.rint((z - p.y_lo) / dy), 0, ny - 1)
+        return np.minimum(ny - 1, c + wn) - np.maximum(0, c - wn) + 1
+
+    h0 = (s.u_hi - s.u_lo) / (s.cands - 1)
+    c0 = s.u_lo + np.arange(s.cands) * h0
+    w0 = width(x[:, None] + c0[None, :]).sum(axis=1)  # per coordinate value, summed over candidates
+    level0 = float(np.outer(w0, w0).sum())
+    wa = width(np.repeat(x, n) + u0[0])
+    wb = width(np.tile(x, n) + u0[1])
+    later = float((wa * wb).sum()) * (s.cands ** 2 * (s.levels - 1) + 1)
+    return level0 + later
+
+
 def coding_cpu_baseline(case):
     """The oracle's coding functions, as they stand, on a bounded sample of
     the same workload, scaled to one whole solve: an encoder update on evenly
@@ -488,6 +601,8 @@ def main():
         return bench_sweep(a)
     if a.workload == "coding":
         return bench_coding(a)
+    if a.workload == "w2":
+        return bench_w2(a)
     if a.workload == "copy-calibration":
         return copy_calibration()
 

@@ -278,8 +278,9 @@ int ucp_coding_solve(ucp_handle* h, const ucp_coding_problem* prob, const ucp_se
  * at most 4096 nodes per coordinate; rectangle rule with weights dx^2 and
  * dy^2.  Vector fields are two planes: [2][n_x^2] for u0, [2][n_y^2] for
  * u1 (first coordinates, then second).  FP64 throughout.  The noise sums
- * run over the nodes within 10 standard deviations of the node nearest
- * x + u in each coordinate (omitted weight below 1e-21 relative). */
+ * run over the floor(10 / dy) nodes on either side of the node nearest
+ * x + u in each coordinate, at least 10 - 1.5 dy noise standard deviations
+ * (omitted weight below 1e-18 relative for dy <= 1). */
 
 /* L0_out[i*n_cand + c] = f(x_i1) f(x_i2) B(u; x_i) with
  * B = 1/2 [k^2 |u|^2 + dy^2 sum_j phi(y_j1 - z1) phi(y_j2 - z2) |z - u1(y_j)|^2],

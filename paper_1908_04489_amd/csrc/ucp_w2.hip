@@ -5,9 +5,11 @@
 // i1 * n + i2; vector fields as two planes).
 //
 //   k_w2_prior    1-D prior f at the x nodes (the 2-D prior is f(x1) f(x2))
-//   k_w2_search   one wave per point, lane q = candidate q of the K x K grid:
-//                 every level of the coarse-to-fine search and the incumbent
-//                 comparison, the selection rule as a wave reduction
+//   k_w2_search   one wave per point: every level of the coarse-to-fine
+//                 search (the wave sums one candidate at a time over the
+//                 window, lanes along its columns; lane q keeps candidate q)
+//                 and the incumbent comparison, the selection rule as a wave
+//                 reduction
 //   k_w2_mc       L_0 = f B for explicit candidates, one lane each
 //   k_w2_u1_part  u1 sums for 64 y nodes over one segment of x nodes,
 //                 max-shifted within the segment
@@ -25,7 +27,7 @@
 namespace ucp {
 namespace {
 
-constexpr double kW2Win = 10.0;  // noise sds summed around the nearest y node
+constexpr double kW2Win = 10.0;  // noise sds (window half-width floor(kW2Win / dy) nodes)
 constexpr int kW2Seg = 16;       // x segments of the u1 sums (at most)
 constexpr int kW2Tile = 256;     // x nodes staged in LDS per step of the u1 sums
 
@@ -133,8 +135,54 @@ __device__ __forceinline__ bool later_wins(double ds, double sa, double sb, doub
   return ds < dw || (ds == dw && (sa < wa || (sa == wa && sb < wb)));
 }
 
+// B of one candidate, summed by a whole wave: the window's columns go in
+// chunks of 64, lane t on column chunk + t (coalesced row segments of u1);
+// the row factors phi(y_j1 - z1) are computed one per lane and broadcast;
+// the lanes' partial sums are added in a fixed tree.  Every lane returns B.
+__device__ double w2_B_wave(const W2Params& P, const double* __restrict__ u1a, const double* __restrict__ u1b,
+                            double x1, double x2, double ua, double ub) {
+  const int t = threadIdx.x & 63;
+  const double z1 = x1 + ua, z2 = x2 + ub;
+  int a1, b1, a2, b2;
+  w2_window(P, z1, a1, b1);
+  w2_window(P, z2, a2, b2);
+  double part = 0.0;
+  for (int cc = a2; cc <= b2; cc += 64) {
+    const int c = cc + t;
+    const bool have = c <= b2;
+    const double g2 = have ? phi(ynode(P, c) - z2) : 0.0;
+    for (int r0 = a1; r0 <= b1; r0 += 64) {
+      const int nr = min(64, b1 - r0 + 1);
+      const double g1v = t < nr ? phi(ynode(P, r0 + t) - z1) : 0.0;
+      // rows in batches of 8, every load of a batch issued before its use
+      // (addresses clamped into the window; the clamped terms are skipped)
+      const int cl = have ? c : a2;
+      for (int k0 = 0; k0 < nr; k0 += 8) {
+        double va[8], vb[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          const long o = (long)(r0 + min(k0 + u, nr - 1)) * P.ny + cl;
+          va[u] = u1a[o];
+          vb[u] = u1b[o];
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          const double g1 = __shfl(g1v, min(k0 + u, 63));
+          if (have && k0 + u < nr) {
+            const double e1 = z1 - va[u], e2 = z2 - vb[u];
+            part = fma(g1 * g2, e1 * e1 + e2 * e2, part);
+          }
+        }
+      }
+    }
+  }
+  for (int o = 32; o > 0; o >>= 1) part += __shfl_xor(part, o);
+  return 0.5 * (P.k * P.k * (ua * ua + ub * ub) + P.dy * P.dy * part);
+}
+
 // One wave per point.  u0_in and u0_out (two planes each) may alias: the
-// wave reads its point before lane 0 writes it.
+// wave reads its point before lane 0 writes it.  The wave sums each
+// candidate in turn (w2_B_wave), and lane q keeps candidate q's B.
 __global__ __launch_bounds__(64) void k_w2_search(W2Params P, const double* __restrict__ f,
                                                   const double* __restrict__ u1, const double* u0_in,
                                                   double* u0_out, double* L0_out) {
@@ -150,7 +198,11 @@ __global__ __launch_bounds__(64) void k_w2_search(W2Params P, const double* __re
     const bool live = q < KK;
     const double ca = live ? cand(P, l, q / K, sa) : 0.0;
     const double cb = live ? cand(P, l, q % K, sb) : 0.0;
-    const double B = live ? w2_B(P, u1a, u1b, x1, x2, ca, cb) : INFINITY;
+    double B = INFINITY;
+    for (int c = 0; c < KK; ++c) {
+      const double Bc = w2_B_wave(P, u1a, u1b, x1, x2, cand(P, l, c / K, sa), cand(P, l, c % K, sb));
+      if (c == q) B = Bc;
+    }
     double m = B;
     for (int o = 32; o > 0; o >>= 1) m = fmin(m, __shfl_xor(m, o));
     if (l > 0 && sB < m) m = sB;
@@ -179,7 +231,7 @@ __global__ __launch_bounds__(64) void k_w2_search(W2Params P, const double* __re
     sB = kB;
   }
   // acceptance against the incumbent (index 1, after the search's winner)
-  const double Bi = w2_B(P, u1a, u1b, x1, x2, ia, ib);
+  const double Bi = w2_B_wave(P, u1a, u1b, x1, x2, ia, ib);
   double m = sB;
   if (Bi < m) m = Bi;
   const double thr = m * (1.0 + 1e-12);
@@ -350,8 +402,10 @@ int w2_params(const ucp_problem* p, const ucp_search* s, W2Params& P) {
   P.dy = (p->y_hi - p->y_lo) / (double)(p->n_y - 1);
   P.inv_dy = 1.0 / P.dy;
   P.Q = std::exp(-P.dy * P.dy);
-  const double wn = std::ceil(kW2Win * P.inv_dy);
-  P.wn = (int)std::fmin(wn, (double)P.ny);
+  // floor: at least kW2Win - dy from z on either side, and on the paper's
+  // grid (dy = 50/159) 63 columns, one chunk of a wave's lanes
+  const double wn = std::floor(kW2Win * P.inv_dy);
+  P.wn = (int)std::fmax(1.0, std::fmin(wn, (double)P.ny));
   if (s) {
     P.u_lo = s->u_lo;
     P.u_hi = s->u_hi;

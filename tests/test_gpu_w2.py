@@ -1,9 +1,10 @@
 """GPU parity of the two-dimensional Witsenhausen calls (Section V-E)
 against the FP64 oracle, on identical seeded inputs.
 
-Tolerances: both sides FP64; the GPU sums the noise within 10 standard
-deviations per coordinate with a per-row recurrence for the Gaussian
-(relative error ~1e-14 against exp per node), the oracle densely with exp:
+Tolerances: both sides FP64; the GPU's search sums the noise over a window
+of floor(10 / dy) nodes either side of the nearest node per coordinate
+(the explicit-candidate and objective sums with a per-row recurrence for
+the Gaussian, relative error ~1e-14), the oracle densely with exp:
   - marginal cost and objective: relative 1e-11;
   - u1: 1e-10 absolute (segmented max-shifted sums against one pass);
   - search and solve: decisions equal to the oracle's.
