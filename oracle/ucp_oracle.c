@@ -1,6 +1,7 @@
 /*
  * Plain FP64 CPU oracle for the marginal-cost solver on Witsenhausen's
- * counterexample.
+ * counterexample, and (at the end of this file) on the zero-delay
+ * source-channel coding problem and the two-dimensional counterexample.
  *
  * TEST INFRASTRUCTURE ONLY.  This is the slow, obviously correct statement
  * of what the GPU path computes.  Only the tests, the smoke check and the
