@@ -149,3 +149,18 @@ def test_fullsize_sampled(env):
     assert np.array_equal(nxt[rows], ref)
     yrows = np.random.default_rng(6).choice(p.n_y, 48, replace=False)
     assert np.max(np.abs(u1h[yrows] - orc.coding_update_u1(p, u0h, yrows))) < 1e-12
+
+
+def test_solve_kernel_timing(env):
+    # ucp_profile around a coding solve: one timed search per round, the
+    # results unchanged by the timing
+    U, orc, torch = env
+    c = W.coding_small_case()
+    ref = U.coding_solve(c.prob, c.search, c.iters, dev(torch, c.u0_init))
+    U.profile(True)
+    out = U.coding_solve(c.prob, c.search, c.iters, dev(torch, c.u0_init))
+    prof = U.profile_read()
+    U.profile(None)
+    assert prof["marginal_cost"][1] == c.iters and prof["marginal_cost"][0] > 0.0
+    assert prof["u1"][1] == c.iters + 1 and prof["objective"][1] == c.iters + 1
+    assert all(torch.equal(a, b) for a, b in zip(ref, out))

@@ -115,3 +115,15 @@ def test_paper_size_sampled(env):
     assert np.array_equal(nxt[:, rows], ref)
     yrows = np.random.default_rng(9).choice(p.n_y ** 2, 24, replace=False)
     assert np.max(np.abs(host(u1)[:, yrows] - orc.w2_update_u1(p, host(u0), yrows))) < 1e-10
+
+
+def test_solve_kernel_timing(env):
+    U, orc, torch = env
+    c = W.w2_small_case()
+    ref = U.w2_solve(c.prob, c.search, c.iters, dev(torch, c.u0_init))
+    U.profile(["marginal_cost"])
+    out = U.w2_solve(c.prob, c.search, c.iters, dev(torch, c.u0_init))
+    prof = U.profile_read()
+    U.profile(None)
+    assert prof["marginal_cost"][1] == c.iters and prof["u1"][1] == 0
+    assert all(torch.equal(a, b) for a, b in zip(ref, out))
