@@ -164,3 +164,27 @@ def test_solve_kernel_timing(env):
     assert prof["marginal_cost"][1] == c.iters and prof["marginal_cost"][0] > 0.0
     assert prof["u1"][1] == c.iters + 1 and prof["objective"][1] == c.iters + 1
     assert all(torch.equal(a, b) for a, b in zip(ref, out))
+
+
+@pytest.mark.parametrize("case", ["two-nodes", "lam0-offgrid", "one-level"])
+def test_degenerate(env, case):
+    """Two-node grids; lam = 0 with every encoder value off the y grid
+    (every window empty: u1 = 0 everywhere and B = 0 for all candidates,
+    so the tie rule alone decides); a single level of two candidates."""
+    U, orc, torch = env
+    if case == "two-nodes":
+        p = W.CodingProblem(2.0, [(1.0, 0.0, 1.0)], -1.0, 1.0, 2, -2.0, 2.0, 2)
+        s, u0 = W.Search(-1.0, 1.0, 2, 3), np.array([0.5, -0.5])
+    elif case == "lam0-offgrid":
+        p = W.CodingProblem(0.0, [(1.0, 0.0, 1.0)], -3.0, 3.0, 301, -2.0, 2.0, 101)
+        s, u0 = W.Search(6.0, 9.0, 3, 5), np.full(301, 7.5)
+    else:
+        p = W.coding_problem(513, 257)
+        s, u0 = W.Search(-3.0, 3.0, 1, 2), W.coding_init(p, 4)
+    u0g, u1g, Jg = U.coding_solve(p, s, 2, dev(torch, u0))
+    r0, r1, rJ = orc.coding_solve(p, s, 2, u0)
+    assert np.array_equal(host(u0g), r0)
+    assert np.max(np.abs(host(u1g) - r1)) < 1e-12
+    assert np.max(np.abs(host(Jg) - rJ) / np.maximum(rJ, 1e-300)) < 1e-11
+    if case == "lam0-offgrid":
+        assert np.all(r1 == 0.0) and np.array_equal(r0, u0)  # ties keep the incumbent

@@ -127,3 +127,23 @@ def test_solve_kernel_timing(env):
     U.profile(None)
     assert prof["marginal_cost"][1] == c.iters and prof["u1"][1] == 0
     assert all(torch.equal(a, b) for a, b in zip(ref, out))
+
+
+@pytest.mark.parametrize("case", ["two-nodes", "k0", "one-level"])
+def test_degenerate(env, case):
+    """2 x 2 grids; k = 0; a single level of 2 x 2 candidates."""
+    U, orc, torch = env
+    if case == "two-nodes":
+        p = W.Problem(0.2, [(1.0, 0.0, 5.0)], -5.0, 5.0, 2, -8.0, 8.0, 2)
+        s, u0 = W.Search(-6.0, 6.0, 2, 3), np.array([[1.0, -1.0, 2.0, 0.0], [0.0, 3.0, -2.0, 1.0]])
+    elif case == "k0":
+        p = W.w2_problem(15, 21, k=0.0)
+        s, u0 = W.Search(-30.0, 30.0, 2, 4), W.w2_init(p, 6)
+    else:
+        p = W.w2_problem(17, 19)
+        s, u0 = W.Search(-20.0, 20.0, 1, 2), W.w2_init(p, 7)
+    u0g, u1g, Jg = U.w2_solve(p, s, 2, dev(torch, u0))
+    r0, r1, rJ = orc.w2_solve(p, s, 2, u0)
+    assert np.array_equal(host(u0g), r0)
+    assert np.max(np.abs(host(u1g) - r1)) < 1e-10
+    assert np.max(np.abs(host(Jg) - rJ) / np.maximum(rJ, 1e-300)) < 1e-11
