@@ -36,7 +36,7 @@ constexpr int kCdTile = 256;    // x nodes per extent tile and per LDS stage
 constexpr int kCdSegMax = 128;  // decoder segments (at most; one tile each where possible)
 constexpr size_t kCdPartBytes = size_t(1) << 28;  // bound of the decoder's partial sums
 constexpr int kCdYGrp = 64;     // y nodes per decoder wave
-constexpr int kCdBlk = 256;     // y nodes per block of the local prefix sums
+constexpr int kCdBlk = 64;      // y nodes per block (one wave) of the local prefix sums
 constexpr int kCdScan = 1024;   // threads of the top-level prefix block
 // A tile whose u0 range lies within these distances of a wave's y range is
 // wholly outside (skipped) or wholly inside (its sums added) every window of
@@ -279,15 +279,14 @@ __global__ __launch_bounds__(kCdYGrp) void k_cd_u1_part(CdParams P, const double
   }
 }
 
-// One block per kCdBlk y nodes.  FROM_PARTS: u1_j = (sum of the segment
+// One wave per kCdBlk y nodes.  FROM_PARTS: u1_j = (sum of the segment
 // partials of f x) / (sum of those of f), 0 where nothing reaches y_j, and
-// u1 is written; otherwise u1 is read.  Then the block's inclusive
-// double-double prefix sums of u1 and u1^2 (Hillis-Steele in LDS) go to L
-// and the block totals to tot (four arrays of n_blk).
+// u1 is written; otherwise u1 is read.  Then the wave's inclusive
+// double-double prefix sums of u1 and u1^2 (Hillis-Steele over lane
+// shuffles) go to L and the wave totals to tot (four arrays of n_blk).
 template <bool FROM_PARTS>
 __global__ __launch_bounds__(kCdBlk) void k_cd_fin_scan(CdParams P, const double* __restrict__ part, double* u1,
                                                         double* __restrict__ L, double* __restrict__ tot) {
-  __shared__ double sh[4][kCdBlk];
   const int t = threadIdx.x;
   const int j = blockIdx.x * kCdBlk + t;
   const int n = P.n_y;
@@ -307,28 +306,13 @@ __global__ __launch_bounds__(kCdBlk) void k_cd_fin_scan(CdParams P, const double
     }
   }
   dd a1 = {v, 0.0}, a2 = two_prod(v, v);
-  sh[0][t] = a1.h;
-  sh[1][t] = a1.l;
-  sh[2][t] = a2.h;
-  sh[3][t] = a2.l;
-  __syncthreads();
   for (int o = 1; o < kCdBlk; o <<= 1) {
-    const bool take = t >= o;
-    dd b1 = {0.0, 0.0}, b2 = {0.0, 0.0};
-    if (take) {
-      b1 = {sh[0][t - o], sh[1][t - o]};
-      b2 = {sh[2][t - o], sh[3][t - o]};
-    }
-    __syncthreads();
-    if (take) {
+    const dd b1 = {__shfl_up(a1.h, o), __shfl_up(a1.l, o)};
+    const dd b2 = {__shfl_up(a2.h, o), __shfl_up(a2.l, o)};
+    if (t >= o) {
       a1 = dd_add(b1, a1);
       a2 = dd_add(b2, a2);
-      sh[0][t] = a1.h;
-      sh[1][t] = a1.l;
-      sh[2][t] = a2.h;
-      sh[3][t] = a2.l;
     }
-    __syncthreads();
   }
   if (j < n) {
     L[j] = a1.h;
