@@ -100,3 +100,44 @@ def test_solve_monotone_and_rows(orc):
     full, _ = orc.w2_argmin(c.prob, c.search, u1, u0)
     part, _ = orc.w2_argmin(c.prob, c.search, u1, u0, rows)
     assert np.array_equal(full[:, rows], part)
+
+
+def test_tie_rule_on_mirror_symmetric_minima(orc):
+    # x = (0, 0) with an odd decoder u1 = 5 sign(y) per coordinate on a
+    # symmetric grid: B(u) is even in each coordinate, its four minima
+    # (+-5, +-5) tie and lie at equal distance from the incumbent (0, 0),
+    # whose own cost is far higher.  The rule (nearest, then the smaller
+    # first coordinate, then the smaller second) must pick (-5, -5); a
+    # reversed comparison or swapped coordinates pick another corner.
+    p = W.w2_problem(21, 41)
+    y = W.nodes(p.y_lo, p.y_hi, p.n_y)
+    v = 5.0 * np.sign(y)
+    u1 = np.stack([np.repeat(v, p.n_y), np.tile(v, p.n_y)])
+    i0 = (p.n_x // 2) * p.n_x + p.n_x // 2  # the node x = (0, 0)
+    B = [orc.w2_B(p, u1, (0.0, 0.0), (a, b)) for a in (-5.0, 5.0) for b in (-5.0, 5.0)]
+    assert max(B) - min(B) <= 1e-13 * min(B)
+    for s in (W.Search(-10.0, 10.0, 1, 5), W.Search(-10.0, 10.0, 2, 5)):
+        u, _ = orc.w2_argmin(p, s, u1, np.zeros((2, p.n_x ** 2)), [i0])
+        assert tuple(u[:, 0]) == (-5.0, -5.0)
+    # with the incumbent at a corner, the nearest corner wins instead
+    u0 = np.zeros((2, p.n_x ** 2))
+    u0[:, i0] = (4.0, -4.0)
+    u, _ = orc.w2_argmin(p, W.Search(-10.0, 10.0, 1, 5), u1, u0, [i0])
+    assert tuple(u[:, 0]) == (5.0, -5.0)
+
+
+def test_tie_rule_orders_the_coordinates(orc):
+    # u1(y) = 5 sign(y1 - y2) (1, -1) is odd under y -> -y, so B(u) = B(-u)
+    # at x = (0, 0); its two minima (-5, 5) and (5, -5) tie at equal
+    # distance from the incumbent (0, 0).  The first coordinate decides
+    # first: (-5, 5).  Deciding by the second first would give (5, -5).
+    p = W.w2_problem(21, 41)
+    y = W.nodes(p.y_lo, p.y_hi, p.n_y)
+    s = 5.0 * np.sign(np.repeat(y, p.n_y) - np.tile(y, p.n_y))
+    u1 = np.stack([s, -s])
+    Bm = orc.w2_B(p, u1, (0.0, 0.0), (-5.0, 5.0))
+    assert abs(Bm - orc.w2_B(p, u1, (0.0, 0.0), (5.0, -5.0))) <= 1e-13 * Bm
+    assert orc.w2_B(p, u1, (0.0, 0.0), (5.0, 5.0)) > 2 * Bm
+    i0 = (p.n_x // 2) * p.n_x + p.n_x // 2
+    u, _ = orc.w2_argmin(p, W.Search(-10.0, 10.0, 1, 5), u1, np.zeros((2, p.n_x ** 2)), [i0])
+    assert tuple(u[:, 0]) == (-5.0, 5.0)
