@@ -6,10 +6,10 @@
 //
 //   k_w2_prior    1-D prior f at the x nodes (the 2-D prior is f(x1) f(x2))
 //   k_w2_search   one wave per point: every level of the coarse-to-fine
-//                 search (the wave sums one candidate at a time over the
-//                 window, lanes along its columns; lane q keeps candidate q)
-//                 and the incumbent comparison, the selection rule as a wave
-//                 reduction
+//                 search (the wave sums the K candidates of one grid column
+//                 together over their shared column window, lanes along the
+//                 columns; lane q keeps candidate q) and the incumbent
+//                 comparison, the selection rule as a wave reduction
 //   k_w2_mc       L_0 = f B for explicit candidates, one lane each
 //   k_w2_u1_part  u1 sums for 64 y nodes over one segment of x nodes,
 //                 max-shifted within the segment
@@ -135,54 +135,77 @@ __device__ __forceinline__ bool later_wins(double ds, double sa, double sb, doub
   return ds < dw || (ds == dw && (sa < wa || (sa == wa && sb < wb)));
 }
 
-// B of one candidate, summed by a whole wave: the window's columns go in
-// chunks of 64, lane t on column chunk + t (coalesced row segments of u1);
-// the row factors phi(y_j1 - z1) are computed one per lane and broadcast;
-// the lanes' partial sums are added in a fixed tree.  Every lane returns B.
-__device__ double w2_B_wave(const W2Params& P, const double* __restrict__ u1a, const double* __restrict__ u1b,
-                            double x1, double x2, double ua, double ub) {
+// B of the nc <= 8 candidates (x1 + c1[q1], x2 + c2) that share their
+// second coordinate, summed together by a whole wave: they share the
+// column window and its factors phi(y_c - z2), so each row segment of u1
+// is loaded once for all of them.  Lane t takes columns chunk + t; the rows
+// run over the union of the candidates' row windows, a row outside a
+// candidate's window weighing zero for it; the row factors of a chunk of
+// 64 rows sit in LDS (tab, 8 x 64).  Every lane returns the nc values in Bq.
+__device__ void w2_B_column(const W2Params& P, const double* __restrict__ u1a, const double* __restrict__ u1b,
+                            double x1, double x2, const double (&c1)[8], double c2, int nc, double (&Bq)[8],
+                            double* tab) {
   const int t = threadIdx.x & 63;
-  const double z1 = x1 + ua, z2 = x2 + ub;
-  int a1, b1, a2, b2;
-  w2_window(P, z1, a1, b1);
+  double z1[8];
+  int ra[8], rb[8];
+  int ua = P.ny, ub = -1;
+#pragma unroll
+  for (int q = 0; q < 8; ++q) {
+    z1[q] = x1 + c1[q];
+    ra[q] = 1;
+    rb[q] = 0;
+    if (q < nc) {
+      w2_window(P, z1[q], ra[q], rb[q]);
+      ua = min(ua, ra[q]);
+      ub = max(ub, rb[q]);
+    }
+  }
+  const double z2 = x2 + c2;
+  int a2, b2;
   w2_window(P, z2, a2, b2);
-  double part = 0.0;
+  double acc[8];
+#pragma unroll
+  for (int q = 0; q < 8; ++q) acc[q] = 0.0;
   for (int cc = a2; cc <= b2; cc += 64) {
     const int c = cc + t;
     const bool have = c <= b2;
     const double g2 = have ? phi(ynode(P, c) - z2) : 0.0;
-    for (int r0 = a1; r0 <= b1; r0 += 64) {
-      const int nr = min(64, b1 - r0 + 1);
-      const double g1v = t < nr ? phi(ynode(P, r0 + t) - z1) : 0.0;
-      // rows in batches of 8, every load of a batch issued before its use
-      // (addresses clamped into the window; the clamped terms are skipped)
-      const int cl = have ? c : a2;
-      for (int k0 = 0; k0 < nr; k0 += 8) {
-        double va[8], vb[8];
+    const int cl = have ? c : a2;
+    for (int r0 = ua; r0 <= ub; r0 += 64) {
+      const int nr = min(64, ub - r0 + 1);
+      const int row = r0 + t;
 #pragma unroll
-        for (int u = 0; u < 8; ++u) {
-          const long o = (long)(r0 + min(k0 + u, nr - 1)) * P.ny + cl;
-          va[u] = u1a[o];
-          vb[u] = u1b[o];
-        }
+      for (int q = 0; q < 8; ++q)
+        tab[q * 64 + t] = (t < nr && row >= ra[q] && row <= rb[q]) ? phi(ynode(P, row) - z1[q]) : 0.0;
+      __syncthreads();
+      for (int k = 0; k < nr; ++k) {
+        const long o = (long)(r0 + k) * P.ny + cl;
+        const double a = u1a[o];
+        const double e2 = z2 - u1b[o];
+        const double e22 = e2 * e2;
 #pragma unroll
-        for (int u = 0; u < 8; ++u) {
-          const double g1 = __shfl(g1v, min(k0 + u, 63));
-          if (have && k0 + u < nr) {
-            const double e1 = z1 - va[u], e2 = z2 - vb[u];
-            part = fma(g1 * g2, e1 * e1 + e2 * e2, part);
+        for (int q = 0; q < 8; ++q) {
+          if (q < nc) {
+            const double e1 = z1[q] - a;
+            acc[q] = fma(tab[q * 64 + k] * g2, fma(e1, e1, e22), acc[q]);
           }
         }
       }
+      __syncthreads();
     }
   }
-  for (int o = 32; o > 0; o >>= 1) part += __shfl_xor(part, o);
-  return 0.5 * (P.k * P.k * (ua * ua + ub * ub) + P.dy * P.dy * part);
+#pragma unroll
+  for (int q = 0; q < 8; ++q) {
+    double v = acc[q];
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    Bq[q] = 0.5 * (P.k * P.k * (c1[q] * c1[q] + c2 * c2) + P.dy * P.dy * v);
+  }
 }
 
 // One wave per point.  u0_in and u0_out (two planes each) may alias: the
-// wave reads its point before lane 0 writes it.  The wave sums each
-// candidate in turn (w2_B_wave), and lane q keeps candidate q's B.
+// wave reads its point before lane 0 writes it.  The wave sums the
+// candidates column by column of the K x K grid (w2_B_column), and lane q
+// keeps candidate q's B.
 __global__ __launch_bounds__(64) void k_w2_search(W2Params P, const double* __restrict__ f,
                                                   const double* __restrict__ u1, const double* u0_in,
                                                   double* u0_out, double* L0_out) {
@@ -193,15 +216,21 @@ __global__ __launch_bounds__(64) void k_w2_search(W2Params P, const double* __re
   const double ia = u0_in[i], ib = u0_in[nn + i];
   const double* u1a = u1;
   const double* u1b = u1 + (long)P.ny * P.ny;
+  __shared__ double tab[8 * 64];
   double sa = 0.0, sb = 0.0, sB = 0.0;
   for (int l = 0; l < P.levels; ++l) {
     const bool live = q < KK;
     const double ca = live ? cand(P, l, q / K, sa) : 0.0;
     const double cb = live ? cand(P, l, q % K, sb) : 0.0;
+    double c1[8], Bq[8];
+#pragma unroll
+    for (int r = 0; r < 8; ++r) c1[r] = r < K ? cand(P, l, r, sa) : 0.0;
     double B = INFINITY;
-    for (int c = 0; c < KK; ++c) {
-      const double Bc = w2_B_wave(P, u1a, u1b, x1, x2, cand(P, l, c / K, sa), cand(P, l, c % K, sb));
-      if (c == q) B = Bc;
+    for (int q2 = 0; q2 < K; ++q2) {
+      w2_B_column(P, u1a, u1b, x1, x2, c1, cand(P, l, q2, sb), K, Bq, tab);
+#pragma unroll
+      for (int r = 0; r < 8; ++r)
+        if (r < K && q == r * K + q2) B = Bq[r];
     }
     double m = B;
     for (int o = 32; o > 0; o >>= 1) m = fmin(m, __shfl_xor(m, o));
@@ -231,7 +260,9 @@ __global__ __launch_bounds__(64) void k_w2_search(W2Params P, const double* __re
     sB = kB;
   }
   // acceptance against the incumbent (index 1, after the search's winner)
-  const double Bi = w2_B_wave(P, u1a, u1b, x1, x2, ia, ib);
+  double ci[8] = {ia, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0}, Bi8[8];
+  w2_B_column(P, u1a, u1b, x1, x2, ci, ib, 1, Bi8, tab);
+  const double Bi = Bi8[0];
   double m = sB;
   if (Bi < m) m = Bi;
   const double thr = m * (1.0 + 1e-12);
