@@ -30,6 +30,7 @@ namespace {
 constexpr double kW2Win = 10.0;  // noise sds (window half-width floor(kW2Win / dy) nodes)
 constexpr int kW2Seg = 16;       // x segments of the u1 sums (at most)
 constexpr int kW2Tile = 256;     // x nodes staged in LDS per step of the u1 sums
+constexpr int kW2Grp = 4;        // candidates of a grid column summed together by the search
 
 struct W2Params {
   double k;
@@ -142,15 +143,16 @@ __device__ __forceinline__ bool later_wins(double ds, double sa, double sb, doub
 // run over the union of the candidates' row windows, a row outside a
 // candidate's window weighing zero for it; the row factors of a chunk of
 // 64 rows sit in LDS (tab, 8 x 64).  Every lane returns the nc values in Bq.
+template <int NC>
 __device__ void w2_B_column(const W2Params& P, const double* __restrict__ u1a, const double* __restrict__ u1b,
-                            double x1, double x2, const double (&c1)[8], double c2, int nc, double (&Bq)[8],
+                            double x1, double x2, const double* c1, double c2, int nc, double* Bq,
                             double* tab) {
   const int t = threadIdx.x & 63;
-  double z1[8];
-  int ra[8], rb[8];
+  double z1[NC];
+  int ra[NC], rb[NC];
   int ua = P.ny, ub = -1;
 #pragma unroll
-  for (int q = 0; q < 8; ++q) {
+  for (int q = 0; q < NC; ++q) {
     z1[q] = x1 + c1[q];
     ra[q] = 1;
     rb[q] = 0;
@@ -163,9 +165,9 @@ __device__ void w2_B_column(const W2Params& P, const double* __restrict__ u1a, c
   const double z2 = x2 + c2;
   int a2, b2;
   w2_window(P, z2, a2, b2);
-  double acc[8];
+  double acc[NC];
 #pragma unroll
-  for (int q = 0; q < 8; ++q) acc[q] = 0.0;
+  for (int q = 0; q < NC; ++q) acc[q] = 0.0;
   for (int cc = a2; cc <= b2; cc += 64) {
     const int c = cc + t;
     const bool have = c <= b2;
@@ -175,7 +177,7 @@ __device__ void w2_B_column(const W2Params& P, const double* __restrict__ u1a, c
       const int nr = min(64, ub - r0 + 1);
       const int row = r0 + t;
 #pragma unroll
-      for (int q = 0; q < 8; ++q)
+      for (int q = 0; q < NC; ++q)
         tab[q * 64 + t] = (t < nr && row >= ra[q] && row <= rb[q]) ? phi(ynode(P, row) - z1[q]) : 0.0;
       __syncthreads();
       for (int k = 0; k < nr; ++k) {
@@ -184,7 +186,7 @@ __device__ void w2_B_column(const W2Params& P, const double* __restrict__ u1a, c
         const double e2 = z2 - u1b[o];
         const double e22 = e2 * e2;
 #pragma unroll
-        for (int q = 0; q < 8; ++q) {
+        for (int q = 0; q < NC; ++q) {
           if (q < nc) {
             const double e1 = z1[q] - a;
             acc[q] = fma(tab[q * 64 + k] * g2, fma(e1, e1, e22), acc[q]);
@@ -195,7 +197,7 @@ __device__ void w2_B_column(const W2Params& P, const double* __restrict__ u1a, c
     }
   }
 #pragma unroll
-  for (int q = 0; q < 8; ++q) {
+  for (int q = 0; q < NC; ++q) {
     double v = acc[q];
     for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
     Bq[q] = 0.5 * (P.k * P.k * (c1[q] * c1[q] + c2 * c2) + P.dy * P.dy * v);
@@ -222,15 +224,18 @@ __global__ __launch_bounds__(64) void k_w2_search(W2Params P, const double* __re
     const bool live = q < KK;
     const double ca = live ? cand(P, l, q / K, sa) : 0.0;
     const double cb = live ? cand(P, l, q % K, sb) : 0.0;
-    double c1[8], Bq[8];
+    double c1[8], Bq[kW2Grp];
 #pragma unroll
     for (int r = 0; r < 8; ++r) c1[r] = r < K ? cand(P, l, r, sa) : 0.0;
     double B = INFINITY;
     for (int q2 = 0; q2 < K; ++q2) {
-      w2_B_column(P, u1a, u1b, x1, x2, c1, cand(P, l, q2, sb), K, Bq, tab);
+      const double c2 = cand(P, l, q2, sb);
+      for (int h = 0; h < K; h += kW2Grp) {  // the column's candidates kW2Grp at a time
+        w2_B_column<kW2Grp>(P, u1a, u1b, x1, x2, c1 + h, c2, min(kW2Grp, K - h), Bq, tab);
 #pragma unroll
-      for (int r = 0; r < 8; ++r)
-        if (r < K && q == r * K + q2) B = Bq[r];
+        for (int r = 0; r < kW2Grp; ++r)
+          if (h + r < K && q == (h + r) * K + q2) B = Bq[r];
+      }
     }
     double m = B;
     for (int o = 32; o > 0; o >>= 1) m = fmin(m, __shfl_xor(m, o));
@@ -260,8 +265,8 @@ __global__ __launch_bounds__(64) void k_w2_search(W2Params P, const double* __re
     sB = kB;
   }
   // acceptance against the incumbent (index 1, after the search's winner)
-  double ci[8] = {ia, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0}, Bi8[8];
-  w2_B_column(P, u1a, u1b, x1, x2, ci, ib, 1, Bi8, tab);
+  double ci[kW2Grp] = {ia}, Bi8[kW2Grp];
+  w2_B_column<kW2Grp>(P, u1a, u1b, x1, x2, ci, ib, 1, Bi8, tab);
   const double Bi = Bi8[0];
   double m = sB;
   if (Bi < m) m = Bi;
