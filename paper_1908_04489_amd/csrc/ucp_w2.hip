@@ -6,10 +6,11 @@
 //
 //   k_w2_prior    1-D prior f at the x nodes (the 2-D prior is f(x1) f(x2))
 //   k_w2_search   one wave per point: every level of the coarse-to-fine
-//                 search (the wave sums the K candidates of one grid column
-//                 together over their shared column window, lanes along the
-//                 columns; lane q keeps candidate q) and the incumbent
-//                 comparison, the selection rule as a wave reduction
+//                 search (the wave sums the candidates of one grid column
+//                 kW2Grp at a time over their shared column window, lanes
+//                 along the columns; lane q keeps candidate q) and the
+//                 incumbent comparison, the selection rule as a wave
+//                 reduction
 //   k_w2_mc       L_0 = f B for explicit candidates, one lane each
 //   k_w2_u1_part  u1 sums for 64 y nodes over one segment of x nodes,
 //                 max-shifted within the segment
@@ -136,13 +137,13 @@ __device__ __forceinline__ bool later_wins(double ds, double sa, double sb, doub
   return ds < dw || (ds == dw && (sa < wa || (sa == wa && sb < wb)));
 }
 
-// B of the nc <= 8 candidates (x1 + c1[q1], x2 + c2) that share their
+// B of the nc <= NC candidates (x1 + c1[q], x2 + c2) that share their
 // second coordinate, summed together by a whole wave: they share the
 // column window and its factors phi(y_c - z2), so each row segment of u1
 // is loaded once for all of them.  Lane t takes columns chunk + t; the rows
 // run over the union of the candidates' row windows, a row outside a
 // candidate's window weighing zero for it; the row factors of a chunk of
-// 64 rows sit in LDS (tab, 8 x 64).  Every lane returns the nc values in Bq.
+// 64 rows sit in LDS (tab, NC x 64).  Every lane returns the nc values in Bq.
 template <int NC>
 __device__ void w2_B_column(const W2Params& P, const double* __restrict__ u1a, const double* __restrict__ u1b,
                             double x1, double x2, const double* c1, double c2, int nc, double* Bq,
@@ -206,8 +207,9 @@ __device__ void w2_B_column(const W2Params& P, const double* __restrict__ u1a, c
 
 // One wave per point.  u0_in and u0_out (two planes each) may alias: the
 // wave reads its point before lane 0 writes it.  The wave sums the
-// candidates column by column of the K x K grid (w2_B_column), and lane q
-// keeps candidate q's B.
+// candidates column by column of the K x K grid, kW2Grp at a time
+// (w2_B_column: fewer at once keeps the registers at three waves per SIMD),
+// and lane q keeps candidate q's B.
 __global__ __launch_bounds__(64) void k_w2_search(W2Params P, const double* __restrict__ f,
                                                   const double* __restrict__ u1, const double* u0_in,
                                                   double* u0_out, double* L0_out) {
