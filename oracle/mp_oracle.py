@@ -51,6 +51,10 @@ def _select(cands, vals, inc):
     return best[1], best[2]
 
 
+def _mpv(v):
+    return v if isinstance(v, mp.mpf) else mp.mpf(float(v))
+
+
 def u1_update(p, u0):
     with mp.workdps(DPS):
         xs = _nodes(p.x_lo, p.x_hi, p.n_x)
@@ -77,7 +81,7 @@ def objective(p, u0, u1):
         for x, fi, u in zip(xs, f, u0):
             u = mp.mpf(float(u))
             a = x + u
-            inner = mp.fsum(mp.npdf(y - a) * (a - mp.mpf(float(v))) ** 2 for y, v in zip(ys, u1))
+            inner = mp.fsum(mp.npdf(y - a) * (a - _mpv(v)) ** 2 for y, v in zip(ys, u1))
             tot += fi * (k2 * u ** 2 + dy * inner)
         return dx * tot
 
@@ -91,7 +95,7 @@ def argmin(p, s, u1, u0_in):
     with mp.workdps(DPS):
         xs = _nodes(p.x_lo, p.x_hi, p.n_x)
         ys = _nodes(p.y_lo, p.y_hi, p.n_y)
-        u1m = [mp.mpf(float(v)) for v in u1]
+        u1m = [v if isinstance(v, mp.mpf) else mp.mpf(float(v)) for v in u1]
         K, L = int(s.cands), int(s.levels)
         h = [(float(s.u_hi) - float(s.u_lo)) / float(K - 1)]
         for _ in range(1, L):
@@ -120,3 +124,21 @@ def argmin(p, s, u1, u0_in):
             cb, _ = _select([mp.mpf(c_best), mp.mpf(inc)], [v_best, v_inc], mp.mpf(inc))
             out.append(float(cb))
         return out
+
+
+def solve(p, s, iters, u0_init):
+    """The solve loop written out from its definition: u1 is the closed-form
+    second controller of the initial u0, J_0 = J(u0, u1); then each round
+    updates u0 point by point with u1 held fixed, replaces u1 by the closed
+    form of the new u0, and records J of the pair.  u1 stays at 40 digits
+    between the steps; u0 is a set of binary64 candidate positions.
+    Returns (u0 as floats, u1 as mpf, J_hist as mpf)."""
+    with mp.workdps(DPS):
+        u0 = [float(v) for v in u0_init]
+        u1 = u1_update(p, u0)
+        J = [objective(p, u0, u1)]
+        for _ in range(int(iters)):
+            u0 = argmin(p, s, u1, u0)
+            u1 = u1_update(p, u0)
+            J.append(objective(p, u0, u1))
+        return u0, u1, J

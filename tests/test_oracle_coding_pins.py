@@ -138,3 +138,19 @@ def test_rows_and_solve_monotone(orc):
     assert np.array_equal(full[rows], part)
     ufull = orc.coding_update_u1(c.prob, u0)
     assert np.array_equal(ufull[[1, 600, 1200]], orc.coding_update_u1(c.prob, u0, [1, 600, 1200]))
+
+
+def test_solve_round_order(orc):
+    """u0 searched with the previous round's decoder, then the decoder of the
+    new u0, and J_t on that pair (J before the decoder update is larger)."""
+    c = W.coding_small_case()
+    p, s = c.prob, c.search
+    u0_prev, u1_prev = c.u0_init, orc.coding_update_u1(p, c.u0_init)
+    for t in (1, 2):
+        u0, u1, J = orc.coding_solve(p, s, t, c.u0_init)
+        step, _ = orc.coding_argmin(p, s, u1_prev, u0_prev)
+        assert np.array_equal(u0, step)
+        assert np.array_equal(u1, orc.coding_update_u1(p, u0))
+        assert J[t] == orc.coding_objective(p, u0, u1)
+        assert J[t] < orc.coding_objective(p, u0, u1_prev) * (1 - 1e-9)
+        u0_prev, u1_prev = u0, u1

@@ -339,3 +339,43 @@ def test_against_mpmath_tiny(orc):
     a, _ = orc.argmin(p, s, u1, u0)
     am = mp_oracle.argmin(p, s, u1, u0)
     assert np.array_equal(a, np.array(am))
+
+
+# ------------------------------------------ order within a round (Q7 reading)
+
+def test_solve_round_order(orc):
+    """Each round updates u0 with the u1 of the previous round, then replaces
+    u1 by the closed form of the new u0, and J_t is taken on that pair.
+    Catches J taken before the u1 update (J(u0_t, u1_{t-1}) is strictly
+    larger: the update is the exact minimiser over u1) and a round that
+    updates u1 before searching u0."""
+    c = W.small_case()
+    p, s = c.prob, c.search
+    u0_prev, u1_prev = c.u0_init, orc.update_u1(p, c.u0_init)
+    for t in (1, 2, 3):
+        u0, u1, J = orc.solve(p, s, t, c.u0_init)
+        step, _ = orc.argmin(p, s, u1_prev, u0_prev)
+        assert np.array_equal(u0, step)
+        assert np.array_equal(u1, orc.update_u1(p, u0))
+        assert J[t] == orc.objective(p, u0, u1)
+        before = orc.objective(p, u0, u1_prev)
+        assert J[t] < before * (1 - 1e-9), (t, J[t], before)
+        u0_prev, u1_prev = u0, u1
+
+
+def test_against_mpmath_two_round_solve(orc):
+    """Two whole rounds of the oracle's solve loop against the same loop run
+    at 40 digits from the definitions (P9): J_hist to 1e-13, u0 equal."""
+    from oracle import mp_oracle
+
+    p = W.Problem(k=0.2, comps=[(0.6, -3.0, 2.0), (0.4, 4.0, 3.0)], x_lo=-12, x_hi=12, n_x=25,
+                  y_lo=-15, y_hi=15, n_y=31)
+    s = W.Search(-8.0, 8.0, 3, 7)
+    u0i = W.init_random_steps(p, 4.0, 5)
+    u0, u1, J = orc.solve(p, s, 2, u0i)
+    m0, m1, Jm = mp_oracle.solve(p, s, 2, u0i)
+    assert np.array_equal(u0, np.array(m0))
+    assert max(abs(float(a) - b) for a, b in zip(m1, u1)) < 1e-13
+    for a, b in zip(Jm, J):
+        assert abs(float(a) - b) <= 1e-13 * b
+    assert float(Jm[2]) < float(Jm[0])

@@ -141,3 +141,19 @@ def test_tie_rule_orders_the_coordinates(orc):
     i0 = (p.n_x // 2) * p.n_x + p.n_x // 2
     u, _ = orc.w2_argmin(p, W.Search(-10.0, 10.0, 1, 5), u1, np.zeros((2, p.n_x ** 2)), [i0])
     assert tuple(u[:, 0]) == (-5.0, 5.0)
+
+
+def test_solve_round_order(orc):
+    """u0 searched with the previous round's u1, then u1 of the new u0, and
+    J_t on that pair (J before the u1 update is larger)."""
+    c = W.w2_small_case()
+    p, s = c.prob, c.search
+    u0_prev, u1_prev = c.u0_init, orc.w2_update_u1(p, c.u0_init)
+    for t in (1, 2):
+        u0, u1, J = orc.w2_solve(p, s, t, c.u0_init)
+        step, _ = orc.w2_argmin(p, s, u1_prev, u0_prev)
+        assert np.array_equal(u0, step)
+        assert np.array_equal(u1, orc.w2_update_u1(p, u0))
+        assert J[t] == orc.w2_objective(p, u0, u1)
+        assert J[t] < orc.w2_objective(p, u0, u1_prev) * (1 - 1e-9)
+        u0_prev, u1_prev = u0, u1
