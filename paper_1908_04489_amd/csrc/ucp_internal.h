@@ -47,9 +47,14 @@ constexpr double kTau32Plain = 5e-6;
 constexpr double kKappa32 = 6e-7;
 constexpr double kTau64 = 1e-12;// FP64 tie band (relative)
 constexpr double kWin32 = 9.0;  // window half-width, noise sds (FP32 terms)
-// FP64 window half-width, noise sds: the dropped tail sums to below 1e-16
-// of B (B >= the unit noise variance, and the tail is ~2 phi(9) (9 + v^2/9))
-constexpr double kWin64 = 9.0;
+// FP64 window half-width, noise sds.  B has no useful lower bound (a point
+// whose x0 + u lands on a flat step of u1 has B far below the noise
+// variance), so the width is set by the dropped tail against B itself: the
+// tail is at most 2 phi(11)/11 max(z - u1)^2 = 3.9e-28 max(z - u1)^2, below
+// 1e-16 of B wherever B >= 4e-12 max(z - u1)^2; on solver states of the
+// sigma = 10 sign controller (B down to 2e-6) it is 6e-21 of B, where 9
+// sds left 3.5e-12.
+constexpr double kWin64 = 11.0;
 // Device counters (spread over slots on separate cache lines): algorithmic
 // marginal-cost terms and FP64 tie re-evaluations.
 constexpr int kCountSlots = 32, kCountStride = 16, kCountTerms = 0, kCountEvalTerms = 4, kCountEvals = 8;
@@ -75,6 +80,8 @@ struct Inst {
   int32_t levels, cands;
   double u_lo, u_hi;
   double h[kMaxLevels];      // candidate spacing per level
+  double tau64;              // relative FP64 tie band of the selection rule
+  double tau32;              // relative part of the FP32 pre-selection band (holds tau64)
   // geometry
   int32_t nw32, nw64;        // window half-widths in y nodes
   int32_t segs;              // marginal-cost units (partial sums) per (tile, candidate)
