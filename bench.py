@@ -1,19 +1,24 @@
 """Benchmark of the MI355X marginal-cost solver.
 
-One step = one whole solve of the workload on one GPU: the prior, the
+Default (``--workload headline``): the largest single-GPU workload, 64
+instances of 65536-node grids on [-40, 40] with seeded 3-component mixture
+priors, k = 0.2, unit Gaussian noise, a 4 levels x 32 candidates search on
+[-30, 30], u0 = 0, 3 rounds, FP32 terms with compensated sums, all in shared
+launches.  One step is one batched solve of every instance: the prior, the
 closed-form u1 of the initial controller, then every round of (the
 coarse-to-fine u0 update over all levels - the marginal-cost sums, the
 per-point selection with FP64 tie re-evaluation and the comparison with the
 incumbent - the u0 advance, the u1 update and the FP64 objective), inputs
-resident in HBM before the timed region.
-
-Default workload: Witsenhausen k=0.2, sigma=5, x0 and y grids of 20001
-nodes on [-25, 25], search 5 levels x 16 candidates on [-30, 30], init
-u0 = sigma sign(x) - x, 30 rounds, FP32 terms with compensated sums.
+resident in HBM before the timed region.  The same line carries the
+serving leg (continuous batching on the 4096-request Poisson trace at 0.8
+and 0.5 of saturation, against one solve at a time run live on the same
+arrivals), the roofline of the marginal-cost kernel from HIP events around
+its launches, and the FP64 oracle's rate on the host (all threads and one).
 
 The metric counts algorithmic marginal-cost terms: (point, candidate,
 y node) triples with |y - x - u| <= 9 noise sds, counted on the device.
-Prints one JSON line.
+Prints one JSON line.  ``--workload paper`` times one 20001-node solve
+(5 x 16, 30 rounds); the other workloads print lines of their own.
 """
 from __future__ import annotations
 
@@ -102,50 +107,96 @@ def workload(name):
     raise SystemExit(f"unknown workload {name}")
 
 
-def cpu_baseline(case, budget_s=12.0):
-    """The FP64 oracle, as it stands, on a bounded sample of the same
-    workload: one u0 update (every level and the incumbent) on evenly spaced
-    rows, given the oracle's own u1 of the initial controller."""
+def host_info():
+    """CPU model and the logical CPUs this process may use."""
+    model = "unknown"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except AttributeError:
+        usable = os.cpu_count()
+    return {"cpu_model": model, "nproc": usable, "cpu_count": os.cpu_count()}
+
+
+def alg_terms(p, rows, visits):
+    """Algorithmic terms of the positions an update evaluated: for each
+    (row i, position c), the y nodes within 9 noise sds of x_i + c, counted
+    with the device counter's rule."""
+    import numpy as np
+
+    dx = (p.x_hi - p.x_lo) / (p.n_x - 1)
+    dy = (p.y_hi - p.y_lo) / (p.n_y - 1)
+    z = (p.x_lo + rows.astype(np.float64) * dx)[:, None] + visits
+    lo = np.maximum(np.ceil((z - 9.0 - p.y_lo) * (1.0 / dy)), 0.0)
+    hi = np.minimum(np.floor((z + 9.0 - p.y_lo) * (1.0 / dy)), p.n_y - 1.0)
+    return float(np.sum(np.maximum(hi - lo + 1.0, 0.0)))
+
+
+def cpu_baseline(cases, budget_s=10.0, one_core_s=6.0, seed=0):
+    """The FP64 oracle, as it stands, on a bounded sample of the workload:
+    one u0 update (every level and the incumbent) of randomly drawn rows of
+    each listed instance, given the oracle's own u1 of the instance's
+    initial controller, first on all the host's threads, then on one.  The
+    work is counted from the positions the oracle evaluated, with the
+    device counter's rule (nodes within 9 noise sds)."""
     import numpy as np
 
     import oracle
 
-    p, s = case.prob, case.search
-    u1 = oracle.update_u1(p, case.u0_init)
-    x = oracle.grid(p.x_lo, p.x_hi, p.n_x)
-    # probe, then size the sample to the budget
-    rows = np.linspace(0, p.n_x - 1, 64).astype(np.int64)
+    rng = np.random.default_rng(seed)
+    u1s = [oracle.update_u1(c.prob, c.u0_init) for c in cases]  # set-up, untimed
+    c0 = cases[0]
+    probe = np.sort(rng.choice(c0.prob.n_x, 32, replace=False))
     t0 = time.perf_counter()
-    oracle.argmin(p, s, u1, case.u0_init, rows=rows)
-    dt = time.perf_counter() - t0
-    n = int(min(p.n_x, max(64, 64 * budget_s / max(dt, 1e-6))))
-    rows = np.linspace(0, p.n_x - 1, n).astype(np.int64)
-    t0 = time.perf_counter()
-    u0o, _ = oracle.argmin(p, s, u1, case.u0_init, rows=rows)
-    dt = time.perf_counter() - t0
-    # algorithmic terms of those rows: same count as the GPU (nodes within 9
-    # of x + u) over the candidates the oracle visited - level 0 is the fixed
-    # grid, later levels sit near the optimum; counted with the level-0 grid
-    # and the final choice as a bound of the right size
-    dy = (p.y_hi - p.y_lo) / (p.n_y - 1)
-    h = oracle.spacings(s)
-    cands = []
-    for r, i in enumerate(rows):
-        c0 = s.u_lo + np.arange(s.cands) * h[0]
-        cl = np.concatenate([c0, np.full(s.cands * (s.levels - 1) + 1, u0o[r])])
-        cands.append(x[i] + cl)
-    z = np.concatenate(cands)
-    lo = np.maximum(np.ceil((z - 9 - p.y_lo) / dy), 0)
-    hi = np.minimum(np.floor((z + 9 - p.y_lo) / dy), p.n_y - 1)
-    alg = float(np.sum(np.maximum(hi - lo + 1, 0)))
-    dense = float(len(z)) * p.n_y
-    return {"value": alg / dt, "unit": "terms/s", "cores": oracle.num_threads(), "kind": "oracle",
-            "sample": f"one u0 update of {n} of {p.n_x} rows (all {s.levels}x{s.cands} levels + incumbent), "
-                      f"{dt:.1f} s wall; dense FP64 evaluation {dense / dt:.3e} terms/s"}
+    oracle.argmin_visits(c0.prob, c0.search, u1s[0], c0.u0_init, probe)
+    per_row = (time.perf_counter() - t0) / len(probe)
+    n = int(max(32, min(c0.prob.n_x, budget_s / len(cases) / max(per_row, 1e-9))))
+    alg = dense = dt = 0.0
+    for c, u1 in zip(cases, u1s):
+        p, s = c.prob, c.search
+        rows = np.sort(rng.choice(p.n_x, min(n, p.n_x), replace=False))
+        t0 = time.perf_counter()
+        _, vis = oracle.argmin_visits(p, s, u1, c.u0_init, rows)
+        dt += time.perf_counter() - t0
+        alg += alg_terms(p, rows, vis)
+        dense += float(vis.size) * p.n_y
+    threads = oracle.num_threads()
+    # one core: fewer rows of the first instance
+    n1 = int(max(8, min(c0.prob.n_x, one_core_s / max(per_row * threads, 1e-9))))
+    rows1 = np.sort(rng.choice(c0.prob.n_x, n1, replace=False))
+    oracle.set_threads(1)
+    try:
+        t0 = time.perf_counter()
+        _, vis1 = oracle.argmin_visits(c0.prob, c0.search, u1s[0], c0.u0_init, rows1)
+        dt1 = time.perf_counter() - t0
+    finally:
+        oracle.set_threads(0)
+    alg1 = alg_terms(c0.prob, rows1, vis1)
+    out = {"value": alg / dt, "unit": "terms/s", "cores": threads, "kind": "oracle",
+           "sample": f"one u0 update of {n} random rows in each of {len(cases)} instance(s) "
+                     f"({cases[0].search.levels}x{cases[0].search.cands} levels + incumbent, "
+                     f"{vis.shape[1]} positions per row), {dt:.1f} s wall on {threads} threads; "
+                     f"dense FP64 evaluation {dense / dt:.3e} terms/s",
+           "one_core": {"value": alg1 / dt1, "unit": "terms/s", "cores": 1,
+                        "sample": f"{n1} rows of {cases[0].name}, {dt1:.1f} s"}}
+    out.update(host_info())
+    return out
 
 
-def bench_batch(a):
-    """64 instances of the 65536-node mixture family in shared launches."""
+METRIC = "marginal-cost quadrature terms/s; served solves/s + p50/p99 at cost err\u22641e-6"
+
+
+def batch_leg(a):
+    """The 64-instance batch of 65536-node mixture-prior problems (4 x 32
+    search, 3 rounds, u0 = 0) in shared launches: one step is one batched
+    solve of every instance.  Returns the fields of the bench line."""
+    import numpy as np
     import torch
 
     import paper_1908_04489_amd as U
@@ -155,7 +206,8 @@ def bench_batch(a):
     probs, srch = [c.prob for c in cases], [c.search for c in cases]
     iters = [c.iters for c in cases]
     u0s = [torch.as_tensor(c.u0_init).cuda() for c in cases]
-    print(f"# batch: {len(cases)} x 65536 nodes, 4x32, {iters[0]} rounds", file=sys.stderr, flush=True)
+    name = f"mixture-batch-{len(cases)}x65536-4x32"
+    print(f"# {name}: {iters[0]} rounds, {a.prec}", file=sys.stderr, flush=True)
     for w in range(a.warmup):
         U.solve_batch(probs, srch, iters, u0s, a.prec)
         print(f"# warmup {w} done", file=sys.stderr, flush=True)
@@ -166,7 +218,7 @@ def bench_batch(a):
     ev0.record(st)
     terms = evaluated = evals = 0
     for k in range(a.steps):
-        U.solve_batch(probs, srch, iters, u0s, a.prec)
+        out = U.solve_batch(probs, srch, iters, u0s, a.prec)
         t_, v_, e_ = U.last_counts()
         terms, evaluated, evals = terms + t_, evaluated + v_, evals + e_
         print(f"# step {k} done", file=sys.stderr, flush=True)
@@ -177,22 +229,41 @@ def bench_batch(a):
     breakdown = kernel_breakdown(U, lambda: U.solve_batch(probs, srch, iters, u0s, a.prec))
     mc_avg_s = mc_ms / 1e3 / max(mc_n, 1)
     achieved = terms / max(mc_n, 1) * SLOTS_PER_TERM / mc_avg_s
-    res = {"metric": "marginal-cost quadrature terms/s", "value": terms / (ms / 1e3), "unit": "terms/s",
-           "n_gpus": 1, "steps": a.steps, "warmup": a.warmup, "ms_per_step": ms / a.steps,
-           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
-           "config": {"workload": f"mixture-batch-{len(cases)}x65536-4x32", "instances": len(cases),
-                      "n_x": 65536, "levels": 4, "cands": 32, "rounds": iters[0], "prec": a.prec},
+    C = cases[0].search.levels * cases[0].search.cands + 1
+    dense = float(len(cases)) * 65536.0 * C * 65536.0 * iters[0] * a.steps
+    res = {"value": terms / (ms / 1e3), "unit": "terms/s", "ms_per_step": ms / a.steps,
+           "config": {"workload": name, "instances": len(cases), "n_x": 65536, "n_y": 65536, "grid": [-40.0, 40.0],
+                      "prior": "3-component Gaussian mixture per instance (seeded)", "k": 0.2, "levels": 4,
+                      "cands": 32, "rounds": iters[0], "init": "u0 = 0", "prec": a.prec},
            "alg_terms_per_step": terms / a.steps, "evaluated_terms_per_step": evaluated / a.steps,
-           "fp64_tie_evals_per_step": evals / a.steps,
+           "fp64_tie_evals_per_step": evals / a.steps, "dense_equiv_terms_per_s": dense / (ms / 1e3),
+           "solves_per_s": len(cases) * a.steps / (ms / 1e3),
            "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_SLOTS / 1e12, "unit": "Tslot/s",
-                        "frac": achieved / PEAK_SLOTS, "traffic": None, "kernel_avg_us": mc_avg_s * 1e6,
-                        "kernel_launches": mc_n},
+                        "frac": achieved / PEAK_SLOTS, "traffic": measured_traffic(name),
+                        "kernel": "k_mc32<FP32_KAHAN> (marginal-cost window sums)",
+                        "per_unit": f"{SLOTS_PER_TERM} FP32 VALU slots per algorithmic term",
+                        "kernel_avg_us": mc_avg_s * 1e6, "kernel_launches": mc_n,
+                        "kernel_terms_per_s": terms / max(mc_n, 1) / mc_avg_s},
            "kernel_ms_per_step": breakdown}
-    print(json.dumps(res), flush=True)
+    if not a.no_check:
+        # the cost error bar: J of the final state of two instances against
+        # the oracle's objective of the same state (FP64 both sides)
+        import oracle
+
+        errs = []
+        for b in (0, len(cases) - 1):
+            u0h, u1h = out[0][b].cpu().numpy(), out[1][b].cpu().numpy()
+            Jo = oracle.objective(probs[b], u0h, u1h)
+            errs.append(abs(out[2][b].cpu().numpy()[-1] - Jo) / Jo)
+        res["J_final_rel_err_vs_oracle_objective"] = float(max(errs))
+    return res, cases
 
 
-def bench_serving(a):
-    """Continuous batching on a Poisson trace against one solve at a time."""
+def serving_leg(a):
+    """Continuous batching on the Poisson trace (4096 requests, seed 0) at
+    0.8 and 0.5 of the server's saturated rate, against one solve at a time
+    (ucp_solve, B = 1) run live, first come first served, on the same
+    arrivals.  Returns the serving fields of the bench line."""
     import numpy as np
     import torch
 
@@ -222,7 +293,7 @@ def bench_serving(a):
                 continue
             srv.step()
             t_now = time.perf_counter() - t0
-            # admission is first-come first-served and at most max_slots
+            # admission is first come first served and at most max_slots
             # requests run at once, so only the first max_slots unfinished
             # requests (in submission order) can have finished in this step
             keep = []
@@ -232,55 +303,84 @@ def bench_serving(a):
                     keep.append((tk, idx))
                 else:
                     done[idx] = t_now
-                    if len(done) % 512 == 0:
+                    if len(done) % 1024 == 0:
                         print(f"# {len(done)}/{n} served", file=sys.stderr, flush=True)
             live = keep + live[max_slots:]
         srv.close()
-        fin = np.array([done[i] for i in range(n)])
-        return fin
+        return np.array([done[i] for i in range(n)])
 
-    # saturated throughput: every request queued at t = 0
-    fin = run_server(np.zeros(n), a.slots)
+    # inputs of the one-at-a-time runs resident on the device beforehand
+    u0_dev = [torch.as_tensor(r.case.u0_init).cuda() for r in trace]
+
+    def run_fifo(arrivals):
+        """ucp_solve per request in arrival order; a request starts when it
+        has arrived and the previous one has finished (ucp_solve returns
+        when its work is done)."""
+        t0 = time.perf_counter()
+        end = np.empty(n)
+        for i, r in enumerate(trace):
+            wait = arrivals[i] - (time.perf_counter() - t0)
+            if wait > 0:
+                time.sleep(wait)
+            c = r.case
+            U.solve(c.prob, c.search, c.iters, u0_dev[i], a.prec)
+            end[i] = time.perf_counter() - t0
+            if (i + 1) % 1024 == 0:
+                print(f"# one at a time: {i + 1}/{n}", file=sys.stderr, flush=True)
+        return end
+
+    fin = run_server(np.zeros(n), a.slots)  # saturated: every request queued at t = 0
     sat = n / fin.max()
     print(f"# server saturated: {sat:.1f} solves/s", file=sys.stderr, flush=True)
-    rate = 0.8 * sat
-    arrivals = unit_t / rate
-    fin = run_server(arrivals, a.slots)
-    lat = fin - arrivals
-    served = n / fin.max()
-    print(f"# server on the trace: {served:.1f} solves/s", file=sys.stderr, flush=True)
-    # one solve at a time (ucp_solve, B = 1), FIFO on the same trace: service
-    # times measured on the GPU, schedule start = max(arrival, previous end)
-    st = torch.cuda.current_stream()
-    svc = np.empty(n)
-    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    for i, r in enumerate(trace):
-        c = r.case
-        u0 = torch.as_tensor(c.u0_init).cuda()
-        ev0.record(st)
-        U.solve(c.prob, c.search, c.iters, u0, a.prec)
-        ev1.record(st)
-        ev1.synchronize()
-        svc[i] = ev0.elapsed_time(ev1) / 1e3
-        if (i + 1) % 512 == 0:
-            print(f"# one at a time: {i + 1}/{n}", file=sys.stderr, flush=True)
-    end = np.empty(n)
-    prev = 0.0
-    for i in range(n):
-        prev = max(arrivals[i], prev) + svc[i]
-        end[i] = prev
-    lat1 = end - arrivals
-    res = {"metric": "served solves/s", "value": served, "unit": "solves/s", "n_gpus": 1, "steps": 1,
-           "warmup": 0, "ms_per_step": fin.max() * 1e3, "higher_is_better": True, "scaling": "weak",
-           "vs_baseline": None, "dtype": "f32", "data": "synthetic",
-           "config": {"workload": f"serving-poisson-{n}", "requests": n, "rate_per_s": rate,
-                      "sizes": [1001, 4001, 8001, 20001], "search": "3x21", "rounds": 20, "max_slots": a.slots,
-                      "prec": a.prec},
-           "p50_latency_s": float(np.percentile(lat, 50)), "p99_latency_s": float(np.percentile(lat, 99)),
-           "saturated_solves_per_s": sat,
-           "one_at_a_time": {"solves_per_s": n / end.max(), "p50_latency_s": float(np.percentile(lat1, 50)),
-                             "p99_latency_s": float(np.percentile(lat1, 99)),
-                             "mean_service_s": float(svc.mean()), "saturated_solves_per_s": n / svc.sum()}}
+    fifo_sat = run_fifo(np.zeros(n))
+    sat1 = n / fifo_sat.max()
+    print(f"# one at a time saturated: {sat1:.1f} solves/s", file=sys.stderr, flush=True)
+    rates = {}
+    for frac in (0.8, 0.5):
+        rate = frac * sat
+        arr = unit_t / rate
+        fin = run_server(arr, a.slots)
+        lat = fin - arr
+        end = run_fifo(arr)
+        lat1 = end - arr
+        rates[f"{frac}x"] = {
+            "offered_per_s": rate,
+            "server": {"solves_per_s": n / fin.max(), "p50_latency_s": float(np.percentile(lat, 50)),
+                       "p99_latency_s": float(np.percentile(lat, 99))},
+            "one_at_a_time": {"solves_per_s": n / end.max(), "p50_latency_s": float(np.percentile(lat1, 50)),
+                              "p99_latency_s": float(np.percentile(lat1, 99))}}
+        print(f"# {frac}x: server p99 {rates[f'{frac}x']['server']['p99_latency_s']:.3f} s, one at a time "
+              f"p99 {rates[f'{frac}x']['one_at_a_time']['p99_latency_s']:.3f} s", file=sys.stderr, flush=True)
+    return {"workload": f"serving-poisson-{n}", "requests": n, "sizes": [1001, 4001, 8001, 20001],
+            "k": "logU[0.05, 0.5]", "sigma": "logU[1, 10]", "search": "3x21", "rounds": 20, "max_slots": a.slots,
+            "prec": a.prec, "saturated_solves_per_s": sat, "one_at_a_time_saturated_solves_per_s": sat1,
+            "rates": rates}
+
+
+def bench_headline(a):
+    """The bench line: the 64 x 65536 batch (the metric's terms/s), the
+    served solves/s with p50/p99, the roofline of the marginal-cost kernel
+    and the oracle's CPU baseline."""
+    res, cases = batch_leg(a)
+    line = {"metric": METRIC, "value": res.pop("value"), "unit": res.pop("unit"), "n_gpus": 1, "steps": a.steps,
+            "warmup": a.warmup, "ms_per_step": res.pop("ms_per_step"), "higher_is_better": True,
+            "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic"}
+    line.update(res)
+    if not a.no_serving:
+        line["serving"] = serving_leg(a)
+    if not a.no_cpu:
+        line["cpu_baseline"] = cpu_baseline(cases[:4])
+    print(json.dumps(line), flush=True)
+
+
+def bench_serving(a):
+    """The serving leg alone, as its own line."""
+    srv = serving_leg(a)
+    r = srv["rates"]["0.8x"]["server"]
+    res = {"metric": "served solves/s", "value": r["solves_per_s"], "unit": "solves/s", "n_gpus": 1, "steps": 1,
+           "warmup": 0, "ms_per_step": srv["requests"] / r["solves_per_s"] * 1e3, "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+           "config": {"workload": srv["workload"]}, "serving": srv}
     print(json.dumps(res), flush=True)
 
 
@@ -405,7 +505,7 @@ def bench_coding(a):
 
 
 def bench_w2(a):
-    """Two-dimensional Witsenhausen (Section V-E): k = 0.2, sigma = 5,
+    """Two-dimensional Witsenhausen (Section V-D): k = 0.2, sigma = 5,
     160 x 160 nodes, 4 levels x 8 x 8 candidates, 10 rounds; one step is
     one whole solve, FP64."""
     import numpy as np
@@ -577,10 +677,13 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="paper")
+    ap.add_argument("--workload", default="headline",
+                    help="headline (64 x 65536 batch + serving + CPU baseline), paper (one 20001-node solve), "
+                         "small, batch, serving, sweep, coding, w2, copy-calibration")
     ap.add_argument("--prec", default="fp32_kahan")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-check", action="store_true", help="skip the FP64 oracle check of the final J")
+    ap.add_argument("--no-serving", action="store_true", help="headline: skip the serving leg")
     ap.add_argument("--requests", type=int, default=4096, help="serving: requests taken from the trace")
     ap.add_argument("--slots", type=int, default=64, help="serving: concurrent solves")
     ap.add_argument("--instances", type=int, default=64, help="batch: instances per launch")
@@ -593,8 +696,11 @@ def main():
               "rows by design, but only the single-GPU kernel is built and measured).", file=sys.stderr)
         sys.exit(2)
 
+    if a.workload == "headline":
+        return bench_headline(a)
     if a.workload == "batch":
-        return bench_batch(a)
+        a.no_serving = True
+        return bench_headline(a)
     if a.workload == "serving":
         return bench_serving(a)
     if a.workload == "sweep":
@@ -678,7 +784,7 @@ def main():
         Jo = oracle.objective(p, out[0].cpu().numpy(), out[1].cpu().numpy())
         res["J_final_rel_err_vs_oracle_objective"] = abs(J[-1] - Jo) / Jo
     if not a.no_cpu:
-        res["cpu_baseline"] = cpu_baseline(case)
+        res["cpu_baseline"] = cpu_baseline([case])
     print(json.dumps(res), flush=True)
 
 

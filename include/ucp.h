@@ -77,11 +77,23 @@ typedef struct ucp_problem {
  * h0 = (u_hi - u_lo) / (cands - 1)); level l takes `cands` equally spaced
  * candidates on [c* - h_{l-1}, c* + h_{l-1}] clamped to [u_lo, u_hi]
  * (h_l = 2 h_{l-1} / (cands - 1)), c* being the best so far, which stays in
- * the comparison; the incumbent u0(x0) is compared last and kept on ties. */
+ * the comparison; the incumbent u0(x0) is compared last and kept on ties.
+ *
+ * tie_rel64: relative tie band of the selection rule (FP64 values within
+ * m (1 + tie_rel64) of the minimum m are ties); 0 selects 1e-12.  Finite,
+ * 0 <= tie_rel64 <= 1e-3.
+ * band_rel32: relative part tau of the FP32 pre-selection band of the FP32
+ * modes, B32 <= m32 (1 + tau + tie_rel64) + 6e-7 sqrt(m32); 0 selects
+ * 5e-7 with compensated sums and 5e-6 with plain sums, the widths that
+ * keep the FP64 minimum in the band (a narrower band is faster and may
+ * drop it).  Finite, 0 <= band_rel32 <= 1e-2.  Ignored in FP64 mode.
+ * A zero-initialised record's two fields select the defaults. */
 typedef struct ucp_search {
   double u_lo, u_hi;
   int32_t levels; /* 1 .. UCP_MAX_LEVELS */
   int32_t cands;  /* 2 .. UCP_MAX_CANDS */
+  double tie_rel64;
+  double band_rel32;
 } ucp_search;
 
 typedef struct ucp_handle ucp_handle;
@@ -93,9 +105,11 @@ const char* ucp_version(void);
 const char* ucp_last_error(void);
 
 /* Create a handle on HIP device `device`.  Allocates no device memory yet;
- * the workspace grows on first use.  Errors: UCP_EINVAL (null out),
- * UCP_EHIP (no such device). */
-int ucp_create(ucp_handle** out, int device);
+ * the workspace grows on first use, never beyond `hbm_budget` bytes
+ * (0 = no limit): a call whose workspace would exceed it fails with
+ * UCP_ENOMEM and enqueues nothing.  Errors: UCP_EINVAL (null out, no such
+ * device), UCP_EHIP (no HIP device). */
+int ucp_create(ucp_handle** out, int device, size_t hbm_budget);
 
 /* Release the handle and its workspace (synchronises the device first).
  * NULL is a no-op. */
@@ -107,9 +121,13 @@ void ucp_destroy(ucp_handle* h);
  *        + dy * sum_j phi(y_j - x_i - u) (x_i + u - u1[j])^2 ),
  *   u = u[i*n_cand + c], phi the N(0,1) density.
  * u1: [n_y]; u: [n_x * n_cand] row-major per point; L0_out: [n_x * n_cand].
- * The sum runs over the nodes within 9 (FP32 modes) or 12 (FP64) noise
+ * The sum runs over the nodes within 9 (FP32 modes) or 11 (FP64) noise
  * standard deviations of the node nearest x_i + u, scaled by the Gaussian
- * at that node (max-shift); omitted weight is below 3e-18 relative.
+ * at that node (max-shift).  The omitted tail is below
+ * 2 phi(W)/W max_j (x_i + u - u1[j])^2 for a window of W sds: 2.6e-19 of
+ * that square at W = 9 (far below the FP32 sums' rounding), 3.9e-28 at
+ * W = 11 (below 1e-16 of the FP64 result wherever it exceeds 4e-12 of
+ * that square).
  * Errors: UCP_EINVAL for null pointers, n_cand < 1, invalid problem. */
 int ucp_marginal_cost(ucp_handle* h, const ucp_problem* prob, ucp_prec prec,
                       const double* u1, const double* u, int64_t n_cand,
@@ -120,11 +138,12 @@ int ucp_marginal_cost(ucp_handle* h, const ucp_problem* prob, ucp_prec prec,
  * the coarse-to-fine search of ucp_search over u of
  * B(u; x_i) = L_0(u, x_i) / f(x_i), with u1 held fixed.
  * Selection at every level and at the final comparison with the incumbent:
- * the candidates within a relative band 1e-12 of the minimum (in FP64) are
- * ties, the one nearest u0_in[i] wins, then the smaller u.  In the FP32
- * modes the minimum and band are first found in FP32 - the band is
- * B <= m (1 + tau) + 6e-7 sqrt(m), tau = 5e-7 with compensated sums and
- * 5e-6 with plain sums - and the band members are re-evaluated in FP64
+ * the candidates within the relative band tie_rel64 (default 1e-12) of the
+ * minimum (in FP64) are ties, the one nearest u0_in[i] wins, then the
+ * smaller u.  In the FP32 modes the minimum and band are first found in
+ * FP32 - the band is B <= m (1 + tau + tie_rel64) + 6e-7 sqrt(m), tau =
+ * band_rel32 (default 5e-7 with compensated sums and 5e-6 with plain sums)
+ * - and the band members are re-evaluated in FP64 (window of 11 sds)
  * before the rule is applied.
  * u1: [n_y]; u0_in, u0_out: [n_x] (may alias); L0_out: [n_x] or NULL - if
  * given, receives f(x_i) * B(u0_out[i]; x_i) evaluated in FP64.
@@ -137,8 +156,12 @@ int ucp_argmin_adaptive(ucp_handle* h, const ucp_problem* prob, const ucp_search
  * u1(y_j) = sum_i x1_i f_i phi(y_j - x1_i) / sum_i f_i phi(y_j - x1_i),
  * x1_i = x_i + u0[i], the exact minimiser of the discrete marginal cost
  * C_1 (the closed form the paper credits to the earlier solver, Section
- * IV-B).  Weights are max-shifted per y_j; in the FP32 modes the weights and
- * the numerator sum are FP32 and the denominator sum is FP64.
+ * IV-B).  Weights are max-shifted per y_j.  The logits are FP64; in the FP32
+ * modes each weight is the FP32 exponential of its FP64 logit, in FP64 mode
+ * the FP64 one.  Numerator and denominator are FP64 sums in every mode
+ * (the two FP32 modes give the same u1): u1 feeds every later marginal
+ * cost, and an FP32 numerator would move it by ~1e-7 |x1|, far beyond the
+ * FP64 tie band of the decisions that follow.
  * u0: [n_x]; u1_out: [n_y].  Errors: UCP_EINVAL. */
 int ucp_update_u1(ucp_handle* h, const ucp_problem* prob, ucp_prec prec,
                   const double* u0, double* u1_out, void* stream);
@@ -154,9 +177,11 @@ int ucp_objective(ucp_handle* h, const ucp_problem* prob, const double* u0,
  * `iters` rounds of (ucp_argmin_adaptive on u0, ucp_update_u1), with
  * J_hist[t] taken after round t.  This is the per-controller loop of
  * Algorithm 1 with the two controllers visited in order, run for a fixed
- * number of rounds; every step stays on the device.
+ * number of rounds; every step stays on the device.  It is ucp_solve_batch
+ * with B = 1 and, like it, synchronises the stream before returning (it
+ * reads the work counters and the non-finite flag).
  * u0_init, u0_out: [n_x]; u1_out: [n_y]; J_hist: [iters + 1].
- * Errors: UCP_EINVAL (iters < 0, invalid inputs). */
+ * Errors: UCP_EINVAL (iters < 0, invalid inputs), UCP_ENONFINITE. */
 int ucp_solve(ucp_handle* h, const ucp_problem* prob, const ucp_search* search, ucp_prec prec,
               int32_t iters, const double* u0_init, double* u0_out, double* u1_out,
               double* J_hist, void* stream);
@@ -235,7 +260,8 @@ int ucp_coding_marginal_cost(ucp_handle* h, const ucp_coding_problem* prob, cons
                              const double* u, int64_t n_cand, double* L0_out, void* stream);
 
 /* One pointwise improvement of u0 with u1 fixed: the coarse-to-fine search
- * and the selection rule of ucp_argmin_adaptive (relative tie band 1e-12,
+ * and the selection rule of ucp_argmin_adaptive (relative tie band
+ * tie_rel64, default 1e-12,
  * nearest to u0_in[i], then the smaller u; the incumbent compared last),
  * every B evaluated in FP64 as in ucp_coding_marginal_cost.
  * u1: [n_y]; u0_in, u0_out: [n_x] (may alias); L0_out: [n_x] or NULL
@@ -269,7 +295,7 @@ int ucp_coding_solve(ucp_handle* h, const ucp_coding_problem* prob, const ucp_se
                      int32_t iters, const double* u0_init, double* u0_out, double* u1_out,
                      double* J_hist, void* stream);
 
-/* ---- Two-dimensional Witsenhausen counterexample (Section V-E) ---------
+/* ---- Two-dimensional Witsenhausen counterexample (Section V-D) ---------
  * x0 in R^2 with both coordinates independent draws of the prior of
  * `prob`, x1 = x0 + u0(x0), y1 = x1 + w with w ~ N(0, I_2),
  * x2 = x1 - u1(y1); minimise J = 1/2 E[k^2 |u0|^2 + |x2|^2] (the paper:
@@ -295,8 +321,8 @@ int ucp_w2_marginal_cost(ucp_handle* h, const ucp_problem* prob, const double* u
  * over the K x K tensor grid of candidates per level (K = cands <= 8;
  * level 0 on [u_lo, u_hi]^2, level l on c* -/+ h_{l-1} in each coordinate,
  * clamped; the best so far carried; spacings as in ucp_search), then the
- * incumbent.  Selection: the candidates within a relative band 1e-12 of
- * the minimum are ties; the nearest to u0_in (squared distance) wins, then
+ * incumbent.  Selection: the candidates within the relative band tie_rel64
+ * (default 1e-12) of the minimum are ties; the nearest to u0_in (squared distance) wins, then
  * the smaller first coordinate, then the smaller second, then the earlier
  * candidate (index q1 * K + q2, the best so far last).
  * u0_in, u0_out: [2][n_x^2] (may alias); L0_out: [n_x^2] or NULL.

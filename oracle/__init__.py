@@ -14,7 +14,8 @@ Problem objects are duck-typed: any object with ``k`` (``lam`` for the
 coding problem of Section V-B, the ``coding_*`` functions), ``comps`` (a sequence
 of ``(weight, mean, sd)`` for the Gaussian-mixture prior of x0), ``x_lo``,
 ``x_hi``, ``n_x``, ``y_lo``, ``y_hi``, ``n_y``.  Search objects need
-``u_lo``, ``u_hi``, ``levels``, ``cands``.
+``u_lo``, ``u_hi``, ``levels``, ``cands`` and may carry ``tie_rel64`` (the
+relative tie band of the selection rule, 0 = 1e-12).
 """
 from __future__ import annotations
 
@@ -54,6 +55,8 @@ class _Search(C.Structure):
         ("u_hi", C.c_double),
         ("levels", C.c_int32),
         ("cands", C.c_int32),
+        ("tie_rel64", C.c_double),
+        ("band_rel32", C.c_double),
     ]
 
 
@@ -89,6 +92,8 @@ def lib():
         L.orc_marginal_cost.argtypes = [P(_Problem), dp, dp, C.c_int64, dp]
         L.orc_spacings.argtypes = [P(_Search), dp]
         L.orc_argmin.argtypes = [P(_Problem), P(_Search), dp, dp, ip, C.c_int64, dp, dp]
+        L.orc_argmin_visits.argtypes = [P(_Problem), P(_Search), dp, dp, ip, C.c_int64, dp, dp]
+        L.orc_set_threads.argtypes = [C.c_int]
         L.orc_update_u1.argtypes = [P(_Problem), dp, ip, C.c_int64, dp]
         L.orc_objective.argtypes = [P(_Problem), dp, dp]
         L.orc_objective.restype = C.c_double
@@ -132,6 +137,8 @@ def _search(s) -> _Search:
     r = _Search()
     r.u_lo, r.u_hi = float(s.u_lo), float(s.u_hi)
     r.levels, r.cands = int(s.levels), int(s.cands)
+    r.tie_rel64 = float(getattr(s, "tie_rel64", 0.0))
+    r.band_rel32 = float(getattr(s, "band_rel32", 0.0))
     return r
 
 
@@ -206,6 +213,24 @@ def argmin(p, s, u1, u0_in, rows=None):
     lib().orc_argmin(C.byref(_prob(p)), C.byref(_search(s)), _dp(u1), _dp(u0_in),
                      rp, n, _dp(u0o), _dp(Bo))
     return u0o, Bo
+
+
+def argmin_visits(p, s, u1, u0_in, rows):
+    """orc_argmin on the listed rows, also returning every position whose B
+    was evaluated: (u0_out [n], visits [n, levels * cands + 1])."""
+    u1 = _f64(u1, int(p.n_y))
+    u0_in = _f64(u0_in, int(p.n_x))
+    n, r = _rows(rows, int(p.n_x))
+    u0o = np.empty(n, np.float64)
+    vis = np.empty((n, int(s.levels) * int(s.cands) + 1), np.float64)
+    lib().orc_argmin_visits(C.byref(_prob(p)), C.byref(_search(s)), _dp(u1), _dp(u0_in),
+                            r.ctypes.data_as(C.POINTER(C.c_int64)), n, _dp(u0o), _dp(vis))
+    return u0o, vis
+
+
+def set_threads(n: int) -> None:
+    """OpenMP threads of the oracle's loops (0: the runtime's default)."""
+    lib().orc_set_threads(int(n))
 
 
 def update_u1(p, u0, rows=None) -> np.ndarray:
@@ -306,7 +331,7 @@ def coding_solve(p, s, iters: int, u0_init):
 
 
 # ---------------------------------------------------------------------------
-# Two-dimensional Witsenhausen (Section V-E): tensor grids, vector fields as
+# Two-dimensional Witsenhausen (Section V-D): tensor grids, vector fields as
 # arrays [2, n * n] (node (i1, i2) at i1 * n + i2).
 
 def _planes(a, n, name):

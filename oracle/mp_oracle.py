@@ -40,11 +40,11 @@ def _Bfun(p, ys, u1, x, u):
     return mp.mpf(p.k) ** 2 * u ** 2 + dy * acc
 
 
-def _select(cands, vals, inc):
+def _select(cands, vals, inc, tau=TAU):
     m = min(vals)
     best = None
     for c, v in zip(cands, vals):
-        if v <= m * (1 + TAU):
+        if v <= m * (1 + tau):
             key = (abs(c - inc), c)
             if best is None or key < best[0]:
                 best = (key, c, v)
@@ -97,6 +97,8 @@ def argmin(p, s, u1, u0_in):
         ys = _nodes(p.y_lo, p.y_hi, p.n_y)
         u1m = [v if isinstance(v, mp.mpf) else mp.mpf(float(v)) for v in u1]
         K, L = int(s.cands), int(s.levels)
+        t64 = float(getattr(s, "tie_rel64", 0.0))
+        tau = mp.mpf(t64) if t64 > 0 else TAU
         h = [(float(s.u_hi) - float(s.u_lo)) / float(K - 1)]
         for _ in range(1, L):
             h.append(2.0 * h[-1] / float(K - 1))
@@ -108,7 +110,7 @@ def argmin(p, s, u1, u0_in):
             inc = float(u0_in[i])
             cs = [float(np.float64(s.u_lo) + np.float64(q) * np.float64(h[0])) for q in range(K)]
             vs = [_Bfun(p, ys, u1m, x, mp.mpf(c)) for c in cs]
-            c_best, v_best = _select([mp.mpf(c) for c in cs], vs, mp.mpf(inc))
+            c_best, v_best = _select([mp.mpf(c) for c in cs], vs, mp.mpf(inc), tau)
             c_best = float(c_best)
             for lvl in range(1, L):
                 cs = []
@@ -118,10 +120,10 @@ def argmin(p, s, u1, u0_in):
                 vs = [_Bfun(p, ys, u1m, x, mp.mpf(c)) for c in cs]
                 cs.append(c_best)
                 vs.append(v_best)
-                cb, v_best = _select([mp.mpf(c) for c in cs], vs, mp.mpf(inc))
+                cb, v_best = _select([mp.mpf(c) for c in cs], vs, mp.mpf(inc), tau)
                 c_best = float(cb)
             v_inc = _Bfun(p, ys, u1m, x, mp.mpf(inc))
-            cb, _ = _select([mp.mpf(c_best), mp.mpf(inc)], [v_best, v_inc], mp.mpf(inc))
+            cb, _ = _select([mp.mpf(c_best), mp.mpf(inc)], [v_best, v_inc], mp.mpf(inc), tau)
             out.append(float(cb))
         return out
 

@@ -35,7 +35,7 @@
 #endif
 
 #define ORC_MAX_COMP 8
-#define ORC_TAU64 1e-12 /* relative tie band of the selection rule */
+#define ORC_TAU64 1e-12 /* relative tie band of the selection rule, unless the search sets one */
 
 /* Problem description: stage-1 weight k, a Gaussian-mixture prior for x0
  * (one component = the paper's N(0, sigma^2)), and the two grids. */
@@ -52,12 +52,19 @@ typedef struct {
   int64_t n_y;
 } orc_problem;
 
-/* Coarse-to-fine search settings for the u0 update. */
+/* Coarse-to-fine search settings for the u0 update.  tie_rel64 is the
+ * relative tie band of the selection rule (0 selects ORC_TAU64);
+ * band_rel32 belongs to the FP32 pre-selection of the GPU path and has no
+ * meaning here (the layout matches the library's search record). */
 typedef struct {
   double u_lo, u_hi;
   int32_t levels;
   int32_t cands;
+  double tie_rel64;
+  double band_rel32;
 } orc_search;
+
+static double orc_tau(const orc_search* s) { return s->tie_rel64 > 0.0 ? s->tie_rel64 : ORC_TAU64; }
 
 static const double ORC_PI = 3.14159265358979323846264338327950288;
 
@@ -139,14 +146,14 @@ void orc_marginal_cost(const orc_problem* p, const double* u1, const double* u,
 
 /* Selection among a finite candidate set (the improvement rule of
  * Section III-B on a finite set): the members whose B lies within a
- * relative band TAU64 of the minimum are ties; among them the one nearest
+ * relative band tau of the minimum are ties; among them the one nearest
  * the incumbent u_inc wins, and an equal distance goes to the smaller u.
  * Returns the index of the chosen member. */
-static int orc_select(int n, const double* c, const double* B, double u_inc) {
+static int orc_select(int n, const double* c, const double* B, double u_inc, double tau) {
   double m = B[0];
   for (int s = 1; s < n; ++s)
     if (B[s] < m) m = B[s];
-  double thr = m * (1.0 + ORC_TAU64);
+  double thr = m * (1.0 + tau);
   int best = -1;
   double bd = 0.0;
   for (int s = 0; s < n; ++s) {
@@ -188,9 +195,12 @@ static double orc_model_B(int model, double lam, const orc_problem* p, const dou
   return model == 1 ? orc_cd_B(p, lam, u1, x, u) : orc_B(p, u1, x, u);
 }
 
+/* visit (NULL, or levels * cands + 1 entries) receives every position whose
+ * B was evaluated, level by level, the incumbent last: the work count of the
+ * CPU baseline. */
 static double orc_argmin_point(const orc_problem* p, const orc_search* s,
                                const double* u1, const double* h, int64_t i,
-                               double u_inc, double* B_out, int model, double lam) {
+                               double u_inc, double* B_out, int model, double lam, double* visit) {
   int K = s->cands;
   double x = orc_node(p->x_lo, p->x_hi, p->n_x, i);
   double* c = (double*)malloc(sizeof(double) * (size_t)(K + 1));
@@ -199,18 +209,21 @@ static double orc_argmin_point(const orc_problem* p, const orc_search* s,
   for (int q = 0; q < K; ++q) {
     c[q] = s->u_lo + (double)q * h[0];
     B[q] = orc_model_B(model, lam, p, u1, x, c[q]);
+    if (visit) visit[q] = c[q];
   }
-  int b = orc_select(K, c, B, u_inc);
+  const double tau = orc_tau(s);
+  int b = orc_select(K, c, B, u_inc, tau);
   double cs = c[b], Bs = B[b];
   /* finer levels around the best so far, which stays in the set */
   for (int l = 1; l < s->levels; ++l) {
     for (int q = 0; q < K; ++q) {
       c[q] = orc_clamp(cs - h[l - 1] + (double)q * h[l], s->u_lo, s->u_hi);
       B[q] = orc_model_B(model, lam, p, u1, x, c[q]);
+      if (visit) visit[l * K + q] = c[q];
     }
     c[K] = cs;
     B[K] = Bs;
-    b = orc_select(K + 1, c, B, u_inc);
+    b = orc_select(K + 1, c, B, u_inc, tau);
     cs = c[b];
     Bs = B[b];
   }
@@ -219,7 +232,8 @@ static double orc_argmin_point(const orc_problem* p, const orc_search* s,
   B[0] = Bs;
   c[1] = u_inc;
   B[1] = orc_model_B(model, lam, p, u1, x, u_inc);
-  b = orc_select(2, c, B, u_inc);
+  if (visit) visit[s->levels * K] = u_inc;
+  b = orc_select(2, c, B, u_inc, tau);
   double r = c[b];
   if (B_out) *B_out = B[b];
   free(c);
@@ -232,23 +246,41 @@ static double orc_argmin_point(const orc_problem* p, const orc_search* s,
  * rows. */
 static void orc_argmin_model(const orc_problem* p, const orc_search* s, const double* u1,
                              const double* u0_in, const int64_t* rows, int64_t n_rows,
-                             double* u0_out, double* B_out, int model, double lam) {
+                             double* u0_out, double* B_out, int model, double lam, double* visits) {
   double h[64];
   orc_spacings(s, h);
   int64_t n = rows ? n_rows : p->n_x;
+  const int64_t nv = (int64_t)s->levels * s->cands + 1;
 #pragma omp parallel for schedule(static)
   for (int64_t r = 0; r < n; ++r) {
     int64_t i = rows ? rows[r] : r;
     double Bv;
-    u0_out[r] = orc_argmin_point(p, s, u1, h, i, u0_in[i], &Bv, model, lam);
+    u0_out[r] = orc_argmin_point(p, s, u1, h, i, u0_in[i], &Bv, model, lam, visits ? visits + r * nv : NULL);
     if (B_out) B_out[r] = Bv;
   }
+}
+
+/* orc_argmin that also reports the positions evaluated per listed row
+ * (visits: [n_rows][levels * cands + 1]). */
+void orc_argmin_visits(const orc_problem* p, const orc_search* s, const double* u1,
+                       const double* u0_in, const int64_t* rows, int64_t n_rows,
+                       double* u0_out, double* visits) {
+  orc_argmin_model(p, s, u1, u0_in, rows, n_rows, u0_out, NULL, 0, 0.0, visits);
+}
+
+/* Thread count of the OpenMP loops (n < 1: the runtime's default). */
+void orc_set_threads(int n) {
+#ifdef _OPENMP
+  omp_set_num_threads(n > 0 ? n : omp_get_num_procs());
+#else
+  (void)n;
+#endif
 }
 
 void orc_argmin(const orc_problem* p, const orc_search* s, const double* u1,
                 const double* u0_in, const int64_t* rows, int64_t n_rows,
                 double* u0_out, double* B_out) {
-  orc_argmin_model(p, s, u1, u0_in, rows, n_rows, u0_out, B_out, 0, 0.0);
+  orc_argmin_model(p, s, u1, u0_in, rows, n_rows, u0_out, B_out, 0, 0.0, NULL);
 }
 
 /* Second controller by its closed form: u1(y) = E[x1 | y1 = y], the exact
@@ -385,7 +417,7 @@ void orc_cd_marginal_cost(const orc_problem* p, double lam, const double* u1, co
 void orc_cd_argmin(const orc_problem* p, double lam, const orc_search* s, const double* u1,
                    const double* u0_in, const int64_t* rows, int64_t n_rows,
                    double* u0_out, double* B_out) {
-  orc_argmin_model(p, s, u1, u0_in, rows, n_rows, u0_out, B_out, 1, lam);
+  orc_argmin_model(p, s, u1, u0_in, rows, n_rows, u0_out, B_out, 1, lam, NULL);
 }
 
 /* Second controller by its closed form, the conditional mean
@@ -459,7 +491,7 @@ void orc_cd_solve(const orc_problem* p, double lam, const orc_search* s, int32_t
 }
 
 /* ------------------------------------------------------------------------
- * Two-dimensional Witsenhausen counterexample (Section V-E): x0 in R^2 with
+ * Two-dimensional Witsenhausen counterexample (Section V-D): x0 in R^2 with
  * both coordinates independent draws of the prior above, x1 = x0 + u0(x0),
  * y1 = x1 + w with w ~ N(0, I_2), x2 = x1 - u1(y1),
  * J = 1/2 E[k^2 |u0(x0)|^2 + |x2|^2].
@@ -518,15 +550,16 @@ void orc2_marginal_cost(const orc_problem* p, const double* u1, const double* u,
   free(f2);
 }
 
-/* Selection among 2-D candidates: ties within the relative band TAU64 of the
+/* Selection among 2-D candidates: ties within the relative band tau of the
  * minimum; the one nearest the incumbent (squared Euclidean distance) wins,
  * then the smaller first coordinate, then the smaller second, then the
  * earlier index. */
-static int orc2_select(int n, const double* ca, const double* cb, const double* B, double ia, double ib) {
+static int orc2_select(int n, const double* ca, const double* cb, const double* B, double ia, double ib,
+                       double tau) {
   double m = B[0];
   for (int s = 1; s < n; ++s)
     if (B[s] < m) m = B[s];
-  double thr = m * (1.0 + ORC_TAU64);
+  double thr = m * (1.0 + tau);
   int best = -1;
   double bd = 0.0;
   for (int s = 0; s < n; ++s) {
@@ -574,7 +607,7 @@ static void orc2_argmin_point(const orc_problem* p, const orc_search* s, const d
       B[KK] = sB;
       n = KK + 1;
     }
-    int b = orc2_select(n, ca, cb, B, ia, ib);
+    int b = orc2_select(n, ca, cb, B, ia, ib, orc_tau(s));
     sa = ca[b];
     sb = cb[b];
     sB = B[b];
@@ -585,7 +618,7 @@ static void orc2_argmin_point(const orc_problem* p, const orc_search* s, const d
   ca[1] = ia;
   cb[1] = ib;
   B[1] = orc2_B(p, u1, x1, x2, ia, ib);
-  int b = orc2_select(2, ca, cb, B, ia, ib);
+  int b = orc2_select(2, ca, cb, B, ia, ib, orc_tau(s));
   *oa = ca[b];
   *ob = cb[b];
   if (oB) *oB = B[b];

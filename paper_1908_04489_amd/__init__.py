@@ -8,7 +8,8 @@ raises immediately - there is no CPU fallback.
 
 Problem and search objects are duck-typed: ``k``, ``comps`` (sequence of
 ``(weight, mean, sd)``), ``x_lo``, ``x_hi``, ``n_x``, ``y_lo``, ``y_hi``,
-``n_y``; and ``u_lo``, ``u_hi``, ``levels``, ``cands``.
+``n_y``; and ``u_lo``, ``u_hi``, ``levels``, ``cands`` (optionally
+``tie_rel64``, ``band_rel32``; 0 selects the library's defaults).
 """
 from __future__ import annotations
 
@@ -53,7 +54,8 @@ class CodingProblem(C.Structure):
 
 
 class Search(C.Structure):
-    _fields_ = [("u_lo", C.c_double), ("u_hi", C.c_double), ("levels", C.c_int32), ("cands", C.c_int32)]
+    _fields_ = [("u_lo", C.c_double), ("u_hi", C.c_double), ("levels", C.c_int32), ("cands", C.c_int32),
+                ("tie_rel64", C.c_double), ("band_rel32", C.c_double)]
 
 
 if not os.path.exists(LIB_PATH):
@@ -66,7 +68,7 @@ _P = C.POINTER
 _sigs = {
     "ucp_version": ([], C.c_char_p),
     "ucp_last_error": ([], C.c_char_p),
-    "ucp_create": ([_P(_vp), C.c_int], C.c_int),
+    "ucp_create": ([_P(_vp), C.c_int, C.c_size_t], C.c_int),
     "ucp_destroy": ([_vp], None),
     "ucp_marginal_cost": ([_vp, _P(Problem), C.c_int, _vp, _vp, C.c_int64, _vp, _vp], C.c_int),
     "ucp_argmin_adaptive": ([_vp, _P(Problem), _P(Search), C.c_int, _vp, _vp, _vp, _vp, _vp], C.c_int),
@@ -138,6 +140,8 @@ def make_problem(p) -> Problem:
 def make_search(s) -> Search:
     r = Search()
     r.u_lo, r.u_hi, r.levels, r.cands = float(s.u_lo), float(s.u_hi), int(s.levels), int(s.cands)
+    r.tie_rel64 = float(getattr(s, "tie_rel64", 0.0))
+    r.band_rel32 = float(getattr(s, "band_rel32", 0.0))
     return r
 
 
@@ -181,7 +185,7 @@ def handle(device: int = 0):
         d = _handles.d = {}
     if device not in d:
         h = _vp()
-        _check(_lib.ucp_create(C.byref(h), int(device)))
+        _check(_lib.ucp_create(C.byref(h), int(device), 0))
         d[device] = h
     return d[device]
 
@@ -478,7 +482,7 @@ def coding_solve(prob, search, iters, u0_init):
     return u0, u1, J
 
 
-# ------------------------------------ two-dimensional Witsenhausen (Section V-E)
+# ------------------------------------ two-dimensional Witsenhausen (Section V-D)
 # Vector fields are device tensors [2, n * n] (node (i1, i2) at i1 * n + i2).
 
 def _dev_planes(t, n, name):

@@ -64,8 +64,12 @@ int check_search(const ucp_search* s) {
   if (!(s->u_lo < s->u_hi) || !std::isfinite(s->u_lo) || !std::isfinite(s->u_hi))
     return fail(UCP_EINVAL, "search needs finite u_lo < u_hi");
   if (std::fabs(s->u_lo) > 1e6 || std::fabs(s->u_hi) > 1e6) return fail(UCP_EINVAL, "search bounds beyond 1e6");
+  if (!(s->tie_rel64 >= 0.0 && s->tie_rel64 <= 1e-3)) return fail(UCP_EINVAL, "tie_rel64 must be in [0, 1e-3]");
+  if (!(s->band_rel32 >= 0.0 && s->band_rel32 <= 1e-2)) return fail(UCP_EINVAL, "band_rel32 must be in [0, 1e-2]");
   return UCP_OK;
 }
+
+double tie_band(const ucp_search* s) { return s && s->tie_rel64 > 0.0 ? s->tie_rel64 : kTau64; }
 
 int check_prec(int prec) {
   if (prec != UCP_FP32 && prec != UCP_FP32_KAHAN && prec != UCP_FP64)
@@ -107,6 +111,9 @@ Inst make_inst(const ucp_problem& p, const ucp_search* s, int prec, int cands_ov
     I.cands = cands_override;
   }
   if (cands_override > 0) I.cands = cands_override;
+  I.tau64 = tie_band(s);
+  // the FP32 band holds every candidate the FP64 band could hold
+  I.tau32 = (s && s->band_rel32 > 0.0 ? s->band_rel32 : prec == UCP_FP32_KAHAN ? kTau32Kahan : kTau32Plain) + I.tau64;
   I.nw32 = (int32_t)std::min<double>(std::ceil(kWin32 / I.dy), (double)I.n_y);
   I.nw64 = (int32_t)std::min<double>(std::ceil(kWin64 / I.dy), (double)I.n_y);
   I.prec = prec;
@@ -219,6 +226,7 @@ using namespace ucp;
 
 struct ucp_handle {
   int device = 0;
+  size_t budget = 0;  // workspace limit in bytes (0: none)
   void* ws = nullptr;
   size_t ws_bytes = 0;
   // kernel timing with HIP events on the caller's stream (ucp_profile)
@@ -231,10 +239,61 @@ struct ucp_handle {
   unsigned long long last_terms = 0;  // algorithmic terms of the last solve
   unsigned long long last_evals = 0;  // FP64 tie re-evaluations of the last solve
   unsigned long long last_evaluated = 0;  // marginal-cost terms the kernels evaluated
+  // Pinned host staging of the instance and launch tables, a ring of
+  // kStageSlots regions: a call writes its tables into the next region and
+  // records an event after the copies, which the call that reuses the region
+  // waits for.  The caller's host memory is never a copy source.
+  static constexpr int kStageSlots = 4;
+  char* stage[kStageSlots] = {nullptr};
+  size_t stage_cap[kStageSlots] = {0};
+  hipEvent_t stage_ev[kStageSlots] = {nullptr};
+  int stage_next = 0;
 };
+
+// Copy host parts to the device through the handle's next staging region,
+// asynchronously on `st`.
+struct HostPart {
+  void* dst;
+  const void* src;
+  size_t bytes;
+};
+static int stage_upload(ucp_handle* h, const std::vector<HostPart>& parts, hipStream_t st) {
+  const int k = h->stage_next;
+  h->stage_next = (k + 1) % ucp_handle::kStageSlots;
+  size_t total = 0;
+  for (const HostPart& p : parts) total += align_up(p.bytes);
+  hipError_t e;
+  if (h->stage_ev[k]) {
+    e = hipEventSynchronize(h->stage_ev[k]);  // the region's previous copies have been read
+    if (e != hipSuccess) return hip_fail(e, "wait for the staging region");
+  } else {
+    e = hipEventCreateWithFlags(&h->stage_ev[k], hipEventDisableTiming);
+    if (e != hipSuccess) return hip_fail(e, "create staging event");
+  }
+  if (total > h->stage_cap[k]) {
+    if (h->stage[k]) (void)hipHostFree(h->stage[k]);
+    h->stage[k] = nullptr;
+    h->stage_cap[k] = 0;
+    e = hipHostMalloc((void**)&h->stage[k], 2 * total, hipHostMallocDefault);
+    if (e != hipSuccess) return fail(UCP_ENOMEM, "pinned staging of %zu bytes: %s", 2 * total, hipGetErrorString(e));
+    h->stage_cap[k] = 2 * total;
+  }
+  char* at = h->stage[k];
+  for (const HostPart& p : parts) {
+    std::memcpy(at, p.src, p.bytes);
+    e = hipMemcpyAsync(p.dst, at, p.bytes, hipMemcpyHostToDevice, st);
+    if (e != hipSuccess) return hip_fail(e, "upload tables");
+    at += align_up(p.bytes);
+  }
+  e = hipEventRecord(h->stage_ev[k], st);
+  if (e != hipSuccess) return hip_fail(e, "record staging event");
+  return UCP_OK;
+}
 
 static int ensure_ws(ucp_handle* h, size_t bytes) {
   if (bytes <= h->ws_bytes) return UCP_OK;
+  if (h->budget && bytes > h->budget)
+    return fail(UCP_ENOMEM, "workspace of %zu bytes exceeds the handle's budget of %zu", bytes, h->budget);
   hipError_t e = hipSetDevice(h->device);
   if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
   if (h->ws) {
@@ -244,6 +303,7 @@ static int ensure_ws(ucp_handle* h, size_t bytes) {
     h->ws_bytes = 0;
   }
   size_t want = align_up(bytes + bytes / 8);
+  if (h->budget) want = std::max(bytes, std::min(want, h->budget));
   e = hipMalloc(&h->ws, want);
   if (e != hipSuccess) {
     h->ws = nullptr;
@@ -343,7 +403,7 @@ const char* ucp_version(void) { return "ucp-mi355x 0.1 (gfx950)"; }
 
 const char* ucp_last_error(void) { return g_err.c_str(); }
 
-int ucp_create(ucp_handle** out, int device) {
+int ucp_create(ucp_handle** out, int device, size_t hbm_budget) {
   if (!out) return fail(UCP_EINVAL, "out is NULL");
   *out = nullptr;
   int n = 0;
@@ -354,6 +414,7 @@ int ucp_create(ucp_handle** out, int device) {
   if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
   ucp_handle* h = new ucp_handle;
   h->device = device;
+  h->budget = hbm_budget;
   *out = h;
   return UCP_OK;
 }
@@ -364,6 +425,10 @@ void ucp_destroy(ucp_handle* h) {
   (void)hipDeviceSynchronize();
   if (h->ws) (void)hipFree(h->ws);
   for (hipEvent_t e : h->ev) (void)hipEventDestroy(e);
+  for (int k = 0; k < ucp_handle::kStageSlots; ++k) {
+    if (h->stage[k]) (void)hipHostFree(h->stage[k]);
+    if (h->stage_ev[k]) (void)hipEventDestroy(h->stage_ev[k]);
+  }
   delete h;
 }
 
@@ -389,8 +454,12 @@ struct Batch {
   }
 };
 
+// Lays out the batch in the workspace, lets `fix` set each carved instance's
+// call-specific fields (outputs, explicit inputs), and uploads the instance
+// and launch tables.
+template <typename Fix>
 int setup_batch(ucp_handle* h, Batch& B, std::vector<Inst> insts, const std::vector<std::vector<char>>& phases,
-                std::vector<int32_t>& host_tab, hipStream_t st) {
+                std::vector<int32_t>& host_tab, hipStream_t st, Fix fix) {
   B.n = (int)insts.size();
   size_t bytes = align_up(sizeof(Inst) * B.n) + align_up(sizeof(int32_t) * phases.size() * kKinds * (B.n + 1));
   for (auto& I : insts) bytes += state_bytes(I);
@@ -401,18 +470,22 @@ int setup_batch(ucp_handle* h, Batch& B, std::vector<Inst> insts, const std::vec
   base += align_up(sizeof(Inst) * B.n);
   B.d_tables = (int32_t*)base;
   base += align_up(sizeof(int32_t) * phases.size() * kKinds * (B.n + 1));
-  for (auto& I : insts) carve_state(I, base);
+  for (int b = 0; b < B.n; ++b) {
+    carve_state(insts[b], base);
+    fix(b, insts[b]);
+  }
   host_tab.clear();
   for (auto& run : phases) {
     std::vector<int32_t> t = build_tables(insts, run);
     host_tab.insert(host_tab.end(), t.begin(), t.end());
   }
   B.insts = std::move(insts);
-  hipError_t e = hipMemcpyAsync(B.d_insts, B.insts.data(), sizeof(Inst) * B.n, hipMemcpyHostToDevice, st);
-  if (e != hipSuccess) return hip_fail(e, "upload instance table");
-  e = hipMemcpyAsync(B.d_tables, host_tab.data(), sizeof(int32_t) * host_tab.size(), hipMemcpyHostToDevice, st);
-  if (e != hipSuccess) return hip_fail(e, "upload launch tables");
-  return UCP_OK;
+  return stage_upload(h, {{B.d_insts, B.insts.data(), sizeof(Inst) * B.n},
+                          {B.d_tables, host_tab.data(), sizeof(int32_t) * host_tab.size()}}, st);
+}
+int setup_batch(ucp_handle* h, Batch& B, std::vector<Inst> insts, const std::vector<std::vector<char>>& phases,
+                std::vector<int32_t>& host_tab, hipStream_t st) {
+  return setup_batch(h, B, std::move(insts), phases, host_tab, st, [](int, Inst&) {});
 }
 
 #define UCP_TRY(expr, what)                      \
@@ -490,15 +563,13 @@ int ucp_solve_batch(ucp_handle* h, int32_t nb, const ucp_problem* probs, const u
     for (int b = 0; b < nb; ++b) phases[t][b] = iters[b] >= t;
   Batch B;
   std::vector<int32_t> tab;
-  if ((rc = setup_batch(h, B, insts, phases, tab, st))) return rc;
+  // J_out of each instance is its J_hist
+  if ((rc = setup_batch(h, B, insts, phases, tab, st, [&](int b, Inst& I) { I.J_out = J_hist[b]; }))) return rc;
   for (int b = 0; b < nb; ++b) {
     Inst& I = B.insts[b];
     UCP_TRY(hipMemcpyAsync(I.u0, u0_init[b], sizeof(double) * I.n_x, hipMemcpyDeviceToDevice, st), "copy u0_init");
     UCP_TRY(clear_state(I, st), "clear state");
   }
-  // J_out of each instance is its J_hist: set through a second table upload
-  for (int b = 0; b < nb; ++b) B.insts[b].J_out = J_hist[b];
-  UCP_TRY(hipMemcpyAsync(B.d_insts, B.insts.data(), sizeof(Inst) * nb, hipMemcpyHostToDevice, st), "upload instance table");
   if ((rc = run_init(B, 0, tab, prec, st))) return rc;
   for (int t = 1; t <= max_it; ++t)
     if ((rc = run_round(h, B, t, tab, prec, max_lv, t, st))) return rc;
@@ -543,14 +614,15 @@ int ucp_argmin_adaptive(ucp_handle* h, const ucp_problem* prob, const ucp_search
   std::vector<std::vector<char>> phases(1, std::vector<char>(1, 1));
   Batch B;
   std::vector<int32_t> tab;
-  if ((rc = setup_batch(h, B, {make_inst(*prob, search, prec, 0)}, phases, tab, st))) return rc;
+  auto fix = [&](int, Inst& I) {
+    I.L0_out = L0_out;
+    I.terms = nullptr;
+  };
+  if ((rc = setup_batch(h, B, {make_inst(*prob, search, prec, 0)}, phases, tab, st, fix))) return rc;
   Inst& I = B.insts[0];
-  I.L0_out = L0_out;
-  I.terms = nullptr;
   UCP_TRY(hipMemcpyAsync(I.u0, u0_in, sizeof(double) * I.n_x, hipMemcpyDeviceToDevice, st), "copy u0");
   UCP_TRY(hipMemcpyAsync(I.u1, u1, sizeof(double) * I.n_y, hipMemcpyDeviceToDevice, st), "copy u1");
   UCP_TRY(clear_state(I, st), "clear state");
-  UCP_TRY(hipMemcpyAsync(B.d_insts, B.insts.data(), sizeof(Inst), hipMemcpyHostToDevice, st), "upload instance");
   UCP_TRY(launch_prior(B.launch(0, kKindPrior, tab), st), "prior kernel");
   UCP_TRY(launch_gtab(B.launch(0, kKindGtab, tab), st), "offset table kernel");
   UCP_TRY(launch_v_from_u1(B.launch(0, kKindU1c, tab), st), "residual kernel");
@@ -596,11 +668,12 @@ int ucp_objective(ucp_handle* h, const ucp_problem* prob, const double* u0, cons
   std::vector<std::vector<char>> phases(1, std::vector<char>(1, 1));
   Batch B;
   std::vector<int32_t> tab;
-  if ((rc = setup_batch(h, B, {make_inst(*prob, nullptr, UCP_FP64, 1)}, phases, tab, st))) return rc;
+  auto fix = [&](int, Inst& I) {
+    I.J_out = J_out;
+    I.terms = nullptr;
+  };
+  if ((rc = setup_batch(h, B, {make_inst(*prob, nullptr, UCP_FP64, 1)}, phases, tab, st, fix))) return rc;
   Inst& I = B.insts[0];
-  I.J_out = J_out;
-  I.terms = nullptr;
-  UCP_TRY(hipMemcpyAsync(B.d_insts, B.insts.data(), sizeof(Inst), hipMemcpyHostToDevice, st), "upload instance");
   UCP_TRY(hipMemcpyAsync(I.u0, u0, sizeof(double) * I.n_x, hipMemcpyDeviceToDevice, st), "copy u0");
   UCP_TRY(hipMemcpyAsync(I.u1, u1, sizeof(double) * I.n_y, hipMemcpyDeviceToDevice, st), "copy u1");
   UCP_TRY(hipMemsetAsync(I.flags, 0, 128, st), "clear flags");
@@ -626,11 +699,12 @@ int ucp_marginal_cost(ucp_handle* h, const ucp_problem* prob, ucp_prec prec, con
   std::vector<int32_t> tab;
   Inst I0 = make_inst(*prob, nullptr, prec, (int)n_cand);
   I0.free_cands = 1;
-  if ((rc = setup_batch(h, B, {I0}, phases, tab, st))) return rc;
+  auto fix = [&](int, Inst& I) {
+    I.u0 = const_cast<double*>(u);  // the explicit candidates [n_x][n_cand], read only
+    I.terms = nullptr;
+  };
+  if ((rc = setup_batch(h, B, {I0}, phases, tab, st, fix))) return rc;
   Inst& I = B.insts[0];
-  I.u0 = const_cast<double*>(u);  // the explicit candidates [n_x][n_cand], read only
-  I.terms = nullptr;
-  UCP_TRY(hipMemcpyAsync(B.d_insts, B.insts.data(), sizeof(Inst), hipMemcpyHostToDevice, st), "upload instance");
   UCP_TRY(hipMemcpyAsync(I.u1, u1, sizeof(double) * I.n_y, hipMemcpyDeviceToDevice, st), "copy u1");
   UCP_TRY(launch_prior(B.launch(0, kKindPrior, tab), st), "prior kernel");
   UCP_TRY(launch_gtab(B.launch(0, kKindGtab, tab), st), "offset table kernel");

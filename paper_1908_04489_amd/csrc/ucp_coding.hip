@@ -56,6 +56,7 @@ struct CdParams {
   double u_lo, u_hi;
   int levels, cands;
   double h[UCP_MAX_LEVELS];  // candidate spacing per level
+  double tau;                // relative tie band of the selection rule
   int seg_tiles;             // decoder segment length in tiles
   int n_seg;                 // decoder segments
   int n_blk;                 // blocks of the local prefix sums
@@ -390,7 +391,7 @@ __device__ __forceinline__ double level_cand(const CdParams& P, int l, int q, do
 }
 
 // The selection rule as a reduction over a group of G lanes: among the
-// candidates with B within the relative band 1e-12 of the minimum, the
+// candidates with B within the relative band tau of the minimum, the
 // smallest (distance to the incumbent, u, index) wins - the nearest, then
 // the smaller u, then the earlier candidate.  Lanes out of the band carry
 // infinite keys.  Every lane of the group ends with the winner.
@@ -433,7 +434,7 @@ __global__ __launch_bounds__(256) void k_cd_search(CdParams P, Pre S, const doub
     const double B = live ? cd_B(P, S, x, c) : INFINITY;
     double m = group_min<G>(B);
     if (l > 0 && Bs < m) m = Bs;
-    const double thr = m * (1.0 + 1e-12);
+    const double thr = m * (1.0 + P.tau);
     double kd = INFINITY, kc = INFINITY, kB = B;
     int kq = 1 << 30;
     if (live && B <= thr) {
@@ -456,7 +457,7 @@ __global__ __launch_bounds__(256) void k_cd_search(CdParams P, Pre S, const doub
   const double Binc = cd_B(P, S, x, uinc);
   double m = Bs;
   if (Binc < m) m = Binc;
-  const double thr = m * (1.0 + 1e-12);
+  const double thr = m * (1.0 + P.tau);
   double rc = cs, rB = Bs;
   const bool win_in = Bs <= thr;
   if (Binc <= thr) {
@@ -555,6 +556,7 @@ int cd_params(const ucp_coding_problem* p, const ucp_search* s, CdParams& P) {
   P.y_lo = p->y_lo;
   P.dy = (p->y_hi - p->y_lo) / (double)(p->n_y - 1);
   P.inv_dy = 1.0 / P.dy;
+  P.tau = tie_band(s);
   if (s) {
     P.u_lo = s->u_lo;
     P.u_hi = s->u_hi;

@@ -941,14 +941,14 @@ __device__ __forceinline__ double grp_min_d(double v) {
 }
 
 // The selection rule on FP64 values among the lanes with `member`: ties
-// within kTau64 of the minimum, the one nearest the incumbent wins, then the
+// within tau64 of the minimum, the one nearest the incumbent wins, then the
 // smaller u, then the lower lane.  Returns the group lane (0 if there is
 // none).
 template <int W>
-__device__ int tie_rule(bool member, double c, double Bf, double uinc, int lane) {
+__device__ int tie_rule(bool member, double c, double Bf, double uinc, int lane, double tau64) {
   const double big = INFINITY;
   const double m = grp_min_d<W>(member ? Bf : big);
-  const bool band = member && Bf <= m * (1.0 + kTau64);
+  const bool band = member && Bf <= m * (1.0 + tau64);
   double k1 = band ? fabs(c - uinc) : big;
   double k2 = band ? c : big;
   int k3 = band ? lane : INT_MAX;
@@ -966,11 +966,10 @@ __device__ int tie_rule(bool member, double c, double Bf, double uinc, int lane)
 // kappa sqrt(m) the rounding of z - u1 (|dB| grows like sqrt(B)).  Returns
 // the member mask over the group (0 when no candidate is finite).
 template <int W>
-__device__ unsigned long long band32(bool in_set, double B32, int prec) {
+__device__ unsigned long long band32(bool in_set, double B32, double tau) {
   const bool fin = in_set && isfinite(B32);
   const double m32 = grp_min_d<W>(fin ? B32 : INFINITY);
   if (!(m32 < INFINITY)) return 0ull;
-  const double tau = prec == UCP_FP32_KAHAN ? kTau32Kahan : kTau32Plain;
   return grp_ballot<W>(fin && B32 <= m32 * (1.0 + tau) + kKappa32 * sqrt(m32));
 }
 
@@ -1022,10 +1021,9 @@ __device__ __forceinline__ double inc_from_set(bool in_set, double c, double B64
 }
 
 // Whether the FP32 band of the pair {b0, b1} (as band32 forms it) holds both.
-__device__ __forceinline__ bool pair_band_both(double b0, double b1, int prec) {
+__device__ __forceinline__ bool pair_band_both(double b0, double b1, double tau) {
   if (!isfinite(b0) || !isfinite(b1)) return false;
   const double m = fmin(b0, b1);
-  const double tau = prec == UCP_FP32_KAHAN ? kTau32Kahan : kTau32Plain;
   const double lim = m * (1.0 + tau) + kKappa32 * sqrt(m);
   return b0 <= lim && b1 <= lim;
 }
@@ -1058,12 +1056,12 @@ __device__ void accept(const Inst& I, int i, double x, double uinc, double cw, d
   double b64 = lane == 0 ? B64w : (PREC == UCP_FP64 ? B32i : B64i);
   if (PREC == UCP_FP64) {
     const bool fin = in2 && isfinite(b32);
-    const int w = tie_rule<W>(fin, c2, b32, uinc, lane);
+    const int w = tie_rule<W>(fin, c2, b32, uinc, lane, I.tau64);
     if (grp_ballot<W>(fin) == 0ull && lane == 0) atomicOr(I.flags, 1);
     finish_point<W>(I, i, grp_shfl<W>(c2, w), grp_shfl<W>(b64, w), x, lane, want_l0);
     return;
   }
-  const unsigned long long mask = band32<W>(in2, b32, PREC);
+  const unsigned long long mask = band32<W>(in2, b32, I.tau32);
   if (mask == 0ull) {
     if (lane == 0) atomicOr(I.flags, 1);
     finish_point<W>(I, i, uinc, NAN, x, lane, want_l0);
@@ -1096,7 +1094,7 @@ __device__ void accept(const Inst& I, int i, double x, double uinc, double cw, d
     if (lane == L) b64 = v;
     ++n_eval;
   }
-  const int w = tie_rule<W>(in2, c2, b64, uinc, lane);
+  const int w = tie_rule<W>(in2, c2, b64, uinc, lane, I.tau64);
   finish_point<W>(I, i, grp_shfl<W>(c2, w), grp_shfl<W>(b64, w), x, lane, want_l0);
 }
 
@@ -1115,9 +1113,9 @@ __device__ void band_point(const Inst& I, int level, int i, int lane, int want_l
   if (PREC == UCP_FP64) {
     const bool fin = in_set && isfinite(B32);
     if (grp_ballot<W>(fin) == 0ull && lane == 0) atomicOr(I.flags, 1);
-    w = tie_rule<W>(fin, c, B32, uinc, lane);
+    w = tie_rule<W>(fin, c, B32, uinc, lane, I.tau64);
   } else {
-    const unsigned long long mask = band32<W>(in_set, B32, PREC);
+    const unsigned long long mask = band32<W>(in_set, B32, I.tau32);
     if (mask == 0ull) {
       if (lane == 0) atomicOr(I.flags, 1);
       w = 0;
@@ -1137,7 +1135,7 @@ __device__ void band_point(const Inst& I, int level, int i, int lane, int want_l
         // FP64 value as a member.)
         if (level == I.levels - 1 && K + 1 < W && !grp_ballot<W>(member && c == uinc)) {
           const double b32i = I.b32inc[i];
-          if (grp_ballot<W>(member && pair_band_both(B32, b32i, PREC))) {
+          if (grp_ballot<W>(member && pair_band_both(B32, b32i, I.tau32))) {
             Q.todo |= 1ull << (K + 1);
             Q.kind = 3;
             if (lane == K + 1) Q.c = uinc;
@@ -1145,7 +1143,7 @@ __device__ void band_point(const Inst& I, int level, int i, int lane, int want_l
         }
         return;
       }
-      w = tie_rule<W>(member, c, B64, uinc, lane);
+      w = tie_rule<W>(member, c, B64, uinc, lane, I.tau64);
     }
   }
   const double cw = grp_shfl<W>(c, w), B32w = grp_shfl<W>(B32, w), B64w = grp_shfl<W>(B64, w);
@@ -1168,10 +1166,10 @@ __device__ void resolve_point(const Inst& I, int level, int i, int lane, int wan
   const double uinc = I.u0[i];
   const double x = I.x_lo + (double)i * I.dx;
   if (kind != 2) {
-    const unsigned long long mask = band32<W>(in_set, B32, PREC);
+    const unsigned long long mask = band32<W>(in_set, B32, I.tau32);
     const bool member = (mask >> lane) & 1ull;
     if (member && isnan(B64)) B64 = qv;
-    const int w = tie_rule<W>(member, c, B64, uinc, lane);
+    const int w = tie_rule<W>(member, c, B64, uinc, lane, I.tau64);
     const double cw = grp_shfl<W>(c, w), B32w = grp_shfl<W>(B32, w), B64w = grp_shfl<W>(B64, w);
     if (lane == 0) {
       I.cbest[i] = cw;
@@ -1191,9 +1189,9 @@ __device__ void resolve_point(const Inst& I, int level, int i, int lane, int wan
     const double c2 = lane == 0 ? cw : uinc;
     const double b32 = lane == 0 ? I.b32best[i] : I.b32inc[i];
     const double b64 = lane == 0 ? (isnan(B64w) ? qv : B64w) : qv;
-    const unsigned long long mask = band32<W>(in2, b32, PREC);
+    const unsigned long long mask = band32<W>(in2, b32, I.tau32);
     const bool member = (mask >> lane) & 1ull;
-    const int w = tie_rule<W>(member, c2, b64, uinc, lane);
+    const int w = tie_rule<W>(member, c2, b64, uinc, lane, I.tau64);
     finish_point<W>(I, i, grp_shfl<W>(c2, w), grp_shfl<W>(b64, w), x, lane, want_l0);
   }
 }

@@ -29,6 +29,8 @@ int fail(int code, const char* fmt, ...);
 int hip_fail(hipError_t e, const char* what);
 int check_problem(const ucp_problem* p);
 int check_search(const ucp_search* s);
+// relative tie band of the selection rule: the search's, or the default
+double tie_band(const ucp_search* s);
 int check_prec(int prec);
 Inst make_inst(const ucp_problem& p, const ucp_search* s, int prec, int cands_override);
 size_t state_bytes(const Inst& I);

@@ -66,6 +66,10 @@ struct ucp_server {
   Inst* d_insts = nullptr;
   int32_t* d_tab = nullptr;
   size_t cap_insts = 0, cap_tab = 0;
+  // pinned host staging of the tables: a step ends by synchronising the
+  // stream, so the next step may overwrite it
+  char* h_stage = nullptr;
+  size_t cap_stage = 0;
 };
 
 static size_t footprint(const Inst& I, int32_t iters) {
@@ -154,6 +158,7 @@ void ucp_server_destroy(ucp_server* s) {
   drain_pool(s);
   if (s->d_insts) (void)hipFree(s->d_insts);
   if (s->d_tab) (void)hipFree(s->d_tab);
+  if (s->h_stage) (void)hipHostFree(s->h_stage);
   (void)hipStreamDestroy(s->stream);
   delete s;
 }
@@ -296,10 +301,20 @@ static int upload_tables(ucp_server* s, const std::vector<char>& fresh, const st
     SRV_TRY(hipMalloc(&s->d_tab, need_t * 2), "allocate launch tables");
     s->cap_tab = need_t * 2;
   }
-  SRV_TRY(hipMemcpyAsync(s->d_insts, insts.data(), sizeof(Inst) * n, hipMemcpyHostToDevice, s->stream), "upload");
-  SRV_TRY(hipMemcpyAsync(s->d_insts + n, insts_round.data(), sizeof(Inst) * n, hipMemcpyHostToDevice, s->stream),
-          "upload");
-  SRV_TRY(hipMemcpyAsync(s->d_tab, tab.data(), need_t, hipMemcpyHostToDevice, s->stream), "upload");
+  // a step that failed part-way may have left uploads in flight
+  SRV_TRY(hipStreamSynchronize(s->stream), "synchronise before staging");
+  if (need_i + need_t > s->cap_stage) {
+    if (s->h_stage) (void)hipHostFree(s->h_stage);
+    s->h_stage = nullptr;
+    s->cap_stage = 0;
+    SRV_TRY(hipHostMalloc((void**)&s->h_stage, 2 * (need_i + need_t), hipHostMallocDefault), "allocate staging");
+    s->cap_stage = 2 * (need_i + need_t);
+  }
+  std::memcpy(s->h_stage, insts.data(), sizeof(Inst) * n);
+  std::memcpy(s->h_stage + sizeof(Inst) * n, insts_round.data(), sizeof(Inst) * n);
+  std::memcpy(s->h_stage + need_i, tab.data(), need_t);
+  SRV_TRY(hipMemcpyAsync(s->d_insts, s->h_stage, need_i, hipMemcpyHostToDevice, s->stream), "upload");
+  SRV_TRY(hipMemcpyAsync(s->d_tab, s->h_stage + need_i, need_t, hipMemcpyHostToDevice, s->stream), "upload");
   return UCP_OK;
 }
 

@@ -1,4 +1,4 @@
-// Two-dimensional Witsenhausen counterexample (Section V-E) on the device,
+// Two-dimensional Witsenhausen counterexample (Section V-D) on the device,
 // FP64: x0 in R^2 with independent coordinates from the prior, x1 = x0 + u0,
 // y1 = x1 + w with w ~ N(0, I_2), x2 = x1 - u1(y1),
 // J = 1/2 E[k^2 |u0|^2 + |x2|^2], on tensor-product grids (node (i1, i2) at
@@ -44,6 +44,7 @@ struct W2Params {
   double u_lo, u_hi;
   int levels, cands;
   double h[UCP_MAX_LEVELS];
+  double tau;          // relative tie band of the selection rule
   int seg_len, n_seg;  // u1 sums: x nodes per segment, segments
 };
 
@@ -242,7 +243,7 @@ __global__ __launch_bounds__(64) void k_w2_search(W2Params P, const double* __re
     double m = B;
     for (int o = 32; o > 0; o >>= 1) m = fmin(m, __shfl_xor(m, o));
     if (l > 0 && sB < m) m = sB;
-    const double thr = m * (1.0 + 1e-12);
+    const double thr = m * (1.0 + P.tau);
     double kd = INFINITY, ka = INFINITY, kb = INFINITY, kB = B;
     int kq = 1 << 30;
     if (live && B <= thr) {
@@ -272,7 +273,7 @@ __global__ __launch_bounds__(64) void k_w2_search(W2Params P, const double* __re
   const double Bi = Bi8[0];
   double m = sB;
   if (Bi < m) m = Bi;
-  const double thr = m * (1.0 + 1e-12);
+  const double thr = m * (1.0 + P.tau);
   double ra = sa, rb = sb, rB = sB;
   if (Bi <= thr) {
     const double da = sa - ia, db = sb - ib;
@@ -425,6 +426,7 @@ int w2_params(const ucp_problem* p, const ucp_search* s, W2Params& P) {
     if (s->cands > 8) return fail(UCP_EINVAL, "2-D search takes at most 8 x 8 candidates per level");
   }
   std::memset(&P, 0, sizeof P);
+  P.tau = tie_band(s);
   P.k = p->k;
   P.n_comp = p->n_comp;
   P.n = (int)p->n_x;

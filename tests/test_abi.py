@@ -50,14 +50,15 @@ def test_version_and_error_codes(U):
 def test_struct_layout_matches_header(U):
     # ucp_problem: k, n_comp, pad, 3 x 8 doubles, x range + n, y range + n
     assert C.sizeof(U.Problem) == 8 + 4 + 4 + 3 * 8 * 8 + 8 + 8 + 8 + 8 + 8 + 8
-    assert C.sizeof(U.Search) == 8 + 8 + 4 + 4
+    # ucp_search: range, levels, cands, tie_rel64, band_rel32
+    assert C.sizeof(U.Search) == 8 + 8 + 4 + 4 + 8 + 8
 
 
 def test_create_without_device_or_with_null(U):
     lib = U.library()
-    assert lib.ucp_create(None, 0) == U.EINVAL
+    assert lib.ucp_create(None, 0, 0) == U.EINVAL
     h = C.c_void_p()
-    rc = lib.ucp_create(C.byref(h), 0)
+    rc = lib.ucp_create(C.byref(h), 0, 0)
     assert rc in (U.EHIP, U.OK)  # no GPU in this container: EHIP
     if rc == U.OK:
         lib.ucp_destroy(h)
@@ -105,7 +106,10 @@ def test_invalid_problem_rejected_before_device_use(U):
     P = U.make_problem(good)
     # bad search / precision / null arrays / null handle
     for s in [W.Search(30, -30, 3, 21), W.Search(-30, 30, 0, 21), W.Search(-30, 30, 3, 1),
-              W.Search(-30, 30, 17, 21), W.Search(-30, 30, 3, 64)]:
+              W.Search(-30, 30, 17, 21), W.Search(-30, 30, 3, 64),
+              W.Search(-30, 30, 3, 21, tie_rel64=-1e-12), W.Search(-30, 30, 3, 21, tie_rel64=float("nan")),
+              W.Search(-30, 30, 3, 21, tie_rel64=1e-2), W.Search(-30, 30, 3, 21, band_rel32=-1e-7),
+              W.Search(-30, 30, 3, 21, band_rel32=0.5)]:
         S2 = U.make_search(s)
         assert lib.ucp_argmin_adaptive(fake, C.byref(P), C.byref(S2), 1, C.c_void_p(8), C.c_void_p(8),
                                        C.c_void_p(8), None, None) == U.EINVAL

@@ -379,3 +379,24 @@ def test_against_mpmath_two_round_solve(orc):
     for a, b in zip(Jm, J):
         assert abs(float(a) - b) <= 1e-13 * b
     assert float(Jm[2]) < float(Jm[0])
+
+
+def test_argmin_tie_band_parameter(orc):
+    """The selection rule's relative tie band comes from the search record.
+    With u1 = a y, B(u; 0) = (k^2 + (1-a)^2) u^2 + a^2 in closed form, so an
+    incumbent at u = d costs a relative delta = (k^2 + (1-a)^2) d^2 / a^2
+    more than the minimum u = 0 (a level-0 node).  A band wider than delta
+    keeps the incumbent; the default band or one narrower than delta moves
+    the point to 0.  Catches a band that ignores the parameter, and one
+    applied to the absolute instead of the relative gap."""
+    p = wide(n=101, half=10.0, n_y=1601, y_half=40.0)
+    y = orc.grid(p.y_lo, p.y_hi, p.n_y)
+    a, d = 0.5, 0.01
+    delta = (K * K + (1 - a) ** 2) * d * d / (a * a)
+    mid = p.n_x // 2
+    u0 = np.full(p.n_x, d)
+    for tau, expect in ((0.0, 0.0), (0.5 * delta, 0.0), (2.0 * delta, d)):
+        s = W.Search(-2.0, 2.0, 1, 11, tie_rel64=tau)
+        out, B = orc.argmin(p, s, a * y, u0, rows=[mid])
+        assert out[0] == expect, (tau, out[0])
+        assert abs(B[0] - (K * K + (1 - a) ** 2) * expect ** 2 - a * a) < 1e-12

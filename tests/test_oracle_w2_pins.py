@@ -1,5 +1,5 @@
 """Pins of the oracle's two-dimensional Witsenhausen functions (Section
-V-E) against the one-dimensional oracle, which the other CPU tests pin to
+V-D) against the one-dimensional oracle, which the other CPU tests pin to
 closed forms.  With a separable controller and independent coordinates the
 2-D sums factor into 1-D ones: J_2D = J_1D * Mx with Mx = dx sum f (the
 prior's mass on the grid), and B_2D is the mean of the two 1-D costs with

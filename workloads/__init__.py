@@ -39,6 +39,8 @@ class Search:
     u_hi: float
     levels: int
     cands: int
+    tie_rel64: float = 0.0   # relative tie band of the selection rule (0: the default 1e-12)
+    band_rel32: float = 0.0  # FP32 pre-selection band of the GPU path (0: its default)
 
 
 @dataclass
@@ -221,7 +223,7 @@ def coding_paper_case(n: int = 20001, iters: int = 30) -> CodingCase:
     return CodingCase(f"coding-{n}-5x16", p, Search(-4.0, 4.0, 5, 16), iters, coding_init(p, 0))
 
 
-# --- two-dimensional Witsenhausen (Section V-E) -----------------------------
+# --- two-dimensional Witsenhausen (Section V-D) -----------------------------
 # x0 in R^2 with both coordinates drawn from the same prior, w ~ N(0, I_2),
 # J = 1/2 E[k^2 |u0|^2 + |x2|^2]; the paper runs k = 0.2, sigma = 5 on
 # 160 x 160 nodes.  Vector fields are arrays [2, n * n], node (i1, i2) at
