@@ -1,4 +1,4 @@
-"""GPU parity of the two-dimensional Witsenhausen calls (Section V-E)
+"""GPU parity of the two-dimensional Witsenhausen calls (Section V-D)
 against the FP64 oracle, on identical seeded inputs.
 
 Tolerances: both sides FP64; the GPU's search sums the noise over a window
