@@ -13,7 +13,8 @@ brute force for tiny grids.
 Problem objects are duck-typed: any object with ``k`` (``lam`` for the
 coding problem of Section V-B, the ``coding_*`` functions), ``comps`` (a sequence
 of ``(weight, mean, sd)`` for the Gaussian-mixture prior of x0), ``x_lo``,
-``x_hi``, ``n_x``, ``y_lo``, ``y_hi``, ``n_y``.  Search objects need
+``x_hi``, ``n_x``, ``y_lo``, ``y_hi``, ``n_y`` and optionally ``noise_sd`` (the
+standard deviation of the Gaussian noise, 1 by default).  Search objects need
 ``u_lo``, ``u_hi``, ``levels``, ``cands`` and may carry ``tie_rel64`` (the
 relative tie band of the selection rule, 0 = 1e-12).
 """
@@ -46,6 +47,7 @@ class _Problem(C.Structure):
         ("y_lo", C.c_double),
         ("y_hi", C.c_double),
         ("n_y", C.c_int64),
+        ("noise_sd", C.c_double),
     ]
 
 
@@ -130,6 +132,7 @@ def _prob(p) -> _Problem:
         s.w[c], s.mu[c], s.sd[c] = float(w), float(mu), float(sd)
     s.x_lo, s.x_hi, s.n_x = float(p.x_lo), float(p.x_hi), int(p.n_x)
     s.y_lo, s.y_hi, s.n_y = float(p.y_lo), float(p.y_hi), int(p.n_y)
+    s.noise_sd = float(getattr(p, "noise_sd", 1.0))
     return s
 
 

@@ -38,7 +38,10 @@
 #define ORC_TAU64 1e-12 /* relative tie band of the selection rule, unless the search sets one */
 
 /* Problem description: stage-1 weight k, a Gaussian-mixture prior for x0
- * (one component = the paper's N(0, sigma^2)), and the two grids. */
+ * (one component = the paper's N(0, sigma^2)), the two grids, and the
+ * standard deviation of the Gaussian noise w (Section V-A fixes 1; 0 also
+ * selects 1).  The coding and two-dimensional problems below have noises
+ * of their own and ignore noise_sd. */
 typedef struct {
   double k;
   int32_t n_comp;
@@ -50,7 +53,10 @@ typedef struct {
   int64_t n_x;
   double y_lo, y_hi;
   int64_t n_y;
+  double noise_sd;
 } orc_problem;
+
+static double orc_noise_sd(const orc_problem* p) { return p->noise_sd > 0.0 ? p->noise_sd : 1.0; }
 
 /* Coarse-to-fine search settings for the u0 update.  tie_rel64 is the
  * relative tie band of the selection rule (0 selects ORC_TAU64);
@@ -112,6 +118,12 @@ void orc_prior(const orc_problem* p, double* f, double* logf) {
 /* Noise density phi(t) of w ~ N(0,1) (Section V-A). */
 static double orc_phi(double t) { return exp(-0.5 * t * t) / sqrt(2.0 * ORC_PI); }
 
+/* Density of w ~ N(0, s^2). */
+static double orc_phi_s(double t, double s) {
+  double u = t / s;
+  return exp(-0.5 * u * u) / (s * sqrt(2.0 * ORC_PI));
+}
+
 /* B(u; x) = L_0(u, x) / f(x): the marginal cost of the first controller
  * at the point x0 = x with u0(x) = u, divided by the prior density.
  * Marginal cost C_0 (Section III-A, definition of C_m) applied to the
@@ -119,12 +131,13 @@ static double orc_phi(double t) { return exp(-0.5 * t * t) / sqrt(2.0 * ORC_PI);
  * phi(y - x - u) (x + u - u1(y))^2, by the rectangle rule on the y grid. */
 double orc_B(const orc_problem* p, const double* u1, double x, double u) {
   double dy = (p->y_hi - p->y_lo) / (double)(p->n_y - 1);
+  double sw = orc_noise_sd(p);
   double z = x + u;
   double s = 0.0;
   for (int64_t j = 0; j < p->n_y; ++j) {
     double y = orc_node(p->y_lo, p->y_hi, p->n_y, j);
     double e = z - u1[j];
-    s += orc_phi(y - z) * e * e;
+    s += orc_phi_s(y - z, sw) * e * e;
   }
   return p->k * p->k * u * u + dy * s;
 }
@@ -296,6 +309,7 @@ void orc_update_u1(const orc_problem* p, const double* u0, const int64_t* rows,
   double* x1 = (double*)malloc(sizeof(double) * (size_t)p->n_x);
   orc_prior(p, NULL, logf);
   for (int64_t i = 0; i < p->n_x; ++i) x1[i] = orc_node(p->x_lo, p->x_hi, p->n_x, i) + u0[i];
+  const double sw = orc_noise_sd(p);
   int64_t n = rows ? n_rows : p->n_y;
 #pragma omp parallel for schedule(static)
   for (int64_t r = 0; r < n; ++r) {
@@ -303,13 +317,13 @@ void orc_update_u1(const orc_problem* p, const double* u0, const int64_t* rows,
     double y = orc_node(p->y_lo, p->y_hi, p->n_y, j);
     double M = -INFINITY;
     for (int64_t i = 0; i < p->n_x; ++i) {
-      double d = y - x1[i];
+      double d = (y - x1[i]) / sw;
       double l = logf[i] - 0.5 * d * d;
       if (l > M) M = l;
     }
     double num = 0.0, den = 0.0;
     for (int64_t i = 0; i < p->n_x; ++i) {
-      double d = y - x1[i];
+      double d = (y - x1[i]) / sw;
       double e = exp(logf[i] - 0.5 * d * d - M);
       num += x1[i] * e;
       den += e;
@@ -325,6 +339,7 @@ void orc_update_u1(const orc_problem* p, const double* u0, const int64_t* rows,
 double orc_objective(const orc_problem* p, const double* u0, const double* u1) {
   double dx = (p->x_hi - p->x_lo) / (double)(p->n_x - 1);
   double dy = (p->y_hi - p->y_lo) / (double)(p->n_y - 1);
+  const double sw = orc_noise_sd(p);
   double* f = (double*)malloc(sizeof(double) * (size_t)p->n_x);
   double* row = (double*)malloc(sizeof(double) * (size_t)p->n_x);
   orc_prior(p, f, NULL);
@@ -335,7 +350,7 @@ double orc_objective(const orc_problem* p, const double* u0, const double* u1) {
     for (int64_t j = 0; j < p->n_y; ++j) {
       double y = orc_node(p->y_lo, p->y_hi, p->n_y, j);
       double e = x1 - u1[j];
-      s += orc_phi(y - x1) * e * e;
+      s += orc_phi_s(y - x1, sw) * e * e;
     }
     row[i] = f[i] * (p->k * p->k * u0[i] * u0[i] + dy * s);
   }

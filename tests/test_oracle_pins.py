@@ -400,3 +400,47 @@ def test_argmin_tie_band_parameter(orc):
         out, B = orc.argmin(p, s, a * y, u0, rows=[mid])
         assert out[0] == expect, (tau, out[0])
         assert abs(B[0] - (K * K + (1 - a) ** 2) * expect ** 2 - a * a) < 1e-12
+
+
+# ------------------------------------------------ noise standard deviation
+
+@pytest.mark.parametrize("sw", [0.5, 2.0])
+def test_noise_sd_closed_forms(orc, sw):
+    """w ~ N(0, sw^2).  With u1 = a y, B(u; x) = k^2 u^2 + (1-a)^2 z^2 + a^2 sw^2
+    (z = x + u); affine u0 = (lam - 1) x gives u1 = lam^2 s^2 / (lam^2 s^2 + sw^2) y
+    and J = k^2 (lam - 1)^2 s^2 + lam^2 s^2 sw^2 / (lam^2 s^2 + sw^2).  Catches
+    a missing 1/sw in the density, the noise variance left at 1 in the
+    exponent of the u1 weights, and sw in place of sw^2."""
+    p = wide(n=4801, half=60.0)
+    p.noise_sd = sw
+    y = orc.grid(p.y_lo, p.y_hi, p.n_y)
+    for a, x, u in ((0.3, 1.7, -0.4), (0.8, -3.0, 2.5)):
+        z = x + u
+        ref = K * K * u * u + (1 - a) ** 2 * z * z + a * a * sw * sw
+        assert abs(orc.B(p, a * y, x, u) - ref) <= 1e-12 * ref
+    for lam in (0.3, 1.0):
+        u0 = W.init_affine(p, lam)
+        u1 = orc.update_u1(p, u0)
+        g = lam ** 2 * SIGMA ** 2 / (lam ** 2 * SIGMA ** 2 + sw * sw)
+        inner = np.abs(y) < 12  # x1 spans [-18, 18] at lam = 0.3: stay clear of its ends
+        assert np.max(np.abs(u1[inner] - g * y[inner])) < 1e-9
+        J = orc.objective(p, u0, g * y)
+        ref = K * K * (lam - 1) ** 2 * SIGMA ** 2 + lam ** 2 * SIGMA ** 2 * sw * sw / (lam ** 2 * SIGMA ** 2 + sw * sw)
+        assert abs(J - ref) <= 1e-10 * ref
+
+
+def test_noise_sd_scaling_is_exact(orc):
+    """Doubling every length (grids, prior, search range) and the noise sd
+    scales the discrete problem exactly: positions double, B and J
+    quadruple, in binary64.  Two whole rounds of the solve loop must show it
+    bit for bit."""
+    c = W.small_case()
+    p1, s1 = c.prob, c.search
+    p2 = W.Problem(k=p1.k, comps=[(1.0, 0.0, 10.0)], x_lo=-50.0, x_hi=50.0, n_x=p1.n_x, y_lo=-50.0, y_hi=50.0,
+                   n_y=p1.n_y, noise_sd=2.0)
+    s2 = W.Search(2 * s1.u_lo, 2 * s1.u_hi, s1.levels, s1.cands)
+    a0, a1, Ja = orc.solve(p1, s1, 2, c.u0_init)
+    b0, b1, Jb = orc.solve(p2, s2, 2, 2.0 * c.u0_init)
+    assert np.array_equal(b0, 2.0 * a0)
+    assert np.max(np.abs(b1 - 2.0 * a1)) <= 1e-13 * np.max(np.abs(b1))
+    assert np.max(np.abs(Jb - 4.0 * Ja) / Jb) <= 1e-14

@@ -31,6 +31,7 @@ class Problem:
     y_lo: float
     y_hi: float
     n_y: int
+    noise_sd: float = 1.0  # standard deviation of the Gaussian noise w (Section V-A: 1)
 
 
 @dataclass
