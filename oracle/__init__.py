@@ -62,6 +62,18 @@ class _Search(C.Structure):
     ]
 
 
+class _Alg1(C.Structure):
+    _fields_ = [
+        ("N", C.c_int32),
+        ("r", C.c_int32),
+        ("p", C.c_double),
+        ("tau", C.c_double),
+        ("tie_rel64", C.c_double),
+        ("max_rounds", C.c_int32),
+        ("pad_", C.c_int32),
+    ]
+
+
 def build(force: bool = True) -> str:
     """Compile the oracle into ``oracle/_ucp_oracle.so`` (gcc, OpenMP)."""
     if force or not os.path.exists(_LIB):
@@ -86,6 +98,7 @@ def lib():
         P = C.POINTER
         dp = P(C.c_double)
         ip = P(C.c_int64)
+        D = C.c_double
         L.orc_num_threads.restype = C.c_int
         L.orc_grid.argtypes = [C.c_double, C.c_double, C.c_int64, dp]
         L.orc_prior.argtypes = [P(_Problem), dp, dp]
@@ -97,10 +110,17 @@ def lib():
         L.orc_argmin_visits.argtypes = [P(_Problem), P(_Search), dp, dp, ip, C.c_int64, dp, dp]
         L.orc_set_threads.argtypes = [C.c_int]
         L.orc_update_u1.argtypes = [P(_Problem), dp, ip, C.c_int64, dp]
+        L.orc_B_derivs.argtypes = [P(_Problem), dp, D, D, dp, dp, dp]
+        L.orc_alg1_local_u0.argtypes = [P(_Problem), D, dp, dp, ip, C.c_int64, dp]
+        L.orc_alg1_local_u1.argtypes = [P(_Problem), dp, dp, ip, C.c_int64, dp]
+        L.orc_alg1_pe_u0.argtypes = [P(_Problem), D, C.c_int32, dp, dp, ip, C.c_int64, dp]
+        L.orc_alg1_pe_u1.argtypes = [P(_Problem), D, C.c_int32, dp, dp, ip, C.c_int64, dp]
+        L.orc_alg1_allocate.argtypes = [C.c_int32, D, D, P(C.c_int32), P(C.c_int32)]
+        L.orc_alg1_solve.argtypes = [P(_Problem), P(_Alg1), dp, dp, dp, dp, dp, P(C.c_int32)]
+        L.orc_alg1_solve.restype = C.c_int32
         L.orc_objective.argtypes = [P(_Problem), dp, dp]
         L.orc_objective.restype = C.c_double
         L.orc_solve.argtypes = [P(_Problem), P(_Search), C.c_int32, dp, dp, dp, dp]
-        D = C.c_double
         L.orc_cd_B.argtypes = [P(_Problem), D, dp, D, D]
         L.orc_cd_B.restype = D
         L.orc_cd_marginal_cost.argtypes = [P(_Problem), D, dp, dp, C.c_int64, dp]
@@ -397,3 +417,79 @@ def w2_solve(p, s, iters: int, u0_init):
     J = np.empty(int(iters) + 1, np.float64)
     lib().orc2_solve(C.byref(_prob(p)), C.byref(_search(s)), int(iters), _dp(u0_init), _dp(u0), _dp(u1), _dp(J))
     return u0, u1, J
+
+
+# ---------------------------------------------------------------------------
+# The paper's generic solver (Algorithm 1) on the Witsenhausen instance.
+
+def B_derivs(p, u1, x: float, u: float):
+    """(B, dB/du, d2B/du2) at one point."""
+    u1 = _f64(u1, int(p.n_y))
+    out = [C.c_double(), C.c_double(), C.c_double()]
+    lib().orc_B_derivs(C.byref(_prob(p)), _dp(u1), float(x), float(u), *[C.byref(o) for o in out])
+    return tuple(o.value for o in out)
+
+
+def _rows_ptr(rows, n):
+    n, r = _rows(rows, n)
+    return n, (r.ctypes.data_as(C.POINTER(C.c_int64)) if r is not None else None)
+
+
+def alg1_local_u0(p, tau, u1, u0, rows=None):
+    u1, u0 = _f64(u1, int(p.n_y)), _f64(u0, int(p.n_x))
+    n, rp = _rows_ptr(rows, int(p.n_x))
+    out = np.empty(n, np.float64)
+    lib().orc_alg1_local_u0(C.byref(_prob(p)), float(tau), _dp(u1), _dp(u0), rp, n, _dp(out))
+    return out
+
+
+def alg1_local_u1(p, u0, u1, rows=None):
+    u0, u1 = _f64(u0, int(p.n_x)), _f64(u1, int(p.n_y))
+    n, rp = _rows_ptr(rows, int(p.n_y))
+    out = np.empty(n, np.float64)
+    lib().orc_alg1_local_u1(C.byref(_prob(p)), _dp(u0), _dp(u1), rp, n, _dp(out))
+    return out
+
+
+def _radius(r):
+    r = int(r)
+    if not 1 <= r <= 31:
+        raise ValueError("radius must be 1..31")
+    return r
+
+
+def alg1_pe_u0(p, u1, u0, r=2, tie=0.0, rows=None):
+    u1, u0 = _f64(u1, int(p.n_y)), _f64(u0, int(p.n_x))
+    n, rp = _rows_ptr(rows, int(p.n_x))
+    out = np.empty(n, np.float64)
+    lib().orc_alg1_pe_u0(C.byref(_prob(p)), float(tie or TAU64), _radius(r), _dp(u1), _dp(u0), rp, n, _dp(out))
+    return out
+
+
+def alg1_pe_u1(p, u0, u1, r=2, tie=0.0, rows=None):
+    u0, u1 = _f64(u0, int(p.n_x)), _f64(u1, int(p.n_y))
+    n, rp = _rows_ptr(rows, int(p.n_y))
+    out = np.empty(n, np.float64)
+    lib().orc_alg1_pe_u1(C.byref(_prob(p)), float(tie or TAU64), _radius(r), _dp(u0), _dp(u1), rp, n, _dp(out))
+    return out
+
+
+def alg1_allocate(N, IL, IP, NL_prev):
+    nl, npp = C.c_int32(int(NL_prev)), C.c_int32()
+    lib().orc_alg1_allocate(int(N), float(IL), float(IP), C.byref(nl), C.byref(npp))
+    return nl.value, npp.value
+
+
+def alg1_solve(p, u0_init, u1_init, N=20, r=2, prec=1e-10, tau=0.1, tie=0.0, max_rounds=100):
+    """Returns (u0, u1, J_log[1 + 2 rounds], NL_log[rounds])."""
+    u0_init, u1_init = _f64(u0_init, int(p.n_x)), _f64(u1_init, int(p.n_y))
+    a = _Alg1()
+    a.N, a.r, a.p, a.tau, a.tie_rel64, a.max_rounds = int(N), _radius(r), float(prec), float(tau), float(tie), \
+        int(max_rounds)
+    u0 = np.empty(int(p.n_x), np.float64)
+    u1 = np.empty(int(p.n_y), np.float64)
+    J = np.empty(1 + 2 * int(max_rounds), np.float64)
+    NL = np.empty(max(1, int(max_rounds)), np.int32)
+    rounds = lib().orc_alg1_solve(C.byref(_prob(p)), C.byref(a), _dp(u0_init), _dp(u1_init), _dp(u0), _dp(u1),
+                                  _dp(J), NL.ctypes.data_as(C.POINTER(C.c_int32)))
+    return u0, u1, J[:1 + 2 * rounds], NL[:rounds]

@@ -144,3 +144,63 @@ def solve(p, s, iters, u0_init):
             u1 = u1_update(p, u0)
             J.append(objective(p, u0, u1))
         return u0, u1, J
+
+
+# --- the generic solver's steps (Algorithm 1), at 40 digits ----------------
+
+def _B_at(p, ys, u1m, x, u):
+    return _Bfun(p, ys, u1m, x, u)
+
+
+def alg1_local_u0(p, tau, u1, u0):
+    """One local update of u0: u - B'/B'' where B'' > 0, else u - tau B', with
+    B' and B'' from mpmath's numerical differentiation of the 40-digit B
+    (independent of the closed-form derivatives)."""
+    with mp.workdps(DPS):
+        xs = _nodes(p.x_lo, p.x_hi, p.n_x)
+        ys = _nodes(p.y_lo, p.y_hi, p.n_y)
+        u1m = [_mpv(v) for v in u1]
+        out = []
+        for x, u in zip(xs, u0):
+            u = mp.mpf(float(u))
+            fn = lambda v: _B_at(p, ys, u1m, x, v)
+            d1 = mp.diff(fn, u, 1)
+            d2 = mp.diff(fn, u, 2)
+            out.append(u - d1 / d2 if d2 > 0 else u - mp.mpf(tau) * d1)
+        return out
+
+
+def alg1_pe_u0(p, u1, u0, r):
+    """Partial exhaustion of u0: each point takes, by the selection rule, the
+    best of the values u0 holds at the nodes within r of it."""
+    with mp.workdps(DPS):
+        xs = _nodes(p.x_lo, p.x_hi, p.n_x)
+        ys = _nodes(p.y_lo, p.y_hi, p.n_y)
+        u1m = [_mpv(v) for v in u1]
+        n = len(xs)
+        out = []
+        for i, x in enumerate(xs):
+            cs = [mp.mpf(float(u0[k])) for k in range(max(0, i - r), min(n, i + r + 1))]
+            vs = [_B_at(p, ys, u1m, x, c) for c in cs]
+            c, _ = _select(cs, vs, mp.mpf(float(u0[i])))
+            out.append(float(c))
+        return out
+
+
+def alg1_pe_u1(p, u0, u1, r):
+    """Partial exhaustion of u1: each y node takes the best of the values u1
+    holds at the nodes within r of it, by C_1(u, y) = dx sum f phi (x1 - u)^2."""
+    with mp.workdps(DPS):
+        xs = _nodes(p.x_lo, p.x_hi, p.n_x)
+        ys = _nodes(p.y_lo, p.y_hi, p.n_y)
+        f = _prior(p, xs)
+        x1 = [x + mp.mpf(float(u)) for x, u in zip(xs, u0)]
+        n = len(ys)
+        out = []
+        for j, y in enumerate(ys):
+            w = [fi * mp.npdf(y - a) for fi, a in zip(f, x1)]
+            cs = [mp.mpf(float(u1[k])) for k in range(max(0, j - r), min(n, j + r + 1))]
+            vs = [mp.fsum(wi * (a - c) ** 2 for wi, a in zip(w, x1)) for c in cs]
+            c, _ = _select(cs, vs, mp.mpf(float(u1[j])))
+            out.append(float(c))
+        return out

@@ -742,3 +742,267 @@ void orc2_solve(const orc_problem* p, const orc_search* s, int32_t iters, const 
   free(u0);
   free(nxt);
 }
+
+/* ------------------------------------------------------------------------
+ * The paper's generic solver (Algorithm 1, Sections III-B to III-D) on the
+ * Witsenhausen instance with its two controllers: u_0 on the x grid and u_1
+ * on the y grid, each improved by local updates (modified Newton on its
+ * marginal cost) and by partial exhaustion over the values the controller
+ * takes on the neighbouring grid nodes (the domain-ball candidate set of
+ * Eq. (2)), with the iterations of each round shared between the two
+ * methods by their last improvements (adaptive minimisation).
+ *
+ * Marginal costs.  C_0(u, x_i) = f_i B(u; x_i) with B as in orc_B.
+ * C_1(u, y_j) = dx sum_i f_i phi(y_j - x1_i) (x1_i - u)^2, the integrand of
+ * J in y_1 (so J = dx sum f k^2 u0^2 + dy sum_j C_1(u1_j, y_j)).
+ *
+ * Readings where the paper is silent or garbled:
+ *  - The local update of u_0 works on B = C_0 / f (f > 0): the Newton step
+ *    is the same, and the gradient step u - tau B'(u) does not vanish where
+ *    f underflows; tau (the "given step size") is a parameter.  No range
+ *    is imposed on u.
+ *  - C_1 is quadratic in u with C_1'' > 0, so its Newton step is taken as
+ *    written, u - C_1'/C_1'', with the weights f_i phi max-shifted per y_j:
+ *    the factor cancels in the step.
+ *  - Partial exhaustion compares the candidates {u_m at the nodes within r
+ *    of the point} (the point's own value among them) by the selection rule
+ *    of the coarse-to-fine search (relative tie band, nearest to the
+ *    current value, then the smaller u); all points of one controller are
+ *    updated from the same previous array (the parallel form of Section
+ *    IV-A).  For u_1 the candidates are compared by C_1 with the same
+ *    max-shifted weights (a positive factor per y_j changes neither the
+ *    order nor the relative band).
+ *  - The improvement of a phase is |J before the phase - J after it| (the
+ *    printed update subtracts J from the previous improvement); the first
+ *    allocation is N_L = floor(N/2), N_P = N - N_L, and an allocation with
+ *    I_L + I_P = 0 keeps the previous one.
+ *  - The loop stops when I_L + I_P <= p or after max_rounds rounds.
+ * Parity status: pinned by the CPU tests (derivatives against the closed
+ * form with a linear u_1 and against central differences, one Newton step
+ * onto the minimiser of the convex case, the u_1 step equal to the closed
+ * form, partial exhaustion never raising J and undoing an isolated spike,
+ * the allocation rule on hand-made improvements, and a 40-digit
+ * evaluation of one local update and one partial exhaustion).
+ * ------------------------------------------------------------------------ */
+
+/* B(u; x) and its first two derivatives in u (the local update's C_0' and
+ * C_0'' divided by f).  With z = x + u, t_j = (y_j - z) / s^2 and
+ * e_j = z - u1_j: d phi_s(y_j - z)/dz = t_j phi_s, so
+ *   B'  = 2 k^2 u + dy sum_j phi_s (t_j e_j^2 + 2 e_j),
+ *   B'' = 2 k^2   + dy sum_j phi_s ((t_j^2 - 1/s^2) e_j^2 + 4 t_j e_j + 2). */
+void orc_B_derivs(const orc_problem* p, const double* u1, double x, double u, double* B, double* B1,
+                  double* B2) {
+  double dy = (p->y_hi - p->y_lo) / (double)(p->n_y - 1);
+  double sw = orc_noise_sd(p);
+  double is2 = 1.0 / (sw * sw);
+  double z = x + u;
+  double s0 = 0.0, s1 = 0.0, s2 = 0.0;
+  for (int64_t j = 0; j < p->n_y; ++j) {
+    double y = orc_node(p->y_lo, p->y_hi, p->n_y, j);
+    double ph = orc_phi_s(y - z, sw);
+    double t = (y - z) * is2;
+    double e = z - u1[j];
+    s0 += ph * e * e;
+    s1 += ph * (t * e * e + 2.0 * e);
+    s2 += ph * ((t * t - is2) * e * e + 4.0 * t * e + 2.0);
+  }
+  double k2 = p->k * p->k;
+  if (B) *B = k2 * u * u + dy * s0;
+  if (B1) *B1 = 2.0 * k2 * u + dy * s1;
+  if (B2) *B2 = 2.0 * k2 + dy * s2;
+}
+
+/* Local update of u_0 (Section III-D): Newton where the curvature is
+ * positive, else a gradient step of size tau. */
+void orc_alg1_local_u0(const orc_problem* p, double tau, const double* u1, const double* u0_in,
+                       const int64_t* rows, int64_t n_rows, double* u0_out) {
+  int64_t n = rows ? n_rows : p->n_x;
+#pragma omp parallel for schedule(static)
+  for (int64_t r = 0; r < n; ++r) {
+    int64_t i = rows ? rows[r] : r;
+    double x = orc_node(p->x_lo, p->x_hi, p->n_x, i);
+    double u = u0_in[i], B1, B2;
+    orc_B_derivs(p, u1, x, u, NULL, &B1, &B2);
+    u0_out[r] = B2 > 0.0 ? u - B1 / B2 : u - tau * B1;
+  }
+}
+
+/* Max-shifted weights of C_1 at y_j: w_i = exp(l_ij - M_j), l_ij = log f_i
+ * - (y_j - x1_i)^2 / (2 s^2), M_j = max_i l_ij (as in orc_update_u1). */
+static void orc_c1_weights(const orc_problem* p, const double* logf, const double* x1, double y, double* w) {
+  const double sw = orc_noise_sd(p);
+  double M = -INFINITY;
+  for (int64_t i = 0; i < p->n_x; ++i) {
+    double d = (y - x1[i]) / sw;
+    double l = logf[i] - 0.5 * d * d;
+    if (l > M) M = l;
+  }
+  for (int64_t i = 0; i < p->n_x; ++i) {
+    double d = (y - x1[i]) / sw;
+    w[i] = exp(logf[i] - 0.5 * d * d - M);
+  }
+}
+
+/* Local update of u_1: the Newton step u - C_1'(u)/C_1''(u) with
+ * C_1' = -2 sum w (x1 - u) and C_1'' = 2 sum w (common factors dropped). */
+void orc_alg1_local_u1(const orc_problem* p, const double* u0, const double* u1_in, const int64_t* rows,
+                       int64_t n_rows, double* u1_out) {
+  double* logf = (double*)malloc(sizeof(double) * (size_t)p->n_x);
+  double* x1 = (double*)malloc(sizeof(double) * (size_t)p->n_x);
+  orc_prior(p, NULL, logf);
+  for (int64_t i = 0; i < p->n_x; ++i) x1[i] = orc_node(p->x_lo, p->x_hi, p->n_x, i) + u0[i];
+  int64_t n = rows ? n_rows : p->n_y;
+#pragma omp parallel
+  {
+    double* w = (double*)malloc(sizeof(double) * (size_t)p->n_x);
+#pragma omp for schedule(static)
+    for (int64_t r = 0; r < n; ++r) {
+      int64_t j = rows ? rows[r] : r;
+      double y = orc_node(p->y_lo, p->y_hi, p->n_y, j);
+      double u = u1_in[j];
+      orc_c1_weights(p, logf, x1, y, w);
+      double c1 = 0.0, c2 = 0.0;
+      for (int64_t i = 0; i < p->n_x; ++i) {
+        c1 += -2.0 * w[i] * (x1[i] - u);
+        c2 += 2.0 * w[i];
+      }
+      u1_out[r] = u - c1 / c2;
+    }
+    free(w);
+  }
+  free(logf);
+  free(x1);
+}
+
+/* Partial exhaustion of u_0 over the values at the nodes within r of x_i. */
+void orc_alg1_pe_u0(const orc_problem* p, double tie, int32_t r, const double* u1, const double* u0_in,
+                    const int64_t* rows, int64_t n_rows, double* u0_out) {
+  int64_t n = rows ? n_rows : p->n_x;
+#pragma omp parallel for schedule(static)
+  for (int64_t q = 0; q < n; ++q) {
+    int64_t i = rows ? rows[q] : q;
+    double x = orc_node(p->x_lo, p->x_hi, p->n_x, i);
+    double c[64], B[64];
+    int m = 0;
+    for (int64_t k = i - r; k <= i + r; ++k) {
+      if (k < 0 || k >= p->n_x) continue;
+      c[m] = u0_in[k];
+      B[m] = orc_B(p, u1, x, c[m]);
+      ++m;
+    }
+    u0_out[q] = c[orc_select(m, c, B, u0_in[i], tie)];
+  }
+}
+
+/* Partial exhaustion of u_1 over the values at the nodes within r of y_j,
+ * compared by C_1(u, y_j) with max-shifted weights. */
+void orc_alg1_pe_u1(const orc_problem* p, double tie, int32_t r, const double* u0, const double* u1_in,
+                    const int64_t* rows, int64_t n_rows, double* u1_out) {
+  double* logf = (double*)malloc(sizeof(double) * (size_t)p->n_x);
+  double* x1 = (double*)malloc(sizeof(double) * (size_t)p->n_x);
+  orc_prior(p, NULL, logf);
+  for (int64_t i = 0; i < p->n_x; ++i) x1[i] = orc_node(p->x_lo, p->x_hi, p->n_x, i) + u0[i];
+  int64_t n = rows ? n_rows : p->n_y;
+#pragma omp parallel
+  {
+    double* w = (double*)malloc(sizeof(double) * (size_t)p->n_x);
+#pragma omp for schedule(static)
+    for (int64_t q = 0; q < n; ++q) {
+      int64_t j = rows ? rows[q] : q;
+      double y = orc_node(p->y_lo, p->y_hi, p->n_y, j);
+      orc_c1_weights(p, logf, x1, y, w);
+      double c[64], C[64];
+      int m = 0;
+      for (int64_t k = j - r; k <= j + r; ++k) {
+        if (k < 0 || k >= p->n_y) continue;
+        c[m] = u1_in[k];
+        double s = 0.0;
+        for (int64_t i = 0; i < p->n_x; ++i) {
+          double e = x1[i] - c[m];
+          s += w[i] * e * e;
+        }
+        C[m] = s;
+        ++m;
+      }
+      u1_out[q] = c[orc_select(m, c, C, u1_in[j], tie)];
+    }
+    free(w);
+  }
+  free(logf);
+  free(x1);
+}
+
+/* Adaptive minimisation (the last line of Algorithm 1's loop): the N
+ * iterations of the next round shared in proportion to the improvements,
+ * each method keeping at least one. */
+void orc_alg1_allocate(int32_t N, double IL, double IP, int32_t* NL, int32_t* NP) {
+  if (IL + IP > 0.0) {
+    double a = floor(IL * (double)N / (IL + IP));
+    int32_t v = (int32_t)a;
+    if (v < 1) v = 1;
+    if (v > N - 1) v = N - 1;
+    *NL = v;
+  }
+  *NP = N - *NL;
+}
+
+typedef struct {
+  int32_t N;          /* iterations per round */
+  int32_t r;          /* partial-exhaustion radius in grid nodes */
+  double p;           /* precision: stop when I_L + I_P <= p */
+  double tau;         /* gradient step size of the local update */
+  double tie_rel64;   /* relative tie band of partial exhaustion (0: ORC_TAU64) */
+  int32_t max_rounds; /* cap on rounds */
+  int32_t pad_;
+} orc_alg1_params;
+
+/* Algorithm 1.  J_log receives J after initialisation and after each phase
+ * ([1 + 2 rounds]); NL_log the local-update iterations of each round.
+ * Returns the number of rounds run. */
+int32_t orc_alg1_solve(const orc_problem* p, const orc_alg1_params* a, const double* u0_init,
+                       const double* u1_init, double* u0_out, double* u1_out, double* J_log, int32_t* NL_log) {
+  const double tie = a->tie_rel64 > 0.0 ? a->tie_rel64 : ORC_TAU64;
+  double* u0 = (double*)malloc(sizeof(double) * (size_t)p->n_x);
+  double* u1 = (double*)malloc(sizeof(double) * (size_t)p->n_y);
+  double* t0 = (double*)malloc(sizeof(double) * (size_t)p->n_x);
+  double* t1 = (double*)malloc(sizeof(double) * (size_t)p->n_y);
+  memcpy(u0, u0_init, sizeof(double) * (size_t)p->n_x);
+  memcpy(u1, u1_init, sizeof(double) * (size_t)p->n_y);
+  double Jc = orc_objective(p, u0, u1);
+  J_log[0] = Jc;
+  double IL = a->p, IP = a->p;
+  int32_t NL = a->N / 2, NP = a->N - NL;
+  int32_t rounds = 0;
+  while (IL + IP > a->p && rounds < a->max_rounds) {
+    NL_log[rounds] = NL;
+    double Jprev = Jc;
+    for (int32_t it = 0; it < NL; ++it) {
+      orc_alg1_local_u0(p, a->tau, u1, u0, NULL, 0, t0);
+      memcpy(u0, t0, sizeof(double) * (size_t)p->n_x);
+      orc_alg1_local_u1(p, u0, u1, NULL, 0, t1);
+      memcpy(u1, t1, sizeof(double) * (size_t)p->n_y);
+    }
+    Jc = orc_objective(p, u0, u1);
+    IL = fabs(Jprev - Jc);
+    J_log[1 + 2 * rounds] = Jc;
+    Jprev = Jc;
+    for (int32_t it = 0; it < NP; ++it) {
+      orc_alg1_pe_u0(p, tie, a->r, u1, u0, NULL, 0, t0);
+      memcpy(u0, t0, sizeof(double) * (size_t)p->n_x);
+      orc_alg1_pe_u1(p, tie, a->r, u0, u1, NULL, 0, t1);
+      memcpy(u1, t1, sizeof(double) * (size_t)p->n_y);
+    }
+    Jc = orc_objective(p, u0, u1);
+    IP = fabs(Jprev - Jc);
+    J_log[2 + 2 * rounds] = Jc;
+    orc_alg1_allocate(a->N, IL, IP, &NL, &NP);
+    ++rounds;
+  }
+  memcpy(u0_out, u0, sizeof(double) * (size_t)p->n_x);
+  memcpy(u1_out, u1, sizeof(double) * (size_t)p->n_y);
+  free(u0);
+  free(u1);
+  free(t0);
+  free(t1);
+  return rounds;
+}
