@@ -57,8 +57,11 @@ typedef enum {
 /* Problem instance: weight k of the stage-1 cost, the prior of x0 as a
  * mixture of n_comp Gaussians (weights w summing to 1, means mu, standard
  * deviations sd > 0), the x0 grid (n_x nodes on [x_lo, x_hi]) and the y1
- * grid (n_y nodes on [y_lo, y_hi]), 2 <= n_x, n_y <= 2^24.  Node i of a
- * grid is lo + i * ((hi - lo) / (n - 1)) in binary64. */
+ * grid (n_y nodes on [y_lo, y_hi]), 2 <= n_x, n_y <= 2^24, and the
+ * standard deviation noise_sd of the Gaussian noise w (Section V-A fixes 1;
+ * 0 also selects 1; otherwise 1e-6 <= noise_sd <= 1e6).  Node i of a grid
+ * is lo + i * ((hi - lo) / (n - 1)) in binary64.  Every window below is
+ * measured in noise standard deviations. */
 typedef struct ucp_problem {
   double k;
   int32_t n_comp;
@@ -70,6 +73,7 @@ typedef struct ucp_problem {
   int64_t n_x;
   double y_lo, y_hi;
   int64_t n_y;
+  double noise_sd;
 } ucp_problem;
 
 /* Coarse-to-fine search of argmin_u L_0(u, x0) per point: level 0 takes
@@ -119,7 +123,7 @@ void ucp_destroy(ucp_handle* h);
  * applied to the Section V-A objective):
  *   L0_out[i*n_cand + c] = f(x_i) * ( k^2 u^2
  *        + dy * sum_j phi(y_j - x_i - u) (x_i + u - u1[j])^2 ),
- *   u = u[i*n_cand + c], phi the N(0,1) density.
+ *   u = u[i*n_cand + c], phi the N(0, noise_sd^2) density.
  * u1: [n_y]; u: [n_x * n_cand] row-major per point; L0_out: [n_x * n_cand].
  * The sum runs over the nodes within 9 (FP32 modes) or 11 (FP64) noise
  * standard deviations of the node nearest x_i + u, scaled by the Gaussian
@@ -301,7 +305,8 @@ int ucp_coding_solve(ucp_handle* h, const ucp_coding_problem* prob, const ucp_se
  * x2 = x1 - u1(y1); minimise J = 1/2 E[k^2 |u0|^2 + |x2|^2] (the paper:
  * k = 0.2, sigma = 5 on 160 x 160 nodes).  The grids are tensor products:
  * x node (i1, i2) at index i1 * n_x + i2, y node (j1, j2) at j1 * n_y + j2,
- * at most 4096 nodes per coordinate; rectangle rule with weights dx^2 and
+ * at most 4096 nodes per coordinate, prob->noise_sd 0 or 1 (the noise is
+ * N(0, I_2)); rectangle rule with weights dx^2 and
  * dy^2.  Vector fields are two planes: [2][n_x^2] for u0, [2][n_y^2] for
  * u1 (first coordinates, then second).  FP64 throughout.  The noise sums
  * run over the floor(10 / dy) nodes on either side of the node nearest

@@ -41,6 +41,7 @@ class Problem(C.Structure):
         ("w", C.c_double * MAX_COMP), ("mu", C.c_double * MAX_COMP), ("sd", C.c_double * MAX_COMP),
         ("x_lo", C.c_double), ("x_hi", C.c_double), ("n_x", C.c_int64),
         ("y_lo", C.c_double), ("y_hi", C.c_double), ("n_y", C.c_int64),
+        ("noise_sd", C.c_double),
     ]
 
 
@@ -134,6 +135,7 @@ def make_problem(p) -> Problem:
         s.w[c], s.mu[c], s.sd[c] = float(w), float(mu), float(sd)
     s.x_lo, s.x_hi, s.n_x = float(p.x_lo), float(p.x_hi), int(p.n_x)
     s.y_lo, s.y_hi, s.n_y = float(p.y_lo), float(p.y_hi), int(p.n_y)
+    s.noise_sd = float(getattr(p, "noise_sd", 1.0))
     return s
 
 

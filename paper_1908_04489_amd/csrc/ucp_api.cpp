@@ -54,6 +54,8 @@ int check_problem(const ucp_problem* p) {
     return fail(UCP_EINVAL, "y grid needs finite y_lo < y_hi");
   if (std::fabs(p->x_lo) > 1e6 || std::fabs(p->x_hi) > 1e6 || std::fabs(p->y_lo) > 1e6 || std::fabs(p->y_hi) > 1e6)
     return fail(UCP_EINVAL, "grid bounds beyond 1e6");
+  if (!(p->noise_sd >= 0.0) || !(p->noise_sd <= 1e6)) return fail(UCP_EINVAL, "noise_sd must be in [0, 1e6] (0: 1)");
+  if (p->noise_sd > 0.0 && p->noise_sd < 1e-6) return fail(UCP_EINVAL, "noise_sd below 1e-6");
   return UCP_OK;
 }
 
@@ -88,7 +90,13 @@ Inst make_inst(const ucp_problem& p, const ucp_search* s, int prec, int cands_ov
   I.y_lo = p.y_lo;
   I.dy = (p.y_hi - p.y_lo) / (double)(p.n_y - 1);
   I.inv_dy = 1.0 / I.dy;
-  I.phi_scale = I.dy * kInvSqrt2Pi;
+  // noise w ~ N(0, s^2): every Gaussian argument is taken in noise sds
+  I.sw = p.noise_sd > 0.0 ? p.noise_sd : 1.0;
+  I.isw = 1.0 / I.sw;
+  I.alpha = std::sqrt(kAlpha2) * I.isw;
+  I.a2 = kAlpha2 * I.isw * I.isw;
+  I.win32 = kWin32 * I.sw;
+  I.phi_scale = I.dy * kInvSqrt2Pi * I.isw;
   I.n_comp = p.n_comp;
   for (int c = 0; c < p.n_comp; ++c) {
     I.w[c] = p.w[c];
@@ -114,8 +122,13 @@ Inst make_inst(const ucp_problem& p, const ucp_search* s, int prec, int cands_ov
   I.tau64 = tie_band(s);
   // the FP32 band holds every candidate the FP64 band could hold
   I.tau32 = (s && s->band_rel32 > 0.0 ? s->band_rel32 : prec == UCP_FP32_KAHAN ? kTau32Kahan : kTau32Plain) + I.tau64;
-  I.nw32 = (int32_t)std::min<double>(std::ceil(kWin32 / I.dy), (double)I.n_y);
-  I.nw64 = (int32_t)std::min<double>(std::ceil(kWin64 / I.dy), (double)I.n_y);
+  I.nw32 = (int32_t)std::min<double>(std::ceil(kWin32 * I.sw / I.dy), (double)I.n_y);
+  I.nw64 = (int32_t)std::min<double>(std::ceil(kWin64 * I.sw / I.dy), (double)I.n_y);
+  // a wave's FP64 walk steps 64 nodes at a time: reseed at least every 24
+  // noise sds, so a weight that underflowed far from its position is
+  // recomputed before its peak
+  I.rs64 = 32;
+  while (I.rs64 > 1 && I.rs64 * 64.0 * I.dy * I.isw > 24.0) I.rs64 /= 2;
   I.prec = prec;
   // window segments: enough work units to fill the GPU when the instance is
   // small, segments of at least 256 nodes

@@ -72,7 +72,10 @@ struct Inst {
   double k2;                 // k^2
   double x_lo, dx;           // x node i = x_lo + i * dx
   double y_lo, dy, inv_dy;   // y node j = y_lo + j * dy
-  double phi_scale;          // dy / sqrt(2 pi)
+  double phi_scale;          // dy / (s sqrt(2 pi)), s the noise sd
+  double sw, isw;            // noise sd s and 1 / s
+  double alpha, a2;          // sqrt(log2(e) / 2) / s and its square: exp(-t^2 / (2 s^2)) = exp2(-(alpha t)^2)
+  double win32;              // FP32 window half-width in y units, kWin32 s
   double w[kMaxComp], mu[kMaxComp], sd[kMaxComp];
   int32_t n_comp;
   int32_t n_x, n_y;
@@ -84,6 +87,7 @@ struct Inst {
   double tau32;              // relative part of the FP32 pre-selection band (holds tau64)
   // geometry
   int32_t nw32, nw64;        // window half-widths in y nodes
+  int32_t rs64;              // FP64 walks: steps of a wave between reseeds (a power of two, <= 32)
   int32_t segs;              // marginal-cost units (partial sums) per (tile, candidate)
   int32_t wsegs;             // equal window segments (the last one dispatched split in two when segs > wsegs)
   int32_t u1_slices;         // x slices of the u1 sums

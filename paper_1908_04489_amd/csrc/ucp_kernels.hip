@@ -123,15 +123,22 @@ __device__ __forceinline__ int nearest_node(const Inst& I, double z) {
 // Lane l takes k = klo + l + W m; along m the Gaussian obeys the exact
 // recurrence g_{k+W} = g_k r_k, r_{k+W} = r_k q with
 // r_k = exp(-W dy t_k - (W dy)^2 / 2) and q = exp(-(W dy)^2), so two
-// multiplies replace an exp; both are recomputed by exp every kReseed steps,
-// which bounds the relative error of any weight by ~kReseed^2/2 ulp
-// (5.7e-14).  Every lane has a node in the first floor(n/W) steps: they run
-// without masks in groups of kPrefetch, the loads of group g + 1 issued
-// before group g is summed (two register buffers); only the last step can be
-// partial.  Even steps go to one accumulator and odd steps to another.
+// multiplies replace an exp; both are recomputed by exp every I.rs64 steps
+// (at most kReseed), which bounds the relative error of any weight by
+// ~kReseed^2/2 ulp (5.7e-14).  (All distances here are in noise sds.)  A
+// pass over the union of several positions' windows starts far from some of
+// them, where a seed beyond 37.6 sds underflows; reseeds at most 24 sds
+// apart (I.rs64 W dy <= 24, steps of W nodes) give every position an exact
+// seed more than 11 sds out, before its window begins; r's exponent is
+// capped so a far seed cannot overflow it.  Every lane has a node in the first floor(n/W)
+// steps: they run without masks in groups of kPrefetch, the loads of group
+// g + 1 issued before group g is summed (two register buffers); only the
+// last step can be partial.  Even steps go to one accumulator and odd steps
+// to another.
 constexpr int kReseed = 32;
 constexpr int kPrefetch = 4;
 static_assert(kReseed % kPrefetch == 0, "reseeds fall on group boundaries");
+constexpr double kRMaxExp = 700.0;  // cap of r's exponent (exp(700) is finite)
 typedef const __attribute__((address_space(1))) double* glb_dptr;
 
 struct B64Walk {
@@ -142,17 +149,23 @@ template <int W>
 __device__ __forceinline__ void b64_reseed(B64Walk& w, int klo, int lane, int m, double dy, double delta, double D) {
   const double d = (double)(klo + lane + W * m) * dy;
   w.g = exp(-0.5 * d * (d + 2.0 * delta));
-  w.r = exp(-D * (d + delta) - 0.5 * D * D);
+  w.r = exp(fmin(-D * (d + delta) - 0.5 * D * D, kRMaxExp));
 }
 
-// Sum one group of kPrefetch steps starting at step m (m even).
-__device__ __forceinline__ void b64_group(const double* uv, double z, double q, B64Walk& w, double& s0, double& s1) {
+// Sum one group of kPrefetch steps starting at step m (m a multiple of
+// kPrefetch, reseeded by the caller when due); reseeds inside the group when
+// the instance reseeds more often than every kPrefetch steps.
+template <int W>
+__device__ __forceinline__ void b64_group(const double* uv, double z, double q, B64Walk& w, double& s0, double& s1,
+                                          int m, int rs, int klo, int lane, double dy, double delta, double D) {
 #pragma unroll
   for (int mm = 0; mm < kPrefetch; mm += 2) {
+    if (rs < kPrefetch && mm > 0 && ((m + mm) & (rs - 1)) == 0) b64_reseed<W>(w, klo, lane, m + mm, dy, delta, D);
     const double e0 = z - uv[mm];
     s0 = fma(w.g * e0, e0, s0);
     w.g *= w.r;
     w.r *= q;
+    if (rs == 1) b64_reseed<W>(w, klo, lane, m + mm + 1, dy, delta, D);
     const double e1 = z - uv[mm + 1];
     s1 = fma(w.g * e1, e1, s1);
     w.g *= w.r;
@@ -163,16 +176,18 @@ __device__ __forceinline__ void b64_group(const double* uv, double z, double q, 
 template <int W = kWave>
 __device__ double b64_wave(const Inst& I, double z, int lane) {
   const int jr = nearest_node(I, z);
-  const double delta = (I.y_lo + (double)jr * I.dy) - z;
+  // offsets in noise sds: delta and the spacing times 1 / noise_sd
+  const double delta = ((I.y_lo + (double)jr * I.dy) - z) * I.isw;
   // 0 <= jr <= n_y - 1, so klo <= 0 <= khi and the window is never empty
   const int klo = max(-I.nw64, -jr), khi = min(I.nw64, I.n_y - 1 - jr);
   const int n = khi - klo + 1;
-  const double dy = I.dy, D = (double)W * dy;
+  const double dy = I.dy * I.isw, D = (double)W * dy;
   const double q = exp(-D * D);
   glb_dptr u1 = (glb_dptr)(I.u1 + jr + klo + lane);  // this lane's node of step m: u1[W m]
   double s0 = 0.0, s1 = 0.0;
   const int steps = (n + W - 1) / W;
   const int groups = (n / W) / kPrefetch;  // unmasked groups
+  const int rs = I.rs64;                   // steps between reseeds (a power of two)
   B64Walk w;
   double ua[kPrefetch], ub[kPrefetch];
   if (groups > 0) {
@@ -184,22 +199,22 @@ __device__ double b64_wave(const Inst& I, double z, int lane) {
     const int m = gi * kPrefetch;
 #pragma unroll
     for (int mm = 0; mm < kPrefetch; ++mm) ub[mm] = u1[W * (m + kPrefetch + mm)];
-    if (m % kReseed == 0) b64_reseed<W>(w, klo, lane, m, dy, delta, D);
-    b64_group(ua, z, q, w, s0, s1);
+    if ((m & (rs - 1)) == 0) b64_reseed<W>(w, klo, lane, m, dy, delta, D);
+    b64_group<W>(ua, z, q, w, s0, s1, m, rs, klo, lane, dy, delta, D);
     // the group after next, or (past the end, unused) the last one: in range
     const int mn = min(m + 2 * kPrefetch, (groups - 1) * kPrefetch);
 #pragma unroll
     for (int mm = 0; mm < kPrefetch; ++mm) ua[mm] = u1[W * (mn + mm)];
-    if ((m + kPrefetch) % kReseed == 0) b64_reseed<W>(w, klo, lane, m + kPrefetch, dy, delta, D);
-    b64_group(ub, z, q, w, s0, s1);
+    if (((m + kPrefetch) & (rs - 1)) == 0) b64_reseed<W>(w, klo, lane, m + kPrefetch, dy, delta, D);
+    b64_group<W>(ub, z, q, w, s0, s1, m + kPrefetch, rs, klo, lane, dy, delta, D);
   }
   if (gi < groups) {  // one group left, already loaded
     const int m = gi * kPrefetch;
-    if (m % kReseed == 0) b64_reseed<W>(w, klo, lane, m, dy, delta, D);
-    b64_group(ua, z, q, w, s0, s1);
+    if ((m & (rs - 1)) == 0) b64_reseed<W>(w, klo, lane, m, dy, delta, D);
+    b64_group<W>(ua, z, q, w, s0, s1, m, rs, klo, lane, dy, delta, D);
   }
   for (int m = groups * kPrefetch; m < steps; ++m) {  // the rest, the last step possibly partial
-    if (m % kReseed == 0) b64_reseed<W>(w, klo, lane, m, dy, delta, D);
+    if ((m & (rs - 1)) == 0) b64_reseed<W>(w, klo, lane, m, dy, delta, D);
     double e = 0.0;
     if (lane + W * m < n) e = z - u1[W * m];
     if (m & 1) s1 = fma(w.g * e, e, s1);
@@ -216,8 +231,10 @@ __device__ double b64_wave(const Inst& I, double z, int lane) {
 // a small bracket): each lane's u1 load serves all R sums.  Per position the
 // same shifted Gaussian and reseeded recurrence as b64_wave, relative to its
 // own nearest node; nodes of the union beyond a position's own window add
-// weights below exp(-40) (terms of the dense sum all the same).  One
-// accumulator per position.
+// weights below exp(-60) (terms of the dense sum all the same).  The union
+// may start far from a position (the objective's rows, a winner and a
+// distant incumbent): its weights there underflow, and the reseed interval
+// (I.rs64) restores them before its peak.  One accumulator per position.
 template <int R, int W = kWave>
 __device__ void b64_multi(const Inst& I, const double* z, int lane, double* out) {
   int jr[R];
@@ -226,12 +243,12 @@ __device__ void b64_multi(const Inst& I, const double* z, int lane, double* out)
 #pragma unroll
   for (int q = 0; q < R; ++q) {
     jr[q] = nearest_node(I, z[q]);
-    delta[q] = (I.y_lo + (double)jr[q] * I.dy) - z[q];
+    delta[q] = ((I.y_lo + (double)jr[q] * I.dy) - z[q]) * I.isw;  // in noise sds
     jlo = min(jlo, max(0, jr[q] - I.nw64));
     jhi = max(jhi, min(I.n_y - 1, jr[q] + I.nw64));
   }
   const int n = jhi - jlo + 1;
-  const double dy = I.dy, D = (double)W * dy;
+  const double dy = I.dy * I.isw, D = (double)W * dy;
   const double qf = exp(-D * D);
   glb_dptr u1 = (glb_dptr)(I.u1 + jlo + lane);  // this lane's node of step m: u1[W m]
   double g[R], r[R], s[R];
@@ -242,12 +259,14 @@ __device__ void b64_multi(const Inst& I, const double* z, int lane, double* out)
     for (int q = 0; q < R; ++q) {
       const double d = (double)(jlo + lane + W * m - jr[q]) * dy;
       g[q] = exp(-0.5 * d * (d + 2.0 * delta[q]));
-      r[q] = exp(-D * (d + delta[q]) - 0.5 * D * D);
+      r[q] = exp(fmin(-D * (d + delta[q]) - 0.5 * D * D, kRMaxExp));
     }
   };
-  auto group = [&](const double* uv) {
+  const int rs = I.rs64;  // steps between reseeds (a power of two)
+  auto group = [&](const double* uv, int m) {
 #pragma unroll
     for (int mm = 0; mm < kPrefetch; ++mm) {
+      if (rs < kPrefetch && mm > 0 && ((m + mm) & (rs - 1)) == 0) reseed(m + mm);
 #pragma unroll
       for (int q = 0; q < R; ++q) {
         const double e = z[q] - uv[mm];
@@ -269,21 +288,21 @@ __device__ void b64_multi(const Inst& I, const double* z, int lane, double* out)
     const int m = gi * kPrefetch;
 #pragma unroll
     for (int mm = 0; mm < kPrefetch; ++mm) ub[mm] = u1[W * (m + kPrefetch + mm)];
-    if (m % kReseed == 0) reseed(m);
-    group(ua);
+    if ((m & (rs - 1)) == 0) reseed(m);
+    group(ua, m);
     const int mn = min(m + 2 * kPrefetch, (groups - 1) * kPrefetch);
 #pragma unroll
     for (int mm = 0; mm < kPrefetch; ++mm) ua[mm] = u1[W * (mn + mm)];
-    if ((m + kPrefetch) % kReseed == 0) reseed(m + kPrefetch);
-    group(ub);
+    if (((m + kPrefetch) & (rs - 1)) == 0) reseed(m + kPrefetch);
+    group(ub, m + kPrefetch);
   }
   if (gi < groups) {
     const int m = gi * kPrefetch;
-    if (m % kReseed == 0) reseed(m);
-    group(ua);
+    if ((m & (rs - 1)) == 0) reseed(m);
+    group(ua, m);
   }
   for (int m = groups * kPrefetch; m < steps; ++m) {
-    if (m % kReseed == 0) reseed(m);
+    if ((m & (rs - 1)) == 0) reseed(m);
     const bool in = lane + W * m < n;
     const double u = in ? u1[W * m] : 0.0;
 #pragma unroll
@@ -299,13 +318,13 @@ __device__ void b64_multi(const Inst& I, const double* z, int lane, double* out)
 }
 
 // Algorithmic terms of one (point, candidate): the y nodes within kWin32
-// noise sds of z (the work the method needs for FP64-level accuracy; the
+// noise sds (I.win32 = kWin32 noise_sd) of z (the work the method needs for FP64-level accuracy; the
 // kernels may evaluate a few more).  Summed per wave, one atomic per wave.
 __device__ __forceinline__ void count_terms(const Inst& I, double z, bool act, int lane) {
   long long n = 0;
   if (act && I.terms) {
-    double lo = ceil((z - kWin32 - I.y_lo) * I.inv_dy);
-    double hi = floor((z + kWin32 - I.y_lo) * I.inv_dy);
+    double lo = ceil((z - I.win32 - I.y_lo) * I.inv_dy);
+    double hi = floor((z + I.win32 - I.y_lo) * I.inv_dy);
     lo = fmax(lo, 0.0);
     hi = fmin(hi, (double)(I.n_y - 1));
     if (hi >= lo) n = (long long)(hi - lo) + 1;
@@ -341,15 +360,16 @@ __global__ __launch_bounds__(256) void k_prior(Launch L) {
   I.logf[i] = lmax + log(acc);
 }
 
-// Offset table of the marginal-cost kernel: G_k = exp(-(k dy)^2 / 2) =
-// exp2(-(k alpha dy)^2) for |k| <= nw32, rounded once from FP64.
+// Offset table of the marginal-cost kernel: G_k = exp(-(k dy / s)^2 / 2) =
+// exp2(-(k alpha dy)^2) for |k| <= nw32 (s the noise sd, alpha =
+// sqrt(log2(e)/2) / s), rounded once from FP64.
 __global__ __launch_bounds__(256) void k_gtab(Launch L) {
   const int u = blockIdx.x;
   const int b = find_inst(L.pre, L.n_inst, u);
   const Inst& I = L.insts[b];
   const int k = (u - L.pre[b]) * 256 + (int)threadIdx.x - I.nw32;
   if (k > I.nw32 + kGtabPad) return;  // padded past the window for the last block's reads
-  const double d = (double)k * I.dy;
+  const double d = (double)k * I.dy * I.isw;
   I.gtab[k + I.nw32] = (float)exp(-0.5 * d * d);
 }
 
@@ -675,7 +695,7 @@ __global__ __launch_bounds__(kMcBlock) void k_mc32(Launch L, int level) {
   }
   int klo = max(s_lo, -jr), khi = min(s_hi, I.n_y - 1 - jr);
   if (!act) { klo = 1; khi = 0; }
-  const double beta = -2.0 * kAlpha2 * I.dy * delta;
+  const double beta = -2.0 * I.a2 * I.dy * delta;
   // Lanes whose weights change by more than 2^kMcBetaMax from node to node
   // (very coarse y grids, or positions far outside the y grid) sum their
   // window term by term below with exact weights; the blocked loops see
@@ -720,9 +740,9 @@ __global__ __launch_bounds__(kMcBlock) void k_mc32(Launch L, int level) {
     if (lane == 0 && ev > 0 && I.terms)
       atomicAdd(I.terms + kCountEvalTerms + (blockIdx.x & (kCountSlots - 1)) * kCountStride, (unsigned long long)ev);
   }
-  const double alpha = sqrt(kAlpha2);
+  const double alpha = I.alpha;
   const bool staged = bhi >= blo && bhi - blo + 1 <= kMcLds;
-  const bool ref = staged && bzhi - bzlo <= 2.0 * kMcRefHalf;
+  const bool ref = staged && bzhi - bzlo <= 2.0 * kMcRefHalf * I.sw;
   const double zc = 0.5 * (bzlo + bzhi);  // block-uniform
   {
     // fields in registers and global-space pointers: the instance is read
@@ -829,15 +849,15 @@ __global__ __launch_bounds__(kMcBlock) void k_mc64(Launch L, int level) {
   count_terms(I, z, act, (int)threadIdx.x % kWave);
   if (!act) return;
   const int jr = nearest_node(I, z);
-  const double delta = (I.y_lo + (double)jr * I.dy) - z;
+  const double delta = ((I.y_lo + (double)jr * I.dy) - z) * I.isw;  // in noise sds
   const int klo = max(-I.nw64, -jr), khi = min(I.nw64, I.n_y - 1 - jr);
-  const double dy = I.dy, qd = exp(-dy * dy);
+  const double dy = I.dy * I.isw, qd = exp(-dy * dy);
   const double* __restrict__ u1 = I.u1 + jr;
   double s0 = 0.0, s1 = 0.0;
   for (int k0 = klo; k0 <= khi; k0 += kReseed) {
     const double d = (double)k0 * dy;
     double g = exp(-0.5 * d * (d + 2.0 * delta));
-    double r = exp(-dy * (d + delta) - 0.5 * dy * dy);
+    double r = exp(fmin(-dy * (d + delta) - 0.5 * dy * dy, kRMaxExp));
     const int k1 = min(khi, k0 + kReseed - 1);
     int k = k0;
     for (; k + 1 <= k1; k += 2) {
@@ -869,17 +889,17 @@ hipError_t launch_mc(const Launch& L, int level, int prec, hipStream_t st, hipEv
   return hipGetLastError();
 }
 
-// B from the partial sums of candidate lane q: k^2 c^2 + dy/sqrt(2 pi)
-// exp(-delta^2/2) * sum (the FP32 sums carry the factor alpha^2).
+// B from the partial sums of candidate lane q: k^2 c^2 + dy/(s sqrt(2 pi))
+// exp(-(delta/s)^2/2) * sum (the FP32 sums carry the factor alpha^2).
 __device__ __forceinline__ double b_from_parts(const Inst& I, int i, int q, int S,
                                                double c, int prec) {
   const double z = (I.x_lo + (double)i * I.dx) + c;
   const int jr = nearest_node(I, z);
-  const double delta = (I.y_lo + (double)jr * I.dy) - z;
+  const double delta = ((I.y_lo + (double)jr * I.dy) - z) * I.isw;  // in noise sds
   const double* p = I.part + ((size_t)i * (I.cands + 1) + q) * S;  // [point][slot][segment]
   double s = 0.0;
   for (int g = 0; g < S; ++g) s += p[g];
-  if (prec != UCP_FP64) s = s / kAlpha2;
+  if (prec != UCP_FP64) s = s / I.a2;
   return I.k2 * c * c + I.phi_scale * exp(-0.5 * delta * delta) * s;
 }
 
@@ -1350,9 +1370,9 @@ template <int PREC>
 __global__ __launch_bounds__(kU1Block) void k_u1_partial(Launch L) {
   constexpr int NW = kU1Block / kWave;
   __shared__ double sD[kU1Chunk];    // D_i = y_c - x1_i
-  __shared__ double sP[kU1Chunk];    // P_i = log2(e) (log f_i - D_i^2 / 2)
-  __shared__ float sDf[kU1Chunk];    // D_i in FP32 (maximum pass only)
-  __shared__ float sPf[kU1Chunk];    // log f_i - D_i^2 / 2 in FP32 (maximum pass only)
+  __shared__ double sP[kU1Chunk];    // P_i = log2(e) (log f_i - D_i^2 / (2 s^2)), s the noise sd
+  __shared__ float sDf[kU1Chunk];    // D_i / s^2 in FP32 (maximum pass only)
+  __shared__ float sPf[kU1Chunk];    // log f_i - D_i^2 / (2 s^2) in FP32 (maximum pass only)
   __shared__ double sb[4][NW];       // per-wave bounds
   const int u = blockIdx.x;
   const int b = find_inst(L.pre, L.n_inst, u);
@@ -1366,7 +1386,9 @@ __global__ __launch_bounds__(kU1Block) void k_u1_partial(Launch L) {
   const int slen = (I.n_x + I.u1_slices - 1) / I.u1_slices;
   const int i0 = slice * slen, i1 = min(I.n_x, i0 + slen);
   const double log2e = 1.4426950408889634073599246810019;
-  const double c2 = 0.5 * log2e;
+  // the noise variance s^2 divides every squared distance: h2 = 1 / (2 s^2)
+  const double is2 = I.isw * I.isw, h2 = 0.5 * is2;
+  const double c2 = h2 * log2e;
   // A lower bound on the logit maximum M_j of every node of the tile: any x
   // node gives one, M_j >= l_ij >= log f_i - max over the tile's y of
   // (y - x1_i)^2 / 2; every kU1Sample-th node is taken.
@@ -1382,20 +1404,21 @@ __global__ __launch_bounds__(kU1Block) void k_u1_partial(Launch L) {
   for (int i = (int)threadIdx.x * kU1Sample; i < nx; i += kU1Block * kU1Sample) {
     const double x1 = (x_lo + (double)i * dx) + u0g[i];
     const double da = ya - x1, db = yb - x1;
-    lb = fmax(lb, lfg[i] - 0.5 * fmax(da * da, db * db));  // NaN terms drop out
+    lb = fmax(lb, lfg[i] - h2 * fmax(da * da, db * db));  // NaN terms drop out
   }
   lb = block_max_d(lb, sb[0]);
   // Around the middle node y_c of the tile, y_j - x1_i = eta_j + D_i with
-  // eta_j = y_j - y_c and D_i = y_c - x1_i, so the log2 weight
-  //   log2(e) (log f_i - (y_j - x1_i)^2 / 2 - M_j) = P_i + Q_j + E_j D_i,
-  // P_i = log2(e) (log f_i - D_i^2 / 2) staged per node, Q_j = -log2(e)
-  // (M_j + eta_j^2 / 2) and E_j = -log2(e) eta_j per lane: one add and one
-  // fma in FP64.  The FP64 numerator sums w D_i (one fma); eta_j times the
+  // eta_j = y_j - y_c and D_i = y_c - x1_i, so the log2 weight (s the
+  // noise sd)
+  //   log2(e) (log f_i - (y_j - x1_i)^2 / (2 s^2) - M_j) = P_i + Q_j + E_j D_i,
+  // P_i = log2(e) (log f_i - D_i^2 / (2 s^2)) staged per node, Q_j =
+  // -log2(e) (M_j + eta_j^2 / (2 s^2)) and E_j = -log2(e) eta_j / s^2 per
+  // lane: one add and one fma in FP64.  The FP64 numerator sums w D_i (one fma); eta_j times the
   // denominator is added once at the end (sum_i w (y_j - x1_i) =
   // sum_i w D_i + eta_j sum_i w).
   const double yc = I.y_lo + (double)((j0 + j1) / 2) * I.dy;
   const double eta = y - yc;
-  const double E = -log2e * eta;
+  const double E = -log2e * eta * is2;
   const float etaf = (float)eta;
   double M = -INFINITY, den = 0.0, num = 0.0;
   for (int c0 = i0; c0 < i1; c0 += kU1Chunk) {
@@ -1408,10 +1431,10 @@ __global__ __launch_bounds__(kU1Block) void k_u1_partial(Launch L) {
       const double x1 = (x_lo + (double)i * dx) + u0g[i];
       const double lf = lfg[i];
       const double D = yc - x1;
-      const double Pn = lf - 0.5 * D * D;
+      const double Pn = lf - h2 * D * D;
       sD[t] = D;
       sP[t] = Pn * log2e;
-      sDf[t] = (float)D;
+      sDf[t] = (float)(D * is2);
       sPf[t] = (float)Pn;
       xmn = fmin(xmn, x1);
       xmx = fmax(xmx, x1);
@@ -1441,12 +1464,12 @@ __global__ __launch_bounds__(kU1Block) void k_u1_partial(Launch L) {
     const double dist = fmax(0.0, fmax(xmn - yb, ya - xmx));
     // skipped weights are below exp(-kU1Cull) of the largest: none of the
     // sums moves (n_x exp(-kU1Cull) < 2^-60)
-    if (!bad && fmx - 0.5 * dist * dist < lb - kU1Cull) continue;
+    if (!bad && fmx - h2 * dist * dist < lb - kU1Cull) continue;
     // chunk maximum of the logits, in FP32: only a shift, any value near
     // the maximum works (the sums below use exact FP64 exponents)
     float mcf = -INFINITY;
     for (int t = 0; t < cn; ++t) mcf = fmaxf(mcf, fmaf(-etaf, sDf[t], sPf[t]));
-    const double mc = (double)mcf - 0.5 * eta * eta;
+    const double mc = (double)mcf - h2 * eta * eta;
     if (mc > M) {  // rescale what was summed under the old maximum
       const double r = M == -INFINITY ? 0.0 : exp(M - mc);
       den *= r;
@@ -1517,7 +1540,7 @@ __global__ __launch_bounds__(kU1Block) void k_u1_combine(Launch L) {
   // the residual from the stored u1, exactly as k_v_from_u1 forms it, so a
   // u0 update sees the same FP32 residual whether u1 came from here or
   // from the caller
-  I.v[j] = (float)(sqrt(kAlpha2) * (y - u1));
+  I.v[j] = (float)(I.alpha * (y - u1));
   if (!isfinite(u1)) atomicOr(I.flags, 1);
 }
 
@@ -1640,7 +1663,7 @@ __global__ __launch_bounds__(256) void k_v_from_u1(Launch L) {
   const int j = (u - L.pre[b]) * 256 + threadIdx.x;
   if (j >= I.n_y) return;
   const double y = I.y_lo + (double)j * I.dy;
-  I.v[j] = (float)(sqrt(kAlpha2) * (y - I.u1[j]));
+  I.v[j] = (float)(I.alpha * (y - I.u1[j]));
 }
 
 hipError_t launch_v_from_u1(const Launch& L, hipStream_t st) {

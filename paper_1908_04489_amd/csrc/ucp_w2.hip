@@ -420,6 +420,8 @@ struct W2Work {
 int w2_params(const ucp_problem* p, const ucp_search* s, W2Params& P) {
   int rc = check_problem(p);
   if (rc) return rc;
+  if (p->noise_sd != 0.0 && p->noise_sd != 1.0)
+    return fail(UCP_EINVAL, "the 2-D problem has unit noise N(0, I_2): noise_sd must be 0 or 1");
   if (p->n_x > 4096 || p->n_y > 4096) return fail(UCP_EINVAL, "2-D grids take at most 4096 nodes per coordinate");
   if (s) {
     if ((rc = check_search(s))) return rc;

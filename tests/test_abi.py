@@ -49,7 +49,7 @@ def test_version_and_error_codes(U):
 
 def test_struct_layout_matches_header(U):
     # ucp_problem: k, n_comp, pad, 3 x 8 doubles, x range + n, y range + n
-    assert C.sizeof(U.Problem) == 8 + 4 + 4 + 3 * 8 * 8 + 8 + 8 + 8 + 8 + 8 + 8
+    assert C.sizeof(U.Problem) == 8 + 4 + 4 + 3 * 8 * 8 + 8 + 8 + 8 + 8 + 8 + 8 + 8  # ... noise_sd
     # ucp_search: range, levels, cands, tie_rel64, band_rel32
     assert C.sizeof(U.Search) == 8 + 8 + 4 + 4 + 8 + 8
 
@@ -69,7 +69,7 @@ def _bad_problems():
     good = W.gaussian_problem(0.2, 5.0, 101, 25.0)
     out = []
     for field, val in [("n_x", 1), ("n_y", 0), ("k", -1.0), ("k", float("nan")), ("x_lo", 30.0),
-                       ("y_hi", -30.0)]:
+                       ("y_hi", -30.0), ("noise_sd", -1.0), ("noise_sd", float("nan")), ("noise_sd", 1e-9)]:
         p = W.gaussian_problem(0.2, 5.0, 101, 25.0)
         setattr(p, field, val)
         out.append(p)
@@ -126,8 +126,9 @@ def test_invalid_problem_rejected_before_device_use(U):
 
 
 def test_coding_struct_and_argument_checks(U):
-    # ucp_coding_problem has the layout of ucp_problem with lam in place of k
-    assert C.sizeof(U.CodingProblem) == C.sizeof(U.Problem)
+    # ucp_coding_problem: the fields of ucp_problem up to n_y, lam in place of
+    # k, no noise_sd (its noise is U(-1, 1))
+    assert C.sizeof(U.CodingProblem) == C.sizeof(U.Problem) - 8
     lib = U.library()
     fake = C.c_void_p(1)
     S = U.make_search(W.Search(-4, 4, 3, 9))

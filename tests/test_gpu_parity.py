@@ -51,7 +51,8 @@ def py_mask(orc, p, u0, u1):
     f, _ = orc.prior(p)
     x1 = orc.grid(p.x_lo, p.x_hi, p.n_x) + u0
     y = orc.grid(p.y_lo, p.y_hi, p.n_y)
-    py = np.array([np.sum(f * np.exp(-0.5 * (yy - x1) ** 2)) for yy in y])
+    sw = getattr(p, "noise_sd", 1.0)
+    py = np.array([np.sum(f * np.exp(-0.5 * ((yy - x1) / sw) ** 2)) for yy in y])
     return py >= 1e-9 * py.max()
 
 
@@ -74,7 +75,15 @@ CASES = {
     # noise sds loses 3.5e-12 of it (the FP64 window is 11 sds)
     "s10": lambda: W.Case("sigma10-k0.05-sign", W.gaussian_problem(0.05, 10.0, 2001, 50.0), W.Search(-55, 55, 3, 21),
                           3, W.init_sign(W.gaussian_problem(0.05, 10.0, 2001, 50.0), 10.0), 10.0),
+    # noise w ~ N(0, 0.7^2): every window, weight and normalisation in noise sds
+    "noise0.7": lambda: _noise_case(0.7),
 }
+
+
+def _noise_case(sw):
+    p = W.gaussian_problem(0.25, 4.0, 1201, 25.0)
+    p.noise_sd = sw
+    return W.Case(f"noise{sw}", p, W.Search(-30, 30, 3, 21), 3, W.init_random_steps(p, 4.0, 12), 4.0)
 
 
 # ------------------------------------------------------------- objective
@@ -325,3 +334,84 @@ def test_wider_fp32_band_same_result_more_fp64_sums(env):
     for x, z in zip(a, b):
         assert np.array_equal(x, z)
     assert e1 > e0
+
+
+def test_noise_sd_scaling_is_exact_on_gpu(env):
+    """Doubling every length and the noise sd scales the discrete problem
+    exactly in binary64 (the log prior only shifts by log 2, which the u1
+    weights' max-shift removes up to rounding), and the kernels' FP32 forms
+    too (alpha halves as the differences double; the offsets in noise sds
+    are unchanged): the GPU solve of the doubled problem is the unit one
+    times 2 (u0 bit for bit, u1 to rounding) and 4 (J), in every
+    arithmetic.  (In the FP32 modes u1's weights are FP32 exponentials of
+    logits that differ by that rounding, so u1 agrees to the FP32 weights'
+    precision there.)"""
+    U, orc, torch = env
+    c = W.small_case()
+    p1, s1 = c.prob, c.search
+    p2 = W.Problem(k=p1.k, comps=[(1.0, 0.0, 10.0)], x_lo=-50.0, x_hi=50.0, n_x=p1.n_x, y_lo=-50.0, y_hi=50.0,
+                   n_y=p1.n_y, noise_sd=2.0)
+    s2 = W.Search(2 * s1.u_lo, 2 * s1.u_hi, s1.levels, s1.cands)
+    for prec in ("fp32_kahan", "fp32", "fp64"):
+        a = [host(t) for t in U.solve(p1, s1, 3, dev(torch, c.u0_init), prec)]
+        b = [host(t) for t in U.solve(p2, s2, 3, dev(torch, 2.0 * c.u0_init), prec)]
+        assert np.array_equal(b[0], 2.0 * a[0]), prec
+        tol = 1e-13 if prec == "fp64" else 1e-7
+        assert np.max(np.abs(b[1] - 2.0 * a[1])) <= tol * np.max(np.abs(b[1])), prec
+        assert np.max(np.abs(b[2] - 4.0 * a[2]) / b[2]) <= 1e-13, prec
+
+
+def test_handle_budget(env):
+    """ucp_create's workspace budget: a solve whose workspace exceeds it
+    fails with UCP_ENOMEM and enqueues nothing; one that fits runs."""
+    import ctypes as C
+
+    U, orc, torch = env
+    lib = U.library()
+    c = W.small_case()
+    P, S = U.make_problem(c.prob), U.make_search(c.search)
+    fp = U.footprint(c.prob, c.search, 2)
+    u0 = dev(torch, c.u0_init)
+    out0 = torch.empty_like(u0)
+    out1 = torch.empty(c.prob.n_y, dtype=torch.float64, device="cuda")
+    J = torch.empty(3, dtype=torch.float64, device="cuda")
+    for budget, want in ((fp // 4, U.ENOMEM), (4 * fp, U.OK)):
+        h = C.c_void_p()
+        assert lib.ucp_create(C.byref(h), 0, budget) == U.OK
+        rc = lib.ucp_solve(h, C.byref(P), C.byref(S), 1, 2, C.c_void_p(u0.data_ptr()), C.c_void_p(out0.data_ptr()),
+                           C.c_void_p(out1.data_ptr()), C.c_void_p(J.data_ptr()), None)
+        lib.ucp_destroy(h)
+        assert rc == want, (budget, rc, U.last_error())
+    ref = [host(t) for t in U.solve(c.prob, c.search, 2, u0)]
+    assert np.array_equal(host(J), ref[2])
+
+
+def test_far_apart_positions_coarse_grid(env):
+    """FP64 passes over the union of several positions' windows (the
+    objective's rows four at a time, the selection's winner with a distant
+    incumbent) on a coarse grid (dy = 0.1, so one wave step spans 6.4 noise
+    sds): x1 alternates between -30 and +30 from point to point, so each
+    union starts 60 sds away from half its positions, whose weights must
+    still be seeded exactly before their windows.  Objective within 1e-12 of
+    the oracle; an update from there matches the oracle's decisions and L_0."""
+    U, orc, torch = env
+    p = W.gaussian_problem(0.2, 5.0, 801, 40.0)
+    x = orc.grid(p.x_lo, p.x_hi, p.n_x)
+    u0 = np.where(np.arange(p.n_x) % 2 == 0, 30.0, -30.0) - x
+    u1 = orc.update_u1(p, u0)
+    J = orc.objective(p, u0, u1)
+    Jg = host(U.objective(p, dev(torch, u0), dev(torch, u1)))[0]
+    assert abs(Jg - J) <= 1e-12 * J, (Jg, J)
+    s = W.Search(-75, 75, 3, 21)
+    ref, Bref = orc.argmin(p, s, u1, u0)
+    f, _ = orc.prior(p)
+    for prec in ("fp32_kahan", "fp64"):
+        got, L0 = U.argmin_adaptive(p, s, dev(torch, u1), dev(torch, u0), prec, want_l0=True)
+        got, L0 = host(got), host(L0)
+        diff = np.nonzero(got != ref)[0]
+        for i in diff:
+            assert orc.B(p, u1, x[i], got[i]) <= Bref[i] * (1 + near_tie()), (prec, i)
+        assert len(diff) <= 1
+        ok = f > 1e-280
+        Lref = f * np.array([orc.B(p, u1, x[i], got[i]) for i in range(p.n_x)])
+        assert np.max(np.abs(L0[ok] - Lref[ok]) / Lref[ok]) <= 1e-12, prec
