@@ -156,6 +156,25 @@ int ucp_argmin_adaptive(ucp_handle* h, const ucp_problem* prob, const ucp_search
                         ucp_prec prec, const double* u1, const double* u0_in,
                         double* u0_out, double* L0_out, void* stream);
 
+/* ucp_argmin_adaptive for callers that cannot allocate device memory (code
+ * under HIP graph capture, serving loops and harnesses that forbid
+ * hipMalloc): the same update, kernels and results, with the workspace
+ * taken from a fixed 64 MiB device array that the library holds on each
+ * GPU it runs on until the process ends, instead of the handle's
+ * workspace.  The call allocates nothing (no hipMalloc, hipFree, pinned
+ * host memory or library routine that allocates) and issues no
+ * hipMemsetAsync; the caller passes every input and output as for
+ * ucp_argmin_adaptive (u0_in and u0_out may alias).  Every call on one GPU
+ * shares that GPU's array: calls that overlap on one GPU (other streams,
+ * other handles or threads) race and must be ordered by the caller.
+ * Errors: as ucp_argmin_adaptive, and UCP_EINVAL when the problem needs
+ * more scratch than the array holds (64 MiB: the 20001-node grid with
+ * 5 x 16 candidates needs 14.2 MiB, the 65536-node grid with 4 x 32 needs
+ * 36.8 MiB; the need grows with n_x (cands + 1) times the window segments). */
+int ucp_argmin_adaptive_noalloc(ucp_handle* h, const ucp_problem* prob, const ucp_search* search,
+                                ucp_prec prec, const double* u1, const double* u0_in,
+                                double* u0_out, double* L0_out, void* stream);
+
 /* Second controller by its closed form, the conditional mean
  * u1(y_j) = sum_i x1_i f_i phi(y_j - x1_i) / sum_i f_i phi(y_j - x1_i),
  * x1_i = x_i + u0[i], the exact minimiser of the discrete marginal cost

@@ -73,6 +73,7 @@ _sigs = {
     "ucp_destroy": ([_vp], None),
     "ucp_marginal_cost": ([_vp, _P(Problem), C.c_int, _vp, _vp, C.c_int64, _vp, _vp], C.c_int),
     "ucp_argmin_adaptive": ([_vp, _P(Problem), _P(Search), C.c_int, _vp, _vp, _vp, _vp, _vp], C.c_int),
+    "ucp_argmin_adaptive_noalloc": ([_vp, _P(Problem), _P(Search), C.c_int, _vp, _vp, _vp, _vp, _vp], C.c_int),
     "ucp_update_u1": ([_vp, _P(Problem), C.c_int, _vp, _vp, _vp], C.c_int),
     "ucp_objective": ([_vp, _P(Problem), _vp, _vp, _vp, _vp], C.c_int),
     "ucp_solve": ([_vp, _P(Problem), _P(Search), C.c_int, C.c_int32, _vp, _vp, _vp, _vp, _vp], C.c_int),
@@ -224,6 +225,23 @@ def argmin_adaptive(prob, search, u1, u0, prec="fp32_kahan", want_l0=False):
                                     _vp(u0.data_ptr()), _vp(out.data_ptr()),
                                     _vp(l0.data_ptr() if l0 is not None else 0), _stream(d)))
     return (out, l0) if want_l0 else out
+
+
+def argmin_adaptive_noalloc(prob, search, u1, u0, out, l0=None, prec="fp32_kahan"):
+    """ucp_argmin_adaptive_noalloc: the u0 update into the caller's tensors
+    ``out`` (and ``l0``), with the library's fixed scratch array; nothing is
+    allocated by the library."""
+    P, S = make_problem(prob), make_search(search)
+    _dev_f64(u1, P.n_y, "u1")
+    _dev_f64(u0, P.n_x, "u0")
+    _dev_f64(out, P.n_x, "out")
+    if l0 is not None:
+        _dev_f64(l0, P.n_x, "l0")
+    d = _dev(u0)
+    _check(_lib.ucp_argmin_adaptive_noalloc(handle(d), C.byref(P), C.byref(S), _prec(prec), _vp(u1.data_ptr()),
+                                            _vp(u0.data_ptr()), _vp(out.data_ptr()),
+                                            _vp(l0.data_ptr() if l0 is not None else 0), _stream(d)))
+    return out
 
 
 def update_u1(prob, u0, prec="fp32_kahan"):
