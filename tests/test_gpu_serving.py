@@ -10,7 +10,12 @@ in ``tests/golden/serving-requests-1001-4001.npz`` by
 ``tests/golden/make_serving_requests.py`` (oracle calls only): J within
 1e-6 relative at every round, u0 equal at every point but at most 0.1%
 (FP64 near-ties) and u1 within 2e-5 where the output density is not
-negligible.  Every served request (the larger ones too) is also bitwise
+negligible.  These problems are symmetric (centred prior, symmetric grids
+and search, odd initial controller), so the point x0 = 0 has two mirror
+minima of exactly equal cost; a solve that takes the other one continues as
+the mirror image of the oracle's (u0(x) -> -u0(-x), u1(y) -> -u1(-y), the
+same J), which is equally correct: the check accepts either image, the
+mirrored positions to within rounding (1e-12).  Every served request (the larger ones too) is also bitwise
 equal to the same request solved alone.
 """
 import os
@@ -77,14 +82,19 @@ def test_served_requests_match_oracle(env):
         u0, u1, J = res[r]
         Jr = g[f"J_{r}"]
         rel = np.max(np.abs(J - Jr) / Jr)
-        nd = int(np.sum(u0 != g[f"u0_{r}"]))
-        m = _density_mask(p, g[f"u0_{r}"])
-        e1 = np.max(np.abs(u1 - g[f"u1_{r}"])[m])
-        print(f"request {r} (n = {p.n_x}, k = {p.k:.3f}, sigma = {c.sigma:.3f}): J rel err {rel:.2e}, "
-              f"u0 differs at {nd} points, u1 err {e1:.2e}")
         assert rel <= 1e-6, r
-        assert nd <= p.n_x // 1000, r
-        assert e1 <= 2e-5, r
+        m = _density_mask(p, g[f"u0_{r}"])
+        images = [("direct", g[f"u0_{r}"], g[f"u1_{r}"], 0.0)]
+        if p.comps[0][1] == 0.0 and p.x_lo == -p.x_hi and p.y_lo == -p.y_hi and c.search.u_lo == -c.search.u_hi:
+            images.append(("mirror", -g[f"u0_{r}"][::-1], -g[f"u1_{r}"][::-1], 1e-12))
+        ok = []
+        for name, ref0, ref1, tol in images:
+            nd = int(np.sum(np.abs(u0 - ref0) > tol * np.maximum(1.0, np.abs(ref0))))
+            e1 = np.max(np.abs(u1 - ref1)[m if name == "direct" else m[::-1]])
+            print(f"request {r} (n = {p.n_x}, k = {p.k:.3f}, sigma = {c.sigma:.3f}) {name}: J rel err {rel:.2e}, "
+                  f"u0 differs at {nd} points, u1 err {e1:.2e}")
+            ok.append(nd <= p.n_x // 1000 and e1 <= 2e-5)
+        assert any(ok), r
     # in the mix = alone, for every request served
     for r in order:
         c = trace[r].case
