@@ -555,6 +555,51 @@ def bench_w2(a):
     print(json.dumps(res), flush=True)
 
 
+def bench_alg1(a):
+    """The paper's generic solver (Algorithm 1): Witsenhausen k = 0.2, sigma =
+    5, grids of a.alg1_n nodes on [-25, 25], both controllers initialised to
+    the identity (Section III-D), N = 20 iterations per round, r = 2 nodes per
+    direction, p = 1e-10 (Section IV), local-update gradient step 0.1; one
+    step is one whole solve to termination (or the round cap), FP64."""
+    import numpy as np
+    import torch
+
+    import paper_1908_04489_amd as U
+    import workloads as W
+
+    p = W.gaussian_problem(0.2, 5.0, a.alg1_n, 25.0)
+    x = torch.as_tensor(W.nodes(p.x_lo, p.x_hi, p.n_x)).cuda()
+    y = torch.as_tensor(W.nodes(p.y_lo, p.y_hi, p.n_y)).cuda()
+    name = f"alg1-wits-{p.n_x}"
+    print(f"# {name}: N = 20, r = 2, p = 1e-10, identity init", file=sys.stderr, flush=True)
+    for w in range(a.warmup):
+        U.alg1_solve(p, x, y, max_rounds=a.alg1_rounds)
+    st = torch.cuda.current_stream()
+    torch.cuda.synchronize()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record(st)
+    for k in range(a.steps):
+        u0, u1, J, NL = U.alg1_solve(p, x, y, max_rounds=a.alg1_rounds)
+        print(f"# step {k} done: {len(NL)} rounds, J = {J[-1].item():.9f}", file=sys.stderr, flush=True)
+    ev1.record(st)
+    torch.cuda.synchronize()
+    ms = ev0.elapsed_time(ev1) / a.steps
+    Jh = J.cpu().numpy()
+    res = {"metric": "generic-solver (Algorithm 1) solves/s", "value": 1e3 / ms, "unit": "solves/s", "n_gpus": 1,
+           "steps": a.steps, "warmup": a.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+           "config": {"workload": name, "n_x": p.n_x, "n_y": p.n_y, "k": 0.2, "sigma": 5.0, "N": 20, "r": 2,
+                      "p": 1e-10, "tau": 0.1, "init": "identity", "max_rounds": a.alg1_rounds},
+           "rounds": len(NL), "NL_per_round": NL, "J_initial": float(Jh[0]), "J_final": float(Jh[-1]),
+           "J_paper_context": 0.166897}
+    if not a.no_check:
+        import oracle
+
+        Jo = oracle.objective(p, u0.cpu().numpy(), u1.cpu().numpy())
+        res["J_final_rel_err_vs_oracle_objective"] = abs(Jh[-1] - Jo) / Jo
+    print(json.dumps(res), flush=True)
+
+
 def w2_cpu_baseline(case):
     """The oracle's 2-D functions, as they stand, on a bounded sample of the
     same workload scaled to one whole solve: the search on evenly spaced
@@ -660,6 +705,29 @@ def kernel_breakdown(U, step):
     return {k: v[0] for k, v in prof.items()}
 
 
+def peak_probe(a):
+    """Issue rates of FP32 FMA, the FP32 base-2 exponential and FP64 FMA on
+    this GPU (every wave slot busy, 8 independent chains per lane), against
+    the published figures: 256 CUs x 128 FP32 lanes x 2.4 GHz = 78.6e12 FP32
+    lane-operations/s without packed math, and the FP64 vector rate, half
+    of that.  The exponential's cost in FMA slots is the ratio of the two
+    FP32 rates."""
+    import paper_1908_04489_amd as U
+
+    out = {}
+    for kind in ("fma32", "exp32", "fma64"):
+        out[kind] = U.peak_probe(kind)
+        print(f"# {kind}: {out[kind]:.3e} lane-ops/s", file=sys.stderr, flush=True)
+    res = {"metric": "VALU issue rate", "value": out["fma32"], "unit": "lane-ops/s", "n_gpus": 1, "steps": 1,
+           "warmup": 1, "ms_per_step": None, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+           "dtype": "f32", "data": "synthetic", "config": {"workload": "peak-probe", "blocks": 8192, "iters": 4096,
+                                                           "chains": 8},
+           "fma32_lane_ops_per_s": out["fma32"], "exp32_lane_ops_per_s": out["exp32"],
+           "fma64_lane_ops_per_s": out["fma64"], "fma32_frac_of_published": out["fma32"] / PEAK_SLOTS,
+           "fma64_frac_of_published": out["fma64"] / (PEAK_SLOTS / 2), "exp32_slots": out["fma32"] / out["exp32"]}
+    print(json.dumps(res), flush=True)
+
+
 def copy_calibration():
     """Plain device-to-device copies of a known size (3 x 256 MiB), run under
     rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE to scale those counters to bytes."""
@@ -679,7 +747,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="headline",
                     help="headline (64 x 65536 batch + serving + CPU baseline), paper (one 20001-node solve), "
-                         "small, batch, serving, sweep, coding, w2, copy-calibration")
+                         "small, batch, serving, sweep, coding, w2, alg1, peak-probe, copy-calibration")
     ap.add_argument("--prec", default="fp32_kahan")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-check", action="store_true", help="skip the FP64 oracle check of the final J")
@@ -690,6 +758,8 @@ def main():
     ap.add_argument("--sweep-n", type=int, default=20001, help="sweep: grid nodes")
     ap.add_argument("--sweep-seeds", type=int, default=9, help="sweep: seeds per (k, sigma)")
     ap.add_argument("--sweep-rows", type=int, default=48, help="sweep: sampled rows per check")
+    ap.add_argument("--alg1-n", type=int, default=20001, help="alg1: grid nodes")
+    ap.add_argument("--alg1-rounds", type=int, default=200, help="alg1: cap on rounds")
     a = ap.parse_args()
     if a.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path (the solver shards over x0 "
@@ -709,6 +779,10 @@ def main():
         return bench_coding(a)
     if a.workload == "w2":
         return bench_w2(a)
+    if a.workload == "peak-probe":
+        return peak_probe(a)
+    if a.workload == "alg1":
+        return bench_alg1(a)
     if a.workload == "copy-calibration":
         return copy_calibration()
 

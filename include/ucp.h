@@ -238,6 +238,16 @@ int ucp_last_counts(ucp_handle* h, uint64_t* terms, uint64_t* evaluated, uint64_
 int ucp_profile(ucp_handle* h, int enable);
 int ucp_profile_read(ucp_handle* h, int kind, double* total_ms, int64_t* launches);
 
+/* Diagnostic, not part of the solver: the issue rate of one VALU operation
+ * the kernels are built from - kind 0 FP32 FMA, 1 the FP32 base-2
+ * exponential, 2 FP64 FMA - as lane-operations per second, with `blocks`
+ * blocks of 256 lanes each running 8 independent chains of `iters`
+ * operations (a second, timed launch after a warm-up).  Allocates a small
+ * device buffer and synchronises `stream`.  This fixes the VALU peak the
+ * marginal-cost kernel's roofline is quoted against.
+ * Errors: UCP_EINVAL, UCP_ENOMEM, UCP_EHIP. */
+int ucp_peak_probe(int kind, int32_t blocks, int32_t iters, double* lane_ops_per_s, void* stream);
+
 /* B independent solves advanced together: every kernel launch covers all
  * instances still running (one flat work list per launch), each instance
  * with its own problem, search and iteration count.  Per-instance results
@@ -248,6 +258,67 @@ int ucp_solve_batch(ucp_handle* h, int32_t B, const ucp_problem* probs,
                     const ucp_search* searches, ucp_prec prec, const int32_t* iters,
                     const double* const* u0_init, double* const* u0_out,
                     double* const* u1_out, double* const* J_hist, void* stream);
+
+/* ---- The paper's generic solver (Algorithm 1, Sections III-B to III-D) --
+ * Both controllers are improved by the paper's own methods instead of the
+ * coarse-to-fine search and the closed form: local updates (a modified
+ * Newton step on each point's marginal cost) and partial exhaustion (each
+ * point takes the best of the values its controller holds at the grid
+ * nodes within r of it, the domain-ball set of Eq. (2)), the N iterations
+ * of each round shared between the two by their last improvements, until
+ * a round improves J by at most p.  Everything is FP64; the windows are
+ * those of the FP64 sums above (11 noise sds).  Readings where the paper is
+ * silent: the local update of u0 works on B = L_0 / f (the Newton step is
+ * the same; the gradient step u - tau B' does not vanish where f
+ * underflows); a phase's improvement is |J before - J after|; partial
+ * exhaustion compares candidates by the selection rule of the search
+ * (relative tie band, nearest to the point's own value, then the smaller
+ * u), every point of a controller from the same previous array; the local
+ * update of u1 is the Newton step of the quadratic C_1, i.e. exactly the
+ * closed form ucp_update_u1 computes in FP64 mode. */
+typedef struct ucp_alg1_params {
+  int32_t N;          /* iterations per round, >= 2 (the paper: 20) */
+  int32_t r;          /* partial-exhaustion radius in grid nodes: 1 or 2 (the paper: 2) */
+  double p;           /* precision: stop once a round's two improvements sum to <= p (the paper: 1e-10) */
+  double tau;         /* gradient step where the curvature is not positive, > 0 */
+  double tie_rel64;   /* relative tie band of partial exhaustion; 0 selects 1e-12 */
+  int32_t max_rounds; /* cap on rounds, >= 1 */
+  int32_t pad_;
+} ucp_alg1_params;
+
+/* One local update of u0 (Section III-D, Local Update): for every x_i, with
+ * u = u0_in[i] and B'(u), B''(u) the first two derivatives of
+ * B(u; x_i) = L_0(u, x_i) / f(x_i) (Gaussian-weighted moments over the
+ * window), u0_out[i] = u - B'/B'' where B'' > 0, else u - tau B'.
+ * u1: [n_y]; u0_in, u0_out: [n_x] (may alias).  Errors: UCP_EINVAL. */
+int ucp_alg1_local_u0(ucp_handle* h, const ucp_problem* prob, double tau, const double* u1,
+                      const double* u0_in, double* u0_out, void* stream);
+
+/* One partial exhaustion of u0 (Section III-D, Partial Exhaustion, and
+ * Eq. (2)): u0_out[i] = the best, by B(.; x_i) and the selection rule, of
+ * u0_in at the nodes i - r .. i + r of the grid.  u0_in, u0_out may alias.
+ * Errors: UCP_EINVAL (also r not 1 or 2). */
+int ucp_alg1_pe_u0(ucp_handle* h, const ucp_problem* prob, double tie_rel64, int32_t r, const double* u1,
+                   const double* u0_in, double* u0_out, void* stream);
+
+/* One partial exhaustion of u1: u1_out[j] = the best of u1_in at the nodes
+ * j - r .. j + r by C_1(u, y_j) = dx sum_i f_i phi(y_j - x1_i)(x1_i - u)^2
+ * (x1 = x + u0), with the weights max-shifted per y_j (a positive factor
+ * per node, which changes neither the order nor the relative band).
+ * u1_in, u1_out may alias.  Errors: UCP_EINVAL. */
+int ucp_alg1_pe_u1(ucp_handle* h, const ucp_problem* prob, double tie_rel64, int32_t r, const double* u0,
+                   const double* u1_in, double* u1_out, void* stream);
+
+/* Algorithm 1 from (u0_init, u1_init) (the paper initialises both to the
+ * identity): J_log (device, [1 + 2 max_rounds]) receives J initially and
+ * after each phase (local updates, then partial exhaustion) of each round;
+ * NL_log (HOST, [max_rounds], or NULL) the local-update iterations of each
+ * round; *rounds_out (HOST) the rounds run.  Reads J back after every
+ * phase and synchronises the stream before returning.
+ * Errors: UCP_EINVAL, UCP_ENONFINITE. */
+int ucp_alg1_solve(ucp_handle* h, const ucp_problem* prob, const ucp_alg1_params* params,
+                   const double* u0_init, const double* u1_init, double* u0_out, double* u1_out,
+                   double* J_log, int32_t* NL_log, int32_t* rounds_out, void* stream);
 
 /* ---- Zero-delay source-channel coding (Section V-B) --------------------
  * x0 ~ prior f (the paper's N(0, 1), or a Gaussian mixture), y0 = x0,

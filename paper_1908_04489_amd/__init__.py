@@ -54,6 +54,11 @@ class CodingProblem(C.Structure):
     ]
 
 
+class Alg1Params(C.Structure):
+    _fields_ = [("N", C.c_int32), ("r", C.c_int32), ("p", C.c_double), ("tau", C.c_double),
+                ("tie_rel64", C.c_double), ("max_rounds", C.c_int32), ("pad_", C.c_int32)]
+
+
 class Search(C.Structure):
     _fields_ = [("u_lo", C.c_double), ("u_hi", C.c_double), ("levels", C.c_int32), ("cands", C.c_int32),
                 ("tie_rel64", C.c_double), ("band_rel32", C.c_double)]
@@ -75,11 +80,17 @@ _sigs = {
     "ucp_argmin_adaptive": ([_vp, _P(Problem), _P(Search), C.c_int, _vp, _vp, _vp, _vp, _vp], C.c_int),
     "ucp_argmin_adaptive_noalloc": ([_vp, _P(Problem), _P(Search), C.c_int, _vp, _vp, _vp, _vp, _vp], C.c_int),
     "ucp_update_u1": ([_vp, _P(Problem), C.c_int, _vp, _vp, _vp], C.c_int),
+    "ucp_alg1_local_u0": ([_vp, _P(Problem), C.c_double, _vp, _vp, _vp, _vp], C.c_int),
+    "ucp_alg1_pe_u0": ([_vp, _P(Problem), C.c_double, C.c_int32, _vp, _vp, _vp, _vp], C.c_int),
+    "ucp_alg1_pe_u1": ([_vp, _P(Problem), C.c_double, C.c_int32, _vp, _vp, _vp, _vp], C.c_int),
+    "ucp_alg1_solve": ([_vp, _P(Problem), _vp, _vp, _vp, _vp, _vp, _vp, _P(C.c_int32), _P(C.c_int32), _vp],
+                       C.c_int),
     "ucp_objective": ([_vp, _P(Problem), _vp, _vp, _vp, _vp], C.c_int),
     "ucp_solve": ([_vp, _P(Problem), _P(Search), C.c_int, C.c_int32, _vp, _vp, _vp, _vp, _vp], C.c_int),
     "ucp_solve_batch": ([_vp, C.c_int32, _P(Problem), _P(Search), C.c_int, _P(C.c_int32), _P(_vp), _P(_vp),
                          _P(_vp), _P(_vp), _vp], C.c_int),
     "ucp_profile": ([_vp, C.c_int], C.c_int),
+    "ucp_peak_probe": ([C.c_int, C.c_int32, C.c_int32, _P(C.c_double), _vp], C.c_int),
     "ucp_profile_read": ([_vp, C.c_int, _P(C.c_double), _P(C.c_int64)], C.c_int),
     "ucp_last_counts": ([_vp, _P(C.c_uint64), _P(C.c_uint64), _P(C.c_uint64)], C.c_int),
     "ucp_footprint": ([_P(Problem), _P(Search), C.c_int, C.c_int32, _P(C.c_size_t)], C.c_int),
@@ -575,3 +586,74 @@ def w2_solve(prob, search, iters, u0_init):
     _check(_lib.ucp_w2_solve(handle(d), C.byref(P), C.byref(S), int(iters), _vp(u0_init.data_ptr()),
                              _vp(u0.data_ptr()), _vp(u1.data_ptr()), _vp(J.data_ptr()), _stream(d)))
     return u0, u1, J
+
+
+# ------------------------------------------------------------------
+# The paper's generic solver (Algorithm 1).
+
+def alg1_local_u0(prob, tau, u1, u0):
+    torch = _torch()
+    P = make_problem(prob)
+    _dev_f64(u1, P.n_y, "u1")
+    _dev_f64(u0, P.n_x, "u0")
+    out = torch.empty_like(u0)
+    d = _dev(u0)
+    _check(_lib.ucp_alg1_local_u0(handle(d), C.byref(P), float(tau), _vp(u1.data_ptr()), _vp(u0.data_ptr()),
+                                  _vp(out.data_ptr()), _stream(d)))
+    return out
+
+
+def alg1_pe_u0(prob, u1, u0, r=2, tie=0.0):
+    torch = _torch()
+    P = make_problem(prob)
+    _dev_f64(u1, P.n_y, "u1")
+    _dev_f64(u0, P.n_x, "u0")
+    out = torch.empty_like(u0)
+    d = _dev(u0)
+    _check(_lib.ucp_alg1_pe_u0(handle(d), C.byref(P), float(tie), int(r), _vp(u1.data_ptr()), _vp(u0.data_ptr()),
+                               _vp(out.data_ptr()), _stream(d)))
+    return out
+
+
+def alg1_pe_u1(prob, u0, u1, r=2, tie=0.0):
+    torch = _torch()
+    P = make_problem(prob)
+    _dev_f64(u0, P.n_x, "u0")
+    _dev_f64(u1, P.n_y, "u1")
+    out = torch.empty_like(u1)
+    d = _dev(u0)
+    _check(_lib.ucp_alg1_pe_u1(handle(d), C.byref(P), float(tie), int(r), _vp(u0.data_ptr()), _vp(u1.data_ptr()),
+                               _vp(out.data_ptr()), _stream(d)))
+    return out
+
+
+def alg1_solve(prob, u0_init, u1_init, N=20, r=2, prec=1e-10, tau=0.1, tie=0.0, max_rounds=100):
+    """Returns (u0, u1, J_log[1 + 2 rounds] as a device tensor, NL_log as a list)."""
+    torch = _torch()
+    P = make_problem(prob)
+    _dev_f64(u0_init, P.n_x, "u0_init")
+    _dev_f64(u1_init, P.n_y, "u1_init")
+    a = Alg1Params()
+    a.N, a.r, a.p, a.tau, a.tie_rel64, a.max_rounds = int(N), int(r), float(prec), float(tau), float(tie), \
+        int(max_rounds)
+    dev = u0_init.device
+    u0 = torch.empty(P.n_x, dtype=torch.float64, device=dev)
+    u1 = torch.empty(P.n_y, dtype=torch.float64, device=dev)
+    J = torch.empty(1 + 2 * int(max_rounds), dtype=torch.float64, device=dev)
+    NL = (C.c_int32 * int(max_rounds))()
+    rounds = C.c_int32()
+    d = _dev(u0_init)
+    _check(_lib.ucp_alg1_solve(handle(d), C.byref(P), C.byref(a), _vp(u0_init.data_ptr()), _vp(u1_init.data_ptr()),
+                               _vp(u0.data_ptr()), _vp(u1.data_ptr()), _vp(J.data_ptr()), NL, C.byref(rounds),
+                               _stream(d)))
+    n = rounds.value
+    return u0, u1, J[:1 + 2 * n], list(NL[:n])
+
+
+def peak_probe(kind, blocks=8192, iters=4096, device=0):
+    """Lane-operations per second of one VALU operation: "fma32", "exp32" or
+    "fma64" (diagnostic; fixes the peak of the roofline)."""
+    k = {"fma32": 0, "exp32": 1, "fma64": 2}[kind]
+    out = C.c_double()
+    _check(_lib.ucp_peak_probe(k, int(blocks), int(iters), C.byref(out), _stream(device)))
+    return out.value

@@ -19,7 +19,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libucp.so")
-SOURCES = ["ucp_kernels.hip", "ucp_coding.hip", "ucp_w2.hip", "ucp_noalloc.hip", "ucp_api.cpp", "ucp_server.cpp"]
+SOURCES = ["ucp_kernels.hip", "ucp_coding.hip", "ucp_w2.hip", "ucp_noalloc.hip", "ucp_probe.hip", "ucp_api.cpp", "ucp_server.cpp"]
 ARCH = os.environ.get("UCP_OFFLOAD_ARCH", "gfx950")
 
 

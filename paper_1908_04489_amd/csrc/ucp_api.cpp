@@ -472,13 +472,15 @@ struct Batch {
 // and launch tables.
 template <typename Fix>
 int setup_batch(ucp_handle* h, Batch& B, std::vector<Inst> insts, const std::vector<std::vector<char>>& phases,
-                std::vector<int32_t>& host_tab, hipStream_t st, Fix fix) {
+                std::vector<int32_t>& host_tab, hipStream_t st, Fix fix, size_t extra = 0, char** extra_out = nullptr) {
   B.n = (int)insts.size();
   size_t bytes = align_up(sizeof(Inst) * B.n) + align_up(sizeof(int32_t) * phases.size() * kKinds * (B.n + 1));
   for (auto& I : insts) bytes += state_bytes(I);
+  bytes += align_up(extra);
   int rc = ensure_ws(h, bytes);
   if (rc) return rc;
   char* base = (char*)h->ws;
+  if (extra_out) *extra_out = base + bytes - align_up(extra);
   B.d_insts = (Inst*)base;
   base += align_up(sizeof(Inst) * B.n);
   B.d_tables = (int32_t*)base;
@@ -725,6 +727,190 @@ int ucp_marginal_cost(ucp_handle* h, const ucp_problem* prob, ucp_prec prec, con
   UCP_TRY(launch_mc(B.launch(0, kKindFree, tab), -1, prec, st), "marginal-cost kernel");
   Launch Lf = B.launch(0, kKindFin, tab);
   UCP_TRY(launch_finish_free(Lf, L0_out, prec, st), "finish kernel");
+  return UCP_OK;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// The paper's generic solver (Algorithm 1): local updates and partial
+// exhaustion for both controllers, adaptive allocation, precision stop.
+
+namespace ucp {
+
+static int check_alg1(const ucp_alg1_params* a) {
+  if (!a) return fail(UCP_EINVAL, "params is NULL");
+  if (a->N < 2 || a->N > 1000000) return fail(UCP_EINVAL, "N must be 2..1e6");
+  if (a->r != 1 && a->r != 2) return fail(UCP_EINVAL, "the partial-exhaustion radius r must be 1 or 2");
+  if (!(a->p >= 0.0) || !std::isfinite(a->p)) return fail(UCP_EINVAL, "p must be finite and >= 0");
+  if (!(a->tau > 0.0) || !std::isfinite(a->tau)) return fail(UCP_EINVAL, "tau must be finite and > 0");
+  if (!(a->tie_rel64 >= 0.0 && a->tie_rel64 <= 1e-3)) return fail(UCP_EINVAL, "tie_rel64 must be in [0, 1e-3]");
+  if (a->max_rounds < 1 || a->max_rounds > 1000000) return fail(UCP_EINVAL, "max_rounds must be 1..1e6");
+  return UCP_OK;
+}
+
+static double alg1_tie(double t) { return t > 0.0 ? t : kTau64; }
+
+// Partial sums of the u1 partial exhaustion: [slices][n_y][2 r + 2].
+static size_t pe_u1_bytes(const Inst& I, int r) { return (size_t)I.u1_slices * I.n_y * (2 * r + 2) * 8; }
+
+}  // namespace ucp
+
+extern "C" {
+
+int ucp_alg1_local_u0(ucp_handle* h, const ucp_problem* prob, double tau, const double* u1, const double* u0_in,
+                      double* u0_out, void* stream) {
+  if (!h) return fail(UCP_EINVAL, "handle is NULL");
+  int rc;
+  if ((rc = check_problem(prob))) return rc;
+  if (!(tau > 0.0) || !std::isfinite(tau)) return fail(UCP_EINVAL, "tau must be finite and > 0");
+  if (!u1 || !u0_in || !u0_out) return fail(UCP_EINVAL, "NULL array argument");
+  UCP_TRY(hipSetDevice(h->device), "hipSetDevice");
+  hipStream_t st = (hipStream_t)stream;
+  std::vector<std::vector<char>> phases(1, std::vector<char>(1, 1));
+  Batch B;
+  std::vector<int32_t> tab;
+  auto fix = [&](int, Inst& I) {
+    I.u1 = const_cast<double*>(u1);  // read only
+    I.terms = nullptr;
+  };
+  if ((rc = setup_batch(h, B, {make_inst(*prob, nullptr, UCP_FP64, 1)}, phases, tab, st, fix))) return rc;
+  Inst& I = B.insts[0];
+  UCP_TRY(clear_state(I, st), "clear state");
+  UCP_TRY(launch_a1_local_u0(B.d_insts, I.n_x, tau, u0_in, I.u0_next, st), "local-update kernel");
+  UCP_TRY(hipMemcpyAsync(u0_out, I.u0_next, sizeof(double) * I.n_x, hipMemcpyDeviceToDevice, st), "copy u0_out");
+  return UCP_OK;
+}
+
+int ucp_alg1_pe_u0(ucp_handle* h, const ucp_problem* prob, double tie_rel64, int32_t r, const double* u1,
+                   const double* u0_in, double* u0_out, void* stream) {
+  if (!h) return fail(UCP_EINVAL, "handle is NULL");
+  int rc;
+  if ((rc = check_problem(prob))) return rc;
+  if (r != 1 && r != 2) return fail(UCP_EINVAL, "r must be 1 or 2");
+  if (!(tie_rel64 >= 0.0 && tie_rel64 <= 1e-3)) return fail(UCP_EINVAL, "tie_rel64 must be in [0, 1e-3]");
+  if (!u1 || !u0_in || !u0_out) return fail(UCP_EINVAL, "NULL array argument");
+  UCP_TRY(hipSetDevice(h->device), "hipSetDevice");
+  hipStream_t st = (hipStream_t)stream;
+  std::vector<std::vector<char>> phases(1, std::vector<char>(1, 1));
+  Batch B;
+  std::vector<int32_t> tab;
+  auto fix = [&](int, Inst& I) {
+    I.u1 = const_cast<double*>(u1);  // read only
+    I.terms = nullptr;
+  };
+  if ((rc = setup_batch(h, B, {make_inst(*prob, nullptr, UCP_FP64, 1)}, phases, tab, st, fix))) return rc;
+  Inst& I = B.insts[0];
+  UCP_TRY(clear_state(I, st), "clear state");
+  UCP_TRY(launch_a1_pe_u0(B.d_insts, I.n_x, r, alg1_tie(tie_rel64), u0_in, I.u0_next, st), "exhaustion kernel");
+  UCP_TRY(hipMemcpyAsync(u0_out, I.u0_next, sizeof(double) * I.n_x, hipMemcpyDeviceToDevice, st), "copy u0_out");
+  return UCP_OK;
+}
+
+int ucp_alg1_pe_u1(ucp_handle* h, const ucp_problem* prob, double tie_rel64, int32_t r, const double* u0,
+                   const double* u1_in, double* u1_out, void* stream) {
+  if (!h) return fail(UCP_EINVAL, "handle is NULL");
+  int rc;
+  if ((rc = check_problem(prob))) return rc;
+  if (r != 1 && r != 2) return fail(UCP_EINVAL, "r must be 1 or 2");
+  if (!(tie_rel64 >= 0.0 && tie_rel64 <= 1e-3)) return fail(UCP_EINVAL, "tie_rel64 must be in [0, 1e-3]");
+  if (!u0 || !u1_in || !u1_out) return fail(UCP_EINVAL, "NULL array argument");
+  UCP_TRY(hipSetDevice(h->device), "hipSetDevice");
+  hipStream_t st = (hipStream_t)stream;
+  std::vector<std::vector<char>> phases(1, std::vector<char>(1, 1));
+  Batch B;
+  std::vector<int32_t> tab;
+  auto fix = [&](int, Inst& I) {
+    I.u0 = const_cast<double*>(u0);  // read only
+    I.terms = nullptr;
+  };
+  Inst I0 = make_inst(*prob, nullptr, UCP_FP64, 1);
+  char* part = nullptr;
+  if ((rc = setup_batch(h, B, {I0}, phases, tab, st, fix, pe_u1_bytes(I0, r), &part))) return rc;
+  Inst& I = B.insts[0];
+  UCP_TRY(clear_state(I, st), "clear state");
+  UCP_TRY(launch_prior(B.launch(0, kKindPrior, tab), st), "prior kernel");
+  UCP_TRY(launch_a1_pe_u1(I, B.d_insts, r, alg1_tie(tie_rel64), u1_in, (double*)part, I.u1, st), "exhaustion kernels");
+  UCP_TRY(hipMemcpyAsync(u1_out, I.u1, sizeof(double) * I.n_y, hipMemcpyDeviceToDevice, st), "copy u1_out");
+  return UCP_OK;
+}
+
+int ucp_alg1_solve(ucp_handle* h, const ucp_problem* prob, const ucp_alg1_params* a, const double* u0_init,
+                   const double* u1_init, double* u0_out, double* u1_out, double* J_log, int32_t* NL_log,
+                   int32_t* rounds_out, void* stream) {
+  if (!h) return fail(UCP_EINVAL, "handle is NULL");
+  int rc;
+  if ((rc = check_problem(prob)) || (rc = check_alg1(a))) return rc;
+  if (!u0_init || !u1_init || !u0_out || !u1_out || !J_log || !rounds_out) return fail(UCP_EINVAL, "NULL argument");
+  UCP_TRY(hipSetDevice(h->device), "hipSetDevice");
+  hipStream_t st = (hipStream_t)stream;
+  std::vector<std::vector<char>> phases(1, std::vector<char>(1, 1));
+  Batch B;
+  std::vector<int32_t> tab;
+  Inst I0 = make_inst(*prob, nullptr, UCP_FP64, 1);
+  const size_t part_bytes = pe_u1_bytes(I0, a->r);
+  auto fix = [&](int, Inst& I) {
+    I.J_out = J_log;
+    I.terms = nullptr;
+  };
+  char* extra = nullptr;
+  if ((rc = setup_batch(h, B, {I0}, phases, tab, st, fix, part_bytes + (size_t)I0.n_y * 8 + 256, &extra))) return rc;
+  Inst& I = B.insts[0];
+  double* part = (double*)extra;
+  double* u1t = (double*)(extra + ((part_bytes + 255) & ~(size_t)255));
+  const double tie = alg1_tie(a->tie_rel64);
+  const Inst* dI = B.d_insts;
+  UCP_TRY(hipMemcpyAsync(I.u0, u0_init, sizeof(double) * I.n_x, hipMemcpyDeviceToDevice, st), "copy u0_init");
+  UCP_TRY(hipMemcpyAsync(I.u1, u1_init, sizeof(double) * I.n_y, hipMemcpyDeviceToDevice, st), "copy u1_init");
+  UCP_TRY(clear_state(I, st), "clear state");
+  UCP_TRY(launch_prior(B.launch(0, kKindPrior, tab), st), "prior kernel");
+  // J into J_log[t], read back for the adaptive allocation
+  auto objective = [&](int t, double* Jh) -> int {
+    UCP_TRY(launch_j_rows(B.launch(0, kKindJRows, tab), st), "objective kernel");
+    UCP_TRY(launch_j_reduce_t(B.launch(0, kKindJRed, tab), t, st), "objective reduce kernel");
+    UCP_TRY(hipMemcpyAsync(Jh, J_log + t, sizeof(double), hipMemcpyDeviceToHost, st), "read J");
+    UCP_TRY(hipStreamSynchronize(st), "synchronise");
+    return UCP_OK;
+  };
+  double Jc = 0.0;
+  if ((rc = objective(0, &Jc))) return rc;
+  double IL = a->p, IP = a->p;
+  int32_t NL = a->N / 2, NP = a->N - NL;
+  int32_t rounds = 0;
+  while (IL + IP > a->p && rounds < a->max_rounds) {
+    if (NL_log) NL_log[rounds] = NL;
+    double Jprev = Jc;
+    for (int32_t it = 0; it < NL; ++it) {
+      UCP_TRY(launch_a1_local_u0(dI, I.n_x, a->tau, I.u0, I.u0_next, st), "local-update kernel");
+      UCP_TRY(launch_copy_u0(B.launch(0, kKindCopy, tab), st), "u0 advance kernel");
+      UCP_TRY(launch_u1_partial(B.launch(0, kKindU1p, tab), UCP_FP64, st), "u1 kernel");
+      UCP_TRY(launch_u1_combine(B.launch(0, kKindU1c, tab), st), "u1 combine kernel");
+    }
+    if ((rc = objective(1 + 2 * rounds, &Jc))) return rc;
+    IL = std::fabs(Jprev - Jc);
+    Jprev = Jc;
+    for (int32_t it = 0; it < NP; ++it) {
+      UCP_TRY(launch_a1_pe_u0(dI, I.n_x, a->r, tie, I.u0, I.u0_next, st), "exhaustion kernel");
+      UCP_TRY(launch_copy_u0(B.launch(0, kKindCopy, tab), st), "u0 advance kernel");
+      UCP_TRY(launch_a1_pe_u1(I, dI, a->r, tie, I.u1, part, u1t, st), "exhaustion kernels");
+      UCP_TRY(hipMemcpyAsync(I.u1, u1t, sizeof(double) * I.n_y, hipMemcpyDeviceToDevice, st), "u1 advance");
+    }
+    if ((rc = objective(2 + 2 * rounds, &Jc))) return rc;
+    IP = std::fabs(Jprev - Jc);
+    if (IL + IP > 0.0) {
+      int32_t v = (int32_t)std::floor(IL * (double)a->N / (IL + IP));
+      NL = std::min(std::max(v, 1), a->N - 1);
+    }
+    NP = a->N - NL;
+    ++rounds;
+  }
+  *rounds_out = rounds;
+  int32_t flags = 0;
+  UCP_TRY(hipMemcpyAsync(u0_out, I.u0, sizeof(double) * I.n_x, hipMemcpyDeviceToDevice, st), "copy u0_out");
+  UCP_TRY(hipMemcpyAsync(u1_out, I.u1, sizeof(double) * I.n_y, hipMemcpyDeviceToDevice, st), "copy u1_out");
+  UCP_TRY(hipMemcpyAsync(&flags, I.flags, 4, hipMemcpyDeviceToHost, st), "read flags");
+  UCP_TRY(hipStreamSynchronize(st), "synchronise");
+  if (flags) return fail(UCP_ENONFINITE, "the solve produced non-finite values");
   return UCP_OK;
 }
 

@@ -147,6 +147,16 @@ hipError_t launch_j_rows(const Launch& L, hipStream_t st, hipEvent_t e0 = nullpt
 hipError_t launch_j_reduce(const Launch& L, hipStream_t st);
 hipError_t launch_copy_u0(const Launch& L, hipStream_t st);
 
+// Generic solver (Algorithm 1) on one instance; dI is the device copy of the
+// instance record.  r is the partial-exhaustion radius (1 or 2).
+hipError_t launch_a1_local_u0(const Inst* dI, int n_x, double tau, const double* u0_in, double* u0_out,
+                              hipStream_t st);
+hipError_t launch_a1_pe_u0(const Inst* dI, int n_x, int r, double tie, const double* u0_in, double* u0_out,
+                           hipStream_t st);
+// part: [u1_slices][n_y][2 r + 2] FP64
+hipError_t launch_a1_pe_u1(const Inst& I, const Inst* dI, int r, double tie, const double* u1_in, double* part,
+                           double* u1_out, hipStream_t st);
+
 // Units per instance of each kernel (host helpers, ucp_kernels.hip).
 int32_t units_mc(const Inst& I, int level);
 int32_t units_select(const Inst& I);

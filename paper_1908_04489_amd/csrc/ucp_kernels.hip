@@ -1678,4 +1678,305 @@ hipError_t launch_finish_free(const Launch& L, double* out, int prec, hipStream_
   return hipGetLastError();
 }
 
+// ------------------------------------------- generic solver (Algorithm 1)
+//
+// The paper's own minimiser per controller: local updates (modified Newton
+// on the marginal cost) and partial exhaustion over the values a controller
+// takes on the neighbouring grid nodes (the domain ball of Eq. (2)).  All in
+// FP64; the kernels take the instance record directly (one instance).
+
+namespace {
+
+// B, B' and B'' of one position over a group of W lanes: the window of
+// b64_wave (11 noise sds around the nearest node), the same shifted
+// Gaussian with its reseeded recurrence, and with T_j = (y_j - z) / s^2,
+// e_j = z - u1_j the three sums
+//   S0 = sum g e^2,  S1 = sum g (T e^2 + 2 e),
+//   S2 = sum g ((T^2 - 1/s^2) e^2 + 4 T e + 2),
+// since d phi_s(y - z)/dz = T phi_s.  Returns dy/(s sqrt(2 pi))
+// exp(-delta^2/2) times each.
+template <int W>
+__device__ void b64_derivs(const Inst& I, double z, int lane, double& S0, double& S1, double& S2) {
+  const int jr = nearest_node(I, z);
+  const double delta = ((I.y_lo + (double)jr * I.dy) - z) * I.isw;  // in noise sds
+  const int klo = max(-I.nw64, -jr), khi = min(I.nw64, I.n_y - 1 - jr);
+  const int n = khi - klo + 1;
+  const double dy = I.dy * I.isw, D = (double)W * dy;
+  const double q = exp(-D * D);
+  const double is2 = I.isw * I.isw;
+  const int rs = I.rs64;
+  glb_dptr u1 = (glb_dptr)(I.u1 + jr + klo + lane);
+  double a0 = 0.0, a1 = 0.0, a2 = 0.0;
+  B64Walk w;
+  const int steps = (n + W - 1) / W;
+  for (int m = 0; m < steps; ++m) {
+    if ((m & (rs - 1)) == 0) b64_reseed<W>(w, klo, lane, m, dy, delta, D);
+    if (lane + W * m < n) {
+      const double t = (double)(klo + lane + W * m) * dy + delta;  // (y_j - z) / s
+      const double T = t * I.isw;
+      const double e = z - u1[W * m];
+      const double e2 = e * e;
+      a0 = fma(w.g, e2, a0);
+      a1 = fma(w.g, fma(T, e2, 2.0 * e), a1);
+      a2 = fma(w.g, fma(T * T - is2, e2, fma(4.0 * T, e, 2.0)), a2);
+    }
+    w.g *= w.r;
+    w.r *= q;
+  }
+  const double sc = I.phi_scale * exp(-0.5 * delta * delta);
+  S0 = sc * grp_sum_d<W>(a0);
+  S1 = sc * grp_sum_d<W>(a1);
+  S2 = sc * grp_sum_d<W>(a2);
+}
+
+// The selection rule among n values (relative tie band, nearest to the
+// incumbent, then the smaller u), serially in one lane.
+__device__ int pick_serial(int n, const double* c, const double* B, double inc, double tie) {
+  double m = B[0];
+  for (int s = 1; s < n; ++s) m = fmin(m, B[s]);
+  const double thr = m * (1.0 + tie);
+  int best = -1;
+  double bd = 0.0;
+  for (int s = 0; s < n; ++s) {
+    if (!(B[s] <= thr)) continue;
+    const double d = fabs(c[s] - inc);
+    if (best < 0 || d < bd || (d == bd && c[s] < c[best])) {
+      best = s;
+      bd = d;
+    }
+  }
+  return best < 0 ? 0 : best;
+}
+
+}  // namespace
+
+// Local update of u0: one wave per point.
+__global__ __launch_bounds__(256) void k_a1_local_u0(const Inst* __restrict__ Ip, double tau,
+                                                     const double* __restrict__ u0_in, double* __restrict__ u0_out) {
+  const Inst& I = *Ip;
+  const int lane = (int)threadIdx.x % kWave;
+  const int i = blockIdx.x * (256 / kWave) + (int)threadIdx.x / kWave;
+  if (i >= I.n_x) return;  // whole waves
+  const double u = u0_in[i];
+  const double x = I.x_lo + (double)i * I.dx;
+  double S0, S1, S2;
+  b64_derivs<kWave>(I, x + u, lane, S0, S1, S2);
+  if (lane == 0) {
+    const double B1 = 2.0 * I.k2 * u + S1, B2 = 2.0 * I.k2 + S2;
+    const double v = B2 > 0.0 ? u - B1 / B2 : u - tau * B1;
+    u0_out[i] = v;
+    if (!isfinite(v)) atomicOr(I.flags, 1);
+  }
+}
+
+// Partial exhaustion of u0: one wave per point; the R = 2r + 1 values of
+// u0_in at the nodes within r (an out-of-grid neighbour stands in as the
+// point's own value, which the set holds anyway) share one FP64 pass over
+// the union of their windows.
+template <int R>
+__global__ __launch_bounds__(256) void k_a1_pe_u0(const Inst* __restrict__ Ip, double tie,
+                                                  const double* __restrict__ u0_in, double* __restrict__ u0_out) {
+  const Inst& I = *Ip;
+  const int lane = (int)threadIdx.x % kWave;
+  const int i = blockIdx.x * (256 / kWave) + (int)threadIdx.x / kWave;
+  if (i >= I.n_x) return;
+  constexpr int r = R / 2;
+  const double x = I.x_lo + (double)i * I.dx;
+  const double inc = u0_in[i];
+  double c[R], z[R], v[R];
+#pragma unroll
+  for (int m = 0; m < R; ++m) {
+    const int k = i - r + m;
+    c[m] = (k >= 0 && k < I.n_x) ? u0_in[k] : inc;
+    z[m] = x + c[m];
+  }
+  b64_multi<R>(I, z, lane, v);
+  if (lane == 0) {
+    double B[R];
+#pragma unroll
+    for (int m = 0; m < R; ++m) B[m] = I.k2 * c[m] * c[m] + v[m];
+    const double res = c[pick_serial(R, c, B, inc, tie)];
+    u0_out[i] = res;
+    if (!isfinite(res)) atomicOr(I.flags, 1);
+  }
+}
+
+// Partial exhaustion of u1, first pass: as k_u1_partial<UCP_FP64> (lane =
+// y node, x nodes of one slice staged in LDS, FP64 weights max-shifted,
+// negligible chunks skipped), accumulating for each of the R candidate
+// values c_m = u1_in[j - r + m] the sum of w (x1 - c_m)^2.  Writes
+// [slice][n_y][1 + R]: the slice's maximum and the R sums.
+template <int R>
+__global__ __launch_bounds__(kU1Block) void k_a1_pe_u1_partial(const Inst* __restrict__ Ip,
+                                                               const double* __restrict__ u1_in,
+                                                               double* __restrict__ part) {
+  constexpr int NW = kU1Block / kWave;
+  constexpr int r = R / 2;
+  __shared__ double sX[kU1Chunk];  // x1_i
+  __shared__ double sL[kU1Chunk];  // log f_i
+  __shared__ double sb[4][NW];
+  const Inst& I = *Ip;
+  const int u = blockIdx.x;
+  const int slice = u % I.u1_slices;
+  const int tile = u / I.u1_slices;
+  const int j = tile * kU1Block + (int)threadIdx.x;
+  const bool act = j < I.n_y;
+  const int jj = act ? j : I.n_y - 1;
+  const double y = I.y_lo + (double)jj * I.dy;
+  const int slen = (I.n_x + I.u1_slices - 1) / I.u1_slices;
+  const int i0 = slice * slen, i1 = min(I.n_x, i0 + slen);
+  const double h2 = 0.5 * I.isw * I.isw;
+  const int nx = I.n_x;
+  const double x_lo = I.x_lo, dx = I.dx;
+  const glb_dptr u0g = (glb_dptr)I.u0, lfg = (glb_dptr)I.logf;
+  double c[R];
+#pragma unroll
+  for (int m = 0; m < R; ++m) {
+    const int k = jj - r + m;
+    c[m] = (k >= 0 && k < I.n_y) ? u1_in[k] : u1_in[jj];
+  }
+  // a lower bound on the logit maximum of every node of the tile (as in
+  // k_u1_partial): chunks whose logits all lie kU1Cull below it are skipped
+  const int j0 = tile * kU1Block, j1 = min(I.n_y, j0 + kU1Block) - 1;
+  const double ya = I.y_lo + (double)j0 * I.dy, yb = I.y_lo + (double)j1 * I.dy;
+  double lb = -INFINITY;
+  for (int i = (int)threadIdx.x * kU1Sample; i < nx; i += kU1Block * kU1Sample) {
+    const double x1 = (x_lo + (double)i * dx) + u0g[i];
+    const double da = ya - x1, db = yb - x1;
+    lb = fmax(lb, lfg[i] - h2 * fmax(da * da, db * db));
+  }
+  lb = block_max_d(lb, sb[0]);
+  double M = -INFINITY, acc[R];
+#pragma unroll
+  for (int m = 0; m < R; ++m) acc[m] = 0.0;
+  for (int c0 = i0; c0 < i1; c0 += kU1Chunk) {
+    const int cn = min(kU1Chunk, i1 - c0);
+    __syncthreads();
+    double xmn = INFINITY, xmx = -INFINITY, fmx = -INFINITY;
+    bool bad = false;
+    for (int t = threadIdx.x; t < cn; t += kU1Block) {
+      const int i = c0 + t;
+      const double x1 = (x_lo + (double)i * dx) + u0g[i];
+      const double lf = lfg[i];
+      sX[t] = x1;
+      sL[t] = lf;
+      xmn = fmin(xmn, x1);
+      xmx = fmax(xmx, x1);
+      fmx = fmax(fmx, lf);
+      bad |= !isfinite(x1) || isnan(lf);
+    }
+    for (int o = kWave / 2; o > 0; o >>= 1) {
+      xmn = fmin(xmn, __shfl_xor(xmn, o));
+      xmx = fmax(xmx, __shfl_xor(xmx, o));
+      fmx = fmax(fmx, __shfl_xor(fmx, o));
+    }
+    const bool wbad = __ballot(bad) != 0ull;
+    if (threadIdx.x % kWave == 0) {
+      sb[1][threadIdx.x / kWave] = xmn;
+      sb[2][threadIdx.x / kWave] = xmx;
+      sb[3][threadIdx.x / kWave] = wbad ? NAN : fmx;
+    }
+    __syncthreads();
+    for (int w = 0; w < NW; ++w) {
+      xmn = fmin(xmn, sb[1][w]);
+      xmx = fmax(xmx, sb[2][w]);
+      fmx = fmax(fmx, sb[3][w]);
+      bad |= isnan(sb[3][w]);
+    }
+    const double dist = fmax(0.0, fmax(xmn - yb, ya - xmx));
+    if (!bad && fmx - h2 * dist * dist < lb - kU1Cull) continue;
+    double mc = -INFINITY;
+    for (int t = 0; t < cn; ++t) {
+      const double d = y - sX[t];
+      mc = fmax(mc, sL[t] - h2 * d * d);
+    }
+    if (mc > M) {
+      const double sc = M == -INFINITY ? 0.0 : exp(M - mc);
+#pragma unroll
+      for (int m = 0; m < R; ++m) acc[m] *= sc;
+      M = mc;
+    }
+    if (!(M > -INFINITY)) continue;
+    for (int t = 0; t < cn; ++t) {
+      const double d = y - sX[t];
+      const double w = exp(sL[t] - h2 * d * d - M);
+#pragma unroll
+      for (int m = 0; m < R; ++m) {
+        const double e = sX[t] - c[m];
+        acc[m] = fma(w * e, e, acc[m]);
+      }
+    }
+  }
+  if (!act) return;
+  double* o = part + ((size_t)slice * I.n_y + j) * (R + 1);
+  o[0] = M;
+#pragma unroll
+  for (int m = 0; m < R; ++m) o[1 + m] = acc[m];
+}
+
+// Second pass: merge the slices at the common maximum (in slice order) and
+// apply the selection rule among the R candidates, the node's own value the
+// incumbent.
+template <int R>
+__global__ __launch_bounds__(256) void k_a1_pe_u1_select(const Inst* __restrict__ Ip, double tie,
+                                                         const double* __restrict__ u1_in,
+                                                         const double* __restrict__ part, double* __restrict__ u1_out) {
+  const Inst& I = *Ip;
+  constexpr int r = R / 2;
+  const int j = blockIdx.x * 256 + (int)threadIdx.x;
+  if (j >= I.n_y) return;
+  double M = -INFINITY;
+  for (int s = 0; s < I.u1_slices; ++s) M = fmax(M, part[((size_t)s * I.n_y + j) * (R + 1)]);
+  double C[R], c[R];
+#pragma unroll
+  for (int m = 0; m < R; ++m) C[m] = 0.0;
+  for (int s = 0; s < I.u1_slices; ++s) {
+    const double* p = part + ((size_t)s * I.n_y + j) * (R + 1);
+    if (!(p[0] > -INFINITY)) continue;
+    const double sc = exp(p[0] - M);
+#pragma unroll
+    for (int m = 0; m < R; ++m) C[m] += p[1 + m] * sc;
+  }
+  const double inc = u1_in[j];
+#pragma unroll
+  for (int m = 0; m < R; ++m) {
+    const int k = j - r + m;
+    c[m] = (k >= 0 && k < I.n_y) ? u1_in[k] : inc;
+  }
+  const double res = c[pick_serial(R, c, C, inc, tie)];
+  u1_out[j] = res;
+  if (!isfinite(res)) atomicOr(I.flags, 1);
+}
+
+hipError_t launch_a1_local_u0(const Inst* dI, int n_x, double tau, const double* u0_in, double* u0_out,
+                              hipStream_t st) {
+  const int blocks = (n_x + 3) / 4;
+  hipLaunchKernelGGL(k_a1_local_u0, dim3(blocks), dim3(256), 0, st, dI, tau, u0_in, u0_out);
+  return hipGetLastError();
+}
+
+hipError_t launch_a1_pe_u0(const Inst* dI, int n_x, int r, double tie, const double* u0_in, double* u0_out,
+                           hipStream_t st) {
+  const int blocks = (n_x + 3) / 4;
+  if (r == 1)
+    hipLaunchKernelGGL(k_a1_pe_u0<3>, dim3(blocks), dim3(256), 0, st, dI, tie, u0_in, u0_out);
+  else
+    hipLaunchKernelGGL(k_a1_pe_u0<5>, dim3(blocks), dim3(256), 0, st, dI, tie, u0_in, u0_out);
+  return hipGetLastError();
+}
+
+hipError_t launch_a1_pe_u1(const Inst& I, const Inst* dI, int r, double tie, const double* u1_in, double* part,
+                           double* u1_out, hipStream_t st) {
+  const int units = ((I.n_y + kU1Block - 1) / kU1Block) * I.u1_slices;
+  const int blocks = (I.n_y + 255) / 256;
+  if (r == 1) {
+    hipLaunchKernelGGL(k_a1_pe_u1_partial<3>, dim3(units), dim3(kU1Block), 0, st, dI, u1_in, part);
+    hipLaunchKernelGGL(k_a1_pe_u1_select<3>, dim3(blocks), dim3(256), 0, st, dI, tie, u1_in, part, u1_out);
+  } else {
+    hipLaunchKernelGGL(k_a1_pe_u1_partial<5>, dim3(units), dim3(kU1Block), 0, st, dI, u1_in, part);
+    hipLaunchKernelGGL(k_a1_pe_u1_select<5>, dim3(blocks), dim3(256), 0, st, dI, tie, u1_in, part, u1_out);
+  }
+  return hipGetLastError();
+}
+
 }  // namespace ucp
