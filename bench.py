@@ -259,6 +259,43 @@ def batch_leg(a):
     return res, cases
 
 
+def gt_leg(a, cases):
+    """The same batch in the Gauss-transform arithmetic (UCP_FP64_GT): every
+    marginal cost in FP64 from a per-node moment table of u1 instead of the
+    window sums (decisions need no FP32 band).  Not the metric's method:
+    reported beside it, with its own time and cost error."""
+    import torch
+
+    import paper_1908_04489_amd as U
+
+    probs, srch = [c.prob for c in cases], [c.search for c in cases]
+    iters = [c.iters for c in cases]
+    u0s = [torch.as_tensor(c.u0_init).cuda() for c in cases]
+    U.solve_batch(probs, srch, iters, u0s, "fp64_gt")  # warm-up
+    st = torch.cuda.current_stream()
+    torch.cuda.synchronize()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record(st)
+    for k in range(a.gt_steps):
+        out = U.solve_batch(probs, srch, iters, u0s, "fp64_gt")
+    ev1.record(st)
+    torch.cuda.synchronize()
+    ms = ev0.elapsed_time(ev1) / a.gt_steps
+    breakdown = kernel_breakdown(U, lambda: U.solve_batch(probs, srch, iters, u0s, "fp64_gt"))
+    res = {"ms_per_step": ms, "solves_per_s": len(cases) * 1e3 / ms, "steps": a.gt_steps,
+           "kernel_ms_per_step": breakdown}
+    print(f"# fp64_gt: {ms:.1f} ms per step", file=sys.stderr, flush=True)
+    if not a.no_check:
+        import oracle
+
+        errs = []
+        for b in (0, len(cases) - 1):
+            Jo = oracle.objective(probs[b], out[0][b].cpu().numpy(), out[1][b].cpu().numpy())
+            errs.append(abs(out[2][b].cpu().numpy()[-1] - Jo) / Jo)
+        res["J_final_rel_err_vs_oracle_objective"] = float(max(errs))
+    return res
+
+
 def serving_leg(a):
     """Continuous batching on the Poisson trace (4096 requests, seed 0) at
     0.8 and 0.5 of the server's saturated rate, against one solve at a time
@@ -366,6 +403,8 @@ def bench_headline(a):
             "warmup": a.warmup, "ms_per_step": res.pop("ms_per_step"), "higher_is_better": True,
             "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic"}
     line.update(res)
+    if a.gt_steps > 0:
+        line["fp64_gt"] = gt_leg(a, cases)
     if not a.no_serving:
         line["serving"] = serving_leg(a)
     if not a.no_cpu:
@@ -752,6 +791,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-check", action="store_true", help="skip the FP64 oracle check of the final J")
     ap.add_argument("--no-serving", action="store_true", help="headline: skip the serving leg")
+    ap.add_argument("--gt-steps", type=int, default=3,
+                    help="headline: timed steps of the same batch in the Gauss-transform arithmetic (0: skip)")
     ap.add_argument("--requests", type=int, default=4096, help="serving: requests taken from the trace")
     ap.add_argument("--slots", type=int, default=64, help="serving: concurrent solves")
     ap.add_argument("--instances", type=int, default=64, help="batch: instances per launch")

@@ -51,8 +51,27 @@ enum {
 typedef enum {
   UCP_FP32 = 0,       /* FP32 terms, plain FP32 accumulation */
   UCP_FP32_KAHAN = 1, /* FP32 terms, compensated (Kahan) accumulation */
-  UCP_FP64 = 2        /* FP64 throughout */
+  UCP_FP64 = 2,       /* FP64 throughout */
+  UCP_FP64_GT = 3     /* FP64 marginal costs from a Gauss transform of u1 (below) */
 } ucp_prec;
+
+/* UCP_FP64_GT: the marginal cost depends on (u, x0) only through
+ * z = x0 + u (besides k^2 u^2), and for z within half a spacing of a y
+ * node y_k, with delta = z - y_k and t_j = (y_j - y_k) / s,
+ *   dy sum_j phi_s(y_j - z)(z - u1_j)^2
+ *     = dy/(s sqrt(2 pi)) e^{-(delta/s)^2/2} sum_n (delta/s)^n / n!
+ *       [A2_n + 2 delta A1_n + delta^2 A0_n](k),
+ *   A_a,n(k) = sum_j e^{-t_j^2/2} t_j^n (y_k - u1_j)^a
+ * (the Gaussian's shift expanded in powers of delta).  After each u1 update
+ * one FP64 pass per y node over its window (11 noise sds) tabulates A for
+ * n <= N, N the smallest order whose truncation (|delta| T / s)^{N+1} /
+ * (N+1)! (T the window) is below 1e-17; every candidate then costs O(N).
+ * Positions farther than half a spacing from the grid are summed directly.
+ * The u1 update and the objective are those of UCP_FP64.  The result
+ * differs from the dense sum by the truncation, the window's tail and the
+ * rounding of the expansion (about 1e-16 of the cost at the tabulated
+ * node).  Grids with dy / noise_sd > 0.05 need N > 12 and are refused
+ * (UCP_EINVAL); so is ucp_argmin_adaptive_noalloc in this mode. */
 
 /* Problem instance: weight k of the stage-1 cost, the prior of x0 as a
  * mixture of n_comp Gaussians (weights w summing to 1, means mu, standard
@@ -242,11 +261,12 @@ int ucp_profile_read(ucp_handle* h, int kind, double* total_ms, int64_t* launche
  * the kernels are built from - kind 0 FP32 FMA, 1 the FP32 base-2
  * exponential, 2 FP64 FMA - as lane-operations per second, with `blocks`
  * blocks of 256 lanes each running 8 independent chains of `iters`
- * operations (a second, timed launch after a warm-up).  Allocates a small
+ * operations (a second, timed launch after a warm-up) on HIP device
+ * `device`.  Allocates a small
  * device buffer and synchronises `stream`.  This fixes the VALU peak the
  * marginal-cost kernel's roofline is quoted against.
  * Errors: UCP_EINVAL, UCP_ENOMEM, UCP_EHIP. */
-int ucp_peak_probe(int kind, int32_t blocks, int32_t iters, double* lane_ops_per_s, void* stream);
+int ucp_peak_probe(int device, int kind, int32_t blocks, int32_t iters, double* lane_ops_per_s, void* stream);
 
 /* B independent solves advanced together: every kernel launch covers all
  * instances still running (one flat work list per launch), each instance

@@ -74,9 +74,31 @@ int check_search(const ucp_search* s) {
 double tie_band(const ucp_search* s) { return s && s->tie_rel64 > 0.0 ? s->tie_rel64 : kTau64; }
 
 int check_prec(int prec) {
-  if (prec != UCP_FP32 && prec != UCP_FP32_KAHAN && prec != UCP_FP64)
+  if (prec != UCP_FP32 && prec != UCP_FP32_KAHAN && prec != UCP_FP64 && prec != UCP_FP64_GT)
     return fail(UCP_EINVAL, "unknown precision %d", prec);
   return UCP_OK;
+}
+
+int check_gt(const Inst& I) {
+  if (I.prec == UCP_FP64_GT && I.gtn > kGtMaxN)
+    return fail(UCP_EINVAL, "UCP_FP64_GT needs dy / noise_sd <= 0.05 (an expansion order <= %d); got dy / sd = %g",
+                kGtMaxN, I.dy * I.isw);
+  return UCP_OK;
+}
+
+// Order N of the Gauss-transform expansion: the smallest with
+// (h T)^{N+1} / (N+1)! <= 1e-17, h = dy / (2 s) the largest |delta| / s and
+// T = (nw64 + 1/2) dy / s the window (in noise sds).  kGtMaxN + 1 when none
+// up to kGtMaxN will do.
+static int32_t gt_order(const Inst& I) {
+  const double h = 0.5 * I.dy * I.isw, T = ((double)I.nw64 + 0.5) * I.dy * I.isw;
+  const double x = h * T;
+  double term = x;  // x^{n+1} / (n+1)! at n = 0
+  for (int n = 0; n <= kGtMaxN; ++n) {
+    if (term <= 1e-17) return std::max(n, 2);
+    term *= x / (double)(n + 2);
+  }
+  return kGtMaxN + 1;
 }
 
 // Constants and launch geometry of one instance.  Everything here depends on
@@ -130,9 +152,10 @@ Inst make_inst(const ucp_problem& p, const ucp_search* s, int prec, int cands_ov
   I.rs64 = 32;
   while (I.rs64 > 1 && I.rs64 * 64.0 * I.dy * I.isw > 24.0) I.rs64 /= 2;
   I.prec = prec;
+  I.gtn = prec == UCP_FP64_GT ? gt_order(I) : 0;
   // window segments: enough work units to fill the GPU when the instance is
   // small, segments of at least 256 nodes
-  if (prec == UCP_FP64) {
+  if (prec == UCP_FP64 || prec == UCP_FP64_GT) {
     I.segs = 1;
     I.wsegs = 1;
   } else {
@@ -167,6 +190,7 @@ size_t state_bytes(const Inst& I) {
   b += align_up((size_t)(2 * I.nw32 + 1 + kGtabPad) * 4);          // gtab (padded past the window)
   b += align_up(nx * (size_t)(I.cands + 1) * (size_t)I.segs * 8); // part
   b += align_up((size_t)I.u1_slices * ny * 3 * 8);                // u1part
+  if (I.prec == UCP_FP64_GT) b += align_up(ny * 3 * (size_t)(I.gtn + 1) * 8);  // gt
   b += 256 + kCountBytes;                                         // flags, counters
   return b;
 }
@@ -192,6 +216,7 @@ void carve_state(Inst& I, char*& base) {
   I.gtab = (float*)take((size_t)(2 * I.nw32 + 1 + kGtabPad) * 4);
   I.part = (double*)take(nx * (size_t)(I.cands + 1) * (size_t)I.segs * 8);
   I.u1part = (double*)take((size_t)I.u1_slices * ny * 3 * 8);
+  I.gt = I.prec == UCP_FP64_GT ? (double*)take(ny * 3 * (size_t)(I.gtn + 1) * 8) : nullptr;
   I.flags = (int32_t*)take(256);
   I.terms = (unsigned long long*)take(kCountBytes);
 }
@@ -226,6 +251,7 @@ std::vector<int32_t> build_tables(const std::vector<Inst>& insts, const std::vec
         else if (k == kKindFree) u = I.free_cands ? units_mc(I, -1) : 0;
         else if (k == kKindFin) u = I.free_cands ? (int32_t)(((int64_t)I.n_x * I.cands + 255) / 256) : 0;
         else if (k == kKindGtab) u = units_gtab(I);
+        else if (k == kKindGt) u = units_gt(I);
       }
       pre[b + 1] = pre[b] + u;
     }
@@ -514,6 +540,7 @@ int setup_batch(ucp_handle* h, Batch& B, std::vector<Inst> insts, const std::vec
 int run_round(ucp_handle* h, const Batch& B, int phase, const std::vector<int32_t>& tab, int prec, int max_levels,
               int t, hipStream_t st) {
   EvPair p;
+  UCP_TRY(launch_gt_table(B.launch(phase, kKindGt, tab), st), "moment table kernel");
   for (int l = 0; l < max_levels; ++l) {
     const Launch Lm = B.launch(phase, kKindMc0 + l, tab), Ls = B.launch(phase, kKindSel0 + l, tab);
     UCP_TRY(prof_pair(h, UCP_PROF_MC, Lm.total > 0, p), "event");
@@ -570,7 +597,10 @@ int ucp_solve_batch(ucp_handle* h, int32_t nb, const ucp_problem* probs, const u
   if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
   hipStream_t st = (hipStream_t)stream;
   std::vector<Inst> insts;
-  for (int b = 0; b < nb; ++b) insts.push_back(make_inst(probs[b], &searches[b], prec, 0));
+  for (int b = 0; b < nb; ++b) {
+    insts.push_back(make_inst(probs[b], &searches[b], prec, 0));
+    if ((rc = check_gt(insts.back()))) return fail(rc, "instance %d: %s", b, g_err.c_str());
+  }
   // phases: phase t (0..max_it) runs the instances with iters >= t
   std::vector<std::vector<char>> phases(max_it + 1, std::vector<char>(nb, 0));
   std::vector<int> phase_of(max_it + 1, 0);
@@ -633,7 +663,9 @@ int ucp_argmin_adaptive(ucp_handle* h, const ucp_problem* prob, const ucp_search
     I.L0_out = L0_out;
     I.terms = nullptr;
   };
-  if ((rc = setup_batch(h, B, {make_inst(*prob, search, prec, 0)}, phases, tab, st, fix))) return rc;
+  const Inst I0 = make_inst(*prob, search, prec, 0);
+  if ((rc = check_gt(I0))) return rc;
+  if ((rc = setup_batch(h, B, {I0}, phases, tab, st, fix))) return rc;
   Inst& I = B.insts[0];
   UCP_TRY(hipMemcpyAsync(I.u0, u0_in, sizeof(double) * I.n_x, hipMemcpyDeviceToDevice, st), "copy u0");
   UCP_TRY(hipMemcpyAsync(I.u1, u1, sizeof(double) * I.n_y, hipMemcpyDeviceToDevice, st), "copy u1");
@@ -641,6 +673,7 @@ int ucp_argmin_adaptive(ucp_handle* h, const ucp_problem* prob, const ucp_search
   UCP_TRY(launch_prior(B.launch(0, kKindPrior, tab), st), "prior kernel");
   UCP_TRY(launch_gtab(B.launch(0, kKindGtab, tab), st), "offset table kernel");
   UCP_TRY(launch_v_from_u1(B.launch(0, kKindU1c, tab), st), "residual kernel");
+  UCP_TRY(launch_gt_table(B.launch(0, kKindGt, tab), st), "moment table kernel");
   for (int l = 0; l < I.levels; ++l) {
     UCP_TRY(launch_mc(B.launch(0, kKindMc0 + l, tab), l, prec, st), "marginal-cost kernel");
     UCP_TRY(launch_select(B.launch(0, kKindSel0 + l, tab), l, prec, L0_out != nullptr, st), "selection kernel");
@@ -714,6 +747,7 @@ int ucp_marginal_cost(ucp_handle* h, const ucp_problem* prob, ucp_prec prec, con
   std::vector<int32_t> tab;
   Inst I0 = make_inst(*prob, nullptr, prec, (int)n_cand);
   I0.free_cands = 1;
+  if ((rc = check_gt(I0))) return rc;
   auto fix = [&](int, Inst& I) {
     I.u0 = const_cast<double*>(u);  // the explicit candidates [n_x][n_cand], read only
     I.terms = nullptr;
@@ -724,6 +758,7 @@ int ucp_marginal_cost(ucp_handle* h, const ucp_problem* prob, ucp_prec prec, con
   UCP_TRY(launch_prior(B.launch(0, kKindPrior, tab), st), "prior kernel");
   UCP_TRY(launch_gtab(B.launch(0, kKindGtab, tab), st), "offset table kernel");
   UCP_TRY(launch_v_from_u1(B.launch(0, kKindU1c, tab), st), "residual kernel");
+  UCP_TRY(launch_gt_table(B.launch(0, kKindGt, tab), st), "moment table kernel");
   UCP_TRY(launch_mc(B.launch(0, kKindFree, tab), -1, prec, st), "marginal-cost kernel");
   Launch Lf = B.launch(0, kKindFin, tab);
   UCP_TRY(launch_finish_free(Lf, L0_out, prec, st), "finish kernel");

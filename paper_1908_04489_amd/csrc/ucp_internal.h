@@ -46,6 +46,7 @@ constexpr double kTau32Kahan = 5e-7;
 constexpr double kTau32Plain = 5e-6;
 constexpr double kKappa32 = 6e-7;
 constexpr double kTau64 = 1e-12;// FP64 tie band (relative)
+constexpr int kGtMaxN = 12;     // highest expansion order of the Gauss-transform table
 constexpr double kWin32 = 9.0;  // window half-width, noise sds (FP32 terms)
 // FP64 window half-width, noise sds.  B has no useful lower bound (a point
 // whose x0 + u lands on a flat step of u1 has B far below the noise
@@ -88,6 +89,7 @@ struct Inst {
   // geometry
   int32_t nw32, nw64;        // window half-widths in y nodes
   int32_t rs64;              // FP64 walks: steps of a wave between reseeds (a power of two, <= 32)
+  int32_t gtn;               // UCP_FP64_GT: expansion order N of the moment table (0 otherwise)
   int32_t segs;              // marginal-cost units (partial sums) per (tile, candidate)
   int32_t wsegs;             // equal window segments (the last one dispatched split in two when segs > wsegs)
   int32_t u1_slices;         // x slices of the u1 sums
@@ -108,6 +110,7 @@ struct Inst {
   double* part;              // marginal-cost partial sums [n_x][cands + 1][segs]
   double* u1part;            // u1 partial sums [u1_slices][n_y][3]
   double* jrow;              // per-point objective terms [n_x]
+  double* gt;                // UCP_FP64_GT moment table [n_y][3][gtn + 1] (A0, A1, A2 by order)
   double* J_out;             // objective output (one double)
   double* L0_out;            // optional FP64 L_0 of the accepted u0 [n_x] (argmin call only)
   int32_t* flags;            // bit 0: non-finite value met
@@ -133,6 +136,8 @@ struct Launch {
 // Kernel launchers (ucp_kernels.hip).  All enqueue on `st`.
 hipError_t launch_prior(const Launch& L, hipStream_t st);
 hipError_t launch_gtab(const Launch& L, hipStream_t st);
+// UCP_FP64_GT: the moment table of every instance in GT mode (after a u1 update)
+hipError_t launch_gt_table(const Launch& L, hipStream_t st);
 // Launchers that take (e0, e1) record e0 when the first kernel starts and e1
 // when the last one ends (hipExtLaunchKernel: no extra packets in the stream).
 hipError_t launch_mc(const Launch& L, int level, int prec, hipStream_t st, hipEvent_t e0 = nullptr,
@@ -165,5 +170,6 @@ int32_t units_u1_combine(const Inst& I);
 int32_t units_j_rows(const Inst& I);
 int32_t units_prior(const Inst& I);
 int32_t units_gtab(const Inst& I);
+int32_t units_gt(const Inst& I);
 
 }  // namespace ucp

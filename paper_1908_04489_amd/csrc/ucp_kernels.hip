@@ -834,22 +834,11 @@ __global__ __launch_bounds__(kMcBlock) void k_mc32(Launch L, int level) {
 // the same shifted Gaussian as b64_wave, walked node by node with the exact
 // recurrence g_{k+1} = g_k r_k, r_{k+1} = r_k exp(-dy^2),
 // r_k = exp(-dy t_k - dy^2/2), reseeded by exp every kReseed nodes.
-__global__ __launch_bounds__(kMcBlock) void k_mc64(Launch L, int level) {
-  const int u = blockIdx.x;
-  const int b = find_inst(L.pre, L.n_inst, u);
-  const Inst& I = L.insts[b];
-  int local = u - L.pre[b];
-  const int kq = level < 0 ? I.cands : (level == 0 ? I.cands + 1 : I.cands);
-  const int q = local % kq;
-  const int tile = local / kq;
-  const int i = tile * kMcBlock + (int)threadIdx.x;
-  const bool act = i < I.n_x;
-  const double c = cand_pos(I, level, q, act ? i : I.n_x - 1);
-  const double z = (I.x_lo + (double)(act ? i : I.n_x - 1) * I.dx) + c;
-  count_terms(I, z, act, (int)threadIdx.x % kWave);
-  if (!act) return;
-  const int jr = nearest_node(I, z);
-  const double delta = ((I.y_lo + (double)jr * I.dy) - z) * I.isw;  // in noise sds
+// One lane's FP64 window sum for position z, node by node: returns
+// sum_k exp(-(t_k^2 - delta^2)/2) (z - u1_{jr+k})^2 over |k| <= nw64, the
+// scale dy/(s sqrt(2 pi)) exp(-delta^2/2) left to the caller (jr the
+// nearest node, delta = (y_jr - z)/s).
+__device__ double lane_sum64(const Inst& I, double z, int jr, double delta) {
   const int klo = max(-I.nw64, -jr), khi = min(I.nw64, I.n_y - 1 - jr);
   const double dy = I.dy * I.isw, qd = exp(-dy * dy);
   const double* __restrict__ u1 = I.u1 + jr;
@@ -875,13 +864,146 @@ __global__ __launch_bounds__(kMcBlock) void k_mc64(Launch L, int level) {
       s0 = fma(g * e0, e0, s0);
     }
   }
-  I.part[(size_t)i * (I.cands + 1) + q] = s0 + s1;
+  return s0 + s1;
+}
+
+__global__ __launch_bounds__(kMcBlock) void k_mc64(Launch L, int level) {
+  const int u = blockIdx.x;
+  const int b = find_inst(L.pre, L.n_inst, u);
+  const Inst& I = L.insts[b];
+  int local = u - L.pre[b];
+  const int kq = level < 0 ? I.cands : (level == 0 ? I.cands + 1 : I.cands);
+  const int q = local % kq;
+  const int tile = local / kq;
+  const int i = tile * kMcBlock + (int)threadIdx.x;
+  const bool act = i < I.n_x;
+  const double c = cand_pos(I, level, q, act ? i : I.n_x - 1);
+  const double z = (I.x_lo + (double)(act ? i : I.n_x - 1) * I.dx) + c;
+  count_terms(I, z, act, (int)threadIdx.x % kWave);
+  if (!act) return;
+  const int jr = nearest_node(I, z);
+  const double delta = ((I.y_lo + (double)jr * I.dy) - z) * I.isw;  // in noise sds
+  I.part[(size_t)i * (I.cands + 1) + q] = lane_sum64(I, z, jr, delta);
+}
+
+// ------------------------------------------- Gauss-transform arithmetic
+//
+// For z within half a spacing of node y_k (delta = z - y_k, in noise sds
+// d = delta / s, t_j = (y_j - y_k) / s):
+//   sum_j exp(-(y_j - z)^2 / (2 s^2)) (z - u1_j)^2
+//     = e^{-d^2/2} sum_n d^n / n! [A2_n + 2 delta A1_n + delta^2 A0_n],
+//   A_a,n = sum_j e^{-t_j^2/2} t_j^n (y_k - u1_j)^a,
+// since exp(t d) = sum_n (t d)^n / n! and z - u1_j = (y_k - u1_j) + delta.
+// k_gt_table tabulates A_a,n (n <= I.gtn) per node after each u1 update:
+// one wave per node over its window of 11 noise sds, the Gaussian by the
+// reseeded recurrence of the FP64 sums (delta = 0 at a node).  k_mc_gt
+// then evaluates every (point, candidate) in O(gtn).
+
+int32_t units_gt(const Inst& I) { return I.prec == UCP_FP64_GT ? (I.n_y + 3) / 4 : 0; }
+
+__global__ __launch_bounds__(256) void k_gt_table(Launch L) {
+  const int u = blockIdx.x;
+  const int b = find_inst(L.pre, L.n_inst, u);
+  const Inst& I = L.insts[b];
+  const int lane = (int)threadIdx.x % kWave;
+  const int k = (u - L.pre[b]) * 4 + (int)threadIdx.x / kWave;
+  if (k >= I.n_y) return;  // whole waves
+  const int N = I.gtn;
+  const int klo = max(-I.nw64, -k), khi = min(I.nw64, I.n_y - 1 - k);
+  const int n = khi - klo + 1;
+  const double dy = I.dy * I.isw, D = (double)kWave * dy;
+  const double q = exp(-D * D);
+  const double yk = I.y_lo + (double)k * I.dy;
+  const int rs = I.rs64;
+  glb_dptr u1 = (glb_dptr)(I.u1 + k + klo + lane);
+  double A0[kGtMaxN + 1], A1[kGtMaxN + 1], A2[kGtMaxN + 1];
+#pragma unroll
+  for (int m = 0; m <= kGtMaxN; ++m) A0[m] = A1[m] = A2[m] = 0.0;
+  B64Walk w;
+  const int steps = (n + kWave - 1) / kWave;
+  for (int m = 0; m < steps; ++m) {
+    if ((m & (rs - 1)) == 0) b64_reseed<kWave>(w, klo, lane, m, dy, 0.0, D);
+    if (lane + kWave * m < n) {
+      const double t = (double)(klo + lane + kWave * m) * dy;
+      const double v = yk - u1[kWave * m];
+      const double v2 = v * v;
+      double p = w.g;
+#pragma unroll
+      for (int o = 0; o <= kGtMaxN; ++o) {
+        if (o <= N) {
+          A0[o] += p;
+          A1[o] = fma(p, v, A1[o]);
+          A2[o] = fma(p, v2, A2[o]);
+          p *= t;
+        }
+      }
+    }
+    w.g *= w.r;
+    w.r *= q;
+  }
+  double* row = I.gt + (size_t)k * 3 * (N + 1);
+#pragma unroll
+  for (int o = 0; o <= kGtMaxN; ++o) {
+    if (o <= N) {
+      const double s0 = grp_sum_d<kWave>(A0[o]), s1 = grp_sum_d<kWave>(A1[o]), s2 = grp_sum_d<kWave>(A2[o]);
+      if (lane == 0) {
+        row[o] = s0;
+        row[(N + 1) + o] = s1;
+        row[2 * (N + 1) + o] = s2;
+      }
+    }
+  }
+}
+
+hipError_t launch_gt_table(const Launch& L, hipStream_t st) {
+  if (L.total == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_gt_table, dim3(L.total), dim3(256), 0, st, L);
+  return hipGetLastError();
+}
+
+// Marginal cost from the table: lane = point, as k_mc64; positions farther
+// than half a spacing from every node (beyond the grid's ends) are summed
+// directly.  Stores B itself.
+__global__ __launch_bounds__(kMcBlock) void k_mc_gt(Launch L, int level) {
+  const int u = blockIdx.x;
+  const int b = find_inst(L.pre, L.n_inst, u);
+  const Inst& I = L.insts[b];
+  int local = u - L.pre[b];
+  const int kq = level < 0 ? I.cands : (level == 0 ? I.cands + 1 : I.cands);
+  const int q = local % kq;
+  const int tile = local / kq;
+  const int i = tile * kMcBlock + (int)threadIdx.x;
+  const bool act = i < I.n_x;
+  const double c = cand_pos(I, level, q, act ? i : I.n_x - 1);
+  const double z = (I.x_lo + (double)(act ? i : I.n_x - 1) * I.dx) + c;
+  count_terms(I, z, act, (int)threadIdx.x % kWave);
+  if (!act) return;
+  const int kn = nearest_node(I, z);
+  const double del = z - (I.y_lo + (double)kn * I.dy);
+  double G;
+  if (fabs(del) <= 0.5 * I.dy * (1.0 + 1e-12)) {
+    const int N = I.gtn;
+    const double* row = I.gt + (size_t)kn * 3 * (N + 1);
+    const double d = del * I.isw;
+    double acc = 0.0;
+    for (int o = N; o >= 0; --o) {
+      const double C = row[2 * (N + 1) + o] + 2.0 * del * row[(N + 1) + o] + del * del * row[o];
+      acc = C + acc * d / (double)(o + 1);
+    }
+    G = I.phi_scale * exp(-0.5 * d * d) * acc;
+  } else {
+    const double delta = -del * I.isw;  // (y_k - z) / s
+    G = I.phi_scale * exp(-0.5 * delta * delta) * lane_sum64(I, z, kn, delta);
+  }
+  I.part[(size_t)i * (I.cands + 1) + q] = I.k2 * c * c + G;
 }
 
 hipError_t launch_mc(const Launch& L, int level, int prec, hipStream_t st, hipEvent_t e0, hipEvent_t e1) {
   if (L.total == 0) return hipSuccess;
   if (prec == UCP_FP64)
     hipExtLaunchKernelGGL(k_mc64, dim3(L.total), dim3(kMcBlock), 0, st, e0, e1, 0, L, level);
+  else if (prec == UCP_FP64_GT)
+    hipExtLaunchKernelGGL(k_mc_gt, dim3(L.total), dim3(kMcBlock), 0, st, e0, e1, 0, L, level);
   else if (prec == UCP_FP32_KAHAN)
     hipExtLaunchKernelGGL(k_mc32<UCP_FP32_KAHAN>, dim3(L.total), dim3(kMcBlock), 0, st, e0, e1, 0, L, level);
   else
@@ -897,6 +1019,7 @@ __device__ __forceinline__ double b_from_parts(const Inst& I, int i, int q, int 
   const int jr = nearest_node(I, z);
   const double delta = ((I.y_lo + (double)jr * I.dy) - z) * I.isw;  // in noise sds
   const double* p = I.part + ((size_t)i * (I.cands + 1) + q) * S;  // [point][slot][segment]
+  if (prec == UCP_FP64_GT) return p[0];  // B itself
   double s = 0.0;
   for (int g = 0; g < S; ++g) s += p[g];
   if (prec != UCP_FP64) s = s / I.a2;
@@ -995,6 +1118,11 @@ __device__ unsigned long long band32(bool in_set, double B32, double tau) {
 
 // This lane's candidate of the level: position, FP32-path B and (FP64 mode,
 // or the carried best) its FP64 B.
+// The arithmetics whose marginal costs are FP64 values (decided directly by
+// the rule, with no FP32 band).
+template <int PREC>
+constexpr bool F64 = PREC == UCP_FP64 || PREC == UCP_FP64_GT;
+
 template <int PREC>
 __device__ void level_view(const Inst& I, int level, int i, int lane, double& c, double& B32, double& B64,
                            bool& in_set) {
@@ -1006,7 +1134,7 @@ __device__ void level_view(const Inst& I, int level, int i, int lane, double& c,
   if (lane < kq) {
     c = cand_pos(I, level, lane, i);
     B32 = b_from_parts(I, i, lane, I.segs, c, PREC);
-    if (PREC == UCP_FP64) B64 = B32;
+    if (F64<PREC>) B64 = B32;
   }
   if (level > 0 && lane == K) {
     c = I.cbest[i];
@@ -1073,8 +1201,8 @@ __device__ void accept(const Inst& I, int i, double x, double uinc, double cw, d
   const bool in2 = lane < 2;
   const double c2 = lane == 0 ? cw : uinc;
   const double b32 = lane == 0 ? B32w : B32i;
-  double b64 = lane == 0 ? B64w : (PREC == UCP_FP64 ? B32i : B64i);
-  if (PREC == UCP_FP64) {
+  double b64 = lane == 0 ? B64w : (F64<PREC> ? B32i : B64i);
+  if (F64<PREC>) {
     const bool fin = in2 && isfinite(b32);
     const int w = tie_rule<W>(fin, c2, b32, uinc, lane, I.tau64);
     if (grp_ballot<W>(fin) == 0ull && lane == 0) atomicOr(I.flags, 1);
@@ -1130,7 +1258,7 @@ __device__ void band_point(const Inst& I, int level, int i, int lane, int want_l
   level_view<PREC>(I, level, i, lane, c, B32, B64, in_set);
   if (level == 0 && lane == K) I.b32inc[i] = B32;
   int w;
-  if (PREC == UCP_FP64) {
+  if (F64<PREC>) {
     const bool fin = in_set && isfinite(B32);
     if (grp_ballot<W>(fin) == 0ull && lane == 0) atomicOr(I.flags, 1);
     w = tie_rule<W>(fin, c, B32, uinc, lane, I.tau64);
@@ -1332,6 +1460,8 @@ hipError_t launch_select(const Launch& L, int level, int prec, int want_l0, hipS
   const dim3 blk(kSelWaves * kWave);
   if (prec == UCP_FP64)
     hipExtLaunchKernelGGL(k_select<UCP_FP64>, dim3(L.total), blk, 0, st, e0, e1, 0, L, level, want_l0);
+  else if (prec == UCP_FP64_GT)
+    hipExtLaunchKernelGGL(k_select<UCP_FP64_GT>, dim3(L.total), blk, 0, st, e0, e1, 0, L, level, want_l0);
   else if (prec == UCP_FP32_KAHAN)
     hipExtLaunchKernelGGL(k_select<UCP_FP32_KAHAN>, dim3(L.total), blk, 0, st, e0, e1, 0, L, level, want_l0);
   else
@@ -1546,7 +1676,7 @@ __global__ __launch_bounds__(kU1Block) void k_u1_combine(Launch L) {
 
 hipError_t launch_u1_partial(const Launch& L, int prec, hipStream_t st, hipEvent_t e0) {
   if (L.total == 0) return hipSuccess;
-  if (prec == UCP_FP64)
+  if (prec == UCP_FP64 || prec == UCP_FP64_GT)  // the u1 update of UCP_FP64_GT is UCP_FP64's
     hipExtLaunchKernelGGL(k_u1_partial<UCP_FP64>, dim3(L.total), dim3(kU1Block), 0, st, e0, nullptr, 0, L);
   else if (prec == UCP_FP32_KAHAN)
     hipExtLaunchKernelGGL(k_u1_partial<UCP_FP32_KAHAN>, dim3(L.total), dim3(kU1Block), 0, st, e0, nullptr, 0, L);

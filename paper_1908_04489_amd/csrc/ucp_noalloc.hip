@@ -108,6 +108,7 @@ extern "C" int ucp_argmin_adaptive_noalloc(ucp_handle* h, const ucp_problem* pro
   if (!h) return fail(UCP_EINVAL, "handle is NULL");
   int rc;
   if ((rc = check_problem(prob)) || (rc = check_search(search)) || (rc = check_prec(prec))) return rc;
+  if (prec == UCP_FP64_GT) return fail(UCP_EINVAL, "the allocation-free update does not take UCP_FP64_GT");
   if (!u1 || !u0_in || !u0_out) return fail(UCP_EINVAL, "NULL array argument");
   const int device = handle_device(h);
   if (device < 0 || device >= kMaxDevices) return fail(UCP_EINVAL, "device %d beyond the supported range", device);

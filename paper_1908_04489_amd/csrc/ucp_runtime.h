@@ -21,6 +21,7 @@ enum : int {
   kKindFree,  // marginal-cost kernel on explicit candidates
   kKindFin,   // L_0 = f B for explicit candidates
   kKindGtab,  // offset table of the marginal-cost kernel
+  kKindGt,    // Gauss-transform moment table (UCP_FP64_GT)
   kKinds
 };
 
@@ -32,6 +33,8 @@ int check_search(const ucp_search* s);
 // relative tie band of the selection rule: the search's, or the default
 double tie_band(const ucp_search* s);
 int check_prec(int prec);
+// UCP_FP64_GT needs an expansion order the kernels hold (N <= kGtMaxN)
+int check_gt(const Inst& I);
 Inst make_inst(const ucp_problem& p, const ucp_search* s, int prec, int cands_override);
 size_t state_bytes(const Inst& I);
 void carve_state(Inst& I, char*& base);

@@ -118,7 +118,9 @@ int ucp_footprint(const ucp_problem* prob, const ucp_search* search, ucp_prec pr
   if (!bytes) return fail(UCP_EINVAL, "bytes is NULL");
   if ((rc = check_problem(prob)) || (rc = check_search(search)) || (rc = check_prec(prec))) return rc;
   if (iters < 0) return fail(UCP_EINVAL, "iters < 0");
-  *bytes = footprint(make_inst(*prob, search, prec, 0), iters);
+  const Inst I = make_inst(*prob, search, prec, 0);
+  if ((rc = check_gt(I))) return rc;
+  *bytes = footprint(I, iters);
   return UCP_OK;
 }
 
@@ -175,6 +177,10 @@ int ucp_server_submit(ucp_server* s, const ucp_problem* prob, const ucp_search* 
   r->iters = iters;
   r->u0_init.assign(u0_init, u0_init + prob->n_x);
   r->inst = make_inst(*prob, search, s->prec, 0);
+  if ((rc = check_gt(r->inst))) {
+    delete r;
+    return rc;
+  }
   r->bytes = footprint(r->inst, iters);
   if (s->budget && r->bytes > s->budget) {
     delete r;
@@ -354,6 +360,7 @@ extern "C" int ucp_server_step(ucp_server* s, int32_t* n_running) {
     SRV_TRY(launch_j_rows(L(0, kKindJRows, 0), st), "objective kernel");
     SRV_TRY(launch_j_reduce_t(L(0, kKindJRed, 0), 0, st), "objective reduce kernel");
     // one round for every running request
+    SRV_TRY(launch_gt_table(L(1, kKindGt, 1), st), "moment table kernel");
     for (int l = 0; l < max_lv; ++l) {
       SRV_TRY(launch_mc(L(1, kKindMc0 + l, 1), l, prec, st), "marginal-cost kernel");
       SRV_TRY(launch_select(L(1, kKindSel0 + l, 1), l, prec, 0, st), "selection kernel");
