@@ -23,8 +23,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.environ.get("UCP_LIBRARY") or os.path.join(HERE, "libucp.so")
 HEADER = os.path.join(os.path.dirname(HERE), "include", "ucp.h")
 
-FP32, FP32_KAHAN, FP64 = 0, 1, 2
-PRECS = {"fp32": FP32, "fp32_kahan": FP32_KAHAN, "kahan": FP32_KAHAN, "fp64": FP64}
+FP32, FP32_KAHAN, FP64, FP64_GT = 0, 1, 2, 3
+PRECS = {"fp32": FP32, "fp32_kahan": FP32_KAHAN, "kahan": FP32_KAHAN, "fp64": FP64, "fp64_gt": FP64_GT, "gt": FP64_GT}
 OK, EINVAL, ENOMEM, EHIP, EAGAIN, ENONFINITE, ENOTFOUND = 0, -1, -2, -3, -4, -5, -6
 MAX_COMP = 8
 
@@ -67,6 +67,14 @@ class Search(C.Structure):
 if not os.path.exists(LIB_PATH):
     raise ImportError(f"{LIB_PATH} is missing: build it with paper_1908_04489_amd.build.build() "
                       "(the solver has no CPU fallback)")
+# torch is loaded first so that its bundled HIP runtime (soname
+# libamdhip64.so.7) is the one this library's dependency of that name
+# binds to.  In the other order the library brings in the system runtime,
+# torch then loads its own copy beside it (it asks for libamdhip64.so by
+# file name), and the library's copy finds no device once torch's has
+# initialised the GPU.
+import torch  # noqa: E402,F401
+
 _lib = C.CDLL(LIB_PATH)
 
 _vp = C.c_void_p
@@ -90,7 +98,7 @@ _sigs = {
     "ucp_solve_batch": ([_vp, C.c_int32, _P(Problem), _P(Search), C.c_int, _P(C.c_int32), _P(_vp), _P(_vp),
                          _P(_vp), _P(_vp), _vp], C.c_int),
     "ucp_profile": ([_vp, C.c_int], C.c_int),
-    "ucp_peak_probe": ([C.c_int, C.c_int32, C.c_int32, _P(C.c_double), _vp], C.c_int),
+    "ucp_peak_probe": ([C.c_int, C.c_int, C.c_int32, C.c_int32, _P(C.c_double), _vp], C.c_int),
     "ucp_profile_read": ([_vp, C.c_int, _P(C.c_double), _P(C.c_int64)], C.c_int),
     "ucp_last_counts": ([_vp, _P(C.c_uint64), _P(C.c_uint64), _P(C.c_uint64)], C.c_int),
     "ucp_footprint": ([_P(Problem), _P(Search), C.c_int, C.c_int32, _P(C.c_size_t)], C.c_int),
@@ -655,5 +663,5 @@ def peak_probe(kind, blocks=8192, iters=4096, device=0):
     "fma64" (diagnostic; fixes the peak of the roofline)."""
     k = {"fma32": 0, "exp32": 1, "fma64": 2}[kind]
     out = C.c_double()
-    _check(_lib.ucp_peak_probe(k, int(blocks), int(iters), C.byref(out), _stream(device)))
+    _check(_lib.ucp_peak_probe(int(device), k, int(blocks), int(iters), C.byref(out), _stream(device)))
     return out.value

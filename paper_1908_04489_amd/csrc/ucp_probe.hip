@@ -64,13 +64,20 @@ __global__ __launch_bounds__(kProbeBlock) void k_probe_fma64(int iters, double* 
 
 using namespace ucp;
 
-// kind 0: FP32 FMA, 1: v_exp_f32, 2: FP64 FMA.  Launches `blocks` blocks of
-// 256 lanes, each lane running kProbeChains chains of `iters` operations,
+// kind 0: FP32 FMA, 1: v_exp_f32, 2: FP64 FMA, on `device`.  Launches
+// `blocks` blocks of 256 lanes, each lane running kProbeChains chains of
+// `iters` operations,
 // times the launch with HIP events on `stream` (synchronising it) and
 // returns the lane-operations per second.
-extern "C" int ucp_peak_probe(int kind, int32_t blocks, int32_t iters, double* lane_ops_per_s, void* stream) {
+extern "C" int ucp_peak_probe(int device, int kind, int32_t blocks, int32_t iters, double* lane_ops_per_s,
+                              void* stream) {
   if (kind < 0 || kind > 2 || blocks < 1 || iters < 1 || !lane_ops_per_s)
     return fail(UCP_EINVAL, "kind must be 0..2, blocks and iters >= 1, output not NULL");
+  int ndev = 0;
+  hipError_t e0_ = hipGetDeviceCount(&ndev);
+  if (e0_ != hipSuccess || ndev <= 0) return fail(UCP_EHIP, "no HIP device available");
+  if (device < 0 || device >= ndev) return fail(UCP_EINVAL, "device %d out of range (have %d)", device, ndev);
+  if ((e0_ = hipSetDevice(device)) != hipSuccess) return hip_fail(e0_, "hipSetDevice");
   hipStream_t st = (hipStream_t)stream;
   void* buf = nullptr;
   const size_t n = (size_t)blocks * kProbeBlock;
