@@ -221,7 +221,7 @@ __global__ __launch_bounds__(64) void k_w2_search(W2Params P, const double* __re
   const double ia = u0_in[i], ib = u0_in[nn + i];
   const double* u1a = u1;
   const double* u1b = u1 + (long)P.ny * P.ny;
-  __shared__ double tab[8 * 64];
+  __shared__ double tab[kW2Grp * 64];
   double sa = 0.0, sb = 0.0, sB = 0.0;
   for (int l = 0; l < P.levels; ++l) {
     const bool live = q < KK;
@@ -444,8 +444,10 @@ int w2_params(const ucp_problem* p, const ucp_search* s, W2Params& P) {
   P.dy = (p->y_hi - p->y_lo) / (double)(p->n_y - 1);
   P.inv_dy = 1.0 / P.dy;
   P.Q = std::exp(-P.dy * P.dy);
-  // floor: at least kW2Win - dy from z on either side, and on the paper's
-  // grid (dy = 50/159) 63 columns, one chunk of a wave's lanes
+  // the window runs wn = floor(kW2Win / dy) nodes either side of z's
+  // nearest node, so every node it drops lies at least (wn + 1/2) dy >=
+  // kW2Win - dy / 2 from z; on the paper's grid (dy = 50/159) that is 31
+  // nodes each side, 63 columns, one chunk of a wave's lanes
   const double wn = std::floor(kW2Win * P.inv_dy);
   P.wn = (int)std::fmax(1.0, std::fmin(wn, (double)P.ny));
   if (s) {
