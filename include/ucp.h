@@ -55,23 +55,33 @@ typedef enum {
   UCP_FP64_GT = 3     /* FP64 marginal costs from a Gauss transform of u1 (below) */
 } ucp_prec;
 
-/* UCP_FP64_GT: the marginal cost depends on (u, x0) only through
- * z = x0 + u (besides k^2 u^2), and for z within half a spacing of a y
- * node y_k, with delta = z - y_k and t_j = (y_j - y_k) / s,
+/* The moment table (Gauss transform of u1).  The marginal cost depends on
+ * (u, x0) only through z = x0 + u (besides k^2 u^2), and about any centre c,
+ * with delta = z - c, d = delta / s and t_j = (y_j - c) / s,
  *   dy sum_j phi_s(y_j - z)(z - u1_j)^2
- *     = dy/(s sqrt(2 pi)) e^{-(delta/s)^2/2} sum_n (delta/s)^n / n!
- *       [A2_n + 2 delta A1_n + delta^2 A0_n](k),
- *   A_a,n(k) = sum_j e^{-t_j^2/2} t_j^n (y_k - u1_j)^a
- * (the Gaussian's shift expanded in powers of delta).  After each u1 update
- * one FP64 pass per y node over its window (11 noise sds) tabulates A for
- * n <= N, N the smallest order whose truncation (|delta| T / s)^{N+1} /
- * (N+1)! (T the window) is below 1e-17; every candidate then costs O(N).
- * Positions farther than half a spacing from the grid are summed directly.
- * The u1 update and the objective are those of UCP_FP64.  The result
- * differs from the dense sum by the truncation, the window's tail and the
- * rounding of the expansion (about 1e-16 of the cost at the tabulated
- * node).  Grids with dy / noise_sd > 0.05 need N > 12 and are refused
- * (UCP_EINVAL); so is ucp_argmin_adaptive_noalloc in this mode. */
+ *     = dy/(s sqrt(2 pi)) e^{-d^2/2} sum_n d^n / n!
+ *       [A2_n + 2 delta A1_n + delta^2 A0_n](c),
+ *   A_a,n(c) = sum_j e^{-t_j^2/2} t_j^n (c - u1_j)^a
+ * (the Gaussian's shift expanded in powers of d).  After each u1 update
+ * one FP64 pass over the window (11 noise sds) of each centre tabulates A
+ * for n <= 12; the centres are every m-th y node, m the largest stride
+ * with m dy / s <= 0.05 for which the series' truncation bound x^13 / 13! /
+ * (1 - x / 14), x = (m dy / 2s) (window in noise sds), is below 1e-17 (m =
+ * 40 on a 65536-node grid over [-40, 40] with s = 1), from 11 noise sds
+ * before the grid to 11 past it.  Every position then costs O(12); one
+ * farther outside has no grid node within its window and a noise sum of
+ * 0.  The table differs from
+ * the dense sum by the truncation, the window's tail and rounding (about
+ * 1e-16 of the cost at the centre; measured within 1e-14 of the dense sum).
+ *
+ * UCP_FP64_GT evaluates every marginal cost from the table and decides on
+ * those FP64 values; its u1 update and objective are those of UCP_FP64.
+ * Grids with dy / noise_sd > 0.05 are refused (UCP_EINVAL); so is
+ * ucp_argmin_adaptive_noalloc in this mode.
+ * In the FP32 modes the searches (solves, ucp_argmin_adaptive, the server)
+ * take the FP64 values that decide FP32 near-ties from the table where
+ * dy / noise_sd <= 0.05, and from FP64 window sums otherwise; L_0 of a
+ * winner that needed no FP64 value comes from a window sum. */
 
 /* Problem instance: weight k of the stage-1 cost, the prior of x0 as a
  * mixture of n_comp Gaussians (weights w summing to 1, means mu, standard

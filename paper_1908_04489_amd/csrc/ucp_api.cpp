@@ -80,25 +80,31 @@ int check_prec(int prec) {
 }
 
 int check_gt(const Inst& I) {
-  if (I.prec == UCP_FP64_GT && I.gtn > kGtMaxN)
-    return fail(UCP_EINVAL, "UCP_FP64_GT needs dy / noise_sd <= 0.05 (an expansion order <= %d); got dy / sd = %g",
-                kGtMaxN, I.dy * I.isw);
+  if (I.prec == UCP_FP64_GT && I.gts == 0)
+    return fail(UCP_EINVAL, "UCP_FP64_GT needs dy / noise_sd <= %g (the moment table's order is %d); got %g",
+                kGtStep, kGtN, I.dy * I.isw);
   return UCP_OK;
 }
 
-// Order N of the Gauss-transform expansion: the smallest with
-// (h T)^{N+1} / (N+1)! <= 1e-17, h = dy / (2 s) the largest |delta| / s and
-// T = (nw64 + 1/2) dy / s the window (in noise sds).  kGtMaxN + 1 when none
-// up to kGtMaxN will do.
-static int32_t gt_order(const Inst& I) {
-  const double h = 0.5 * I.dy * I.isw, T = ((double)I.nw64 + 0.5) * I.dy * I.isw;
-  const double x = h * T;
-  double term = x;  // x^{n+1} / (n+1)! at n = 0
-  for (int n = 0; n <= kGtMaxN; ++n) {
-    if (term <= 1e-17) return std::max(n, 2);
-    term *= x / (double)(n + 2);
+// Stride of the moment table's rows, in y nodes: the largest m with
+// m dy / s <= kGtStep for which order kGtN meets the truncation bound
+//   x^{N+1} / (N+1)! / (1 - x / (N+2)) <= 1e-17,  x = h T,
+// h = m dy / (2 s) the largest |z - y_k| / s of a position from its row's
+// node and T = nw64 dy / s the window's reach (the remainder of the series
+// of exp(t d), |t| <= T, |d| <= h).  0 when even m = 1 is too coarse.
+static int32_t gt_stride(const Inst& I) {
+  const double r = I.dy * I.isw;
+  if (r > kGtStep * (1.0 + 1e-12)) return 0;
+  const double T = (double)I.nw64 * r;
+  int32_t m = std::max(1, (int32_t)std::floor(kGtStep / r * (1.0 + 1e-12)));
+  m = std::min(m, std::max(1, I.nw64));
+  for (; m >= 1; --m) {
+    const double x = 0.5 * (double)m * r * T;
+    double b = 1.0;
+    for (int n = 1; n <= kGtN + 1; ++n) b *= x / (double)n;
+    if (b / (1.0 - x / (double)(kGtN + 2)) <= 1e-17) return m;
   }
-  return kGtMaxN + 1;
+  return 0;
 }
 
 // Constants and launch geometry of one instance.  Everything here depends on
@@ -152,7 +158,19 @@ Inst make_inst(const ucp_problem& p, const ucp_search* s, int prec, int cands_ov
   I.rs64 = 32;
   while (I.rs64 > 1 && I.rs64 * 64.0 * I.dy * I.isw > 24.0) I.rs64 /= 2;
   I.prec = prec;
-  I.gtn = prec == UCP_FP64_GT ? gt_order(I) : 0;
+  // the moment table: UCP_FP64_GT takes every cost from it; a search in the
+  // FP32 modes takes its FP64 values (tie-breaks, L_0) from it where the
+  // grid allows, and from window sums elsewhere.  UCP_FP64 keeps none.
+  if (prec == UCP_FP64_GT || (s && prec != UCP_FP64)) {
+    I.gts = gt_stride(I);
+    if (I.gts) {
+      // centres from nw64 nodes before the grid to nw64 past it: every
+      // position with a grid node in its window is within half a stride of
+      // one
+      I.gto = (I.nw64 + I.gts - 1) / I.gts * I.gts;
+      I.gtr = (I.n_y - 1 + 2 * I.gto + I.gts - 1) / I.gts + 1;
+    }
+  }
   // window segments: enough work units to fill the GPU when the instance is
   // small, segments of at least 256 nodes
   if (prec == UCP_FP64 || prec == UCP_FP64_GT) {
@@ -190,7 +208,7 @@ size_t state_bytes(const Inst& I) {
   b += align_up((size_t)(2 * I.nw32 + 1 + kGtabPad) * 4);          // gtab (padded past the window)
   b += align_up(nx * (size_t)(I.cands + 1) * (size_t)I.segs * 8); // part
   b += align_up((size_t)I.u1_slices * ny * 3 * 8);                // u1part
-  if (I.prec == UCP_FP64_GT) b += align_up(ny * 3 * (size_t)(I.gtn + 1) * 8);  // gt
+  if (I.gts) b += align_up((size_t)I.gtr * 3 * (kGtN + 1) * 8);   // gt
   b += 256 + kCountBytes;                                         // flags, counters
   return b;
 }
@@ -216,7 +234,7 @@ void carve_state(Inst& I, char*& base) {
   I.gtab = (float*)take((size_t)(2 * I.nw32 + 1 + kGtabPad) * 4);
   I.part = (double*)take(nx * (size_t)(I.cands + 1) * (size_t)I.segs * 8);
   I.u1part = (double*)take((size_t)I.u1_slices * ny * 3 * 8);
-  I.gt = I.prec == UCP_FP64_GT ? (double*)take(ny * 3 * (size_t)(I.gtn + 1) * 8) : nullptr;
+  I.gt = I.gts ? (double*)take((size_t)I.gtr * 3 * (kGtN + 1) * 8) : nullptr;
   I.flags = (int32_t*)take(256);
   I.terms = (unsigned long long*)take(kCountBytes);
 }

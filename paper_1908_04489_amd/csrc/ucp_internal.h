@@ -46,7 +46,8 @@ constexpr double kTau32Kahan = 5e-7;
 constexpr double kTau32Plain = 5e-6;
 constexpr double kKappa32 = 6e-7;
 constexpr double kTau64 = 1e-12;// FP64 tie band (relative)
-constexpr int kGtMaxN = 12;     // highest expansion order of the Gauss-transform table
+constexpr int kGtN = 12;        // expansion order of the Gauss-transform moment table
+constexpr double kGtStep = 0.05; // its rows lie at most this many noise sds apart
 constexpr double kWin32 = 9.0;  // window half-width, noise sds (FP32 terms)
 // FP64 window half-width, noise sds.  B has no useful lower bound (a point
 // whose x0 + u lands on a flat step of u1 has B far below the noise
@@ -89,7 +90,9 @@ struct Inst {
   // geometry
   int32_t nw32, nw64;        // window half-widths in y nodes
   int32_t rs64;              // FP64 walks: steps of a wave between reseeds (a power of two, <= 32)
-  int32_t gtn;               // UCP_FP64_GT: expansion order N of the moment table (0 otherwise)
+  int32_t gts;               // moment table: rows every gts-th y node (0: no table)
+  int32_t gtr;               // its rows, centred on nodes r gts - gto (r < gtr), from at
+  int32_t gto;               // least nw64 before the grid to nw64 past it (gto a multiple of gts)
   int32_t segs;              // marginal-cost units (partial sums) per (tile, candidate)
   int32_t wsegs;             // equal window segments (the last one dispatched split in two when segs > wsegs)
   int32_t u1_slices;         // x slices of the u1 sums
@@ -110,7 +113,7 @@ struct Inst {
   double* part;              // marginal-cost partial sums [n_x][cands + 1][segs]
   double* u1part;            // u1 partial sums [u1_slices][n_y][3]
   double* jrow;              // per-point objective terms [n_x]
-  double* gt;                // UCP_FP64_GT moment table [n_y][3][gtn + 1] (A0, A1, A2 by order)
+  double* gt;                // moment table [gtr][3][kGtN + 1] (A0, A1, A2 by order), or NULL
   double* J_out;             // objective output (one double)
   double* L0_out;            // optional FP64 L_0 of the accepted u0 [n_x] (argmin call only)
   int32_t* flags;            // bit 0: non-finite value met
@@ -136,7 +139,7 @@ struct Launch {
 // Kernel launchers (ucp_kernels.hip).  All enqueue on `st`.
 hipError_t launch_prior(const Launch& L, hipStream_t st);
 hipError_t launch_gtab(const Launch& L, hipStream_t st);
-// UCP_FP64_GT: the moment table of every instance in GT mode (after a u1 update)
+// The moment table of every instance that keeps one (from its current u1)
 hipError_t launch_gt_table(const Launch& L, hipStream_t st);
 // Launchers that take (e0, e1) record e0 when the first kernel starts and e1
 // when the last one ends (hipExtLaunchKernel: no extra packets in the stream).

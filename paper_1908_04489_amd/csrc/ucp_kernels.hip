@@ -888,37 +888,41 @@ __global__ __launch_bounds__(kMcBlock) void k_mc64(Launch L, int level) {
 
 // ------------------------------------------- Gauss-transform arithmetic
 //
-// For z within half a spacing of node y_k (delta = z - y_k, in noise sds
-// d = delta / s, t_j = (y_j - y_k) / s):
+// For z within d = (z - c) / s of a centre c (delta = z - c, t_j =
+// (y_j - c) / s):
 //   sum_j exp(-(y_j - z)^2 / (2 s^2)) (z - u1_j)^2
 //     = e^{-d^2/2} sum_n d^n / n! [A2_n + 2 delta A1_n + delta^2 A0_n],
-//   A_a,n = sum_j e^{-t_j^2/2} t_j^n (y_k - u1_j)^a,
-// since exp(t d) = sum_n (t d)^n / n! and z - u1_j = (y_k - u1_j) + delta.
-// k_gt_table tabulates A_a,n (n <= I.gtn) per node after each u1 update:
-// one wave per node over its window of 11 noise sds, the Gaussian by the
-// reseeded recurrence of the FP64 sums (delta = 0 at a node).  k_mc_gt
-// then evaluates every (point, candidate) in O(gtn).
+//   A_a,n = sum_j e^{-t_j^2/2} t_j^n (c - u1_j)^a,
+// since exp(t d) = sum_n (t d)^n / n! and z - u1_j = (c - u1_j) + delta.
+// The table holds A_a,n (n <= kGtN) for the centres c = y_lo + k dy, k =
+// r gts - gto (row r), over the grid nodes within nw64 of k; the centres run
+// from nw64 nodes before the grid to nw64 past it (the sums still run over
+// grid nodes only), so every z whose window holds a grid node lies within
+// half a row spacing of a centre, and any other z has a noise sum of 0.
+// k_gt_table fills it after each u1 update: one wave per row over its
+// window, the Gaussian by the reseeded recurrence of the FP64 sums (delta
+// = 0 at a centre).  gt_noise_sum then costs O(kGtN) per position.
 
-int32_t units_gt(const Inst& I) { return I.prec == UCP_FP64_GT ? (I.n_y + 3) / 4 : 0; }
+int32_t units_gt(const Inst& I) { return I.gts ? (I.gtr + 3) / 4 : 0; }
 
 __global__ __launch_bounds__(256) void k_gt_table(Launch L) {
   const int u = blockIdx.x;
   const int b = find_inst(L.pre, L.n_inst, u);
   const Inst& I = L.insts[b];
   const int lane = (int)threadIdx.x % kWave;
-  const int k = (u - L.pre[b]) * 4 + (int)threadIdx.x / kWave;
-  if (k >= I.n_y) return;  // whole waves
-  const int N = I.gtn;
+  const int r = (u - L.pre[b]) * 4 + (int)threadIdx.x / kWave;
+  if (r >= I.gtr) return;  // whole waves
+  const int k = r * I.gts - I.gto;  // the row's centre node (may lie off the grid)
   const int klo = max(-I.nw64, -k), khi = min(I.nw64, I.n_y - 1 - k);
-  const int n = khi - klo + 1;
+  const int n = max(0, khi - klo + 1);  // 0 for a centre whose window misses the grid
   const double dy = I.dy * I.isw, D = (double)kWave * dy;
   const double q = exp(-D * D);
   const double yk = I.y_lo + (double)k * I.dy;
   const int rs = I.rs64;
-  glb_dptr u1 = (glb_dptr)(I.u1 + k + klo + lane);
-  double A0[kGtMaxN + 1], A1[kGtMaxN + 1], A2[kGtMaxN + 1];
+  glb_dptr u1 = (glb_dptr)(I.u1 + max(0, k + klo) + lane);  // k + klo >= 0 whenever n > 0
+  double A0[kGtN + 1], A1[kGtN + 1], A2[kGtN + 1];
 #pragma unroll
-  for (int m = 0; m <= kGtMaxN; ++m) A0[m] = A1[m] = A2[m] = 0.0;
+  for (int m = 0; m <= kGtN; ++m) A0[m] = A1[m] = A2[m] = 0.0;
   B64Walk w;
   const int steps = (n + kWave - 1) / kWave;
   for (int m = 0; m < steps; ++m) {
@@ -929,28 +933,24 @@ __global__ __launch_bounds__(256) void k_gt_table(Launch L) {
       const double v2 = v * v;
       double p = w.g;
 #pragma unroll
-      for (int o = 0; o <= kGtMaxN; ++o) {
-        if (o <= N) {
-          A0[o] += p;
-          A1[o] = fma(p, v, A1[o]);
-          A2[o] = fma(p, v2, A2[o]);
-          p *= t;
-        }
+      for (int o = 0; o <= kGtN; ++o) {
+        A0[o] += p;
+        A1[o] = fma(p, v, A1[o]);
+        A2[o] = fma(p, v2, A2[o]);
+        p *= t;
       }
     }
     w.g *= w.r;
     w.r *= q;
   }
-  double* row = I.gt + (size_t)k * 3 * (N + 1);
+  double* row = I.gt + (size_t)r * 3 * (kGtN + 1);
 #pragma unroll
-  for (int o = 0; o <= kGtMaxN; ++o) {
-    if (o <= N) {
-      const double s0 = grp_sum_d<kWave>(A0[o]), s1 = grp_sum_d<kWave>(A1[o]), s2 = grp_sum_d<kWave>(A2[o]);
-      if (lane == 0) {
-        row[o] = s0;
-        row[(N + 1) + o] = s1;
-        row[2 * (N + 1) + o] = s2;
-      }
+  for (int o = 0; o <= kGtN; ++o) {
+    const double s0 = grp_sum_d<kWave>(A0[o]), s1 = grp_sum_d<kWave>(A1[o]), s2 = grp_sum_d<kWave>(A2[o]);
+    if (lane == 0) {
+      row[o] = s0;
+      row[(kGtN + 1) + o] = s1;
+      row[2 * (kGtN + 1) + o] = s2;
     }
   }
 }
@@ -961,9 +961,46 @@ hipError_t launch_gt_table(const Launch& L, hipStream_t st) {
   return hipGetLastError();
 }
 
-// Marginal cost from the table: lane = point, as k_mc64; positions farther
-// than half a spacing from every node (beyond the grid's ends) are summed
-// directly.  Stores B itself.
+// 1 / n for the series' Horner steps.
+__constant__ double kGtInv[kGtN + 2] = {0.0,       1.0,       1.0 / 2,  1.0 / 3,  1.0 / 4,  1.0 / 5,  1.0 / 6,
+                                        1.0 / 7,   1.0 / 8,   1.0 / 9,  1.0 / 10, 1.0 / 11, 1.0 / 12, 1.0 / 13};
+static_assert(kGtN == 12, "kGtInv holds 1/n for n <= kGtN + 1");
+
+// The noise part of B at z, dy/(s sqrt(2 pi)) sum_j exp(-(y_j - z)^2 /
+// (2 s^2)) (z - u1_j)^2 over the grid nodes within the window, per lane,
+// from the moment table: the row whose centre is nearest z (within half a
+// row spacing), or 0 where no row is that near (no grid node within the
+// window).  LEAN keeps the series loop rolled (three row loads per order
+// instead of all 3 (kGtN + 1) at once), for callers whose registers are
+// scarce.
+template <bool LEAN = false>
+__device__ __forceinline__ double gt_noise_sum(const Inst& I, double z) {
+  const double span = (double)I.gts * I.dy;
+  const double rr = rint((z - I.y_lo) / span) + (double)(I.gto / I.gts);
+  if (!(rr >= 0.0 && rr <= (double)(I.gtr - 1))) return 0.0;
+  const int r = (int)rr;
+  const double del = z - (I.y_lo + (double)(r * I.gts - I.gto) * I.dy);
+  const double* row = I.gt + (size_t)r * 3 * (kGtN + 1);
+  const double d = del * I.isw;
+  double acc = 0.0;
+  if (LEAN) {
+#pragma unroll 1
+    for (int o = kGtN; o >= 0; --o) {
+      const double C = fma(del, fma(del, row[o], 2.0 * row[(kGtN + 1) + o]), row[2 * (kGtN + 1) + o]);
+      acc = fma(acc, d * kGtInv[o + 1], C);
+    }
+  } else {
+#pragma unroll
+    for (int o = kGtN; o >= 0; --o) {
+      const double C = fma(del, fma(del, row[o], 2.0 * row[(kGtN + 1) + o]), row[2 * (kGtN + 1) + o]);
+      acc = fma(acc, d * kGtInv[o + 1], C);
+    }
+  }
+  return I.phi_scale * exp(-0.5 * d * d) * acc;
+}
+
+// Marginal cost from the table (UCP_FP64_GT): lane = point, as k_mc64.
+// Stores B itself.
 __global__ __launch_bounds__(kMcBlock) void k_mc_gt(Launch L, int level) {
   const int u = blockIdx.x;
   const int b = find_inst(L.pre, L.n_inst, u);
@@ -978,24 +1015,7 @@ __global__ __launch_bounds__(kMcBlock) void k_mc_gt(Launch L, int level) {
   const double z = (I.x_lo + (double)(act ? i : I.n_x - 1) * I.dx) + c;
   count_terms(I, z, act, (int)threadIdx.x % kWave);
   if (!act) return;
-  const int kn = nearest_node(I, z);
-  const double del = z - (I.y_lo + (double)kn * I.dy);
-  double G;
-  if (fabs(del) <= 0.5 * I.dy * (1.0 + 1e-12)) {
-    const int N = I.gtn;
-    const double* row = I.gt + (size_t)kn * 3 * (N + 1);
-    const double d = del * I.isw;
-    double acc = 0.0;
-    for (int o = N; o >= 0; --o) {
-      const double C = row[2 * (N + 1) + o] + 2.0 * del * row[(N + 1) + o] + del * del * row[o];
-      acc = C + acc * d / (double)(o + 1);
-    }
-    G = I.phi_scale * exp(-0.5 * d * d) * acc;
-  } else {
-    const double delta = -del * I.isw;  // (y_k - z) / s
-    G = I.phi_scale * exp(-0.5 * delta * delta) * lane_sum64(I, z, kn, delta);
-  }
-  I.part[(size_t)i * (I.cands + 1) + q] = I.k2 * c * c + G;
+  I.part[(size_t)i * (I.cands + 1) + q] = I.k2 * c * c + gt_noise_sum(I, z);
 }
 
 hipError_t launch_mc(const Launch& L, int level, int prec, hipStream_t st, hipEvent_t e0, hipEvent_t e1) {
@@ -1227,7 +1247,10 @@ __device__ void accept(const Inst& I, int i, double x, double uinc, double cw, d
     Q.c = c2;
     return;
   }
-  if (todo == 3ull) {  // both: one pass over their windows
+  if (I.gt) {  // each lane its own value from the moment table
+    if ((todo >> lane) & 1ull) b64 = I.k2 * c2 * c2 + gt_noise_sum<true>(I, x + c2);
+    n_eval += __popcll(todo);
+  } else if (todo == 3ull) {  // both: one pass over their windows
     const double c0 = grp_shfl<W>(c2, 0), c1 = grp_shfl<W>(c2, 1);
     const double z[2] = {x + c0, x + c1};
     double v[2];
@@ -1404,30 +1427,42 @@ __device__ void select_block(const Inst& I, int local, int level, int want_l0, S
     }
   }
   __syncthreads();
+  int n_gt = 0;  // values this thread took from the moment table
   if (total) {
-    const int wl = (int)threadIdx.x % kWave;
-    for (int ch = wid; ch * kEvalChunk < total; ch += kSelWaves) {
-      SelItem it[kEvalChunk];
-#pragma unroll
-      for (int q = 0; q < kEvalChunk; ++q) it[q] = sq[ch * kEvalChunk + q];
-      int cnt = 0;  // valid entries lead the chunk
-#pragma unroll
-      for (int q = 0; q < kEvalChunk; ++q) cnt += it[q].i >= 0;
-      if (cnt == 0) continue;
-      const double x = I.x_lo + (double)it[0].i * I.dx;
-      double z[kEvalChunk], v[kEvalChunk];
-#pragma unroll
-      for (int q = 0; q < kEvalChunk; ++q) z[q] = x + (q < cnt ? it[q].c : it[0].c);  // static indices only
-      if (cnt == 1) v[0] = b64_wave(I, z[0], wl);
-      else if (cnt == 2) b64_multi<2>(I, z, wl, v);
-      else if (cnt == 3) b64_multi<3>(I, z, wl, v);
-      else b64_multi<4>(I, z, wl, v);
-      if (wl == 0) {
-#pragma unroll
-        for (int q = 0; q < kEvalChunk; ++q)
-          if (q < cnt) sres[ch * kEvalChunk + q] = I.k2 * it[q].c * it[q].c + v[q];
+    if (!F64<PREC> && I.gt) {
+      // one thread per queued position, its value from the moment table
+      for (int e = (int)threadIdx.x; e < total; e += kSelWaves * kWave) {
+        const SelItem it = sq[e];
+        if (it.i < 0) continue;
+        const double z = (I.x_lo + (double)it.i * I.dx) + it.c;
+        sres[e] = I.k2 * it.c * it.c + gt_noise_sum(I, z);
+        ++n_gt;
       }
-      n_eval += wl == 0 ? cnt : 0;
+    } else {
+      const int wl = (int)threadIdx.x % kWave;
+      for (int ch = wid; ch * kEvalChunk < total; ch += kSelWaves) {
+        SelItem it[kEvalChunk];
+#pragma unroll
+        for (int q = 0; q < kEvalChunk; ++q) it[q] = sq[ch * kEvalChunk + q];
+        int cnt = 0;  // valid entries lead the chunk
+#pragma unroll
+        for (int q = 0; q < kEvalChunk; ++q) cnt += it[q].i >= 0;
+        if (cnt == 0) continue;
+        const double x = I.x_lo + (double)it[0].i * I.dx;
+        double z[kEvalChunk], v[kEvalChunk];
+#pragma unroll
+        for (int q = 0; q < kEvalChunk; ++q) z[q] = x + (q < cnt ? it[q].c : it[0].c);  // static indices only
+        if (cnt == 1) v[0] = b64_wave(I, z[0], wl);
+        else if (cnt == 2) b64_multi<2>(I, z, wl, v);
+        else if (cnt == 3) b64_multi<3>(I, z, wl, v);
+        else b64_multi<4>(I, z, wl, v);
+        if (wl == 0) {
+#pragma unroll
+          for (int q = 0; q < kEvalChunk; ++q)
+            if (q < cnt) sres[ch * kEvalChunk + q] = I.k2 * it[q].c * it[q].c + v[q];
+        }
+        n_eval += wl == 0 ? cnt : 0;
+      }
     }
     __syncthreads();
     if (Q.kind) {
@@ -1435,9 +1470,10 @@ __device__ void select_block(const Inst& I, int local, int level, int want_l0, S
       resolve_point<PREC, W>(I, level, i, lane, want_l0, n_eval, Q.kind, qv, c, B32, B64, in_set);
     }
   }
-  // one count per wave: the group leaders' counts (band and resolve) and
-  // the wave's chunk counts
-  int ne = lane == 0 ? n_eval : ((int)threadIdx.x % kWave == 0 ? n_eval : 0);
+  // one count per wave: the group leaders' counts (band and resolve, and
+  // the wave's chunk counts, kept by its first lane) and every thread's
+  // values from the moment table
+  int ne = (lane == 0 ? n_eval : 0) + n_gt;
   for (int o = kWave / 2; o > 0; o >>= 1) ne += __shfl_xor(ne, o);
   if ((int)threadIdx.x % kWave == 0) count_evals(I, ne);
 }

@@ -50,11 +50,13 @@ size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
 
 // The state the u0 update uses, carved from `base`: the update reads the
 // caller's u0 and u1 in place, and never touches the u1 partial sums, the
-// objective rows or the work counters.
+// objective rows or the work counters.  The moment table (FP32 modes on
+// grids fine enough for it) is rebuilt from u1 by every call.
 size_t update_bytes(const Inst& I) {
   const size_t nx = (size_t)I.n_x, ny = (size_t)I.n_y;
   return 7 * align256(nx * 8) + align256(ny * 4) + align256((size_t)(2 * I.nw32 + 1 + kGtabPad) * 4) +
-         align256(nx * (size_t)(I.cands + 1) * (size_t)I.segs * 8) + 256;
+         align256(nx * (size_t)(I.cands + 1) * (size_t)I.segs * 8) + 256 +
+         (I.gts ? align256((size_t)I.gtr * 3 * (kGtN + 1) * 8) : 0);
 }
 void carve_update(Inst& I, char* base) {
   const size_t nx = (size_t)I.n_x, ny = (size_t)I.n_y;
@@ -74,6 +76,7 @@ void carve_update(Inst& I, char* base) {
   I.gtab = (float*)take((size_t)(2 * I.nw32 + 1 + kGtabPad) * 4);
   I.part = (double*)take(nx * (size_t)(I.cands + 1) * (size_t)I.segs * 8);
   I.flags = (int32_t*)take(256);
+  I.gt = I.gts ? (double*)take((size_t)I.gtr * 3 * (kGtN + 1) * 8) : nullptr;
   I.u1part = nullptr;
   I.jrow = nullptr;
   I.terms = nullptr;
@@ -156,6 +159,7 @@ extern "C" int ucp_argmin_adaptive_noalloc(ucp_handle* h, const ucp_problem* pro
   NA_TRY(launch_prior(L(kKindPrior), st), "prior kernel");
   NA_TRY(launch_gtab(L(kKindGtab), st), "offset table kernel");
   NA_TRY(launch_v_from_u1(L(kKindU1c), st), "residual kernel");
+  NA_TRY(launch_gt_table(L(kKindGt), st), "moment table kernel");
   for (int l = 0; l < I.levels; ++l) {
     NA_TRY(launch_mc(L(kKindMc0 + l), l, prec, st), "marginal-cost kernel");
     NA_TRY(launch_select(L(kKindSel0 + l), l, prec, L0_out != nullptr, st), "selection kernel");

@@ -33,7 +33,7 @@ int check_search(const ucp_search* s);
 // relative tie band of the selection rule: the search's, or the default
 double tie_band(const ucp_search* s);
 int check_prec(int prec);
-// UCP_FP64_GT needs an expansion order the kernels hold (N <= kGtMaxN)
+// UCP_FP64_GT needs a grid its moment table can serve (dy / s <= kGtStep)
 int check_gt(const Inst& I);
 Inst make_inst(const ucp_problem& p, const ucp_search* s, int prec, int cands_override);
 size_t state_bytes(const Inst& I);
