@@ -558,7 +558,8 @@ int setup_batch(ucp_handle* h, Batch& B, std::vector<Inst> insts, const std::vec
 int run_round(ucp_handle* h, const Batch& B, int phase, const std::vector<int32_t>& tab, int prec, int max_levels,
               int t, hipStream_t st) {
   EvPair p;
-  UCP_TRY(launch_gt_table(B.launch(phase, kKindGt, tab), st), "moment table kernel");
+  // the levels read the moment table of the current u1, built after the
+  // u1 update that produced it (previous round, or the set-up)
   for (int l = 0; l < max_levels; ++l) {
     const Launch Lm = B.launch(phase, kKindMc0 + l, tab), Ls = B.launch(phase, kKindSel0 + l, tab);
     UCP_TRY(prof_pair(h, UCP_PROF_MC, Lm.total > 0, p), "event");
@@ -571,6 +572,7 @@ int run_round(ucp_handle* h, const Batch& B, int phase, const std::vector<int32_
   UCP_TRY(prof_pair(h, UCP_PROF_U1, Lp.total > 0 && Lc.total > 0, p), "event");
   UCP_TRY(launch_u1_partial(Lp, prec, st, p.a), "u1 kernel");
   UCP_TRY(launch_u1_combine(Lc, st, p.b), "u1 combine kernel");
+  UCP_TRY(launch_gt_table(B.launch(phase, kKindGt, tab), st), "moment table kernel");
   const Launch Lr = B.launch(phase, kKindJRows, tab), Ld = B.launch(phase, kKindJRed, tab);
   UCP_TRY(prof_pair(h, UCP_PROF_J, Lr.total > 0 && Ld.total > 0, p), "event");
   UCP_TRY(launch_j_rows(Lr, st, p.a), "objective kernel");
@@ -584,6 +586,7 @@ int run_init(const Batch& B, int phase, const std::vector<int32_t>& tab, int pre
   UCP_TRY(launch_gtab(B.launch(phase, kKindGtab, tab), st), "offset table kernel");
   UCP_TRY(launch_u1_partial(B.launch(phase, kKindU1p, tab), prec, st), "u1 kernel");
   UCP_TRY(launch_u1_combine(B.launch(phase, kKindU1c, tab), st), "u1 combine kernel");
+  UCP_TRY(launch_gt_table(B.launch(phase, kKindGt, tab), st), "moment table kernel");
   UCP_TRY(launch_j_rows(B.launch(phase, kKindJRows, tab), st), "objective kernel");
   UCP_TRY(launch_j_reduce_t(B.launch(phase, kKindJRed, tab), 0, st), "objective reduce kernel");
   return UCP_OK;

@@ -1729,12 +1729,24 @@ hipError_t launch_u1_combine(const Launch& L, hipStream_t st, hipEvent_t e1) {
 
 // ------------------------------------------------------------- objective
 
-int32_t units_j_rows(const Inst& I) { return (I.n_x + kJWaves * kJPts - 1) / (kJWaves * kJPts); }
+// With a moment table (built from the u1 the objective is taken with) one
+// thread per point, else one wave per kJPts points.
+int32_t units_j_rows(const Inst& I) {
+  return I.gts ? (I.n_x + kJWaves * kWave - 1) / (kJWaves * kWave) : (I.n_x + kJWaves * kJPts - 1) / (kJWaves * kJPts);
+}
 
 __global__ __launch_bounds__(kJWaves * kWave) void k_j_rows(Launch L) {
   const int u = blockIdx.x;
   const int b = find_inst(L.pre, L.n_inst, u);
   const Inst& I = L.insts[b];
+  if (I.gts) {  // the point's noise sum from the moment table
+    const int i = (u - L.pre[b]) * (kJWaves * kWave) + (int)threadIdx.x;
+    if (i >= I.n_x) return;
+    const double u0 = I.u0[i];
+    const double z = (I.x_lo + (double)i * I.dx) + u0;
+    I.jrow[i] = I.f[i] * (I.k2 * u0 * u0 + gt_noise_sum(I, z));
+    return;
+  }
   const int wid = threadIdx.x / kWave, lane = threadIdx.x % kWave;
   // kJPts consecutive points per wave: their x1 mostly coincide (the
   // controller is a staircase), so one pass over the union of their windows

@@ -357,10 +357,11 @@ extern "C" int ucp_server_step(ucp_server* s, int32_t* n_running) {
     SRV_TRY(launch_gtab(L(0, kKindGtab, 0), st), "offset table kernel");
     SRV_TRY(launch_u1_partial(L(0, kKindU1p, 0), prec, st), "u1 kernel");
     SRV_TRY(launch_u1_combine(L(0, kKindU1c, 0), st), "u1 combine kernel");
+    SRV_TRY(launch_gt_table(L(0, kKindGt, 0), st), "moment table kernel");
     SRV_TRY(launch_j_rows(L(0, kKindJRows, 0), st), "objective kernel");
     SRV_TRY(launch_j_reduce_t(L(0, kKindJRed, 0), 0, st), "objective reduce kernel");
-    // one round for every running request
-    SRV_TRY(launch_gt_table(L(1, kKindGt, 1), st), "moment table kernel");
+    // one round for every running request (the levels read the moment
+    // table built after the request's last u1 update)
     for (int l = 0; l < max_lv; ++l) {
       SRV_TRY(launch_mc(L(1, kKindMc0 + l, 1), l, prec, st), "marginal-cost kernel");
       SRV_TRY(launch_select(L(1, kKindSel0 + l, 1), l, prec, 0, st), "selection kernel");
@@ -368,6 +369,7 @@ extern "C" int ucp_server_step(ucp_server* s, int32_t* n_running) {
     SRV_TRY(launch_copy_u0(L(1, kKindCopy, 1), st), "u0 advance kernel");
     SRV_TRY(launch_u1_partial(L(1, kKindU1p, 1), prec, st), "u1 kernel");
     SRV_TRY(launch_u1_combine(L(1, kKindU1c, 1), st), "u1 combine kernel");
+    SRV_TRY(launch_gt_table(L(1, kKindGt, 1), st), "moment table kernel");
     SRV_TRY(launch_j_rows(L(1, kKindJRows, 1), st), "objective kernel");
     SRV_TRY(launch_j_reduce_t(L(1, kKindJRed, 1), 0, st), "objective reduce kernel");
     // retire
