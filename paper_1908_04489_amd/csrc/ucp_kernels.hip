@@ -925,23 +925,43 @@ __global__ __launch_bounds__(256) void k_gt_table(Launch L) {
   for (int m = 0; m <= kGtN; ++m) A0[m] = A1[m] = A2[m] = 0.0;
   B64Walk w;
   const int steps = (n + kWave - 1) / kWave;
-  for (int m = 0; m < steps; ++m) {
-    if ((m & (rs - 1)) == 0) b64_reseed<kWave>(w, klo, lane, m, dy, 0.0, D);
-    if (lane + kWave * m < n) {
-      const double t = (double)(klo + lane + kWave * m) * dy;
-      const double v = yk - u1[kWave * m];
-      const double v2 = v * v;
-      double p = w.g;
+  // u1 loads of the next kGtGroup steps are issued before the current
+  // group is consumed: a small table has about one wave per SIMD, which
+  // would otherwise wait out each step's load
+  constexpr int kGtGroup = 8;
+  double nx[kGtGroup];
 #pragma unroll
-      for (int o = 0; o <= kGtN; ++o) {
-        A0[o] += p;
-        A1[o] = fma(p, v, A1[o]);
-        A2[o] = fma(p, v2, A2[o]);
-        p *= t;
+  for (int e = 0; e < kGtGroup; ++e) nx[e] = lane + kWave * e < n ? (double)u1[kWave * e] : 0.0;
+  for (int m0 = 0; m0 < steps; m0 += kGtGroup) {
+    double uv[kGtGroup];
+#pragma unroll
+    for (int e = 0; e < kGtGroup; ++e) {
+      uv[e] = nx[e];
+      const int mn = m0 + kGtGroup + e;
+      nx[e] = lane + kWave * mn < n ? (double)u1[kWave * mn] : 0.0;
+    }
+#pragma unroll
+    for (int e = 0; e < kGtGroup; ++e) {
+      const int m = m0 + e;
+      if (m < steps) {
+        if ((m & (rs - 1)) == 0) b64_reseed<kWave>(w, klo, lane, m, dy, 0.0, D);
+        if (lane + kWave * m < n) {
+          const double t = (double)(klo + lane + kWave * m) * dy;
+          const double v = yk - uv[e];
+          const double v2 = v * v;
+          double p = w.g;
+#pragma unroll
+          for (int o = 0; o <= kGtN; ++o) {
+            A0[o] += p;
+            A1[o] = fma(p, v, A1[o]);
+            A2[o] = fma(p, v2, A2[o]);
+            p *= t;
+          }
+        }
+        w.g *= w.r;
+        w.r *= q;
       }
     }
-    w.g *= w.r;
-    w.r *= q;
   }
   double* row = I.gt + (size_t)r * 3 * (kGtN + 1);
 #pragma unroll
