@@ -112,6 +112,7 @@ struct Inst {
   double* b32inc;            // FP32-path cost B of the incumbent [n_x]
   double* part;              // marginal-cost partial sums [n_x][cands + 1][segs]
   double* u1part;            // u1 partial sums [u1_slices][n_y][3]
+  double* u1stat;            // u1 culling data: per-tile logit bounds, then per-chunk x1 range and max log f
   double* jrow;              // per-point objective terms [n_x]
   double* gt;                // moment table [gtr][3][kGtN + 1] (A0, A1, A2 by order), or NULL
   double* J_out;             // objective output (one double)
@@ -169,6 +170,8 @@ hipError_t launch_a1_pe_u1(const Inst& I, const Inst* dI, int r, double tie, con
 int32_t units_mc(const Inst& I, int level);
 int32_t units_select(const Inst& I);
 int32_t units_u1_partial(const Inst& I);
+// doubles of the u1 culling data
+size_t u1stat_doubles(const Inst& I);
 int32_t units_u1_combine(const Inst& I);
 int32_t units_j_rows(const Inst& I);
 int32_t units_prior(const Inst& I);

@@ -1552,14 +1552,100 @@ __device__ __forceinline__ double block_max_d(double v, double* sw) {
   return v;
 }
 
+// Culling data of the u1 sums, each part depending on one tile or one chunk
+// alone (so the partial-sum blocks need not recompute it): per tile the
+// lower bound lb of its logit maxima, per chunk of a slice the range of its
+// x1 and its largest log f (NaN when the chunk holds a non-finite x1 or
+// log f).  Layout: [tiles] bounds, then [slices][chunks per slice][3].
+__host__ __device__ inline int u1_tiles(const Inst& I) { return (I.n_y + kU1Block - 1) / kU1Block; }
+__host__ __device__ inline int u1_slen(const Inst& I) { return (I.n_x + I.u1_slices - 1) / I.u1_slices; }
+__host__ __device__ inline int u1_cps(const Inst& I) { return (u1_slen(I) + kU1Chunk - 1) / kU1Chunk; }
+size_t u1stat_doubles(const Inst& I) { return (size_t)u1_tiles(I) + (size_t)I.u1_slices * u1_cps(I) * 3; }
+
+// On the units of k_u1_partial: unit (tile, slice 0) takes its tile's
+// bound, unit (tile 0, slice) the chunks of its slice; the others exit.
+__global__ __launch_bounds__(kU1Block) void k_u1_stats(Launch L) {
+  constexpr int NW = kU1Block / kWave;
+  __shared__ double sb[3][NW];
+  const int u = blockIdx.x;
+  const int b = find_inst(L.pre, L.n_inst, u);
+  const Inst& I = L.insts[b];
+  const int local = u - L.pre[b];
+  const int slice = local % I.u1_slices;
+  const int tile = local / I.u1_slices;
+  if (slice != 0 && tile != 0) return;
+  const int nx = I.n_x;
+  const double x_lo = I.x_lo, dx = I.dx;
+  const double h2 = 0.5 * I.isw * I.isw;
+  const glb_dptr u0g = (glb_dptr)I.u0, lfg = (glb_dptr)I.logf;
+  if (slice == 0) {
+    // A lower bound on the logit maximum M_j of every node of the tile: any x
+    // node gives one, M_j >= l_ij >= log f_i - max over the tile's y of
+    // (y - x1_i)^2 / (2 s^2); every kU1Sample-th node is taken.
+    const int j0 = tile * kU1Block, j1 = min(I.n_y, j0 + kU1Block) - 1;
+    const double ya = I.y_lo + (double)j0 * I.dy, yb = I.y_lo + (double)j1 * I.dy;
+    double lb = -INFINITY;
+    for (int i = (int)threadIdx.x * kU1Sample; i < nx; i += kU1Block * kU1Sample) {
+      const double x1 = (x_lo + (double)i * dx) + u0g[i];
+      const double da = ya - x1, db = yb - x1;
+      lb = fmax(lb, lfg[i] - h2 * fmax(da * da, db * db));  // NaN terms drop out
+    }
+    lb = block_max_d(lb, sb[0]);
+    if (threadIdx.x == 0) I.u1stat[tile] = lb;
+    __syncthreads();  // sb is reused below
+  }
+  if (tile == 0) {
+    const int slen = u1_slen(I);
+    const int i0 = slice * slen, i1 = min(nx, i0 + slen);
+    double* cs = I.u1stat + u1_tiles(I) + (size_t)slice * u1_cps(I) * 3;
+    for (int c0 = i0, k = 0; c0 < i1; c0 += kU1Chunk, ++k) {
+      const int cn = min(kU1Chunk, i1 - c0);
+      double xmn = INFINITY, xmx = -INFINITY, fmx = -INFINITY;
+      bool bad = false;
+      for (int t = threadIdx.x; t < cn; t += kU1Block) {
+        const int i = c0 + t;
+        const double x1 = (x_lo + (double)i * dx) + u0g[i];
+        const double lf = lfg[i];
+        xmn = fmin(xmn, x1);
+        xmx = fmax(xmx, x1);
+        fmx = fmax(fmx, lf);
+        bad |= !isfinite(x1) || isnan(lf);
+      }
+      for (int o = kWave / 2; o > 0; o >>= 1) {
+        xmn = fmin(xmn, __shfl_xor(xmn, o));
+        xmx = fmax(xmx, __shfl_xor(xmx, o));
+        fmx = fmax(fmx, __shfl_xor(fmx, o));
+      }
+      const bool wbad = __ballot(bad) != 0ull;
+      if (threadIdx.x % kWave == 0) {
+        sb[0][threadIdx.x / kWave] = xmn;
+        sb[1][threadIdx.x / kWave] = xmx;
+        sb[2][threadIdx.x / kWave] = wbad ? NAN : fmx;
+      }
+      __syncthreads();
+      if (threadIdx.x == 0) {
+        bool cbad = false;
+        for (int w = 0; w < NW; ++w) {
+          xmn = fmin(xmn, sb[0][w]);
+          xmx = fmax(xmx, sb[1][w]);
+          fmx = fmax(fmx, sb[2][w]);
+          cbad |= isnan(sb[2][w]);
+        }
+        cs[k * 3 + 0] = xmn;
+        cs[k * 3 + 1] = xmx;
+        cs[k * 3 + 2] = cbad ? NAN : fmx;
+      }
+      __syncthreads();
+    }
+  }
+}
+
 template <int PREC>
 __global__ __launch_bounds__(kU1Block) void k_u1_partial(Launch L) {
-  constexpr int NW = kU1Block / kWave;
   __shared__ double sD[kU1Chunk];    // D_i = y_c - x1_i
   __shared__ double sP[kU1Chunk];    // P_i = log2(e) (log f_i - D_i^2 / (2 s^2)), s the noise sd
   __shared__ float sDf[kU1Chunk];    // D_i / s^2 in FP32 (maximum pass only)
   __shared__ float sPf[kU1Chunk];    // log f_i - D_i^2 / (2 s^2) in FP32 (maximum pass only)
-  __shared__ double sb[4][NW];       // per-wave bounds
   const int u = blockIdx.x;
   const int b = find_inst(L.pre, L.n_inst, u);
   const Inst& I = L.insts[b];
@@ -1569,30 +1655,21 @@ __global__ __launch_bounds__(kU1Block) void k_u1_partial(Launch L) {
   const int j = tile * kU1Block + (int)threadIdx.x;
   const bool act = j < I.n_y;
   const double y = I.y_lo + (double)(act ? j : 0) * I.dy;
-  const int slen = (I.n_x + I.u1_slices - 1) / I.u1_slices;
+  const int slen = u1_slen(I);
   const int i0 = slice * slen, i1 = min(I.n_x, i0 + slen);
   const double log2e = 1.4426950408889634073599246810019;
   // the noise variance s^2 divides every squared distance: h2 = 1 / (2 s^2)
   const double is2 = I.isw * I.isw, h2 = 0.5 * is2;
   const double c2 = h2 * log2e;
-  // A lower bound on the logit maximum M_j of every node of the tile: any x
-  // node gives one, M_j >= l_ij >= log f_i - max over the tile's y of
-  // (y - x1_i)^2 / 2; every kU1Sample-th node is taken.
   const int j0 = tile * kU1Block, j1 = min(I.n_y, j0 + kU1Block) - 1;
   const double ya = I.y_lo + (double)j0 * I.dy, yb = I.y_lo + (double)j1 * I.dy;
   // the instance is read through a generic pointer, which the LDS stores
   // below could alias: its fields and arrays are taken into registers and
   // global-space pointers once
-  const int nx = I.n_x;
   const double x_lo = I.x_lo, dx = I.dx;
   const glb_dptr u0g = (glb_dptr)I.u0, lfg = (glb_dptr)I.logf;
-  double lb = -INFINITY;
-  for (int i = (int)threadIdx.x * kU1Sample; i < nx; i += kU1Block * kU1Sample) {
-    const double x1 = (x_lo + (double)i * dx) + u0g[i];
-    const double da = ya - x1, db = yb - x1;
-    lb = fmax(lb, lfg[i] - h2 * fmax(da * da, db * db));  // NaN terms drop out
-  }
-  lb = block_max_d(lb, sb[0]);
+  const double lb = I.u1stat[tile];  // lower bound of the tile's logit maxima (k_u1_stats)
+  const double* cstat = I.u1stat + u1_tiles(I) + (size_t)slice * u1_cps(I) * 3;
   // Around the middle node y_c of the tile, y_j - x1_i = eta_j + D_i with
   // eta_j = y_j - y_c and D_i = y_c - x1_i, so the log2 weight (s the
   // noise sd)
@@ -1607,11 +1684,17 @@ __global__ __launch_bounds__(kU1Block) void k_u1_partial(Launch L) {
   const double E = -log2e * eta * is2;
   const float etaf = (float)eta;
   double M = -INFINITY, den = 0.0, num = 0.0;
-  for (int c0 = i0; c0 < i1; c0 += kU1Chunk) {
+  for (int c0 = i0, k = 0; c0 < i1; c0 += kU1Chunk, ++k) {
     const int cn = min(kU1Chunk, i1 - c0);
-    __syncthreads();
-    double xmn = INFINITY, xmx = -INFINITY, fmx = -INFINITY;
-    bool bad = false;
+    // the chunk's largest possible logit over the tile's nodes:
+    // max log f - (distance from [ya, yb] to [min x1, max x1])^2 / (2 s^2);
+    // skipped weights are below exp(-kU1Cull) of the largest: none of the
+    // sums moves (n_x exp(-kU1Cull) < 2^-60).  A chunk with a non-finite x1
+    // or log f (NaN maximum) is never skipped.
+    const double xmn = cstat[k * 3 + 0], xmx = cstat[k * 3 + 1], fmx = cstat[k * 3 + 2];
+    const double dist = fmax(0.0, fmax(xmn - yb, ya - xmx));
+    if (!isnan(fmx) && fmx - h2 * dist * dist < lb - kU1Cull) continue;
+    __syncthreads();  // the previous chunk's readers are done
     for (int t = threadIdx.x; t < cn; t += kU1Block) {
       const int i = c0 + t;
       const double x1 = (x_lo + (double)i * dx) + u0g[i];
@@ -1622,35 +1705,8 @@ __global__ __launch_bounds__(kU1Block) void k_u1_partial(Launch L) {
       sP[t] = Pn * log2e;
       sDf[t] = (float)(D * is2);
       sPf[t] = (float)Pn;
-      xmn = fmin(xmn, x1);
-      xmx = fmax(xmx, x1);
-      fmx = fmax(fmx, lf);
-      bad |= !isfinite(x1) || isnan(lf);
-    }
-    // the chunk's largest possible logit over the tile's nodes:
-    // max log f - (distance from [ya, yb] to [min x1, max x1])^2 / 2
-    for (int o = kWave / 2; o > 0; o >>= 1) {
-      xmn = fmin(xmn, __shfl_xor(xmn, o));
-      xmx = fmax(xmx, __shfl_xor(xmx, o));
-      fmx = fmax(fmx, __shfl_xor(fmx, o));
-    }
-    const bool wbad = __ballot(bad) != 0ull;
-    if (threadIdx.x % kWave == 0) {
-      sb[1][threadIdx.x / kWave] = xmn;
-      sb[2][threadIdx.x / kWave] = xmx;
-      sb[3][threadIdx.x / kWave] = wbad ? NAN : fmx;
     }
     __syncthreads();
-    for (int w = 0; w < NW; ++w) {
-      xmn = fmin(xmn, sb[1][w]);
-      xmx = fmax(xmx, sb[2][w]);
-      fmx = fmax(fmx, sb[3][w]);
-      bad |= isnan(sb[3][w]);
-    }
-    const double dist = fmax(0.0, fmax(xmn - yb, ya - xmx));
-    // skipped weights are below exp(-kU1Cull) of the largest: none of the
-    // sums moves (n_x exp(-kU1Cull) < 2^-60)
-    if (!bad && fmx - h2 * dist * dist < lb - kU1Cull) continue;
     // chunk maximum of the logits, in FP32: only a shift, any value near
     // the maximum works (the sums below use exact FP64 exponents)
     float mcf = -INFINITY;
@@ -1732,12 +1788,13 @@ __global__ __launch_bounds__(kU1Block) void k_u1_combine(Launch L) {
 
 hipError_t launch_u1_partial(const Launch& L, int prec, hipStream_t st, hipEvent_t e0) {
   if (L.total == 0) return hipSuccess;
+  hipExtLaunchKernelGGL(k_u1_stats, dim3(L.total), dim3(kU1Block), 0, st, e0, nullptr, 0, L);
   if (prec == UCP_FP64 || prec == UCP_FP64_GT)  // the u1 update of UCP_FP64_GT is UCP_FP64's
-    hipExtLaunchKernelGGL(k_u1_partial<UCP_FP64>, dim3(L.total), dim3(kU1Block), 0, st, e0, nullptr, 0, L);
+    hipLaunchKernelGGL(k_u1_partial<UCP_FP64>, dim3(L.total), dim3(kU1Block), 0, st, L);
   else if (prec == UCP_FP32_KAHAN)
-    hipExtLaunchKernelGGL(k_u1_partial<UCP_FP32_KAHAN>, dim3(L.total), dim3(kU1Block), 0, st, e0, nullptr, 0, L);
+    hipLaunchKernelGGL(k_u1_partial<UCP_FP32_KAHAN>, dim3(L.total), dim3(kU1Block), 0, st, L);
   else
-    hipExtLaunchKernelGGL(k_u1_partial<UCP_FP32>, dim3(L.total), dim3(kU1Block), 0, st, e0, nullptr, 0, L);
+    hipLaunchKernelGGL(k_u1_partial<UCP_FP32>, dim3(L.total), dim3(kU1Block), 0, st, L);
   return hipGetLastError();
 }
 

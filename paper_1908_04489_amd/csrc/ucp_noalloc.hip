@@ -78,6 +78,7 @@ void carve_update(Inst& I, char* base) {
   I.flags = (int32_t*)take(256);
   I.gt = I.gts ? (double*)take((size_t)I.gtr * 3 * (kGtN + 1) * 8) : nullptr;
   I.u1part = nullptr;
+  I.u1stat = nullptr;
   I.jrow = nullptr;
   I.terms = nullptr;
 }
