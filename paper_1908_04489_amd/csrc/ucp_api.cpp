@@ -261,7 +261,7 @@ std::vector<int32_t> build_tables(const std::vector<Inst>& insts, const std::vec
       int32_t u = 0;
       if (running[b]) {
         if (k < kKindSel0) u = I.free_cands ? 0 : units_mc(I, k - kKindMc0);
-        else if (k < kKindU1p) u = (k - kKindSel0) < I.levels ? units_select(I) : 0;
+        else if (k < kKindU1p) u = (k - kKindSel0) < I.levels && !table_select(I) ? units_select(I) : 0;
         else if (k == kKindU1p) u = units_u1_partial(I);
         else if (k == kKindU1c) u = units_u1_combine(I);
         else if (k == kKindJRows) u = units_j_rows(I);
@@ -272,6 +272,7 @@ std::vector<int32_t> build_tables(const std::vector<Inst>& insts, const std::vec
         else if (k == kKindFin) u = I.free_cands ? (int32_t)(((int64_t)I.n_x * I.cands + 255) / 256) : 0;
         else if (k == kKindGtab) u = units_gtab(I);
         else if (k == kKindGt) u = units_gt(I);
+        else if (k >= kKindSelT0) u = (k - kKindSelT0) < I.levels && table_select(I) ? units_select(I) : 0;
       }
       pre[b + 1] = pre[b] + u;
     }
@@ -563,11 +564,12 @@ int run_round(ucp_handle* h, const Batch& B, int phase, const std::vector<int32_
   // the levels read the moment table of the current u1, built after the
   // u1 update that produced it (previous round, or the set-up)
   for (int l = 0; l < max_levels; ++l) {
-    const Launch Lm = B.launch(phase, kKindMc0 + l, tab), Ls = B.launch(phase, kKindSel0 + l, tab);
+    const Launch Lm = B.launch(phase, kKindMc0 + l, tab), Ls = B.launch(phase, kKindSel0 + l, tab),
+                 Lt = B.launch(phase, kKindSelT0 + l, tab);
     UCP_TRY(prof_pair(h, UCP_PROF_MC, Lm.total > 0, p), "event");
     UCP_TRY(launch_mc(Lm, l, prec, st, p.a, p.b), "marginal-cost kernel");
-    UCP_TRY(prof_pair(h, UCP_PROF_SELECT, Ls.total > 0, p), "event");
-    UCP_TRY(launch_select(Ls, l, prec, 0, st, p.a, p.b), "selection kernel");
+    UCP_TRY(prof_pair(h, UCP_PROF_SELECT, Ls.total > 0 || Lt.total > 0, p), "event");
+    UCP_TRY(launch_select(Ls, Lt, l, prec, 0, st, p.a, p.b), "selection kernel");
   }
   UCP_TRY(launch_copy_u0(B.launch(phase, kKindCopy, tab), st), "u0 advance kernel");
   const Launch Lp = B.launch(phase, kKindU1p, tab), Lc = B.launch(phase, kKindU1c, tab);
@@ -699,7 +701,9 @@ int ucp_argmin_adaptive(ucp_handle* h, const ucp_problem* prob, const ucp_search
   UCP_TRY(launch_gt_table(B.launch(0, kKindGt, tab), st), "moment table kernel");
   for (int l = 0; l < I.levels; ++l) {
     UCP_TRY(launch_mc(B.launch(0, kKindMc0 + l, tab), l, prec, st), "marginal-cost kernel");
-    UCP_TRY(launch_select(B.launch(0, kKindSel0 + l, tab), l, prec, L0_out != nullptr, st), "selection kernel");
+    UCP_TRY(launch_select(B.launch(0, kKindSel0 + l, tab), B.launch(0, kKindSelT0 + l, tab), l, prec,
+                          L0_out != nullptr, st),
+            "selection kernel");
   }
   UCP_TRY(hipMemcpyAsync(u0_out, I.u0_next, sizeof(double) * I.n_x, hipMemcpyDeviceToDevice, st), "copy u0_out");
   return UCP_OK;

@@ -121,6 +121,12 @@ struct Inst {
   unsigned long long* terms; // counters [kCountSlots][kCountStride] (NULL: not counted)
 };
 
+// Whether the instance's selection takes its FP64 values from the moment
+// table (the FP32 modes on grids that have one).
+__host__ __device__ inline bool table_select(const Inst& I) {
+  return I.gts > 0 && (I.prec == UCP_FP32 || I.prec == UCP_FP32_KAHAN);
+}
+
 // Lanes per point in the selection kernels: two points per wave when the
 // level's set and the incumbent (cands + 2 lanes) fit in half a wave.
 __host__ __device__ inline int sel_width(const Inst& I) { return I.cands + 2 <= 32 ? 32 : 64; }
@@ -146,8 +152,11 @@ hipError_t launch_gt_table(const Launch& L, hipStream_t st);
 // when the last one ends (hipExtLaunchKernel: no extra packets in the stream).
 hipError_t launch_mc(const Launch& L, int level, int prec, hipStream_t st, hipEvent_t e0 = nullptr,
                      hipEvent_t e1 = nullptr);
-hipError_t launch_select(const Launch& L, int level, int prec, int final_l0, hipStream_t st, hipEvent_t e0 = nullptr,
-                         hipEvent_t e1 = nullptr);
+// The selection of one level: Lw over the instances that settle their FP32
+// ties by FP64 window sums, Lt over those that take them from the moment
+// table (table_select).
+hipError_t launch_select(const Launch& Lw, const Launch& Lt, int level, int prec, int final_l0, hipStream_t st,
+                         hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
 hipError_t launch_finish_free(const Launch& L, double* out, int prec, hipStream_t st);
 hipError_t launch_j_reduce_t(const Launch& L, int t, hipStream_t st, hipEvent_t e1 = nullptr);
 hipError_t launch_u1_partial(const Launch& L, int prec, hipStream_t st, hipEvent_t e0 = nullptr);

@@ -1216,9 +1216,12 @@ __device__ __forceinline__ bool pair_band_both(double b0, double b1, double tau)
   return b0 <= lim && b1 <= lim;
 }
 
-template <int W>
+template <int W, bool T>
 __device__ void finish_point(const Inst& I, int i, double res, double Bres, double x, int lane, int want_l0) {
-  if (want_l0 && isnan(Bres)) Bres = I.k2 * res * res + b64_wave<W>(I, x + res, lane);
+  if (want_l0 && isnan(Bres)) {
+    if constexpr (T) Bres = I.k2 * res * res + gt_noise_sum<true>(I, x + res);
+    else Bres = I.k2 * res * res + b64_wave<W>(I, x + res, lane);
+  }
   if (lane == 0) {
     I.u0_next[i] = res;
     if (!isfinite(res)) atomicOr(I.flags, 1);
@@ -1230,11 +1233,11 @@ __device__ void finish_point(const Inst& I, int i, double res, double Bres, doub
 // (B64i its FP64 value where known).  In the band phase (inline_eval =
 // false) a two-member band is queued (returned in Q); in the resolve phase
 // missing FP64 sums are evaluated in place.
-template <int PREC, int W>
+template <int PREC, int W, bool T>
 __device__ void accept(const Inst& I, int i, double x, double uinc, double cw, double B32w, double B64w, double B64i,
                        int lane, bool inline_eval, int want_l0, int& n_eval, Queued& Q) {
   if (cw == uinc) {
-    finish_point<W>(I, i, uinc, B64w, x, lane, want_l0);
+    finish_point<W, T>(I, i, uinc, B64w, x, lane, want_l0);
     return;
   }
   const double B32i = I.b32inc[i];
@@ -1246,18 +1249,18 @@ __device__ void accept(const Inst& I, int i, double x, double uinc, double cw, d
     const bool fin = in2 && isfinite(b32);
     const int w = tie_rule<W>(fin, c2, b32, uinc, lane, I.tau64);
     if (grp_ballot<W>(fin) == 0ull && lane == 0) atomicOr(I.flags, 1);
-    finish_point<W>(I, i, grp_shfl<W>(c2, w), grp_shfl<W>(b64, w), x, lane, want_l0);
+    finish_point<W, T>(I, i, grp_shfl<W>(c2, w), grp_shfl<W>(b64, w), x, lane, want_l0);
     return;
   }
   const unsigned long long mask = band32<W>(in2, b32, I.tau32);
   if (mask == 0ull) {
     if (lane == 0) atomicOr(I.flags, 1);
-    finish_point<W>(I, i, uinc, NAN, x, lane, want_l0);
+    finish_point<W, T>(I, i, uinc, NAN, x, lane, want_l0);
     return;
   }
   if (__popcll(mask) == 1) {
     const int w = __ffsll((long long)mask) - 1;
-    finish_point<W>(I, i, grp_shfl<W>(c2, w), grp_shfl<W>(b64, w), x, lane, want_l0);
+    finish_point<W, T>(I, i, grp_shfl<W>(c2, w), grp_shfl<W>(b64, w), x, lane, want_l0);
     return;
   }
   const unsigned long long todo = grp_ballot<W>(in2 && isnan(b64));
@@ -1267,7 +1270,7 @@ __device__ void accept(const Inst& I, int i, double x, double uinc, double cw, d
     Q.c = c2;
     return;
   }
-  if (I.gt) {  // each lane its own value from the moment table
+  if constexpr (T) {  // each lane its own value from the moment table
     if ((todo >> lane) & 1ull) b64 = I.k2 * c2 * c2 + gt_noise_sum<true>(I, x + c2);
     n_eval += __popcll(todo);
   } else if (todo == 3ull) {  // both: one pass over their windows
@@ -1286,13 +1289,13 @@ __device__ void accept(const Inst& I, int i, double x, double uinc, double cw, d
     ++n_eval;
   }
   const int w = tie_rule<W>(in2, c2, b64, uinc, lane, I.tau64);
-  finish_point<W>(I, i, grp_shfl<W>(c2, w), grp_shfl<W>(b64, w), x, lane, want_l0);
+  finish_point<W, T>(I, i, grp_shfl<W>(c2, w), grp_shfl<W>(b64, w), x, lane, want_l0);
 }
 
 // Band phase for one point: decide it, or return in Q the FP64 sums it
 // needs; the lane's view of the level (c, B32, B64, in_set) is returned for
 // the resolve phase.
-template <int PREC, int W>
+template <int PREC, int W, bool T>
 __device__ void band_point(const Inst& I, int level, int i, int lane, int want_l0, int& n_eval, Queued& Q,
                            double& c, double& B32, double& B64, bool& in_set) {
   const int K = I.cands;
@@ -1345,13 +1348,13 @@ __device__ void band_point(const Inst& I, int level, int i, int lane, int want_l
   }
   if (level == I.levels - 1) {
     const double B64i = inc_from_set<W>(in_set, c, B64, uinc);
-    accept<PREC, W>(I, i, x, uinc, cw, B32w, B64w, B64i, lane, false, want_l0, n_eval, Q);
+    accept<PREC, W, T>(I, i, x, uinc, cw, B32w, B64w, B64i, lane, false, want_l0, n_eval, Q);
   }
 }
 
 // Resolve phase for a point that queued FP64 sums; `qv` is this lane's
 // queued sum (NaN where the lane queued none).
-template <int PREC, int W>
+template <int PREC, int W, bool T>
 __device__ void resolve_point(const Inst& I, int level, int i, int lane, int want_l0, int& n_eval, int kind,
                               double qv, double c, double B32, double B64, bool in_set) {
   const double uinc = I.u0[i];
@@ -1371,7 +1374,7 @@ __device__ void resolve_point(const Inst& I, int level, int i, int lane, int wan
       Queued Q;
       double B64i = inc_from_set<W>(in_set, c, B64, uinc);
       if (kind == 3 && isnan(B64i)) B64i = grp_shfl<W>(qv, I.cands + 1);
-      accept<PREC, W>(I, i, x, uinc, cw, B32w, B64w, B64i, lane, true, want_l0, n_eval, Q);
+      accept<PREC, W, T>(I, i, x, uinc, cw, B32w, B64w, B64i, lane, true, want_l0, n_eval, Q);
     }
   } else {
     // the queued incumbent comparison: lane 0 the winner, lane 1 the incumbent
@@ -1383,7 +1386,7 @@ __device__ void resolve_point(const Inst& I, int level, int i, int lane, int wan
     const unsigned long long mask = band32<W>(in2, b32, I.tau32);
     const bool member = (mask >> lane) & 1ull;
     const int w = tie_rule<W>(member, c2, b64, uinc, lane, I.tau64);
-    finish_point<W>(I, i, grp_shfl<W>(c2, w), grp_shfl<W>(b64, w), x, lane, want_l0);
+    finish_point<W, T>(I, i, grp_shfl<W>(c2, w), grp_shfl<W>(b64, w), x, lane, want_l0);
   }
 }
 
@@ -1406,7 +1409,7 @@ constexpr int kSelCapMax = (UCP_MAX_CANDS + 2 + kEvalChunk - 1) / kEvalChunk * k
 //     b64_multi over the union of a chunk's windows, results to LDS;
 //  3. resolve: the queued points decide on their FP64 values.
 // Every dependency stays in the block, so one launch serves a level.
-template <int PREC, int W>
+template <int PREC, int W, bool T>
 __device__ void select_block(const Inst& I, int local, int level, int want_l0, SelItem* sq, double* sres,
                              int* s_cnt) {
   constexpr int G = kWave / W;
@@ -1422,7 +1425,7 @@ __device__ void select_block(const Inst& I, int local, int level, int want_l0, S
   double c = 0.0, B32 = INFINITY, B64 = NAN;
   bool in_set = false;
   int n_eval = 0;
-  if (have) band_point<PREC, W>(I, level, i, lane, want_l0, n_eval, Q, c, B32, B64, in_set);
+  if (have) band_point<PREC, W, T>(I, level, i, lane, want_l0, n_eval, Q, c, B32, B64, in_set);
   const int nq = __popcll(Q.todo);
   if (lane == 0) s_cnt[grp] = pad_chunk(nq);
   __syncthreads();
@@ -1449,7 +1452,7 @@ __device__ void select_block(const Inst& I, int local, int level, int want_l0, S
   __syncthreads();
   int n_gt = 0;  // values this thread took from the moment table
   if (total) {
-    if (!F64<PREC> && I.gt) {
+    if constexpr (T) {
       // one thread per queued position, its value from the moment table
       for (int e = (int)threadIdx.x; e < total; e += kSelWaves * kWave) {
         const SelItem it = sq[e];
@@ -1487,7 +1490,7 @@ __device__ void select_block(const Inst& I, int local, int level, int want_l0, S
     __syncthreads();
     if (Q.kind) {
       const double qv = (Q.todo >> lane) & 1ull ? sres[base + __popcll(Q.todo & ((1ull << lane) - 1ull))] : NAN;
-      resolve_point<PREC, W>(I, level, i, lane, want_l0, n_eval, Q.kind, qv, c, B32, B64, in_set);
+      resolve_point<PREC, W, T>(I, level, i, lane, want_l0, n_eval, Q.kind, qv, c, B32, B64, in_set);
     }
   }
   // one count per wave: the group leaders' counts (band and resolve, and
@@ -1498,7 +1501,11 @@ __device__ void select_block(const Inst& I, int local, int level, int want_l0, S
   if ((int)threadIdx.x % kWave == 0) count_evals(I, ne);
 }
 
-template <int PREC>
+// T: the instances of this launch take their FP64 values from the moment
+// table (FP32 modes on grids that have one; the window-sum code is then not
+// compiled in, which keeps the kernel's registers, and so its occupancy,
+// those of the band and resolve phases alone).
+template <int PREC, bool T>
 __global__ __launch_bounds__(kSelWaves * kWave) void k_select(Launch L, int level, int want_l0) {
   __shared__ SelItem sq[kSelWaves * 2 * kSelCapMax];
   __shared__ double sres[kSelWaves * 2 * kSelCapMax];
@@ -1506,23 +1513,35 @@ __global__ __launch_bounds__(kSelWaves * kWave) void k_select(Launch L, int leve
   const int u = blockIdx.x;
   const int b = find_inst(L.pre, L.n_inst, u);
   const Inst& I = L.insts[b];
-  if (sel_width(I) == 32) select_block<PREC, 32>(I, u - L.pre[b], level, want_l0, sq, sres, s_cnt);
-  else select_block<PREC, kWave>(I, u - L.pre[b], level, want_l0, sq, sres, s_cnt);
+  if (sel_width(I) == 32) select_block<PREC, 32, T>(I, u - L.pre[b], level, want_l0, sq, sres, s_cnt);
+  else select_block<PREC, kWave, T>(I, u - L.pre[b], level, want_l0, sq, sres, s_cnt);
 }
 
-hipError_t launch_select(const Launch& L, int level, int prec, int want_l0, hipStream_t st, hipEvent_t e0,
-                         hipEvent_t e1) {
-  if (L.total == 0) return hipSuccess;
+static hipError_t launch_select_one(const Launch& L, int level, int prec, int want_l0, bool table, hipStream_t st,
+                                    hipEvent_t e0, hipEvent_t e1) {
   const dim3 blk(kSelWaves * kWave);
   if (prec == UCP_FP64)
-    hipExtLaunchKernelGGL(k_select<UCP_FP64>, dim3(L.total), blk, 0, st, e0, e1, 0, L, level, want_l0);
-  else if (prec == UCP_FP64_GT)
-    hipExtLaunchKernelGGL(k_select<UCP_FP64_GT>, dim3(L.total), blk, 0, st, e0, e1, 0, L, level, want_l0);
+    hipExtLaunchKernelGGL((k_select<UCP_FP64, false>), dim3(L.total), blk, 0, st, e0, e1, 0, L, level, want_l0);
+  else if (prec == UCP_FP64_GT)  // decides on FP64 values directly; its table serves any L_0 left open
+    hipExtLaunchKernelGGL((k_select<UCP_FP64_GT, true>), dim3(L.total), blk, 0, st, e0, e1, 0, L, level, want_l0);
+  else if (prec == UCP_FP32_KAHAN && table)
+    hipExtLaunchKernelGGL((k_select<UCP_FP32_KAHAN, true>), dim3(L.total), blk, 0, st, e0, e1, 0, L, level, want_l0);
   else if (prec == UCP_FP32_KAHAN)
-    hipExtLaunchKernelGGL(k_select<UCP_FP32_KAHAN>, dim3(L.total), blk, 0, st, e0, e1, 0, L, level, want_l0);
+    hipExtLaunchKernelGGL((k_select<UCP_FP32_KAHAN, false>), dim3(L.total), blk, 0, st, e0, e1, 0, L, level, want_l0);
+  else if (table)
+    hipExtLaunchKernelGGL((k_select<UCP_FP32, true>), dim3(L.total), blk, 0, st, e0, e1, 0, L, level, want_l0);
   else
-    hipExtLaunchKernelGGL(k_select<UCP_FP32>, dim3(L.total), blk, 0, st, e0, e1, 0, L, level, want_l0);
+    hipExtLaunchKernelGGL((k_select<UCP_FP32, false>), dim3(L.total), blk, 0, st, e0, e1, 0, L, level, want_l0);
   return hipGetLastError();
+}
+
+hipError_t launch_select(const Launch& Lw, const Launch& Lt, int level, int prec, int want_l0, hipStream_t st,
+                         hipEvent_t e0, hipEvent_t e1) {
+  const bool w = Lw.total > 0, t = Lt.total > 0;
+  hipError_t e = hipSuccess;
+  if (w) e = launch_select_one(Lw, level, prec, want_l0, false, st, e0, t ? nullptr : e1);
+  if (e == hipSuccess && t) e = launch_select_one(Lt, level, prec, want_l0, true, st, w ? nullptr : e0, e1);
+  return e;
 }
 
 // ------------------------------------------------------------ u1 update

@@ -163,7 +163,7 @@ extern "C" int ucp_argmin_adaptive_noalloc(ucp_handle* h, const ucp_problem* pro
   NA_TRY(launch_gt_table(L(kKindGt), st), "moment table kernel");
   for (int l = 0; l < I.levels; ++l) {
     NA_TRY(launch_mc(L(kKindMc0 + l), l, prec, st), "marginal-cost kernel");
-    NA_TRY(launch_select(L(kKindSel0 + l), l, prec, L0_out != nullptr, st), "selection kernel");
+    NA_TRY(launch_select(L(kKindSel0 + l), L(kKindSelT0 + l), l, prec, L0_out != nullptr, st), "selection kernel");
   }
   NA_TRY(hipMemcpyAsync(u0_out, I.u0_next, sizeof(double) * I.n_x, hipMemcpyDeviceToDevice, st), "copy u0_out");
 #undef NA_TRY

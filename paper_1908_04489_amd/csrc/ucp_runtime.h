@@ -21,8 +21,9 @@ enum : int {
   kKindFree,  // marginal-cost kernel on explicit candidates
   kKindFin,   // L_0 = f B for explicit candidates
   kKindGtab,  // offset table of the marginal-cost kernel
-  kKindGt,    // Gauss-transform moment table (UCP_FP64_GT)
-  kKinds
+  kKindGt,    // moment table of the noise sums
+  kKindSelT0,  // selection kernel of instances with table_select, level l at kKindSelT0 + l
+  kKinds = kKindSelT0 + kMaxLevels
 };
 
 extern thread_local std::string g_err;

@@ -364,7 +364,7 @@ extern "C" int ucp_server_step(ucp_server* s, int32_t* n_running) {
     // table built after the request's last u1 update)
     for (int l = 0; l < max_lv; ++l) {
       SRV_TRY(launch_mc(L(1, kKindMc0 + l, 1), l, prec, st), "marginal-cost kernel");
-      SRV_TRY(launch_select(L(1, kKindSel0 + l, 1), l, prec, 0, st), "selection kernel");
+      SRV_TRY(launch_select(L(1, kKindSel0 + l, 1), L(1, kKindSelT0 + l, 1), l, prec, 0, st), "selection kernel");
     }
     SRV_TRY(launch_copy_u0(L(1, kKindCopy, 1), st), "u0 advance kernel");
     SRV_TRY(launch_u1_partial(L(1, kKindU1p, 1), prec, st), "u1 kernel");
