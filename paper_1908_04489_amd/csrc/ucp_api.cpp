@@ -272,6 +272,7 @@ std::vector<int32_t> build_tables(const std::vector<Inst>& insts, const std::vec
         else if (k == kKindFin) u = I.free_cands ? (int32_t)(((int64_t)I.n_x * I.cands + 255) / 256) : 0;
         else if (k == kKindGtab) u = units_gtab(I);
         else if (k == kKindGt) u = units_gt(I);
+        else if (k == kKindU1s) u = units_u1_stats(I);
         else if (k >= kKindSelT0) u = (k - kKindSelT0) < I.levels && table_select(I) ? units_select(I) : 0;
       }
       pre[b + 1] = pre[b] + u;
@@ -574,7 +575,7 @@ int run_round(ucp_handle* h, const Batch& B, int phase, const std::vector<int32_
   UCP_TRY(launch_copy_u0(B.launch(phase, kKindCopy, tab), st), "u0 advance kernel");
   const Launch Lp = B.launch(phase, kKindU1p, tab), Lc = B.launch(phase, kKindU1c, tab);
   UCP_TRY(prof_pair(h, UCP_PROF_U1, Lp.total > 0 && Lc.total > 0, p), "event");
-  UCP_TRY(launch_u1_partial(Lp, prec, st, p.a), "u1 kernel");
+  UCP_TRY(launch_u1_partial(B.launch(phase, kKindU1s, tab), Lp, prec, st, p.a), "u1 kernel");
   UCP_TRY(launch_u1_combine(Lc, st, p.b), "u1 combine kernel");
   UCP_TRY(launch_gt_table(B.launch(phase, kKindGt, tab), st), "moment table kernel");
   const Launch Lr = B.launch(phase, kKindJRows, tab), Ld = B.launch(phase, kKindJRed, tab);
@@ -588,7 +589,7 @@ int run_round(ucp_handle* h, const Batch& B, int phase, const std::vector<int32_
 int run_init(const Batch& B, int phase, const std::vector<int32_t>& tab, int prec, hipStream_t st) {
   UCP_TRY(launch_prior(B.launch(phase, kKindPrior, tab), st), "prior kernel");
   UCP_TRY(launch_gtab(B.launch(phase, kKindGtab, tab), st), "offset table kernel");
-  UCP_TRY(launch_u1_partial(B.launch(phase, kKindU1p, tab), prec, st), "u1 kernel");
+  UCP_TRY(launch_u1_partial(B.launch(phase, kKindU1s, tab), B.launch(phase, kKindU1p, tab), prec, st), "u1 kernel");
   UCP_TRY(launch_u1_combine(B.launch(phase, kKindU1c, tab), st), "u1 combine kernel");
   UCP_TRY(launch_gt_table(B.launch(phase, kKindGt, tab), st), "moment table kernel");
   UCP_TRY(launch_j_rows(B.launch(phase, kKindJRows, tab), st), "objective kernel");
@@ -726,7 +727,7 @@ int ucp_update_u1(ucp_handle* h, const ucp_problem* prob, ucp_prec prec, const d
   UCP_TRY(hipMemsetAsync(I.flags, 0, 128, st), "clear flags");
   UCP_TRY(launch_prior(B.launch(0, kKindPrior, tab), st), "prior kernel");
   UCP_TRY(launch_gtab(B.launch(0, kKindGtab, tab), st), "offset table kernel");
-  UCP_TRY(launch_u1_partial(B.launch(0, kKindU1p, tab), prec, st), "u1 kernel");
+  UCP_TRY(launch_u1_partial(B.launch(0, kKindU1s, tab), B.launch(0, kKindU1p, tab), prec, st), "u1 kernel");
   UCP_TRY(launch_u1_combine(B.launch(0, kKindU1c, tab), st), "u1 combine kernel");
   UCP_TRY(hipMemcpyAsync(u1_out, I.u1, sizeof(double) * I.n_y, hipMemcpyDeviceToDevice, st), "copy u1_out");
   return UCP_OK;
@@ -945,7 +946,7 @@ int ucp_alg1_solve(ucp_handle* h, const ucp_problem* prob, const ucp_alg1_params
     for (int32_t it = 0; it < NL; ++it) {
       UCP_TRY(launch_a1_local_u0(dI, I.n_x, a->tau, I.u0, I.u0_next, st), "local-update kernel");
       UCP_TRY(launch_copy_u0(B.launch(0, kKindCopy, tab), st), "u0 advance kernel");
-      UCP_TRY(launch_u1_partial(B.launch(0, kKindU1p, tab), UCP_FP64, st), "u1 kernel");
+      UCP_TRY(launch_u1_partial(B.launch(0, kKindU1s, tab), B.launch(0, kKindU1p, tab), UCP_FP64, st), "u1 kernel");
       UCP_TRY(launch_u1_combine(B.launch(0, kKindU1c, tab), st), "u1 combine kernel");
     }
     if ((rc = objective(1 + 2 * rounds, &Jc))) return rc;

@@ -159,7 +159,9 @@ hipError_t launch_select(const Launch& Lw, const Launch& Lt, int level, int prec
                          hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
 hipError_t launch_finish_free(const Launch& L, double* out, int prec, hipStream_t st);
 hipError_t launch_j_reduce_t(const Launch& L, int t, hipStream_t st, hipEvent_t e1 = nullptr);
-hipError_t launch_u1_partial(const Launch& L, int prec, hipStream_t st, hipEvent_t e0 = nullptr);
+// the u1 partial sums: Ls the culling-data units (kKindU1s), L the
+// partial-sum units (kKindU1p) of the same instances
+hipError_t launch_u1_partial(const Launch& Ls, const Launch& L, int prec, hipStream_t st, hipEvent_t e0 = nullptr);
 hipError_t launch_u1_combine(const Launch& L, hipStream_t st, hipEvent_t e1 = nullptr);
 hipError_t launch_j_rows(const Launch& L, hipStream_t st, hipEvent_t e0 = nullptr);
 hipError_t launch_j_reduce(const Launch& L, hipStream_t st);
@@ -179,6 +181,7 @@ hipError_t launch_a1_pe_u1(const Inst& I, const Inst* dI, int r, double tie, con
 int32_t units_mc(const Inst& I, int level);
 int32_t units_select(const Inst& I);
 int32_t units_u1_partial(const Inst& I);
+int32_t units_u1_stats(const Inst& I);
 // doubles of the u1 culling data
 size_t u1stat_doubles(const Inst& I);
 int32_t units_u1_combine(const Inst& I);

@@ -1581,8 +1581,9 @@ __host__ __device__ inline int u1_slen(const Inst& I) { return (I.n_x + I.u1_sli
 __host__ __device__ inline int u1_cps(const Inst& I) { return (u1_slen(I) + kU1Chunk - 1) / kU1Chunk; }
 size_t u1stat_doubles(const Inst& I) { return (size_t)u1_tiles(I) + (size_t)I.u1_slices * u1_cps(I) * 3; }
 
-// On the units of k_u1_partial: unit (tile, slice 0) takes its tile's
-// bound, unit (tile 0, slice) the chunks of its slice; the others exit.
+// One unit per tile (its bound) and one per slice (its chunks).
+int32_t units_u1_stats(const Inst& I) { return u1_tiles(I) + I.u1_slices; }
+
 __global__ __launch_bounds__(kU1Block) void k_u1_stats(Launch L) {
   constexpr int NW = kU1Block / kWave;
   __shared__ double sb[3][NW];
@@ -1590,14 +1591,14 @@ __global__ __launch_bounds__(kU1Block) void k_u1_stats(Launch L) {
   const int b = find_inst(L.pre, L.n_inst, u);
   const Inst& I = L.insts[b];
   const int local = u - L.pre[b];
-  const int slice = local % I.u1_slices;
-  const int tile = local / I.u1_slices;
-  if (slice != 0 && tile != 0) return;
+  const int ntiles = u1_tiles(I);
+  const int tile = local < ntiles ? local : -1;
+  const int slice = local < ntiles ? -1 : local - ntiles;
   const int nx = I.n_x;
   const double x_lo = I.x_lo, dx = I.dx;
   const double h2 = 0.5 * I.isw * I.isw;
   const glb_dptr u0g = (glb_dptr)I.u0, lfg = (glb_dptr)I.logf;
-  if (slice == 0) {
+  if (tile >= 0) {
     // A lower bound on the logit maximum M_j of every node of the tile: any x
     // node gives one, M_j >= l_ij >= log f_i - max over the tile's y of
     // (y - x1_i)^2 / (2 s^2); every kU1Sample-th node is taken.
@@ -1611,9 +1612,7 @@ __global__ __launch_bounds__(kU1Block) void k_u1_stats(Launch L) {
     }
     lb = block_max_d(lb, sb[0]);
     if (threadIdx.x == 0) I.u1stat[tile] = lb;
-    __syncthreads();  // sb is reused below
-  }
-  if (tile == 0) {
+  } else {
     const int slen = u1_slen(I);
     const int i0 = slice * slen, i1 = min(nx, i0 + slen);
     double* cs = I.u1stat + u1_tiles(I) + (size_t)slice * u1_cps(I) * 3;
@@ -1805,9 +1804,9 @@ __global__ __launch_bounds__(kU1Block) void k_u1_combine(Launch L) {
   if (!isfinite(u1)) atomicOr(I.flags, 1);
 }
 
-hipError_t launch_u1_partial(const Launch& L, int prec, hipStream_t st, hipEvent_t e0) {
+hipError_t launch_u1_partial(const Launch& Ls, const Launch& L, int prec, hipStream_t st, hipEvent_t e0) {
   if (L.total == 0) return hipSuccess;
-  hipExtLaunchKernelGGL(k_u1_stats, dim3(L.total), dim3(kU1Block), 0, st, e0, nullptr, 0, L);
+  hipExtLaunchKernelGGL(k_u1_stats, dim3(Ls.total), dim3(kU1Block), 0, st, e0, nullptr, 0, Ls);
   if (prec == UCP_FP64 || prec == UCP_FP64_GT)  // the u1 update of UCP_FP64_GT is UCP_FP64's
     hipLaunchKernelGGL(k_u1_partial<UCP_FP64>, dim3(L.total), dim3(kU1Block), 0, st, L);
   else if (prec == UCP_FP32_KAHAN)

@@ -22,6 +22,7 @@ enum : int {
   kKindFin,   // L_0 = f B for explicit candidates
   kKindGtab,  // offset table of the marginal-cost kernel
   kKindGt,    // moment table of the noise sums
+  kKindU1s,   // culling data of the u1 sums (one unit per tile and per slice)
   kKindSelT0,  // selection kernel of instances with table_select, level l at kKindSelT0 + l
   kKinds = kKindSelT0 + kMaxLevels
 };

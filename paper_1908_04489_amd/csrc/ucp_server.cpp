@@ -355,7 +355,7 @@ extern "C" int ucp_server_step(ucp_server* s, int32_t* n_running) {
     // set-up of the new requests
     SRV_TRY(launch_prior(L(0, kKindPrior, 0), st), "prior kernel");
     SRV_TRY(launch_gtab(L(0, kKindGtab, 0), st), "offset table kernel");
-    SRV_TRY(launch_u1_partial(L(0, kKindU1p, 0), prec, st), "u1 kernel");
+    SRV_TRY(launch_u1_partial(L(0, kKindU1s, 0), L(0, kKindU1p, 0), prec, st), "u1 kernel");
     SRV_TRY(launch_u1_combine(L(0, kKindU1c, 0), st), "u1 combine kernel");
     SRV_TRY(launch_gt_table(L(0, kKindGt, 0), st), "moment table kernel");
     SRV_TRY(launch_j_rows(L(0, kKindJRows, 0), st), "objective kernel");
@@ -367,7 +367,7 @@ extern "C" int ucp_server_step(ucp_server* s, int32_t* n_running) {
       SRV_TRY(launch_select(L(1, kKindSel0 + l, 1), L(1, kKindSelT0 + l, 1), l, prec, 0, st), "selection kernel");
     }
     SRV_TRY(launch_copy_u0(L(1, kKindCopy, 1), st), "u0 advance kernel");
-    SRV_TRY(launch_u1_partial(L(1, kKindU1p, 1), prec, st), "u1 kernel");
+    SRV_TRY(launch_u1_partial(L(1, kKindU1s, 1), L(1, kKindU1p, 1), prec, st), "u1 kernel");
     SRV_TRY(launch_u1_combine(L(1, kKindU1c, 1), st), "u1 combine kernel");
     SRV_TRY(launch_gt_table(L(1, kKindGt, 1), st), "moment table kernel");
     SRV_TRY(launch_j_rows(L(1, kKindJRows, 1), st), "objective kernel");
