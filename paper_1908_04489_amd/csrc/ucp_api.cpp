@@ -206,7 +206,7 @@ size_t state_bytes(const Inst& I) {
   b += 9 * align_up(nx * 8);                                      // u0 u0_next f logf cbest b32best b64best b32inc jrow
   b += align_up(ny * 8) + align_up(ny * 4);                       // u1 v
   b += align_up((size_t)(2 * I.nw32 + 1 + kGtabPad) * 4);          // gtab (padded past the window)
-  b += align_up(nx * (size_t)(I.cands + 1) * (size_t)I.segs * 8); // part
+  b += align_up(part_doubles(I) * 8);                             // part
   b += align_up((size_t)I.u1_slices * ny * 3 * 8);                // u1part
   b += align_up(u1stat_doubles(I) * 8);                           // u1stat
   if (I.gts) b += align_up((size_t)I.gtr * 3 * (kGtN + 1) * 8);   // gt
@@ -233,7 +233,7 @@ void carve_state(Inst& I, char*& base) {
   I.u1 = (double*)take(ny * 8);
   I.v = (float*)take(ny * 4);
   I.gtab = (float*)take((size_t)(2 * I.nw32 + 1 + kGtabPad) * 4);
-  I.part = (double*)take(nx * (size_t)(I.cands + 1) * (size_t)I.segs * 8);
+  I.part = (double*)take(part_doubles(I) * 8);
   I.u1part = (double*)take((size_t)I.u1_slices * ny * 3 * 8);
   I.u1stat = (double*)take(u1stat_doubles(I) * 8);
   I.gt = I.gts ? (double*)take((size_t)I.gtr * 3 * (kGtN + 1) * 8) : nullptr;

@@ -110,7 +110,7 @@ struct Inst {
   double* b32best;           // its FP32-path cost B [n_x]
   double* b64best;           // its FP64 cost B, NaN when not evaluated [n_x]
   double* b32inc;            // FP32-path cost B of the incumbent [n_x]
-  double* part;              // marginal-cost partial sums [n_x][cands + 1][segs]
+  double* part;              // marginal-cost partial sums, part_idx(point, slot, segment)
   double* u1part;            // u1 partial sums [u1_slices][n_y][3]
   double* u1stat;            // u1 culling data: per-tile logit bounds, then per-chunk x1 range and max log f
   double* jrow;              // per-point objective terms [n_x]
@@ -120,6 +120,20 @@ struct Inst {
   int32_t* flags;            // bit 0: non-finite value met
   unsigned long long* terms; // counters [kCountSlots][kCountStride] (NULL: not counted)
 };
+
+// Marginal-cost partial sums: tiles of kPartTile consecutive points, each
+// tile laid out [slot][segment][point], so a wave of the marginal-cost
+// kernels (64 consecutive points, one slot and segment) writes whole 64-byte
+// lines and a selection block (8 consecutive points) reads one contiguous
+// span.  n_x is padded to whole tiles.
+constexpr int kPartTile = 8;
+__host__ __device__ inline size_t part_idx(const Inst& I, int i, int q, int g) {
+  return (((size_t)(i / kPartTile) * (size_t)(I.cands + 1) + (size_t)q) * (size_t)I.segs + (size_t)g) * kPartTile +
+         (size_t)(i % kPartTile);
+}
+__host__ __device__ inline size_t part_doubles(const Inst& I) {
+  return (size_t)((I.n_x + kPartTile - 1) / kPartTile) * kPartTile * (size_t)(I.cands + 1) * (size_t)I.segs;
+}
 
 // Whether the instance's selection takes its FP64 values from the moment
 // table (the FP32 modes on grids that have one).

@@ -822,12 +822,9 @@ __global__ __launch_bounds__(kMcBlock) void k_mc32(Launch L, int level) {
       else acc = fmaf(g * e, e, acc);
     }
   }
-  // point-major layout [n_x][cands + 1][segs]: the selection's wave for point
-  // i reads its whole row (a few cache lines).  The row is written by blocks
-  // spread over all XCDs, so each L2 writes back partial lines (about 4x the
-  // array's bytes); the kernel is ALU-bound and this costs no time, while the
-  // point-fastest layout costs the selection kernels more.
-  if (act) I.part[((size_t)i * (I.cands + 1) + q) * S + sidx] = KAHAN ? (double)acc - (double)comp : (double)acc;
+  // tiles of 8 points [slot][segment][point] (part_idx): the wave's 64
+  // consecutive points write 8 whole lines
+  if (act) I.part[part_idx(I, i, q, sidx)] = KAHAN ? (double)acc - (double)comp : (double)acc;
 }
 
 // FP64 marginal cost (precision-study mode): lane = point, window kWin64,
@@ -883,7 +880,7 @@ __global__ __launch_bounds__(kMcBlock) void k_mc64(Launch L, int level) {
   if (!act) return;
   const int jr = nearest_node(I, z);
   const double delta = ((I.y_lo + (double)jr * I.dy) - z) * I.isw;  // in noise sds
-  I.part[(size_t)i * (I.cands + 1) + q] = lane_sum64(I, z, jr, delta);
+  I.part[part_idx(I, i, q, 0)] = lane_sum64(I, z, jr, delta);
 }
 
 // ------------------------------------------- Gauss-transform arithmetic
@@ -1035,7 +1032,7 @@ __global__ __launch_bounds__(kMcBlock) void k_mc_gt(Launch L, int level) {
   const double z = (I.x_lo + (double)(act ? i : I.n_x - 1) * I.dx) + c;
   count_terms(I, z, act, (int)threadIdx.x % kWave);
   if (!act) return;
-  I.part[(size_t)i * (I.cands + 1) + q] = I.k2 * c * c + gt_noise_sum(I, z);
+  I.part[part_idx(I, i, q, 0)] = I.k2 * c * c + gt_noise_sum(I, z);
 }
 
 hipError_t launch_mc(const Launch& L, int level, int prec, hipStream_t st, hipEvent_t e0, hipEvent_t e1) {
@@ -1058,10 +1055,10 @@ __device__ __forceinline__ double b_from_parts(const Inst& I, int i, int q, int 
   const double z = (I.x_lo + (double)i * I.dx) + c;
   const int jr = nearest_node(I, z);
   const double delta = ((I.y_lo + (double)jr * I.dy) - z) * I.isw;  // in noise sds
-  const double* p = I.part + ((size_t)i * (I.cands + 1) + q) * S;  // [point][slot][segment]
+  const double* p = I.part + part_idx(I, i, q, 0);  // segment g at p[g * kPartTile]
   if (prec == UCP_FP64_GT) return p[0];  // B itself
   double s = 0.0;
-  for (int g = 0; g < S; ++g) s += p[g];
+  for (int g = 0; g < S; ++g) s += p[(size_t)g * kPartTile];
   if (prec != UCP_FP64) s = s / I.a2;
   return I.k2 * c * c + I.phi_scale * exp(-0.5 * delta * delta) * s;
 }

@@ -55,7 +55,7 @@ size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
 size_t update_bytes(const Inst& I) {
   const size_t nx = (size_t)I.n_x, ny = (size_t)I.n_y;
   return 7 * align256(nx * 8) + align256(ny * 4) + align256((size_t)(2 * I.nw32 + 1 + kGtabPad) * 4) +
-         align256(nx * (size_t)(I.cands + 1) * (size_t)I.segs * 8) + 256 +
+         align256(part_doubles(I) * 8) + 256 +
          (I.gts ? align256((size_t)I.gtr * 3 * (kGtN + 1) * 8) : 0);
 }
 void carve_update(Inst& I, char* base) {
@@ -74,7 +74,7 @@ void carve_update(Inst& I, char* base) {
   I.b32inc = (double*)take(nx * 8);
   I.v = (float*)take(ny * 4);
   I.gtab = (float*)take((size_t)(2 * I.nw32 + 1 + kGtabPad) * 4);
-  I.part = (double*)take(nx * (size_t)(I.cands + 1) * (size_t)I.segs * 8);
+  I.part = (double*)take(part_doubles(I) * 8);
   I.flags = (int32_t*)take(256);
   I.gt = I.gts ? (double*)take((size_t)I.gtr * 3 * (kGtN + 1) * 8) : nullptr;
   I.u1part = nullptr;
