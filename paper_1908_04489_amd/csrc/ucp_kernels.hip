@@ -114,6 +114,16 @@ __device__ __forceinline__ int nearest_node(const Inst& I, double z) {
   return (int)jf;
 }
 
+// Centre of the FP32 window of z: the nearest node of the grid extended
+// past its ends (a position beyond the grid keeps its own window, clipped
+// to the grid, and one more than nw32 nodes out has none), held within
+// [-nw32 - 1, n_y + nw32]; NaN maps to node 0.
+__device__ __forceinline__ int window_centre32(const Inst& I, double z) {
+  double jf = rint((z - I.y_lo) * I.inv_dy);
+  jf = fmin(fmax(jf, -(double)I.nw32 - 1.0), (double)(I.n_y + I.nw32));
+  return isnan(jf) ? 0 : (int)jf;
+}
+
 // FP64 window sum for one position z, spread over a group of W lanes (a
 // wave, or in the selection kernels possibly an aligned half of one):
 // returns dy/sqrt(2 pi) * sum_j phi(y_j - z) (z - u1_j)^2 over the nodes
@@ -682,7 +692,9 @@ __global__ __launch_bounds__(kMcBlock) void k_mc32(Launch L, int level) {
   const double c = cand_pos(I, level, q, ii);
   const double x = I.x_lo + (double)ii * I.dx;
   const double z = x + c;
-  const int jr = nearest_node(I, z);
+  // the window's centre: past the grid's ends the nearest node of the
+  // extended grid, so the window holds only nodes within nw32 of z
+  const int jr = window_centre32(I, z);
   const double delta = (I.y_lo + (double)jr * I.dy) - z;
   const int nw = I.nw32;
   const int seglen = (2 * nw + 1 + WS - 1) / WS;
@@ -735,7 +747,7 @@ __global__ __launch_bounds__(kMcBlock) void k_mc32(Launch L, int level) {
   if (sidx == 0) {
     count_terms(I, z, act, lane);
     // terms this unit's (point, candidate) evaluates over all its segments
-    long long ev = act ? (long long)(min(nw, I.n_y - 1 - jr) - max(-nw, -jr) + 1) : 0;
+    long long ev = act ? (long long)max(0, min(nw, I.n_y - 1 - jr) - max(-nw, -jr) + 1) : 0;
     for (int o = kWave / 2; o > 0; o >>= 1) ev += __shfl_xor(ev, o);
     if (lane == 0 && ev > 0 && I.terms)
       atomicAdd(I.terms + kCountEvalTerms + (blockIdx.x & (kCountSlots - 1)) * kCountStride, (unsigned long long)ev);
@@ -1053,7 +1065,9 @@ hipError_t launch_mc(const Launch& L, int level, int prec, hipStream_t st, hipEv
 __device__ __forceinline__ double b_from_parts(const Inst& I, int i, int q, int S,
                                                double c, int prec) {
   const double z = (I.x_lo + (double)i * I.dx) + c;
-  const int jr = nearest_node(I, z);
+  // the node the kernel's sums are taken around (FP32: the window centre of
+  // k_mc32, which may lie past the grid's ends; FP64: the nearest grid node)
+  const int jr = prec == UCP_FP64 ? nearest_node(I, z) : window_centre32(I, z);
   const double delta = ((I.y_lo + (double)jr * I.dy) - z) * I.isw;  // in noise sds
   const double* p = I.part + part_idx(I, i, q, 0);  // segment g at p[g * kPartTile]
   if (prec == UCP_FP64_GT) return p[0];  // B itself
