@@ -1524,8 +1524,21 @@ __global__ __launch_bounds__(kSelWaves * kWave) void k_select(Launch L, int leve
   const int u = blockIdx.x;
   const int b = find_inst(L.pre, L.n_inst, u);
   const Inst& I = L.insts[b];
-  if (sel_width(I) == 32) select_block<PREC, 32, T>(I, u - L.pre[b], level, want_l0, sq, sres, s_cnt);
-  else select_block<PREC, kWave, T>(I, u - L.pre[b], level, want_l0, sq, sres, s_cnt);
+  const int local = u - L.pre[b];
+  if (sel_width(I) == 32) {
+    select_block<PREC, 32, T>(I, local, level, want_l0, sq, sres, s_cnt);
+  } else {
+    // 4 points per block, half of a tile of partial sums.  Workgroups go to
+    // the XCDs in turn (workgroup w to XCD w mod 8), so within each 16
+    // blocks the two halves of a tile go to blocks 8 apart: one XCD, one L2.
+    const int units = L.pre[b + 1] - L.pre[b];
+    int lb = local;
+    if (local < units / 16 * 16) {
+      const int r = local % 16;
+      lb = local - r + 2 * (r % 8) + r / 8;
+    }
+    select_block<PREC, kWave, T>(I, lb, level, want_l0, sq, sres, s_cnt);
+  }
 }
 
 static hipError_t launch_select_one(const Launch& L, int level, int prec, int want_l0, bool table, hipStream_t st,
