@@ -1517,7 +1517,7 @@ __device__ void select_block(const Inst& I, int local, int level, int want_l0, S
 // compiled in, which keeps the kernel's registers, and so its occupancy,
 // those of the band and resolve phases alone).
 template <int PREC, bool T>
-__global__ __launch_bounds__(kSelWaves * kWave) void k_select(Launch L, int level, int want_l0) {
+__global__ __launch_bounds__(kSelWaves * kWave, T ? 6 : 2) void k_select(Launch L, int level, int want_l0) {
   __shared__ SelItem sq[kSelWaves * 2 * kSelCapMax];
   __shared__ double sres[kSelWaves * 2 * kSelCapMax];
   __shared__ int s_cnt[kSelWaves * 2];
