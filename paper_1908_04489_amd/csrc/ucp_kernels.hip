@@ -14,12 +14,18 @@
 //   k_mc32<P>      marginal-cost window sums for one level of the search,
 //                  FP32 terms, plain (P=0) or compensated (P=1) sums
 //   k_mc64         the same in FP64 (precision-study mode)
-//   k_select<P>    per point: level minimum, FP32 tie band, FP64
-//                  re-evaluation of the band members (queued and evaluated
-//                  within the block), selection rule, next bracket, and
-//                  after the last level the comparison with the incumbent
-//   k_u1_partial<P>/k_u1_combine   closed-form second controller
+//   k_gt_table     moment table of the noise sum (a Gauss transform of u1,
+//                  Section III-A on the Section V-A cost), after each u1
+//                  update
+//   k_mc_gt        marginal costs from the table (UCP_FP64_GT)
+//   k_select<P,T>  per point: level minimum, FP32 tie band, FP64 values of
+//                  the band members (from the table, T, or FP64 window
+//                  sums; queued and evaluated within the block), selection
+//                  rule, next bracket, and after the last level the
+//                  comparison with the incumbent
+//   k_u1_stats/k_u1_partial<P>/k_u1_combine   closed-form second controller
 //   k_j_rows/k_j_reduce            objective in FP64, fixed-order reduction
+//   k_a1_*         the generic solver's steps (Section III-B to III-D)
 #include <hip/hip_runtime.h>
 #include <hip/hip_ext.h>
 
@@ -1098,11 +1104,12 @@ __global__ __launch_bounds__(256) void k_mc_finish(Launch L, double* out, int pr
 // an aligned half-wave (W = 32, two points per wave).  Lane q of the group
 // holds candidate q of the level (lane `cands` the best so far, or at level
 // 0 the incumbent, whose FP32-path B is kept for the final comparison).
-// FP32 minimum and tie band; a one-member band (and FP64 mode) decides at
-// once, otherwise the members without an FP64 value queue their FP64
-// window sums in the block, which evaluates them and then decides.  On the
-// last level a decided point runs the comparison with the incumbent the
-// same way.  Every cross-lane step of a group (minimum, ballot, shuffle)
+// FP32 minimum and tie band; a one-member band (and the FP64 arithmetics)
+// decides at once, otherwise the members without an FP64 value queue their
+// positions in the block, which evaluates their FP64 values (from the
+// moment table, or FP64 window sums where the instance has none) and then
+// decides.  On the last level a decided point runs the comparison with the
+// incumbent the same way.  Every cross-lane step of a group (minimum, ballot, shuffle)
 // reads lanes of its own group only, and every branch depends on values
 // uniform over the group, so the two groups of a wave may take different
 // paths.  W is a function of the instance alone.
@@ -1200,7 +1207,7 @@ __device__ __forceinline__ void count_evals(const Inst& I, int n) {
     atomicAdd(I.terms + kCountEvals + (blockIdx.x & (kCountSlots - 1)) * kCountStride, (unsigned long long)n);
 }
 
-// Points whose decision needs FP64 window sums queue them in their block:
+// Points whose decision needs FP64 values queue them in their block:
 // kind 1 = the level's band members (lane q), kind 2 = the comparison of
 // the level's winner (lane 0) with the incumbent (lane 1), kind 3 = on the
 // last level, the band members and (lane cands + 1) the incumbent, whose
@@ -1401,7 +1408,7 @@ __device__ void resolve_point(const Inst& I, int level, int i, int lane, int wan
   }
 }
 
-// A queued FP64 window sum of the block: point and position (i < 0 pads).
+// A queued FP64 value of the block: point and position (i < 0 pads).
 struct SelItem {
   int32_t i;
   double c;
@@ -1416,8 +1423,10 @@ constexpr int kSelCapMax = (UCP_MAX_CANDS + 2 + kEvalChunk - 1) / kEvalChunk * k
 //     in the block's queue (a point's entries padded to whole chunks of
 //     kEvalChunk, so the positions that share one pass depend on the point
 //     alone);
-//  2. eval: the block's whole waves take the chunks in turn, one pass of
-//     b64_multi over the union of a chunk's windows, results to LDS;
+//  2. eval: with a moment table (T) one thread per queued position, its
+//     value from the table; else the block's whole waves take the chunks in
+//     turn, one pass of b64_multi over the union of a chunk's windows;
+//     results to LDS;
 //  3. resolve: the queued points decide on their FP64 values.
 // Every dependency stays in the block, so one launch serves a level.
 template <int PREC, int W, bool T>
