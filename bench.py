@@ -64,10 +64,14 @@ SLOTS_PER_TERM = 3.46875
 
 
 def kernel_source_hash():
+    """Hash of the marginal-cost kernel's sources (the kernels and the
+    shared header with their constants and layouts)."""
     import hashlib
 
-    path = os.path.join(ROOT, "paper_1908_04489_amd", "csrc", "ucp_kernels.hip")
-    return hashlib.sha256(open(path, "rb").read()).hexdigest()[:16]
+    h = hashlib.sha256()
+    for name in ("ucp_kernels.hip", "ucp_internal.h"):
+        h.update(open(os.path.join(ROOT, "paper_1908_04489_amd", "csrc", name), "rb").read())
+    return h.hexdigest()[:16]
 
 
 def measured_traffic(workload_name):

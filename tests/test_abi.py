@@ -229,3 +229,25 @@ def test_bench_reads_committed_traffic_only_for_its_kernel_source(tmp_path):
     assert bench.parse_traffic(str(p), "0123456789abcdef") == 49956841.0
     assert bench.parse_traffic(str(p), "fedcba9876543210") is None
     assert bench.parse_traffic(str(tmp_path / "missing.md"), "0123456789abcdef") is None
+
+
+def test_kernel_source_hash_covers_kernels_and_header(tmp_path, monkeypatch):
+    """The traffic figure goes stale when either the kernels or the header
+    holding their tile sizes and layouts changes."""
+    import shutil
+
+    import bench
+
+    src = os.path.join(ROOT, "paper_1908_04489_amd", "csrc")
+    dst = tmp_path / "paper_1908_04489_amd" / "csrc"
+    dst.mkdir(parents=True)
+    for name in ("ucp_kernels.hip", "ucp_internal.h"):
+        shutil.copy(os.path.join(src, name), dst / name)
+    monkeypatch.setattr(bench, "ROOT", str(tmp_path))
+    h0 = bench.kernel_source_hash()
+    for name in ("ucp_kernels.hip", "ucp_internal.h"):
+        with open(dst / name, "a") as f:
+            f.write("\n")
+        h1 = bench.kernel_source_hash()
+        assert h1 != h0, name
+        h0 = h1
