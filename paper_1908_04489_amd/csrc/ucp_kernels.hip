@@ -1530,9 +1530,12 @@ __device__ void select_block(const Inst& I, int local, int level, int want_l0, S
 // T: the instances of this launch take their FP64 values from the moment
 // table (FP32 modes on grids that have one; the window-sum code is then not
 // compiled in, which keeps the kernel's registers, and so its occupancy,
-// those of the band and resolve phases alone).
+// those of the band and resolve phases alone).  The table variant waits on
+// memory most of its cycles and runs at 8 waves per SIMD (64 registers, a
+// few spilled), where more waves hide more of that latency than the spills
+// cost.
 template <int PREC, bool T>
-__global__ __launch_bounds__(kSelWaves * kWave, T ? 6 : 2) void k_select(Launch L, int level, int want_l0) {
+__global__ __launch_bounds__(kSelWaves * kWave, T ? 8 : 2) void k_select(Launch L, int level, int want_l0) {
   __shared__ SelItem sq[kSelWaves * 2 * kSelCapMax];
   __shared__ double sres[kSelWaves * 2 * kSelCapMax];
   __shared__ int s_cnt[kSelWaves * 2];
