@@ -195,6 +195,10 @@ Inst make_inst(const ucp_problem& p, const ucp_search* s, int prec, int cands_ov
   // at most 32 slices (the combine kernel's lane groups take 32)
   const int slen = std::max(512, (I.n_x + 31) / 32);
   I.u1_slices = (I.n_x + slen - 1) / slen;
+  // several y nodes per lane where the grid is large enough to fill the
+  // chip with a quarter of the lanes and fine enough that the weight ratio
+  // between neighbouring nodes stays moderate
+  I.u1_npl = I.n_y >= kU1NplMinNodes && I.dy <= kU1NplMaxStep * I.sw ? kU1Npl : 1;
   return I;
 }
 

@@ -29,10 +29,15 @@ constexpr int kGtabPad = 16;    // offset-table entries past the window (>= the 
 constexpr double kMcRefHalf = 2.5;
 constexpr double kMcBetaMax = 4.0; // blocked sums only where weights change by <= 2^4 per node
 constexpr int kSelWaves = 4;    // selection kernel: waves per block
-constexpr int kU1Block = 256;   // u1 kernels: one lane per y node
+constexpr int kU1Block = 256;   // u1 kernels: lanes per block (one or kU1Npl y nodes each)
 constexpr int kU1Chunk = 512;   // x nodes staged in LDS per step of the u1 sums
 constexpr int kU1Sample = 32;   // x-node stride of the sample bounding a tile's logit maximum
 constexpr double kU1Cull = 64.0; // chunks whose logits all lie this far below that bound are skipped
+// y nodes per lane of the u1 sums on large, fine grids (one exponential
+// per x node and lane, the other nodes' weights by a staged ratio)
+constexpr int kU1Npl = 4;
+constexpr int kU1NplMinNodes = 32768;  // grids of at least this many y nodes
+constexpr double kU1NplMaxStep = 0.05; // and a spacing of at most this many noise sds
 constexpr int kJWaves = 4;      // objective: one wave ...
 constexpr int kJPts = 4;        // ... per kJPts consecutive x nodes
 // FP32 tie band B32 <= m (1 + tau) + kappa sqrt(m): tau covers the relative
@@ -96,6 +101,7 @@ struct Inst {
   int32_t segs;              // marginal-cost units (partial sums) per (tile, candidate)
   int32_t wsegs;             // equal window segments (the last one dispatched split in two when segs > wsegs)
   int32_t u1_slices;         // x slices of the u1 sums
+  int32_t u1_npl;            // consecutive y nodes per lane of the u1 sums (1 or kU1Npl)
   int32_t prec;              // ucp_prec
   int32_t free_cands;        // 1: explicit candidates (u0 holds [n_x][cands]), no search
   // state

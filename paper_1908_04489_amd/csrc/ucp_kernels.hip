@@ -1591,12 +1591,18 @@ hipError_t launch_select(const Launch& Lw, const Launch& Lt, int level, int prec
 // u1_j = y_j - v_j with v_j = sum_i w_ij d_ij / sum_i w_ij, d_ij = y_j - x1_i,
 // w_ij = exp(l_ij - M), l_ij = log f_i - d_ij^2 / 2 (the conditional mean
 // written around the y nodes so the numerator terms stay small).  Unit =
-// (tile of 256 y nodes, slice of x nodes); each slice keeps an online
-// maximum M, and the combine kernel merges the slices in a fixed order.
-// Chunks of x nodes whose weights are negligible for the whole tile are
-// skipped.
+// (tile of y nodes, slice of x nodes), each lane taking u1_npl consecutive
+// nodes of the tile; each slice keeps an online maximum M, and the combine
+// kernel merges the slices in a fixed order.  Chunks of x nodes whose
+// weights are negligible for the whole tile are skipped.
 
-int32_t units_u1_partial(const Inst& I) { return ((I.n_y + kU1Block - 1) / kU1Block) * I.u1_slices; }
+// y nodes per tile: one block of lanes, u1_npl nodes each
+__host__ __device__ inline int u1_tile_nodes(const Inst& I) { return kU1Block * I.u1_npl; }
+__host__ __device__ inline int u1_tiles(const Inst& I) { return (I.n_y + u1_tile_nodes(I) - 1) / u1_tile_nodes(I); }
+__host__ __device__ inline int u1_slen(const Inst& I) { return (I.n_x + I.u1_slices - 1) / I.u1_slices; }
+__host__ __device__ inline int u1_cps(const Inst& I) { return (u1_slen(I) + kU1Chunk - 1) / kU1Chunk; }
+
+int32_t units_u1_partial(const Inst& I) { return u1_tiles(I) * I.u1_slices; }
 // The combine gives each y node a group of kU1Grp lanes, lane g taking the
 // slices g, g + kU1Grp, ... (at most 32 slices), so a block covers
 // kU1Block / kU1Grp nodes.
@@ -1618,9 +1624,6 @@ __device__ __forceinline__ double block_max_d(double v, double* sw) {
 // lower bound lb of its logit maxima, per chunk of a slice the range of its
 // x1 and its largest log f (NaN when the chunk holds a non-finite x1 or
 // log f).  Layout: [tiles] bounds, then [slices][chunks per slice][3].
-__host__ __device__ inline int u1_tiles(const Inst& I) { return (I.n_y + kU1Block - 1) / kU1Block; }
-__host__ __device__ inline int u1_slen(const Inst& I) { return (I.n_x + I.u1_slices - 1) / I.u1_slices; }
-__host__ __device__ inline int u1_cps(const Inst& I) { return (u1_slen(I) + kU1Chunk - 1) / kU1Chunk; }
 size_t u1stat_doubles(const Inst& I) { return (size_t)u1_tiles(I) + (size_t)I.u1_slices * u1_cps(I) * 3; }
 
 // One unit per tile (its bound) and one per slice (its chunks).
@@ -1644,7 +1647,7 @@ __global__ __launch_bounds__(kU1Block) void k_u1_stats(Launch L) {
     // A lower bound on the logit maximum M_j of every node of the tile: any x
     // node gives one, M_j >= l_ij >= log f_i - max over the tile's y of
     // (y - x1_i)^2 / (2 s^2); every kU1Sample-th node is taken.
-    const int j0 = tile * kU1Block, j1 = min(I.n_y, j0 + kU1Block) - 1;
+    const int j0 = tile * u1_tile_nodes(I), j1 = min(I.n_y, j0 + u1_tile_nodes(I)) - 1;
     const double ya = I.y_lo + (double)j0 * I.dy, yb = I.y_lo + (double)j1 * I.dy;
     double lb = -INFINITY;
     for (int i = (int)threadIdx.x * kU1Sample; i < nx; i += kU1Block * kU1Sample) {
@@ -1700,50 +1703,56 @@ __global__ __launch_bounds__(kU1Block) void k_u1_stats(Launch L) {
   }
 }
 
-template <int PREC>
-__global__ __launch_bounds__(kU1Block) void k_u1_partial(Launch L) {
-  __shared__ double sD[kU1Chunk];    // D_i = y_c - x1_i
-  __shared__ double sP[kU1Chunk];    // P_i = log2(e) (log f_i - D_i^2 / (2 s^2)), s the noise sd
-  __shared__ float sDf[kU1Chunk];    // D_i / s^2 in FP32 (maximum pass only)
-  __shared__ float sPf[kU1Chunk];    // log f_i - D_i^2 / (2 s^2) in FP32 (maximum pass only)
-  const int u = blockIdx.x;
-  const int b = find_inst(L.pre, L.n_inst, u);
-  const Inst& I = L.insts[b];
-  const int local = u - L.pre[b];
-  const int slice = local % I.u1_slices;
-  const int tile = local / I.u1_slices;
-  const int j = tile * kU1Block + (int)threadIdx.x;
-  const bool act = j < I.n_y;
-  const double y = I.y_lo + (double)(act ? j : 0) * I.dy;
+// The sums of one unit, NPL consecutive y nodes per lane.  Around the
+// middle node y_c of the tile, y_j - x1_i = eta_j + D_i with eta_j = y_j -
+// y_c and D_i = y_c - x1_i, so the log2 weight (s the noise sd)
+//   log2(e) (log f_i - (y_j - x1_i)^2 / (2 s^2) - M) = P_i + Q_j + E_j D_i,
+// P_i = log2(e) (log f_i - D_i^2 / (2 s^2)) staged per node, Q_j =
+// -log2(e) (M + eta_j^2 / (2 s^2)) and E_j = -log2(e) eta_j / s^2 per lane:
+// one add and one fma in FP64.  The FP64 numerator sums w D_i (one fma);
+// eta_j times the denominator is added once at the end (sum_i w (y_j -
+// x1_i) = sum_i w D_i + eta_j sum_i w).  With NPL > 1 the lane's first node
+// takes its weight as above and node m + 1 the weight of node m times
+// R_i = exp2(-log2(e) dy D_i / s^2), staged per x node (one exponential per
+// x node and lane instead of one per term).  That product differs from
+// node m + 1's weight by the factor exp(-(eta_{m+1}^2 - eta_m^2) / (2 s^2)),
+// which depends on neither i nor the slice: every slice's sums of the node
+// carry it, so it cancels in the combine's ratio and is left out.  M is one
+// shift for the lane's nodes, taken from its second node's logits: the
+// nodes lie within a few dy of each other (dy <= kU1NplMaxStep noise sds),
+// so no weight leaves the FP32 range.
+template <int PREC, int NPL>
+__device__ __forceinline__ void u1_partial_sums(const Inst& I, int tile, int slice, double* sD, double* sP,
+                                                float* sDf, float* sPf, double* sR) {
+  const int tn = kU1Block * NPL;
+  const int jb = tile * tn + (int)threadIdx.x * NPL;  // the lane's first node
+  const bool act = jb < I.n_y;
+  const double y = I.y_lo + (double)(NPL == 1 && !act ? 0 : jb) * I.dy;
   const int slen = u1_slen(I);
   const int i0 = slice * slen, i1 = min(I.n_x, i0 + slen);
   const double log2e = 1.4426950408889634073599246810019;
   // the noise variance s^2 divides every squared distance: h2 = 1 / (2 s^2)
   const double is2 = I.isw * I.isw, h2 = 0.5 * is2;
   const double c2 = h2 * log2e;
-  const int j0 = tile * kU1Block, j1 = min(I.n_y, j0 + kU1Block) - 1;
+  const int j0 = tile * tn, j1 = min(I.n_y, j0 + tn) - 1;
   const double ya = I.y_lo + (double)j0 * I.dy, yb = I.y_lo + (double)j1 * I.dy;
   // the instance is read through a generic pointer, which the LDS stores
   // below could alias: its fields and arrays are taken into registers and
   // global-space pointers once
-  const double x_lo = I.x_lo, dx = I.dx;
+  const double x_lo = I.x_lo, dx = I.dx, dy = I.dy;
   const glb_dptr u0g = (glb_dptr)I.u0, lfg = (glb_dptr)I.logf;
   const double lb = I.u1stat[tile];  // lower bound of the tile's logit maxima (k_u1_stats)
   const double* cstat = I.u1stat + u1_tiles(I) + (size_t)slice * u1_cps(I) * 3;
-  // Around the middle node y_c of the tile, y_j - x1_i = eta_j + D_i with
-  // eta_j = y_j - y_c and D_i = y_c - x1_i, so the log2 weight (s the
-  // noise sd)
-  //   log2(e) (log f_i - (y_j - x1_i)^2 / (2 s^2) - M_j) = P_i + Q_j + E_j D_i,
-  // P_i = log2(e) (log f_i - D_i^2 / (2 s^2)) staged per node, Q_j =
-  // -log2(e) (M_j + eta_j^2 / (2 s^2)) and E_j = -log2(e) eta_j / s^2 per
-  // lane: one add and one fma in FP64.  The FP64 numerator sums w D_i (one fma); eta_j times the
-  // denominator is added once at the end (sum_i w (y_j - x1_i) =
-  // sum_i w D_i + eta_j sum_i w).
   const double yc = I.y_lo + (double)((j0 + j1) / 2) * I.dy;
   const double eta = y - yc;
   const double E = -log2e * eta * is2;
-  const float etaf = (float)eta;
-  double M = -INFINITY, den = 0.0, num = 0.0;
+  const double Es = -log2e * dy * is2;  // log2 of the weight ratio per node and unit D
+  // the node whose logits set the shift
+  const double etaR = NPL > 1 ? eta + dy : eta;
+  const float etaRf = (float)etaR;
+  double M = -INFINITY, den[NPL], num[NPL];
+#pragma unroll
+  for (int m = 0; m < NPL; ++m) den[m] = num[m] = 0.0;
   for (int c0 = i0, k = 0; c0 < i1; c0 += kU1Chunk, ++k) {
     const int cn = min(kU1Chunk, i1 - c0);
     // the chunk's largest possible logit over the tile's nodes:
@@ -1765,34 +1774,72 @@ __global__ __launch_bounds__(kU1Block) void k_u1_partial(Launch L) {
       sP[t] = Pn * log2e;
       sDf[t] = (float)(D * is2);
       sPf[t] = (float)Pn;
+      if (NPL > 1) sR[t] = exp2(Es * D);
     }
     __syncthreads();
     // chunk maximum of the logits, in FP32: only a shift, any value near
     // the maximum works (the sums below use exact FP64 exponents)
     float mcf = -INFINITY;
-    for (int t = 0; t < cn; ++t) mcf = fmaxf(mcf, fmaf(-etaf, sDf[t], sPf[t]));
-    const double mc = (double)mcf - h2 * eta * eta;
+    for (int t = 0; t < cn; ++t) mcf = fmaxf(mcf, fmaf(-etaRf, sDf[t], sPf[t]));
+    const double mc = (double)mcf - h2 * etaR * etaR;
     if (mc > M) {  // rescale what was summed under the old maximum
       const double r = M == -INFINITY ? 0.0 : exp(M - mc);
-      den *= r;
-      num *= r;
+#pragma unroll
+      for (int m = 0; m < NPL; ++m) {
+        den[m] *= r;
+        num[m] *= r;
+      }
       M = mc;
     }
     if (!(M > -INFINITY)) continue;  // every logit is -inf (or NaN): nothing to add
     const double Q = -log2e * M - c2 * eta * eta;
     for (int t = 0; t < cn; ++t) {
-      const double a = fma(E, sD[t], sP[t] + Q);  // log2 of the shifted weight
+      const double D = sD[t];
+      const double a = fma(E, D, sP[t] + Q);  // log2 of the shifted weight
       // FP64 weight in FP64 mode, else the FP32 exp2 of the rounded exponent
-      const double w = PREC == UCP_FP64 ? exp2(a) : (double)__builtin_amdgcn_exp2f((float)a);
-      num = fma(w, sD[t], num);
-      den += w;
+      double w = PREC == UCP_FP64 ? exp2(a) : (double)__builtin_amdgcn_exp2f((float)a);
+      num[0] = fma(w, D, num[0]);
+      den[0] += w;
+      if (NPL > 1) {
+        const double R = sR[t];
+#pragma unroll
+        for (int m = 1; m < NPL; ++m) {
+          w *= R;
+          num[m] = fma(w, D, num[m]);
+          den[m] += w;
+        }
+      }
     }
   }
-  if (!act) return;
-  double* o = I.u1part + ((size_t)slice * I.n_y + j) * 3;
-  o[0] = M;
-  o[1] = num + eta * den;
-  o[2] = den;
+#pragma unroll
+  for (int m = 0; m < NPL; ++m) {
+    const int j = jb + m;
+    if (j >= I.n_y) break;
+    const double em = NPL == 1 ? eta : (I.y_lo + (double)j * dy) - yc;
+    double* o = I.u1part + ((size_t)slice * I.n_y + j) * 3;
+    o[0] = M;
+    o[1] = num[m] + em * den[m];
+    o[2] = den[m];
+  }
+}
+
+template <int PREC>
+__global__ __launch_bounds__(kU1Block, 5) void k_u1_partial(Launch L) {
+  __shared__ double sD[kU1Chunk];    // D_i = y_c - x1_i
+  __shared__ double sP[kU1Chunk];    // P_i = log2(e) (log f_i - D_i^2 / (2 s^2)), s the noise sd
+  __shared__ float sDf[kU1Chunk];    // D_i / s^2 in FP32 (maximum pass only)
+  __shared__ float sPf[kU1Chunk];    // log f_i - D_i^2 / (2 s^2) in FP32 (maximum pass only)
+  __shared__ double sR[kU1Chunk];    // R_i = exp2(-log2(e) dy D_i / s^2) (several nodes per lane only)
+  const int u = blockIdx.x;
+  const int b = find_inst(L.pre, L.n_inst, u);
+  const Inst& I = L.insts[b];
+  const int local = u - L.pre[b];
+  const int slice = local % I.u1_slices;
+  const int tile = local / I.u1_slices;
+  if (I.u1_npl == kU1Npl)
+    u1_partial_sums<PREC, kU1Npl>(I, tile, slice, sD, sP, sDf, sPf, sR);
+  else
+    u1_partial_sums<PREC, 1>(I, tile, slice, sD, sP, sDf, sPf, sR);
 }
 
 __global__ __launch_bounds__(kU1Block) void k_u1_combine(Launch L) {

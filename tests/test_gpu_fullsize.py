@@ -79,6 +79,13 @@ def test_large_mixture_batch_sampled(env):
         # sampled rows would not give the GPU's input exactly, so take the GPU u1 of the
         # initial state and check the u0 update against the oracle given it
         u1_0 = U.update_u1(p, torch.as_tensor(c.u0_init).cuda(), "fp32_kahan")
+        # u1 at full size (four y nodes per lane) on sampled rows, in the
+        # FP32 modes' arithmetic and in FP64
+        yr = np.sort(np.concatenate([rng.choice(p.n_y, 128, replace=False), [0, p.n_y // 2, p.n_y - 1]]))
+        ref1 = orc.update_u1(p, c.u0_init, rows=yr)
+        assert np.max(np.abs(u1_0.cpu().numpy()[yr] - ref1)) <= 2e-5
+        u1_64 = U.update_u1(p, torch.as_tensor(c.u0_init).cuda(), "fp64").cpu().numpy()
+        assert np.max(np.abs(u1_64[yr] - ref1)) <= 1e-11
         got = U.argmin_adaptive(p, s, u1_0, torch.as_tensor(c.u0_init).cuda(), "fp32_kahan").cpu().numpy()
         assert np.array_equal(got, u0s[b].cpu().numpy())  # the same update as inside the batched solve
         rows = np.sort(rng.choice(p.n_x, 48, replace=False))

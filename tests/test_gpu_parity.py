@@ -128,6 +128,41 @@ def test_update_u1(env, name, prec, tol):
     assert np.all(np.isfinite(got))
 
 
+# Grids of at least 32768 y nodes spaced at most 0.05 noise sds take four
+# consecutive y nodes per lane in the u1 sums (one exponential per x node
+# and lane, the other nodes by a staged ratio).  Narrow x grids keep the
+# oracle quick; 33001 nodes end on a ragged tile whose last lane holds one
+# node; 32767 nodes stay at one node per lane.
+NPL_CASES = {
+    "mix-33001": lambda: W.Problem(0.2, [(0.5, -6.0, 2.0), (0.3, 3.0, 1.5), (0.2, 9.0, 3.0)], -20, 22, 2001,
+                                   -40, 40, 33001),
+    "gauss-32768": lambda: W.Problem(0.2, [(1.0, 0.0, 5.0)], -25, 25, 1501, -40, 40, 32768),
+    "noise0.7-40001": lambda: _with_noise(W.Problem(0.25, [(1.0, 0.0, 4.0)], -25, 25, 1201, -30, 30, 40001), 0.7),
+    "one-per-lane-32767": lambda: W.Problem(0.2, [(1.0, 0.0, 5.0)], -25, 25, 1501, -40, 40, 32767),
+}
+
+
+def _with_noise(p, sw):
+    p.noise_sd = sw
+    return p
+
+
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-11), ("fp32_kahan", 2e-5), ("fp32", 2e-5)])
+@pytest.mark.parametrize("name", list(NPL_CASES))
+def test_update_u1_nodes_per_lane(env, name, prec, tol):
+    U, orc, torch = env
+    p = NPL_CASES[name]()
+    u0 = W.init_random_steps(p, 5.0, 17)
+    ref = orc.update_u1(p, u0)
+    got = host(U.update_u1(p, dev(torch, u0), prec))
+    m = py_mask(orc, p, u0, ref)
+    err = np.max(np.abs(got[m] - ref[m]))
+    assert err <= tol, err
+    assert np.all(np.isfinite(got))
+    # the ragged tile's last nodes and the grid's ends
+    assert np.all(np.abs(got[-5:] - ref[-5:])[m[-5:]] <= tol) and np.all(np.abs(got[:5] - ref[:5])[m[:5]] <= tol)
+
+
 # -------------------------------------------------------- marginal cost
 
 @pytest.mark.parametrize("prec,tol", [("fp64", 1e-12), ("fp32_kahan", 2e-5), ("fp32", 2e-5)])
