@@ -210,7 +210,7 @@ int ucp_argmin_adaptive_noalloc(ucp_handle* h, const ucp_problem* prob, const uc
  * C_1 (the closed form the paper credits to the earlier solver, Section
  * IV-B).  Weights are max-shifted per y_j.  The logits are FP64; in the FP32
  * modes each weight is the FP32 exponential of its FP64 logit, in FP64 mode
- * the FP64 one.  On grids of at least 32768 y nodes spaced at most 0.05
+ * the FP64 one.  On grids of at least 16384 y nodes spaced at most 0.05
  * noise sds, three of every four consecutive nodes take their weights as
  * the previous node's times an FP64 ratio per x node, exp2(-log2(e) dy
  * (y_c - x1_i) / s^2) (a common factor per node cancels in the ratio), so

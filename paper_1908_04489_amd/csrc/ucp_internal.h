@@ -36,7 +36,7 @@ constexpr double kU1Cull = 64.0; // chunks whose logits all lie this far below t
 // y nodes per lane of the u1 sums on large, fine grids (one exponential
 // per x node and lane, the other nodes' weights by a staged ratio)
 constexpr int kU1Npl = 4;
-constexpr int kU1NplMinNodes = 32768;  // grids of at least this many y nodes
+constexpr int kU1NplMinNodes = 16384;  // grids of at least this many y nodes
 constexpr double kU1NplMaxStep = 0.05; // and a spacing of at most this many noise sds
 constexpr int kJWaves = 4;      // objective: one wave ...
 constexpr int kJPts = 4;        // ... per kJPts consecutive x nodes

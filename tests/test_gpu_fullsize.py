@@ -60,7 +60,7 @@ def test_paper_resolution_sampled(env):
     rows = np.sort(rng.choice(p.n_x, 192, replace=False))
     rows = np.concatenate([rows, [0, 1, p.n_x // 2, p.n_x - 2, p.n_x - 1]])  # edges and the x = 0 node
     assert _check_rows(orc, p, s, u1, u0, got, rows) <= 1
-    # u1 of the updated u0, sampled rows
+    # u1 of the updated u0 (four y nodes per lane), sampled rows
     u1n = U.update_u1(p, torch.as_tensor(got).cuda(), "fp32_kahan").cpu().numpy()
     yr = np.sort(rng.choice(p.n_y, 256, replace=False))
     ref = orc.update_u1(p, got, rows=yr)

@@ -128,17 +128,17 @@ def test_update_u1(env, name, prec, tol):
     assert np.all(np.isfinite(got))
 
 
-# Grids of at least 32768 y nodes spaced at most 0.05 noise sds take four
+# Grids of at least 16384 y nodes spaced at most 0.05 noise sds take four
 # consecutive y nodes per lane in the u1 sums (one exponential per x node
 # and lane, the other nodes by a staged ratio).  Narrow x grids keep the
 # oracle quick; 33001 nodes end on a ragged tile whose last lane holds one
-# node; 32767 nodes stay at one node per lane.
+# node; 16384 nodes sit on the threshold, 16383 stay at one node per lane.
 NPL_CASES = {
     "mix-33001": lambda: W.Problem(0.2, [(0.5, -6.0, 2.0), (0.3, 3.0, 1.5), (0.2, 9.0, 3.0)], -20, 22, 2001,
                                    -40, 40, 33001),
-    "gauss-32768": lambda: W.Problem(0.2, [(1.0, 0.0, 5.0)], -25, 25, 1501, -40, 40, 32768),
+    "gauss-16384": lambda: W.Problem(0.2, [(1.0, 0.0, 5.0)], -25, 25, 1501, -40, 40, 16384),
     "noise0.7-40001": lambda: _with_noise(W.Problem(0.25, [(1.0, 0.0, 4.0)], -25, 25, 1201, -30, 30, 40001), 0.7),
-    "one-per-lane-32767": lambda: W.Problem(0.2, [(1.0, 0.0, 5.0)], -25, 25, 1501, -40, 40, 32767),
+    "one-per-lane-16383": lambda: W.Problem(0.2, [(1.0, 0.0, 5.0)], -25, 25, 1501, -40, 40, 16383),
 }
 
 
