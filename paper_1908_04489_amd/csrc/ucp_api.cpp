@@ -590,14 +590,19 @@ int run_round(ucp_handle* h, const Batch& B, int phase, const std::vector<int32_
 }
 
 // u1 and J[0] from the initial u0 (after the prior).
-int run_init(const Batch& B, int phase, const std::vector<int32_t>& tab, int prec, hipStream_t st) {
+int run_init(ucp_handle* h, const Batch& B, int phase, const std::vector<int32_t>& tab, int prec, hipStream_t st) {
+  EvPair p;
   UCP_TRY(launch_prior(B.launch(phase, kKindPrior, tab), st), "prior kernel");
   UCP_TRY(launch_gtab(B.launch(phase, kKindGtab, tab), st), "offset table kernel");
-  UCP_TRY(launch_u1_partial(B.launch(phase, kKindU1s, tab), B.launch(phase, kKindU1p, tab), prec, st), "u1 kernel");
-  UCP_TRY(launch_u1_combine(B.launch(phase, kKindU1c, tab), st), "u1 combine kernel");
+  const Launch Lp = B.launch(phase, kKindU1p, tab), Lc = B.launch(phase, kKindU1c, tab);
+  UCP_TRY(prof_pair(h, UCP_PROF_U1, Lp.total > 0 && Lc.total > 0, p), "event");
+  UCP_TRY(launch_u1_partial(B.launch(phase, kKindU1s, tab), Lp, prec, st, p.a), "u1 kernel");
+  UCP_TRY(launch_u1_combine(Lc, st, p.b), "u1 combine kernel");
   UCP_TRY(launch_gt_table(B.launch(phase, kKindGt, tab), st), "moment table kernel");
-  UCP_TRY(launch_j_rows(B.launch(phase, kKindJRows, tab), st), "objective kernel");
-  UCP_TRY(launch_j_reduce_t(B.launch(phase, kKindJRed, tab), 0, st), "objective reduce kernel");
+  const Launch Lr = B.launch(phase, kKindJRows, tab), Ld = B.launch(phase, kKindJRed, tab);
+  UCP_TRY(prof_pair(h, UCP_PROF_J, Lr.total > 0 && Ld.total > 0, p), "event");
+  UCP_TRY(launch_j_rows(Lr, st, p.a), "objective kernel");
+  UCP_TRY(launch_j_reduce_t(Ld, 0, st, p.b), "objective reduce kernel");
   return UCP_OK;
 }
 
@@ -645,7 +650,7 @@ int ucp_solve_batch(ucp_handle* h, int32_t nb, const ucp_problem* probs, const u
     UCP_TRY(hipMemcpyAsync(I.u0, u0_init[b], sizeof(double) * I.n_x, hipMemcpyDeviceToDevice, st), "copy u0_init");
     UCP_TRY(clear_state(I, st), "clear state");
   }
-  if ((rc = run_init(B, 0, tab, prec, st))) return rc;
+  if ((rc = run_init(h, B, 0, tab, prec, st))) return rc;
   for (int t = 1; t <= max_it; ++t)
     if ((rc = run_round(h, B, t, tab, prec, max_lv, t, st))) return rc;
   std::vector<int32_t> flags(nb, 0);
