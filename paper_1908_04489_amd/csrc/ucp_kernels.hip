@@ -2163,65 +2163,66 @@ __global__ __launch_bounds__(256) void k_a1_pe_u0(const Inst* __restrict__ Ip, d
   }
 }
 
-// Partial exhaustion of u1, first pass: as k_u1_partial<UCP_FP64> (lane =
-// y node, x nodes of one slice staged in LDS, FP64 weights max-shifted,
-// negligible chunks skipped), accumulating for each of the R candidate
-// values c_m = u1_in[j - r + m] the sum of w (x1 - c_m)^2.  Writes
-// [slice][n_y][1 + R]: the slice's maximum and the R sums.
-template <int R>
-__global__ __launch_bounds__(kU1Block) void k_a1_pe_u1_partial(const Inst* __restrict__ Ip,
-                                                               const double* __restrict__ u1_in,
-                                                               double* __restrict__ part) {
+// Partial exhaustion of u1, first pass: as k_u1_partial<UCP_FP64> (x nodes
+// of one slice staged in LDS, FP64 weights max-shifted, negligible chunks
+// skipped, one or u1_npl consecutive y nodes per lane, the weights of a
+// lane's later nodes by the staged ratio R_i), accumulating for each node j
+// the weighted moments T_a = sum_i w (x1_i - u1_in[j])^a, a = 0, 1, 2.  The
+// candidates' sums follow from them: for c_m = u1_in[j] + delta_m,
+// sum_i w (x1_i - c_m)^2 = T_2 - 2 delta_m T_1 + delta_m^2 T_0.  The ratio
+// leaves out a factor common to the node's slices and candidates, which
+// the selection rule (relative to the minimum) does not see.  Writes
+// [slice][n_y][2 r + 2]: the slice's maximum and T_0, T_1, T_2.
+template <int NPL>
+__device__ __forceinline__ void a1_u1_moments(const Inst& I, int tile, int slice, const double* __restrict__ u1_in,
+                                              double* __restrict__ part, int stride, double* sD, double* sP,
+                                              double* sR, double* sb) {
   constexpr int NW = kU1Block / kWave;
-  constexpr int r = R / 2;
-  __shared__ double sX[kU1Chunk];  // x1_i
-  __shared__ double sL[kU1Chunk];  // log f_i
-  __shared__ double sb[4][NW];
-  const Inst& I = *Ip;
-  const int u = blockIdx.x;
-  const int slice = u % I.u1_slices;
-  const int tile = u / I.u1_slices;
-  const int j = tile * kU1Block + (int)threadIdx.x;
-  const bool act = j < I.n_y;
-  const int jj = act ? j : I.n_y - 1;
-  const double y = I.y_lo + (double)jj * I.dy;
+  const int tn = kU1Block * NPL;
+  const int jb = tile * tn + (int)threadIdx.x * NPL;  // the lane's first node
   const int slen = (I.n_x + I.u1_slices - 1) / I.u1_slices;
   const int i0 = slice * slen, i1 = min(I.n_x, i0 + slen);
-  const double h2 = 0.5 * I.isw * I.isw;
+  const double log2e = 1.4426950408889634073599246810019;
+  const double is2 = I.isw * I.isw, h2 = 0.5 * is2, c2 = h2 * log2e;
   const int nx = I.n_x;
-  const double x_lo = I.x_lo, dx = I.dx;
+  const double x_lo = I.x_lo, dx = I.dx, dy = I.dy;
   const glb_dptr u0g = (glb_dptr)I.u0, lfg = (glb_dptr)I.logf;
-  double c[R];
+  double cref[NPL];  // each node's own u1 value, the moments' origin
 #pragma unroll
-  for (int m = 0; m < R; ++m) {
-    const int k = jj - r + m;
-    c[m] = (k >= 0 && k < I.n_y) ? u1_in[k] : u1_in[jj];
-  }
+  for (int m = 0; m < NPL; ++m) cref[m] = u1_in[min(jb + m, I.n_y - 1)];
   // a lower bound on the logit maximum of every node of the tile (as in
-  // k_u1_partial): chunks whose logits all lie kU1Cull below it are skipped
-  const int j0 = tile * kU1Block, j1 = min(I.n_y, j0 + kU1Block) - 1;
-  const double ya = I.y_lo + (double)j0 * I.dy, yb = I.y_lo + (double)j1 * I.dy;
+  // k_u1_stats): chunks whose logits all lie kU1Cull below it are skipped
+  const int j0 = tile * tn, j1 = min(I.n_y, j0 + tn) - 1;
+  const double ya = I.y_lo + (double)j0 * dy, yb = I.y_lo + (double)j1 * dy;
   double lb = -INFINITY;
   for (int i = (int)threadIdx.x * kU1Sample; i < nx; i += kU1Block * kU1Sample) {
     const double x1 = (x_lo + (double)i * dx) + u0g[i];
     const double da = ya - x1, db = yb - x1;
     lb = fmax(lb, lfg[i] - h2 * fmax(da * da, db * db));
   }
-  lb = block_max_d(lb, sb[0]);
-  double M = -INFINITY, acc[R];
+  lb = block_max_d(lb, sb);
+  // logits around the tile's middle node y_c as in k_u1_partial
+  const double yc = I.y_lo + (double)((j0 + j1) / 2) * dy;
+  const double eta = (I.y_lo + (double)(NPL == 1 ? min(jb, I.n_y - 1) : jb) * dy) - yc;
+  const double E = -log2e * eta * is2;
+  const double Es = -log2e * dy * is2;
+  const double etaR = NPL > 1 ? eta + dy : eta;  // the node whose logits set the shift
+  double M = -INFINITY, T0[NPL], T1[NPL], T2[NPL];
 #pragma unroll
-  for (int m = 0; m < R; ++m) acc[m] = 0.0;
+  for (int m = 0; m < NPL; ++m) T0[m] = T1[m] = T2[m] = 0.0;
   for (int c0 = i0; c0 < i1; c0 += kU1Chunk) {
     const int cn = min(kU1Chunk, i1 - c0);
-    __syncthreads();
+    __syncthreads();  // the previous chunk's readers are done
     double xmn = INFINITY, xmx = -INFINITY, fmx = -INFINITY;
     bool bad = false;
     for (int t = threadIdx.x; t < cn; t += kU1Block) {
       const int i = c0 + t;
       const double x1 = (x_lo + (double)i * dx) + u0g[i];
       const double lf = lfg[i];
-      sX[t] = x1;
-      sL[t] = lf;
+      const double D = yc - x1;
+      sD[t] = D;
+      sP[t] = (lf - h2 * D * D) * log2e;
+      if (NPL > 1) sR[t] = exp2(Es * D);
       xmn = fmin(xmn, x1);
       xmx = fmax(xmx, x1);
       fmx = fmax(fmx, lf);
@@ -2234,51 +2235,84 @@ __global__ __launch_bounds__(kU1Block) void k_a1_pe_u1_partial(const Inst* __res
     }
     const bool wbad = __ballot(bad) != 0ull;
     if (threadIdx.x % kWave == 0) {
-      sb[1][threadIdx.x / kWave] = xmn;
-      sb[2][threadIdx.x / kWave] = xmx;
-      sb[3][threadIdx.x / kWave] = wbad ? NAN : fmx;
+      sb[NW + threadIdx.x / kWave] = xmn;
+      sb[2 * NW + threadIdx.x / kWave] = xmx;
+      sb[3 * NW + threadIdx.x / kWave] = wbad ? NAN : fmx;
     }
     __syncthreads();
     for (int w = 0; w < NW; ++w) {
-      xmn = fmin(xmn, sb[1][w]);
-      xmx = fmax(xmx, sb[2][w]);
-      fmx = fmax(fmx, sb[3][w]);
-      bad |= isnan(sb[3][w]);
+      xmn = fmin(xmn, sb[NW + w]);
+      xmx = fmax(xmx, sb[2 * NW + w]);
+      fmx = fmax(fmx, sb[3 * NW + w]);
+      bad |= isnan(sb[3 * NW + w]);
     }
     const double dist = fmax(0.0, fmax(xmn - yb, ya - xmx));
     if (!bad && fmx - h2 * dist * dist < lb - kU1Cull) continue;
+    // the chunk's largest logit of the shift node (in log2 units)
+    const double ER = -log2e * etaR * is2;
     double mc = -INFINITY;
-    for (int t = 0; t < cn; ++t) {
-      const double d = y - sX[t];
-      mc = fmax(mc, sL[t] - h2 * d * d);
-    }
+    for (int t = 0; t < cn; ++t) mc = fmax(mc, fma(ER, sD[t], sP[t]));
+    mc = mc / log2e - h2 * etaR * etaR;
     if (mc > M) {
       const double sc = M == -INFINITY ? 0.0 : exp(M - mc);
 #pragma unroll
-      for (int m = 0; m < R; ++m) acc[m] *= sc;
+      for (int m = 0; m < NPL; ++m) {
+        T0[m] *= sc;
+        T1[m] *= sc;
+        T2[m] *= sc;
+      }
       M = mc;
     }
     if (!(M > -INFINITY)) continue;
+    const double Q = -log2e * M - c2 * eta * eta;
     for (int t = 0; t < cn; ++t) {
-      const double d = y - sX[t];
-      const double w = exp(sL[t] - h2 * d * d - M);
+      const double D = sD[t];
+      double w = exp2(fma(E, D, sP[t] + Q));
+      const double x1 = yc - D;
 #pragma unroll
-      for (int m = 0; m < R; ++m) {
-        const double e = sX[t] - c[m];
-        acc[m] = fma(w * e, e, acc[m]);
+      for (int m = 0; m < NPL; ++m) {
+        if (m) w *= sR[t];
+        const double e = x1 - cref[m];
+        const double we = w * e;
+        T0[m] += w;
+        T1[m] += we;
+        T2[m] = fma(we, e, T2[m]);
       }
     }
   }
-  if (!act) return;
-  double* o = part + ((size_t)slice * I.n_y + j) * (R + 1);
-  o[0] = M;
 #pragma unroll
-  for (int m = 0; m < R; ++m) o[1 + m] = acc[m];
+  for (int m = 0; m < NPL; ++m) {
+    const int j = jb + m;
+    if (j >= I.n_y) break;
+    double* o = part + ((size_t)slice * I.n_y + j) * stride;
+    o[0] = M;
+    o[1] = T0[m];
+    o[2] = T1[m];
+    o[3] = T2[m];
+  }
 }
 
-// Second pass: merge the slices at the common maximum (in slice order) and
-// apply the selection rule among the R candidates, the node's own value the
-// incumbent.
+template <int R>
+__global__ __launch_bounds__(kU1Block, 4) void k_a1_pe_u1_partial(const Inst* __restrict__ Ip,
+                                                                  const double* __restrict__ u1_in,
+                                                                  double* __restrict__ part) {
+  __shared__ double sD[kU1Chunk];  // D_i = y_c - x1_i
+  __shared__ double sP[kU1Chunk];  // log2(e) (log f_i - D_i^2 / (2 s^2))
+  __shared__ double sR[kU1Chunk];  // exp2(-log2(e) dy D_i / s^2) (several nodes per lane only)
+  __shared__ double sb[4 * (kU1Block / kWave)];
+  const Inst& I = *Ip;
+  const int u = blockIdx.x;
+  const int slice = u % I.u1_slices;
+  const int tile = u / I.u1_slices;
+  if (I.u1_npl == kU1Npl)
+    a1_u1_moments<kU1Npl>(I, tile, slice, u1_in, part, R + 1, sD, sP, sR, sb);
+  else
+    a1_u1_moments<1>(I, tile, slice, u1_in, part, R + 1, sD, sP, sR, sb);
+}
+
+// Second pass: merge the slices' moments at the common maximum (in slice
+// order), form each candidate's sum from them and apply the selection rule
+// among the R candidates, the node's own value the incumbent.
 template <int R>
 __global__ __launch_bounds__(256) void k_a1_pe_u1_select(const Inst* __restrict__ Ip, double tie,
                                                          const double* __restrict__ u1_in,
@@ -2289,21 +2323,23 @@ __global__ __launch_bounds__(256) void k_a1_pe_u1_select(const Inst* __restrict_
   if (j >= I.n_y) return;
   double M = -INFINITY;
   for (int s = 0; s < I.u1_slices; ++s) M = fmax(M, part[((size_t)s * I.n_y + j) * (R + 1)]);
-  double C[R], c[R];
-#pragma unroll
-  for (int m = 0; m < R; ++m) C[m] = 0.0;
+  double T0 = 0.0, T1 = 0.0, T2 = 0.0;
   for (int s = 0; s < I.u1_slices; ++s) {
     const double* p = part + ((size_t)s * I.n_y + j) * (R + 1);
     if (!(p[0] > -INFINITY)) continue;
     const double sc = exp(p[0] - M);
-#pragma unroll
-    for (int m = 0; m < R; ++m) C[m] += p[1 + m] * sc;
+    T0 += p[1] * sc;
+    T1 += p[2] * sc;
+    T2 += p[3] * sc;
   }
   const double inc = u1_in[j];
+  double C[R], c[R];
 #pragma unroll
   for (int m = 0; m < R; ++m) {
     const int k = j - r + m;
     c[m] = (k >= 0 && k < I.n_y) ? u1_in[k] : inc;
+    const double d = c[m] - inc;
+    C[m] = fma(d, fma(d, T0, -2.0 * T1), T2);
   }
   const double res = c[pick_serial(R, c, C, inc, tie)];
   u1_out[j] = res;
@@ -2329,7 +2365,7 @@ hipError_t launch_a1_pe_u0(const Inst* dI, int n_x, int r, double tie, const dou
 
 hipError_t launch_a1_pe_u1(const Inst& I, const Inst* dI, int r, double tie, const double* u1_in, double* part,
                            double* u1_out, hipStream_t st) {
-  const int units = ((I.n_y + kU1Block - 1) / kU1Block) * I.u1_slices;
+  const int units = u1_tiles(I) * I.u1_slices;
   const int blocks = (I.n_y + 255) / 256;
   if (r == 1) {
     hipLaunchKernelGGL(k_a1_pe_u1_partial<3>, dim3(units), dim3(kU1Block), 0, st, dI, u1_in, part);

@@ -1,5 +1,6 @@
 """The u1 sums with several consecutive y nodes per lane, modelled in numpy
-from their statement and checked against the oracle's u1 on the CPU.
+from their statement and checked against the oracle's u1 on the CPU; and
+the generic solver's u1 partial exhaustion sums formed from moments.
 
 Around the middle node y_c of a tile (eta_j = y_j - y_c, D_i = y_c - x1_i,
 s the noise sd), the shifted log2 weight of x node i at y node j is
@@ -75,3 +76,28 @@ def test_nodes_per_lane_matches_oracle(orc, n_x, n_y, sw):
     m = py >= 1e-9 * py.max()
     assert np.max(np.abs(got[m] - ref[m])) <= 1e-11
     assert spread > 1e-6  # the left-out factor is real, and cancels
+
+
+def test_partial_exhaustion_sums_from_moments(orc):
+    """The u1 partial exhaustion of the generic solver forms each
+    candidate's sum sum_i w (x1_i - c_m)^2 from the weighted moments about
+    the node's own value, T_2 - 2 d T_1 + d^2 T_0 with d = c_m - u1_j.
+    Checked against the direct sums, with u1 the conditional mean (as in
+    the solver) and candidates up to jumps of the controller."""
+    p = W.Problem(0.2, [(0.5, -6.0, 2.0), (0.3, 3.0, 1.5), (0.2, 9.0, 3.0)], -20, 22, 401, -40, 40, 1601)
+    u0 = W.init_random_steps(p, 5.0, 5)
+    u1 = orc.update_u1(p, u0)
+    _, logf = orc.prior(p)
+    x1 = W.nodes(p.x_lo, p.x_hi, p.n_x) + u0
+    y = W.nodes(p.y_lo, p.y_hi, p.n_y)
+    worst = 0.0
+    for j in range(2, p.n_y - 2, 7):
+        lw = logf - 0.5 * (y[j] - x1) ** 2
+        w = np.exp(lw - lw.max())
+        e = x1 - u1[j]
+        T0, T1, T2 = np.sum(w), np.sum(w * e), np.sum(w * e * e)
+        for c in list(u1[j - 2:j + 3]) + [u1[j] + 3.0, u1[j] - 7.5]:
+            d = c - u1[j]
+            direct = np.sum(w * (x1 - c) ** 2)
+            worst = max(worst, abs(T2 - 2 * d * T1 + d * d * T0 - direct) / direct)
+    assert worst <= 1e-13, worst
