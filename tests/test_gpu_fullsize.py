@@ -8,8 +8,9 @@ a sample checks those rows exactly).
     oracle on sampled rows given the same inputs; the FP64 objective of the
     state is compared in full.
   - 65536-node grids with a 3-component mixture prior, 4 x 32 search (the
-    largest single-instance size of the batched workload), two instances
-    in one batched launch: sampled u0 rows and J.
+    largest single-instance size of the batched workload), four instances
+    in one batched launch: 259 sampled u0 rows each (the update given the
+    GPU's u1), 259 sampled u1 rows (FP32 and FP64 arithmetic) and J.
 """
 import numpy as np
 import pytest
@@ -69,8 +70,8 @@ def test_paper_resolution_sampled(env):
 
 def test_large_mixture_batch_sampled(env):
     U, orc, torch = env
-    cases = [W.mixture_case(s, n=65536, iters=1) for s in (0, 1)]
-    u0s, u1s, Js = U.solve_batch([c.prob for c in cases], [c.search for c in cases], [1, 1],
+    cases = [W.mixture_case(s, n=65536, iters=1) for s in (0, 1, 2, 3)]
+    u0s, u1s, Js = U.solve_batch([c.prob for c in cases], [c.search for c in cases], [1] * len(cases),
                                  [torch.as_tensor(c.u0_init).cuda() for c in cases])
     rng = np.random.default_rng(1)
     for b, c in enumerate(cases):
@@ -81,14 +82,14 @@ def test_large_mixture_batch_sampled(env):
         u1_0 = U.update_u1(p, torch.as_tensor(c.u0_init).cuda(), "fp32_kahan")
         # u1 at full size (four y nodes per lane) on sampled rows, in the
         # FP32 modes' arithmetic and in FP64
-        yr = np.sort(np.concatenate([rng.choice(p.n_y, 128, replace=False), [0, p.n_y // 2, p.n_y - 1]]))
+        yr = np.sort(np.concatenate([rng.choice(p.n_y, 256, replace=False), [0, p.n_y // 2, p.n_y - 1]]))
         ref1 = orc.update_u1(p, c.u0_init, rows=yr)
         assert np.max(np.abs(u1_0.cpu().numpy()[yr] - ref1)) <= 2e-5
         u1_64 = U.update_u1(p, torch.as_tensor(c.u0_init).cuda(), "fp64").cpu().numpy()
         assert np.max(np.abs(u1_64[yr] - ref1)) <= 1e-11
         got = U.argmin_adaptive(p, s, u1_0, torch.as_tensor(c.u0_init).cuda(), "fp32_kahan").cpu().numpy()
         assert np.array_equal(got, u0s[b].cpu().numpy())  # the same update as inside the batched solve
-        rows = np.sort(rng.choice(p.n_x, 48, replace=False))
+        rows = np.sort(np.concatenate([rng.choice(p.n_x, 256, replace=False), [0, p.n_x // 2, p.n_x - 1]]))
         assert _check_rows(orc, p, s, u1_0.cpu().numpy(), c.u0_init, got, rows) <= 1
         Jo = orc.objective(p, u0s[b].cpu().numpy(), u1s[b].cpu().numpy())
         assert abs(Js[b].cpu().numpy()[-1] - Jo) <= 1e-12 * Jo
