@@ -315,7 +315,7 @@ def serving_leg(a):
     trace = W.serving_trace(n_req=n, rate=1.0, seed=0)  # unit rate: arrival times rescaled below
     unit_t = np.array([r.arrival for r in trace])
 
-    def run_server(arrivals, max_slots):
+    def run_server(arrivals, max_slots, keep_out=None):
         srv = U.Server(max_slots=max_slots, prec=a.prec)
         t0 = time.perf_counter()
         nxt = 0
@@ -344,6 +344,8 @@ def serving_leg(a):
                     keep.append((tk, idx))
                 else:
                     done[idx] = t_now
+                    if keep_out is not None:
+                        keep_out[idx] = out
                     if len(done) % 1024 == 0:
                         print(f"# {len(done)}/{n} served", file=sys.stderr, flush=True)
             live = keep + live[max_slots:]
@@ -353,7 +355,7 @@ def serving_leg(a):
     # inputs of the one-at-a-time runs resident on the device beforehand
     u0_dev = [torch.as_tensor(r.case.u0_init).cuda() for r in trace]
 
-    def run_fifo(arrivals):
+    def run_fifo(arrivals, keep_out=None):
         """ucp_solve per request in arrival order; a request starts when it
         has arrived and the previous one has finished (ucp_solve returns
         when its work is done)."""
@@ -364,18 +366,25 @@ def serving_leg(a):
             if wait > 0:
                 time.sleep(wait)
             c = r.case
-            U.solve(c.prob, c.search, c.iters, u0_dev[i], a.prec)
+            out = U.solve(c.prob, c.search, c.iters, u0_dev[i], a.prec)
+            if keep_out is not None:
+                keep_out.append(out)  # device tensors, compared after the timed runs
             end[i] = time.perf_counter() - t0
             if (i + 1) % 1024 == 0:
                 print(f"# one at a time: {i + 1}/{n}", file=sys.stderr, flush=True)
         return end
 
-    fin = run_server(np.zeros(n), a.slots)  # saturated: every request queued at t = 0
+    served, alone = {}, []
+    fin = run_server(np.zeros(n), a.slots, served)  # saturated: every request queued at t = 0
     sat = n / fin.max()
     print(f"# server saturated: {sat:.1f} solves/s", file=sys.stderr, flush=True)
-    fifo_sat = run_fifo(np.zeros(n))
+    fifo_sat = run_fifo(np.zeros(n), alone)
     sat1 = n / fifo_sat.max()
     print(f"# one at a time saturated: {sat1:.1f} solves/s", file=sys.stderr, flush=True)
+    # every request served in the mix against the same request solved alone
+    same = sum(all(np.array_equal(sv, t.cpu().numpy()) for sv, t in zip(served[i], alone[i])) for i in range(n))
+    del served, alone
+    print(f"# served results bitwise equal to the same request alone: {same}/{n}", file=sys.stderr, flush=True)
     rates = {}
     for frac in (0.8, 0.5):
         rate = frac * sat
@@ -395,7 +404,10 @@ def serving_leg(a):
     return {"workload": f"serving-poisson-{n}", "requests": n, "sizes": [1001, 4001, 8001, 20001],
             "k": "logU[0.05, 0.5]", "sigma": "logU[1, 10]", "search": "3x21", "rounds": 20, "max_slots": a.slots,
             "prec": a.prec, "saturated_solves_per_s": sat, "one_at_a_time_saturated_solves_per_s": sat1,
-            "rates": rates}
+            "rates": rates,
+            "served_equal_alone": {"requests": n, "bitwise_equal": int(same),
+                                   "compared": "u0, u1 and J of each request of the saturated server run "
+                                               "against ucp_solve of the same request alone"}}
 
 
 def bench_headline(a):
