@@ -1,9 +1,10 @@
-"""Writes ``serving-requests-1001-4001.npz``: whole FP64 oracle solves of
-eight requests of the serving trace (Poisson arrivals, seed 0;
+"""Writes ``serving-requests-64.npz``: whole FP64 oracle solves of 64
+requests of the serving trace (Poisson arrivals, seed 0;
 k ~ logU[0.05, 0.5], sigma ~ logU[1, 10], sign controller, 3 x 21 search,
-20 rounds), the first five of 1001 nodes and the first three of 4001 nodes
-in arrival order.  The GPU test serves them in a mix with larger requests
-and compares every round's J and the final controllers with these.
+20 rounds), stratified by size: the first 48 of 1001 nodes and the first 16
+of 4001 nodes in arrival order (an oracle solve takes about 3 s and 47 s).
+The GPU test serves them in a mix with larger requests and compares every
+round's J and the final controllers with these.
 
 Calls only the oracle.  Run from the repository root:
     python tests/golden/make_serving_requests.py
@@ -20,12 +21,12 @@ sys.path.insert(0, ROOT)
 import oracle  # noqa: E402
 import workloads as W  # noqa: E402
 
-OUT = os.path.join(os.path.dirname(os.path.abspath(__file__)), "serving-requests-1001-4001.npz")
+OUT = os.path.join(os.path.dirname(os.path.abspath(__file__)), "serving-requests-64.npz")
 
 
 def pick(trace):
-    small = [r for r, q in enumerate(trace) if q.case.prob.n_x == 1001][:5]
-    mid = [r for r, q in enumerate(trace) if q.case.prob.n_x == 4001][:3]
+    small = [r for r, q in enumerate(trace) if q.case.prob.n_x == 1001][:48]
+    mid = [r for r, q in enumerate(trace) if q.case.prob.n_x == 4001][:16]
     return sorted(small + mid)
 
 

@@ -1,12 +1,12 @@
 """Served results against the FP64 oracle.
 
-Eight requests of the serving trace (seed 0; k ~ logU[0.05, 0.5],
-sigma ~ logU[1, 10], sign controller, 3 x 21 search, 20 rounds; five of
-1001 nodes and three of 4001 nodes) run through the continuous-batching
+64 requests of the serving trace (seed 0; k ~ logU[0.05, 0.5],
+sigma ~ logU[1, 10], sign controller, 3 x 21 search, 20 rounds; stratified:
+48 of 1001 nodes and 16 of 4001 nodes) run through the continuous-batching
 server in a mix with four larger requests of the same trace (8001 and 20001
-nodes), admitted while others run (at most four in flight).  Each of the
-eight is compared with the oracle's whole solve of the same request, stored
-in ``tests/golden/serving-requests-1001-4001.npz`` by
+nodes), admitted while others run (at most eight in flight).  Each of the
+64 is compared with the oracle's whole solve of the same request, stored
+in ``tests/golden/serving-requests-64.npz`` by
 ``tests/golden/make_serving_requests.py`` (oracle calls only): J within
 1e-6 relative at every round, u0 equal at every point but at most 0.1%
 (FP64 near-ties) and u1 within 2e-5 where the output density is not
@@ -27,7 +27,7 @@ import workloads as W
 
 pytestmark = pytest.mark.gpu
 
-GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "serving-requests-1001-4001.npz")
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "serving-requests-64.npz")
 
 
 @pytest.fixture(scope="module")
@@ -57,7 +57,7 @@ def test_served_requests_match_oracle(env):
     checked = [int(r) for r in g["index"]]
     big = [r for r, q in enumerate(trace) if q.case.prob.n_x in (8001, 20001)][:4]
     order = sorted(checked + big)
-    srv = U.Server(max_slots=4)
+    srv = U.Server(max_slots=8)
     tickets = {}
     for k, r in enumerate(order):  # staggered: a step after every second submission
         c = trace[r].case
@@ -65,7 +65,7 @@ def test_served_requests_match_oracle(env):
         if k % 2:
             srv.step()
     res = {}
-    for _ in range(400):
+    for _ in range(5000):
         srv.step()
         for r, t in tickets.items():
             if r not in res:
