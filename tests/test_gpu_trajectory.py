@@ -1,4 +1,6 @@
-"""The whole 20001-node benchmark solve (k = 0.2, sigma = 5, grids of 20001
+"""Whole solves against the FP64 oracle's stored trajectories.
+
+The 20001-node benchmark solve (k = 0.2, sigma = 5, grids of 20001
 nodes on [-25, 25], 5 levels x 16 candidates on [-30, 30], the sign
 controller, 30 rounds, FP32 compensated sums) against the FP64 oracle's
 trajectory of the same solve, stored in
@@ -10,6 +12,10 @@ the path; the arithmetic gives ~1e-15), u0 after the first and the last
 round equal to the oracle's at every point but at most 0.1% (FP64
 near-ties), and u1 after the last round within 1e-6 where the output
 density is not negligible.
+
+The precision sweep's nine seed-0 instances, 10 rounds in each arithmetic,
+against the oracle's trajectories in ``tests/golden/sweep-seed0-20001-10r.npz``
+(per-round J, sampled rows of the final controllers).
 """
 import os
 
@@ -63,3 +69,39 @@ def test_headline_trajectory_against_oracle(env):
     err = np.max(np.abs(u1g - g["u1_final"])[mask])
     print(f"u1 after round 30: max abs err {err:.2e} on {mask.sum()} nodes")
     assert err <= 1e-6
+
+
+SWEEP = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "sweep-seed0-20001-10r.npz")
+
+
+@pytest.mark.parametrize("prec", ["fp32", "fp32_kahan", "fp64"])
+def test_sweep_seed0_trajectories_against_oracle(env, prec):
+    """The precision sweep's seed-0 instances (20001 nodes; k in {0.05,
+    0.2, 0.5} x sigma in {1, 5, 10}; 5 x 16 search; random 8-step start),
+    10 rounds in each arithmetic, against the oracle's trajectories stored in
+    ``tests/golden/sweep-seed0-20001-10r.npz`` by
+    ``tests/golden/make_sweep_seed0_trajectories.py`` (oracle calls only):
+    J after every round within 1e-6 relative, u0 after round 10 equal on
+    the 1024 sampled rows but at most one (an FP64 near-tie), u1 after round
+    10 within 1e-6 on the sampled rows with output density."""
+    U, torch = env
+    g = np.load(SWEEP, allow_pickle=False)
+    cases = W.sweep_cases(n=20001, seeds=[0])
+    assert [c.name for c in cases] == list(g["names"])
+    for q, c in enumerate(cases):
+        p, s = c.prob, c.search
+        u0g, u1g, Jg = (t.cpu().numpy() for t in U.solve(p, s, 10, torch.as_tensor(c.u0_init).cuda(), prec))
+        Jr = g[f"J_{q}"]
+        rel = np.max(np.abs(Jg - Jr) / Jr)
+        xr, yr = g[f"xrows_{q}"], g[f"yrows_{q}"]
+        nd = int(np.sum(u0g[xr] != g[f"u0_{q}"]))
+        x1 = W.nodes(p.x_lo, p.x_hi, p.n_x) + u0g
+        f = np.exp(-0.5 * (W.nodes(p.x_lo, p.x_hi, p.n_x) / c.sigma) ** 2)
+        py = np.exp(-0.5 * (W.nodes(p.y_lo, p.y_hi, p.n_y)[yr, None] - x1[None, :]) ** 2) @ f
+        pyall = np.exp(-0.5 * (W.nodes(p.y_lo, p.y_hi, p.n_y)[::16, None] - x1[None, :]) ** 2) @ f
+        m = py >= 1e-9 * pyall.max()
+        e1 = float(np.max(np.abs(u1g[yr] - g[f"u1_{q}"])[m]))
+        print(f"{c.name} {prec}: J rel err {rel:.2e}, u0 differs at {nd} of {len(xr)} rows, u1 err {e1:.2e}")
+        assert rel <= 1e-6, c.name
+        assert nd <= 1, c.name
+        assert e1 <= 1e-6, c.name
