@@ -247,7 +247,8 @@ def batch_leg(a):
                         "kernel": "k_mc32<FP32_KAHAN> (marginal-cost window sums)",
                         "per_unit": f"{SLOTS_PER_TERM} FP32 VALU slots per algorithmic term",
                         "kernel_avg_us": mc_avg_s * 1e6, "kernel_launches": mc_n,
-                        "kernel_terms_per_s": terms / max(mc_n, 1) / mc_avg_s},
+                        "kernel_terms_per_s": terms / max(mc_n, 1) / mc_avg_s,
+                        "kernel_dense_equiv_terms_per_s": dense / max(mc_n, 1) / mc_avg_s},
            "kernel_ms_per_step": breakdown}
     if not a.no_check:
         # the cost error bar: J of the final state of two instances against
