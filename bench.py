@@ -820,7 +820,7 @@ def main():
     ap.add_argument("--alg1-rounds", type=int, default=200, help="alg1: cap on rounds")
     a = ap.parse_args()
     if a.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path (the solver shards over x0 "
+        print("bench.py runs on one GPU only: the library has no multi-GPU path (the solver shards over x0 "
               "rows by design, but only the single-GPU kernel is built and measured).", file=sys.stderr)
         sys.exit(2)
 
